@@ -1,0 +1,154 @@
+/*
+ * stomsfem.h -- C ABI of the MI355X (gfx950) implementation of the simultaneous
+ * local upscaling step of the stochastic multiscale FEM of Hou, Li & Zhang,
+ * "Exploring the locally low dimensional structure in solving random elliptic
+ * PDEs" (StoMsFEM).
+ *
+ * Problem (Sec. 1, eq. eqn): -div(a(x,xi) grad u) = f on D = [0,1]^2, u = 0
+ * on the boundary, for many samples xi.  D is cut into ncx x ncy square coarse
+ * elements K (Sec. 2.2), each resolved by an m x m fine Q1 grid (m = H/h).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller; they must
+ *    stay valid until the work queued on `stream` has completed.  `stream` is
+ *    a hipStream_t (NULL = the default stream).  Every call is asynchronous
+ *    with respect to the host unless stated otherwise.
+ *  - Coefficient samples a are piecewise constant per fine element (sampled at
+ *    the element centroid), row-major [nsamples][ncy*m][ncx*m] (y index
+ *    outer).  a_dtype selects float64 (STOMSFEM_F64) or float32 (STOMSFEM_F32).
+ *  - Coarse element K = (kx, ky) has index ky*ncx + kx.  Its four nodes are
+ *    numbered counter-clockwise from the lower-left corner: 0=(x0,y0),
+ *    1=(x1,y0), 2=(x1,y1), 3=(x0,y1).  A 4x4 symmetric upscaled stiffness is
+ *    stored as its 10 unique entries in the order 00,01,02,03,11,12,13,22,23,33.
+ *  - Coarse unknowns are the interior coarse nodes (zero Dirichlet data) in
+ *    natural order: node (ix, iy), 1 <= ix < ncx, 1 <= iy < ncy, has index
+ *    (iy-1)*(ncx-1) + (ix-1).
+ *  - Return value: STOMSFEM_OK or a negative stomsfem_status.  Argument errors
+ *    are detected on the host before anything is queued.  Numerical events
+ *    that concern one (element, sample) pair are reported in the optional
+ *    per-pair `status` array and do not fail the call.  A failed HIP launch
+ *    returns STOMSFEM_EHIP; faults inside kernels surface at the caller's next
+ *    synchronising call.  stomsfem_last_error() gives a thread-local message.
+ *  - Calls never print and never abort the process.
+ */
+#ifndef STOMSFEM_H
+#define STOMSFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STOMSFEM_OK = 0,
+  STOMSFEM_EINVAL = -1,   /* bad argument (caught on the host, nothing queued) */
+  STOMSFEM_ENOMEM = -2,   /* device workspace could not be allocated */
+  STOMSFEM_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+  STOMSFEM_ENOTSPD = -4,  /* per pair: a pivot of the local/coarse factorisation was <= 0 or NaN */
+  STOMSFEM_ENOCONV = -5,  /* per pair: mixed-precision refinement did not converge (result recomputed in FP64) */
+  STOMSFEM_EVERSION = -6  /* model file / ABI version mismatch */
+} stomsfem_status;
+
+enum { STOMSFEM_F64 = 0, STOMSFEM_F32 = 1 };
+
+/* Arithmetic of the local cell solves. */
+enum {
+  STOMSFEM_PREC_F64 = 0,          /* FP64 factorisation and energies */
+  STOMSFEM_PREC_F32_REFINE64 = 1  /* FP32 factorisation, FP64 residuals and energies */
+};
+
+/* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
+ * nodal functions p^l restricted to the element boundary. */
+enum { STOMSFEM_BC_LINEAR = 0 };
+
+#define STOMSFEM_ABI_VERSION 1
+
+/* ABI version (STOMSFEM_ABI_VERSION of the built library). */
+int stomsfem_version(void);
+
+/* Human-readable description of the last error on the calling thread. */
+const char* stomsfem_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Coefficient samples of the synthetic bump family (the nonlinear transform
+ * of Sec. 2.1.3, eq. nonlinear1, applied to an affine sum of local modes):
+ *
+ *   a(x, xi) = (base + amp sin(2 pi x1/eps) sin(2 pi x2/eps))
+ *              * exp(beta * sum_j xi_j psi_j(x)),
+ *   psi_j(x) = (1 - |x - c_j|^2 / rho^2)^2 for |x - c_j| < rho, else 0,
+ *
+ * with the g*g bump centres c_j = ((j mod g) + 1/2, floor(j/g) + 1/2) / g.
+ * Sampled at the centroids of an nfine x nfine grid on [0,1]^2.
+ *   xi : device [nsamples][nxi] float64, nxi >= g*g (only the first g*g used)
+ *   a  : device out [nsamples][nfine][nfine] in a_dtype
+ * ------------------------------------------------------------------------ */
+int stomsfem_coef_bumps(int64_t nsamples, int32_t nfine, const double* xi, int32_t nxi, int32_t g, double rho,
+                        double eps, double base, double amp, double beta, void* a, int32_t a_dtype,
+                        void* stream);
+
+/* ------------------------------------------------------------------------
+ * Simultaneous local upscaling (Sec. 2.2 eqs. MsFEB and stiffness_local;
+ * Sec. 3 eq. MsFEB2): for every coarse element K and every sample, solve the
+ * cell problems -div(a grad phi^l) = 0 in K, phi^l = p^l on the boundary of
+ * K, on the m x m fine Q1 grid, and form
+ *
+ *   S_ll' = int_K a grad phi^l . grad phi^l'      (l, l' = 0..3).
+ *
+ * One homogeneous batch shares ncx, ncy and m.  Several batches (for example
+ * different m) are processed by one call.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t ncx, ncy;   /* coarse elements per direction (>= 1) */
+  int32_t m;          /* fine cells per coarse element per direction (1..48) */
+  int32_t a_dtype;    /* STOMSFEM_F64 or STOMSFEM_F32 */
+  int64_t nsamples;   /* >= 0 */
+  const void* a;      /* device [nsamples][ncy*m][ncx*m] */
+  double* S;          /* device out [nsamples][ncy*ncx][10] */
+  int32_t* status;    /* device out [nsamples][ncy*ncx] per-pair status, or NULL */
+} stomsfem_batch;
+
+/*   batches   : host array of nbatch descriptors (read during the call only)
+ *   precision : STOMSFEM_PREC_F64 (FP32 refinement is reserved: EINVAL)
+ *   bc        : STOMSFEM_BC_LINEAR
+ * Per-pair status: STOMSFEM_OK, or STOMSFEM_ENOTSPD when a pivot of the local
+ * factorisation is not positive (a <= 0 or NaN somewhere in K); S is then
+ * undefined for that pair. */
+int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream);
+
+/* Same computation through the simple reference kernel (one workgroup per
+ * pair, band window in LDS, any m); used to cross-check the tuned kernels. */
+int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched coarse solve and quantity of interest (Sec. 2.2 eq. upscaleSUF;
+ * Petrov-Galerkin load of eq. stiffness_local_petrov; Monte Carlo estimators
+ * of Sec. 4.1.1).  For every sample: assemble the global coarse stiffness
+ * from S[s][K], drop the boundary nodes (zero Dirichlet data), solve
+ * S U = b in FP64, then
+ *   qoi_mean[i] = (1/N) sum_s U[s][i],
+ *   qoi_var[i]  = (1/N) sum_s U[s][i]^2 - qoi_mean[i]^2   (paper's estimator).
+ *   S       : device [nsamples][ncy*ncx][10] float64
+ *   load    : device [ncy*ncx][4] element loads b^K_l, or NULL for f = 1 with
+ *             b^K_l = int_K p^l = H^2/4, H = 1/ncx (square elements)
+ *   U       : device out [nsamples][(ncx-1)*(ncy-1)]
+ *   qoi_mean, qoi_var : device out [(ncx-1)*(ncy-1)], each may be NULL
+ *   status  : device out [nsamples] (OK or ENOTSPD), may be NULL
+ * Uses library-owned device workspace (see stomsfem_workspace_reserve).
+ * ------------------------------------------------------------------------ */
+int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
+                          double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
+
+/* Grow the library-owned device workspace of the current device to at least
+ * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample
+ * in flight).  Calls made after a large enough reservation allocate nothing.
+ * Synchronous.  Returns OK or ENOMEM. */
+int stomsfem_workspace_reserve(int64_t bytes);
+
+/* Release the workspace of the current device (synchronous). */
+int stomsfem_workspace_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STOMSFEM_H */

@@ -1,0 +1,217 @@
+// Host side of the C ABI declared in include/stomsfem.h: argument
+// validation, the library-owned device workspace, and kernel dispatch.
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace stomsfem {
+hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
+hipError_t launch_upscale_ref(const UpArgs& args, int a_dtype, hipStream_t st);
+size_t upscale_ref_lds_bytes(int m);
+hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st);
+bool tiled_supports(int m);
+hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
+                         double* var, int32_t* status, double* work, hipStream_t st);
+int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples);
+size_t coarse_lds_bytes(int ncx);
+hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
+                             double base, double amp, double beta, void* a, int a_dtype, hipStream_t st);
+}  // namespace stomsfem
+
+using namespace stomsfem;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return STOMSFEM_EHIP;
+}
+
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mutex;
+std::unordered_map<int, Workspace> g_ws;
+
+// Returns a device buffer of at least `bytes` on the current device, growing
+// the library workspace when needed (the growth is a synchronous hipMalloc).
+int workspace_get(size_t bytes, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  Workspace& w = g_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) {
+      w.ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(STOMSFEM_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return STOMSFEM_OK;
+}
+
+// True when p is device (or managed) memory visible to the current device.
+bool device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+#if HIP_VERSION_MAJOR >= 6
+  const auto t = attr.type;
+#else
+  const auto t = attr.memoryType;
+#endif
+  return t == hipMemoryTypeDevice || t == hipMemoryTypeManaged;
+}
+
+int check_batch(const stomsfem_batch& b, int idx) {
+  const std::string w = "batch " + std::to_string(idx) + ": ";
+  if (b.ncx < 1 || b.ncy < 1) return fail(STOMSFEM_EINVAL, w + "ncx and ncy must be >= 1");
+  if (b.m < 1 || b.m > 48) return fail(STOMSFEM_EINVAL, w + "m must be in 1..48");
+  if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, w + "bad a_dtype");
+  if (b.nsamples < 0) return fail(STOMSFEM_EINVAL, w + "nsamples < 0");
+  if ((int64_t)b.ncx * b.m > (1 << 20) || (int64_t)b.ncy * b.m > (1 << 20))
+    return fail(STOMSFEM_EINVAL, w + "fine grid too large");
+  if (b.nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(b.a)) return fail(STOMSFEM_EINVAL, w + "a is not a device pointer");
+  if (!device_ptr(b.S)) return fail(STOMSFEM_EINVAL, w + "S is not a device pointer");
+  if (b.status && !device_ptr(b.status)) return fail(STOMSFEM_EINVAL, w + "status is not a device pointer");
+  return STOMSFEM_OK;
+}
+
+UpArgs to_args(const stomsfem_batch& b) {
+  UpArgs a;
+  a.nsamples = b.nsamples;
+  a.ncx = b.ncx;
+  a.ncy = b.ncy;
+  a.m = b.m;
+  a.npairs = b.nsamples * (int64_t)b.ncx * b.ncy;
+  a.a = b.a;
+  a.S = b.S;
+  a.status = b.status;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stomsfem_version(void) { return STOMSFEM_ABI_VERSION; }
+
+const char* stomsfem_last_error(void) { return g_last_error.c_str(); }
+
+int stomsfem_coef_bumps(int64_t nsamples, int32_t nfine, const double* xi, int32_t nxi, int32_t g, double rho,
+                        double eps, double base, double amp, double beta, void* a, int32_t a_dtype, void* stream) {
+  if (nsamples < 0 || nfine < 1 || g < 1 || nxi < g * g) return fail(STOMSFEM_EINVAL, "coef_bumps: bad sizes");
+  if (!(rho > 0.0) || !(eps > 0.0)) return fail(STOMSFEM_EINVAL, "coef_bumps: rho and eps must be > 0");
+  if (a_dtype != STOMSFEM_F64 && a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, "coef_bumps: bad a_dtype");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi) || !device_ptr(a)) return fail(STOMSFEM_EINVAL, "coef_bumps: xi and a must be device pointers");
+  hipError_t e = launch_coef_bumps(nsamples, nfine, xi, nxi, g, rho, eps, base, amp, beta, a, a_dtype,
+                                   (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coef_bumps launch");
+}
+
+int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream) {
+  if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(STOMSFEM_EINVAL, "upscale: bad batch list");
+  if (precision != STOMSFEM_PREC_F64) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_PREC_F64 is available");
+  if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_BC_LINEAR is available");
+  for (int i = 0; i < nbatch; ++i) {
+    int rc = check_batch(batches[i], i);
+    if (rc != STOMSFEM_OK) return rc;
+  }
+  for (int i = 0; i < nbatch; ++i) {
+    const stomsfem_batch& b = batches[i];
+    if (b.nsamples == 0) continue;
+    UpArgs args = to_args(b);
+    hipError_t e;
+    if (b.m <= 8)
+      e = launch_upscale_small(args, b.a_dtype, (hipStream_t)stream);
+    else if (tiled_supports(b.m))
+      e = launch_upscale_tiled(args, b.a_dtype, (hipStream_t)stream);
+    else
+      e = launch_upscale_ref(args, b.a_dtype, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "upscale launch");
+  }
+  return STOMSFEM_OK;
+}
+
+int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* stream) {
+  if (!batch) return fail(STOMSFEM_EINVAL, "upscale_reference: NULL batch");
+  if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale_reference: only STOMSFEM_BC_LINEAR");
+  int rc = check_batch(*batch, 0);
+  if (rc != STOMSFEM_OK) return rc;
+  if (batch->nsamples == 0) return STOMSFEM_OK;
+  hipError_t e = launch_upscale_ref(to_args(*batch), batch->a_dtype, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_reference launch");
+}
+
+int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
+                          double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream) {
+  if (ncx < 1 || ncy < 1 || nsamples < 0) return fail(STOMSFEM_EINVAL, "coarse_solve: bad sizes");
+  if (ncx > 1024 || ncy > 1024) return fail(STOMSFEM_EINVAL, "coarse_solve: ncx, ncy must be <= 1024");
+  if (coarse_lds_bytes(ncx) > 64 * 1024) return fail(STOMSFEM_EINVAL, "coarse_solve: ncx too large for the LDS window");
+  const int nU = (ncx - 1) * (ncy - 1);
+  if (nU == 0) return STOMSFEM_OK;
+  if (nsamples > 0 && (!device_ptr(S) || !device_ptr(U)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve: S and U must be device pointers");
+  if (load && !device_ptr(load)) return fail(STOMSFEM_EINVAL, "coarse_solve: load must be a device pointer");
+  if ((qoi_mean && !device_ptr(qoi_mean)) || (qoi_var && !device_ptr(qoi_var)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve: qoi outputs must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "coarse_solve: status must be a device pointer");
+  void* work = nullptr;
+  if (nsamples > 0) {
+    int rc = workspace_get(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), &work);
+    if (rc != STOMSFEM_OK) return rc;
+  }
+  hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
+                               (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve launch");
+}
+
+int stomsfem_workspace_reserve(int64_t bytes) {
+  if (bytes < 0) return fail(STOMSFEM_EINVAL, "workspace_reserve: bytes < 0");
+  void* p = nullptr;
+  return bytes == 0 ? STOMSFEM_OK : workspace_get((size_t)bytes, &p);
+}
+
+int stomsfem_workspace_release(void) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end() && it->second.ptr) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(it->second.ptr);
+    g_ws.erase(it);
+  }
+  return STOMSFEM_OK;
+}
+
+}  // extern "C"

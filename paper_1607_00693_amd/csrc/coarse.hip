@@ -1,0 +1,194 @@
+// Batched coarse solve S U = b (Sec. 2.2 eq. upscaleSUF) with the
+// Petrov-Galerkin load (eq. stiffness_local_petrov), and the Monte Carlo
+// mean / variance of the coarse solution (Sec. 4.1.1).
+//
+// One workgroup per sample.  The interior coarse nodes in natural order give
+// a 9-point band of half-width ncx; the global stiffness rows are assembled
+// on the fly from the four upscaled element matrices around each node as
+// they enter an LDS window of (ncx+1) x (ncx+1) entries.  FP64 LDL^T with the
+// forward substitution fused; the retired columns of L go to a per-workgroup
+// slice of the library workspace and are read back once by the backward
+// substitution, which is done by one wavefront with a shuffle reduction.
+#include "common.h"
+
+namespace stomsfem {
+
+constexpr int COARSE_THREADS = 256;
+
+struct CoarseArgs {
+  int32_t ncx, ncy;
+  int64_t nsamples;
+  const double* S;
+  const double* load;
+  double* U;
+  int32_t* status;
+  double* work;  // gridDim.x * nU * (ncx+1) doubles
+};
+
+__device__ __forceinline__ double selem(const double* Sk, int i, int j) {
+  // packed upper triangle 00,01,02,03,11,12,13,22,23,33
+  if (i > j) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+  const int base = i == 0 ? 0 : i == 1 ? 4 : i == 2 ? 7 : 9;
+  return Sk[base + (j - i)];
+}
+
+__global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs args) {
+  extern __shared__ double smem[];
+  const int ncx = args.ncx, ncy = args.ncy;
+  const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, B = ncx, WN = B + 1;
+  double* Wn = smem;        // WN*WN
+  double* F = Wn + WN * WN;  // WN (forward-substituted rhs window)
+  double* X = F + WN;        // WN (backward substitution window)
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int Mc = ncx * ncy;
+  const double H = 1.0 / ncx;
+  double* Lc = args.work + (int64_t)blockIdx.x * nU * WN;  // column j: [d_j, l_{j+1,j}, ..., l_{j+B,j}]
+
+  for (int64_t s = blockIdx.x; s < args.nsamples; s += gridDim.x) {
+    const double* Ss = args.S + s * (int64_t)Mc * 10;
+    double* Us = args.U + s * (int64_t)nU;
+    __syncthreads();
+    for (int i = tid; i < WN * WN; i += blockDim.x) Wn[i] = 0.0;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+
+    // Row r of the coarse system: node (ix, iy) = grid node (px, py); its four
+    // elements SW=(px-1,py-1), SE=(px,py-1), NW=(px-1,py), NE=(px,py) see it as
+    // local node 2, 3, 1, 0 respectively.
+    auto insert_row = [&](int r) {
+      const int ix = r % nix, iy = r / nix, px = ix + 1, py = iy + 1;
+      const double* sSW = Ss + ((py - 1) * ncx + (px - 1)) * 10;
+      const double* sSE = Ss + ((py - 1) * ncx + px) * 10;
+      const double* sNW = Ss + (py * ncx + (px - 1)) * 10;
+      const double* sNE = Ss + (py * ncx + px) * 10;
+      if (tid <= B) {
+        const int t = tid;
+        double v = 0.0;
+        if (t == 0) v += (selem(sSW, 2, 2) + selem(sSE, 3, 3)) + (selem(sNW, 1, 1) + selem(sNE, 0, 0));
+        if (t == 1 && ix >= 1) v += selem(sSW, 2, 3) + selem(sNW, 1, 0);
+        if (t == nix - 1 && iy >= 1 && ix <= nix - 2) v += selem(sSE, 3, 1);
+        if (t == nix && iy >= 1) v += selem(sSW, 2, 1) + selem(sSE, 3, 0);
+        if (t == nix + 1 && iy >= 1 && ix >= 1) v += selem(sSW, 2, 0);
+        if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;
+      } else if (tid == B + 1) {
+        double b;
+        if (args.load) {
+          const double* L = args.load;
+          b = (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
+              (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
+        } else {
+          b = H * H;  // four elements, int_K p^l = H^2/4 each
+        }
+        F[r % WN] = b;
+      }
+    };
+
+    for (int r = 0; r < (B < nU ? B : nU); ++r) insert_row(r);
+    __syncthreads();
+    for (int j = 0; j < nU; ++j) {
+      if (j + B < nU) {
+        insert_row(j + B);
+        __syncthreads();
+      }
+      const int jj = j % WN;
+      const double d = Wn[jj * WN + jj];
+      const double inv = 1.0 / d;
+      const int cnt = (j + B < nU - 1 ? j + B : nU - 1) - j;
+      // column j of L (and the pivot) to the workspace; rhs forward step
+      if (tid <= cnt) {
+        const double v = tid == 0 ? d : Wn[((j + tid) % WN) * WN + jj] * inv;
+        Lc[(int64_t)j * WN + tid] = v;
+        if (tid > 0) F[(j + tid) % WN] -= v * F[jj];
+      }
+      if (tid == 0) {
+        if (!(d > 0.0)) bad = 1;
+        Us[j] = F[jj];  // y_j, overwritten by x_j below
+      }
+      const int npairs = cnt * (cnt + 1) / 2;
+      for (int q = tid; q < npairs; q += blockDim.x) {
+        int io = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+        while (io * (io + 1) / 2 > q) --io;
+        while ((io + 1) * (io + 2) / 2 <= q) ++io;
+        const int ko = q - io * (io + 1) / 2;
+        const int i = j + 1 + io, k = j + 1 + ko;
+        Wn[(i % WN) * WN + (k % WN)] -= Wn[(i % WN) * WN + jj] * inv * Wn[(k % WN) * WN + jj];
+      }
+      __syncthreads();
+    }
+    // backward substitution x_j = y_j / d_j - sum_{t=1..B} l_{j+t,j} x_{j+t}
+    if (tid < 64) {
+      for (int t = tid; t < WN; t += 64) X[t] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      for (int j = nU - 1; j >= 0; --j) {
+        const double* col = Lc + (int64_t)j * WN;
+        double part = 0.0;
+        for (int t = 1 + tid; t <= B; t += 64)
+          if (j + t < nU) part += col[t] * X[(j + t) % WN];
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        const double x = Us[j] / col[0] - part;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (tid == 0) {
+          X[j % WN] = x;
+          Us[j] = x;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+      if (tid == 0 && args.status) args.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+    }
+  }
+}
+
+// qoi_mean[i] = (1/N) sum_s U[s][i]; qoi_var[i] = (1/N) sum_s U^2 - mean^2.
+// Fixed summation order over s (bitwise reproducible).
+__global__ void qoi_kernel(int64_t N, int nU, const double* U, double* mean, double* var) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nU) return;
+  double m1 = 0.0, m2 = 0.0;
+  for (int64_t s = 0; s < N; ++s) {
+    const double u = U[s * nU + i];
+    m1 += u;
+    m2 += u * u;
+  }
+  const double inv = N > 0 ? 1.0 / (double)N : 0.0;
+  m1 *= inv;
+  m2 *= inv;
+  if (mean) mean[i] = m1;
+  if (var) var[i] = m2 - m1 * m1;
+}
+
+size_t coarse_lds_bytes(int ncx) {
+  const int WN = ncx + 1;
+  return sizeof(double) * ((size_t)WN * WN + 2 * (size_t)WN);
+}
+
+int64_t coarse_grid(int64_t nsamples) { return nsamples < 2048 ? nsamples : 2048; }
+
+int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
+  return coarse_grid(nsamples) * (int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1);
+}
+
+hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
+                         double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
+  const int nU = (ncx - 1) * (ncy - 1);
+  if (N > 0 && nU > 0) {
+    CoarseArgs a{ncx, ncy, N, S, load, U, status, work};
+    hipLaunchKernelGGL(coarse_solve_kernel, dim3((unsigned)coarse_grid(N)), dim3(COARSE_THREADS),
+                       coarse_lds_bytes(ncx), st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if ((mean || var) && nU > 0) {
+    hipLaunchKernelGGL(qoi_kernel, dim3((nU + 255) / 256), dim3(256), 0, st, N, nU, U, mean, var);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+}  // namespace stomsfem

@@ -1,0 +1,62 @@
+// Coefficient samples of the synthetic bump family: the exponential
+// transform of Sec. 2.1.3 (eq. nonlinear1) applied to an affine sum of
+// compactly supported local modes, times a periodic oscillation,
+//   a(x, xi) = (base + amp sin(2 pi x1/eps) sin(2 pi x2/eps))
+//              * exp(beta * sum_j xi_j psi_j(x)),
+//   psi_j(x) = (1 - |x - c_j|^2/rho^2)^2 inside the disc of radius rho.
+// One thread per fine element, sampled at the centroid.  Only bumps whose
+// centre cell lies within ceil(rho*g) cells of the point are visited, in
+// increasing j.
+#include "common.h"
+
+namespace stomsfem {
+
+struct CoefArgs {
+  int64_t nsamples;
+  int32_t nfine, nxi, g;
+  double rho, eps, base, amp, beta;
+  const double* xi;
+  void* a;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void coef_bumps_kernel(CoefArgs c) {
+  const int64_t per = (int64_t)c.nfine * c.nfine;
+  const int64_t total = c.nsamples * per;
+  const double h = 1.0 / c.nfine;
+  const double rho2 = c.rho * c.rho;
+  const int reach = (int)ceil(c.rho * c.g);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = t / per;
+    const int rem = (int)(t - s * per);
+    const int iy = rem / c.nfine, ix = rem - iy * c.nfine;
+    const double x = (ix + 0.5) * h, y = (iy + 0.5) * h;
+    const double* xs = c.xi + s * c.nxi;
+    const int bx = min((int)(x * c.g), c.g - 1), by = min((int)(y * c.g), c.g - 1);
+    double field = 0.0;
+    for (int jy = max(by - reach, 0); jy <= min(by + reach, c.g - 1); ++jy)
+      for (int jx = max(bx - reach, 0); jx <= min(bx + reach, c.g - 1); ++jx) {
+        const double cx = (jx + 0.5) / c.g, cy = (jy + 0.5) / c.g;
+        const double r2 = ((x - cx) * (x - cx) + (y - cy) * (y - cy)) / rho2;
+        if (r2 < 1.0) field += xs[jy * c.g + jx] * (1.0 - r2) * (1.0 - r2);
+      }
+    const double osc = c.base + c.amp * sin(2.0 * M_PI * x / c.eps) * sin(2.0 * M_PI * y / c.eps);
+    ((T*)c.a)[t] = (T)(osc * exp(c.beta * field));
+  }
+}
+
+hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
+                             double base, double amp, double beta, void* a, int a_dtype, hipStream_t st) {
+  CoefArgs c{nsamples, nfine, nxi, g, rho, eps, base, amp, beta, xi, a};
+  const int64_t total = nsamples * (int64_t)nfine * nfine;
+  if (total == 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 1 << 20) blocks = 1 << 20;
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL(coef_bumps_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, c);
+  else
+    hipLaunchKernelGGL(coef_bumps_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+}  // namespace stomsfem

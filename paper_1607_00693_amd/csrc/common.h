@@ -1,0 +1,84 @@
+// Shared device-side definitions of the HIP path (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stomsfem.h"
+
+namespace stomsfem {
+
+// Arguments of one homogeneous upscaling batch, passed by value to kernels.
+struct UpArgs {
+  int64_t nsamples;
+  int32_t ncx, ncy, m;
+  int64_t npairs;     // nsamples * ncx * ncy
+  const void* a;
+  double* S;
+  int32_t* status;
+};
+
+// Row-major offset of the m x m block of coarse element K of sample s.
+__device__ __forceinline__ int64_t block_offset(int64_t s, int K, int ncx, int ncy, int m) {
+  const int64_t lda = (int64_t)ncx * m;
+  const int kx = K % ncx, ky = K / ncx;
+  return s * ((int64_t)ncy * m) * lda + (int64_t)ky * m * lda + (int64_t)kx * m;
+}
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p, int64_t i) {
+  return (double)p[i];
+}
+
+// Bilinear corner functions p^l at the boundary node (px, py) of the m x m
+// local grid, l = 0..2 (p^3 follows from the partition of unity).
+__host__ __device__ constexpr double pcorner(int l, int px, int py, int m) {
+  return l == 0   ? (1.0 - (double)px / m) * (1.0 - (double)py / m)
+         : l == 1 ? ((double)px / m) * (1.0 - (double)py / m)
+                  : ((double)px / m) * ((double)py / m);
+}
+
+// Q1 element matrix of int grad N_a . grad N_b on a square (unit coefficient),
+// nodes counter-clockwise from the lower-left corner.
+__host__ __device__ constexpr double kref(int a, int b) {
+  return a == b ? 4.0 / 6.0 : ((a - b == 2 || b - a == 2) ? -2.0 / 6.0 : -1.0 / 6.0);
+}
+
+// Energy g_e^l . K_ref g_e^l' of one fine element whose nodes lying on the
+// boundary of the coarse element carry the bilinear data p^l (interior nodes
+// carry 0).  Element (ex, ey) of the m x m local grid.
+__host__ __device__ constexpr double bb_coef(int l, int lp, int ex, int ey, int m) {
+  double s = 0.0;
+  for (int al = 0; al < 4; ++al) {
+    const int pxa = ex + (al == 1 || al == 2), pya = ey + (al >= 2);
+    const bool ba = pxa == 0 || pxa == m || pya == 0 || pya == m;
+    if (!ba) continue;
+    for (int be = 0; be < 4; ++be) {
+      const int pxb = ex + (be == 1 || be == 2), pyb = ey + (be >= 2);
+      const bool bb = pxb == 0 || pxb == m || pyb == 0 || pyb == m;
+      if (!bb) continue;
+      s += pcorner(l, pxa, pya, m) * kref(al, be) * pcorner(lp, pxb, pyb, m);
+    }
+  }
+  return s;
+}
+
+// Write the packed 10 entries of S from its 3x3 block on l, l' < 3 using
+// phi^3 = 1 - phi^0 - phi^1 - phi^2 (constants are a-harmonic, so S 1 = 0).
+__device__ __forceinline__ void store_packed(double* out, const double s[3][3]) {
+  const double s03 = -(s[0][0] + s[0][1] + s[0][2]);
+  const double s13 = -(s[0][1] + s[1][1] + s[1][2]);
+  const double s23 = -(s[0][2] + s[1][2] + s[2][2]);
+  const double s33 = -(s03 + s13 + s23);
+  out[0] = s[0][0];
+  out[1] = s[0][1];
+  out[2] = s[0][2];
+  out[3] = s03;
+  out[4] = s[1][1];
+  out[5] = s[1][2];
+  out[6] = s13;
+  out[7] = s[2][2];
+  out[8] = s23;
+  out[9] = s33;
+}
+
+}  // namespace stomsfem

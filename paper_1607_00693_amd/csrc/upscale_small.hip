@@ -1,0 +1,212 @@
+// Local upscaling, one (coarse element, sample) pair per lane, for m <= 8.
+//
+// Cell problems (Sec. 2.2, eq. MsFEM cell problem; Sec. 3 eq. MsFEB2): on the
+// m x m fine Q1 grid of a coarse element K, with interior unknowns x_I and
+// boundary data g^l = p^l,
+//     K_II x_I^l = f^l := -K_IB g^l ,      l = 0, 1, 2,
+// and the upscaled stiffness (eq. stiffness_local) is the Schur complement
+// of the local stiffness onto the boundary, contracted with the data:
+//     S_ll' = g^l . K_BB g^l'  -  f^l . K_II^{-1} f^l' .
+// With K_II = L D L^T (unit lower L, natural node order, half-bandwidth m)
+// and y^l = L^{-1} f^l, the second term is sum_j y_j^l y_j^l' / d_j, so the
+// factor is consumed as it is produced: a sliding (m+1) x (m+1) window of
+// the band is all that is ever stored, and no back substitution is needed.
+// phi^3 = 1 - sum phi^l gives the fourth row and column (S 1 = 0).
+//
+// Everything here is compile-time structured: the loop over the NI = (m-1)^2
+// pivots is fully unrolled, the window lives in registers with static
+// indices, and only the coefficient values are runtime data.  The
+// coefficient block is read row by row (two element rows live at a time).
+#include "common.h"
+
+namespace stomsfem {
+
+template <int M, typename T>
+struct SmallCell {
+  static constexpr int n = M - 1;   // interior nodes per grid row
+  static constexpr int NI = n * n;  // interior unknowns
+  static constexpr int B = M;       // half-bandwidth (9-point stencil, natural order)
+  static constexpr int WN = B + 1;  // window rows
+
+  double W[WN][WN];    // entry (r, c), c <= r, stored at [r % WN][c % WN]
+  double F[WN][3];     // right-hand sides, row r at [r % WN]
+  double alo[M], ahi[M];  // element rows iy and iy+1 of the current fresh grid row
+  double sbb[3][3];    // g . K_BB g'
+  double sc[3][3];     // sum y y^T / d
+  bool ok;
+
+  const T* a;
+  int64_t lda;
+
+  __device__ __forceinline__ void load_elem_row(int ey, double* dst) {
+#pragma unroll
+    for (int ex = 0; ex < M; ++ex) dst[ex] = ld(a, ey * lda + ex);
+    // boundary-boundary energy of the elements of this row that touch the boundary
+#pragma unroll
+    for (int ex = 0; ex < M; ++ex) {
+      if (!(ey == 0 || ey == M - 1 || ex == 0 || ex == M - 1)) continue;
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int lp = l; lp < 3; ++lp) sbb[l][lp] += dst[ex] * bb_coef(l, lp, ex, ey, M);
+    }
+  }
+
+  // Original matrix row r (node (ix, iy), grid node (ix+1, iy+1)) and its
+  // right-hand sides -sum_{boundary neighbours} k_rb g^l_b.
+  __device__ __forceinline__ void insert_row(int r) {
+    const int ix = r % n, iy = r / n;
+    const int px = ix + 1, py = iy + 1;
+    if (ix == 0) {  // entering a new grid row: shift the element-row pair
+      if (iy == 0) {
+        load_elem_row(0, alo);
+      } else {
+#pragma unroll
+        for (int e = 0; e < M; ++e) alo[e] = ahi[e];
+      }
+      load_elem_row(iy + 1, ahi);
+    }
+    const double aSW = alo[ix], aSE = alo[ix + 1], aNW = ahi[ix], aNE = ahi[ix + 1];
+    const double diag = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+    const double cW = -(aSW + aNW) * (1.0 / 6.0), cE = -(aSE + aNE) * (1.0 / 6.0);
+    const double cS = -(aSW + aSE) * (1.0 / 6.0), cN = -(aNW + aNE) * (1.0 / 6.0);
+    const double cSW = -aSW * (1.0 / 3.0), cSE = -aSE * (1.0 / 3.0);
+    const double cNW = -aNW * (1.0 / 3.0), cNE = -aNE * (1.0 / 3.0);
+    const int rr = r % WN;
+#pragma unroll
+    for (int c = (r - B > 0 ? r - B : 0); c <= r; ++c) W[rr][c % WN] = 0.0;
+    W[rr][r % WN] = diag;
+    double f[3] = {0.0, 0.0, 0.0};
+    // neighbour (dx, dy) with coupling k: lower interior neighbours go into the
+    // band, boundary neighbours into the right-hand sides, upper interior
+    // neighbours are held by their own (later) rows.
+    auto nb = [&](int dx, int dy, double k) __attribute__((always_inline)) {
+      const int qx = px + dx, qy = py + dy;
+      const bool bnd = qx == 0 || qx == M || qy == 0 || qy == M;
+      if (bnd) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) f[l] -= k * pcorner(l, qx, qy, M);
+      } else {
+        const int c = (qy - 1) * n + (qx - 1);
+        if (c < r) W[rr][c % WN] = k;
+      }
+    };
+    nb(-1, 0, cW);
+    nb(1, 0, cE);
+    nb(0, -1, cS);
+    nb(0, 1, cN);
+    nb(-1, -1, cSW);
+    nb(1, -1, cSE);
+    nb(-1, 1, cNW);
+    nb(1, 1, cNE);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) F[rr][l] = f[l];
+  }
+
+  // Eliminate pivot j: rank-1 update of the window, forward substitution of
+  // the right-hand sides, accumulation of y y^T / d.
+  __device__ __forceinline__ void eliminate(int j) {
+    const int jj = j % WN;
+    const double d = W[jj][jj];
+    ok = ok && (d > 0.0);
+    const double inv = 1.0 / d;
+    const int iend = (j + B < NI - 1) ? j + B : NI - 1;
+    double t[WN], l[WN];
+#pragma unroll
+    for (int i = j + 1; i <= iend; ++i) {
+      t[i - j] = W[i % WN][jj];
+      l[i - j] = t[i - j] * inv;
+    }
+#pragma unroll
+    for (int i = j + 1; i <= iend; ++i)
+#pragma unroll
+      for (int k = j + 1; k <= i; ++k) W[i % WN][k % WN] -= l[i - j] * t[k - j];
+    const double y0 = F[jj][0], y1 = F[jj][1], y2 = F[jj][2];
+#pragma unroll
+    for (int i = j + 1; i <= iend; ++i) {
+      F[i % WN][0] -= l[i - j] * y0;
+      F[i % WN][1] -= l[i - j] * y1;
+      F[i % WN][2] -= l[i - j] * y2;
+    }
+    const double z0 = y0 * inv, z1 = y1 * inv, z2 = y2 * inv;
+    sc[0][0] += z0 * y0;
+    sc[0][1] += z0 * y1;
+    sc[0][2] += z0 * y2;
+    sc[1][1] += z1 * y1;
+    sc[1][2] += z1 * y2;
+    sc[2][2] += z2 * y2;
+  }
+
+  __device__ __forceinline__ void run(double* out, int32_t* status) {
+    ok = true;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int lp = 0; lp < 3; ++lp) sbb[l][lp] = sc[l][lp] = 0.0;
+    if constexpr (NI == 0) {
+      // m = 1: every node is a boundary node
+      load_elem_row(0, alo);
+    } else {
+#pragma unroll
+      for (int r = 0; r < (B < NI ? B : NI); ++r) insert_row(r);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (j + B < NI) insert_row(j + B);
+        eliminate(j);
+      }
+    }
+    double s[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int lp = l; lp < 3; ++lp) {
+        s[l][lp] = sbb[l][lp] - sc[l][lp];
+        s[lp][l] = s[l][lp];
+      }
+    store_packed(out, s);
+    if (status) *status = ok ? STOMSFEM_OK : STOMSFEM_ENOTSPD;
+  }
+};
+
+template <int M, typename T>
+__global__ __launch_bounds__(64) void upscale_lane_kernel(UpArgs args) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= args.npairs) return;
+  const int Mc = args.ncx * args.ncy;
+  const int64_t s = p / Mc;
+  const int K = (int)(p - s * Mc);
+  SmallCell<M, T> cell;
+  cell.a = (const T*)args.a + block_offset(s, K, args.ncx, args.ncy, M);
+  cell.lda = (int64_t)args.ncx * M;
+  cell.run(args.S + p * 10, args.status ? args.status + p : nullptr);
+}
+
+template <int M, typename T>
+static hipError_t launch_lane(const UpArgs& args, hipStream_t st) {
+  const int threads = 64;
+  const int64_t blocks = (args.npairs + threads - 1) / threads;
+  hipLaunchKernelGGL((upscale_lane_kernel<M, T>), dim3((unsigned)blocks), dim3(threads), 0, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st) {
+  const bool f32 = a_dtype == STOMSFEM_F32;
+#define CASE(MM)                                                                           \
+  case MM:                                                                                 \
+    return f32 ? launch_lane<MM, float>(args, st) : launch_lane<MM, double>(args, st);
+  switch (args.m) {
+    CASE(1)
+    CASE(2)
+    CASE(3)
+    CASE(4)
+    CASE(5)
+    CASE(6)
+    CASE(7)
+    CASE(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+}  // namespace stomsfem

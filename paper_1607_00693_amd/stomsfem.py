@@ -1,0 +1,177 @@
+"""Thin ctypes binding of libstomsfem.so with the C entry-point names.
+
+Only argument marshalling happens here: torch tensors supply device memory and
+the current HIP stream; every step of the computation runs in the library's
+kernels.  There is no CPU fallback: if the library is missing or the tensors
+are not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstomsfem.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EVERSION = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+PREC_F64, PREC_F32_REFINE64 = 0, 1
+BC_LINEAR = 0
+
+_DT = {torch.float64: F64, torch.float32: F32}
+
+
+class StomsfemError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+class Batch(C.Structure):
+    _fields_ = [
+        ("ncx", C.c_int32),
+        ("ncy", C.c_int32),
+        ("m", C.c_int32),
+        ("a_dtype", C.c_int32),
+        ("nsamples", C.c_int64),
+        ("a", C.c_void_p),
+        ("S", C.c_void_p),
+        ("status", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libstomsfem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python paper_1607_00693_amd/build.py` "
+            "(or __graft_entry__.build()); there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "stomsfem_version": (C.c_int, []),
+        "stomsfem_last_error": (C.c_char_p, []),
+        "stomsfem_coef_bumps": (C.c_int, [i64, i32, vp, i32, i32, dbl, dbl, dbl, dbl, dbl, vp, i32, vp]),
+        "stomsfem_upscale": (C.c_int, [C.POINTER(Batch), i32, i32, i32, vp]),
+        "stomsfem_upscale_reference": (C.c_int, [C.POINTER(Batch), i32, vp]),
+        "stomsfem_coarse_solve": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
+        "stomsfem_workspace_reserve": (C.c_int, [i64]),
+        "stomsfem_workspace_release": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(fn: str, rc: int):
+    if rc != OK:
+        msg = lib().stomsfem_last_error()
+        raise StomsfemError(fn, rc, msg.decode() if msg else "")
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def version() -> int:
+    return lib().stomsfem_version()
+
+
+def coef_bumps(xi: torch.Tensor, nfine: int, g: int, rho: float, eps: float, base: float = 2.0,
+               amp: float = 1.8, beta: float = 0.5, dtype=torch.float64, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Coefficient samples a[N][nfine][nfine] of the bump family (see stomsfem.h)."""
+    assert xi.dtype == torch.float64
+    N, nxi = xi.shape
+    if out is None:
+        out = torch.empty((N, nfine, nfine), dtype=dtype, device=xi.device)
+    _check("stomsfem_coef_bumps", lib().stomsfem_coef_bumps(
+        N, nfine, _ptr(xi), nxi, g, rho, eps, base, amp, beta, _ptr(out), _DT[out.dtype], _stream(stream)))
+    return out
+
+
+def make_batch(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor, status: torch.Tensor | None) -> Batch:
+    N = a.shape[0]
+    assert a.shape[1:] == (ncy * m, ncx * m), f"a has shape {tuple(a.shape)}"
+    assert S.dtype == torch.float64 and S.shape == (N, ncx * ncy, 10)
+    if status is not None:
+        assert status.dtype == torch.int32 and status.shape == (N, ncx * ncy)
+    return Batch(ncx, ncy, m, _DT[a.dtype], N, _ptr(a), _ptr(S), _ptr(status))
+
+
+def upscale(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None,
+            status: torch.Tensor | None = None, precision: int = PREC_F64, stream=None):
+    """Upscaled stiffness S[N][ncy*ncx][10] for one homogeneous batch."""
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, ncx * ncy, 10), dtype=torch.float64, device=a.device)
+    b = make_batch(a, ncx, ncy, m, S, status)
+    _check("stomsfem_upscale", lib().stomsfem_upscale(C.byref(b), 1, precision, BC_LINEAR, _stream(stream)))
+    return S
+
+
+def upscale_batches(batches: list[Batch], precision: int = PREC_F64, stream=None):
+    arr = (Batch * len(batches))(*batches)
+    _check("stomsfem_upscale", lib().stomsfem_upscale(arr, len(batches), precision, BC_LINEAR, _stream(stream)))
+
+
+def upscale_reference(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None,
+                      status: torch.Tensor | None = None, stream=None):
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, ncx * ncy, 10), dtype=torch.float64, device=a.device)
+    b = make_batch(a, ncx, ncy, m, S, status)
+    _check("stomsfem_upscale_reference", lib().stomsfem_upscale_reference(C.byref(b), BC_LINEAR, _stream(stream)))
+    return S
+
+
+def coarse_solve(S: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None = None,
+                 U: torch.Tensor | None = None, qoi_mean: torch.Tensor | None = None,
+                 qoi_var: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+    """Per-sample coarse solutions U[N][(ncx-1)(ncy-1)] and the MC mean/variance."""
+    N = S.shape[0]
+    assert S.dtype == torch.float64 and S.shape == (N, ncx * ncy, 10)
+    nU = (ncx - 1) * (ncy - 1)
+    dev = S.device
+    if U is None:
+        U = torch.empty((N, nU), dtype=torch.float64, device=dev)
+    if qoi_mean is None:
+        qoi_mean = torch.empty(nU, dtype=torch.float64, device=dev)
+    if qoi_var is None:
+        qoi_var = torch.empty(nU, dtype=torch.float64, device=dev)
+    if load is not None:
+        assert load.dtype == torch.float64 and load.shape == (ncx * ncy, 4)
+    _check("stomsfem_coarse_solve", lib().stomsfem_coarse_solve(
+        ncx, ncy, N, _ptr(S), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
+    return U, qoi_mean, qoi_var
+
+
+def workspace_reserve(nbytes: int):
+    _check("stomsfem_workspace_reserve", lib().stomsfem_workspace_reserve(int(nbytes)))
+
+
+def workspace_release():
+    _check("stomsfem_workspace_release", lib().stomsfem_workspace_release())

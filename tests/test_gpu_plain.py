@@ -1,0 +1,176 @@
+"""GPU parity of the plain FP64 path (through the C-ABI) against the CPU oracle.
+
+Tolerances (FP64 path): per (element, sample) pair,
+max_q |S_q - S_q^ref| <= 1e-10 * max_q |S_q^ref|; per sample,
+||U - U^ref||_2 <= 1e-10 ||U^ref||_2.  Both sides solve SPD systems whose
+condition numbers are below 1e5 here, so a correct FP64 implementation lands
+near 1e-13; 1e-10 leaves room for the different elimination orders.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_00693_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STOL = 1e-10
+UTOL = 1e-10
+
+
+def say(msg):
+    print(f"[gpu-plain] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sm():
+    from paper_1607_00693_amd import stomsfem
+
+    assert torch.cuda.is_available()
+    stomsfem.lib()
+    return stomsfem
+
+
+def s_relerr(S, Sref):
+    S, Sref = np.asarray(S), np.asarray(Sref)
+    return (np.abs(S - Sref).max(-1) / np.abs(Sref).max(-1)).max()
+
+
+def u_relerr(U, Uref):
+    return (np.linalg.norm(U - Uref, axis=-1) / np.linalg.norm(Uref, axis=-1)).max()
+
+
+def test_mesh8_end_to_end(sm, orc):
+    wl = W.MESH8
+    say(f"mesh8 end to end: N={wl.nsamples} nc={wl.nc} m={wl.m}")
+    xi = W.uniform_xi(wl.nsamples, wl.nxi, wl.seed)
+    a_ref = orc.coef_bumps(xi, wl.nfine, **wl.coef_params())
+    xi_d = torch.from_numpy(xi).cuda()
+    a = sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(a.cpu().numpy(), a_ref, rtol=1e-14, atol=0)
+    status = torch.full((wl.nsamples, wl.M), 99, dtype=torch.int32, device="cuda")
+    S = sm.upscale(a, wl.nc, wl.nc, wl.m, status=status)
+    U, mean, var = sm.coarse_solve(S, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    S_ref, _, _ = orc.upscale(a_ref, wl.nc, wl.nc, wl.m)
+    U_ref, mean_ref, var_ref = orc.coarse_solve(S_ref, wl.nc, wl.nc)
+    assert (status.cpu().numpy() == 0).all()
+    assert s_relerr(S.cpu().numpy(), S_ref) < STOL
+    assert u_relerr(U.cpu().numpy(), U_ref) < UTOL
+    np.testing.assert_allclose(mean.cpu().numpy(), mean_ref, rtol=UTOL)
+    np.testing.assert_allclose(var.cpu().numpy(), var_ref, rtol=1e-8, atol=1e-12 * np.abs(mean_ref).max() ** 2)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_small_m_ragged(sm, orc, m):
+    # ncx != ncy, a pair count that is not a multiple of the 64-lane wavefront,
+    # log-normal coefficients spanning about four decades
+    ncx, ncy, N = 3, 5, 7
+    say(f"small m ragged: m={m} ncx={ncx} ncy={ncy} N={N}")
+    a_np = W.lognormal_field((N, ncy * m, ncx * m), 1.5, 500 + m)
+    a = torch.from_numpy(a_np).cuda()
+    S = sm.upscale(a, ncx, ncy, m)
+    torch.cuda.synchronize()
+    S_ref, _, _ = orc.upscale(a_np, ncx, ncy, m)
+    assert s_relerr(S.cpu().numpy(), S_ref) < STOL
+
+
+@pytest.mark.parametrize("m", [8, 12, 16, 32])
+def test_reference_kernel(sm, orc, m):
+    ncx, ncy, N = 2, 3, 2
+    say(f"reference kernel: m={m} ncx={ncx} ncy={ncy} N={N}")
+    a_np = W.lognormal_field((N, ncy * m, ncx * m), 1.0, 600 + m)
+    a = torch.from_numpy(a_np).cuda()
+    S = sm.upscale_reference(a, ncx, ncy, m)
+    torch.cuda.synchronize()
+    S_ref, _, _ = orc.upscale(a_np, ncx, ncy, m)
+    assert s_relerr(S.cpu().numpy(), S_ref) < STOL
+
+
+@pytest.mark.parametrize("m", [8, 16, 32])
+def test_dispatch_kernel_matches_oracle(sm, orc, m):
+    ncx, ncy, N = 4, 3, 3
+    say(f"dispatch kernel: m={m} ncx={ncx} ncy={ncy} N={N}")
+    a_np = W.lognormal_field((N, ncy * m, ncx * m), 1.0, 700 + m)
+    a = torch.from_numpy(a_np).cuda()
+    S = sm.upscale(a, ncx, ncy, m)
+    torch.cuda.synchronize()
+    S_ref, _, _ = orc.upscale(a_np, ncx, ncy, m)
+    assert s_relerr(S.cpu().numpy(), S_ref) < STOL
+
+
+def test_float32_coefficients(sm, orc):
+    # FP32 coefficient storage: the solve is still FP64 on the widened values
+    m, nc, N = 8, 3, 4
+    say("float32 coefficients")
+    a32 = W.lognormal_field((N, nc * m, nc * m), 1.0, 800).astype(np.float32)
+    S = sm.upscale(torch.from_numpy(a32).cuda(), nc, nc, m)
+    torch.cuda.synchronize()
+    S_ref, _, _ = orc.upscale(a32.astype(np.float64), nc, nc, m)
+    assert s_relerr(S.cpu().numpy(), S_ref) < STOL
+
+
+def test_bad_pivot_flags_only_that_pair(sm):
+    m, nc, N = 8, 2, 3
+    say("non-positive coefficient status")
+    a_np = W.lognormal_field((N, nc * m, nc * m), 0.5, 900)
+    a_np[1, 3, 12] = -50.0       # sample 1, element K=(1,0)
+    a_np[2, 9, 2] = np.nan       # sample 2, element K=(0,1)
+    a = torch.from_numpy(a_np).cuda()
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    sm.upscale(a, nc, nc, m, status=st)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    expect = np.zeros_like(st)
+    expect[1, 1] = sm.ENOTSPD
+    expect[2, 2] = sm.ENOTSPD
+    np.testing.assert_array_equal(st, expect)
+
+
+def test_empty_and_invalid_arguments(sm):
+    say("empty and invalid arguments")
+    a = torch.empty((0, 16, 16), dtype=torch.float64, device="cuda")
+    S = sm.upscale(a, 2, 2, 8)
+    assert S.shape == (0, 4, 10)
+    with pytest.raises(sm.StomsfemError) as e:
+        sm.upscale(torch.ones((1, 16, 16), dtype=torch.float64, device="cuda"), 2, 2, 8, precision=7)
+    assert e.value.code == sm.EINVAL
+    # host memory is rejected before anything is queued
+    a_host = torch.ones((1, 16, 16), dtype=torch.float64)
+    S_dev = torch.empty((1, 4, 10), dtype=torch.float64, device="cuda")
+    b = sm.Batch(2, 2, 8, sm.F64, 1, a_host.data_ptr(), S_dev.data_ptr(), None)
+    import ctypes
+    rc = sm.lib().stomsfem_upscale(ctypes.byref(b), 1, sm.PREC_F64, sm.BC_LINEAR, None)
+    assert rc == sm.EINVAL
+
+
+@pytest.mark.parametrize("ncx,ncy", [(2, 2), (5, 3), (3, 7), (16, 16)])
+def test_coarse_solve(sm, orc, ncx, ncy):
+    N, m = 5, 4
+    say(f"coarse solve ncx={ncx} ncy={ncy}")
+    a_np = W.lognormal_field((N, ncy * m, ncx * m), 1.0, 1000 + ncx * 10 + ncy)
+    S_ref, _, _ = orc.upscale(a_np, ncx, ncy, m)
+    S = torch.from_numpy(S_ref).cuda()
+    load_np = W.uniform_array((ncx * ncy, 4), 0.0, 1.0, 77)
+    for load in (None, load_np):
+        U, mean, var = sm.coarse_solve(S, ncx, ncy, load=None if load is None else torch.from_numpy(load).cuda())
+        torch.cuda.synchronize()
+        U_ref, mean_ref, var_ref = orc.coarse_solve(S_ref, ncx, ncy, load_vec=load)
+        assert u_relerr(U.cpu().numpy(), U_ref) < UTOL
+        np.testing.assert_allclose(mean.cpu().numpy(), mean_ref, rtol=UTOL, atol=1e-300)
+
+
+def test_coarse_two_by_two_closed_form(sm):
+    # nc = 2, S = K_ref (a == 1), f = 1: U = 3/32
+    say("coarse 2x2 closed form")
+    K = np.array([[4, -1, -2, -1], [-1, 4, -1, -2], [-2, -1, 4, -1], [-1, -2, -1, 4]]) / 6.0
+    Sp = np.array([K[i, j] for (i, j) in [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]])
+    S = torch.from_numpy(np.tile(Sp, (3, 4, 1))).cuda()
+    U, mean, var = sm.coarse_solve(S, 2, 2)
+    torch.cuda.synchronize()
+    assert np.abs(U.cpu().numpy() - 3.0 / 32.0).max() < 1e-15
+    assert abs(var.cpu().numpy()[0]) < 1e-16
