@@ -1,6 +1,353 @@
-// placeholder, replaced by the register-tiled kernel
+// Local upscaling for m = 16 and m = 32: register-tiled sliding-window LDL^T.
+//
+// Mathematics as in upscale_small.hip (Sec. 2.2 eqs. MsFEB and
+// stiffness_local): S_ll' = g^l.K_BB g^l' - sum_j y_j^l y_j^l' / d_j with
+// K_II = L D L^T and y = L^{-1} f, f^l = -K_IB g^l, so the factor is consumed
+// as it is produced and never stored.
+//
+// Layout.  The band of K_II (natural order, half-bandwidth m) is eliminated
+// in panels of T columns.  The live part of the band after a panel is an
+// m x m window = NT x NT tiles of T x T (NT = 4).  Its NT(NT+1)/2 = 10
+// lower-triangle tiles are held in the registers of 10 lanes; a wavefront
+// serves 6 (element, sample) pairs.  Tile ownership is circular: the lane
+// for the residue pair {P, Q} (mod NT) holds whichever of the tiles with row
+// and column indices congruent to P and Q lies in the lower triangle of the
+// current window.  When the window slides by one tile the only tiles that
+// change owner are those leaving through the panel, and their lanes take
+// over the tiles entering at the bottom, so no tile ever moves between
+// lanes.  Per panel:
+//   1. T lanes build the entering matrix rows (9-point stencil from the
+//      coefficient block, Dirichlet lifts as right-hand sides);
+//   2. the lane holding the diagonal tile factors it in registers (LDL^T),
+//      forward-substitutes the right-hand sides and accumulates y y^T / d;
+//   3. the lanes holding the sub-diagonal panel tiles publish them in LDS;
+//      each of the 10 lanes solves a few panel rows against the unit L;
+//   4. every lane applies the rank-T update W_R D^{-1} W_C^T to its tile.
+// Communication inside a wavefront only (LDS plus wave-level ordering).
 #include "common.h"
+
 namespace stomsfem {
-bool tiled_supports(int) { return false; }
-hipError_t launch_upscale_tiled(const UpArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
+
+#define WAVE_SYNC()                                    \
+  do {                                                 \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                   \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+  } while (0)
+
+constexpr int TL_NT = 4;               // tiles per window side
+constexpr int TL_G = 10;               // lanes per pair = NT (NT + 1) / 2
+constexpr int TL_SLOTS = 64 / TL_G;    // pairs per wavefront (6)
+
+template <int M, int T>
+struct TiledLds {
+  static constexpr int NT = TL_NT;
+  static constexpr int FW = (NT + 1) * T;  // rhs window rows
+  double pw[T][M];     // panel rows, transposed: pw[k][rho] = W(row rho of the panel, column k)
+  double L[T][T];      // unit lower factor of the diagonal tile
+  double invd[T];      // 1 / d_k
+  double u[T][3];      // D^{-1} y of the pivot rows
+  double fr[T][5];     // entering rows: diag, W, SE, S, SW couplings
+  double f[FW][3];     // right-hand sides of the live rows (circular)
+  double red[TL_G][13];
+};
+
+template <int M, int T, typename TA>
+__global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
+  constexpr int NT = TL_NT;
+  static_assert(M == NT * T, "window must be NT x NT tiles");
+  constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
+  constexpr int FW = (NT + 1) * T;
+  using Lds = TiledLds<M, T>;
+  __shared__ Lds lds_all[TL_SLOTS];
+
+  const int lane = threadIdx.x;
+  if (lane >= TL_SLOTS * TL_G) return;
+  const int q = lane / TL_G, g = lane - q * TL_G;
+  Lds& sh = lds_all[q];
+  // residue pair {P, Q}, P >= Q, of this lane: g = P (P + 1) / 2 + Q
+  const int P = g >= 6 ? 3 : g >= 3 ? 2 : g >= 1 ? 1 : 0;
+  const int Q = g - P * (P + 1) / 2;
+
+  int64_t p = (int64_t)blockIdx.x * TL_SLOTS + q;
+  const bool valid = p < args.npairs;
+  if (!valid) p = args.npairs - 1;
+  const int Mc = args.ncx * args.ncy;
+  const int64_t s = p / Mc;
+  const int K = (int)(p - s * Mc);
+  const TA* a = (const TA*)args.a + block_offset(s, K, args.ncx, args.ncy, M);
+  const int64_t lda = (int64_t)args.ncx * M;
+
+  double tile[T][T];
+  double sbb[6] = {0, 0, 0, 0, 0, 0};
+  double sc[6] = {0, 0, 0, 0, 0, 0};
+  bool bad = false;
+
+  // ---- g . K_BB g' over the 4(m-1) elements touching the boundary ----
+  for (int e = g; e < 4 * (M - 1); e += TL_G) {
+    int ex, ey;
+    if (e < M) { ex = e; ey = 0; }                         // bottom row
+    else if (e < 2 * M) { ex = e - M; ey = M - 1; }        // top row
+    else if (e < 3 * M - 2) { ex = 0; ey = e - 2 * M + 1; } // left column, corners excluded
+    else { ex = M - 1; ey = e - (3 * M - 2) + 1; }         // right column, corners excluded
+    const double ae = ld(a, ey * lda + ex);
+    int qq = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int lp = l; lp < 3; ++lp) sbb[qq++] += ae * bb_coef(l, lp, ex, ey, M);
+  }
+
+  // ---- entering rows: lane g < T builds row r = T*rt + g ----
+  // coefficient values of the four elements around the node of row r
+  auto load_quad = [&](int r, double* q4) {
+    if (r < NI) {
+      const int ix = r % n, iy = r / n;
+      q4[0] = ld(a, iy * lda + ix);
+      q4[1] = ld(a, iy * lda + ix + 1);
+      q4[2] = ld(a, (iy + 1) * lda + ix);
+      q4[3] = ld(a, (iy + 1) * lda + ix + 1);
+    } else {
+      q4[0] = q4[1] = q4[2] = q4[3] = 0.0;
+    }
+  };
+  // stencil row (lower couplings) into sh.fr[i], right-hand sides into sh.f
+  auto build_row = [&](int r, int i, const double* q4) {
+    double fr[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+    double rhs[3] = {0.0, 0.0, 0.0};
+    if (r < NI) {
+      const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+      const double aSW = q4[0], aSE = q4[1], aNW = q4[2], aNE = q4[3];
+      fr[0] = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+      const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+      const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+      const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0), -(aSW + aSE) * (1.0 / 6.0),
+                            -(aNW + aNE) * (1.0 / 6.0), -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
+                            -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int qx = px + dxs[d], qy = py + dys[d];
+        if (qx == 0 || qx == M || qy == 0 || qy == M) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) rhs[l] -= ks[d] * pcorner(l, qx, qy, M);
+        }
+      }
+      // lower interior neighbours: W (offset 1), SE (n-1), S (n), SW (n+1)
+      if (ix >= 1) fr[1] = ks[0];
+      if (iy >= 1 && ix <= n - 2) fr[2] = ks[5];
+      if (iy >= 1) fr[3] = ks[2];
+      if (iy >= 1 && ix >= 1) fr[4] = ks[4];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sh.fr[i][c] = fr[c];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) sh.f[r % FW][l] = rhs[l];
+  };
+  // original values of tile (row tile rt, column tile rt - dt) from sh.fr
+  auto fresh_tile = [&](int dt) {
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const int delta = T * dt + i - k;
+        double v = 0.0;
+        if (delta == 0) v = sh.fr[i][0];
+        else if (delta == 1) v = sh.fr[i][1];
+        else if (delta == n - 1) v = sh.fr[i][2];
+        else if (delta == n) v = sh.fr[i][3];
+        else if (delta == n + 1) v = sh.fr[i][4];
+        tile[i][k] = v;
+      }
+  };
+
+  // ---- initial window: tiles (R, C), R, C < NT, all original ----
+  {
+    const int R0 = P, C0 = Q;
+    double q4[4];
+    for (int rt = 0; rt < NT; ++rt) {
+      if (g < T) {
+        load_quad(T * rt + g, q4);
+        build_row(T * rt + g, g, q4);
+      }
+      WAVE_SYNC();
+      if (R0 == rt) fresh_tile(R0 - C0);
+      WAVE_SYNC();
+    }
+  }
+
+  // prefetch of the coefficients for the rows entering at panel 0
+  double q4n[4];
+  if (g < T) load_quad(T * NT + g, q4n);
+
+  for (int J = 0; J < NP; ++J) {
+    const int j0 = J % NT;
+    // current tile of this lane: w(X) = J + ((X - J) mod NT)
+    const int wP = J + ((P - j0 + NT) % NT), wQ = J + ((Q - j0 + NT) % NT);
+    const int R = wP > wQ ? wP : wQ, C = wP > wQ ? wQ : wP;
+
+    // 1. rows entering with row tile J + NT; their panel-column tile
+    //    (J+NT, J) has SW, S, SE couplings at columns i, i+1, i+2
+    if (g < T) {
+      const int r = T * (J + NT) + g;
+      double q4[4] = {q4n[0], q4n[1], q4n[2], q4n[3]};
+      if (J + 1 < NP) load_quad(r + T, q4n);
+      build_row(r, g, q4);
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        double v = 0.0;
+        if (k == g) v = sh.fr[g][4];
+        else if (k == g + 1) v = sh.fr[g][3];
+        else if (k == g + 2) v = sh.fr[g][2];
+        sh.pw[k][(NT - 1) * T + g] = v;
+      }
+    }
+    // 2. diagonal tile: in-register LDL^T, forward substitution, y y^T / d
+    if (R == J && C == J) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double d = tile[k][k];
+        bad = bad || !(d > 0.0);
+        const double inv = 1.0 / d;
+        sh.invd[k] = inv;
+#pragma unroll
+        for (int i = k + 1; i < T; ++i) {
+          const double li = tile[i][k] * inv;
+#pragma unroll
+          for (int c = k + 1; c <= i; ++c) tile[i][c] -= li * tile[c][k];
+        }
+#pragma unroll
+        for (int i = k + 1; i < T; ++i) {
+          tile[i][k] *= inv;
+          sh.L[i][k] = tile[i][k];
+        }
+      }
+      double y[T][3];
+#pragma unroll
+      for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          double v = sh.f[(T * J + k) % FW][l];
+#pragma unroll
+          for (int kk = 0; kk < k; ++kk) v -= tile[k][kk] * y[kk][l];
+          y[k][l] = v;
+        }
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double inv = sh.invd[k];
+        const double z0 = y[k][0] * inv, z1 = y[k][1] * inv, z2 = y[k][2] * inv;
+        sc[0] += z0 * y[k][0];
+        sc[1] += z0 * y[k][1];
+        sc[2] += z0 * y[k][2];
+        sc[3] += z1 * y[k][1];
+        sc[4] += z1 * y[k][2];
+        sc[5] += z2 * y[k][2];
+        sh.u[k][0] = z0;
+        sh.u[k][1] = z1;
+        sh.u[k][2] = z2;
+      }
+    } else if (C == J) {
+      // 3a. sub-diagonal panel tile (R, J) -> panel rows (R-J-1)*T ...
+      const int rb = (R - J - 1) * T;
+#pragma unroll
+      for (int i = 0; i < T; ++i)
+#pragma unroll
+        for (int k = 0; k < T; ++k) sh.pw[k][rb + i] = tile[i][k];
+    }
+    WAVE_SYNC();
+    // 3b. panel rows: W = A L^{-T}; rhs -= W u
+    for (int rho = g; rho < NT * T; rho += TL_G) {
+      double w[T];
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        double v = sh.pw[k][rho];
+#pragma unroll
+        for (int kk = 0; kk < k; ++kk) v -= w[kk] * sh.L[k][kk];
+        w[k] = v;
+      }
+      double* fr = sh.f[(T * (J + 1) + rho) % FW];
+      double f0 = fr[0], f1 = fr[1], f2 = fr[2];
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        sh.pw[k][rho] = w[k];
+        f0 -= w[k] * sh.u[k][0];
+        f1 -= w[k] * sh.u[k][1];
+        f2 -= w[k] * sh.u[k][2];
+      }
+      fr[0] = f0;
+      fr[1] = f1;
+      fr[2] = f2;
+    }
+    // 4a. lanes whose tile left through the panel take the entering tile
+    int Rn = R, Cn = C;
+    if (C == J) {
+      Rn = J + NT;
+      Cn = (R == J) ? J + NT : R;
+      fresh_tile(Rn - Cn);
+    }
+    WAVE_SYNC();
+    // 4b. trailing update of the new window [J+1, J+NT]
+    {
+      const int rb = (Rn - J - 1) * T, cb = (Cn - J - 1) * T;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double inv = sh.invd[k];
+        double wr[T], zc[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) wr[i] = sh.pw[k][rb + i];
+#pragma unroll
+        for (int c = 0; c < T; ++c) zc[c] = sh.pw[k][cb + c] * inv;
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+#pragma unroll
+          for (int c = 0; c < T; ++c) tile[i][c] -= wr[i] * zc[c];
+      }
+    }
+    WAVE_SYNC();
+  }
+
+  // ---- reduce the ten lanes' partial energies and write S ----
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    sh.red[g][t] = sbb[t];
+    sh.red[g][6 + t] = sc[t];
+  }
+  sh.red[g][12] = bad ? 1.0 : 0.0;
+  WAVE_SYNC();
+  if (g == 0 && valid) {
+    double t6[6];
+    bool anybad = false;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      double b = 0.0, c = 0.0;
+      for (int h = 0; h < TL_G; ++h) {
+        b += sh.red[h][t];
+        c += sh.red[h][6 + t];
+      }
+      t6[t] = b - c;
+    }
+    for (int h = 0; h < TL_G; ++h) anybad = anybad || sh.red[h][12] != 0.0;
+    const double s3[3][3] = {{t6[0], t6[1], t6[2]}, {t6[1], t6[3], t6[4]}, {t6[2], t6[4], t6[5]}};
+    store_packed(args.S + p * 10, s3);
+    if (args.status) args.status[p] = anybad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+  }
+}
+
+bool tiled_supports(int m) { return m == 16 || m == 32; }
+
+template <int M, int T>
+static hipError_t launch_t(const UpArgs& args, int a_dtype, hipStream_t st) {
+  const int64_t blocks = (args.npairs + TL_SLOTS - 1) / TL_SLOTS;
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+  else
+    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, double>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st) {
+  if (args.m == 16) return launch_t<16, 4>(args, a_dtype, st);
+  if (args.m == 32) return launch_t<32, 8>(args, a_dtype, st);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace stomsfem
