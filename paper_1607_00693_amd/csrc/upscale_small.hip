@@ -17,9 +17,22 @@
 // pivots is fully unrolled, the window lives in registers with static
 // indices, and only the coefficient values are runtime data.  The
 // coefficient block is read row by row (two element rows live at a time).
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 
 namespace stomsfem {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1, so
+// that every index into the register window is a constant.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 template <int M, typename T>
 struct SmallCell {
@@ -39,6 +52,9 @@ struct SmallCell {
   int64_t lda;
 
   __device__ __forceinline__ void load_elem_row(int ey, double* dst) {
+    // keep the scheduler from hoisting every coefficient load of the fully
+    // unrolled elimination to the top (that would hold all m*m values live)
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int ex = 0; ex < M; ++ex) dst[ex] = ld(a, ey * lda + ex);
     // boundary-boundary energy of the elements of this row that touch the boundary
@@ -54,11 +70,12 @@ struct SmallCell {
 
   // Original matrix row r (node (ix, iy), grid node (ix+1, iy+1)) and its
   // right-hand sides -sum_{boundary neighbours} k_rb g^l_b.
-  __device__ __forceinline__ void insert_row(int r) {
-    const int ix = r % n, iy = r / n;
-    const int px = ix + 1, py = iy + 1;
-    if (ix == 0) {  // entering a new grid row: shift the element-row pair
-      if (iy == 0) {
+  template <int r>
+  __device__ __forceinline__ void insert_row() {
+    constexpr int ix = r % n, iy = r / n;
+    constexpr int px = ix + 1, py = iy + 1;
+    if constexpr (ix == 0) {  // entering a new grid row: shift the element-row pair
+      if constexpr (iy == 0) {
         load_elem_row(0, alo);
       } else {
 #pragma unroll
@@ -72,7 +89,7 @@ struct SmallCell {
     const double cS = -(aSW + aSE) * (1.0 / 6.0), cN = -(aNW + aNE) * (1.0 / 6.0);
     const double cSW = -aSW * (1.0 / 3.0), cSE = -aSE * (1.0 / 3.0);
     const double cNW = -aNW * (1.0 / 3.0), cNE = -aNE * (1.0 / 3.0);
-    const int rr = r % WN;
+    constexpr int rr = r % WN;
 #pragma unroll
     for (int c = (r - B > 0 ? r - B : 0); c <= r; ++c) W[rr][c % WN] = 0.0;
     W[rr][r % WN] = diag;
@@ -105,12 +122,13 @@ struct SmallCell {
 
   // Eliminate pivot j: rank-1 update of the window, forward substitution of
   // the right-hand sides, accumulation of y y^T / d.
-  __device__ __forceinline__ void eliminate(int j) {
-    const int jj = j % WN;
+  template <int j>
+  __device__ __forceinline__ void eliminate() {
+    constexpr int jj = j % WN;
     const double d = W[jj][jj];
     ok = ok && (d > 0.0);
     const double inv = 1.0 / d;
-    const int iend = (j + B < NI - 1) ? j + B : NI - 1;
+    constexpr int iend = (j + B < NI - 1) ? j + B : NI - 1;
     double t[WN], l[WN];
 #pragma unroll
     for (int i = j + 1; i <= iend; ++i) {
@@ -147,13 +165,12 @@ struct SmallCell {
       // m = 1: every node is a boundary node
       load_elem_row(0, alo);
     } else {
-#pragma unroll
-      for (int r = 0; r < (B < NI ? B : NI); ++r) insert_row(r);
-#pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        if (j + B < NI) insert_row(j + B);
-        eliminate(j);
-      }
+      static_for<0, (B < NI ? B : NI)>([&](auto r) { insert_row<decltype(r)::value>(); });
+      static_for<0, NI>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j + B < NI) insert_row<j + B>();
+        eliminate<j>();
+      });
     }
     double s[3][3];
 #pragma unroll

@@ -39,18 +39,44 @@ constexpr int TL_NT = 4;               // tiles per window side
 constexpr int TL_G = 10;               // lanes per pair = NT (NT + 1) / 2
 constexpr int TL_SLOTS = 64 / TL_G;    // pairs per wavefront (6)
 
+// Per-pair LDS block, kept small: occupancy is limited by LDS (seven
+// wavefronts per CU at m = 32).  TL_PAD > 0 would stagger the panel row
+// blocks over the LDS banks, but costs one wavefront per CU, which was
+// measured to matter more.  The block size is padded to 80 mod 128 bytes so
+// that the six pairs of a wavefront start on different banks.
+constexpr int TL_PAD = 0;
+
 template <int M, int T>
-struct TiledLds {
+struct TiledLdsCore {
   static constexpr int NT = TL_NT;
   static constexpr int FW = (NT + 1) * T;  // rhs window rows
-  double pw[T][M];     // panel rows, transposed: pw[k][rho] = W(row rho of the panel, column k)
-  double L[T][T];      // unit lower factor of the diagonal tile
-  double invd[T];      // 1 / d_k
-  double u[T][3];      // D^{-1} y of the pivot rows
-  double fr[T][5];     // entering rows: diag, W, SE, S, SW couplings
-  double f[FW][3];     // right-hand sides of the live rows (circular)
-  double red[TL_G][13];
+  union {
+    double pw[T][NT][T + TL_PAD];  // panel rows: pw[k][R'][i] = W(row R'*T+i of the panel, column k)
+    double red[TL_G][13];          // final reduction (after the last panel)
+  };
+  double L[T * (T - 1) / 2];  // strict lower part of the unit factor of the diagonal tile, row-packed
+  double invd[T];             // 1 / d_k
+  double fr[T][2];            // entering rows: diagonal and W couplings
+  double fx[4];               // entering rows: SE of rows T-2, T-1 and S of row T-1 (+ pad)
+  double f[FW][3];            // right-hand sides of the live rows (circular); the pivot
+                              // rows' slots hold D^{-1} y once the diagonal tile is factored
 };
+
+template <int M, int T>
+struct TiledLds : TiledLdsCore<M, T> {
+  static constexpr int PADB = ((80 - (int)(sizeof(TiledLdsCore<M, T>) % 128)) + 128) % 128;
+  char pad[PADB == 0 ? 128 : PADB];
+};
+
+// 1/d by Newton's iteration on the hardware reciprocal estimate (two steps
+// take the estimate to full double precision).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 
 template <int M, int T, typename TA>
 __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
@@ -79,24 +105,8 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
   const int64_t lda = (int64_t)args.ncx * M;
 
   double tile[T][T];
-  double sbb[6] = {0, 0, 0, 0, 0, 0};
   double sc[6] = {0, 0, 0, 0, 0, 0};
   bool bad = false;
-
-  // ---- g . K_BB g' over the 4(m-1) elements touching the boundary ----
-  for (int e = g; e < 4 * (M - 1); e += TL_G) {
-    int ex, ey;
-    if (e < M) { ex = e; ey = 0; }                         // bottom row
-    else if (e < 2 * M) { ex = e - M; ey = M - 1; }        // top row
-    else if (e < 3 * M - 2) { ex = 0; ey = e - 2 * M + 1; } // left column, corners excluded
-    else { ex = M - 1; ey = e - (3 * M - 2) + 1; }         // right column, corners excluded
-    const double ae = ld(a, ey * lda + ex);
-    int qq = 0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int lp = l; lp < 3; ++lp) sbb[qq++] += ae * bb_coef(l, lp, ex, ey, M);
-  }
 
   // ---- entering rows: lane g < T builds row r = T*rt + g ----
   // coefficient values of the four elements around the node of row r
@@ -111,53 +121,69 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
       q4[0] = q4[1] = q4[2] = q4[3] = 0.0;
     }
   };
-  // stencil row (lower couplings) into sh.fr[i], right-hand sides into sh.f
-  auto build_row = [&](int r, int i, const double* q4) {
-    double fr[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+  // stencil row r (tile row i): diagonal and W coupling into sh.fr[i], the
+  // far-band couplings SE, S of the last two rows into sh.fx, right-hand
+  // sides into sh.f; fr[] returns (D, W, SE, S, SW) to the caller.
+  auto build_row = [&](int r, int i, const double* q4, double* fr) {
+    fr[0] = 1.0;
+    fr[1] = fr[2] = fr[3] = fr[4] = 0.0;
     double rhs[3] = {0.0, 0.0, 0.0};
     if (r < NI) {
       const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
       const double aSW = q4[0], aSE = q4[1], aNW = q4[2], aNE = q4[3];
       fr[0] = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
-      const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-      const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+      constexpr int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+      constexpr int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
       const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0), -(aSW + aSE) * (1.0 / 6.0),
                             -(aNW + aNE) * (1.0 / 6.0), -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
                             -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
+      constexpr double hinv = 1.0 / M;
 #pragma unroll
       for (int d = 0; d < 8; ++d) {
         const int qx = px + dxs[d], qy = py + dys[d];
-        if (qx == 0 || qx == M || qy == 0 || qy == M) {
-#pragma unroll
-          for (int l = 0; l < 3; ++l) rhs[l] -= ks[d] * pcorner(l, qx, qy, M);
-        }
+        const bool bnd = qx == 0 || qx == M || qy == 0 || qy == M;
+        const double x = qx * hinv, y = qy * hinv;
+        const double k = bnd ? ks[d] : 0.0;
+        rhs[0] -= k * ((1.0 - x) * (1.0 - y));
+        rhs[1] -= k * (x * (1.0 - y));
+        rhs[2] -= k * (x * y);
       }
       // lower interior neighbours: W (offset 1), SE (n-1), S (n), SW (n+1)
-      if (ix >= 1) fr[1] = ks[0];
-      if (iy >= 1 && ix <= n - 2) fr[2] = ks[5];
-      if (iy >= 1) fr[3] = ks[2];
-      if (iy >= 1 && ix >= 1) fr[4] = ks[4];
+      fr[1] = ix >= 1 ? ks[0] : 0.0;
+      fr[2] = (iy >= 1 && ix <= n - 2) ? ks[5] : 0.0;
+      fr[3] = iy >= 1 ? ks[2] : 0.0;
+      fr[4] = (iy >= 1 && ix >= 1) ? ks[4] : 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) sh.fr[i][c] = fr[c];
+    sh.fr[i][0] = fr[0];
+    sh.fr[i][1] = fr[1];
+    if (i == T - 2) sh.fx[0] = fr[2];
+    if (i == T - 1) {
+      sh.fx[1] = fr[2];
+      sh.fx[2] = fr[3];
+    }
 #pragma unroll
     for (int l = 0; l < 3; ++l) sh.f[r % FW][l] = rhs[l];
   };
   // original values of tile (row tile rt, column tile rt - dt) from sh.fr
+  // Couplings sit at three tile offsets: dt = 0 (diagonal and W), dt = 1
+  // (the W coupling of the tile's first row, which lies in the previous
+  // column tile) and dt = NT-1 (SE and S at the far end of the band).
   auto fresh_tile = [&](int dt) {
+    const bool d0 = dt == 0, d1 = dt == 1, dl = dt == NT - 1;
 #pragma unroll
     for (int i = 0; i < T; ++i)
 #pragma unroll
-      for (int k = 0; k < T; ++k) {
-        const int delta = T * dt + i - k;
-        double v = 0.0;
-        if (delta == 0) v = sh.fr[i][0];
-        else if (delta == 1) v = sh.fr[i][1];
-        else if (delta == n - 1) v = sh.fr[i][2];
-        else if (delta == n) v = sh.fr[i][3];
-        else if (delta == n + 1) v = sh.fr[i][4];
-        tile[i][k] = v;
-      }
+      for (int k = 0; k < T; ++k) tile[i][k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      tile[i][i] = d0 ? sh.fr[i][0] : 0.0;
+      if (i >= 1) tile[i][i - 1] = d0 ? sh.fr[i][1] : 0.0;
+    }
+    tile[0][T - 1] = d1 ? sh.fr[0][1] : 0.0;      // offset 1 (W) across the tile edge
+    static_assert(T >= 3 && NT >= 3 && T * (NT - 1) == M - T, "band edge inside one tile column");
+    tile[T - 2][0] = dl ? sh.fx[0] : 0.0;  // offset n-1 (SE)
+    tile[T - 1][1] = dl ? sh.fx[1] : 0.0;
+    tile[T - 1][0] = dl ? sh.fx[2] : 0.0;  // offset n (S)
   };
 
   // ---- initial window: tiles (R, C), R, C < NT, all original ----
@@ -166,8 +192,9 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
     double q4[4];
     for (int rt = 0; rt < NT; ++rt) {
       if (g < T) {
+        double frv[5];
         load_quad(T * rt + g, q4);
-        build_row(T * rt + g, g, q4);
+        build_row(T * rt + g, g, q4, frv);
       }
       WAVE_SYNC();
       if (R0 == rt) fresh_tile(R0 - C0);
@@ -191,14 +218,15 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
       const int r = T * (J + NT) + g;
       double q4[4] = {q4n[0], q4n[1], q4n[2], q4n[3]};
       if (J + 1 < NP) load_quad(r + T, q4n);
-      build_row(r, g, q4);
+      double frv[5];
+      build_row(r, g, q4, frv);
 #pragma unroll
       for (int k = 0; k < T; ++k) {
         double v = 0.0;
-        if (k == g) v = sh.fr[g][4];
-        else if (k == g + 1) v = sh.fr[g][3];
-        else if (k == g + 2) v = sh.fr[g][2];
-        sh.pw[k][(NT - 1) * T + g] = v;
+        if (k == g) v = frv[4];
+        else if (k == g + 1) v = frv[3];
+        else if (k == g + 2) v = frv[2];
+        sh.pw[k][NT - 1][g] = v;
       }
     }
     // 2. diagonal tile: in-register LDL^T, forward substitution, y y^T / d
@@ -207,7 +235,7 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
       for (int k = 0; k < T; ++k) {
         const double d = tile[k][k];
         bad = bad || !(d > 0.0);
-        const double inv = 1.0 / d;
+        const double inv = recip(d);
         sh.invd[k] = inv;
 #pragma unroll
         for (int i = k + 1; i < T; ++i) {
@@ -218,7 +246,7 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
 #pragma unroll
         for (int i = k + 1; i < T; ++i) {
           tile[i][k] *= inv;
-          sh.L[i][k] = tile[i][k];
+          sh.L[i * (i - 1) / 2 + k] = tile[i][k];
         }
       }
       double y[T][3];
@@ -241,41 +269,74 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
         sc[3] += z1 * y[k][1];
         sc[4] += z1 * y[k][2];
         sc[5] += z2 * y[k][2];
-        sh.u[k][0] = z0;
-        sh.u[k][1] = z1;
-        sh.u[k][2] = z2;
+        double* fu = sh.f[(T * J + k) % FW];
+        fu[0] = z0;
+        fu[1] = z1;
+        fu[2] = z2;
       }
     } else if (C == J) {
       // 3a. sub-diagonal panel tile (R, J) -> panel rows (R-J-1)*T ...
-      const int rb = (R - J - 1) * T;
+      const int rb = R - J - 1;
 #pragma unroll
       for (int i = 0; i < T; ++i)
 #pragma unroll
-        for (int k = 0; k < T; ++k) sh.pw[k][rb + i] = tile[i][k];
+        for (int k = 0; k < T; ++k) sh.pw[k][rb][i] = tile[i][k];
     }
     WAVE_SYNC();
-    // 3b. panel rows: W = A L^{-T}; rhs -= W u
-    for (int rho = g; rho < NT * T; rho += TL_G) {
-      double w[T];
+    // 3b. panel rows: W = A L^{-T}; rhs -= W u.  Each lane owns rows
+    // rho = g + 10 t and solves them one at a time (solving two at a time
+    // saves LDS reads of L and u but exceeds the register budget at T = 8).
+    {
+      constexpr int NR = NT * T, RPL = (NR + TL_G - 1) / TL_G, CH = 1;
+#pragma unroll 1
+      for (int t0 = 0; t0 < RPL; t0 += CH) {
+        double w[CH][T], fa[CH][3];
+        int rows[CH];
+        bool oks[CH];
 #pragma unroll
-      for (int k = 0; k < T; ++k) {
-        double v = sh.pw[k][rho];
+        for (int c = 0; c < CH; ++c) {
+          const int t = t0 + c;
+          const int rho = g + TL_G * t;
+          oks[c] = t < RPL && ((t + 1) * TL_G <= NR || rho < NR);
+          rows[c] = oks[c] ? rho : 0;
 #pragma unroll
-        for (int kk = 0; kk < k; ++kk) v -= w[kk] * sh.L[k][kk];
-        w[k] = v;
+          for (int k = 0; k < T; ++k) w[c][k] = sh.pw[k][rows[c] / T][rows[c] % T];
+          const double* fr = sh.f[(T * (J + 1) + rows[c]) % FW];
+          fa[c][0] = fr[0];
+          fa[c][1] = fr[1];
+          fa[c][2] = fr[2];
+        }
+#pragma unroll
+        for (int k = 1; k < T; ++k)
+#pragma unroll
+          for (int kk = 0; kk < k; ++kk) {
+            const double lkk = sh.L[k * (k - 1) / 2 + kk];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) w[c][k] -= w[c][kk] * lkk;
+          }
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+          const double* fu = sh.f[(T * J + k) % FW];
+          const double u0 = fu[0], u1 = fu[1], u2 = fu[2];
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            fa[c][0] -= w[c][k] * u0;
+            fa[c][1] -= w[c][k] * u1;
+            fa[c][2] -= w[c][k] * u2;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (!oks[c]) continue;
+          const int rho = rows[c];
+#pragma unroll
+          for (int k = 0; k < T; ++k) sh.pw[k][rho / T][rho % T] = w[c][k];
+          double* fr = sh.f[(T * (J + 1) + rho) % FW];
+          fr[0] = fa[c][0];
+          fr[1] = fa[c][1];
+          fr[2] = fa[c][2];
+        }
       }
-      double* fr = sh.f[(T * (J + 1) + rho) % FW];
-      double f0 = fr[0], f1 = fr[1], f2 = fr[2];
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        sh.pw[k][rho] = w[k];
-        f0 -= w[k] * sh.u[k][0];
-        f1 -= w[k] * sh.u[k][1];
-        f2 -= w[k] * sh.u[k][2];
-      }
-      fr[0] = f0;
-      fr[1] = f1;
-      fr[2] = f2;
     }
     // 4a. lanes whose tile left through the panel take the entering tile
     int Rn = R, Cn = C;
@@ -287,15 +348,15 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
     WAVE_SYNC();
     // 4b. trailing update of the new window [J+1, J+NT]
     {
-      const int rb = (Rn - J - 1) * T, cb = (Cn - J - 1) * T;
+      const int rb = Rn - J - 1, cb = Cn - J - 1;
 #pragma unroll
       for (int k = 0; k < T; ++k) {
         const double inv = sh.invd[k];
         double wr[T], zc[T];
 #pragma unroll
-        for (int i = 0; i < T; ++i) wr[i] = sh.pw[k][rb + i];
+        for (int i = 0; i < T; ++i) wr[i] = sh.pw[k][rb][i];
 #pragma unroll
-        for (int c = 0; c < T; ++c) zc[c] = sh.pw[k][cb + c] * inv;
+        for (int c = 0; c < T; ++c) zc[c] = sh.pw[k][cb][c] * inv;
 #pragma unroll
         for (int i = 0; i < T; ++i)
 #pragma unroll
@@ -303,6 +364,23 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
       }
     }
     WAVE_SYNC();
+  }
+
+  // ---- g . K_BB g' over the 4(m-1) elements touching the boundary ----
+  // (done after the elimination so that these sums are not live across it)
+  double sbb[6] = {0, 0, 0, 0, 0, 0};
+  for (int e = g; e < 4 * (M - 1); e += TL_G) {
+    int ex, ey;
+    if (e < M) { ex = e; ey = 0; }                         // bottom row
+    else if (e < 2 * M) { ex = e - M; ey = M - 1; }        // top row
+    else if (e < 3 * M - 2) { ex = 0; ey = e - 2 * M + 1; } // left column, corners excluded
+    else { ex = M - 1; ey = e - (3 * M - 2) + 1; }         // right column, corners excluded
+    const double ae = ld(a, ey * lda + ex);
+    int qq = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int lp = l; lp < 3; ++lp) sbb[qq++] += ae * bb_coef(l, lp, ex, ey, M);
   }
 
   // ---- reduce the ten lanes' partial energies and write S ----
