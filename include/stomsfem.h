@@ -139,6 +139,49 @@ int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* st
 int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
                           double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Reduced-basis acceleration (Sec. 3.2: eqs. KLphi, localRB, localRBsystem,
+ * RBaffine/localAF; Algorithms 3 and 4).
+ *
+ * stomsfem_reduce (offline, Algorithm 3): from the training coefficient
+ * samples `train` (S and status are not used and may be NULL), solve the cell
+ * problems for phi^l, l = 0..2, and per patch K form the mean phibar^l and
+ * the KL expansion of the centred phi^l in the energy inner product of
+ * K_II(abar) (abar = training mean of the coefficient), with one shared basis
+ * for the three l.  r_K = min(r_max, smallest r whose relative tail
+ * sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol).  The model stores,
+ * per patch and fine element e, the P = r(r+1)/2 + 3r + 6 coefficients that
+ * make the online Galerkin system a linear function of the coefficient
+ * values a_e (the Q1 stiffness is affine in a_e).  Requires 2 <= m <= 16 and
+ * 1 <= r_max <= 8.  Allocates device memory (owned by the model) and
+ * synchronises `stream` before returning.
+ *
+ * stomsfem_reduce_apply (online, Algorithm 4): S_rb for every pair of
+ * `batch` (same ncx, ncy, m as the training batch):
+ *   [A, Fh, B] = a_K^T G_K,   S_ll' = B_ll' - Fh_l . A^{-1} Fh_l'
+ * precision STOMSFEM_PREC_F32_REFINE64 (the default online stage, m = 8):
+ * FP32 MFMA GEMM with FP32 accumulation, FP64 r x r solve;
+ * STOMSFEM_PREC_F64: FP64 throughout (reference).  Per-pair status ENOTSPD
+ * if the r x r system is not positive definite.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+typedef struct stomsfem_model stomsfem_model;
+
+int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,
+                    void* stream);
+int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
+                          void* stream);
+
+/* Copy model data to host memory (synchronous).  which:
+ *   0 = r per patch        (int32  [ncy*ncx])
+ *   1 = eigenvalues lambda (double [ncy*ncx][(m-1)^2], descending)
+ *   2 = modes Z            (double [ncy*ncx][(m-1)^2][8], columns >= r_K are 0)
+ *   3 = means phibar       (double [ncy*ncx][3][(m-1)^2])
+ * bytes must equal the size of the array. */
+int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host_dst, int64_t bytes);
+
+/* Free a model (synchronous with respect to the device). */
+int stomsfem_model_free(stomsfem_model* model);
+
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample
  * in flight).  Calls made after a large enough reservation allocate nothing.

@@ -5,6 +5,7 @@
 #include <unordered_map>
 
 #include "common.h"
+#include "rb.h"
 
 namespace stomsfem {
 hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
@@ -118,6 +119,37 @@ UpArgs to_args(const stomsfem_batch& b) {
 
 }  // namespace
 
+// Library-owned model (reduced basis).  All arrays live on `device`.
+struct stomsfem_model {
+  int kind = 0;  // 1 = reduced basis
+  int device = 0;
+  int ncx = 0, ncy = 0, m = 0, rmax = 8, KD = 0, PP = 0;
+  int32_t* rK = nullptr;
+  double* lambda = nullptr;
+  double* Z = nullptr;
+  double* phibar = nullptr;
+  float* G32 = nullptr;
+  double* G64 = nullptr;
+};
+
+namespace {
+void model_release(stomsfem_model* md) {
+  if (!md) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(md->device);
+  hipDeviceSynchronize();
+  hipFree(md->rK);
+  hipFree(md->lambda);
+  hipFree(md->Z);
+  hipFree(md->phibar);
+  hipFree(md->G32);
+  hipFree(md->G64);
+  hipSetDevice(cur);
+  delete md;
+}
+}  // namespace
+
 extern "C" {
 
 int stomsfem_version(void) { return STOMSFEM_ABI_VERSION; }
@@ -191,6 +223,133 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
   hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
                                (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve launch");
+}
+
+int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,
+                    void* stream) {
+  if (!train || !model) return fail(STOMSFEM_EINVAL, "reduce: NULL argument");
+  *model = nullptr;
+  const stomsfem_batch& b = *train;
+  if (b.ncx < 1 || b.ncy < 1 || b.m < 2 || b.m > 16) return fail(STOMSFEM_EINVAL, "reduce: need 2 <= m <= 16");
+  if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, "reduce: bad a_dtype");
+  if (b.nsamples < 1) return fail(STOMSFEM_EINVAL, "reduce: need at least one training sample");
+  if (r_max < 1 || r_max > 8) return fail(STOMSFEM_EINVAL, "reduce: r_max must be in 1..8");
+  if (!(tail_tol >= 0.0)) return fail(STOMSFEM_EINVAL, "reduce: tail_tol must be >= 0");
+  if (!device_ptr(b.a)) return fail(STOMSFEM_EINVAL, "reduce: a is not a device pointer");
+  const int m = b.m, nI = (m - 1) * (m - 1), Mc = b.ncx * b.ncy;
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 1;
+  hipGetDevice(&md->device);
+  md->ncx = b.ncx;
+  md->ncy = b.ncy;
+  md->m = m;
+  md->rmax = 8;
+  md->KD = rb_pad_kd(m);
+  md->PP = rb_pad_p(md->rmax);
+  double* phi = nullptr;
+  double* work = nullptr;
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->rK, sizeof(int32_t) * Mc);
+  A((void**)&md->lambda, sizeof(double) * Mc * nI);
+  A((void**)&md->Z, sizeof(double) * (size_t)Mc * nI * md->rmax);
+  A((void**)&md->phibar, sizeof(double) * (size_t)Mc * 3 * nI);
+  A((void**)&md->G32, sizeof(float) * (size_t)Mc * md->KD * md->PP);
+  A((void**)&md->G64, sizeof(double) * (size_t)Mc * md->KD * md->PP);
+  A((void**)&phi, sizeof(double) * (size_t)b.nsamples * Mc * 3 * nI);
+  A((void**)&work, sizeof(double) * (size_t)Mc * 4 * nI * nI);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(phi);
+    hipFree(work);
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "reduce: device allocation failed");
+  }
+  UpArgs up = to_args(b);
+  e = launch_cell_phi(up, b.a_dtype, phi, st);
+  if (e == hipSuccess) {
+    RbBuildArgs ba{};
+    ba.ncx = b.ncx;
+    ba.ncy = b.ncy;
+    ba.m = m;
+    ba.ntrain = (int32_t)b.nsamples;
+    ba.rmax = md->rmax;
+    ba.rcap = r_max;
+    ba.tail_tol = tail_tol;
+    ba.a = b.a;
+    ba.a_dtype = b.a_dtype;
+    ba.phi = phi;
+    ba.work = work;
+    ba.Z = md->Z;
+    ba.phibar = md->phibar;
+    ba.lambda = md->lambda;
+    ba.rK = md->rK;
+    ba.G32 = md->G32;
+    ba.G64 = md->G64;
+    ba.KD = md->KD;
+    ba.PP = md->PP;
+    ba.max_sweeps = 30;
+    e = launch_rb_build(ba, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(phi);
+  hipFree(work);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "reduce");
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
+                          void* stream) {
+  if (!model || !batch) return fail(STOMSFEM_EINVAL, "reduce_apply: NULL argument");
+  if (model->kind != 1) return fail(STOMSFEM_EINVAL, "reduce_apply: not a reduced-basis model");
+  int rc = check_batch(*batch, 0);
+  if (rc != STOMSFEM_OK) return rc;
+  if (batch->ncx != model->ncx || batch->ncy != model->ncy || batch->m != model->m)
+    return fail(STOMSFEM_EINVAL, "reduce_apply: batch mesh differs from the model's");
+  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64)
+    return fail(STOMSFEM_EINVAL, "reduce_apply: bad precision");
+  const bool f64 = precision == STOMSFEM_PREC_F64;
+  if (!f64 && model->m != 8) return fail(STOMSFEM_EINVAL, "reduce_apply: the MFMA online stage needs m = 8");
+  if (batch->nsamples == 0) return STOMSFEM_OK;
+  RbApplyArgs ra{};
+  ra.up = to_args(*batch);
+  ra.rmax = model->rmax;
+  ra.KD = model->KD;
+  ra.PP = model->PP;
+  ra.rK = model->rK;
+  ra.G32 = model->G32;
+  ra.G64 = model->G64;
+  hipError_t e = launch_rb_apply(ra, batch->a_dtype, f64, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "reduce_apply launch");
+}
+
+int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host_dst, int64_t bytes) {
+  if (!model || !host_dst) return fail(STOMSFEM_EINVAL, "model_export: NULL argument");
+  const int Mc = model->ncx * model->ncy, nI = (model->m - 1) * (model->m - 1);
+  const void* src = nullptr;
+  int64_t need = 0;
+  switch (which) {
+    case 0: src = model->rK; need = 4LL * Mc; break;
+    case 1: src = model->lambda; need = 8LL * Mc * nI; break;
+    case 2: src = model->Z; need = 8LL * Mc * nI * model->rmax; break;
+    case 3: src = model->phibar; need = 8LL * Mc * 3 * nI; break;
+    default: return fail(STOMSFEM_EINVAL, "model_export: unknown array");
+  }
+  if (bytes != need) return fail(STOMSFEM_EINVAL, "model_export: size mismatch, expected " + std::to_string(need));
+  hipError_t e = hipMemcpy(host_dst, src, (size_t)need, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "model_export");
+}
+
+int stomsfem_model_free(stomsfem_model* model) {
+  model_release(model);
+  return STOMSFEM_OK;
 }
 
 int stomsfem_workspace_reserve(int64_t bytes) {

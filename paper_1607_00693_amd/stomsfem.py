@@ -64,6 +64,10 @@ def lib():
         "stomsfem_upscale_reference": (C.c_int, [C.POINTER(Batch), i32, vp]),
         "stomsfem_coarse_solve": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_workspace_reserve": (C.c_int, [i64]),
+        "stomsfem_reduce": (C.c_int, [C.POINTER(Batch), i32, dbl, C.POINTER(vp), vp]),
+        "stomsfem_reduce_apply": (C.c_int, [vp, C.POINTER(Batch), i32, vp]),
+        "stomsfem_model_export": (C.c_int, [vp, i32, vp, i64]),
+        "stomsfem_model_free": (C.c_int, [vp]),
         "stomsfem_workspace_release": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
@@ -175,3 +179,58 @@ def workspace_reserve(nbytes: int):
 
 def workspace_release():
     _check("stomsfem_workspace_release", lib().stomsfem_workspace_release())
+
+
+class Model:
+    """Owns a library model handle (freed with stomsfem_model_free)."""
+
+    def __init__(self, handle, ncx, ncy, m):
+        self.handle = handle
+        self.ncx, self.ncy, self.m = ncx, ncy, m
+
+    def free(self):
+        if self.handle:
+            lib().stomsfem_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self, which: str):
+        import numpy as np
+
+        M = self.ncx * self.ncy
+        nI = (self.m - 1) ** 2
+        spec = {"r": (0, np.int32, (M,)), "lambda": (1, np.float64, (M, nI)),
+                "Z": (2, np.float64, (M, nI, 8)), "phibar": (3, np.float64, (M, 3, nI))}
+        code, dt, shape = spec[which]
+        out = np.zeros(shape, dtype=dt)
+        _check("stomsfem_model_export", lib().stomsfem_model_export(
+            self.handle, code, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+
+def reduce(a_train: torch.Tensor, ncx: int, ncy: int, m: int, r_max: int = 8, tail_tol: float = 1e-6,
+           stream=None) -> Model:
+    """Offline reduced-basis build from training coefficients [Ntr][ncy*m][ncx*m]."""
+    N = a_train.shape[0]
+    assert a_train.shape[1:] == (ncy * m, ncx * m)
+    b = Batch(ncx, ncy, m, _DT[a_train.dtype], N, _ptr(a_train), None, None)
+    h = C.c_void_p()
+    _check("stomsfem_reduce", lib().stomsfem_reduce(C.byref(b), r_max, tail_tol, C.byref(h), _stream(stream)))
+    return Model(h, ncx, ncy, m)
+
+
+def reduce_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,
+                 status: torch.Tensor | None = None, precision: int = PREC_F32_REFINE64, stream=None):
+    """Online reduced-basis upscaling S[N][M][10] for coefficient samples a."""
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, model.ncx * model.ncy, 10), dtype=torch.float64, device=a.device)
+    b = make_batch(a, model.ncx, model.ncy, model.m, S, status)
+    _check("stomsfem_reduce_apply", lib().stomsfem_reduce_apply(model.handle, C.byref(b), precision,
+                                                                _stream(stream)))
+    return S

@@ -1,0 +1,111 @@
+"""GPU reduced-basis path (offline build + online stage, through the C-ABI)
+against the reduced-basis oracle and the plain oracle.
+
+Tolerances: the FP64 online stage reproduces the oracle's S_rb to 1e-7
+relative (both build the same energy-KL subspace from the same snapshots;
+the eigen-solvers differ, so agreement is limited by the spectral gap after
+the 8th mode, not by rounding); the FP32 MFMA stage to 2e-4 relative
+(single-precision GEMM with 64-term FP32 accumulation); the coarse solution
+through the reduced path stays within 1e-3 of the plain path.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_00693_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-rb] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sm():
+    from paper_1607_00693_amd import stomsfem
+
+    stomsfem.lib()
+    return stomsfem
+
+
+@pytest.fixture(scope="module")
+def setup(sm, orc):
+    from oracle import rb
+
+    wl = W.MESH8
+    nc, m = 4, 8   # the lower-left 4x4 coarse elements of the 8x8 bump workload
+    ntr = 24
+    xi_tr = W.uniform_xi(ntr, wl.nxi, 2003)
+    xi_te = W.uniform_xi(6, wl.nxi, 1003)
+    a_tr = orc.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())[:, : nc * m, : nc * m].copy()
+    a_te = orc.coef_bumps(xi_te, wl.nfine, **wl.coef_params())[:, : nc * m, : nc * m].copy()
+    say(f"build: nc={nc} m={m} ntrain={ntr}")
+    model = sm.reduce(torch.from_numpy(a_tr).cuda(), nc, nc, m, r_max=8, tail_tol=1e-6)
+    orc_models = []
+    for K in range(nc * nc):
+        kx, ky = K % nc, K // nc
+        orc_models.append(rb.rb_offline(a_tr[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m], r_max=8, tail_tol=1e-6))
+    return dict(nc=nc, m=m, model=model, orc_models=orc_models, a_te=a_te)
+
+
+def _oracle_S(setup, a):
+    from oracle import rb
+    nc, m = setup["nc"], setup["m"]
+    out = np.zeros((a.shape[0], nc * nc, 10))
+    for s in range(a.shape[0]):
+        for K in range(nc * nc):
+            kx, ky = K % nc, K // nc
+            out[s, K] = rb.rb_online_S(setup["orc_models"][K], a[s, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m])
+    return out
+
+
+def rel(S, R):
+    return (np.abs(S - R).max(-1) / np.abs(R).max(-1)).max()
+
+
+def test_rb_offline_matches_oracle(sm, setup):
+    say("offline: r and eigenvalues")
+    r = setup["model"].export("r")
+    lam = setup["model"].export("lambda")
+    for K, om in enumerate(setup["orc_models"]):
+        assert r[K] == om["r"]
+        ref = om["sigma"][:8] ** 2
+        np.testing.assert_allclose(lam[K, :8], ref, rtol=1e-8, atol=1e-12 * ref[0])
+
+
+def test_rb_online_f64_matches_oracle(sm, setup):
+    say("online FP64")
+    a = setup["a_te"]
+    S = sm.reduce_apply(setup["model"], torch.from_numpy(a).cuda(), precision=sm.PREC_F64)
+    torch.cuda.synchronize()
+    assert rel(S.cpu().numpy(), _oracle_S(setup, a)) < 1e-7
+
+
+def test_rb_online_mfma_fp32(sm, orc, setup):
+    say("online FP32 MFMA")
+    a = setup["a_te"]
+    for dt in (torch.float64, torch.float32):
+        st = torch.full((a.shape[0], setup["nc"] ** 2), 99, dtype=torch.int32, device="cuda")
+        S = sm.reduce_apply(setup["model"], torch.from_numpy(a).to(dt).cuda(), status=st)
+        torch.cuda.synchronize()
+        assert (st.cpu().numpy() == 0).all()
+        assert rel(S.cpu().numpy(), _oracle_S(setup, a)) < 2e-4
+    # against the plain path: the reduced-basis error itself
+    S_plain, _, _ = orc.upscale(a, setup["nc"], setup["nc"], setup["m"])
+    assert rel(S.cpu().numpy(), S_plain) < 1e-3
+
+
+def test_rb_coarse_solution_error(sm, orc, setup):
+    say("coarse solution through the reduced path")
+    a = setup["a_te"]
+    nc, m = setup["nc"], setup["m"]
+    S = sm.reduce_apply(setup["model"], torch.from_numpy(a).cuda())
+    U, _, _ = sm.coarse_solve(S, nc, nc)
+    torch.cuda.synchronize()
+    S_plain, _, _ = orc.upscale(a, nc, nc, m)
+    U_plain, _, _ = orc.coarse_solve(S_plain, nc, nc)
+    err = np.linalg.norm(U.cpu().numpy() - U_plain, axis=1) / np.linalg.norm(U_plain, axis=1)
+    assert err.max() < 1e-3
