@@ -1,0 +1,78 @@
+"""Pins of the MLP oracle: finite differences, exact special cases, GELU."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1607_00693_amd import workloads as W
+
+
+def _params(kin, seed, scale=0.5):
+    from oracle import mlp
+    return W.uniform_array(mlp.nparams(kin), -scale, scale, seed)
+
+
+def test_gelu_matches_normal_cdf_definition():
+    from oracle import mlp
+    from scipy.stats import norm
+    z = np.linspace(-6, 6, 101)
+    np.testing.assert_allclose(mlp.gelu(z), z * norm.cdf(z), rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(mlp.gelu_grad(z), norm.cdf(z) + z * norm.pdf(z), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kin", [1, 2, 4])
+def test_gradient_matches_central_differences(kin):
+    from oracle import mlp
+    flat = _params(kin, 10 + kin)
+    X = W.uniform_array((7, kin), -1, 1, 20 + kin)
+    T = W.uniform_array((7, 10), -2, 2, 30 + kin)
+    L, g = mlp.grad(flat, X, T, kin)
+    rng = np.random.default_rng(40 + kin)
+    idx = rng.choice(flat.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(flat)
+        e[i] = h
+        Lp = mlp.loss(mlp.forward(flat + e, X, kin)[0], T)
+        Lm = mlp.loss(mlp.forward(flat - e, X, kin)[0], T)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_zero_weights_give_bias():
+    from oracle import mlp
+    kin = 4
+    ps = mlp.unpack_params(np.zeros(mlp.nparams(kin)), kin)
+    ps[-1] = W.uniform_array(20, -1, 1, 3)
+    Y, _ = mlp.forward(mlp.pack_params(ps), W.uniform_array((5, kin), -1, 1, 4), kin)
+    np.testing.assert_array_equal(Y, np.tile(ps[-1], (5, 1)))
+
+
+def test_adam_first_step_is_signed_lr():
+    # with zero moments, the bias-corrected first Adam step is -lr * sign(g)
+    from oracle import mlp
+    g = W.uniform_array(50, -3, 3, 5)
+    x1, _, _ = mlp.adam_step(np.zeros(50), g, np.zeros(50), np.zeros(50), 1, 0.01, eps=0.0)
+    np.testing.assert_allclose(x1, -0.01 * np.sign(g), rtol=1e-12)
+
+
+def test_gate_accepts_exact_and_rejects_inconsistent(orc):
+    from oracle import mlp
+    a = W.lognormal_field((3, 8, 8), 0.5, 6)
+    S = np.stack([orc.cell_S(b)[0] for b in a])
+    mu, sd = S.mean(0), np.maximum(S.std(0), 1e-3)
+    Y = np.concatenate([(S - mu) / sd, (S - mu) / sd], axis=1)
+    X = np.zeros((3, 4))
+    ok, Sp, resid, unc = mlp.gate(Y, mu, sd, X, 4, 1e-3)
+    assert ok.all() and resid.max() < 1e-12 and unc.max() == 0
+    np.testing.assert_allclose(Sp, S, rtol=0, atol=1e-12 * np.abs(S).max())
+    # perturb one head: disagreement; perturb both alike: row-sum residual
+    Y2 = Y.copy()
+    Y2[0, 10] += 0.1 / sd[0] * np.abs(S[0]).max()
+    Y2[1, [0, 10]] += 0.1 / sd[0] * np.abs(S[1]).max()
+    X2 = X.copy()
+    X2[2, 1] = 1.5
+    ok2, _, resid2, unc2 = mlp.gate(Y2, mu, sd, X2, 4, 1e-3)
+    assert list(ok2) == [False, False, False]
+    assert unc2[0] > 1e-2 and resid2[1] > 1e-2
+    assert mlp.gate(Y2, mu, sd, X2, 1, 1e-3)[0][2]   # out-of-box variable not local => accepted
