@@ -54,8 +54,9 @@ enum { STOMSFEM_F64 = 0, STOMSFEM_F32 = 1 };
 
 /* Arithmetic of the local cell solves. */
 enum {
-  STOMSFEM_PREC_F64 = 0,          /* FP64 factorisation and energies */
-  STOMSFEM_PREC_F32_REFINE64 = 1  /* FP32 factorisation, FP64 residuals and energies */
+  STOMSFEM_PREC_F64 = 0,           /* FP64 factorisation and energies */
+  STOMSFEM_PREC_F32_REFINE64 = 1,  /* FP32 arithmetic where the entry point allows it, FP64 residuals/energies */
+  STOMSFEM_PREC_BF16 = 2           /* BF16 matrix-core products with FP32 accumulation (surrogate) */
 };
 
 /* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
@@ -181,6 +182,89 @@ int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host
 
 /* Free a model (synchronous with respect to the device). */
 int stomsfem_model_free(stomsfem_model* model);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate.  A per-patch multilayer perceptron maps the patch's
+ * local random variables (the xi_j whose mode touches K: the local
+ * parametrization of Sec. 3, eq. MsFEB2, at most 4, zero padded) to the 10
+ * unique entries of S_K: 4 -> 64 -> 64 -> 64 -> 2 x 10, GELU(z) = z Phi(z),
+ * two output heads, targets standardised per patch and entry with the
+ * training mean and standard deviation.  Parameters per patch
+ * (STOMSFEM_MLP_NPARAM floats, row-major, in this order): W1[4][64], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[64][20], b4[20].
+ * Gate per pair (tolerance tau): S = (S_A + S_B)/2 of the heads,
+ *   residual    = max_l |sum_l' S_ll'| / max|S|,
+ *   uncertainty = max|S_A - S_B| / max|S|,
+ * accepted if both <= tau and every local variable lies in [-box, box];
+ * accepted S are projected to zero row sums (S <- P S P, P = I - 1 1^T/4).
+ * Rejected pairs, and 1% of accepted pairs chosen by a hash of the pair index
+ * ((p * 2654435761) mod 100 == 0, p = s*M + K) for auditing, are recomputed
+ * by the plain path (m = 8) with the coefficient regenerated from xi.
+ * ------------------------------------------------------------------------ */
+#define STOMSFEM_MLP_NPARAM 9940
+#define STOMSFEM_MLP_BATCH 32
+
+typedef struct {
+  int32_t g;                             /* g x g bumps */
+  double rho, eps, base, amp, beta;      /* see stomsfem_coef_bumps */
+} stomsfem_bump_family;
+
+/* Local variables of every patch for the bump family (host computation):
+ * local_vars[K][kmax] = the indices j (increasing) of the bumps whose support
+ * contains a fine-element centroid of K, -1 padded; nlocal[K] their number
+ * (may be NULL).  EINVAL if a patch has more than kmax. */
+int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfem_bump_family* fam, int32_t kmax,
+                              int32_t* local_vars, int32_t* nlocal);
+
+/* Create a surrogate (m <= 8): local_vars host [M][4], init_params host
+ * [M][STOMSFEM_MLP_NPARAM] (the caller draws the initial weights), fam = the
+ * coefficient family used by the fallback, box = training box of the local
+ * variables.  Synchronous. */
+int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
+                        const stomsfem_bump_family* fam, double box, stomsfem_model** model);
+
+/* Training pairs from the plain path: xi device [ntrain][nxi], S device
+ * [ntrain][M][10].  Computes the standardisation and the per-patch inputs
+ * and targets (device copies owned by the model). */
+int stomsfem_mlp_set_data(stomsfem_model* model, const double* xi, int32_t nxi, const double* S, int64_t ntrain,
+                          void* stream);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * minibatches of STOMSFEM_MLP_BATCH pairs per patch taken cyclically from
+ * perm (device int64 [ntrain], NULL = identity order); FP32 forward and
+ * backward on the GPU.  loss (device [M], may be NULL) receives the last
+ * minibatch loss per patch. */
+int stomsfem_mlp_train(stomsfem_model* model, int32_t steps, float lr, const int64_t* perm, float* loss, void* stream);
+
+/* Gradient of the loss for one explicit minibatch (no update): xb device
+ * [M][32][4], tb device [M][32][10] (standardised targets), grads device
+ * [M][STOMSFEM_MLP_NPARAM], loss device [M] or NULL. */
+int stomsfem_mlp_grad(const stomsfem_model* model, const float* xb, const float* tb, float* grads, float* loss,
+                      void* stream);
+
+/* Copy the parameters out to dst (any memory) and/or in from src (either may
+ * be NULL); asynchronous on stream. */
+int stomsfem_mlp_params(stomsfem_model* model, float* dst, const float* src, void* stream);
+
+/* Standardisation of the targets (host [M][10] each; either may be NULL). */
+int stomsfem_mlp_standardization(const stomsfem_model* model, double* mu_host, double* sd_host);
+
+/* Raw network outputs Y device [nsamples][M][20] for xi device
+ * [nsamples][nxi]; precision STOMSFEM_PREC_BF16 (matrix cores) or
+ * STOMSFEM_PREC_F32_REFINE64 (FP32 reference). */
+int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
+                         int32_t precision, void* stream);
+
+/* Surrogate upscaling with gate and plain fallback: S device
+ * [nsamples][M][10]; status device [nsamples][M] or NULL: 0 = surrogate
+ * accepted, 1 = recomputed by the plain path (gate), 2 = audited (plain),
+ * STOMSFEM_ENOTSPD from a fallback solve.  stats device uint64[4] or NULL,
+ * accumulated (not cleared): [0] gate rejections, [1] audits, [2] max relative
+ * error max|S_pred - S|/max|S| of rejected predictions, [3] same for audited
+ * accepted ones (as IEEE-754 double bit patterns).  May grow a model-owned
+ * buffer (a synchronous allocation) when nsamples exceeds earlier calls. */
+int stomsfem_upscale_surrogate(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                               int32_t* status, double gate_tol, int32_t precision, uint64_t* stats, void* stream);
 
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample

@@ -6,6 +6,7 @@
 
 #include "common.h"
 #include "rb.h"
+#include "mlp.h"
 
 namespace stomsfem {
 hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
@@ -130,6 +131,24 @@ struct stomsfem_model {
   double* phibar = nullptr;
   float* G32 = nullptr;
   double* G64 = nullptr;
+  // learned surrogate (kind 2)
+  int32_t* lv = nullptr;      // [M][4]
+  float* params = nullptr;    // [M][NP]
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  double* mu = nullptr;       // [M][10]
+  double* sd = nullptr;
+  double* sd_raw = nullptr;
+  float* X = nullptr;         // [M][ntrain][4]
+  float* T = nullptr;         // [M][ntrain][10]
+  int64_t ntrain = 0;
+  int64_t adam_t = 0;
+  double box = 1.0;
+  stomsfem_bump_family fam{};
+  int32_t lv_max = -1;        // largest local-variable index
+  int64_t* list = nullptr;    // fallback list
+  int64_t list_cap = 0;
+  unsigned long long* counter = nullptr;
 };
 
 namespace {
@@ -145,6 +164,17 @@ void model_release(stomsfem_model* md) {
   hipFree(md->phibar);
   hipFree(md->G32);
   hipFree(md->G64);
+  hipFree(md->lv);
+  hipFree(md->params);
+  hipFree(md->m1);
+  hipFree(md->m2);
+  hipFree(md->mu);
+  hipFree(md->sd);
+  hipFree(md->sd_raw);
+  hipFree(md->X);
+  hipFree(md->T);
+  hipFree(md->list);
+  hipFree(md->counter);
   hipSetDevice(cur);
   delete md;
 }
@@ -350,6 +380,259 @@ int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host
 int stomsfem_model_free(stomsfem_model* model) {
   model_release(model);
   return STOMSFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned surrogate
+// ---------------------------------------------------------------------------
+int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfem_bump_family* fam, int32_t kmax,
+                              int32_t* local_vars, int32_t* nlocal) {
+  if (!fam || !local_vars || ncx < 1 || ncy < 1 || m < 1 || kmax < 1 || fam->g < 1 || !(fam->rho > 0))
+    return fail(STOMSFEM_EINVAL, "local_vars_bumps: bad arguments");
+  const int nfx = ncx * m;  // square fine cells of side 1 / (ncx m)
+  const double h = 1.0 / nfx;
+  for (int K = 0; K < ncx * ncy; ++K) {
+    const int kx = K % ncx, ky = K / ncx;
+    int cnt = 0;
+    for (int j = 0; j < fam->g * fam->g; ++j) {
+      const double cx = ((j % fam->g) + 0.5) / fam->g, cy = ((j / fam->g) + 0.5) / fam->g;
+      bool touch = false;
+      for (int ey = 0; ey < m && !touch; ++ey)
+        for (int ex = 0; ex < m && !touch; ++ex) {
+          const double x = (kx * m + ex + 0.5) * h, y = (ky * m + ey + 0.5) * h;
+          const double r2 = ((x - cx) * (x - cx) + (y - cy) * (y - cy)) / (fam->rho * fam->rho);
+          touch = r2 < 1.0;
+        }
+      if (!touch) continue;
+      if (cnt >= kmax) return fail(STOMSFEM_EINVAL, "local_vars_bumps: more than kmax local variables");
+      local_vars[K * kmax + cnt++] = j;
+    }
+    for (int c = cnt; c < kmax; ++c) local_vars[K * kmax + c] = -1;
+    if (nlocal) nlocal[K] = cnt;
+  }
+  return STOMSFEM_OK;
+}
+
+int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
+                        const stomsfem_bump_family* fam, double box, stomsfem_model** model) {
+  if (!local_vars || !init_params || !model) return fail(STOMSFEM_EINVAL, "mlp_create: NULL argument");
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 8) return fail(STOMSFEM_EINVAL, "mlp_create: need 1 <= m <= 8");
+  if (!(box > 0)) return fail(STOMSFEM_EINVAL, "mlp_create: box must be > 0");
+  *model = nullptr;
+  const int Mc = ncx * ncy;
+  auto* md = new stomsfem_model();
+  md->kind = 2;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->box = box;
+  if (fam) md->fam = *fam;
+  for (int i = 0; i < Mc * MLP_KIN; ++i) {
+    if (local_vars[i] < -1) {
+      delete md;
+      return fail(STOMSFEM_EINVAL, "mlp_create: local variable indices must be >= 0 or -1 (padding)");
+    }
+    if (local_vars[i] > md->lv_max) md->lv_max = local_vars[i];
+  }
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->lv, sizeof(int32_t) * Mc * MLP_KIN);
+  A((void**)&md->params, sizeof(float) * (size_t)Mc * MLP_NP);
+  A((void**)&md->m1, sizeof(float) * (size_t)Mc * MLP_NP);
+  A((void**)&md->m2, sizeof(float) * (size_t)Mc * MLP_NP);
+  A((void**)&md->mu, sizeof(double) * Mc * 10);
+  A((void**)&md->sd, sizeof(double) * Mc * 10);
+  A((void**)&md->sd_raw, sizeof(double) * Mc * 10);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemcpy(md->lv, local_vars, sizeof(int32_t) * Mc * MLP_KIN, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->params, init_params, sizeof(float) * (size_t)Mc * MLP_NP, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(md->m1, 0, sizeof(float) * (size_t)Mc * MLP_NP);
+  if (e == hipSuccess) e = hipMemset(md->m2, 0, sizeof(float) * (size_t)Mc * MLP_NP);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "mlp_create: device allocation failed");
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_mlp_set_data(stomsfem_model* model, const double* xi, int32_t nxi, const double* S, int64_t ntrain,
+                          void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_set_data: not a surrogate model");
+  if (ntrain < 1 || nxi < 1) return fail(STOMSFEM_EINVAL, "mlp_set_data: bad sizes");
+  if (model->lv_max >= nxi) return fail(STOMSFEM_EINVAL, "mlp_set_data: nxi smaller than the local variable indices");
+  if (!device_ptr(xi) || !device_ptr(S)) return fail(STOMSFEM_EINVAL, "mlp_set_data: xi and S must be device pointers");
+  const int Mc = model->ncx * model->ncy;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "mlp_set_data");
+  hipFree(model->X);
+  hipFree(model->T);
+  model->X = model->T = nullptr;
+  e = hipMalloc(&model->X, sizeof(float) * (size_t)Mc * ntrain * MLP_KIN);
+  if (e == hipSuccess) e = hipMalloc(&model->T, sizeof(float) * (size_t)Mc * ntrain * 10);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(STOMSFEM_ENOMEM, "mlp_set_data: device allocation failed");
+  }
+  model->ntrain = ntrain;
+  MlpDataArgs d{};
+  d.npatch = Mc;
+  d.nxi = nxi;
+  d.ntrain = ntrain;
+  d.lv = model->lv;
+  d.xi = xi;
+  d.S = S;
+  d.mu = model->mu;
+  d.sd = model->sd;
+  d.sd_raw = model->sd_raw;
+  d.X = model->X;
+  d.T = model->T;
+  e = launch_mlp_data(d, st);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "mlp_set_data launch");
+}
+
+int stomsfem_mlp_train(stomsfem_model* model, int32_t steps, float lr, const int64_t* perm, float* loss, void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_train: not a surrogate model");
+  if (model->ntrain < 1) return fail(STOMSFEM_EINVAL, "mlp_train: no training data (stomsfem_mlp_set_data)");
+  if (steps < 0 || !(lr > 0)) return fail(STOMSFEM_EINVAL, "mlp_train: bad steps or lr");
+  if (perm && !device_ptr(perm)) return fail(STOMSFEM_EINVAL, "mlp_train: perm must be a device pointer");
+  if (loss && !device_ptr(loss)) return fail(STOMSFEM_EINVAL, "mlp_train: loss must be a device pointer");
+  if (steps == 0) return STOMSFEM_OK;
+  MlpTrainArgs t{};
+  t.npatch = model->ncx * model->ncy;
+  t.ntrain = model->ntrain;
+  t.steps = steps;
+  t.t0 = model->adam_t;
+  t.lr = lr;
+  t.params = model->params;
+  t.m1 = model->m1;
+  t.m2 = model->m2;
+  t.X = model->X;
+  t.T = model->T;
+  t.perm = perm;
+  t.loss = loss;
+  hipError_t e = launch_mlp_train(t, true, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp_train launch");
+  model->adam_t += steps;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_mlp_grad(const stomsfem_model* model, const float* xb, const float* tb, float* grads, float* loss,
+                      void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_grad: not a surrogate model");
+  if (!device_ptr(xb) || !device_ptr(tb) || !device_ptr(grads))
+    return fail(STOMSFEM_EINVAL, "mlp_grad: xb, tb and grads must be device pointers");
+  MlpTrainArgs t{};
+  t.npatch = model->ncx * model->ncy;
+  t.ntrain = MLP_BATCH;
+  t.steps = 1;
+  t.params = model->params;
+  t.xb = xb;
+  t.tb = tb;
+  t.grads = grads;
+  t.loss = loss;
+  hipError_t e = launch_mlp_train(t, false, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "mlp_grad launch");
+}
+
+int stomsfem_mlp_params(stomsfem_model* model, float* dst, const float* src, void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_params: not a surrogate model");
+  const size_t bytes = sizeof(float) * (size_t)model->ncx * model->ncy * MLP_NP;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (dst) e = hipMemcpyAsync(dst, model->params, bytes, hipMemcpyDefault, st);
+  if (e == hipSuccess && src) e = hipMemcpyAsync(model->params, src, bytes, hipMemcpyDefault, st);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "mlp_params");
+}
+
+int stomsfem_mlp_standardization(const stomsfem_model* model, double* mu_host, double* sd_host) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_standardization: not a surrogate model");
+  const size_t bytes = sizeof(double) * model->ncx * model->ncy * 10;
+  hipError_t e = hipSuccess;
+  if (mu_host) e = hipMemcpy(mu_host, model->mu, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && sd_host) e = hipMemcpy(sd_host, model->sd, bytes, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "mlp_standardization");
+}
+
+static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
+                            double* S, int32_t* status, double tau, int32_t precision, uint64_t* stats,
+                            void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "surrogate: not a surrogate model");
+  if (nsamples < 0 || nxi < 1) return fail(STOMSFEM_EINVAL, "surrogate: bad sizes");
+  if (model->lv_max >= nxi) return fail(STOMSFEM_EINVAL, "surrogate: nxi smaller than the local variable indices");
+  if (precision != STOMSFEM_PREC_F32_REFINE64 && precision != STOMSFEM_PREC_BF16)
+    return fail(STOMSFEM_EINVAL, "surrogate: precision must be STOMSFEM_PREC_F32_REFINE64 (FP32) or STOMSFEM_PREC_BF16");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi)) return fail(STOMSFEM_EINVAL, "surrogate: xi must be a device pointer");
+  if ((Y && !device_ptr(Y)) || (S && !device_ptr(S)) || (status && !device_ptr(status)) ||
+      (stats && !device_ptr(stats)))
+    return fail(STOMSFEM_EINVAL, "surrogate: outputs must be device pointers");
+  const int Mc = model->ncx * model->ncy;
+  if (S) {
+    if (model->m != 8) return fail(STOMSFEM_EINVAL, "surrogate: the plain fallback is built for m = 8");
+    if (model->fam.g < 1 || model->fam.g * model->fam.g > nxi)
+      return fail(STOMSFEM_EINVAL, "surrogate: the model's coefficient family does not match xi");
+    const int64_t need = nsamples * Mc;
+    if (model->list_cap < need) {
+      hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+      if (e == hipSuccess) {
+        hipFree(model->list);
+        model->list = nullptr;
+        model->list_cap = 0;
+        e = hipMalloc(&model->list, sizeof(int64_t) * need);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STOMSFEM_ENOMEM, "surrogate: fallback list allocation failed");
+      }
+      model->list_cap = need;
+    }
+  }
+  MlpInferArgs a{};
+  a.npatch = Mc;
+  a.ncx = model->ncx;
+  a.nxi = nxi;
+  a.nsamples = nsamples;
+  a.params = model->params;
+  a.lv = model->lv;
+  a.mu = model->mu;
+  a.sd = model->sd;
+  a.xi = xi;
+  a.box = model->box;
+  a.tau = tau;
+  a.Y = Y;
+  a.S = S;
+  a.status = status;
+  a.count = model->counter;
+  a.list = model->list;
+  a.stats = (unsigned long long*)stats;
+  a.bump_g = model->fam.g;
+  a.bump_rho = model->fam.rho;
+  a.bump_eps = model->fam.eps;
+  a.bump_base = model->fam.base;
+  a.bump_amp = model->fam.amp;
+  a.bump_beta = model->fam.beta;
+  hipError_t e = launch_mlp_infer(a, precision == STOMSFEM_PREC_BF16, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "surrogate launch");
+}
+
+int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
+                         int32_t precision, void* stream) {
+  if (!Y) return fail(STOMSFEM_EINVAL, "mlp_predict: NULL Y");
+  return mlp_infer_common(const_cast<stomsfem_model*>(model), xi, nxi, nsamples, Y, nullptr, nullptr, 0.0, precision,
+                          nullptr, stream);
+}
+
+int stomsfem_upscale_surrogate(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                               int32_t* status, double gate_tol, int32_t precision, uint64_t* stats, void* stream) {
+  if (!S) return fail(STOMSFEM_EINVAL, "upscale_surrogate: NULL S");
+  if (!(gate_tol >= 0)) return fail(STOMSFEM_EINVAL, "upscale_surrogate: gate_tol must be >= 0");
+  return mlp_infer_common(model, xi, nxi, nsamples, nullptr, S, status, gate_tol, precision, stats, stream);
 }
 
 int stomsfem_workspace_reserve(int64_t bytes) {

@@ -24,24 +24,12 @@ __global__ __launch_bounds__(256) void coef_bumps_kernel(CoefArgs c) {
   const int64_t per = (int64_t)c.nfine * c.nfine;
   const int64_t total = c.nsamples * per;
   const double h = 1.0 / c.nfine;
-  const double rho2 = c.rho * c.rho;
-  const int reach = (int)ceil(c.rho * c.g);
+  const BumpParams bp{c.g, c.rho, c.eps, c.base, c.amp, c.beta};
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = t / per;
     const int rem = (int)(t - s * per);
     const int iy = rem / c.nfine, ix = rem - iy * c.nfine;
-    const double x = (ix + 0.5) * h, y = (iy + 0.5) * h;
-    const double* xs = c.xi + s * c.nxi;
-    const int bx = min((int)(x * c.g), c.g - 1), by = min((int)(y * c.g), c.g - 1);
-    double field = 0.0;
-    for (int jy = max(by - reach, 0); jy <= min(by + reach, c.g - 1); ++jy)
-      for (int jx = max(bx - reach, 0); jx <= min(bx + reach, c.g - 1); ++jx) {
-        const double cx = (jx + 0.5) / c.g, cy = (jy + 0.5) / c.g;
-        const double r2 = ((x - cx) * (x - cx) + (y - cy) * (y - cy)) / rho2;
-        if (r2 < 1.0) field += xs[jy * c.g + jx] * (1.0 - r2) * (1.0 - r2);
-      }
-    const double osc = c.base + c.amp * sin(2.0 * M_PI * x / c.eps) * sin(2.0 * M_PI * y / c.eps);
-    ((T*)c.a)[t] = (T)(osc * exp(c.beta * field));
+    ((T*)c.a)[t] = (T)bump_coef((ix + 0.5) * h, (iy + 0.5) * h, c.xi + s * c.nxi, bp);
   }
 }
 

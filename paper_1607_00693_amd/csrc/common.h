@@ -81,4 +81,28 @@ __device__ __forceinline__ void store_packed(double* out, const double s[3][3]) 
   out[9] = s33;
 }
 
+// Parameters of the synthetic bump coefficient family (see coef.hip).
+struct BumpParams {
+  int32_t g;
+  double rho, eps, base, amp, beta;
+};
+
+// a(x, xi) of the bump family at the point (x, y), xs = this sample's xi.
+// Only bumps whose centre cell lies within ceil(rho*g) cells are visited, in
+// increasing index order.
+__device__ __forceinline__ double bump_coef(double x, double y, const double* xs, const BumpParams& bp) {
+  const double rho2 = bp.rho * bp.rho;
+  const int reach = (int)ceil(bp.rho * bp.g);
+  const int bx = min((int)(x * bp.g), bp.g - 1), by = min((int)(y * bp.g), bp.g - 1);
+  double field = 0.0;
+  for (int jy = max(by - reach, 0); jy <= min(by + reach, bp.g - 1); ++jy)
+    for (int jx = max(bx - reach, 0); jx <= min(bx + reach, bp.g - 1); ++jx) {
+      const double cx = (jx + 0.5) / bp.g, cy = (jy + 0.5) / bp.g;
+      const double r2 = ((x - cx) * (x - cx) + (y - cy) * (y - cy)) / rho2;
+      if (r2 < 1.0) field += xs[jy * bp.g + jx] * (1.0 - r2) * (1.0 - r2);
+    }
+  const double osc = bp.base + bp.amp * sin(2.0 * M_PI * x / bp.eps) * sin(2.0 * M_PI * y / bp.eps);
+  return osc * exp(bp.beta * field);
+}
+
 }  // namespace stomsfem

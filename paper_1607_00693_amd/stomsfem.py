@@ -17,7 +17,10 @@ LIB_PATH = os.path.join(PKG, "libstomsfem.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EVERSION = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
-PREC_F64, PREC_F32_REFINE64 = 0, 1
+PREC_F64, PREC_F32_REFINE64, PREC_BF16 = 0, 1, 2
+MLP_NPARAM = 9940
+MLP_BATCH = 32
+MLP_KIN = 4
 BC_LINEAR = 0
 
 _DT = {torch.float64: F64, torch.float32: F32}
@@ -27,6 +30,11 @@ class StomsfemError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed with status {code}: {msg}")
         self.code = code
+
+
+class BumpFamily(C.Structure):
+    _fields_ = [("g", C.c_int32), ("rho", C.c_double), ("eps", C.c_double), ("base", C.c_double),
+                ("amp", C.c_double), ("beta", C.c_double)]
 
 
 class Batch(C.Structure):
@@ -68,6 +76,15 @@ def lib():
         "stomsfem_reduce_apply": (C.c_int, [vp, C.POINTER(Batch), i32, vp]),
         "stomsfem_model_export": (C.c_int, [vp, i32, vp, i64]),
         "stomsfem_model_free": (C.c_int, [vp]),
+        "stomsfem_local_vars_bumps": (C.c_int, [i32, i32, i32, C.POINTER(BumpFamily), i32, vp, vp]),
+        "stomsfem_mlp_create": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(BumpFamily), dbl, C.POINTER(vp)]),
+        "stomsfem_mlp_set_data": (C.c_int, [vp, vp, i32, vp, i64, vp]),
+        "stomsfem_mlp_train": (C.c_int, [vp, i32, C.c_float, vp, vp, vp]),
+        "stomsfem_mlp_grad": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "stomsfem_mlp_params": (C.c_int, [vp, vp, vp, vp]),
+        "stomsfem_mlp_standardization": (C.c_int, [vp, vp, vp]),
+        "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
+        "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
@@ -233,4 +250,92 @@ def reduce_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,
     b = make_batch(a, model.ncx, model.ncy, model.m, S, status)
     _check("stomsfem_reduce_apply", lib().stomsfem_reduce_apply(model.handle, C.byref(b), precision,
                                                                 _stream(stream)))
+    return S
+
+
+def bump_family(wl) -> BumpFamily:
+    p = wl.coef_params()
+    return BumpFamily(p["g"], p["rho"], p["eps"], p["base"], p["amp"], p["beta"])
+
+
+def local_vars_bumps(ncx: int, ncy: int, m: int, fam: BumpFamily, kmax: int = MLP_KIN):
+    """Host computation of each patch's local variables -> (lv [M][kmax] int32, nlocal [M])."""
+    import numpy as np
+
+    M = ncx * ncy
+    lv = np.zeros((M, kmax), dtype=np.int32)
+    nl = np.zeros(M, dtype=np.int32)
+    _check("stomsfem_local_vars_bumps", lib().stomsfem_local_vars_bumps(
+        ncx, ncy, m, C.byref(fam), kmax, lv.ctypes.data_as(C.c_void_p), nl.ctypes.data_as(C.c_void_p)))
+    return lv, nl
+
+
+def mlp_create(ncx: int, ncy: int, m: int, lv, init_params, fam: BumpFamily, box: float = 1.0) -> Model:
+    import numpy as np
+
+    lv = np.ascontiguousarray(lv, dtype=np.int32)
+    ip = np.ascontiguousarray(init_params, dtype=np.float32)
+    assert ip.shape == (ncx * ncy, MLP_NPARAM) and lv.shape == (ncx * ncy, MLP_KIN)
+    h = C.c_void_p()
+    _check("stomsfem_mlp_create", lib().stomsfem_mlp_create(
+        ncx, ncy, m, lv.ctypes.data_as(C.c_void_p), ip.ctypes.data_as(C.c_void_p), C.byref(fam), box, C.byref(h)))
+    return Model(h, ncx, ncy, m)
+
+
+def mlp_set_data(model: Model, xi: torch.Tensor, S: torch.Tensor, stream=None):
+    assert xi.dtype == torch.float64 and S.dtype == torch.float64
+    _check("stomsfem_mlp_set_data", lib().stomsfem_mlp_set_data(
+        model.handle, _ptr(xi), xi.shape[1], _ptr(S), xi.shape[0], _stream(stream)))
+
+
+def mlp_train(model: Model, steps: int, lr: float, perm: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+              stream=None):
+    _check("stomsfem_mlp_train", lib().stomsfem_mlp_train(model.handle, steps, lr, _ptr(perm), _ptr(loss),
+                                                          _stream(stream)))
+
+
+def mlp_grad(model: Model, xb: torch.Tensor, tb: torch.Tensor, stream=None):
+    M = model.ncx * model.ncy
+    grads = torch.empty((M, MLP_NPARAM), dtype=torch.float32, device=xb.device)
+    loss = torch.empty(M, dtype=torch.float32, device=xb.device)
+    _check("stomsfem_mlp_grad", lib().stomsfem_mlp_grad(model.handle, _ptr(xb), _ptr(tb), _ptr(grads), _ptr(loss),
+                                                        _stream(stream)))
+    return grads, loss
+
+
+def mlp_params(model: Model, stream=None) -> torch.Tensor:
+    out = torch.empty((model.ncx * model.ncy, MLP_NPARAM), dtype=torch.float32, device="cuda")
+    _check("stomsfem_mlp_params", lib().stomsfem_mlp_params(model.handle, _ptr(out), None, _stream(stream)))
+    return out
+
+
+def mlp_standardization(model: Model):
+    import numpy as np
+
+    M = model.ncx * model.ncy
+    mu = np.zeros((M, 10))
+    sd = np.zeros((M, 10))
+    _check("stomsfem_mlp_standardization", lib().stomsfem_mlp_standardization(
+        model.handle, mu.ctypes.data_as(C.c_void_p), sd.ctypes.data_as(C.c_void_p)))
+    return mu, sd
+
+
+def mlp_predict(model: Model, xi: torch.Tensor, precision: int = PREC_BF16, stream=None) -> torch.Tensor:
+    N = xi.shape[0]
+    Y = torch.empty((N, model.ncx * model.ncy, 20), dtype=torch.float32, device=xi.device)
+    _check("stomsfem_mlp_predict", lib().stomsfem_mlp_predict(model.handle, _ptr(xi), xi.shape[1], N, _ptr(Y),
+                                                              precision, _stream(stream)))
+    return Y
+
+
+def upscale_surrogate(model: Model, xi: torch.Tensor, gate_tol: float = 1e-3, precision: int = PREC_BF16,
+                      S: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                      stats: torch.Tensor | None = None, stream=None):
+    N = xi.shape[0]
+    M = model.ncx * model.ncy
+    if S is None:
+        S = torch.empty((N, M, 10), dtype=torch.float64, device=xi.device)
+    _check("stomsfem_upscale_surrogate", lib().stomsfem_upscale_surrogate(
+        model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), gate_tol, precision, _ptr(stats),
+        _stream(stream)))
     return S

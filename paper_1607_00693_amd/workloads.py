@@ -76,3 +76,23 @@ def lognormal_field(shape, sigma: float, seed: int) -> np.ndarray:
     """Element-wise independent log-normal coefficient exp(sigma * N(0,1))."""
     rng = np.random.default_rng(seed)
     return np.exp(sigma * rng.standard_normal(size=shape))
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    """Seeded permutation of range(n) (minibatch order), int64."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int64)
+
+
+def mlp_init(npatch: int, seed: int, kin: int = 4, width: int = 64, nout: int = 20) -> np.ndarray:
+    """Initial surrogate weights [npatch][nparams] (float32): Glorot-uniform
+    weights, zero biases, in the packing W1, b1, W2, b2, W3, b3, W4, b4."""
+    rng = np.random.default_rng(seed)
+    shapes = [(kin, width), (width,), (width, width), (width,), (width, width), (width,), (width, nout), (nout,)]
+    parts = []
+    for shp in shapes:
+        if len(shp) == 2:
+            lim = np.sqrt(6.0 / (shp[0] + shp[1]))
+            parts.append(rng.uniform(-lim, lim, size=(npatch,) + shp).reshape(npatch, -1))
+        else:
+            parts.append(np.zeros((npatch, shp[0])))
+    return np.concatenate(parts, axis=1).astype(np.float32)

@@ -1,0 +1,140 @@
+"""GPU learned surrogate through the C-ABI: gradients and forward pass against
+the FP64 oracle, training on plain-path pairs, gate + fallback, and what the
+trained network gains over the plain path.
+
+Tolerances: FP32 gradients within 1e-4 of the FP64 oracle relative to the
+largest gradient entry of the patch (single-precision sums of 32 to 64
+terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
+units); BF16 forward within 5e-2 of FP32 (bf16 keeps 8 significant bits).
+The end-to-end criterion is the coarse solution: surrogate within 1e-3
+(relative, per sample) of the plain FP64 path.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_00693_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-mlp] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sm():
+    from paper_1607_00693_amd import stomsfem
+
+    stomsfem.lib()
+    return stomsfem
+
+
+def _model(sm, wl, seed):
+    fam = sm.bump_family(wl)
+    lv, nl = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, fam)
+    init = W.mlp_init(wl.M, seed)
+    return sm.mlp_create(wl.nc, wl.nc, wl.m, lv, init, fam, 1.0), lv, nl, init
+
+
+def test_gradients_match_oracle(sm):
+    from oracle import mlp
+    wl = W.MESH8
+    say("gradients vs oracle")
+    model, lv, nl, init = _model(sm, wl, 11)
+    xb = W.uniform_array((wl.M, 32, 4), -1, 1, 12).astype(np.float32)
+    tb = W.uniform_array((wl.M, 32, 10), -2, 2, 13).astype(np.float32)
+    g, loss = sm.mlp_grad(model, torch.from_numpy(xb).cuda(), torch.from_numpy(tb).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    loss = loss.cpu().numpy()
+    for K in range(0, wl.M, 7):
+        L, gref = mlp.grad(init[K].astype(np.float64), xb[K].astype(np.float64), tb[K].astype(np.float64), 4)
+        assert abs(loss[K] - L) < 1e-5 * max(1.0, L)
+        assert np.abs(g[K] - gref).max() < 1e-4 * np.abs(gref).max(), K
+
+
+@pytest.fixture(scope="module")
+def trained(sm):
+    wl = W.MESH8
+    model, lv, nl, _ = _model(sm, wl, 4004)
+    ntr = 2048
+    say(f"training data: {ntr} plain solves per patch")
+    xi_tr = torch.from_numpy(W.uniform_xi(ntr, wl.nxi, 2004)).cuda()
+    a_tr = sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    S_tr = sm.upscale(a_tr, wl.nc, wl.nc, wl.m)
+    sm.mlp_set_data(model, xi_tr, S_tr)
+    perm = torch.from_numpy(W.permutation(ntr, 5004)).cuda()
+    loss = torch.zeros(wl.M, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    for steps, lr in ((4000, 2e-3), (4000, 5e-4), (4000, 1e-4)):
+        sm.mlp_train(model, steps, lr, perm, loss)
+    torch.cuda.synchronize()
+    say(f"trained 12000 steps in {time.perf_counter() - t0:.2f} s; final minibatch loss max {loss.max().item():.3e}")
+    return dict(wl=wl, model=model, lv=lv, nl=nl)
+
+
+def test_forward_fp32_and_bf16(sm, trained):
+    from oracle import mlp
+    wl, model, lv = trained["wl"], trained["model"], trained["lv"]
+    say("forward FP32 vs oracle, BF16 vs FP32")
+    xi = W.uniform_xi(64, wl.nxi, 1004)
+    xi_d = torch.from_numpy(xi).cuda()
+    Y32 = sm.mlp_predict(model, xi_d, sm.PREC_F32_REFINE64).cpu().numpy()
+    Y16 = sm.mlp_predict(model, xi_d, sm.PREC_BF16).cpu().numpy()
+    params = sm.mlp_params(model).cpu().numpy()
+    for K in range(0, wl.M, 5):
+        X = np.where(lv[K] >= 0, xi[:, np.maximum(lv[K], 0)], 0.0).astype(np.float32).astype(np.float64)
+        Yref, _ = mlp.forward(params[K].astype(np.float64), X, 4)
+        assert np.abs(Y32[:, K] - Yref).max() < 1e-5 * max(1.0, np.abs(Yref).max())
+    d = np.abs(Y16 - Y32).max()
+    say(f"max |Y_bf16 - Y_fp32| = {d:.3e} (standardised units)")
+    assert d < 5e-2
+
+
+def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
+    wl, model = trained["wl"], trained["model"]
+    N = 4096
+    say(f"surrogate vs plain on {N} test samples")
+    xi_d = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1004)).cuda()
+    a = sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params())
+    S_plain = sm.upscale(a, wl.nc, wl.nc, wl.m)
+    status = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    S_sur = sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, status=status, stats=stats)
+    U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    U_s, _, _ = sm.coarse_solve(S_sur, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    Sp, Ss = S_plain.cpu().numpy(), S_sur.cpu().numpy()
+    acc = st == 0
+    fb = st == 1
+    aud = st == 2
+    assert (st >= 0).all()
+    # recomputed pairs are the plain path's results bit for bit
+    assert np.array_equal(Ss[fb | aud], Sp[fb | aud])
+    err = np.abs(Ss - Sp).max(-1) / np.abs(Sp).max(-1)
+    ue = (np.linalg.norm(U_s.cpu().numpy() - U_p.cpu().numpy(), axis=1) / np.linalg.norm(U_p.cpu().numpy(), axis=1))
+    s = stats.cpu().numpy().view(np.uint64)
+    say(f"accepted {acc.mean():.3f}, fallback {fb.mean():.3f}, audited {aud.mean():.4f}; "
+        f"max S err accepted {err[acc].max() if acc.any() else 0:.2e}; max U err {ue.max():.2e}; "
+        f"stats rejections {s[0]} audits {s[1]}")
+    assert s[0] == fb.sum() and s[1] == aud.sum()
+    assert ue.max() < 1e-3
+    # gain: throughput of the surrogate path against the plain path on the
+    # same inputs (plain: coefficient generation + local solves)
+    def timed(f, reps=5):
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+    tp = timed(lambda: sm.upscale(sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params(), out=a), wl.nc, wl.nc, wl.m,
+                                  S=S_plain))
+    ts = timed(lambda: sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, S=S_sur))
+    say(f"plain {N * wl.M / tp / 1e9:.2f} G pairs/s, surrogate {N * wl.M / ts / 1e9:.2f} G pairs/s, "
+        f"gain {tp / ts:.2f}x")
