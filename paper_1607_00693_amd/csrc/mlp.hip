@@ -12,8 +12,9 @@
 //                            gradient, otherwise the raw gradient is written
 //                            (parity checks against the oracle).
 //   mlp_infer_bf16_kernel    BF16 MFMA (v_mfma_f32_16x16x16bf16_1k, FP32
-//                            accumulation, FP32 bias + GELU) inference, then
-//                            the gate per pair;
+//                            accumulation, three-term bf16 splitting of
+//                            weights and activations, FP32 bias + GELU)
+//                            inference, then the gate per pair;
 //   mlp_infer_f32_kernel     FP32 inference (reference for the BF16 one);
 //   mlp_fallback_kernel      plain solve (m = 8 lane kernel) of the pairs the
 //                            gate rejected plus a 1% audit of accepted ones,
@@ -389,41 +390,56 @@ __global__ __launch_bounds__(64) void mlp_infer_f32_kernel(MlpInferArgs a) {
 }
 
 // BF16 MFMA inference.  Workgroup = 4 wavefronts x 16 samples of one patch.
-// Weights are converted to bf16 (round to nearest even) into LDS, stored
-// transposed (n-major) so that each lane's four consecutive k are adjacent.
+// Every FP32 weight w and activation h is carried as two bf16 numbers,
+// w = w_hi + w_lo, h = h_hi + h_lo (w_hi = bf16(w), w_lo = bf16(w - w_hi)), and
+// each product is formed as h_hi w_hi + h_hi w_lo + h_lo w_hi on the matrix
+// cores with FP32 accumulation (the h_lo w_lo term is below FP32 rounding).
+// Weights are stored transposed (n-major) so that each lane's four
+// consecutive k are adjacent in LDS.
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 constexpr int BF_KIN = 16;  // layer-1 K padded to one MFMA K step
 constexpr int BF_NO = 32;   // 20 outputs padded to two N tiles
+constexpr int BF_LD = WD + 4;
 
-__global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
+constexpr int BF_WAVES = 8;               // wavefronts per workgroup
+constexpr int BF_TILE = 16 * BF_WAVES;     // samples per tile
+
+__global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferArgs a) {
   using s4 = __attribute__((__vector_size__(4 * sizeof(short)))) short;
   using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const int K = blockIdx.y;
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
-  __shared__ uint16_t W1t[WD][BF_KIN], W2t[WD][WD + 4], W3t[WD][WD + 4], W4t[BF_NO][WD + 4];
+  constexpr int NT = 64 * BF_WAVES;
+  // [2] = hi, lo
+  __shared__ uint16_t W1t[2][WD][BF_KIN], W2t[2][WD][BF_LD], W3t[2][WD][BF_LD], W4t[2][BF_NO][BF_LD];
   __shared__ float bias[3 * WD + BF_NO];
-  __shared__ uint16_t Hs[4][2][16][WD + 4];
-  __shared__ float Ys[4][16][BF_NO + 1];
+  __shared__ uint16_t Hs[BF_WAVES][2][2][16][BF_LD];  // wave, ping-pong buffer, hi/lo, row, k
+  __shared__ float Ys[BF_WAVES][16][BF_NO + 1];
   const float* P = a.params + (int64_t)K * MLP_NP;
-  for (int i = tid; i < WD * BF_KIN; i += 256) {
+  auto split = [](float v, uint16_t& hi, uint16_t& lo) {
+    hi = to_bf16(v);
+    lo = to_bf16(v - from_bf16(hi));
+  };
+  for (int i = tid; i < WD * BF_KIN; i += NT) {
     const int nn = i / BF_KIN, k = i % BF_KIN;
-    W1t[nn][k] = to_bf16(k < MLP_KIN ? P[MLP_OW1 + k * WD + nn] : 0.0f);
+    split(k < MLP_KIN ? P[MLP_OW1 + k * WD + nn] : 0.0f, W1t[0][nn][k], W1t[1][nn][k]);
   }
-  for (int i = tid; i < WD * WD; i += 256) {
+  for (int i = tid; i < WD * WD; i += NT) {
     const int nn = i / WD, k = i % WD;
-    W2t[nn][k] = to_bf16(P[MLP_OW2 + k * WD + nn]);
-    W3t[nn][k] = to_bf16(P[MLP_OW3 + k * WD + nn]);
+    split(P[MLP_OW2 + k * WD + nn], W2t[0][nn][k], W2t[1][nn][k]);
+    split(P[MLP_OW3 + k * WD + nn], W3t[0][nn][k], W3t[1][nn][k]);
   }
-  for (int i = tid; i < BF_NO * WD; i += 256) {
+  for (int i = tid; i < BF_NO * WD; i += NT) {
     const int nn = i / WD, k = i % WD;
-    W4t[nn][k] = to_bf16(nn < NO ? P[MLP_OW4 + k * NO + nn] : 0.0f);
+    split(nn < NO ? P[MLP_OW4 + k * NO + nn] : 0.0f, W4t[0][nn][k], W4t[1][nn][k]);
   }
-  for (int i = tid; i < 3 * WD + BF_NO; i += 256) {
+  for (int i = tid; i < 3 * WD + BF_NO; i += NT) {
     float v;
     if (i < WD) v = P[MLP_OB1 + i];
     else if (i < 2 * WD) v = P[MLP_OB2 + i - WD];
@@ -431,8 +447,11 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
     else v = (i - 3 * WD) < NO ? P[MLP_OB4 + i - 3 * WD] : 0.0f;
     bias[i] = v;
   }
+  const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  __syncthreads();
   // inputs of this wavefront's 16 samples (row = sample, k < 4 used)
-  const int64_t sbase = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int64_t sbase = tile * BF_TILE + 16 * w;
   for (int i = lane; i < 16 * BF_KIN; i += 64) {
     const int r = i / BF_KIN, k = i % BF_KIN;
     const int64_t s = sbase + r;
@@ -441,35 +460,42 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
       const int j = a.lv[K * MLP_KIN + k];
       v = j >= 0 ? (float)a.xi[s * a.nxi + j] : 0.0f;
     }
-    Hs[w][0][r][k] = to_bf16(v);
+    split(v, Hs[w][0][0][r][k], Hs[w][0][1][r][k]);
   }
   __syncthreads();
   const int row = lane & 15, kq = lane >> 4;  // A: row, k group; B: column, k group
-  auto loadA = [&](int buf, int k0) {
+  auto loadA = [&](int buf, int part, int k0) {
     s4 v;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (short)Hs[w][buf][row][k0 + 4 * kq + t];
+    for (int t = 0; t < 4; ++t) v[t] = (short)Hs[w][buf][part][row][k0 + 4 * kq + t];
     return v;
   };
   auto store_act = [&](int buf, int ntile, const f4& c, int boff) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 4 * kq + v, col = 16 * ntile + (lane & 15);
-      Hs[w][buf][r][col] = to_bf16(gelu_f(c[v] + bias[boff + col]));
+      split(gelu_f(c[v] + bias[boff + col]), Hs[w][buf][0][r][col], Hs[w][buf][1][r][col]);
     }
+  };
+  auto mma3 = [](const s4& ah, const s4& al, const s4& bh, const s4& bl, f4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
   };
   // layer 1: [16 x 16] x [16 x 64]
   {
-    const s4 av = loadA(0, 0);
+    const s4 ah = loadA(0, 0, 0), al = loadA(0, 1, 0);
     f4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      s4 bv;
+      s4 bh, bl;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bv[t] = (short)W1t[16 * nt + row][4 * kq + t];
-      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        bh[t] = (short)W1t[0][16 * nt + row][4 * kq + t];
+        bl[t] = (short)W1t[1][16 * nt + row][4 * kq + t];
+      }
+      acc[nt] = mma3(ah, al, bh, bl, f4{0.f, 0.f, 0.f, 0.f});
     }
-    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) store_act(1, nt, acc[nt], 0);
   }
@@ -483,17 +509,19 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
     for (int nt = 0; nt < 4; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const s4 av = loadA(inb, 16 * kk);
+      const s4 ah = loadA(inb, 0, 16 * kk), al = loadA(inb, 1, 16 * kk);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        s4 bv;
+        s4 bh, bl;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          bv[t] = (short)(layer == 0 ? W2t[16 * nt + row][16 * kk + 4 * kq + t] : W3t[16 * nt + row][16 * kk + 4 * kq + t]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nt], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+          const int nn = 16 * nt + row, k = 16 * kk + 4 * kq + t;
+          bh[t] = (short)(layer == 0 ? W2t[0][nn][k] : W3t[0][nn][k]);
+          bl[t] = (short)(layer == 0 ? W2t[1][nn][k] : W3t[1][nn][k]);
+        }
+        acc[nt] = mma3(ah, al, bh, bl, acc[nt]);
       }
     }
-    __syncthreads();
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) store_act(outb, nt, acc[nt], (layer + 1) * WD);
     __syncthreads();
@@ -503,13 +531,16 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
     f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const s4 av = loadA(1, 16 * kk);
+      const s4 ah = loadA(1, 0, 16 * kk), al = loadA(1, 1, 16 * kk);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
-        s4 bv;
+        s4 bh, bl;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) bv[t] = (short)W4t[16 * nt + row][16 * kk + 4 * kq + t];
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nt], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+          bh[t] = (short)W4t[0][16 * nt + row][16 * kk + 4 * kq + t];
+          bl[t] = (short)W4t[1][16 * nt + row][16 * kk + 4 * kq + t];
+        }
+        acc[nt] = mma3(ah, al, bh, bl, acc[nt]);
       }
     }
 #pragma unroll
@@ -538,6 +569,7 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(MlpInferArgs a) {
       }
     }
   }
+  }  // tiles
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
@@ -587,8 +619,11 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)a.count, 1);
   }
   if (bf16) {
-    const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
-    hipLaunchKernelGGL(mlp_infer_bf16_kernel, grid, dim3(256), 0, st, a);
+    const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
+    int64_t gx = (1024 + a.npatch - 1) / a.npatch;  // about four workgroups per CU in total
+    if (gx > ntiles) gx = ntiles;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3((unsigned)gx, (unsigned)a.npatch), dim3(64 * BF_WAVES), 0, st, a);
   } else {
     const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
     hipLaunchKernelGGL(mlp_infer_f32_kernel, grid, dim3(64), 0, st, a);

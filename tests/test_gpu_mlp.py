@@ -5,7 +5,8 @@ trained network gains over the plain path.
 Tolerances: FP32 gradients within 1e-4 of the FP64 oracle relative to the
 largest gradient entry of the patch (single-precision sums of 32 to 64
 terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
-units); BF16 forward within 5e-2 of FP32 (bf16 keeps 8 significant bits).
+units); BF16 forward (three-term bf16 splitting, FP32 accumulation) within 1e-3
+of FP32.
 The end-to-end criterion is the coarse solution: surrogate within 1e-3
 (relative, per sample) of the plain FP64 path.
 """
@@ -91,12 +92,12 @@ def test_forward_fp32_and_bf16(sm, trained):
         assert np.abs(Y32[:, K] - Yref).max() < 1e-5 * max(1.0, np.abs(Yref).max())
     d = np.abs(Y16 - Y32).max()
     say(f"max |Y_bf16 - Y_fp32| = {d:.3e} (standardised units)")
-    assert d < 5e-2
+    assert d < 1e-3
 
 
 def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
     wl, model = trained["wl"], trained["model"]
-    N = 4096
+    N = 16384
     say(f"surrogate vs plain on {N} test samples")
     xi_d = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1004)).cuda()
     a = sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params())
