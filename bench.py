@@ -50,6 +50,24 @@ def plain_flops_per_pair(m: int) -> float:
     return f
 
 
+def profiled_traffic_per_pair():
+    """Calibrated HBM bytes per pair of the m = 32 upscaling kernel from the
+    committed counter summary, or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "upscale_mesh32_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1607_00693_amd", "csrc", "upscale_tiled.hip")
+    try:
+        vals = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
+                    and line.split(": ", 1)[0] in ("traffic_bytes_per_pair", "kernel_source_sha1"))
+        if hashlib.sha1(open(src, "rb").read()).hexdigest() != vals["kernel_source_sha1"].strip():
+            return None
+        return float(vals["traffic_bytes_per_pair"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, budget_s: float = 15.0):
     import numpy as np
 
@@ -81,6 +99,101 @@ def cpu_baseline(wl, budget_s: float = 15.0):
     }
 
 
+def _timed(fn, reps=5):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def measure_accelerations(log):
+    """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
+    16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
+    2048 training samples per patch, 65536 test samples, gate 1e-3) against
+    the plain FP64 path at the same shapes.  Each comparison reports
+    throughputs in pairs/s, their ratio and the worst per-sample relative
+    error of the coarse solution against the plain path."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.MESH8
+    out = {}
+
+    def coarse_err(Sa, Sb):
+        Ua, _, _ = sm.coarse_solve(Sa, wl.nc, wl.nc)
+        Ub, _, _ = sm.coarse_solve(Sb, wl.nc, wl.nc)
+        d = torch.linalg.norm(Ua - Ub, dim=1) / torch.linalg.norm(Ub, dim=1)
+        return float(d.max().item())
+
+    # --- reduced basis ---
+    N = 16384
+    xi_tr = torch.from_numpy(W.uniform_xi(256, wl.nxi, 2003)).cuda()
+    a_tr = sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    t0 = time.perf_counter()
+    model = sm.reduce(a_tr, wl.nc, wl.nc, wl.m, r_max=8, tail_tol=1e-6)
+    t_off = time.perf_counter() - t0
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1003)).cuda()
+    a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)
+    S_rb = torch.empty((N, wl.M, 10), dtype=torch.float64, device="cuda")
+    S_pl = torch.empty_like(S_rb)
+    t_rb = _timed(lambda: sm.reduce_apply(model, a32, S=S_rb))
+    t_pl = _timed(lambda: sm.upscale(a32, wl.nc, wl.nc, wl.m, S=S_pl))
+    out["reduced_basis"] = {
+        "workload": f"8x8 coarse, H/h=8, 256 training samples, r<=8 (tail 1e-6), {N} online samples, FP32 a",
+        "offline_s": t_off, "r": int(model.export("r").max()),
+        "pairs_per_s": N * wl.M / t_rb, "plain_pairs_per_s": N * wl.M / t_pl, "ratio": t_pl / t_rb,
+        "max_coarse_rel_err": coarse_err(S_rb, S_pl)}
+    log(f"reduced basis: {out['reduced_basis']}")
+    model.free()
+    del a_tr, a32
+
+    # --- learned surrogate ---
+    fam = sm.bump_family(wl)
+    lv, _ = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, fam)
+    mdl = sm.mlp_create(wl.nc, wl.nc, wl.m, lv, W.mlp_init(wl.M, 4004), fam, 1.0)
+    ntr = 2048
+    t0 = time.perf_counter()
+    xi_tr = torch.from_numpy(W.uniform_xi(ntr, wl.nxi, 2004)).cuda()
+    S_tr = sm.upscale(sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    sm.mlp_set_data(mdl, xi_tr, S_tr)
+    perm = torch.from_numpy(W.permutation(ntr, 5004)).cuda()
+    for steps, lr in ((8000, 2e-3), (8000, 5e-4), (8000, 1e-4)):
+        sm.mlp_train(mdl, steps, lr, perm)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    N = 65536
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1004)).cuda()
+    a = torch.empty((N, wl.nfine, wl.nfine), dtype=torch.float64, device="cuda")
+    S_pl = torch.empty((N, wl.M, 10), dtype=torch.float64, device="cuda")
+    S_su = torch.empty_like(S_pl)
+    status = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+
+    def plain():
+        sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), out=a)
+        sm.upscale(a, wl.nc, wl.nc, wl.m, S=S_pl)
+
+    t_pl = _timed(plain)
+    t_su = _timed(lambda: sm.upscale_surrogate(mdl, xi, 1e-3, sm.PREC_BF16, S=S_su, status=status))
+    st = status.cpu().numpy()
+    out["learned_surrogate"] = {
+        "workload": f"8x8 coarse, H/h=8, 64 per-patch MLPs (k<=4 -> 64x3 -> 2x10, GELU), {ntr} training "
+                    f"samples/patch, {N} test samples, gate tau=1e-3, BF16 MFMA (3-term split)",
+        "train_s": t_train, "pairs_per_s": N * wl.M / t_su, "plain_pairs_per_s": N * wl.M / t_pl,
+        "ratio": t_pl / t_su, "accepted": float((st == 0).mean()), "fallback": float((st == 1).mean()),
+        "audited": float((st == 2).mean()), "max_coarse_rel_err": coarse_err(S_su, S_pl)}
+    log(f"learned surrogate: {out['learned_surrogate']}")
+    mdl.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +202,9 @@ def main():
     ap.add_argument("--workload", default="mesh32", choices=["mesh32", "mesh8"])
     ap.add_argument("--nsamples", type=int, default=0, help="override the sample count (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (calibrates HBM byte counters in a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -133,6 +249,12 @@ def main():
         if record:
             ev[3].record(stream)
 
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -186,13 +308,20 @@ def main():
             "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": (None if (tpp := profiled_traffic_per_pair()) is None or wl.m != 32 else tpp * pairs),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes": bytes_alg,
             "kernel": "local upscaling (FP64 VALU)",
             "flops_per_pair": plain_flops_per_pair(wl.m),
             "hbm_frac_algorithmic": bytes_alg / (t_up * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "cpu_baseline": None,
     }
+    if not args.no_accelerations:
+        del a
+        torch.cuda.empty_cache()
+        print("[bench] reduced basis and learned surrogate at the 8x8 mesh", file=sys.stderr, flush=True)
+        out["accelerations"] = measure_accelerations(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
