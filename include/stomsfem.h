@@ -177,6 +177,10 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
  *   1 = eigenvalues lambda (double [ncy*ncx][(m-1)^2], descending)
  *   2 = modes Z            (double [ncy*ncx][(m-1)^2][8], columns >= r_K are 0)
  *   3 = means phibar       (double [ncy*ncx][3][(m-1)^2])
+ * (reduced-basis models), and for interpolation models:
+ *   4 = node table         (double [rows][10], rows = sum_K nnodes^k_K)
+ *   5 = row offsets        (int64  [ncy*ncx + 1]; patch K owns rows
+ *                           off[K] .. off[K+1]-1)
  * bytes must equal the size of the array. */
 int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host_dst, int64_t bytes);
 
@@ -265,6 +269,38 @@ int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t 
  * buffer (a synchronous allocation) when nsamples exceeds earlier calls. */
 int stomsfem_upscale_surrogate(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
                                int32_t* status, double gate_tol, int32_t precision, uint64_t* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Random interpolation (Sec. 3.1, Algorithms 1 and 2; error in Sec. 3.1.1).
+ *
+ * stomsfem_interp_build (offline, Algorithm 1): for every patch K with k_K
+ * local variables (local_vars host [M][4], increasing indices < g*g, -1
+ * padded at the end, as from stomsfem_local_vars_bumps), the tensor grid of
+ * nnodes (2..9) Chebyshev-Gauss-Lobatto points per variable on the box
+ * [lo, hi],  t_d = lo + (cos(pi d / (nnodes-1)) + 1)(hi - lo)/2,  and S_K at
+ * every node, computed on the GPU by the plain path (coefficients of the
+ * bump family `fam` with the local variables at the node and every other
+ * variable 0, which does not change a on K).  Row c of patch K holds the
+ * node whose digit for local variable i is (c / nnodes^(k-1-i)) mod nnodes
+ * (variable 0 slowest).  1 <= m <= 48.  Allocates device memory owned by the
+ * model and synchronises `stream`.  ENOTSPD if a node's cell problem fails.
+ *
+ * stomsfem_interp_apply (online, Algorithm 2): S device [nsamples][M][10]
+ * for xi device [nsamples][nxi]: the tensor Lagrange interpolant of every
+ * entry at the pair's local variables, evaluated in FP64 in barycentric form.
+ * Pairs with a local variable outside [lo, hi] (or NaN) are computed by the
+ * plain path with the coefficient regenerated from xi (the remark after
+ * Algorithm 2).  status device [nsamples][M] or NULL: 0 = interpolated,
+ * 1 = computed plainly, STOMSFEM_ENOTSPD from such a solve.  *nfallback
+ * (host, may be NULL) receives the number of plainly computed pairs.
+ * Synchronises `stream` once (to read that number); may grow a model-owned
+ * buffer (a synchronous allocation) when nsamples exceeds earlier calls.
+ * ------------------------------------------------------------------------ */
+int stomsfem_interp_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                          const stomsfem_bump_family* fam, int32_t nnodes, double lo, double hi,
+                          stomsfem_model** model, void* stream);
+int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                          int32_t* status, int64_t* nfallback, void* stream);
 
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample

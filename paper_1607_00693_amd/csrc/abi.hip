@@ -3,10 +3,13 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
+#include <algorithm>
 
 #include "common.h"
 #include "rb.h"
 #include "mlp.h"
+#include "ri.h"
 
 namespace stomsfem {
 hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
@@ -105,6 +108,13 @@ int check_batch(const stomsfem_batch& b, int idx) {
   return STOMSFEM_OK;
 }
 
+// Plain upscaling of one homogeneous batch with the kernel suited to its m.
+hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st) {
+  if (args.m <= 8) return launch_upscale_small(args, a_dtype, st);
+  if (tiled_supports(args.m)) return launch_upscale_tiled(args, a_dtype, st);
+  return launch_upscale_ref(args, a_dtype, st);
+}
+
 UpArgs to_args(const stomsfem_batch& b) {
   UpArgs a;
   a.nsamples = b.nsamples;
@@ -149,6 +159,19 @@ struct stomsfem_model {
   int64_t* list = nullptr;    // fallback list
   int64_t list_cap = 0;
   unsigned long long* counter = nullptr;
+  // random interpolation (kind 3)
+  int nn = 0;
+  double lo = -1.0, hi = 1.0;
+  int64_t rows = 0;           // table rows (tensor nodes of all patches)
+  int64_t* off = nullptr;     // [M + 1]
+  int32_t* nlv = nullptr;     // [M]
+  double* table = nullptr;    // [rows][10]
+  int64_t chunk = 0;          // pairs per plain-solve chunk
+  double* blk = nullptr;      // [chunk][m][m] coefficient blocks
+  double* xin = nullptr;      // [chunk][nxi] node random vectors
+  int64_t* pairs = nullptr;   // [chunk]
+  double* Sc = nullptr;       // [chunk][10]
+  int32_t* stc = nullptr;     // [chunk]
 };
 
 namespace {
@@ -175,6 +198,14 @@ void model_release(stomsfem_model* md) {
   hipFree(md->T);
   hipFree(md->list);
   hipFree(md->counter);
+  hipFree(md->off);
+  hipFree(md->nlv);
+  hipFree(md->table);
+  hipFree(md->blk);
+  hipFree(md->xin);
+  hipFree(md->pairs);
+  hipFree(md->Sc);
+  hipFree(md->stc);
   hipSetDevice(cur);
   delete md;
 }
@@ -209,14 +240,7 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
   for (int i = 0; i < nbatch; ++i) {
     const stomsfem_batch& b = batches[i];
     if (b.nsamples == 0) continue;
-    UpArgs args = to_args(b);
-    hipError_t e;
-    if (b.m <= 8)
-      e = launch_upscale_small(args, b.a_dtype, (hipStream_t)stream);
-    else if (tiled_supports(b.m))
-      e = launch_upscale_tiled(args, b.a_dtype, (hipStream_t)stream);
-    else
-      e = launch_upscale_ref(args, b.a_dtype, (hipStream_t)stream);
+    hipError_t e = launch_upscale_any(to_args(b), b.a_dtype, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "upscale launch");
   }
   return STOMSFEM_OK;
@@ -365,11 +389,19 @@ int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host
   const int Mc = model->ncx * model->ncy, nI = (model->m - 1) * (model->m - 1);
   const void* src = nullptr;
   int64_t need = 0;
+  if (which >= 0 && which <= 3 && model->kind != 1)
+    return fail(STOMSFEM_EINVAL, "model_export: not a reduced-basis model");
   switch (which) {
     case 0: src = model->rK; need = 4LL * Mc; break;
     case 1: src = model->lambda; need = 8LL * Mc * nI; break;
     case 2: src = model->Z; need = 8LL * Mc * nI * model->rmax; break;
     case 3: src = model->phibar; need = 8LL * Mc * 3 * nI; break;
+    case 4:
+      if (model->kind != 3) return fail(STOMSFEM_EINVAL, "model_export: not an interpolation model");
+      src = model->table; need = 8LL * model->rows * 10; break;
+    case 5:
+      if (model->kind != 3) return fail(STOMSFEM_EINVAL, "model_export: not an interpolation model");
+      src = model->off; need = 8LL * (Mc + 1); break;
     default: return fail(STOMSFEM_EINVAL, "model_export: unknown array");
   }
   if (bytes != need) return fail(STOMSFEM_EINVAL, "model_export: size mismatch, expected " + std::to_string(need));
@@ -633,6 +665,225 @@ int stomsfem_upscale_surrogate(stomsfem_model* model, const double* xi, int32_t 
   if (!S) return fail(STOMSFEM_EINVAL, "upscale_surrogate: NULL S");
   if (!(gate_tol >= 0)) return fail(STOMSFEM_EINVAL, "upscale_surrogate: gate_tol must be >= 0");
   return mlp_infer_common(model, xi, nxi, nsamples, nullptr, S, status, gate_tol, precision, stats, stream);
+}
+
+// ---------------------------------------------------------------------------
+// random interpolation
+// ---------------------------------------------------------------------------
+static BumpParams bump_params(const stomsfem_bump_family& f) {
+  return BumpParams{f.g, f.rho, f.eps, f.base, f.amp, f.beta};
+}
+
+// Plain solve of `count` listed pairs (p = s * M + K of the model's mesh)
+// with coefficients regenerated from xi, in chunks through the model's
+// buffers; S[p] and status[p] (code, or the solve's status) are written.
+static int ri_plain_pairs(stomsfem_model* md, const int64_t* list, int64_t count, const double* xi, int32_t nxi,
+                          double* S, int32_t* status, int32_t code, hipStream_t st) {
+  for (int64_t start = 0; start < count; start += md->chunk) {
+    const int64_t cnt = std::min(md->chunk, count - start);
+    RegenArgs r{};
+    r.ncx = md->ncx;
+    r.ncy = md->ncy;
+    r.m = md->m;
+    r.nxi = nxi;
+    r.bp = bump_params(md->fam);
+    r.pairs = list + start;
+    r.count = cnt;
+    r.xi = xi;
+    r.out = md->blk;
+    hipError_t e = launch_regen_blocks(r, st);
+    if (e == hipSuccess) {
+      UpArgs u{};
+      u.nsamples = cnt;
+      u.ncx = u.ncy = 1;
+      u.m = md->m;
+      u.npairs = cnt;
+      u.a = md->blk;
+      u.S = md->Sc;
+      u.status = md->stc;
+      e = launch_upscale_any(u, STOMSFEM_F64, st);
+    }
+    if (e == hipSuccess) e = launch_scatter_pairs(list + start, cnt, md->Sc, md->stc, S, status, code, st);
+    if (e != hipSuccess) return hip_fail(e, "interp: plain solve launch");
+  }
+  return STOMSFEM_OK;
+}
+
+int stomsfem_interp_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                          const stomsfem_bump_family* fam, int32_t nnodes, double lo, double hi,
+                          stomsfem_model** model, void* stream) {
+  if (!local_vars || !fam || !model) return fail(STOMSFEM_EINVAL, "interp_build: NULL argument");
+  *model = nullptr;
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 48) return fail(STOMSFEM_EINVAL, "interp_build: need 1 <= m <= 48");
+  if (nnodes < RI_NN_MIN || nnodes > RI_NN_MAX) return fail(STOMSFEM_EINVAL, "interp_build: nnodes must be in 2..9");
+  if (!(lo < hi)) return fail(STOMSFEM_EINVAL, "interp_build: need lo < hi");
+  if (fam->g < 1 || !(fam->rho > 0) || !(fam->eps > 0)) return fail(STOMSFEM_EINVAL, "interp_build: bad family");
+  const int Mc = ncx * ncy, nxi = fam->g * fam->g;
+  std::vector<int32_t> nlv(Mc);
+  std::vector<int64_t> off(Mc + 1, 0);
+  int32_t lv_max = -1;
+  for (int K = 0; K < Mc; ++K) {
+    int k = 0;
+    while (k < RI_KMAX && local_vars[K * RI_KMAX + k] >= 0) ++k;
+    for (int i = 0; i < RI_KMAX; ++i) {
+      const int32_t j = local_vars[K * RI_KMAX + i];
+      if ((i < k && j >= nxi) || (i >= k && j != -1))
+        return fail(STOMSFEM_EINVAL, "interp_build: local variables must be < g*g, -1 padded at the end");
+      if (i > 0 && i < k && j <= local_vars[K * RI_KMAX + i - 1])
+        return fail(STOMSFEM_EINVAL, "interp_build: local variables of a patch must be increasing");
+      if (j > lv_max) lv_max = j;
+    }
+    nlv[K] = k;
+    int64_t n = 1;
+    for (int i = 0; i < k; ++i) n *= nnodes;
+    off[K + 1] = off[K] + n;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 3;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->fam = *fam;
+  md->lv_max = lv_max;
+  md->nn = nnodes;
+  md->lo = lo;
+  md->hi = hi;
+  md->rows = off[Mc];
+  md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->table, sizeof(double) * (size_t)md->rows * 10);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+  A((void**)&md->xin, sizeof(double) * (size_t)md->chunk * nxi);
+  A((void**)&md->pairs, sizeof(int64_t) * (size_t)md->chunk);
+  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "interp_build: device allocation failed");
+  }
+  e = hipMemcpy(md->lv, local_vars, sizeof(int32_t) * Mc * RI_KMAX, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  std::vector<int32_t> sth;
+  int bad = 0;
+  for (int64_t start = 0; e == hipSuccess && start < md->rows; start += md->chunk) {
+    const int64_t cnt = std::min(md->chunk, md->rows - start);
+    RiNodeArgs na{};
+    na.npatch = Mc;
+    na.nxi = nxi;
+    na.nn = nnodes;
+    na.lo = lo;
+    na.hi = hi;
+    na.off = md->off;
+    na.lv = md->lv;
+    na.nlv = md->nlv;
+    na.start = start;
+    na.count = cnt;
+    na.xi_out = md->xin;
+    na.pairs_out = md->pairs;
+    e = launch_ri_nodes(na, st);
+    if (e != hipSuccess) break;
+    RegenArgs r{};
+    r.ncx = ncx;
+    r.ncy = ncy;
+    r.m = m;
+    r.nxi = nxi;
+    r.bp = bump_params(*fam);
+    r.pairs = md->pairs;
+    r.count = cnt;
+    r.xi = md->xin;
+    r.out = md->blk;
+    e = launch_regen_blocks(r, st);
+    if (e != hipSuccess) break;
+    UpArgs u{};
+    u.nsamples = cnt;
+    u.ncx = u.ncy = 1;
+    u.m = m;
+    u.npairs = cnt;
+    u.a = md->blk;
+    u.S = md->table + start * 10;
+    u.status = md->stc;
+    e = launch_upscale_any(u, STOMSFEM_F64, st);
+    if (e != hipSuccess) break;
+    sth.resize(cnt);
+    e = hipMemcpyAsync(sth.data(), md->stc, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int64_t i = 0; e == hipSuccess && i < cnt; ++i) bad |= sth[i] != 0;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "interp_build");
+  }
+  if (bad) {
+    model_release(md);
+    return fail(STOMSFEM_ENOTSPD, "interp_build: a cell problem at an interpolation node is not positive definite");
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                          int32_t* status, int64_t* nfallback, void* stream) {
+  if (nfallback) *nfallback = 0;
+  if (!model || model->kind != 3) return fail(STOMSFEM_EINVAL, "interp_apply: not an interpolation model");
+  if (nsamples < 0 || nxi < model->fam.g * model->fam.g)
+    return fail(STOMSFEM_EINVAL, "interp_apply: nxi smaller than the family's g*g");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi) || !device_ptr(S)) return fail(STOMSFEM_EINVAL, "interp_apply: xi and S must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "interp_apply: status must be a device pointer");
+  const int Mc = model->ncx * model->ncy;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = nsamples * Mc;
+  if (model->list_cap < need) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+      hipFree(model->list);
+      model->list = nullptr;
+      model->list_cap = 0;
+      e = hipMalloc(&model->list, sizeof(int64_t) * need);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STOMSFEM_ENOMEM, "interp_apply: fallback list allocation failed");
+    }
+    model->list_cap = need;
+  }
+  RiApplyArgs a{};
+  a.npatch = Mc;
+  a.nxi = nxi;
+  a.nn = model->nn;
+  a.nsamples = nsamples;
+  a.lo = model->lo;
+  a.hi = model->hi;
+  a.table = model->table;
+  a.off = model->off;
+  a.lv = model->lv;
+  a.nlv = model->nlv;
+  a.xi = xi;
+  a.S = S;
+  a.status = status;
+  a.list = model->list;
+  a.list_count = model->counter;
+  hipError_t e = launch_zero_u64(model->counter, st);
+  if (e == hipSuccess) e = launch_ri_apply(a, st);
+  unsigned long long n = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "interp_apply");
+  if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "interp_apply: fallback count out of range");
+  if (nfallback) *nfallback = (int64_t)n;
+  return ri_plain_pairs(model, model->list, (int64_t)n, xi, nxi, S, status, 1, st);
 }
 
 int stomsfem_workspace_reserve(int64_t bytes) {

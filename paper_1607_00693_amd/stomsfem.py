@@ -86,6 +86,9 @@ def lib():
         "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
         "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
+        "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
+                                            C.POINTER(vp), vp]),
+        "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -222,7 +225,11 @@ class Model:
         M = self.ncx * self.ncy
         nI = (self.m - 1) ** 2
         spec = {"r": (0, np.int32, (M,)), "lambda": (1, np.float64, (M, nI)),
-                "Z": (2, np.float64, (M, nI, 8)), "phibar": (3, np.float64, (M, 3, nI))}
+                "Z": (2, np.float64, (M, nI, 8)), "phibar": (3, np.float64, (M, 3, nI)),
+                "offsets": (5, np.int64, (M + 1,))}
+        if which == "table":
+            rows = int(self.export("offsets")[-1])
+            spec["table"] = (4, np.float64, (rows, 10))
         code, dt, shape = spec[which]
         out = np.zeros(shape, dtype=dt)
         _check("stomsfem_model_export", lib().stomsfem_model_export(
@@ -339,3 +346,31 @@ def upscale_surrogate(model: Model, xi: torch.Tensor, gate_tol: float = 1e-3, pr
         model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), gate_tol, precision, _ptr(stats),
         _stream(stream)))
     return S
+
+
+def interp_build(ncx: int, ncy: int, m: int, lv, fam: BumpFamily, nnodes: int, lo: float = -1.0, hi: float = 1.0,
+                 stream=None) -> Model:
+    """Offline random interpolation: S at the tensor Chebyshev-Gauss-Lobatto
+    nodes of every patch's local variables (lv [M][4], -1 padded)."""
+    import numpy as np
+
+    lv = np.ascontiguousarray(lv, dtype=np.int32)
+    assert lv.shape == (ncx * ncy, MLP_KIN)
+    h = C.c_void_p()
+    _check("stomsfem_interp_build", lib().stomsfem_interp_build(
+        ncx, ncy, m, lv.ctypes.data_as(C.c_void_p), C.byref(fam), nnodes, lo, hi, C.byref(h), _stream(stream)))
+    return Model(h, ncx, ncy, m)
+
+
+def interp_apply(model: Model, xi: torch.Tensor, S: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                 stream=None):
+    """Online random interpolation S[N][M][10]; returns (S, number of pairs
+    computed by the plain path because a local variable left the box)."""
+    assert xi.dtype == torch.float64
+    N = xi.shape[0]
+    if S is None:
+        S = torch.empty((N, model.ncx * model.ncy, 10), dtype=torch.float64, device=xi.device)
+    nfb = C.c_int64(0)
+    _check("stomsfem_interp_apply", lib().stomsfem_interp_apply(
+        model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), C.byref(nfb), _stream(stream)))
+    return S, nfb.value
