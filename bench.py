@@ -111,6 +111,47 @@ def _timed(fn, reps=5):
     return (time.perf_counter() - t) / reps
 
 
+def measure_interpolation(wl, xi, S_plain, t_plain_ms, nn_list, log):
+    """Random interpolation (Sec. 3.1) on the benchmark mesh: offline node
+    solves, then the online evaluation from xi, against the plain path from xi
+    (coefficient generation + upscaling, t_plain_ms).  Reports throughput,
+    ratio, the largest error of S relative to max|S| per pair, and the worst
+    per-sample relative error of the coarse solution."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+
+    fam = sm.bump_family(wl)
+    lv, nl = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, fam)
+    N = xi.shape[0]
+    pairs = N * wl.M
+    U_pl, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    out = {}
+    for nn in nn_list:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = sm.interp_build(wl.nc, wl.nc, wl.m, lv, fam, nn)
+        t_off = time.perf_counter() - t0
+        S_ri = torch.empty_like(S_plain)
+        t_on = _timed(lambda: sm.interp_apply(model, xi, S=S_ri))
+        scale = S_plain.abs().amax(dim=2, keepdim=True)
+        s_err = float(((S_ri - S_plain).abs() / scale).max())
+        U_ri, _, _ = sm.coarse_solve(S_ri, wl.nc, wl.nc)
+        u_err = float((torch.linalg.norm(U_ri - U_pl, dim=1) / torch.linalg.norm(U_pl, dim=1)).max())
+        rows = int(model.export("offsets")[-1])
+        out[f"nodes_{nn}"] = {
+            "offline_s": t_off, "node_solves": rows, "table_MB": rows * 80 / 1e6,
+            "pairs_per_s": pairs / t_on, "plain_pairs_per_s": pairs / (t_plain_ms * 1e-3),
+            "ratio": t_plain_ms * 1e-3 / t_on,
+            "flops_per_pair": float(np.mean(20.0 * nn ** nl.astype(np.float64))),
+            "max_S_rel_err": s_err, "max_coarse_rel_err": u_err}
+        log(f"interpolation nn={nn}: {out[f'nodes_{nn}']}")
+        model.free()
+        del S_ri
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -154,6 +195,16 @@ def measure_accelerations(log):
     log(f"reduced basis: {out['reduced_basis']}")
     model.free()
     del a_tr, a32
+
+    # --- random interpolation at the same mesh and samples (FP64 a for the plain side) ---
+    a64 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params())
+    S_pl = sm.upscale(a64, wl.nc, wl.nc, wl.m)
+    t_pl = _timed(lambda: (sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), out=a64),
+                           sm.upscale(a64, wl.nc, wl.nc, wl.m, S=S_pl)))
+    out["random_interpolation"] = measure_interpolation(wl, xi, S_pl, t_pl * 1e3, (5, 7), log)
+    out["random_interpolation"]["workload"] = (f"8x8 coarse, H/h=8, {N} samples, Chebyshev-Lobatto tensor "
+                                               "nodes per local variable (k<=4), FP64")
+    del a64
 
     # --- learned surrogate ---
     fam = sm.bump_family(wl)
@@ -318,10 +369,17 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_accelerations:
+        print("[bench] random interpolation at the benchmark mesh", file=sys.stderr, flush=True)
+        ri_out = measure_interpolation(wl, xi, S, t_gen + t_up, (5, 7),
+                                       lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
+                              "Chebyshev-Lobatto tensor nodes per local variable (k<=4), FP64; plain side = "
+                              "coefficient generation + upscaling kernels")
         del a
         torch.cuda.empty_cache()
         print("[bench] reduced basis and learned surrogate at the 8x8 mesh", file=sys.stderr, flush=True)
         out["accelerations"] = measure_accelerations(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        out["accelerations"]["random_interpolation_bench_mesh"] = ri_out
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
