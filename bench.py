@@ -375,11 +375,26 @@ def main():
         ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
                               "Chebyshev-Lobatto tensor nodes per local variable (k<=4), FP64; plain side = "
                               "coefficient generation + upscaling kernels")
+        print("[bench] FP32 factorisation + FP64 refinement on the first 64 samples", file=sys.stderr, flush=True)
+        ns = min(64, wl.nsamples)
+        a_sub, S_sub = a[:ns], S[:ns]
+        S_mx = torch.empty_like(S_sub)
+        st_mx = torch.empty((ns, wl.M), dtype=torch.int32, device=dev)
+        t_mx = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_mx, status=st_mx,
+                                               precision=stomsfem.PREC_F32_REFINE64), reps=2)
+        S_64 = torch.empty_like(S_sub)
+        t_64 = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_64), reps=2)
+        mixed = {"workload": f"first {ns} samples of the benchmark batch ({ns * wl.M} pairs)",
+                 "pairs_per_s": ns * wl.M / t_mx, "fp64_pairs_per_s": ns * wl.M / t_64, "ratio": t_64 / t_mx,
+                 "recomputed_fp64": int((st_mx == 1).sum().item()),
+                 "max_S_rel_err_vs_fp64": float(((S_mx - S_64).abs().amax(dim=2) / S_64.abs().amax(dim=2)).max())}
+        print(f"[bench] fp32+refinement: {mixed}", file=sys.stderr, flush=True)
         del a
         torch.cuda.empty_cache()
         print("[bench] reduced basis and learned surrogate at the 8x8 mesh", file=sys.stderr, flush=True)
         out["accelerations"] = measure_accelerations(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
         out["accelerations"]["random_interpolation_bench_mesh"] = ri_out
+        out["accelerations"]["fp32_solve_fp64_refinement_bench_mesh"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

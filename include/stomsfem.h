@@ -110,11 +110,23 @@ typedef struct {
 } stomsfem_batch;
 
 /*   batches   : host array of nbatch descriptors (read during the call only)
- *   precision : STOMSFEM_PREC_F64 (FP32 refinement is reserved: EINVAL)
+ *   precision : STOMSFEM_PREC_F64 -- FP64 factorisation (asynchronous);
+ *               STOMSFEM_PREC_F32_REFINE64 (m <= 32) -- FP32 band LDL^T of
+ *               K_II, FP64 residuals r = f - K_II x with FP64 coefficients,
+ *               x += (LDL^T)^{-1} r until max_l |r^l|_inf / |f^l|_inf <=
+ *               STOMSFEM_REFINE_TOL (at most STOMSFEM_REFINE_MAXIT solves),
+ *               S from the FP64 energy sum of the refined phi^l; pairs that
+ *               do not converge are recomputed by the FP64 kernels.  Needs
+ *               (m-1)^2 (4 m + 40) bytes of LDS per workgroup (161 KB at
+ *               m = 32; EINVAL if the device allows less), uses the library
+ *               workspace and synchronises `stream` once per batch.
  *   bc        : STOMSFEM_BC_LINEAR
- * Per-pair status: STOMSFEM_OK, or STOMSFEM_ENOTSPD when a pivot of the local
- * factorisation is not positive (a <= 0 or NaN somewhere in K); S is then
- * undefined for that pair. */
+ * Per-pair status: STOMSFEM_OK; 1 = recomputed in FP64 because the
+ * refinement did not converge (F32_REFINE64 only); STOMSFEM_ENOTSPD when a
+ * pivot of the FP64 factorisation is not positive (a <= 0 or NaN somewhere
+ * in K), S is then undefined for that pair. */
+#define STOMSFEM_REFINE_TOL 1e-10
+#define STOMSFEM_REFINE_MAXIT 8
 int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream);
 
 /* Same computation through the simple reference kernel (one workgroup per

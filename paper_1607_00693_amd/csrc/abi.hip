@@ -10,6 +10,7 @@
 #include "rb.h"
 #include "mlp.h"
 #include "ri.h"
+#include "mixed.h"
 
 namespace stomsfem {
 hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
@@ -229,17 +230,88 @@ int stomsfem_coef_bumps(int64_t nsamples, int32_t nfine, const double* xi, int32
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coef_bumps launch");
 }
 
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One batch in STOMSFEM_PREC_F32_REFINE64: the mixed-precision kernel, then
+// the FP64 kernels on the pairs it hands back (read synchronously).
+static int upscale_refined(const stomsfem_batch& b, hipStream_t st) {
+  UpArgs up = to_args(b);
+  const int m = b.m;
+  const int64_t chunk = std::min<int64_t>(
+      up.npairs, std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m))));
+  const size_t off_list = 256;
+  const size_t off_blk = off_list + align256(sizeof(int64_t) * (size_t)up.npairs);
+  const size_t off_Sc = off_blk + align256(sizeof(double) * (size_t)chunk * m * m);
+  const size_t off_stc = off_Sc + align256(sizeof(double) * 10 * (size_t)chunk);
+  const size_t total = off_stc + align256(sizeof(int32_t) * (size_t)chunk);
+  void* ws = nullptr;
+  int rc = workspace_get(total, &ws);
+  if (rc != STOMSFEM_OK) return rc;
+  char* base = (char*)ws;
+  auto* counter = (unsigned long long*)base;
+  auto* list = (int64_t*)(base + off_list);
+  auto* blk = (double*)(base + off_blk);
+  auto* Sc = (double*)(base + off_Sc);
+  auto* stc = (int32_t*)(base + off_stc);
+  MixedArgs ma{};
+  ma.up = up;
+  ma.tol = STOMSFEM_REFINE_TOL;
+  ma.max_iter = STOMSFEM_REFINE_MAXIT;
+  ma.list = list;
+  ma.count = counter;
+  hipError_t e = launch_zero_u64(counter, st);
+  if (e == hipSuccess) e = launch_upscale_mixed(ma, b.a_dtype, st);
+  unsigned long long n = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, counter, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "upscale (FP32 + FP64 refinement)");
+  if (n > (unsigned long long)up.npairs) return fail(STOMSFEM_EHIP, "upscale: refinement fallback count out of range");
+  for (int64_t start = 0; start < (int64_t)n && e == hipSuccess; start += chunk) {
+    const int64_t cnt = std::min<int64_t>(chunk, (int64_t)n - start);
+    e = launch_gather_blocks(up, b.a_dtype, list + start, cnt, blk, st);
+    if (e == hipSuccess) {
+      UpArgs u{};
+      u.nsamples = cnt;
+      u.ncx = u.ncy = 1;
+      u.m = m;
+      u.npairs = cnt;
+      u.a = blk;
+      u.S = Sc;
+      u.status = stc;
+      e = launch_upscale_any(u, STOMSFEM_F64, st);
+    }
+    if (e == hipSuccess) e = launch_scatter_pairs(list + start, cnt, Sc, stc, b.S, b.status, 1, st);
+  }
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale: FP64 recompute launch");
+}
+
 int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream) {
   if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(STOMSFEM_EINVAL, "upscale: bad batch list");
-  if (precision != STOMSFEM_PREC_F64) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_PREC_F64 is available");
+  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64)
+    return fail(STOMSFEM_EINVAL, "upscale: precision must be STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32_REFINE64");
   if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_BC_LINEAR is available");
   for (int i = 0; i < nbatch; ++i) {
     int rc = check_batch(batches[i], i);
     if (rc != STOMSFEM_OK) return rc;
+    if (precision == STOMSFEM_PREC_F32_REFINE64 && batches[i].nsamples > 0) {
+      if (batches[i].m > 32) return fail(STOMSFEM_EINVAL, "upscale: FP32 + refinement needs m <= 32");
+      int dev = 0, maxlds = 0;
+      hipGetDevice(&dev);
+      hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+      if (upscale_mixed_lds_bytes(batches[i].m) + 256 > (size_t)maxlds)
+        return fail(STOMSFEM_EINVAL, "upscale: FP32 + refinement needs " +
+                                         std::to_string(upscale_mixed_lds_bytes(batches[i].m)) +
+                                         " bytes of LDS per workgroup; the device allows " + std::to_string(maxlds));
+    }
   }
   for (int i = 0; i < nbatch; ++i) {
     const stomsfem_batch& b = batches[i];
     if (b.nsamples == 0) continue;
+    if (precision == STOMSFEM_PREC_F32_REFINE64) {
+      int rc = upscale_refined(b, (hipStream_t)stream);
+      if (rc != STOMSFEM_OK) return rc;
+      continue;
+    }
     hipError_t e = launch_upscale_any(to_args(b), b.a_dtype, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "upscale launch");
   }
