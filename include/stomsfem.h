@@ -89,6 +89,27 @@ int stomsfem_coef_bumps(int64_t nsamples, int32_t nfine, const double* xi, int32
                         void* stream);
 
 /* ------------------------------------------------------------------------
+ * High-contrast channels-and-inclusions medium (synthetic stand-in for the
+ * media of Secs. 5.1-5.2, which exist only as figures): background 1 plus
+ * nfeat features j (kind 0 = horizontal channel on fine row floor(y0*nfine),
+ * covering centroids x0 <= xc <= x0 + size; kind 1 = vertical channel on
+ * column floor(x0*nfine), y0 <= yc <= y0 + size; kind 2 = square of side
+ * size centred at (x0, y0), |xc - x0| <= size/2 and |yc - y0| <= size/2).
+ * A fine element takes the conductivity of the highest-index feature that
+ * covers it,  theta_j = 10^(decades / (1 + exp(-xi_j)))  (a bounded positive
+ * transform of a Gaussian variable, Sec. 2.1.3).
+ *
+ * stomsfem_feature_map: map device int32 [nfine][nfine] = that index or -1;
+ *   kind, x0, y0, size device arrays [nfeat], nfeat <= 1024.  Asynchronous.
+ * stomsfem_coef_features: a device [nsamples][nfine][nfine] (a_dtype) from
+ *   the map and xi device [nsamples][nxi] (nxi >= nfeat).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+int stomsfem_feature_map(int32_t nfine, int32_t nfeat, const int32_t* kind, const double* x0, const double* y0,
+                         const double* size, int32_t* map, void* stream);
+int stomsfem_coef_features(int64_t nsamples, int32_t nfine, const int32_t* map, int32_t nfeat, const double* xi,
+                           int32_t nxi, double decades, void* a, int32_t a_dtype, void* stream);
+
+/* ------------------------------------------------------------------------
  * Simultaneous local upscaling (Sec. 2.2 eqs. MsFEB and stiffness_local;
  * Sec. 3 eq. MsFEB2): for every coarse element K and every sample, solve the
  * cell problems -div(a grad phi^l) = 0 in K, phi^l = p^l on the boundary of

@@ -56,6 +56,7 @@ def load():
         "orc_fine_fem": (i32, [i32, dp, dbl, dp]),
         "orc_cell_system_dense": (i32, [i32, dp, sz, i32, dp, dp]),
         "orc_coef_bumps": (i32, [i64, i32, dp, i32, i32, dbl, dbl, dbl, dbl, dbl, dp, i32]),
+        "orc_coef_features": (i32, [i64, i32, i32, ip, dp, dp, dp, dp, i32, dbl, dp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -215,4 +216,20 @@ def coef_bumps(xi: np.ndarray, nfine: int, g: int, rho: float, eps: float,
     st = load().orc_coef_bumps(N, nfine, _p(xi), nxi, g, rho, eps, base, amp, beta, _p(a), nthreads)
     if st != 0:
         raise RuntimeError(f"orc_coef_bumps status {st}")
+    return a
+
+
+def coef_features(xi: np.ndarray, nfine: int, kind, x0, y0, size, decades: float = 4.0,
+                  nthreads: int = 0) -> np.ndarray:
+    """Coefficient samples a[N][nfine][nfine] of the channels-and-inclusions
+    medium (see orc_coef_features)."""
+    xi = _c(xi)
+    N, nxi = xi.shape
+    kind = np.ascontiguousarray(kind, dtype=np.int32)
+    x0, y0, size = _c(x0), _c(y0), _c(size)
+    a = np.zeros((N, nfine, nfine))
+    st = load().orc_coef_features(N, nfine, len(kind), kind.ctypes.data_as(C.POINTER(C.c_int32)), _p(x0), _p(y0),
+                                  _p(size), _p(xi), nxi, decades, _p(a), nthreads)
+    if st != 0:
+        raise RuntimeError(f"orc_coef_features status {st}")
     return a

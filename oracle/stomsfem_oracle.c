@@ -525,3 +525,49 @@ int orc_coef_bumps(int64_t N, int nfine, const double* xi, int nxi, int g, doubl
   }
   return ORC_OK;
 }
+
+/* High-contrast channels-and-inclusions medium (synthetic stand-in for the
+ * media of Sec. 5.1-5.2, which the paper gives only as figures).  Feature j
+ * (kind 0: horizontal channel, 1: vertical channel, 2: square inclusion)
+ * covers the fine elements (centroid xc, yc, cell size h = 1/nfine):
+ *   horizontal: row floor(y0 nfine) and x0 <= xc <= x0 + size;
+ *   vertical:   column floor(x0 nfine) and y0 <= yc <= y0 + size;
+ *   square:     |xc - x0| <= size/2 and |yc - y0| <= size/2 (x0, y0 = centre).
+ * a = theta_j of the highest-index feature covering the element, 1 where
+ * none does, theta_j = 10^(decades * sigmoid(xi_j)) (the transform makes a
+ * positive and bounded, Sec. 2.1.3). */
+int orc_coef_features(int64_t N, int nfine, int nfeat, const int32_t* kind, const double* x0, const double* y0,
+                      const double* size, const double* xi, int nxi, double decades, double* a, int nthreads) {
+  if (N < 0 || nfine < 1 || nfeat < 0 || nxi < nfeat || !a || (N > 0 && !xi)) return ORC_EINVAL;
+  const double h = 1.0 / nfine;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+  for (int64_t t = 0; t < N * nfine; ++t) {
+    const int64_t s = t / nfine;
+    const int iy = (int)(t % nfine);
+    const double* xs = xi + s * nxi;
+    for (int ix = 0; ix < nfine; ++ix) {
+      const double xc = (ix + 0.5) * h, yc = (iy + 0.5) * h;
+      double v = 1.0;
+      for (int j = 0; j < nfeat; ++j) {
+        int cover = 0;
+        if (kind[j] == 0) {
+          int row = (int)floor(y0[j] * nfine);
+          if (row > nfine - 1) row = nfine - 1;
+          cover = iy == row && xc >= x0[j] && xc <= x0[j] + size[j];
+        } else if (kind[j] == 1) {
+          int col = (int)floor(x0[j] * nfine);
+          if (col > nfine - 1) col = nfine - 1;
+          cover = ix == col && yc >= y0[j] && yc <= y0[j] + size[j];
+        } else {
+          cover = fabs(xc - x0[j]) <= 0.5 * size[j] && fabs(yc - y0[j]) <= 0.5 * size[j];
+        }
+        if (cover) v = pow(10.0, decades / (1.0 + exp(-xs[j])));
+      }
+      a[(s * nfine + iy) * (int64_t)nfine + ix] = v;
+    }
+  }
+  return ORC_OK;
+}

@@ -24,6 +24,10 @@ int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples);
 size_t coarse_lds_bytes(int ncx);
 hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
                              double base, double amp, double beta, void* a, int a_dtype, hipStream_t st);
+hipError_t launch_feature_map(int nfine, int nfeat, const int32_t* kind, const double* x0, const double* y0,
+                              const double* size, int32_t* map, hipStream_t st);
+hipError_t launch_coef_features(int64_t nsamples, int nfine, const int32_t* map, int nfeat, const double* xi, int nxi,
+                                double decades, void* a, int a_dtype, hipStream_t st);
 }  // namespace stomsfem
 
 using namespace stomsfem;
@@ -228,6 +232,28 @@ int stomsfem_coef_bumps(int64_t nsamples, int32_t nfine, const double* xi, int32
   hipError_t e = launch_coef_bumps(nsamples, nfine, xi, nxi, g, rho, eps, base, amp, beta, a, a_dtype,
                                    (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coef_bumps launch");
+}
+
+int stomsfem_feature_map(int32_t nfine, int32_t nfeat, const int32_t* kind, const double* x0, const double* y0,
+                         const double* size, int32_t* map, void* stream) {
+  if (nfine < 1 || nfeat < 0 || nfeat > 1024) return fail(STOMSFEM_EINVAL, "feature_map: need nfine >= 1, 0 <= nfeat <= 1024");
+  if (!device_ptr(map)) return fail(STOMSFEM_EINVAL, "feature_map: map must be a device pointer");
+  if (nfeat > 0 && (!device_ptr(kind) || !device_ptr(x0) || !device_ptr(y0) || !device_ptr(size)))
+    return fail(STOMSFEM_EINVAL, "feature_map: geometry arrays must be device pointers");
+  hipError_t e = launch_feature_map(nfine, nfeat, kind, x0, y0, size, map, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "feature_map launch");
+}
+
+int stomsfem_coef_features(int64_t nsamples, int32_t nfine, const int32_t* map, int32_t nfeat, const double* xi,
+                           int32_t nxi, double decades, void* a, int32_t a_dtype, void* stream) {
+  if (nsamples < 0 || nfine < 1 || nfeat < 0 || nfeat > 1024 || nxi < nfeat)
+    return fail(STOMSFEM_EINVAL, "coef_features: bad sizes");
+  if (a_dtype != STOMSFEM_F64 && a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, "coef_features: bad a_dtype");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(map) || !device_ptr(a) || (nfeat > 0 && !device_ptr(xi)))
+    return fail(STOMSFEM_EINVAL, "coef_features: map, xi and a must be device pointers");
+  hipError_t e = launch_coef_features(nsamples, nfine, map, nfeat, xi, nxi, decades, a, a_dtype, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coef_features launch");
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

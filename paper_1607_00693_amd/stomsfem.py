@@ -86,6 +86,8 @@ def lib():
         "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
         "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
+        "stomsfem_feature_map": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
+        "stomsfem_coef_features": (C.c_int, [i64, i32, vp, i32, vp, i32, dbl, vp, i32, vp]),
         "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
                                             C.POINTER(vp), vp]),
         "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
@@ -374,3 +376,25 @@ def interp_apply(model: Model, xi: torch.Tensor, S: torch.Tensor | None = None, 
     _check("stomsfem_interp_apply", lib().stomsfem_interp_apply(
         model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), C.byref(nfb), _stream(stream)))
     return S, nfb.value
+
+
+def feature_map(nfine: int, kind: torch.Tensor, x0: torch.Tensor, y0: torch.Tensor, size: torch.Tensor,
+                stream=None) -> torch.Tensor:
+    """Index of the highest feature covering each fine element (-1: background)."""
+    out = torch.empty((nfine, nfine), dtype=torch.int32, device=kind.device)
+    _check("stomsfem_feature_map", lib().stomsfem_feature_map(
+        nfine, kind.shape[0], _ptr(kind), _ptr(x0), _ptr(y0), _ptr(size), _ptr(out), _stream(stream)))
+    return out
+
+
+def coef_features(fmap: torch.Tensor, nfeat: int, xi: torch.Tensor, decades: float = 4.0, dtype=torch.float64,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Coefficient samples a[N][nfine][nfine] of the channels-and-inclusions medium."""
+    assert xi.dtype == torch.float64 and fmap.dtype == torch.int32
+    N, nxi = xi.shape
+    nfine = fmap.shape[0]
+    if out is None:
+        out = torch.empty((N, nfine, nfine), dtype=dtype, device=xi.device)
+    _check("stomsfem_coef_features", lib().stomsfem_coef_features(
+        N, nfine, _ptr(fmap), nfeat, _ptr(xi), nxi, decades, _ptr(out), _DT[out.dtype], _stream(stream)))
+    return out

@@ -12,6 +12,11 @@ Workloads (synthetic stand-ins: the paper's own media exist only as figures):
 * ``mesh32``  -- 32 x 32 coarse elements, H/h = 32 (1024 x 1024 fine Q1), 64
   bumps of radius 1/8 on an 8 x 8 grid, eps = 1/256, xi ~ U[-1,1]^64,
   4096 samples.
+* ``channels64`` -- 64 x 64 coarse elements, 8192 samples in 32 batches of
+  256, H/h drawn per batch from {8, 16, 32}; background 1 plus 40 thin
+  channels and 40 square inclusions (80 variables, xi ~ N(0,1)^80), each
+  feature's conductivity set by its variable with up to four decades of
+  contrast.
 """
 from __future__ import annotations
 
@@ -96,3 +101,54 @@ def mlp_init(npatch: int, seed: int, kin: int = 4, width: int = 64, nout: int = 
         else:
             parts.append(np.zeros((npatch, shp[0])))
     return np.concatenate(parts, axis=1).astype(np.float32)
+
+
+@dataclasses.dataclass(frozen=True)
+class ChannelWorkload:
+    name: str = "channels64"
+    nc: int = 64
+    nbatch: int = 32
+    batch: int = 256          # samples per batch
+    m_choices: tuple = (8, 16, 32)
+    nchan: int = 40
+    nsq: int = 40
+    decades: float = 4.0      # conductivity 10^(decades * sigmoid(xi_j))
+    geom_seed: int = 3005
+    m_seed: int = 4005
+    xi_seed: int = 1005
+
+    @property
+    def nxi(self) -> int:
+        return self.nchan + self.nsq
+
+    @property
+    def M(self) -> int:
+        return self.nc * self.nc
+
+
+CHANNELS64 = ChannelWorkload()
+
+
+def channel_geometry(wl: ChannelWorkload = CHANNELS64):
+    """Feature geometry in continuous coordinates of the unit square:
+    (kind int32 [nf], x0, y0, size float64 [nf]).  Channels 0..nchan-1: kind
+    0 (horizontal) or 1 (vertical) with probability 1/2, start point
+    (x0, y0) ~ U[0,1]^2, length ~ U[0.25, 1].  Squares: kind 2, centre
+    (x0, y0) ~ U[0,1]^2, side ~ U[1/256, 1/64]."""
+    rng = np.random.default_rng(wl.geom_seed)
+    orient = rng.integers(0, 2, size=wl.nchan)
+    start = rng.uniform(0.0, 1.0, size=(wl.nchan, 2))
+    length = rng.uniform(0.25, 1.0, size=wl.nchan)
+    centre = rng.uniform(0.0, 1.0, size=(wl.nsq, 2))
+    side = rng.uniform(1.0 / 256, 1.0 / 64, size=wl.nsq)
+    kind = np.concatenate([orient, np.full(wl.nsq, 2)]).astype(np.int32)
+    x0 = np.concatenate([start[:, 0], centre[:, 0]])
+    y0 = np.concatenate([start[:, 1], centre[:, 1]])
+    size = np.concatenate([length, side])
+    return kind, x0, y0, size
+
+
+def batch_m(wl: ChannelWorkload = CHANNELS64) -> np.ndarray:
+    """H/h of each batch, drawn uniformly from wl.m_choices."""
+    rng = np.random.default_rng(wl.m_seed)
+    return np.asarray(wl.m_choices)[rng.integers(0, len(wl.m_choices), size=wl.nbatch)].astype(np.int32)
