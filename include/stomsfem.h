@@ -335,6 +335,48 @@ int stomsfem_interp_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* lo
 int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
                           int32_t* status, int64_t* nfallback, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Execution plans.  A stage is one batch of samples taken through the whole
+ * path: coefficient generation from xi, local upscaling (FP64), coarse
+ * assembly and solve with the Petrov-Galerkin load for f = 1, and the Monte
+ * Carlo mean and variance of U over the batch (Sec. 2.2 eqs. MsFEB,
+ * stiffness_local, upscaleSUF; Sec. 4.1.1).  stomsfem_plan_create groups the
+ * stages by (ncx, m), gives every group its own device buffers and stream,
+ * and captures HIP graphs: one for the whole plan, whose group branches run
+ * concurrently (stages of one group run in order), and one per stage.
+ * Replays allocate and synchronise nothing; replays of one plan must not
+ * overlap (the groups' buffers are reused).  U and status of a stage are
+ * left in group buffers when the stage gives NULL (overwritten by the next
+ * stage of the group).  Square coarse meshes, 2 <= ncx <= 64.
+ * ------------------------------------------------------------------------ */
+enum { STOMSFEM_FAMILY_BUMPS = 0, STOMSFEM_FAMILY_FEATURES = 1 };
+
+typedef struct {
+  int32_t ncx, ncy, m;
+  int64_t nsamples;
+  int32_t a_dtype;                  /* storage of the generated coefficient */
+  int32_t family;                   /* STOMSFEM_FAMILY_* */
+  stomsfem_bump_family bumps;       /* family BUMPS: see stomsfem_coef_bumps */
+  const int32_t* feature_map;       /* family FEATURES: device [ncy*m][ncx*m] */
+  int32_t nfeat;
+  double decades;
+  const double* xi;                 /* device [nsamples][nxi] */
+  int32_t nxi;
+  double* U;                        /* device out [nsamples][(ncx-1)(ncy-1)] or NULL */
+  double* qoi_mean;                 /* device out [(ncx-1)(ncy-1)] or NULL */
+  double* qoi_var;                  /* device out [(ncx-1)(ncy-1)] or NULL */
+  int32_t* status;                  /* device out [nsamples][ncx*ncy] or NULL */
+} stomsfem_stage;
+
+typedef struct stomsfem_plan stomsfem_plan;
+
+/* Synchronous (allocates, captures). */
+int stomsfem_plan_create(const stomsfem_stage* stages, int32_t nstage, stomsfem_plan** plan);
+/* Replay the whole plan (stage = -1) or one stage on `stream`; asynchronous. */
+int stomsfem_plan_launch(stomsfem_plan* plan, int32_t stage, void* stream);
+/* Synchronous. */
+int stomsfem_plan_free(stomsfem_plan* plan);
+
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample
  * in flight).  Calls made after a large enough reservation allocate nothing.

@@ -113,13 +113,6 @@ int check_batch(const stomsfem_batch& b, int idx) {
   return STOMSFEM_OK;
 }
 
-// Plain upscaling of one homogeneous batch with the kernel suited to its m.
-hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st) {
-  if (args.m <= 8) return launch_upscale_small(args, a_dtype, st);
-  if (tiled_supports(args.m)) return launch_upscale_tiled(args, a_dtype, st);
-  return launch_upscale_ref(args, a_dtype, st);
-}
-
 UpArgs to_args(const stomsfem_batch& b) {
   UpArgs a;
   a.nsamples = b.nsamples;
@@ -134,6 +127,17 @@ UpArgs to_args(const stomsfem_batch& b) {
 }
 
 }  // namespace
+
+namespace stomsfem {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// Plain upscaling of one homogeneous batch with the kernel suited to its m.
+hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st) {
+  if (args.m <= 8) return launch_upscale_small(args, a_dtype, st);
+  if (tiled_supports(args.m)) return launch_upscale_tiled(args, a_dtype, st);
+  return launch_upscale_ref(args, a_dtype, st);
+}
+}  // namespace stomsfem
 
 // Library-owned model (reduced basis).  All arrays live on `device`.
 struct stomsfem_model {

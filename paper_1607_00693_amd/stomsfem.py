@@ -37,6 +37,14 @@ class BumpFamily(C.Structure):
                 ("amp", C.c_double), ("beta", C.c_double)]
 
 
+class Stage(C.Structure):
+    _fields_ = [("ncx", C.c_int32), ("ncy", C.c_int32), ("m", C.c_int32), ("nsamples", C.c_int64),
+                ("a_dtype", C.c_int32), ("family", C.c_int32), ("bumps", BumpFamily),
+                ("feature_map", C.c_void_p), ("nfeat", C.c_int32), ("decades", C.c_double),
+                ("xi", C.c_void_p), ("nxi", C.c_int32), ("U", C.c_void_p), ("qoi_mean", C.c_void_p),
+                ("qoi_var", C.c_void_p), ("status", C.c_void_p)]
+
+
 class Batch(C.Structure):
     _fields_ = [
         ("ncx", C.c_int32),
@@ -88,6 +96,9 @@ def lib():
         "stomsfem_workspace_release": (C.c_int, []),
         "stomsfem_feature_map": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
         "stomsfem_coef_features": (C.c_int, [i64, i32, vp, i32, vp, i32, dbl, vp, i32, vp]),
+        "stomsfem_plan_create": (C.c_int, [C.POINTER(Stage), i32, C.POINTER(vp)]),
+        "stomsfem_plan_launch": (C.c_int, [vp, i32, vp]),
+        "stomsfem_plan_free": (C.c_int, [vp]),
         "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
                                             C.POINTER(vp), vp]),
         "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
@@ -398,3 +409,47 @@ def coef_features(fmap: torch.Tensor, nfeat: int, xi: torch.Tensor, decades: flo
     _check("stomsfem_coef_features", lib().stomsfem_coef_features(
         N, nfine, _ptr(fmap), nfeat, _ptr(xi), nxi, decades, _ptr(out), _DT[out.dtype], _stream(stream)))
     return out
+
+
+FAMILY_BUMPS, FAMILY_FEATURES = 0, 1
+
+
+def make_stage(nc: int, m: int, xi: torch.Tensor, *, bumps: BumpFamily | None = None,
+               feature_map: torch.Tensor | None = None, nfeat: int = 0, decades: float = 4.0,
+               a_dtype=torch.float64, U: torch.Tensor | None = None, qoi_mean: torch.Tensor | None = None,
+               qoi_var: torch.Tensor | None = None, status: torch.Tensor | None = None) -> Stage:
+    """Descriptor of one plan stage (the tensors must outlive the plan)."""
+    assert xi.dtype == torch.float64 and xi.is_contiguous()
+    fam = bumps if bumps is not None else BumpFamily(0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    return Stage(nc, nc, m, xi.shape[0], _DT[a_dtype], FAMILY_BUMPS if bumps is not None else FAMILY_FEATURES, fam,
+                 _ptr(feature_map), nfeat, decades, _ptr(xi), xi.shape[1], _ptr(U), _ptr(qoi_mean), _ptr(qoi_var),
+                 _ptr(status))
+
+
+class Plan:
+    """Owns a library execution plan (stomsfem_plan_free on release)."""
+
+    def __init__(self, handle, nstage):
+        self.handle = handle
+        self.nstage = nstage
+
+    def launch(self, stage: int = -1, stream=None):
+        _check("stomsfem_plan_launch", lib().stomsfem_plan_launch(self.handle, stage, _stream(stream)))
+
+    def free(self):
+        if self.handle:
+            lib().stomsfem_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def plan_create(stages: list[Stage]) -> Plan:
+    arr = (Stage * len(stages))(*stages)
+    h = C.c_void_p()
+    _check("stomsfem_plan_create", lib().stomsfem_plan_create(arr, len(stages), C.byref(h)))
+    return Plan(h, len(stages))
