@@ -56,7 +56,8 @@ enum { STOMSFEM_F64 = 0, STOMSFEM_F32 = 1 };
 enum {
   STOMSFEM_PREC_F64 = 0,           /* FP64 factorisation and energies */
   STOMSFEM_PREC_F32_REFINE64 = 1,  /* FP32 arithmetic where the entry point allows it, FP64 residuals/energies */
-  STOMSFEM_PREC_BF16 = 2           /* BF16 matrix-core products with FP32 accumulation (surrogate) */
+  STOMSFEM_PREC_BF16 = 2,          /* BF16 matrix-core products with FP32 accumulation (surrogate) */
+  STOMSFEM_PREC_AUTO = 3           /* stomsfem_upscale: the autotuner's choice for (m, a_dtype), else FP64 */
 };
 
 /* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
@@ -132,6 +133,8 @@ typedef struct {
 
 /*   batches   : host array of nbatch descriptors (read during the call only)
  *   precision : STOMSFEM_PREC_F64 -- FP64 factorisation (asynchronous);
+ *               STOMSFEM_PREC_AUTO -- per batch, the precision the autotuner
+ *               chose for its (m, a_dtype) (FP64 when untuned);
  *               STOMSFEM_PREC_F32_REFINE64 (m <= 32) -- FP32 band LDL^T of
  *               K_II, FP64 residuals r = f - K_II x with FP64 coefficients,
  *               x += (LDL^T)^{-1} r until max_l |r^l|_inf / |f^l|_inf <=
@@ -376,6 +379,33 @@ int stomsfem_plan_create(const stomsfem_stage* stages, int32_t nstage, stomsfem_
 int stomsfem_plan_launch(stomsfem_plan* plan, int32_t stage, void* stream);
 /* Synchronous. */
 int stomsfem_plan_free(stomsfem_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the plain upscaling kernels.  For the batch's (m, a_dtype) on
+ * the current device it times, with HIP events over `reps` launches after a
+ * warm-up, every launch shape (workgroup size 64/128/256 of the per-lane
+ * kernel for m <= 8; 1 or 2 wavefronts per workgroup of the tiled kernel for
+ * m = 16, 32), keeps only shapes whose S equals the default shape's bit for
+ * bit, then times FP64 against STOMSFEM_PREC_F32_REFINE64 on a prefix of
+ * about 16384 pairs (the refined variant must agree to 1e-10 relative).  The
+ * fastest choice is recorded for the process and used by every later
+ * stomsfem_upscale (launch shape; precision when the caller passes
+ * STOMSFEM_PREC_AUTO) and by plans created afterwards.  Synchronous;
+ * overwrites batch->S (left holding the chosen configuration's result).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t m, a_dtype;
+  int32_t lane_block;     /* chosen workgroup size (m <= 8) */
+  int32_t tiled_waves;    /* chosen wavefronts per workgroup (m = 16, 32) */
+  int32_t precision;      /* STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32_REFINE64 */
+  int32_t candidates;     /* launch shapes timed */
+  double ms_default;      /* default shape, ms per launch */
+  double ms_best;         /* chosen shape, ms per launch */
+} stomsfem_tuning;
+
+int stomsfem_autotune(const stomsfem_batch* batch, int32_t reps, stomsfem_tuning* out, void* stream);
+/* Forget the choices made on the current device. */
+int stomsfem_tuning_reset(void);
 
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample

@@ -5,6 +5,10 @@
 #include <unordered_map>
 #include <vector>
 #include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <tuple>
 
 #include "common.h"
 #include "rb.h"
@@ -13,10 +17,10 @@
 #include "mixed.h"
 
 namespace stomsfem {
-hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st);
+hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st, int block);
 hipError_t launch_upscale_ref(const UpArgs& args, int a_dtype, hipStream_t st);
 size_t upscale_ref_lds_bytes(int m);
-hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st);
+hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st, int waves);
 bool tiled_supports(int m);
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
                          double* var, int32_t* status, double* work, hipStream_t st);
@@ -131,11 +135,36 @@ UpArgs to_args(const stomsfem_batch& b) {
 namespace stomsfem {
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
-// Plain upscaling of one homogeneous batch with the kernel suited to its m.
-hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st) {
-  if (args.m <= 8) return launch_upscale_small(args, a_dtype, st);
-  if (tiled_supports(args.m)) return launch_upscale_tiled(args, a_dtype, st);
+// Launch configuration of the plain upscaling kernels per (device, m,
+// coefficient dtype), chosen by stomsfem_autotune (defaults otherwise).
+struct LaunchCfg {
+  int lane_block = 64;   // workgroup size of the per-lane kernel (m <= 8)
+  int tiled_waves = 1;   // wavefronts per workgroup of the tiled kernel (m = 16, 32)
+  int precision = STOMSFEM_PREC_F64;
+  double ms_default = 0.0, ms_best = 0.0;
+  int tuned = 0;
+};
+std::mutex g_tune_mx;
+std::map<std::tuple<int, int, int>, LaunchCfg> g_tune;
+
+LaunchCfg tuned_cfg(int m, int a_dtype) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mx);
+  auto it = g_tune.find({dev, m, a_dtype});
+  return it == g_tune.end() ? LaunchCfg{} : it->second;
+}
+
+hipError_t launch_upscale_cfg(const UpArgs& args, int a_dtype, hipStream_t st, const LaunchCfg& c) {
+  if (args.m <= 8) return launch_upscale_small(args, a_dtype, st, c.lane_block);
+  if (tiled_supports(args.m)) return launch_upscale_tiled(args, a_dtype, st, c.tiled_waves);
   return launch_upscale_ref(args, a_dtype, st);
+}
+
+// Plain FP64 upscaling of one homogeneous batch with the kernel suited to its
+// m, in the tuned launch shape.
+hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st) {
+  return launch_upscale_cfg(args, a_dtype, st, tuned_cfg(args.m, a_dtype));
 }
 }  // namespace stomsfem
 
@@ -317,13 +346,15 @@ static int upscale_refined(const stomsfem_batch& b, hipStream_t st) {
 
 int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream) {
   if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(STOMSFEM_EINVAL, "upscale: bad batch list");
-  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64)
-    return fail(STOMSFEM_EINVAL, "upscale: precision must be STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32_REFINE64");
+  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64 && precision != STOMSFEM_PREC_AUTO)
+    return fail(STOMSFEM_EINVAL, "upscale: precision must be STOMSFEM_PREC_F64, _F32_REFINE64 or _AUTO");
   if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_BC_LINEAR is available");
   for (int i = 0; i < nbatch; ++i) {
     int rc = check_batch(batches[i], i);
     if (rc != STOMSFEM_OK) return rc;
-    if (precision == STOMSFEM_PREC_F32_REFINE64 && batches[i].nsamples > 0) {
+    const int prec_i =
+        precision == STOMSFEM_PREC_AUTO ? tuned_cfg(batches[i].m, batches[i].a_dtype).precision : precision;
+    if (prec_i == STOMSFEM_PREC_F32_REFINE64 && batches[i].nsamples > 0) {
       if (batches[i].m > 32) return fail(STOMSFEM_EINVAL, "upscale: FP32 + refinement needs m <= 32");
       int dev = 0, maxlds = 0;
       hipGetDevice(&dev);
@@ -337,7 +368,8 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
   for (int i = 0; i < nbatch; ++i) {
     const stomsfem_batch& b = batches[i];
     if (b.nsamples == 0) continue;
-    if (precision == STOMSFEM_PREC_F32_REFINE64) {
+    const int prec_b = precision == STOMSFEM_PREC_AUTO ? tuned_cfg(b.m, b.a_dtype).precision : precision;
+    if (prec_b == STOMSFEM_PREC_F32_REFINE64) {
       int rc = upscale_refined(b, (hipStream_t)stream);
       if (rc != STOMSFEM_OK) return rc;
       continue;
@@ -986,6 +1018,146 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
   if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "interp_apply: fallback count out of range");
   if (nfallback) *nfallback = (int64_t)n;
   return ri_plain_pairs(model, model->list, (int64_t)n, xi, nxi, S, status, 1, st);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static int time_launches(const std::function<int()>& launch, int reps, hipStream_t st, double* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int rc = e == hipSuccess ? launch() : STOMSFEM_EHIP;  // warm-up
+  if (rc == STOMSFEM_OK && e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && rc == STOMSFEM_OK && e == hipSuccess; ++r) rc = launch();
+  if (rc == STOMSFEM_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+  if (rc == STOMSFEM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (rc == STOMSFEM_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (rc != STOMSFEM_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  *ms = (double)t / reps;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_autotune(const stomsfem_batch* batch, int32_t reps, stomsfem_tuning* out, void* stream) {
+  if (!batch || reps < 1) return fail(STOMSFEM_EINVAL, "autotune: NULL batch or reps < 1");
+  int rc = check_batch(*batch, 0);
+  if (rc != STOMSFEM_OK) return rc;
+  if (batch->nsamples == 0) return fail(STOMSFEM_EINVAL, "autotune: empty batch");
+  hipStream_t st = (hipStream_t)stream;
+  const stomsfem_batch& b = *batch;
+  const UpArgs up = to_args(b);
+  const int64_t M = (int64_t)b.ncx * b.ncy;
+  const size_t sbytes = sizeof(double) * 10 * (size_t)up.npairs;
+  // 1. launch shape on the whole batch; every variant must reproduce the
+  //    default variant bit for bit (same arithmetic per pair)
+  std::vector<LaunchCfg> shapes;
+  if (b.m <= 8) {
+    for (int bs : {64, 128, 256}) shapes.push_back(LaunchCfg{bs, 1});
+  } else if (tiled_supports(b.m)) {
+    for (int wv : {1, 2}) shapes.push_back(LaunchCfg{64, wv});
+  } else {
+    shapes.push_back(LaunchCfg{});
+  }
+  std::vector<unsigned char> ref(sbytes), got(sbytes);
+  double best_ms = 0.0, default_ms = 0.0;
+  LaunchCfg best = shapes[0];
+  for (size_t i = 0; i < shapes.size(); ++i) {
+    double ms = 0.0;
+    const LaunchCfg c = shapes[i];
+    rc = time_launches([&]() {
+      hipError_t e = launch_upscale_cfg(up, b.a_dtype, st, c);
+      return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "autotune launch");
+    }, reps, st, &ms);
+    if (rc != STOMSFEM_OK) return rc;
+    hipError_t e = hipMemcpy(i == 0 ? ref.data() : got.data(), b.S, sbytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "autotune copy");
+    if (i > 0 && got != ref) continue;  // a shape that changes the result is never chosen
+    if (i == 0) default_ms = ms;
+    if (i == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  // 2. precision variant on a prefix of the samples (the refined variant can
+  //    be much slower); it must agree with FP64 to the refinement tolerance
+  best.precision = STOMSFEM_PREC_F64;
+  if (b.m <= 32) {
+    int dev = 0, maxlds = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (upscale_mixed_lds_bytes(b.m) + 256 <= (size_t)maxlds) {
+      stomsfem_batch sub = b;
+      sub.nsamples = std::max<int64_t>(1, std::min<int64_t>(b.nsamples, (16384 + M - 1) / M));
+      const size_t sub_bytes = sizeof(double) * 10 * (size_t)(sub.nsamples * M);
+      double ms64 = 0.0, ms32 = 0.0;
+      rc = time_launches([&]() {
+        hipError_t e = launch_upscale_cfg(to_args(sub), sub.a_dtype, st, best);
+        return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "autotune launch");
+      }, reps, st, &ms64);
+      if (rc != STOMSFEM_OK) return rc;
+      std::vector<double> s64(sub_bytes / 8), s32(sub_bytes / 8);
+      hipError_t e = hipMemcpy(s64.data(), b.S, sub_bytes, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "autotune copy");
+      rc = time_launches([&]() { return upscale_refined(sub, st); }, reps, st, &ms32);
+      if (rc != STOMSFEM_OK) return rc;
+      e = hipMemcpy(s32.data(), b.S, sub_bytes, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "autotune copy");
+      bool agree = true;
+      for (size_t p = 0; p < s64.size() / 10 && agree; ++p) {
+        double d = 0.0, sc = 0.0;
+        for (int q = 0; q < 10; ++q) {
+          d = std::max(d, std::fabs(s64[p * 10 + q] - s32[p * 10 + q]));
+          sc = std::max(sc, std::fabs(s64[p * 10 + q]));
+        }
+        agree = d <= 1e-10 * sc;
+      }
+      if (agree && ms32 < ms64) best.precision = STOMSFEM_PREC_F32_REFINE64;
+    }
+  }
+  // leave the batch's S from the chosen configuration
+  if (best.precision == STOMSFEM_PREC_F32_REFINE64) {
+    rc = upscale_refined(b, st);
+    if (rc != STOMSFEM_OK) return rc;
+  } else {
+    hipError_t e = launch_upscale_cfg(up, b.a_dtype, st, best);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "autotune final launch");
+  }
+  best.ms_default = default_ms;
+  best.ms_best = best_ms;
+  best.tuned = 1;
+  {
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tune_mx);
+    g_tune[{dev, b.m, b.a_dtype}] = best;
+  }
+  if (out) {
+    out->m = b.m;
+    out->a_dtype = b.a_dtype;
+    out->lane_block = best.lane_block;
+    out->tiled_waves = best.tiled_waves;
+    out->precision = best.precision;
+    out->ms_default = default_ms;
+    out->ms_best = best_ms;
+    out->candidates = (int32_t)shapes.size();
+  }
+  return STOMSFEM_OK;
+}
+
+int stomsfem_tuning_reset(void) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mx);
+  for (auto it = g_tune.begin(); it != g_tune.end();) {
+    if (std::get<0>(it->first) == dev) it = g_tune.erase(it);
+    else ++it;
+  }
+  return STOMSFEM_OK;
 }
 
 int stomsfem_workspace_reserve(int64_t bytes) {

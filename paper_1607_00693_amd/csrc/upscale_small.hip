@@ -21,8 +21,8 @@
 
 namespace stomsfem {
 
-template <int M, typename T>
-__global__ __launch_bounds__(64) void upscale_lane_kernel(UpArgs args) {
+template <int M, typename T, int BS>
+__global__ __launch_bounds__(BS) void upscale_lane_kernel(UpArgs args) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= args.npairs) return;
   const int Mc = args.ncx * args.ncy;
@@ -34,19 +34,25 @@ __global__ __launch_bounds__(64) void upscale_lane_kernel(UpArgs args) {
   cell.run(args.S + p * 10, args.status ? args.status + p : nullptr);
 }
 
-template <int M, typename T>
-static hipError_t launch_lane(const UpArgs& args, hipStream_t st) {
-  const int threads = 64;
-  const int64_t blocks = (args.npairs + threads - 1) / threads;
-  hipLaunchKernelGGL((upscale_lane_kernel<M, T>), dim3((unsigned)blocks), dim3(threads), 0, st, args);
+template <int M, typename T, int BS>
+static hipError_t launch_lane_bs(const UpArgs& args, hipStream_t st) {
+  const int64_t blocks = (args.npairs + BS - 1) / BS;
+  hipLaunchKernelGGL((upscale_lane_kernel<M, T, BS>), dim3((unsigned)blocks), dim3(BS), 0, st, args);
   return hipGetLastError();
 }
 
-hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st) {
+template <int M, typename T>
+static hipError_t launch_lane(const UpArgs& args, int block, hipStream_t st) {
+  if (block == 128) return launch_lane_bs<M, T, 128>(args, st);
+  if (block == 256) return launch_lane_bs<M, T, 256>(args, st);
+  return launch_lane_bs<M, T, 64>(args, st);
+}
+
+hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st, int block) {
   const bool f32 = a_dtype == STOMSFEM_F32;
 #define CASE(MM)                                                                           \
   case MM:                                                                                 \
-    return f32 ? launch_lane<MM, float>(args, st) : launch_lane<MM, double>(args, st);
+    return f32 ? launch_lane<MM, float>(args, block, st) : launch_lane<MM, double>(args, block, st);
   switch (args.m) {
     CASE(1)
     CASE(2)

@@ -78,24 +78,26 @@ __device__ __forceinline__ double recip(double d) {
   return __builtin_fma(r, e, r);
 }
 
-template <int M, int T, typename TA>
-__global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
+template <int M, int T, typename TA, int WV>
+__global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
   constexpr int NT = TL_NT;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
   constexpr int FW = (NT + 1) * T;
   using Lds = TiledLds<M, T>;
-  __shared__ Lds lds_all[TL_SLOTS];
+  __shared__ Lds lds_all[WV][TL_SLOTS];
 
-  const int lane = threadIdx.x;
+  // WV independent wavefronts per workgroup (a launch-shape choice only)
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   if (lane >= TL_SLOTS * TL_G) return;
   const int q = lane / TL_G, g = lane - q * TL_G;
-  Lds& sh = lds_all[q];
+  Lds& sh = lds_all[wave][q];
   // residue pair {P, Q}, P >= Q, of this lane: g = P (P + 1) / 2 + Q
   const int P = g >= 6 ? 3 : g >= 3 ? 2 : g >= 1 ? 1 : 0;
   const int Q = g - P * (P + 1) / 2;
 
-  int64_t p = (int64_t)blockIdx.x * TL_SLOTS + q;
+  int64_t p = ((int64_t)blockIdx.x * WV + wave) * TL_SLOTS + q;
   const bool valid = p < args.npairs;
   if (!valid) p = args.npairs - 1;
   const int Mc = args.ncx * args.ncy;
@@ -412,19 +414,26 @@ __global__ __launch_bounds__(64) void upscale_tiled_kernel(UpArgs args) {
 
 bool tiled_supports(int m) { return m == 16 || m == 32; }
 
-template <int M, int T>
+template <int M, int T, int WV>
 static hipError_t launch_t(const UpArgs& args, int a_dtype, hipStream_t st) {
-  const int64_t blocks = (args.npairs + TL_SLOTS - 1) / TL_SLOTS;
+  const int64_t per_block = (int64_t)TL_SLOTS * WV;
+  const int64_t blocks = (args.npairs + per_block - 1) / per_block;
   if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, float, WV>), dim3((unsigned)blocks), dim3(64 * WV), 0, st, args);
   else
-    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, double>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+    hipLaunchKernelGGL((upscale_tiled_kernel<M, T, double, WV>), dim3((unsigned)blocks), dim3(64 * WV), 0, st, args);
   return hipGetLastError();
 }
 
-hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st) {
-  if (args.m == 16) return launch_t<16, 4>(args, a_dtype, st);
-  if (args.m == 32) return launch_t<32, 8>(args, a_dtype, st);
+template <int M, int T>
+static hipError_t launch_tw(const UpArgs& args, int a_dtype, hipStream_t st, int waves) {
+  if (waves == 2) return launch_t<M, T, 2>(args, a_dtype, st);
+  return launch_t<M, T, 1>(args, a_dtype, st);
+}
+
+hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st, int waves) {
+  if (args.m == 16) return launch_tw<16, 4>(args, a_dtype, st, waves);
+  if (args.m == 32) return launch_tw<32, 8>(args, a_dtype, st, waves);
   return hipErrorInvalidValue;
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libstomsfem.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EVERSION = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
-PREC_F64, PREC_F32_REFINE64, PREC_BF16 = 0, 1, 2
+PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO = 0, 1, 2, 3
 MLP_NPARAM = 9940
 MLP_BATCH = 32
 MLP_KIN = 4
@@ -43,6 +43,12 @@ class Stage(C.Structure):
                 ("feature_map", C.c_void_p), ("nfeat", C.c_int32), ("decades", C.c_double),
                 ("xi", C.c_void_p), ("nxi", C.c_int32), ("U", C.c_void_p), ("qoi_mean", C.c_void_p),
                 ("qoi_var", C.c_void_p), ("status", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("m", C.c_int32), ("a_dtype", C.c_int32), ("lane_block", C.c_int32), ("tiled_waves", C.c_int32),
+                ("precision", C.c_int32), ("candidates", C.c_int32), ("ms_default", C.c_double),
+                ("ms_best", C.c_double)]
 
 
 class Batch(C.Structure):
@@ -99,6 +105,8 @@ def lib():
         "stomsfem_plan_create": (C.c_int, [C.POINTER(Stage), i32, C.POINTER(vp)]),
         "stomsfem_plan_launch": (C.c_int, [vp, i32, vp]),
         "stomsfem_plan_free": (C.c_int, [vp]),
+        "stomsfem_autotune": (C.c_int, [C.POINTER(Batch), i32, C.POINTER(Tuning), vp]),
+        "stomsfem_tuning_reset": (C.c_int, []),
         "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
                                             C.POINTER(vp), vp]),
         "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
@@ -453,3 +461,20 @@ def plan_create(stages: list[Stage]) -> Plan:
     h = C.c_void_p()
     _check("stomsfem_plan_create", lib().stomsfem_plan_create(arr, len(stages), C.byref(h)))
     return Plan(h, len(stages))
+
+
+def autotune(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None, reps: int = 5,
+             stream=None) -> dict:
+    """Tune the plain upscaling kernels for this batch's (m, dtype); the choice
+    is used by later calls in this process.  Returns the tuner's report."""
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, ncx * ncy, 10), dtype=torch.float64, device=a.device)
+    b = make_batch(a, ncx, ncy, m, S, None)
+    t = Tuning()
+    _check("stomsfem_autotune", lib().stomsfem_autotune(C.byref(b), reps, C.byref(t), _stream(stream)))
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+def tuning_reset():
+    _check("stomsfem_tuning_reset", lib().stomsfem_tuning_reset())
