@@ -39,8 +39,8 @@ constexpr int TL_NT = 4;               // tiles per window side
 constexpr int TL_G = 10;               // lanes per pair = NT (NT + 1) / 2
 constexpr int TL_SLOTS = 64 / TL_G;    // pairs per wavefront (6)
 
-// Per-pair LDS block, kept small: occupancy is limited by LDS (seven
-// wavefronts per CU at m = 32).  TL_PAD > 0 would stagger the panel row
+// Per-pair LDS block, kept small: occupancy is limited by LDS (eight
+// wavefronts per CU at m = 32, 19.7 KB each).  TL_PAD > 0 would stagger the panel row
 // blocks over the LDS banks, but costs one wavefront per CU, which was
 // measured to matter more.  The block size is padded to 80 mod 128 bytes so
 // that the six pairs of a wavefront start on different banks.
@@ -49,7 +49,7 @@ constexpr int TL_PAD = 0;
 template <int M, int T>
 struct TiledLdsCore {
   static constexpr int NT = TL_NT;
-  static constexpr int FW = (NT + 1) * T;  // rhs window rows
+  static constexpr int FW = NT * T;  // rhs window rows
   union {
     double pw[T][NT][T + TL_PAD];  // panel rows: pw[k][R'][i] = W(row R'*T+i of the panel, column k)
     double red[TL_G][13];          // final reduction (after the last panel)
@@ -59,7 +59,9 @@ struct TiledLdsCore {
   double fr[T][2];            // entering rows: diagonal and W couplings
   double fx[4];               // entering rows: SE of rows T-2, T-1 and S of row T-1 (+ pad)
   double f[FW][3];            // right-hand sides of the live rows (circular); the pivot
-                              // rows' slots hold D^{-1} y once the diagonal tile is factored
+                              // rows' slots hold D^{-1} y once the diagonal tile is factored.
+                              // Rows entering during a panel keep theirs in registers until
+                              // the panel is solved, then take the retired pivot rows' slots.
 };
 
 template <int M, int T>
@@ -79,11 +81,14 @@ __device__ __forceinline__ double recip(double d) {
 }
 
 template <int M, int T, typename TA, int WV>
-__global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
+// Occupancy floor: at m = 16 four wavefronts per SIMD (the LDS limit) beat
+// the spill-free register allocation (two) by 40% even with spills; at m = 32
+// two wavefronts per SIMD without spills.
+__global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kernel(UpArgs args) {
   constexpr int NT = TL_NT;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
-  constexpr int FW = (NT + 1) * T;
+  constexpr int FW = NT * T;
   using Lds = TiledLds<M, T>;
   __shared__ Lds lds_all[WV][TL_SLOTS];
 
@@ -125,8 +130,9 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
   };
   // stencil row r (tile row i): diagonal and W coupling into sh.fr[i], the
   // far-band couplings SE, S of the last two rows into sh.fx, right-hand
-  // sides into sh.f; fr[] returns (D, W, SE, S, SW) to the caller.
-  auto build_row = [&](int r, int i, const double* q4, double* fr) {
+  // sides into sh.f (or into rhs_out for rows entering during a panel);
+  // fr[] returns (D, W, SE, S, SW) to the caller.
+  auto build_row = [&](int r, int i, const double* q4, double* fr, double* rhs_out) {
     fr[0] = 1.0;
     fr[1] = fr[2] = fr[3] = fr[4] = 0.0;
     double rhs[3] = {0.0, 0.0, 0.0};
@@ -163,8 +169,13 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
       sh.fx[1] = fr[2];
       sh.fx[2] = fr[3];
     }
+    if (rhs_out) {
 #pragma unroll
-    for (int l = 0; l < 3; ++l) sh.f[r % FW][l] = rhs[l];
+      for (int l = 0; l < 3; ++l) rhs_out[l] = rhs[l];
+    } else {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) sh.f[r % FW][l] = rhs[l];
+    }
   };
   // original values of tile (row tile rt, column tile rt - dt) from sh.fr
   // Couplings sit at three tile offsets: dt = 0 (diagonal and W), dt = 1
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
       if (g < T) {
         double frv[5];
         load_quad(T * rt + g, q4);
-        build_row(T * rt + g, g, q4, frv);
+        build_row(T * rt + g, g, q4, frv, nullptr);
       }
       WAVE_SYNC();
       if (R0 == rt) fresh_tile(R0 - C0);
@@ -208,6 +219,7 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
   double q4n[4];
   if (g < T) load_quad(T * NT + g, q4n);
 
+  double ent[3] = {0.0, 0.0, 0.0};  // entering row's right-hand sides (lanes g < T)
   for (int J = 0; J < NP; ++J) {
     const int j0 = J % NT;
     // current tile of this lane: w(X) = J + ((X - J) mod NT)
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
       double q4[4] = {q4n[0], q4n[1], q4n[2], q4n[3]};
       if (J + 1 < NP) load_quad(r + T, q4n);
       double frv[5];
-      build_row(r, g, q4, frv);
+      build_row(r, g, q4, frv, ent);
 #pragma unroll
       for (int k = 0; k < T; ++k) {
         double v = 0.0;
@@ -285,58 +297,54 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
         for (int k = 0; k < T; ++k) sh.pw[k][rb][i] = tile[i][k];
     }
     WAVE_SYNC();
-    // 3b. panel rows: W = A L^{-T}; rhs -= W u.  Each lane owns rows
-    // rho = g + 10 t and solves them one at a time (solving two at a time
-    // saves LDS reads of L and u but exceeds the register budget at T = 8).
+    // 3b. panel rows: W = A L^{-T}; rhs -= W u.  Rows one at a time (two at
+    // a time saves LDS reads of L and u but exceeds the register budget at
+    // T = 8).  Lane g < T solves the entering row NE + g last, from and into
+    // its registers; the other NE rows go round the lanes (10 t + g), lanes
+    // >= T taking the last round.
     {
-      constexpr int NR = NT * T, RPL = (NR + TL_G - 1) / TL_G, CH = 1;
+      constexpr int NR = NT * T, NE = NR - T, RPL = (NR + TL_G - 1) / TL_G;
+      static_assert(T * (RPL - 1) + (TL_G - T) * RPL >= NE, "panel rows fit the lanes");
 #pragma unroll 1
-      for (int t0 = 0; t0 < RPL; t0 += CH) {
-        double w[CH][T], fa[CH][3];
-        int rows[CH];
-        bool oks[CH];
+      for (int t = 0; t < RPL; ++t) {
+        const bool last = t == RPL - 1;
+        const bool entering = last && g < T;
+        const int rho0 = !last ? TL_G * t + g : (g < T ? NE + g : TL_G * t + g - T);
+        const bool ok = entering || rho0 < NE;
+        const int rho = ok ? rho0 : 0;
+        double w[T], fa[3];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          const int t = t0 + c;
-          const int rho = g + TL_G * t;
-          oks[c] = t < RPL && ((t + 1) * TL_G <= NR || rho < NR);
-          rows[c] = oks[c] ? rho : 0;
-#pragma unroll
-          for (int k = 0; k < T; ++k) w[c][k] = sh.pw[k][rows[c] / T][rows[c] % T];
-          const double* fr = sh.f[(T * (J + 1) + rows[c]) % FW];
-          fa[c][0] = fr[0];
-          fa[c][1] = fr[1];
-          fa[c][2] = fr[2];
+        for (int k = 0; k < T; ++k) w[k] = sh.pw[k][rho / T][rho % T];
+        {
+          const double* fr = sh.f[(T * (J + 1) + rho) % FW];
+          fa[0] = entering ? ent[0] : fr[0];
+          fa[1] = entering ? ent[1] : fr[1];
+          fa[2] = entering ? ent[2] : fr[2];
         }
 #pragma unroll
         for (int k = 1; k < T; ++k)
 #pragma unroll
-          for (int kk = 0; kk < k; ++kk) {
-            const double lkk = sh.L[k * (k - 1) / 2 + kk];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) w[c][k] -= w[c][kk] * lkk;
-          }
+          for (int kk = 0; kk < k; ++kk) w[k] -= w[kk] * sh.L[k * (k - 1) / 2 + kk];
 #pragma unroll
         for (int k = 0; k < T; ++k) {
           const double* fu = sh.f[(T * J + k) % FW];
-          const double u0 = fu[0], u1 = fu[1], u2 = fu[2];
-#pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            fa[c][0] -= w[c][k] * u0;
-            fa[c][1] -= w[c][k] * u1;
-            fa[c][2] -= w[c][k] * u2;
-          }
+          fa[0] -= w[k] * fu[0];
+          fa[1] -= w[k] * fu[1];
+          fa[2] -= w[k] * fu[2];
         }
+        if (ok) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          if (!oks[c]) continue;
-          const int rho = rows[c];
-#pragma unroll
-          for (int k = 0; k < T; ++k) sh.pw[k][rho / T][rho % T] = w[c][k];
-          double* fr = sh.f[(T * (J + 1) + rho) % FW];
-          fr[0] = fa[c][0];
-          fr[1] = fa[c][1];
-          fr[2] = fa[c][2];
+          for (int k = 0; k < T; ++k) sh.pw[k][rho / T][rho % T] = w[k];
+          if (entering) {
+            ent[0] = fa[0];
+            ent[1] = fa[1];
+            ent[2] = fa[2];
+          } else {
+            double* fr = sh.f[(T * (J + 1) + rho) % FW];
+            fr[0] = fa[0];
+            fr[1] = fa[1];
+            fr[2] = fa[2];
+          }
         }
       }
     }
@@ -348,6 +356,14 @@ __global__ __launch_bounds__(64 * WV) void upscale_tiled_kernel(UpArgs args) {
       fresh_tile(Rn - Cn);
     }
     WAVE_SYNC();
+    // the entering rows' right-hand sides take the retired pivot slots (every
+    // read of the pivot rows' D^{-1} y happened before the barrier)
+    if (g < T) {
+      double* fe = sh.f[(T * (J + NT) + g) % FW];
+      fe[0] = ent[0];
+      fe[1] = ent[1];
+      fe[2] = ent[2];
+    }
     // 4b. trailing update of the new window [J+1, J+NT]
     {
       const int rb = Rn - J - 1, cb = Cn - J - 1;
