@@ -19,31 +19,56 @@ struct CoefArgs {
   void* a;
 };
 
+// One workgroup per 16 x 16 tile of one sample.  The oscillating factor is
+// separable, sin(2 pi x/eps) sin(2 pi y/eps), so its sines are evaluated once
+// per tile row and column (32 instead of 512 per tile) and shared in LDS;
+// every value is computed by the same expressions as the per-element form.
+constexpr int COEF_TILE = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void coef_bumps_kernel(CoefArgs c) {
-  const int64_t per = (int64_t)c.nfine * c.nfine;
-  const int64_t total = c.nsamples * per;
+__global__ __launch_bounds__(256) void coef_bumps_kernel(CoefArgs c, int tiles_x) {
+  __shared__ double sx[COEF_TILE], sy[COEF_TILE];
+  const int64_t tiles = (int64_t)tiles_x * tiles_x;
+  const int64_t nblk = c.nsamples * tiles;
   const double h = 1.0 / c.nfine;
+  const int lane = threadIdx.x;
   const BumpParams bp{c.g, c.rho, c.eps, c.base, c.amp, c.beta};
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = t / per;
-    const int rem = (int)(t - s * per);
-    const int iy = rem / c.nfine, ix = rem - iy * c.nfine;
-    ((T*)c.a)[t] = (T)bump_coef((ix + 0.5) * h, (iy + 0.5) * h, c.xi + s * c.nxi, bp);
+  // workgroup-uniform loop over (sample, tile): the grid is capped so that
+  // the launch stays within the per-dispatch thread limit
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t s = b / tiles;
+    const int tt = (int)(b - s * tiles);
+    const int tx = tt % tiles_x, ty = tt / tiles_x;
+    __syncthreads();  // the previous tile's readers are done with sx, sy
+    if (lane < COEF_TILE) {
+      const double x = ((tx * COEF_TILE + lane) + 0.5) * h;
+      sx[lane] = sin(2.0 * M_PI * x / c.eps);
+    } else if (lane < 2 * COEF_TILE) {
+      const double y = ((ty * COEF_TILE + lane - COEF_TILE) + 0.5) * h;
+      sy[lane - COEF_TILE] = sin(2.0 * M_PI * y / c.eps);
+    }
+    __syncthreads();
+    const int ix = tx * COEF_TILE + (lane % COEF_TILE), iy = ty * COEF_TILE + lane / COEF_TILE;
+    if (ix < c.nfine && iy < c.nfine) {
+      const double x = (ix + 0.5) * h, y = (iy + 0.5) * h;
+      const double field = bump_field(x, y, c.xi + s * c.nxi, bp);
+      const double osc = c.base + c.amp * sx[lane % COEF_TILE] * sy[lane / COEF_TILE];
+      ((T*)c.a)[(s * c.nfine + iy) * (int64_t)c.nfine + ix] = (T)(osc * exp(c.beta * field));
+    }
   }
 }
 
 hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
                              double base, double amp, double beta, void* a, int a_dtype, hipStream_t st) {
   CoefArgs c{nsamples, nfine, nxi, g, rho, eps, base, amp, beta, xi, a};
-  const int64_t total = nsamples * (int64_t)nfine * nfine;
-  if (total == 0) return hipSuccess;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 1 << 20) blocks = 1 << 20;
+  const int tiles_x = (nfine + COEF_TILE - 1) / COEF_TILE;
+  int64_t blocks = nsamples * (int64_t)tiles_x * tiles_x;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
   if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL(coef_bumps_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(coef_bumps_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, c, tiles_x);
   else
-    hipLaunchKernelGGL(coef_bumps_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(coef_bumps_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, c, tiles_x);
   return hipGetLastError();
 }
 
@@ -94,17 +119,25 @@ constexpr int FEAT_TILE = 4096;  // fine elements per workgroup
 template <typename T>
 __global__ __launch_bounds__(256) void coef_features_kernel(int64_t per, int32_t nfeat, const int32_t* __restrict__ map,
                                                             const double* __restrict__ xi, int32_t nxi, double decades,
-                                                            int64_t tiles, T* __restrict__ a) {
+                                                            int64_t tiles, int64_t nblk, T* __restrict__ a) {
   __shared__ double th[FEAT_MAX];
-  const int64_t s = blockIdx.x / tiles;
-  const int64_t e0 = (blockIdx.x - s * tiles) * FEAT_TILE;
-  for (int j = threadIdx.x; j < nfeat; j += 256) th[j] = pow(10.0, decades / (1.0 + exp(-xi[s * nxi + j])));
-  __syncthreads();
-  T* as = a + s * per;
-  const int64_t e1 = min(e0 + FEAT_TILE, per);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int32_t f = map[e];
-    as[e] = (T)((unsigned)f < (unsigned)nfeat ? th[f] : 1.0);
+  int64_t s_loaded = -1;
+  // workgroup-uniform loop over (sample, tile) with a capped grid
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t s = b / tiles;
+    const int64_t e0 = (b - s * tiles) * FEAT_TILE;
+    if (s != s_loaded) {
+      __syncthreads();
+      for (int j = threadIdx.x; j < nfeat; j += 256) th[j] = pow(10.0, decades / (1.0 + exp(-xi[s * nxi + j])));
+      __syncthreads();
+      s_loaded = s;
+    }
+    T* as = a + s * per;
+    const int64_t e1 = min(e0 + FEAT_TILE, per);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      const int32_t f = map[e];
+      as[e] = (T)((unsigned)f < (unsigned)nfeat ? th[f] : 1.0);
+    }
   }
 }
 
@@ -121,14 +154,15 @@ hipError_t launch_coef_features(int64_t nsamples, int nfine, const int32_t* map,
                                 double decades, void* a, int a_dtype, hipStream_t st) {
   const int64_t per = (int64_t)nfine * nfine;
   const int64_t tiles = (per + FEAT_TILE - 1) / FEAT_TILE;
-  const int64_t blocks = nsamples * tiles;
-  if (blocks == 0) return hipSuccess;
+  const int64_t nblk = nsamples * tiles;
+  if (nblk == 0) return hipSuccess;
+  const int64_t blocks = nblk < (1 << 20) ? nblk : (1 << 20);
   if (a_dtype == STOMSFEM_F32)
     hipLaunchKernelGGL(coef_features_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, per, nfeat, map, xi,
-                       nxi, decades, tiles, (float*)a);
+                       nxi, decades, tiles, nblk, (float*)a);
   else
     hipLaunchKernelGGL(coef_features_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, per, nfeat, map, xi,
-                       nxi, decades, tiles, (double*)a);
+                       nxi, decades, tiles, nblk, (double*)a);
   return hipGetLastError();
 }
 

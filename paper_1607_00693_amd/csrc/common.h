@@ -87,20 +87,30 @@ struct BumpParams {
   double rho, eps, base, amp, beta;
 };
 
-// a(x, xi) of the bump family at the point (x, y), xs = this sample's xi.
-// Only bumps whose centre cell lies within ceil(rho*g) cells are visited, in
-// increasing index order.
-__device__ __forceinline__ double bump_coef(double x, double y, const double* xs, const BumpParams& bp) {
-  const double rho2 = bp.rho * bp.rho;
+// sum_j xi_j psi_j(x, y) of the bump family at the point (x, y), xs = this
+// sample's xi.  Only bumps whose centre cell lies within ceil(rho*g) cells
+// are visited, in increasing index order.
+// (Multiplications by 1/g and 1/rho^2 replace the divisions: exact when g
+// and rho are powers of two, within an ulp otherwise.)
+__device__ __forceinline__ double bump_field(double x, double y, const double* xs, const BumpParams& bp) {
+  const double ginv = 1.0 / bp.g, rinv2 = 1.0 / (bp.rho * bp.rho);
   const int reach = (int)ceil(bp.rho * bp.g);
   const int bx = min((int)(x * bp.g), bp.g - 1), by = min((int)(y * bp.g), bp.g - 1);
   double field = 0.0;
-  for (int jy = max(by - reach, 0); jy <= min(by + reach, bp.g - 1); ++jy)
+  for (int jy = max(by - reach, 0); jy <= min(by + reach, bp.g - 1); ++jy) {
+    const double cy = (jy + 0.5) * ginv, dy2 = (y - cy) * (y - cy);
     for (int jx = max(bx - reach, 0); jx <= min(bx + reach, bp.g - 1); ++jx) {
-      const double cx = (jx + 0.5) / bp.g, cy = (jy + 0.5) / bp.g;
-      const double r2 = ((x - cx) * (x - cx) + (y - cy) * (y - cy)) / rho2;
+      const double cx = (jx + 0.5) * ginv;
+      const double r2 = ((x - cx) * (x - cx) + dy2) * rinv2;
       if (r2 < 1.0) field += xs[jy * bp.g + jx] * (1.0 - r2) * (1.0 - r2);
     }
+  }
+  return field;
+}
+
+// a(x, xi) of the bump family at the point (x, y).
+__device__ __forceinline__ double bump_coef(double x, double y, const double* xs, const BumpParams& bp) {
+  const double field = bump_field(x, y, xs, bp);
   const double osc = bp.base + bp.amp * sin(2.0 * M_PI * x / bp.eps) * sin(2.0 * M_PI * y / bp.eps);
   return osc * exp(bp.beta * field);
 }
