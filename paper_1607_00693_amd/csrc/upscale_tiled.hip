@@ -305,6 +305,15 @@ __global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kern
     {
       constexpr int NR = NT * T, NE = NR - T, RPL = (NR + TL_G - 1) / TL_G;
       static_assert(T * (RPL - 1) + (TL_G - T) * RPL >= NE, "panel rows fit the lanes");
+      // the pivot rows' D^{-1} y is the same for every row: read it once
+      double ur[T][3];
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double* fu = sh.f[(T * J + k) % FW];
+        ur[k][0] = fu[0];
+        ur[k][1] = fu[1];
+        ur[k][2] = fu[2];
+      }
 #pragma unroll 1
       for (int t = 0; t < RPL; ++t) {
         const bool last = t == RPL - 1;
@@ -327,10 +336,9 @@ __global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kern
           for (int kk = 0; kk < k; ++kk) w[k] -= w[kk] * sh.L[k * (k - 1) / 2 + kk];
 #pragma unroll
         for (int k = 0; k < T; ++k) {
-          const double* fu = sh.f[(T * J + k) % FW];
-          fa[0] -= w[k] * fu[0];
-          fa[1] -= w[k] * fu[1];
-          fa[2] -= w[k] * fu[2];
+          fa[0] -= w[k] * ur[k][0];
+          fa[1] -= w[k] * ur[k][1];
+          fa[2] -= w[k] * ur[k][2];
         }
         if (ok) {
 #pragma unroll
