@@ -226,6 +226,60 @@ def measure_channels(log, reps=3):
     return out
 
 
+def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((8000, 2e-3), (8000, 5e-4),
+                                                                           (8000, 1e-4))):
+    """Learned surrogate on the benchmark mesh: one MLP per patch trained on
+    ntrain plain solves (seed 2000 + workload), then gated BF16 inference with
+    the plain fallback on the benchmark's own xi, against the plain path from
+    xi (coefficient generation + upscaling, t_plain_ms)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    fam = sm.bump_family(wl)
+    lv, nl = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, fam)
+    mdl = sm.mlp_create(wl.nc, wl.nc, wl.m, lv, W.mlp_init(wl.M, 4000 + wl.seed % 1000), fam, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xi_tr = torch.from_numpy(W.uniform_xi(ntrain, wl.nxi, 2000 + wl.seed % 1000)).cuda()
+    S_tr = torch.empty((ntrain, wl.M, 10), dtype=torch.float64, device="cuda")
+    chunk = 256
+    for c0 in range(0, ntrain, chunk):  # training data from the plain path, in chunks
+        a_tr = sm.coef_bumps(xi_tr[c0:c0 + chunk], wl.nfine, **wl.coef_params())
+        sm.upscale(a_tr, wl.nc, wl.nc, wl.m, S=S_tr[c0:c0 + chunk])
+        del a_tr
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sm.mlp_set_data(mdl, xi_tr, S_tr)
+    perm = torch.from_numpy(W.permutation(ntrain, 5000 + wl.seed % 1000)).cuda()
+    t0 = time.perf_counter()
+    for steps, lr in schedule:
+        sm.mlp_train(mdl, steps, lr, perm)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    N = xi.shape[0]
+    S_su = torch.empty_like(S_plain)
+    status = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    t_su = _timed(lambda: sm.upscale_surrogate(mdl, xi, 1e-3, sm.PREC_BF16, S=S_su, status=status), reps=3)
+    st = status.cpu()
+    U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    U_s, _, _ = sm.coarse_solve(S_su, wl.nc, wl.nc)
+    u_err = float((torch.linalg.norm(U_s - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())
+    pairs = N * wl.M
+    out = {"workload": f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.M} per-patch MLPs (k<=4 -> 64x3 -> 2x10, GELU), "
+                       f"{ntrain} training samples/patch, {sum(s for s, _ in schedule)} Adam steps, the benchmark's "
+                       f"{N} samples, gate tau=1e-3, BF16 MFMA (3-term split); plain side = generation + upscaling",
+           "training_data_s": t_data, "train_s": t_train,
+           "pairs_per_s": pairs / t_su, "plain_pairs_per_s": pairs / (t_plain_ms * 1e-3),
+           "ratio": t_plain_ms * 1e-3 / t_su,
+           "accepted": float((st == 0).float().mean()), "fallback": float((st == 1).float().mean()),
+           "audited": float((st == 2).float().mean()), "max_coarse_rel_err": u_err}
+    log(f"surrogate on the benchmark mesh: {out}")
+    mdl.free()
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -455,6 +509,9 @@ def main():
         ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
                               "Chebyshev-Lobatto tensor nodes per local variable (k<=4), FP64; plain side = "
                               "coefficient generation + upscaling kernels")
+        print("[bench] learned surrogate at the benchmark mesh", file=sys.stderr, flush=True)
+        sur_out = measure_surrogate(wl, xi, S, t_gen + t_up,
+                                    lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
         print("[bench] FP32 factorisation + FP64 refinement on the first 64 samples", file=sys.stderr, flush=True)
         ns = min(64, wl.nsamples)
         a_sub, S_sub = a[:ns], S[:ns]
@@ -474,6 +531,7 @@ def main():
         print("[bench] reduced basis and learned surrogate at the 8x8 mesh", file=sys.stderr, flush=True)
         out["accelerations"] = measure_accelerations(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
         out["accelerations"]["random_interpolation_bench_mesh"] = ri_out
+        out["accelerations"]["learned_surrogate_bench_mesh"] = sur_out
         out["accelerations"]["fp32_solve_fp64_refinement_bench_mesh"] = mixed
         print("[bench] channels-and-inclusions workload through a graph plan", file=sys.stderr, flush=True)
         out["channels64_plan"] = measure_channels(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))

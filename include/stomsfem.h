@@ -239,7 +239,10 @@ int stomsfem_model_free(stomsfem_model* model);
  * accepted S are projected to zero row sums (S <- P S P, P = I - 1 1^T/4).
  * Rejected pairs, and 1% of accepted pairs chosen by a hash of the pair index
  * ((p * 2654435761) mod 100 == 0, p = s*M + K) for auditing, are recomputed
- * by the plain path (m = 8) with the coefficient regenerated from xi.
+ * by the plain FP64 path with the coefficient regenerated from xi: a fused
+ * kernel for m = 8 (asynchronous); for other m the listed pairs' coefficient
+ * blocks go through the upscaling kernels in chunks, after one synchronous
+ * read of their number.
  * ------------------------------------------------------------------------ */
 #define STOMSFEM_MLP_NPARAM 9940
 #define STOMSFEM_MLP_BATCH 32
@@ -256,7 +259,7 @@ typedef struct {
 int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfem_bump_family* fam, int32_t kmax,
                               int32_t* local_vars, int32_t* nlocal);
 
-/* Create a surrogate (m <= 8): local_vars host [M][4], init_params host
+/* Create a surrogate (1 <= m <= 48): local_vars host [M][4], init_params host
  * [M][STOMSFEM_MLP_NPARAM] (the caller draws the initial weights), fam = the
  * coefficient family used by the fallback, box = training box of the local
  * variables.  Synchronous. */

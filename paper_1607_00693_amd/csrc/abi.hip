@@ -582,7 +582,7 @@ int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfe
 int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
                         const stomsfem_bump_family* fam, double box, stomsfem_model** model) {
   if (!local_vars || !init_params || !model) return fail(STOMSFEM_EINVAL, "mlp_create: NULL argument");
-  if (ncx < 1 || ncy < 1 || m < 1 || m > 8) return fail(STOMSFEM_EINVAL, "mlp_create: need 1 <= m <= 8");
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 48) return fail(STOMSFEM_EINVAL, "mlp_create: need 1 <= m <= 48");
   if (!(box > 0)) return fail(STOMSFEM_EINVAL, "mlp_create: box must be > 0");
   *model = nullptr;
   const int Mc = ncx * ncy;
@@ -613,6 +613,12 @@ int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* loca
   A((void**)&md->sd, sizeof(double) * Mc * 10);
   A((void**)&md->sd_raw, sizeof(double) * Mc * 10);
   A((void**)&md->counter, sizeof(unsigned long long));
+  if (m != 8) {  // buffers of the chunked plain fallback (regenerate, upscale, compare)
+    md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+    A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+    A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+    A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  }
   if (e == hipSuccess) e = hipMemcpy(md->lv, local_vars, sizeof(int32_t) * Mc * MLP_KIN, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->params, init_params, sizeof(float) * (size_t)Mc * MLP_NP, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(md->m1, 0, sizeof(float) * (size_t)Mc * MLP_NP);
@@ -740,7 +746,6 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
     return fail(STOMSFEM_EINVAL, "surrogate: outputs must be device pointers");
   const int Mc = model->ncx * model->ncy;
   if (S) {
-    if (model->m != 8) return fail(STOMSFEM_EINVAL, "surrogate: the plain fallback is built for m = 8");
     if (model->fam.g < 1 || model->fam.g * model->fam.g > nxi)
       return fail(STOMSFEM_EINVAL, "surrogate: the model's coefficient family does not match xi");
     const int64_t need = nsamples * Mc;
@@ -783,8 +788,46 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   a.bump_base = model->fam.base;
   a.bump_amp = model->fam.amp;
   a.bump_beta = model->fam.beta;
-  hipError_t e = launch_mlp_infer(a, precision == STOMSFEM_PREC_BF16, (hipStream_t)stream);
-  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "surrogate launch");
+  a.m = model->m;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_mlp_infer(a, precision == STOMSFEM_PREC_BF16, st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate launch");
+  if (!S || model->m == 8) return STOMSFEM_OK;
+  // plain fallback for m != 8: the listed pairs in chunks (reads the count)
+  unsigned long long n = 0;
+  e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate fallback count");
+  if (n > (unsigned long long)(nsamples * Mc)) return fail(STOMSFEM_EHIP, "surrogate: fallback count out of range");
+  for (int64_t start = 0; start < (int64_t)n && e == hipSuccess; start += model->chunk) {
+    const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
+    RegenArgs r{};
+    r.ncx = model->ncx;
+    r.ncy = model->ncy;
+    r.m = model->m;
+    r.nxi = nxi;
+    r.bp = BumpParams{model->fam.g, model->fam.rho, model->fam.eps, model->fam.base, model->fam.amp, model->fam.beta};
+    r.pairs = model->list + start;
+    r.count = cnt;
+    r.xi = xi;
+    r.out = model->blk;
+    e = launch_regen_blocks(r, st);
+    if (e == hipSuccess) {
+      UpArgs u{};
+      u.nsamples = cnt;
+      u.ncx = u.ncy = 1;
+      u.m = model->m;
+      u.npairs = cnt;
+      u.a = model->blk;
+      u.S = model->Sc;
+      u.status = model->stc;
+      e = launch_upscale_any(u, STOMSFEM_F64, st);
+    }
+    if (e == hipSuccess)
+      e = launch_mlp_fallback_finish(model->list + start, cnt, model->Sc, model->stc, S, status,
+                                     (unsigned long long*)stats, st);
+  }
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "surrogate fallback launch");
 }
 
 int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,

@@ -71,10 +71,17 @@ struct MlpInferArgs {
   unsigned long long* stats;  // [4] or NULL
   int32_t bump_g;
   double bump_rho, bump_eps, bump_base, bump_amp, bump_beta;
+  int32_t m;            // fine cells per patch side; the fused fallback serves m = 8
 };
 
 hipError_t launch_mlp_train(const MlpTrainArgs& a, bool train, hipStream_t st);
 hipError_t launch_mlp_data(const MlpDataArgs& d, hipStream_t st);
 hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st);
+// Second half of the plain fallback for m != 8: the listed pairs' plain S
+// (Sc, stc, computed by the regular kernels on regenerated coefficients) is
+// compared with the prediction in S, stored, and counted as the fused
+// fallback does.
+hipError_t launch_mlp_fallback_finish(const int64_t* list, int64_t count, const double* Sc, const int32_t* stc,
+                                      double* S, int32_t* status, unsigned long long* stats, hipStream_t st);
 
 }  // namespace stomsfem

@@ -614,6 +614,38 @@ __global__ __launch_bounds__(64) void mlp_fallback_kernel(MlpInferArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void mlp_fallback_finish_kernel(const int64_t* __restrict__ list, int64_t count,
+                                                                  const double* __restrict__ Sc,
+                                                                  const int32_t* __restrict__ stc, double* S,
+                                                                  int32_t* status, unsigned long long* stats) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const int64_t p = list[i];
+  double* So = S + p * 10;
+  double err = 0.0, sc = 0.0;
+  for (int q = 0; q < 10; ++q) {
+    const double v = Sc[i * 10 + q];
+    err = fmax(err, fabs(So[q] - v));
+    sc = fmax(sc, fabs(v));
+    So[q] = v;
+  }
+  const double rel = sc > 0 ? err / sc : 0.0;
+  const bool audited = status && status[p] == MLP_ST_AUDIT;
+  if (stats) {
+    atomicAdd(&stats[audited ? 1 : 0], 1ull);
+    atomicMax(&stats[audited ? 3 : 2], (unsigned long long)__double_as_longlong(rel));
+  }
+  if (status) status[p] = stc[i] != STOMSFEM_OK ? stc[i] : (audited ? MLP_ST_AUDIT : MLP_ST_FALLBACK);
+}
+
+hipError_t launch_mlp_fallback_finish(const int64_t* list, int64_t count, const double* Sc, const int32_t* stc,
+                                      double* S, int32_t* status, unsigned long long* stats, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mlp_fallback_finish_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, list, count,
+                     Sc, stc, S, status, stats);
+  return hipGetLastError();
+}
+
 hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
   if (a.S) {
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)a.count, 1);
@@ -629,7 +661,7 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
     hipLaunchKernelGGL(mlp_infer_f32_kernel, grid, dim3(64), 0, st, a);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !a.S) return e;
+  if (e != hipSuccess || !a.S || a.m != 8) return e;
   int64_t blocks = (a.nsamples * a.npatch + 63) / 64;
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;

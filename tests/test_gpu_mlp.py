@@ -139,3 +139,39 @@ def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
     ts = timed(lambda: sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, S=S_sur))
     say(f"plain {N * wl.M / tp / 1e9:.2f} G pairs/s, surrogate {N * wl.M / ts / 1e9:.2f} G pairs/s, "
         f"gain {tp / ts:.2f}x")
+
+
+def test_surrogate_mesh32_generic_fallback(sm):
+    # H/h = 32: the plain fallback regenerates the listed pairs' coefficient
+    # blocks and runs them through the upscaling kernels in chunks
+    wl = W.MESH32
+    model, lv, nl, _ = _model(sm, wl, 4002)
+    ntr = 256
+    xi_tr = torch.from_numpy(W.uniform_xi(ntr, wl.nxi, 2002)).cuda()
+    S_tr = sm.upscale(sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    sm.mlp_set_data(model, xi_tr, S_tr)
+    perm = torch.from_numpy(W.permutation(ntr, 5002)).cuda()
+    for steps, lr in ((1500, 2e-3), (1500, 5e-4)):
+        sm.mlp_train(model, steps, lr, perm)
+    N = 48
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, wl.seed)).cuda()
+    S_plain = sm.upscale(sm.coef_bumps(xi, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    status = torch.full((N, wl.M), -9, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    S_sur = sm.upscale_surrogate(model, xi, 1e-3, sm.PREC_BF16, status=status, stats=stats)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    Sp, Ss = S_plain.cpu().numpy(), S_sur.cpu().numpy()
+    assert set(np.unique(st)) <= {0, 1, 2}
+    fb, aud = st == 1, st == 2
+    say(f"mesh32: accepted {(st == 0).mean():.3f}, fallback {fb.mean():.3f}, audited {aud.mean():.4f}")
+    assert fb.any() and aud.any()
+    # recomputed pairs equal the plain path bit for bit; accepted ones pass the gate
+    assert np.array_equal(Ss[fb | aud], Sp[fb | aud])
+    s = stats.cpu().numpy().view(np.uint64)
+    assert s[0] == fb.sum() and s[1] == aud.sum()
+    U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    U_s, _, _ = sm.coarse_solve(S_sur, wl.nc, wl.nc)
+    ue = torch.linalg.norm(U_s - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)
+    assert float(ue.max()) < 1e-3
+    model.free()
