@@ -174,3 +174,35 @@ def test_coarse_two_by_two_closed_form(sm):
     torch.cuda.synchronize()
     assert np.abs(U.cpu().numpy() - 3.0 / 32.0).max() < 1e-15
     assert abs(var.cpu().numpy()[0]) < 1e-16
+
+
+def test_mesh32_full_batch_sampled(sm, orc):
+    # the benchmark's configuration: 32 x 32 coarse, H/h = 32, all 4096
+    # samples in one batch (34 GB of FP64 coefficients), the autotuned launch;
+    # sampled pairs and whole samples against the oracle
+    wl = W.MESH32
+    xi_np = W.uniform_xi(wl.nsamples, wl.nxi, wl.seed)
+    xi = torch.from_numpy(xi_np).cuda()
+    a = sm.coef_bumps(xi, wl.nfine, **wl.coef_params())
+    S = torch.empty((wl.nsamples, wl.M, 10), dtype=torch.float64, device="cuda")
+    rep = sm.autotune(a, wl.nc, wl.nc, wl.m, S=S, reps=1)
+    st = torch.full((wl.nsamples, wl.M), -9, dtype=torch.int32, device="cuda")
+    sm.upscale(a, wl.nc, wl.nc, wl.m, S=S, status=st)
+    U, qm, qv = sm.coarse_solve(S, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    say(f"mesh32 full batch: tuned {rep}")
+    assert int((st != 0).sum()) == 0
+    assert bool(torch.isfinite(S).all()) and bool(torch.isfinite(U).all())
+    rng = np.random.default_rng(77)
+    samples = [0, wl.nsamples - 1] + rng.choice(wl.nsamples, 2, replace=False).tolist()
+    for s in samples:
+        a_s = orc.coef_bumps(xi_np[s:s + 1], wl.nfine, **wl.coef_params())
+        np.testing.assert_allclose(a[s].cpu().numpy(), a_s[0], rtol=1e-14, atol=0)
+        Sr, _, _ = orc.upscale(a_s, wl.nc, wl.nc, wl.m)
+        assert s_relerr(S[s].cpu().numpy(), Sr[0]) <= STOL
+        Ur, _, _ = orc.coarse_solve(Sr, wl.nc, wl.nc)
+        assert u_relerr(U[s:s + 1].cpu().numpy(), Ur) <= UTOL
+    # QoI: the sample mean of U over the batch
+    np.testing.assert_allclose(qm.cpu().numpy(), U.mean(dim=0).cpu().numpy(), rtol=1e-12, atol=0)
+    sm.tuning_reset()
+    del a
