@@ -14,6 +14,10 @@
 namespace stomsfem {
 
 constexpr int COARSE_THREADS = 256;
+constexpr int COARSE_NQ = 16;  // trailing-triangle entries per thread: B (B+1)/2 <= 4096, i.e. ncx <= 90
+
+// x mod w for 0 <= x < 2w
+__device__ __forceinline__ int wrap(int x, int w) { return x >= w ? x - w : x; }
 
 struct CoarseArgs {
   int32_t ncx, ncy;
@@ -43,11 +47,24 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
   double* Wn = smem;        // WN*WN
   double* F = Wn + WN * WN;  // WN (forward-substituted rhs window)
   double* X = F + WN;        // WN (backward substitution window)
+  double* Ec = X + WN;       // 4 x ncx x 10: ring of element rows of S (row e in slot e % 4)
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int Mc = ncx * ncy;
   const double H = 1.0 / ncx;
   double* Lc = args.work + (int64_t)blockIdx.x * nU * WN;  // column j: [d_j, l_{j+1,j}, ..., l_{j+B,j}]
+  // entries (io >= ko) of the B x B trailing triangle handled by this thread,
+  // the same for every pivot column (io = B marks an unused slot)
+  int tio[COARSE_NQ], tko[COARSE_NQ];
+#pragma unroll
+  for (int q = 0; q < COARSE_NQ; ++q) {
+    const int t = tid + COARSE_THREADS * q;
+    int io = 0;
+    while ((io + 1) * (io + 2) / 2 <= t) ++io;
+    const bool used = t < B * (B + 1) / 2;
+    tio[q] = used ? io : B;
+    tko[q] = used ? t - io * (io + 1) / 2 : 0;
+  }
 
   for (int64_t s = blockIdx.x; s < args.nsamples; s += gridDim.x) {
     const double* Ss = args.S + s * (int64_t)Mc * 10;
@@ -55,6 +72,17 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     __syncthreads();
     for (int i = tid; i < WN * WN; i += blockDim.x) Wn[i] = 0.0;
     if (tid == 0) bad = 0;
+    // Element rows of S go through an LDS ring.  Node row iy uses element rows
+    // iy and iy + 1.  Rows 0..3 are loaded here; in the elimination loop
+    // (where a barrier follows every inserted row) the first node of node
+    // row iy >= 2 loads element row iy + 2 into the slot of row iy - 2, which
+    // only node rows up to iy - 2 used; node row iy + 1 needs it nix columns
+    // later.
+    auto load_erow = [&](int e) {
+      if (e < ncy)
+        for (int t = tid; t < ncx * 10; t += blockDim.x) Ec[(e % 4) * ncx * 10 + t] = Ss[(int64_t)e * ncx * 10 + t];
+    };
+    for (int e = 0; e < 4; ++e) load_erow(e);
     __syncthreads();
 
     // Row r of the coarse system: node (ix, iy) = grid node (px, py); its four
@@ -62,10 +90,13 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     // local node 2, 3, 1, 0 respectively.
     auto insert_row = [&](int r) {
       const int ix = r % nix, iy = r / nix, px = ix + 1, py = iy + 1;
-      const double* sSW = Ss + ((py - 1) * ncx + (px - 1)) * 10;
-      const double* sSE = Ss + ((py - 1) * ncx + px) * 10;
-      const double* sNW = Ss + (py * ncx + (px - 1)) * 10;
-      const double* sNE = Ss + (py * ncx + px) * 10;
+      if (ix == 0 && iy >= 2 && r >= B) load_erow(iy + 2);
+      const double* eS = Ec + ((py - 1) % 4) * ncx * 10;
+      const double* eN = Ec + (py % 4) * ncx * 10;
+      const double* sSW = eS + (px - 1) * 10;
+      const double* sSE = eS + px * 10;
+      const double* sNW = eN + (px - 1) * 10;
+      const double* sNE = eN + px * 10;
       if (tid <= B) {
         const int t = tid;
         double v = 0.0;
@@ -74,7 +105,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
         if (t == nix - 1 && iy >= 1 && ix <= nix - 2) v += selem(sSE, 3, 1);
         if (t == nix && iy >= 1) v += selem(sSW, 2, 1) + selem(sSE, 3, 0);
         if (t == nix + 1 && iy >= 1 && ix >= 1) v += selem(sSW, 2, 0);
-        if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;
+        if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;  // once per row
       } else if (tid == B + 1) {
         double b;
         if (args.load) {
@@ -101,22 +132,22 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       const int cnt = (j + B < nU - 1 ? j + B : nU - 1) - j;
       // column j of L (and the pivot) to the workspace; rhs forward step
       if (tid <= cnt) {
-        const double v = tid == 0 ? d : Wn[((j + tid) % WN) * WN + jj] * inv;
+        const int rt = wrap(jj + tid, WN);
+        const double v = tid == 0 ? d : Wn[rt * WN + jj] * inv;
         Lc[(int64_t)j * WN + tid] = v;
-        if (tid > 0) F[(j + tid) % WN] -= v * F[jj];
+        if (tid > 0) F[rt] -= v * F[jj];
       }
       if (tid == 0) {
         if (!(d > 0.0)) bad = 1;
         Us[j] = F[jj];  // y_j, overwritten by x_j below
       }
-      const int npairs = cnt * (cnt + 1) / 2;
-      for (int q = tid; q < npairs; q += blockDim.x) {
-        int io = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-        while (io * (io + 1) / 2 > q) --io;
-        while ((io + 1) * (io + 2) / 2 <= q) ++io;
-        const int ko = q - io * (io + 1) / 2;
-        const int i = j + 1 + io, k = j + 1 + ko;
-        Wn[(i % WN) * WN + (k % WN)] -= Wn[(i % WN) * WN + jj] * inv * Wn[(k % WN) * WN + jj];
+      // rank-1 update of the trailing triangle: this thread's fixed entries
+#pragma unroll
+      for (int q = 0; q < COARSE_NQ; ++q) {
+        if (tio[q] < cnt) {
+          const int ri = wrap(jj + 1 + tio[q], WN), rk = wrap(jj + 1 + tko[q], WN);
+          Wn[ri * WN + rk] -= Wn[ri * WN + jj] * inv * Wn[rk * WN + jj];
+        }
       }
       __syncthreads();
     }
@@ -165,7 +196,7 @@ __global__ void qoi_kernel(int64_t N, int nU, const double* U, double* mean, dou
 
 size_t coarse_lds_bytes(int ncx) {
   const int WN = ncx + 1;
-  return sizeof(double) * ((size_t)WN * WN + 2 * (size_t)WN);
+  return sizeof(double) * ((size_t)WN * WN + 2 * (size_t)WN + 40 * (size_t)ncx);
 }
 
 int64_t coarse_grid(int64_t nsamples) { return nsamples < 2048 ? nsamples : 2048; }
@@ -177,6 +208,7 @@ int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                          double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
   const int nU = (ncx - 1) * (ncy - 1);
+  if (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ) return hipErrorInvalidValue;
   if (N > 0 && nU > 0) {
     CoarseArgs a{ncx, ncy, N, S, load, U, status, work};
     hipLaunchKernelGGL(coarse_solve_kernel, dim3((unsigned)coarse_grid(N)), dim3(COARSE_THREADS),
