@@ -14,7 +14,17 @@
 namespace stomsfem {
 
 constexpr int COARSE_THREADS = 256;
-constexpr int COARSE_NQ = 16;  // trailing-triangle entries per thread: B (B+1)/2 <= 4096, i.e. ncx <= 90
+constexpr int COARSE_NQ = 12;  // largest NQ: B (B+1)/2 <= 3072
+constexpr int COARSE_BMAX = 72;
+
+// Workgroup barrier that orders LDS only: a pivot step does not wait for
+// its global stores (retired L columns, y_j) to complete.
+#define COARSE_SYNC()                                                 \
+  do {                                                                \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");   \
+    __builtin_amdgcn_s_barrier();                                     \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");   \
+  } while (0)
 
 // x mod w for 0 <= x < 2w
 __device__ __forceinline__ int wrap(int x, int w) { return x >= w ? x - w : x; }
@@ -40,6 +50,8 @@ __device__ __forceinline__ double selem(const double* Sk, int i, int j) {
   return Sk[base + (j - i)];
 }
 
+// NQ = trailing-triangle entries per lane, >= B (B+1) / (2 * 64).
+template <int NQ>
 __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs args) {
   extern __shared__ double smem[];
   const int ncx = args.ncx, ncy = args.ncy;
@@ -49,21 +61,21 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
   double* X = F + WN;        // WN (backward substitution window)
   double* Ec = X + WN;       // 4 x ncx x 10: ring of element rows of S (row e in slot e % 4)
   __shared__ int bad;
+  __shared__ double colv[COARSE_BMAX];  // pivot column (unscaled), a separate object from the window
   const int tid = threadIdx.x;
   const int Mc = ncx * ncy;
   const double H = 1.0 / ncx;
   double* Lc = args.work + (int64_t)blockIdx.x * nU * WN;  // column j: [d_j, l_{j+1,j}, ..., l_{j+B,j}]
-  // entries (io >= ko) of the B x B trailing triangle handled by this thread,
-  // the same for every pivot column (io = B marks an unused slot)
-  int tio[COARSE_NQ], tko[COARSE_NQ];
+  // entries (io >= ko) of the B x B trailing triangle handled by this lane,
+  // the same for every pivot column, packed io | ko << 8 (io = B: unused)
+  int tik[NQ];
 #pragma unroll
-  for (int q = 0; q < COARSE_NQ; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int t = tid + COARSE_THREADS * q;
     int io = 0;
     while ((io + 1) * (io + 2) / 2 <= t) ++io;
     const bool used = t < B * (B + 1) / 2;
-    tio[q] = used ? io : B;
-    tko[q] = used ? t - io * (io + 1) / 2 : 0;
+    tik[q] = used ? (io | ((t - io * (io + 1) / 2) << 8)) : B;
   }
 
   for (int64_t s = blockIdx.x; s < args.nsamples; s += gridDim.x) {
@@ -97,8 +109,19 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       const double* sSE = eS + px * 10;
       const double* sNW = eN + (px - 1) * 10;
       const double* sNE = eN + px * 10;
-      if (tid <= B) {
-        const int t = tid;
+      for (int t = tid; t <= B + 1; t += COARSE_THREADS) {
+        if (t > B) {
+          double b;
+          if (args.load) {
+            const double* L = args.load;
+            b = (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
+                (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
+          } else {
+            b = H * H;  // four elements, int_K p^l = H^2/4 each
+          }
+          F[r % WN] = b;
+          continue;
+        }
         double v = 0.0;
         if (t == 0) v += (selem(sSW, 2, 2) + selem(sSE, 3, 3)) + (selem(sNW, 1, 1) + selem(sNE, 0, 0));
         if (t == 1 && ix >= 1) v += selem(sSW, 2, 3) + selem(sNW, 1, 0);
@@ -106,16 +129,6 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
         if (t == nix && iy >= 1) v += selem(sSW, 2, 1) + selem(sSE, 3, 0);
         if (t == nix + 1 && iy >= 1 && ix >= 1) v += selem(sSW, 2, 0);
         if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;  // once per row
-      } else if (tid == B + 1) {
-        double b;
-        if (args.load) {
-          const double* L = args.load;
-          b = (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
-              (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
-        } else {
-          b = H * H;  // four elements, int_K p^l = H^2/4 each
-        }
-        F[r % WN] = b;
       }
     };
 
@@ -124,33 +137,51 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     for (int j = 0; j < nU; ++j) {
       if (j + B < nU) {
         insert_row(j + B);
-        __syncthreads();
+        COARSE_SYNC();
       }
       const int jj = j % WN;
       const double d = Wn[jj * WN + jj];
       const double inv = 1.0 / d;
       const int cnt = (j + B < nU - 1 ? j + B : nU - 1) - j;
       // column j of L (and the pivot) to the workspace; rhs forward step
-      if (tid <= cnt) {
-        const int rt = wrap(jj + tid, WN);
-        const double v = tid == 0 ? d : Wn[rt * WN + jj] * inv;
-        Lc[(int64_t)j * WN + tid] = v;
-        if (tid > 0) F[rt] -= v * F[jj];
+      for (int t = tid; t <= cnt; t += COARSE_THREADS) {
+        const int rt = wrap(jj + t, WN);
+        const double c = Wn[rt * WN + jj];
+        const double v = t == 0 ? d : c * inv;
+        if (t > 0) colv[t - 1] = c;
+        Lc[(int64_t)j * WN + t] = v;
+        if (t > 0) F[rt] -= v * F[jj];
       }
+      COARSE_SYNC();
       if (tid == 0) {
         if (!(d > 0.0)) bad = 1;
         Us[j] = F[jj];  // y_j, overwritten by x_j below
       }
-      // rank-1 update of the trailing triangle: this thread's fixed entries
+      // rank-1 update of the trailing triangle, this lane's fixed entries:
+      // all reads first, then all writes (distinct addresses), so that the
+      // reads are not serialised behind possibly aliasing writes
+      {
+        double wv[NQ];
+        int idx[NQ];
 #pragma unroll
-      for (int q = 0; q < COARSE_NQ; ++q) {
-        if (tio[q] < cnt) {
-          const int ri = wrap(jj + 1 + tio[q], WN), rk = wrap(jj + 1 + tko[q], WN);
-          Wn[ri * WN + rk] -= Wn[ri * WN + jj] * inv * Wn[rk * WN + jj];
+        for (int q = 0; q < NQ; ++q) {
+          const int io = tik[q] & 255, ko = tik[q] >> 8;
+          idx[q] = wrap(jj + 1 + io, WN) * WN + wrap(jj + 1 + ko, WN);
+          wv[q] = io < cnt ? Wn[idx[q]] : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int io = tik[q] & 255, ko = tik[q] >> 8;
+          if (io < cnt) wv[q] -= colv[io] * inv * colv[ko];
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if ((tik[q] & 255) < cnt) Wn[idx[q]] = wv[q];
       }
-      __syncthreads();
+      COARSE_SYNC();
     }
+    // the retired columns and y must be visible to the backward substitution
+    __syncthreads();
     // backward substitution x_j = y_j / d_j - sum_{t=1..B} l_{j+t,j} x_{j+t}
     if (tid < 64) {
       for (int t = tid; t < WN; t += 64) X[t] = 0.0;
@@ -199,7 +230,7 @@ size_t coarse_lds_bytes(int ncx) {
   return sizeof(double) * ((size_t)WN * WN + 2 * (size_t)WN + 40 * (size_t)ncx);
 }
 
-int64_t coarse_grid(int64_t nsamples) { return nsamples < 2048 ? nsamples : 2048; }
+int64_t coarse_grid(int64_t nsamples) { return nsamples < 4096 ? nsamples : 4096; }
 
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
   return coarse_grid(nsamples) * (int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1);
@@ -208,11 +239,16 @@ int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                          double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
   const int nU = (ncx - 1) * (ncy - 1);
-  if (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ) return hipErrorInvalidValue;
+  if (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ || ncx > COARSE_BMAX) return hipErrorInvalidValue;
   if (N > 0 && nU > 0) {
     CoarseArgs a{ncx, ncy, N, S, load, U, status, work};
-    hipLaunchKernelGGL(coarse_solve_kernel, dim3((unsigned)coarse_grid(N)), dim3(COARSE_THREADS),
-                       coarse_lds_bytes(ncx), st, a);
+    const int need = (ncx * (ncx + 1) / 2 + COARSE_THREADS - 1) / COARSE_THREADS;
+    const dim3 grid((unsigned)coarse_grid(N)), block(COARSE_THREADS);
+    const size_t lds = coarse_lds_bytes(ncx);
+    if (need <= 4)
+      hipLaunchKernelGGL(coarse_solve_kernel<4>, grid, block, lds, st, a);
+    else
+      hipLaunchKernelGGL(coarse_solve_kernel<COARSE_NQ>, grid, block, lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
