@@ -34,3 +34,31 @@ def test_library_exports_every_declared_symbol():
     assert not missing, f"not exported: {missing}"
     lib.stomsfem_version.restype = ctypes.c_int
     assert lib.stomsfem_version() == 1
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    # the product path has no CPU fallback: a missing library is an error
+    from paper_1607_00693_amd import stomsfem
+
+    monkeypatch.setattr(stomsfem, "_lib", None)
+    monkeypatch.setattr(stomsfem, "LIB_PATH", str(tmp_path / "libstomsfem.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        stomsfem.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        stomsfem.version()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_validation_without_gpu():
+    # argument checks run on the host before anything touches a device
+    lib = ctypes.CDLL(LIB)
+    lib.stomsfem_coarse_solve.restype = ctypes.c_int
+    rc = lib.stomsfem_coarse_solve(ctypes.c_int32(0), ctypes.c_int32(3), ctypes.c_int64(1), None, None, None, None,
+                                   None, None, None)
+    assert rc == -1  # EINVAL: ncx < 1
+    lib.stomsfem_last_error.restype = ctypes.c_char_p
+    assert b"bad sizes" in lib.stomsfem_last_error()
+    lib.stomsfem_autotune.restype = ctypes.c_int
+    assert lib.stomsfem_autotune(None, ctypes.c_int32(1), None, None) == -1
+    lib.stomsfem_plan_create.restype = ctypes.c_int
+    assert lib.stomsfem_plan_create(None, ctypes.c_int32(0), None) == -1
