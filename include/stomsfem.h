@@ -410,6 +410,42 @@ int stomsfem_autotune(const stomsfem_batch* batch, int32_t reps, stomsfem_tuning
 /* Forget the choices made on the current device. */
 int stomsfem_tuning_reset(void);
 
+/* ------------------------------------------------------------------------
+ * Model files, counters, training alias.
+ *
+ * stomsfem_model_save: writes any model (reduced basis, random
+ *   interpolation, learned surrogate) to `path`: a header (magic "STOMSFEM",
+ *   ABI version, kind, mesh, scalars, coefficient family) followed by the
+ *   model's device arrays, each preceded by (index, element size, count).
+ *   The surrogate's training data are not written (stomsfem_mlp_set_data
+ *   again before further training).  Synchronous.
+ * stomsfem_model_load: reads such a file onto the current device; the loaded
+ *   model's online results are bitwise those of the saved one.
+ *   STOMSFEM_EVERSION for a file of another ABI version or no model file,
+ *   EINVAL for a corrupt one.  Synchronous.
+ * stomsfem_stats_get / _reset: process-wide counters of pairs through the
+ *   refined FP32 path and their FP64 recomputations, random-interpolation
+ *   pairs and their out-of-box plain solves, surrogate pairs and their plain
+ *   recomputations (for m != 8; at m = 8 the counts stay on the device, see
+ *   the `stats` argument of stomsfem_upscale_surrogate).
+ * stomsfem_surrogate_train: the same as stomsfem_mlp_train.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t refine_pairs, refine_recomputed;
+  uint64_t interp_pairs, interp_fallbacks;
+  uint64_t surrogate_pairs, surrogate_recomputed;
+} stomsfem_stats;
+
+int stomsfem_model_save(const stomsfem_model* model, const char* path);
+int stomsfem_model_load(const char* path, stomsfem_model** model);
+/* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation;
+ * any output pointer may be NULL. */
+int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
+int stomsfem_stats_get(stomsfem_stats* out);
+int stomsfem_stats_reset(void);
+int stomsfem_surrogate_train(stomsfem_model* model, int32_t steps, float lr, const int64_t* perm, float* loss,
+                             void* stream);
+
 /* Grow the library-owned device workspace of the current device to at least
  * `bytes` (the coarse solve needs 8*(ncx-1)*(ncy-1)*(ncx+1) bytes per sample
  * in flight).  Calls made after a large enough reservation allocate nothing.

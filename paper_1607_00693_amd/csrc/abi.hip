@@ -5,6 +5,9 @@
 #include <unordered_map>
 #include <vector>
 #include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
 #include <cmath>
 #include <functional>
 #include <map>
@@ -134,6 +137,10 @@ UpArgs to_args(const stomsfem_batch& b) {
 
 namespace stomsfem {
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// process-wide counters reported by stomsfem_stats_get
+std::atomic<uint64_t> g_refine_pairs{0}, g_refine_recomputed{0}, g_interp_pairs{0}, g_interp_fallbacks{0},
+    g_surrogate_pairs{0}, g_surrogate_recomputed{0};
 
 // Launch configuration of the plain upscaling kernels per (device, m,
 // coefficient dtype), chosen by stomsfem_autotune (defaults otherwise).
@@ -325,6 +332,8 @@ static int upscale_refined(const stomsfem_batch& b, hipStream_t st) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "upscale (FP32 + FP64 refinement)");
   if (n > (unsigned long long)up.npairs) return fail(STOMSFEM_EHIP, "upscale: refinement fallback count out of range");
+  g_refine_pairs += (uint64_t)up.npairs;
+  g_refine_recomputed += n;
   for (int64_t start = 0; start < (int64_t)n && e == hipSuccess; start += chunk) {
     const int64_t cnt = std::min<int64_t>(chunk, (int64_t)n - start);
     e = launch_gather_blocks(up, b.a_dtype, list + start, cnt, blk, st);
@@ -799,6 +808,8 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "surrogate fallback count");
   if (n > (unsigned long long)(nsamples * Mc)) return fail(STOMSFEM_EHIP, "surrogate: fallback count out of range");
+  g_surrogate_pairs += (uint64_t)(nsamples * Mc);
+  g_surrogate_recomputed += n;
   for (int64_t start = 0; start < (int64_t)n && e == hipSuccess; start += model->chunk) {
     const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
     RegenArgs r{};
@@ -1060,6 +1071,8 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
   if (e != hipSuccess) return hip_fail(e, "interp_apply");
   if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "interp_apply: fallback count out of range");
   if (nfallback) *nfallback = (int64_t)n;
+  g_interp_pairs += (uint64_t)need;
+  g_interp_fallbacks += n;
   return ri_plain_pairs(model, model->list, (int64_t)n, xi, nxi, S, status, 1, st);
 }
 
@@ -1200,6 +1213,222 @@ int stomsfem_tuning_reset(void) {
     if (std::get<0>(it->first) == dev) it = g_tune.erase(it);
     else ++it;
   }
+  return STOMSFEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// counters, training alias, model files
+// ---------------------------------------------------------------------------
+int stomsfem_stats_get(stomsfem_stats* out) {
+  if (!out) return fail(STOMSFEM_EINVAL, "stats_get: NULL");
+  out->refine_pairs = g_refine_pairs.load();
+  out->refine_recomputed = g_refine_recomputed.load();
+  out->interp_pairs = g_interp_pairs.load();
+  out->interp_fallbacks = g_interp_fallbacks.load();
+  out->surrogate_pairs = g_surrogate_pairs.load();
+  out->surrogate_recomputed = g_surrogate_recomputed.load();
+  return STOMSFEM_OK;
+}
+
+int stomsfem_stats_reset(void) {
+  g_refine_pairs = 0;
+  g_refine_recomputed = 0;
+  g_interp_pairs = 0;
+  g_interp_fallbacks = 0;
+  g_surrogate_pairs = 0;
+  g_surrogate_recomputed = 0;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m) {
+  if (!model) return fail(STOMSFEM_EINVAL, "model_shape: NULL model");
+  if (kind) *kind = model->kind;
+  if (ncx) *ncx = model->ncx;
+  if (ncy) *ncy = model->ncy;
+  if (m) *m = model->m;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_surrogate_train(stomsfem_model* model, int32_t steps, float lr, const int64_t* perm, float* loss,
+                             void* stream) {
+  return stomsfem_mlp_train(model, steps, lr, perm, loss, stream);
+}
+
+namespace {
+struct ModelFileHeader {
+  char magic[8];
+  uint32_t abi, kind;
+  int32_t ncx, ncy, m, nn;
+  int32_t rmax, KD, PP, lv_max;
+  int64_t rows, adam_t;
+  double box, lo, hi;
+  stomsfem_bump_family fam;
+};
+struct ArrayRecord {
+  uint32_t id, elem;
+  uint64_t count;
+};
+const char kModelMagic[8] = {'S', 'T', 'O', 'M', 'S', 'F', 'E', 'M'};
+
+struct ArraySpec {
+  void** dev;
+  size_t elem;
+  size_t count;
+};
+
+std::vector<ArraySpec> model_arrays(stomsfem_model* md) {
+  const size_t M = (size_t)md->ncx * md->ncy, nI = (size_t)(md->m - 1) * (md->m - 1);
+  switch (md->kind) {
+    case 1:
+      return {{(void**)&md->rK, 4, M},
+              {(void**)&md->lambda, 8, M * nI},
+              {(void**)&md->Z, 8, M * nI * md->rmax},
+              {(void**)&md->phibar, 8, M * 3 * nI},
+              {(void**)&md->G32, 4, M * md->KD * md->PP},
+              {(void**)&md->G64, 8, M * md->KD * md->PP}};
+    case 2:
+      return {{(void**)&md->lv, 4, M * MLP_KIN},   {(void**)&md->params, 4, M * MLP_NP},
+              {(void**)&md->m1, 4, M * MLP_NP},    {(void**)&md->m2, 4, M * MLP_NP},
+              {(void**)&md->mu, 8, M * 10},        {(void**)&md->sd, 8, M * 10},
+              {(void**)&md->sd_raw, 8, M * 10}};
+    case 3:
+      return {{(void**)&md->lv, 4, M * RI_KMAX},
+              {(void**)&md->nlv, 4, M},
+              {(void**)&md->off, 8, M + 1},
+              {(void**)&md->table, 8, (size_t)md->rows * 10}};
+    default:
+      return {};
+  }
+}
+}  // namespace
+
+int stomsfem_model_save(const stomsfem_model* model, const char* path) {
+  if (!model || !path) return fail(STOMSFEM_EINVAL, "model_save: NULL argument");
+  if (model->kind < 1 || model->kind > 3) return fail(STOMSFEM_EINVAL, "model_save: unknown model kind");
+  ModelFileHeader h{};
+  std::memcpy(h.magic, kModelMagic, 8);
+  h.abi = STOMSFEM_ABI_VERSION;
+  h.kind = (uint32_t)model->kind;
+  h.ncx = model->ncx;
+  h.ncy = model->ncy;
+  h.m = model->m;
+  h.nn = model->nn;
+  h.rmax = model->rmax;
+  h.KD = model->KD;
+  h.PP = model->PP;
+  h.lv_max = model->lv_max;
+  h.rows = model->rows;
+  h.adam_t = model->adam_t;
+  h.box = model->box;
+  h.lo = model->lo;
+  h.hi = model->hi;
+  h.fam = model->fam;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "model_save");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(STOMSFEM_EINVAL, std::string("model_save: cannot open ") + path);
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+  uint32_t id = 0;
+  for (const ArraySpec& a : model_arrays(const_cast<stomsfem_model*>(model))) {
+    std::vector<unsigned char> buf(a.elem * a.count);
+    if (ok && !buf.empty()) ok = hipMemcpy(buf.data(), *a.dev, buf.size(), hipMemcpyDeviceToHost) == hipSuccess;
+    const ArrayRecord r{id++, (uint32_t)a.elem, (uint64_t)a.count};
+    ok = ok && std::fwrite(&r, sizeof(r), 1, f) == 1;
+    if (ok && !buf.empty()) ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? STOMSFEM_OK : fail(STOMSFEM_EHIP, std::string("model_save: write to ") + path + " failed");
+}
+
+int stomsfem_model_load(const char* path, stomsfem_model** model) {
+  if (!path || !model) return fail(STOMSFEM_EINVAL, "model_load: NULL argument");
+  *model = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(STOMSFEM_EINVAL, std::string("model_load: cannot open ") + path);
+  ModelFileHeader h{};
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kModelMagic, 8) != 0) {
+    std::fclose(f);
+    return fail(STOMSFEM_EVERSION, "model_load: not a model file");
+  }
+  if (h.abi != STOMSFEM_ABI_VERSION) {
+    std::fclose(f);
+    return fail(STOMSFEM_EVERSION, "model_load: written by ABI version " + std::to_string(h.abi));
+  }
+  const bool sane = h.kind >= 1 && h.kind <= 3 && h.ncx >= 1 && h.ncy >= 1 && h.ncx <= 4096 && h.ncy <= 4096 &&
+                    h.m >= 1 && h.m <= 48 && h.rows >= 0 && h.rmax >= 0 && h.rmax <= 8 && h.KD >= 0 && h.PP >= 0 &&
+                    h.KD <= 4096 && h.PP <= 4096 && (h.kind != 3 || (h.nn >= RI_NN_MIN && h.nn <= RI_NN_MAX));
+  if (!sane) {
+    std::fclose(f);
+    return fail(STOMSFEM_EINVAL, "model_load: corrupt header");
+  }
+  auto* md = new stomsfem_model();
+  hipGetDevice(&md->device);
+  md->kind = (int)h.kind;
+  md->ncx = h.ncx;
+  md->ncy = h.ncy;
+  md->m = h.m;
+  md->nn = h.nn;
+  md->rmax = h.rmax;
+  md->KD = h.KD;
+  md->PP = h.PP;
+  md->lv_max = h.lv_max;
+  md->rows = h.rows;
+  md->adam_t = h.adam_t;
+  md->box = h.box;
+  md->lo = h.lo;
+  md->hi = h.hi;
+  md->fam = h.fam;
+  int rc = STOMSFEM_OK;
+  uint32_t id = 0;
+  for (const ArraySpec& a : model_arrays(md)) {
+    ArrayRecord r{};
+    if (std::fread(&r, sizeof(r), 1, f) != 1 || r.id != id++ || r.elem != a.elem || r.count != a.count) {
+      rc = fail(STOMSFEM_EINVAL, "model_load: array table does not match the header");
+      break;
+    }
+    std::vector<unsigned char> buf(a.elem * a.count);
+    if (!buf.empty() && std::fread(buf.data(), 1, buf.size(), f) != buf.size()) {
+      rc = fail(STOMSFEM_EINVAL, "model_load: truncated file");
+      break;
+    }
+    if (hipMalloc(a.dev, std::max<size_t>(buf.size(), 8)) != hipSuccess) {
+      (void)hipGetLastError();
+      *a.dev = nullptr;
+      rc = fail(STOMSFEM_ENOMEM, "model_load: device allocation failed");
+      break;
+    }
+    if (!buf.empty() && hipMemcpy(*a.dev, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(STOMSFEM_EHIP, "model_load: copy failed");
+      break;
+    }
+  }
+  std::fclose(f);
+  // work buffers of the online stages, as the constructors make them
+  if (rc == STOMSFEM_OK && (md->kind == 2 || md->kind == 3)) {
+    hipError_t e = hipMalloc((void**)&md->counter, sizeof(unsigned long long));
+    const int m = md->m;
+    const bool chunked = md->kind == 3 || m != 8;
+    if (chunked) {
+      md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+      if (e == hipSuccess) e = hipMalloc((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+      if (e == hipSuccess) e = hipMalloc((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+      if (e == hipSuccess) e = hipMalloc((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+    }
+    if (md->kind == 3) {
+      const int nxi = std::max(1, md->fam.g * md->fam.g);
+      if (e == hipSuccess) e = hipMalloc((void**)&md->xin, sizeof(double) * (size_t)md->chunk * nxi);
+      if (e == hipSuccess) e = hipMalloc((void**)&md->pairs, sizeof(int64_t) * (size_t)md->chunk);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      rc = fail(STOMSFEM_ENOMEM, "model_load: device allocation failed");
+    }
+  }
+  if (rc != STOMSFEM_OK) {
+    model_release(md);
+    return rc;
+  }
+  *model = md;
   return STOMSFEM_OK;
 }
 

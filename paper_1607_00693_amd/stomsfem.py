@@ -107,6 +107,12 @@ def lib():
         "stomsfem_plan_free": (C.c_int, [vp]),
         "stomsfem_autotune": (C.c_int, [C.POINTER(Batch), i32, C.POINTER(Tuning), vp]),
         "stomsfem_tuning_reset": (C.c_int, []),
+        "stomsfem_model_save": (C.c_int, [vp, C.c_char_p]),
+        "stomsfem_model_load": (C.c_int, [C.c_char_p, C.POINTER(vp)]),
+        "stomsfem_model_shape": (C.c_int, [vp, vp, vp, vp, vp]),
+        "stomsfem_stats_get": (C.c_int, [vp]),
+        "stomsfem_stats_reset": (C.c_int, []),
+        "stomsfem_surrogate_train": (C.c_int, [vp, i32, C.c_float, vp, vp, vp]),
         "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
                                             C.POINTER(vp), vp]),
         "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
@@ -239,6 +245,9 @@ class Model:
             self.free()
         except Exception:
             pass
+
+    def save(self, path: str):
+        _check("stomsfem_model_save", lib().stomsfem_model_save(self.handle, os.fsencode(path)))
 
     def export(self, which: str):
         import numpy as np
@@ -478,3 +487,28 @@ def autotune(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None
 
 def tuning_reset():
     _check("stomsfem_tuning_reset", lib().stomsfem_tuning_reset())
+
+
+def model_load(path: str) -> Model:
+    """Load a model file written by Model.save onto the current device."""
+    h = C.c_void_p()
+    _check("stomsfem_model_load", lib().stomsfem_model_load(os.fsencode(path), C.byref(h)))
+    kind, ncx, ncy, m = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check("stomsfem_model_shape", lib().stomsfem_model_shape(h, C.byref(kind), C.byref(ncx), C.byref(ncy),
+                                                             C.byref(m)))
+    return Model(h, ncx.value, ncy.value, m.value)
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("refine_pairs", "refine_recomputed", "interp_pairs", "interp_fallbacks",
+                                          "surrogate_pairs", "surrogate_recomputed")]
+
+
+def stats_get() -> dict:
+    st = Stats()
+    _check("stomsfem_stats_get", lib().stomsfem_stats_get(C.byref(st)))
+    return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+
+def stats_reset():
+    _check("stomsfem_stats_reset", lib().stomsfem_stats_reset())

@@ -62,3 +62,27 @@ def test_host_validation_without_gpu():
     assert lib.stomsfem_autotune(None, ctypes.c_int32(1), None, None) == -1
     lib.stomsfem_plan_create.restype = ctypes.c_int
     assert lib.stomsfem_plan_create(None, ctypes.c_int32(0), None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_model_file_rejections_and_counters_on_host(tmp_path):
+    # rejected before any device work: missing file, foreign file, wrong ABI version
+    import struct
+
+    from paper_1607_00693_amd import stomsfem
+
+    with pytest.raises(stomsfem.StomsfemError) as e:
+        stomsfem.model_load(str(tmp_path / "nothing.bin"))
+    assert e.value.code == stomsfem.EINVAL
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a model file at all" * 10)
+    with pytest.raises(stomsfem.StomsfemError) as e:
+        stomsfem.model_load(str(junk))
+    assert e.value.code == stomsfem.EVERSION
+    old = tmp_path / "old.bin"
+    old.write_bytes(b"STOMSFEM" + struct.pack("<II", 999, 3) + bytes(200))
+    with pytest.raises(stomsfem.StomsfemError) as e:
+        stomsfem.model_load(str(old))
+    assert e.value.code == stomsfem.EVERSION
+    stomsfem.stats_reset()
+    assert all(v == 0 for v in stomsfem.stats_get().values())
