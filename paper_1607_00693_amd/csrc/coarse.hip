@@ -5,10 +5,27 @@
 // One workgroup per sample.  The interior coarse nodes in natural order give
 // a 9-point band of half-width ncx; the global stiffness rows are assembled
 // on the fly from the four upscaled element matrices around each node as
-// they enter an LDS window of (ncx+1) x (ncx+1) entries.  FP64 LDL^T with the
-// forward substitution fused; the retired columns of L go to a per-workgroup
-// slice of the library workspace and are read back once by the backward
-// substitution, which is done by one wavefront with a shuffle reduction.
+// they enter an LDS window of (ncx+1) x (ncx+1) entries.
+//
+// Forward pass: FP64 LDL^T with the forward substitution fused, one
+// workgroup barrier per pivot column.  In the phase of pivot j every thread
+// applies the rank-1 update of pivot j to its fixed entries of the trailing
+// triangle; the threads whose entries make up column j+1 also write it (and
+// 1/d_{j+1}) to the other half of a double-buffered LDS column, so pivot j+1
+// can start right after the barrier.  The same phase does the forward
+// substitution step of pivot j, writes column j of L to a per-workgroup
+// slice of the library workspace and assembles the row entering the window
+// (its coefficients and load prefetched into registers a phase or a node row
+// ahead, so no global load sits between two barriers).
+//
+// Backward pass L^T x = z, z = D^{-1} y (column-oriented, a second kernel
+// with one wavefront per sample, so that the forward kernel keeps its small
+// register footprint and the backward passes of many samples overlap):
+// lane l keeps z_i for the indices i = l (mod 64) of three consecutive blocks
+// of 64 unknowns in registers.  Step j reads x_j = z_j from lane j mod 64 (a
+// cross-lane read, no memory round trip) and subtracts l_{j,i} x_j from the
+// z_i, i in [j-B, j), of every lane; the L entries are loaded a few steps
+// ahead, and the z values of the block after next one block ahead.
 #include "common.h"
 
 namespace stomsfem {
@@ -16,6 +33,8 @@ namespace stomsfem {
 constexpr int COARSE_THREADS = 256;
 constexpr int COARSE_NQ = 12;  // largest NQ: B (B+1)/2 <= 3072
 constexpr int COARSE_BMAX = 72;
+constexpr int COARSE_NE = (COARSE_BMAX * 10 + COARSE_THREADS - 1) / COARSE_THREADS;  // element-row prefetch
+constexpr int COARSE_PD = 8;  // backward substitution: L entries loaded this many steps ahead
 
 // Workgroup barrier that orders LDS only: a pivot step does not wait for
 // its global stores (retired L columns, y_j) to complete.
@@ -29,6 +48,14 @@ constexpr int COARSE_BMAX = 72;
 // x mod w for 0 <= x < 2w
 __device__ __forceinline__ int wrap(int x, int w) { return x >= w ? x - w : x; }
 
+// value of v in lane `lane` (wave-uniform lane index)
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 struct CoarseArgs {
   int32_t ncx, ncy;
   int64_t nsamples;
@@ -36,7 +63,7 @@ struct CoarseArgs {
   const double* load;
   double* U;
   int32_t* status;
-  double* work;  // gridDim.x * nU * (ncx+1) doubles
+  double* work;  // nsamples * (nU * (ncx+1) + 1) doubles (one launch's samples)
 };
 
 __device__ __forceinline__ double selem(const double* Sk, int i, int j) {
@@ -50,22 +77,58 @@ __device__ __forceinline__ double selem(const double* Sk, int i, int j) {
   return Sk[base + (j - i)];
 }
 
-// NQ = trailing-triangle entries per lane, >= B (B+1) / (2 * 64).
+// L entries of backward step j for lane `lam`, zero where the lane's index is
+// not in [j-B, j).  Lc column i: [1/d_i, l_{i+1,i}, ..., l_{i+B,i}], so
+// l_{j,i} = Lc[i WN + j - i]; for the lane's index i = 64 k' + lam of block
+// k' that is Lc[(64 k' + lam)(WN - 1) + j].  Lanes outside the band read the
+// zero kept at Lc[zero], so that the loaded value is used as is and the load
+// is waited for only where it is consumed, COARSE_PD steps later.
+struct BackStep {
+  double lc, l1, l2;
+};
+
+// FAR: B may exceed 64, so indices two blocks down can be in [j-B, j)
+template <bool FAR>
+__device__ __forceinline__ BackStep back_loads(const double* Lc, int64_t zero, int WN, int B, int nU, int j,
+                                               int lam) {
+  // every step issues the same loads (out-of-range steps read the zero), so
+  // that the number of loads in flight behind any one of them is fixed
+  BackStep r{0.0, 0.0, 0.0};
+  const bool in = j >= 0 && j < nU;
+  const int k = j >> 6, u = j & 63;
+  const int dc = u - lam;  // offset j - i in block k; + 64 in block k-1, + 128 in block k-2
+  const bool oc = in && dc >= 1 && dc <= B, o1 = in && k >= 1 && dc + 64 <= B;
+  const int64_t base = (int64_t)(64 * k + lam) * (WN - 1) + j;  // block k
+  const int64_t step = (int64_t)64 * (WN - 1);
+  r.lc = Lc[oc ? base : zero];
+  r.l1 = Lc[o1 ? base - step : zero];
+  if (FAR) {
+    const bool o2 = in && k >= 2 && dc + 128 <= B;
+    r.l2 = Lc[o2 ? base - 2 * step : zero];
+  }
+  return r;
+}
+
+// NQ = trailing-triangle entries per lane, >= B (B+1) / (2 * 64); NQ = 4
+// serves B <= 44.
 template <int NQ>
 __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs args) {
   extern __shared__ double smem[];
   const int ncx = args.ncx, ncy = args.ncy;
-  const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, B = ncx, WN = B + 1;
-  double* Wn = smem;        // WN*WN
-  double* F = Wn + WN * WN;  // WN (forward-substituted rhs window)
-  double* X = F + WN;        // WN (backward substitution window)
-  double* Ec = X + WN;       // 4 x ncx x 10: ring of element rows of S (row e in slot e % 4)
+  const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, B = ncx, WN = B + 1, FN = B + 2;
+  double* Wn = smem;         // WN*WN: row r in slot r % WN, column c in slot c % WN
+  double* F = Wn + WN * WN;  // FN: forward-substituted rhs, row r in slot r % FN
+  double* Ec = F + FN;       // 4 x ncx x 10: ring of element rows of S (row e in slot e % 4)
   __shared__ int bad;
-  __shared__ double colv[COARSE_BMAX];  // pivot column (unscaled), a separate object from the window
+  __shared__ double colv[2][COARSE_BMAX];  // colv[j & 1][t - 1] = W(j + t, j), t = 1..B
+  __shared__ double pinv[2];               // pinv[j & 1] = 1 / d_j
   const int tid = threadIdx.x;
   const int Mc = ncx * ncy;
   const double H = 1.0 / ncx;
-  double* Lc = args.work + (int64_t)blockIdx.x * nU * WN;  // column j: [d_j, l_{j+1,j}, ..., l_{j+B,j}]
+  // column j: [1/d_j, l_{j+1,j}, ..., l_{j+B,j}], then one zero
+  double* Lc = args.work + (int64_t)blockIdx.x * ((int64_t)nU * WN + 1);
+  const int64_t zero = (int64_t)nU * WN;
+  if (tid == 0) Lc[zero] = 0.0;
   // entries (io >= ko) of the B x B trailing triangle handled by this lane,
   // the same for every pivot column, packed io | ko << 8 (io = B: unused)
   int tik[NQ];
@@ -78,88 +141,109 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     tik[q] = used ? (io | ((t - io * (io + 1) / 2) << 8)) : B;
   }
 
-  for (int64_t s = blockIdx.x; s < args.nsamples; s += gridDim.x) {
+  // one sample per workgroup: its slice of the workspace must survive until
+  // the backward kernel has read it
+  {
+    const int64_t s = blockIdx.x;
+    if (s >= args.nsamples) return;
     const double* Ss = args.S + s * (int64_t)Mc * 10;
     double* Us = args.U + s * (int64_t)nU;
-    __syncthreads();
     for (int i = tid; i < WN * WN; i += blockDim.x) Wn[i] = 0.0;
     if (tid == 0) bad = 0;
     // Element rows of S go through an LDS ring.  Node row iy uses element rows
-    // iy and iy + 1.  Rows 0..3 are loaded here; in the elimination loop
-    // (where a barrier follows every inserted row) the first node of node
-    // row iy >= 2 loads element row iy + 2 into the slot of row iy - 2, which
-    // only node rows up to iy - 2 used; node row iy + 1 needs it nix columns
-    // later.
-    auto load_erow = [&](int e) {
+    // iy and iy + 1.  Rows 0..3 are loaded here; the first node of node row
+    // iy >= 2 stores element row iy + 2 (prefetched into registers at node
+    // row iy - 1) into the slot of row iy - 2, which only node rows up to
+    // iy - 2 used, and prefetches element row iy + 3.
+    double epre[COARSE_NE];
+    auto erow_fetch = [&](int e) {
+#pragma unroll
+      for (int k = 0; k < COARSE_NE; ++k) {
+        const int t = tid + COARSE_THREADS * k;
+        epre[k] = (e < ncy && t < ncx * 10) ? Ss[(int64_t)e * ncx * 10 + t] : 0.0;
+      }
+    };
+    auto erow_store = [&](int e) {
+#pragma unroll
+      for (int k = 0; k < COARSE_NE; ++k) {
+        const int t = tid + COARSE_THREADS * k;
+        if (e < ncy && t < ncx * 10) Ec[(e % 4) * ncx * 10 + t] = epre[k];
+      }
+    };
+    for (int e = 0; e < 4; ++e)
       if (e < ncy)
         for (int t = tid; t < ncx * 10; t += blockDim.x) Ec[(e % 4) * ncx * 10 + t] = Ss[(int64_t)e * ncx * 10 + t];
+    erow_fetch(4);
+
+    // load of row r (the last thread keeps the next row's value)
+    auto node_load = [&](int r) -> double {
+      if (r >= nU) return 0.0;
+      const int px = r % nix + 1, py = r / nix + 1;
+      if (!args.load) return H * H;  // four elements, int_K p^l = H^2/4 each
+      const double* L = args.load;
+      return (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
+             (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
     };
-    for (int e = 0; e < 4; ++e) load_erow(e);
+    double bnext = tid == COARSE_THREADS - 1 ? node_load(0) : 0.0;
     __syncthreads();
 
     // Row r of the coarse system: node (ix, iy) = grid node (px, py); its four
     // elements SW=(px-1,py-1), SE=(px,py-1), NW=(px-1,py), NE=(px,py) see it as
-    // local node 2, 3, 1, 0 respectively.
-    auto insert_row = [&](int r) {
+    // local node 2, 3, 1, 0 respectively.  The entry at offset B (the SW
+    // coupling, column r - B) also goes to colB, the next pivot's column.
+    auto insert_row = [&](int r, double* colB) {
       const int ix = r % nix, iy = r / nix, px = ix + 1, py = iy + 1;
-      if (ix == 0 && iy >= 2 && r >= B) load_erow(iy + 2);
+      if (ix == 0 && iy >= 2) {
+        erow_store(iy + 2);
+        erow_fetch(iy + 3);
+      }
       const double* eS = Ec + ((py - 1) % 4) * ncx * 10;
       const double* eN = Ec + (py % 4) * ncx * 10;
       const double* sSW = eS + (px - 1) * 10;
       const double* sSE = eS + px * 10;
       const double* sNW = eN + (px - 1) * 10;
       const double* sNE = eN + px * 10;
-      for (int t = tid; t <= B + 1; t += COARSE_THREADS) {
-        if (t > B) {
-          double b;
-          if (args.load) {
-            const double* L = args.load;
-            b = (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
-                (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
-          } else {
-            b = H * H;  // four elements, int_K p^l = H^2/4 each
-          }
-          F[r % WN] = b;
-          continue;
-        }
+      for (int t = tid; t <= B; t += COARSE_THREADS) {
         double v = 0.0;
         if (t == 0) v += (selem(sSW, 2, 2) + selem(sSE, 3, 3)) + (selem(sNW, 1, 1) + selem(sNE, 0, 0));
         if (t == 1 && ix >= 1) v += selem(sSW, 2, 3) + selem(sNW, 1, 0);
         if (t == nix - 1 && iy >= 1 && ix <= nix - 2) v += selem(sSE, 3, 1);
         if (t == nix && iy >= 1) v += selem(sSW, 2, 1) + selem(sSE, 3, 0);
         if (t == nix + 1 && iy >= 1 && ix >= 1) v += selem(sSW, 2, 0);
-        if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;  // once per row
+        if (r - t >= 0) {
+          Wn[(r % WN) * WN + ((r - t) % WN)] = v;  // every entry of the row, once
+          if (t == B && colB) colB[B - 1] = v;
+        }
+      }
+      if (tid == COARSE_THREADS - 1) {
+        F[r % FN] = bnext;
+        bnext = node_load(r + 1);
       }
     };
 
-    for (int r = 0; r < (B < nU ? B : nU); ++r) insert_row(r);
+    const int r0 = B < nU - 1 ? B : nU - 1;
+    for (int r = 0; r <= r0; ++r) {
+      insert_row(r, nullptr);
+      __syncthreads();
+    }
+    // pivot 0's column and 1/d_0
+    for (int t = 1 + tid; t <= r0; t += COARSE_THREADS) colv[0][t - 1] = Wn[t * WN];
+    if (tid == 0) {
+      const double d = Wn[0];
+      pinv[0] = 1.0 / d;
+      if (!(d > 0.0)) bad = 1;
+    }
     __syncthreads();
+
     for (int j = 0; j < nU; ++j) {
-      if (j + B < nU) {
-        insert_row(j + B);
-        COARSE_SYNC();
-      }
+      const int b = j & 1;
+      const double inv = pinv[b];
       const int jj = j % WN;
-      const double d = Wn[jj * WN + jj];
-      const double inv = 1.0 / d;
       const int cnt = (j + B < nU - 1 ? j + B : nU - 1) - j;
-      // column j of L (and the pivot) to the workspace; rhs forward step
-      for (int t = tid; t <= cnt; t += COARSE_THREADS) {
-        const int rt = wrap(jj + t, WN);
-        const double c = Wn[rt * WN + jj];
-        const double v = t == 0 ? d : c * inv;
-        if (t > 0) colv[t - 1] = c;
-        Lc[(int64_t)j * WN + t] = v;
-        if (t > 0) F[rt] -= v * F[jj];
-      }
-      COARSE_SYNC();
-      if (tid == 0) {
-        if (!(d > 0.0)) bad = 1;
-        Us[j] = F[jj];  // y_j, overwritten by x_j below
-      }
       // rank-1 update of the trailing triangle, this lane's fixed entries:
       // all reads first, then all writes (distinct addresses), so that the
-      // reads are not serialised behind possibly aliasing writes
+      // reads are not serialised behind possibly aliasing writes.  Entries
+      // in the first column of the triangle are column j+1.
       {
         double wv[NQ];
         int idx[NQ];
@@ -172,37 +256,99 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int io = tik[q] & 255, ko = tik[q] >> 8;
-          if (io < cnt) wv[q] -= colv[io] * inv * colv[ko];
+          if (io < cnt) wv[q] -= colv[b][io] * inv * colv[b][ko];
         }
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          if ((tik[q] & 255) < cnt) Wn[idx[q]] = wv[q];
+        for (int q = 0; q < NQ; ++q) {
+          const int io = tik[q] & 255, ko = tik[q] >> 8;
+          if (io < cnt) {
+            Wn[idx[q]] = wv[q];
+            if (ko == 0) {
+              if (io > 0) {
+                colv[b ^ 1][io - 1] = wv[q];
+              } else {
+                pinv[b ^ 1] = 1.0 / wv[q];
+                if (!(wv[q] > 0.0)) bad = 1;
+              }
+            }
+          }
+        }
       }
+      // forward substitution step and column j of L (F[j] is final: every
+      // pivot above it has been applied in an earlier phase)
+      for (int t = 1 + tid; t <= cnt; t += COARSE_THREADS) {
+        const double l = colv[b][t - 1] * inv;
+        Lc[(int64_t)j * WN + t] = l;
+        F[(j + t) % FN] -= l * F[j % FN];
+      }
+      if (tid == 0) {
+        Lc[(int64_t)j * WN] = inv;
+        Us[j] = F[j % FN] * inv;  // z_j = y_j / d_j, overwritten by x_j below
+      }
+      // the row entering the window takes the slot of row j (its last reader
+      // was the phase before); its F slot is that of row j - 1
+      if (j + 1 + B < nU) insert_row(j + 1 + B, colv[b ^ 1]);
       COARSE_SYNC();
     }
-    // the retired columns and y must be visible to the backward substitution
-    __syncthreads();
-    // backward substitution x_j = y_j / d_j - sum_{t=1..B} l_{j+t,j} x_{j+t}
-    if (tid < 64) {
-      for (int t = tid; t < WN; t += 64) X[t] = 0.0;
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      for (int j = nU - 1; j >= 0; --j) {
-        const double* col = Lc + (int64_t)j * WN;
-        double part = 0.0;
-        for (int t = 1 + tid; t <= B; t += 64)
-          if (j + t < nU) part += col[t] * X[(j + t) % WN];
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-        const double x = Us[j] / col[0] - part;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (tid == 0) {
-          X[j % WN] = x;
-          Us[j] = x;
+    if (tid == 0 && args.status) args.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+  }
+}
+
+// Backward substitution L^T x = z for the samples of one forward launch: one
+// wavefront per sample (workgroup slice blockIdx.x of the workspace).
+template <bool FAR>
+__global__ __launch_bounds__(64) void coarse_back_kernel(CoarseArgs args) {
+  const int ncx = args.ncx, ncy = args.ncy;
+  const int nU = (ncx - 1) * (ncy - 1), B = ncx, WN = B + 1;
+  const int64_t s = blockIdx.x;
+  if (s >= args.nsamples) return;
+  const double* Lc = args.work + s * ((int64_t)nU * WN + 1);
+  const int64_t zero = (int64_t)nU * WN;
+  double* Us = args.U + s * (int64_t)nU;
+  const int lam = threadIdx.x;
+  const int kt = (nU - 1) >> 6;
+  auto yload = [&](int k) -> double {
+    const int i = 64 * k + lam;
+    return (k >= 0 && i < nU) ? Us[i] : 0.0;
+  };
+  // yc, y1, y2: blocks k, k-1, k-2 (y2 only if FAR); yp: the next block to
+  // enter, loaded one block ahead
+  double yc = yload(kt), y1 = yload(kt - 1), y2 = FAR ? yload(kt - 2) : 0.0;
+  double yp = yload(FAR ? kt - 3 : kt - 2);
+  BackStep pf[COARSE_PD];
+#pragma unroll
+  for (int d = 0; d < COARSE_PD; ++d) pf[d] = back_loads<FAR>(Lc, zero, WN, B, nU, 64 * kt + 63 - d, lam);
+  for (int k = kt; k >= 0; --k) {
+    double xs = 0.0;
+    // groups of COARSE_PD steps; step j issues the loads of step
+    // j - COARSE_PD, and the empty asm statements keep the compiler from
+    // moving them next to their use
+#pragma unroll 1
+    for (int u0 = 63; u0 >= 0; u0 -= COARSE_PD) {
+#pragma unroll
+      for (int d = 0; d < COARSE_PD; ++d) {
+        const int u = u0 - d, j = 64 * k + u;
+        if (j < nU) {
+          const double x = lane_value(yc, u);
+          xs = lam == u ? x : xs;
+          yc = __builtin_fma(-pf[d].lc, x, yc);
+          y1 = __builtin_fma(-pf[d].l1, x, y1);
+          if (FAR) y2 = __builtin_fma(-pf[d].l2, x, y2);
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // the slot is free again: load step j - COARSE_PD into it
+        pf[d] = back_loads<FAR>(Lc, zero, WN, B, nU, j - COARSE_PD, lam);
+        __asm__ volatile("" ::: "memory");
       }
-      if (tid == 0 && args.status) args.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+    }
+    if (64 * k + lam < nU) Us[64 * k + lam] = xs;
+    yc = y1;
+    if (FAR) {
+      y1 = y2;
+      y2 = yp;
+      yp = yload(k - 4);
+    } else {
+      y1 = yp;
+      yp = yload(k - 3);
     }
   }
 }
@@ -227,13 +373,13 @@ __global__ void qoi_kernel(int64_t N, int nU, const double* U, double* mean, dou
 
 size_t coarse_lds_bytes(int ncx) {
   const int WN = ncx + 1;
-  return sizeof(double) * ((size_t)WN * WN + 2 * (size_t)WN + 40 * (size_t)ncx);
+  return sizeof(double) * ((size_t)WN * WN + (size_t)WN + 1 + 40 * (size_t)ncx);
 }
 
 int64_t coarse_grid(int64_t nsamples) { return nsamples < 4096 ? nsamples : 4096; }
 
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
-  return coarse_grid(nsamples) * (int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1);
+  return coarse_grid(nsamples) * ((int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1) + 1);
 }
 
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
@@ -241,16 +387,26 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
   const int nU = (ncx - 1) * (ncy - 1);
   if (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ || ncx > COARSE_BMAX) return hipErrorInvalidValue;
   if (N > 0 && nU > 0) {
-    CoarseArgs a{ncx, ncy, N, S, load, U, status, work};
     const int need = (ncx * (ncx + 1) / 2 + COARSE_THREADS - 1) / COARSE_THREADS;
-    const dim3 grid((unsigned)coarse_grid(N)), block(COARSE_THREADS);
     const size_t lds = coarse_lds_bytes(ncx);
-    if (need <= 4)
-      hipLaunchKernelGGL(coarse_solve_kernel<4>, grid, block, lds, st, a);
-    else
-      hipLaunchKernelGGL(coarse_solve_kernel<COARSE_NQ>, grid, block, lds, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t chunk = coarse_grid(N);  // samples per launch pair: the workspace holds their L factors
+    for (int64_t c = 0; c < N; c += chunk) {
+      const int64_t n = N - c < chunk ? N - c : chunk;
+      CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * 10, load, U + c * (int64_t)nU,
+                   status ? status + c : nullptr, work};
+      if (need <= 4)
+        hipLaunchKernelGGL(coarse_solve_kernel<4>, dim3((unsigned)n), dim3(COARSE_THREADS), lds, st, a);
+      else
+        hipLaunchKernelGGL(coarse_solve_kernel<COARSE_NQ>, dim3((unsigned)n), dim3(COARSE_THREADS), lds, st, a);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      if (ncx > 64)
+        hipLaunchKernelGGL(coarse_back_kernel<true>, dim3((unsigned)n), dim3(64), 0, st, a);
+      else
+        hipLaunchKernelGGL(coarse_back_kernel<false>, dim3((unsigned)n), dim3(64), 0, st, a);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if ((mean || var) && nU > 0) {
     hipLaunchKernelGGL(qoi_kernel, dim3((nU + 255) / 256), dim3(256), 0, st, N, nU, U, mean, var);
