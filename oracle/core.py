@@ -57,6 +57,12 @@ def load():
         "orc_cell_system_dense": (i32, [i32, dp, sz, i32, dp, dp]),
         "orc_coef_bumps": (i32, [i64, i32, dp, i32, i32, dbl, dbl, dbl, dbl, dbl, dp, i32]),
         "orc_coef_features": (i32, [i64, i32, i32, ip, dp, dp, dp, dp, i32, dbl, dp, i32]),
+        "orc_os_origin": (i32, [i32, i32, i32, i32]),
+        "orc_cell_phi_os": (i32, [i32, i32, i32, i32, dp, sz, i32, i32, dp, dp]),
+        "orc_cell_S_os": (i32, [i32, i32, i32, i32, dp, sz, i32, i32, dp]),
+        "orc_upscale_os": (i32, [i64, i32, i32, i32, i32, dp, dp, ip, i32]),
+        "orc_band_lu_solve": (i32, [i32, i32, i32, dp, dp]),
+        "orc_coarse_pg_solve": (i32, [i32, i32, i64, dp, dp, dp, dp, dp, ip, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -233,3 +239,80 @@ def coef_features(xi: np.ndarray, nfine: int, kind, x0, y0, size, decades: float
     if st != 0:
         raise RuntimeError(f"orc_coef_features status {st}")
     return a
+
+
+# --- oversampling and the Petrov-Galerkin local stiffness --------------------
+
+
+def os_origin(k: int, m: int, o: int, nf: int) -> int:
+    """First fine cell (one axis) of the oversampled patch of coarse element k."""
+    return int(load().orc_os_origin(k, m, o, nf))
+
+
+def cell_phi_os(a: np.ndarray, m: int, o: int, kx: int, ky: int):
+    """Oversampled basis on K: (phi [4][m+1][m+1], Psi [4][4] = psi^j(x_k)).
+    a: one sample's whole field [nfy][nfx]."""
+    a = _c(a)
+    phi = np.zeros((4, m + 1, m + 1))
+    Psi = np.zeros((4, 4))
+    st = load().orc_cell_phi_os(m, o, a.shape[1], a.shape[0], _p(a), a.shape[1], kx, ky, _p(phi), _p(Psi))
+    if st != 0:
+        raise RuntimeError(f"orc_cell_phi_os status {st}")
+    return phi, Psi
+
+
+def cell_S_os(a: np.ndarray, m: int, o: int, kx: int, ky: int) -> np.ndarray:
+    """Petrov-Galerkin stiffness S[l][l'] (trial l, bilinear test l') of element (kx, ky)."""
+    a = _c(a)
+    S = np.zeros(16)
+    st = load().orc_cell_S_os(m, o, a.shape[1], a.shape[0], _p(a), a.shape[1], kx, ky, _p(S))
+    if st != 0:
+        raise RuntimeError(f"orc_cell_S_os status {st}")
+    return S.reshape(4, 4)
+
+
+def upscale_os(a: np.ndarray, ncx: int, ncy: int, m: int, o: int, nthreads: int = 0):
+    """a: [N][ncy*m][ncx*m] -> (S16 [N][M][16] row-major [l][l'], status [N][M])."""
+    a = _c(a)
+    N = a.shape[0]
+    assert a.shape[1:] == (ncy * m, ncx * m)
+    S = np.zeros((N, ncx * ncy, 16))
+    status = np.zeros((N, ncx * ncy), dtype=np.int32)
+    st = load().orc_upscale_os(N, ncx, ncy, m, o, _p(a), _p(S), status.ctypes.data_as(C.POINTER(C.c_int32)),
+                               nthreads)
+    if st != 0:
+        raise RuntimeError(f"orc_upscale_os status {st}")
+    return S, status
+
+
+def band_lu_solve(A: np.ndarray, b: np.ndarray, kl: int, ku: int) -> np.ndarray:
+    """Solve the dense-stored banded A x = b with the oracle's banded LU."""
+    A = _c(A)
+    n = A.shape[0]
+    w = 2 * kl + ku + 1
+    W = np.zeros((n, w))
+    for i in range(n):
+        for c in range(max(0, i - kl), min(n, i + ku + 1)):
+            W[i, c - i + kl] = A[i, c]
+    x = _c(b).copy()
+    st = load().orc_band_lu_solve(n, kl, ku, _p(W), _p(x))
+    if st != 0:
+        raise RuntimeError(f"orc_band_lu_solve status {st}")
+    return x
+
+
+def coarse_solve_pg(S16: np.ndarray, ncx: int, ncy: int, load_vec: np.ndarray | None = None, nthreads: int = 0):
+    """S16: [N][M][16] -> (U [N][(ncx-1)(ncy-1)], mean, var) of the Petrov-Galerkin coarse system."""
+    S16 = _c(S16)
+    N = S16.shape[0]
+    nU = (ncx - 1) * (ncy - 1)
+    U = np.zeros((N, nU))
+    mean = np.zeros(nU)
+    var = np.zeros(nU)
+    status = np.zeros(N, dtype=np.int32)
+    lv = None if load_vec is None else _c(load_vec)
+    st = load().orc_coarse_pg_solve(ncx, ncy, N, _p(S16), _p(lv), _p(U), _p(mean), _p(var),
+                                    status.ctypes.data_as(C.POINTER(C.c_int32)), nthreads)
+    if st != 0:
+        raise RuntimeError(f"orc_coarse_pg_solve status {st}")
+    return U, mean, var

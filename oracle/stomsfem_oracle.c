@@ -15,6 +15,10 @@
  *     Dirichlet problems are solved (no partition-of-unity shortcut) with a
  *     textbook banded Cholesky (Cholesky-Crout, left looking);
  *   - the upscaled stiffness by the element-sum form of eq. stiffness_local;
+ *   - oversampling (remark in Sec. 2.2): cell problems on an enlarged patch,
+ *     the basis re-normalised to nodal values on K, and the Petrov-Galerkin
+ *     stiffness of eq. stiffness_local_petrov with bilinear test functions;
+ *     its non-symmetric coarse system by banded LU with partial pivoting;
  *   - coarse assembly and solve of S U = b (eq. upscaleSUF), Petrov-Galerkin
  *     load (eq. stiffness_local_petrov) for f = 1;
  *   - the Monte Carlo mean and variance of the coarse solution (Sec. 4.1.1);
@@ -399,6 +403,250 @@ int orc_coarse_solve(int ncx, int ncy, int64_t N, const double* S, const double*
 #endif
   for (int64_t s = 0; s < N; ++s) {
     int st = orc_coarse_one(ncx, ncy, S + s * M * 10, load, U + s * nU);
+    if (status) status[s] = st;
+    if (st < worst) worst = st;
+  }
+  if (qoi_mean || qoi_var) {
+    for (int i = 0; i < nU; ++i) {
+      double m1 = 0.0, m2 = 0.0;
+      for (int64_t s = 0; s < N; ++s) {
+        double u = U[s * nU + i];
+        m1 += u;
+        m2 += u * u;
+      }
+      m1 = N > 0 ? m1 / (double)N : 0.0;
+      m2 = N > 0 ? m2 / (double)N : 0.0;
+      if (qoi_mean) qoi_mean[i] = m1;
+      if (qoi_var) qoi_var[i] = m2 - m1 * m1;
+    }
+  }
+  return worst;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2, remark   */
+/* on oversampling, and eq. stiffness_local_petrov).                          */
+/* ------------------------------------------------------------------------ */
+
+/* Origin (fine-cell index, one axis) of the oversampled patch of coarse
+ * element k: m + 2o cells centred on the element's m cells, moved inside
+ * [0, nf) where it would stick out of the domain. */
+int orc_os_origin(int k, int m, int o, int nf) {
+  int x0 = k * m - o;
+  if (x0 > nf - (m + 2 * o)) x0 = nf - (m + 2 * o);
+  if (x0 < 0) x0 = 0;
+  return x0;
+}
+
+/* X = A^{-1} (4x4, row-major) by Gauss-Jordan elimination with partial
+ * pivoting.  Returns ORC_EINVAL if a pivot vanishes. */
+static int inv4(const double A[16], double X[16]) {
+  double M[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) M[i][j] = j < 4 ? A[4 * i + j] : (j - 4 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 4; ++c) {
+    int p = c;
+    for (int i = c + 1; i < 4; ++i)
+      if (fabs(M[i][c]) > fabs(M[p][c])) p = i;
+    if (!(fabs(M[p][c]) > 0.0)) return ORC_EINVAL;
+    for (int j = 0; j < 8; ++j) {
+      double t = M[c][j];
+      M[c][j] = M[p][j];
+      M[p][j] = t;
+    }
+    double inv = 1.0 / M[c][c];
+    for (int j = 0; j < 8; ++j) M[c][j] *= inv;
+    for (int i = 0; i < 4; ++i) {
+      if (i == c) continue;
+      double f = M[i][c];
+      for (int j = 0; j < 8; ++j) M[i][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) X[4 * i + j] = M[i][4 + j];
+  return ORC_OK;
+}
+
+/* Oversampled MsFEM basis of coarse element (kx, ky) (m x m fine cells,
+ * oversampling by o fine cells on each side, so the patch has m + 2o cells
+ * per side; the oversampling ratio is (m + 2o)/m):
+ *   1. the four cell problems (eq. MsFEB) on the patch, with the bilinear
+ *      nodal functions of the patch corners as boundary data: psi^j;
+ *   2. Psi[k][j] = psi^j(x_k) at the corners x_k of K (CCW from lower left);
+ *   3. phi^i = sum_j C[i][j] psi^j restricted to K, with C chosen so that
+ *      phi^i(x_k) = delta_ik, i.e. C Psi^T = I.
+ * a: the sample's whole field [nfy][lda]; phiK: [4][(m+1)^2] on K's nodes.
+ * Psi (optional): [16]. */
+int orc_cell_phi_os(int m, int o, int nfx, int nfy, const double* a, ptrdiff_t lda, int kx, int ky, double* phiK,
+                    double* Psi_out) {
+  const int mp = m + 2 * o, nnp = mp + 1, nn = m + 1;
+  if (m < 1 || o < 0 || mp > nfx || mp > nfy) return ORC_EINVAL;
+  const int x0 = orc_os_origin(kx, m, o, nfx), y0 = orc_os_origin(ky, m, o, nfy);
+  double* psi = (double*)malloc(sizeof(double) * 4 * (size_t)nnp * nnp);
+  if (!psi) return ORC_ENOMEM;
+  int st = orc_cell_phi(mp, a + (ptrdiff_t)y0 * lda + x0, lda, ORC_BC_LINEAR, psi);
+  if (st != ORC_OK) {
+    free(psi);
+    return st;
+  }
+  const int cx = kx * m - x0, cy = ky * m - y0; /* K's lower-left node in patch nodes */
+  const int kpx[4] = {cx, cx + m, cx + m, cx}, kpy[4] = {cy, cy, cy + m, cy + m};
+  double Psi[16], PsiT[16], C[16];
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) Psi[4 * k + j] = psi[(size_t)j * nnp * nnp + kpy[k] * nnp + kpx[k]];
+  if (Psi_out) memcpy(Psi_out, Psi, sizeof Psi);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) PsiT[4 * i + j] = Psi[4 * j + i];
+  st = inv4(PsiT, C); /* C = (Psi^T)^{-1} */
+  if (st == ORC_OK)
+    for (int i = 0; i < 4; ++i)
+      for (int py = 0; py <= m; ++py)
+        for (int px = 0; px <= m; ++px) {
+          double v = 0.0;
+          for (int j = 0; j < 4; ++j) v += C[4 * i + j] * psi[(size_t)j * nnp * nnp + (cy + py) * nnp + (cx + px)];
+          phiK[(size_t)i * nn * nn + py * nn + px] = v;
+        }
+  free(psi);
+  return st;
+}
+
+/* Petrov-Galerkin upscaled stiffness of coarse element (kx, ky) with
+ * oversampling: S16[l][l'] = int_K a grad phi^l . grad p^l' (row-major; l the
+ * oversampled multiscale trial function, p^l' the bilinear nodal test
+ * function of K), by the element sum.  o = 0 gives the MsFEM stiffness of
+ * eq. stiffness_local. */
+int orc_cell_S_os(int m, int o, int nfx, int nfy, const double* a, ptrdiff_t lda, int kx, int ky, double S16[16]) {
+  const int nn = m + 1;
+  double* phiK = (double*)malloc(sizeof(double) * 8 * (size_t)nn * nn);
+  if (!phiK) return ORC_ENOMEM;
+  double* pt = phiK + 4 * (size_t)nn * nn;
+  int st = orc_cell_phi_os(m, o, nfx, nfy, a, lda, kx, ky, phiK, NULL);
+  if (st == ORC_OK) {
+    for (int py = 0; py <= m; ++py)
+      for (int px = 0; px <= m; ++px) {
+        const double x = (double)px / m, y = (double)py / m;
+        const int id = py * nn + px;
+        pt[0 * nn * nn + id] = (1.0 - x) * (1.0 - y);
+        pt[1 * nn * nn + id] = x * (1.0 - y);
+        pt[2 * nn * nn + id] = x * y;
+        pt[3 * nn * nn + id] = (1.0 - x) * y;
+      }
+    orc_energy_S(m, a + (ptrdiff_t)ky * m * lda + (ptrdiff_t)kx * m, lda, phiK, pt, S16);
+  }
+  free(phiK);
+  return st;
+}
+
+/* All pairs.  a: [N][ncy*m][ncx*m]; S16: [N][ncy*ncx][16]; status optional. */
+int orc_upscale_os(int64_t N, int ncx, int ncy, int m, int o, const double* a, double* S16, int32_t* status,
+                   int nthreads) {
+  if (N < 0 || ncx < 1 || ncy < 1 || m < 1 || o < 0 || !a || !S16) return ORC_EINVAL;
+  if (m + 2 * o > ncx * m || m + 2 * o > ncy * m) return ORC_EINVAL;
+  const int64_t M = (int64_t)ncx * ncy;
+  const ptrdiff_t lda = (ptrdiff_t)ncx * m;
+  const int64_t per_sample = (int64_t)ncy * m * lda;
+  int worst = ORC_OK;
+  ensure_kref();
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads) reduction(min : worst)
+#endif
+  for (int64_t t = 0; t < N * M; ++t) {
+    int64_t s = t / M;
+    int K = (int)(t % M);
+    int st = orc_cell_S_os(m, o, ncx * m, ncy * m, a + s * per_sample, lda, K % ncx, K / ncx, S16 + t * 16);
+    if (status) status[t] = st;
+    if (st < worst) worst = st;
+  }
+  return worst;
+}
+
+/* Banded LU with partial pivoting (kl sub-, ku super-diagonals; row i keeps
+ * columns [i - kl, i + kl + ku], the upper band widened by kl for the row
+ * interchanges) and the solve of A x = b in place.  A(i, c) at
+ * W[i * (2 kl + ku + 1) + c - i + kl].  Returns 0 or ORC_ENOTSPD on a zero
+ * pivot. */
+#define GB(W, w, kl, i, c) (W)[(size_t)(i) * (w) + ((c) - (i) + (kl))]
+int orc_band_lu_solve(int n, int kl, int ku, double* W, double* b) {
+  const int w = 2 * kl + ku + 1;
+  for (int j = 0; j < n; ++j) {
+    int i1 = j + kl < n - 1 ? j + kl : n - 1;
+    int p = j;
+    for (int i = j + 1; i <= i1; ++i)
+      if (fabs(GB(W, w, kl, i, j)) > fabs(GB(W, w, kl, p, j))) p = i;
+    if (!(fabs(GB(W, w, kl, p, j)) > 0.0)) return ORC_ENOTSPD;
+    int c1 = j + kl + ku < n - 1 ? j + kl + ku : n - 1;
+    if (p != j) {
+      for (int c = j; c <= c1; ++c) {
+        double t = GB(W, w, kl, j, c);
+        GB(W, w, kl, j, c) = GB(W, w, kl, p, c);
+        GB(W, w, kl, p, c) = t;
+      }
+      double t = b[j];
+      b[j] = b[p];
+      b[p] = t;
+    }
+    for (int i = j + 1; i <= i1; ++i) {
+      double l = GB(W, w, kl, i, j) / GB(W, w, kl, j, j);
+      GB(W, w, kl, i, j) = 0.0;
+      for (int c = j + 1; c <= c1; ++c) GB(W, w, kl, i, c) -= l * GB(W, w, kl, j, c);
+      b[i] -= l * b[j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = b[i];
+    int c1 = i + kl + ku < n - 1 ? i + kl + ku : n - 1;
+    for (int c = i + 1; c <= c1; ++c) t -= GB(W, w, kl, i, c) * b[c];
+    b[i] = t / GB(W, w, kl, i, i);
+  }
+  return ORC_OK;
+}
+
+/* One sample of the Petrov-Galerkin coarse system (eq. upscaleSUF with the
+ * local quantities of eq. stiffness_local_petrov): the equation of interior
+ * node a (test function a) is sum_b G[a][b] U_b = b_a with
+ * G[a][b] = sum_K S16^K[l(b)][l'(a)].  S16: [M][16]; load as in
+ * orc_coarse_one. */
+int orc_coarse_pg_one(int ncx, int ncy, const double* S16, const double* load, double* U) {
+  const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, kl = ncx, ku = ncx;
+  if (nU <= 0) return ORC_OK;
+  const int w = 2 * kl + ku + 1;
+  double* W = (double*)calloc((size_t)nU * w, sizeof(double));
+  if (!W) return ORC_ENOMEM;
+  const double H = 1.0 / ncx;
+  for (int i = 0; i < nU; ++i) U[i] = 0.0;
+  for (int ky = 0; ky < ncy; ++ky)
+    for (int kx = 0; kx < ncx; ++kx) {
+      int K = ky * ncx + kx;
+      int px[4] = {kx, kx + 1, kx + 1, kx};
+      int py[4] = {ky, ky, ky + 1, ky + 1};
+      for (int te = 0; te < 4; ++te) { /* test (row) */
+        int ia = (px[te] > 0 && px[te] < ncx && py[te] > 0 && py[te] < ncy) ? (py[te] - 1) * nix + (px[te] - 1) : -1;
+        if (ia < 0) continue;
+        U[ia] += load ? load[(size_t)K * 4 + te] : 0.25 * H * H;
+        for (int tr = 0; tr < 4; ++tr) { /* trial (column) */
+          int ib = (px[tr] > 0 && px[tr] < ncx && py[tr] > 0 && py[tr] < ncy) ? (py[tr] - 1) * nix + (px[tr] - 1) : -1;
+          if (ib >= 0) GB(W, w, kl, ia, ib) += S16[(size_t)K * 16 + 4 * tr + te];
+        }
+      }
+    }
+  int st = orc_band_lu_solve(nU, kl, ku, W, U);
+  free(W);
+  return st;
+}
+
+int orc_coarse_pg_solve(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
+                        double* qoi_mean, double* qoi_var, int32_t* status, int nthreads) {
+  if (ncx < 1 || ncy < 1 || N < 0 || !S16 || !U) return ORC_EINVAL;
+  const int64_t M = (int64_t)ncx * ncy;
+  const int nU = (ncx - 1) * (ncy - 1);
+  int worst = ORC_OK;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(min : worst)
+#endif
+  for (int64_t s = 0; s < N; ++s) {
+    int st = orc_coarse_pg_one(ncx, ncy, S16 + s * M * 16, load, U + s * nU);
     if (status) status[s] = st;
     if (st < worst) worst = st;
   }
