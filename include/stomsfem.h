@@ -177,6 +177,38 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
                           double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2: remark on
+ * oversampling, eq. stiffness_local_petrov; Sec. 4.1.1 for the coarse solve).
+ *
+ * stomsfem_upscale_os: for every pair of `batch` the cell problems of
+ * eq. MsFEB are solved on the patch of M = m + 2*oversample fine cells per
+ * side centred on K (moved inside the domain where it would stick out), with
+ * the bilinear nodal functions of the patch corners as boundary data; the
+ * basis is recombined to take the nodal values delta_ik at the corners of K,
+ * and
+ *   S[l][l'] = int_K a grad phi^l . grad p^l'   (p^l': K's bilinear functions)
+ * is written as 16 row-major doubles per pair (l: trial, l': test; corners
+ * counter-clockwise from the lower left) to batch->S, which must therefore
+ * hold [nsamples][ncy*ncx][16].  S is not symmetric when oversample > 0;
+ * oversample = 0 gives the unpacked stiffness of stomsfem_upscale.  The
+ * oversampling ratio is M/m (2 for oversample = m/2).  Requires
+ * 2 <= M <= 32 and M <= ncx*m, ncy*m (EINVAL otherwise).  Per-pair status
+ * ENOTSPD if a pivot is not positive or the corner values of the patch
+ * solutions are singular (S undefined).  Asynchronous.
+ *
+ * stomsfem_coarse_solve_pg: the coarse solve of stomsfem_coarse_solve for
+ * the non-symmetric system assembled from S16 [nsamples][ncy*ncx][16]: the
+ * equation of interior test node a is sum_b G[a][b] U_b = b_a with
+ * G[a][b] = sum_K S^K[l(b)][l'(a)] (l(b), l'(a): the nodes' local indices in
+ * K); FP64 LU without pivoting.  Same arguments, outputs and workspace use
+ * as stomsfem_coarse_solve; requires ncx <= 64; status ENOTSPD if a pivot is
+ * not positive.
+ * ------------------------------------------------------------------------ */
+int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* stream);
+int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S16, const double* load,
+                             double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
+
+/* ------------------------------------------------------------------------
  * Reduced-basis acceleration (Sec. 3.2: eqs. KLphi, localRB, localRBsystem,
  * RBaffine/localAF; Algorithms 3 and 4).
  *

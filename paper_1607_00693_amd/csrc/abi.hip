@@ -27,8 +27,12 @@ hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st,
 bool tiled_supports(int m);
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
                          double* var, int32_t* status, double* work, hipStream_t st);
+hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
+                            double* mean, double* var, int32_t* status, double* work, hipStream_t st);
+hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+bool upscale_os_supports(int m, int o);
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples);
-size_t coarse_lds_bytes(int ncx);
+size_t coarse_lds_bytes(int ncx, bool pg);
 hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
                              double base, double amp, double beta, void* a, int a_dtype, hipStream_t st);
 hipError_t launch_feature_map(int nfine, int nfeat, const int32_t* kind, const double* x0, const double* y0,
@@ -403,7 +407,7 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
                           double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream) {
   if (ncx < 1 || ncy < 1 || nsamples < 0) return fail(STOMSFEM_EINVAL, "coarse_solve: bad sizes");
   if (ncx > 1024 || ncy > 1024) return fail(STOMSFEM_EINVAL, "coarse_solve: ncx, ncy must be <= 1024");
-  if (coarse_lds_bytes(ncx) > 64 * 1024) return fail(STOMSFEM_EINVAL, "coarse_solve: ncx too large for the LDS window");
+  if (coarse_lds_bytes(ncx, false) > 64 * 1024) return fail(STOMSFEM_EINVAL, "coarse_solve: ncx too large for the LDS window");
   const int nU = (ncx - 1) * (ncy - 1);
   if (nU == 0) return STOMSFEM_OK;
   if (nsamples > 0 && (!device_ptr(S) || !device_ptr(U)))
@@ -420,6 +424,45 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
   hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
                                (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve launch");
+}
+
+int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* stream) {
+  if (!batch) return fail(STOMSFEM_EINVAL, "upscale_os: NULL batch");
+  int rc = check_batch(*batch, 0);
+  if (rc != STOMSFEM_OK) return rc;
+  const stomsfem_batch& b = *batch;
+  if (oversample < 0 || !upscale_os_supports(b.m, oversample))
+    return fail(STOMSFEM_EINVAL, "upscale_os: need oversample >= 0 and 2 <= m + 2*oversample <= 32");
+  const int64_t M = b.m + 2 * (int64_t)oversample;
+  if (M > (int64_t)b.ncx * b.m || M > (int64_t)b.ncy * b.m)
+    return fail(STOMSFEM_EINVAL, "upscale_os: the oversampled patch is larger than the domain");
+  if (b.nsamples == 0) return STOMSFEM_OK;
+  hipError_t e = launch_upscale_os(to_args(b), oversample, b.a_dtype, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_os launch");
+}
+
+int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S16, const double* load,
+                             double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream) {
+  if (ncx < 1 || ncy < 1 || nsamples < 0) return fail(STOMSFEM_EINVAL, "coarse_solve_pg: bad sizes");
+  if (ncx > 64 || ncy > 1024) return fail(STOMSFEM_EINVAL, "coarse_solve_pg: need ncx <= 64 and ncy <= 1024");
+  if (coarse_lds_bytes(ncx, true) > 64 * 1024)
+    return fail(STOMSFEM_EINVAL, "coarse_solve_pg: ncx too large for the LDS window");
+  const int nU = (ncx - 1) * (ncy - 1);
+  if (nU == 0) return STOMSFEM_OK;
+  if (nsamples > 0 && (!device_ptr(S16) || !device_ptr(U)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve_pg: S16 and U must be device pointers");
+  if (load && !device_ptr(load)) return fail(STOMSFEM_EINVAL, "coarse_solve_pg: load must be a device pointer");
+  if ((qoi_mean && !device_ptr(qoi_mean)) || (qoi_var && !device_ptr(qoi_var)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve_pg: qoi outputs must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "coarse_solve_pg: status must be a device pointer");
+  void* work = nullptr;
+  if (nsamples > 0) {
+    int rc = workspace_get(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), &work);
+    if (rc != STOMSFEM_OK) return rc;
+  }
+  hipError_t e = launch_coarse_pg(ncx, ncy, nsamples, S16, load, U, qoi_mean, qoi_var, status, (double*)work,
+                                  (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve_pg launch");
 }
 
 int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,

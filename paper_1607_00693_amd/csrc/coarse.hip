@@ -33,7 +33,7 @@ namespace stomsfem {
 constexpr int COARSE_THREADS = 256;
 constexpr int COARSE_NQ = 12;  // largest NQ: B (B+1)/2 <= 3072
 constexpr int COARSE_BMAX = 72;
-constexpr int COARSE_NE = (COARSE_BMAX * 10 + COARSE_THREADS - 1) / COARSE_THREADS;  // element-row prefetch
+constexpr int COARSE_PG_BMAX = 64;  // Petrov-Galerkin: full B x B trailing square, <= 16 entries per lane
 constexpr int COARSE_PD = 8;  // backward substitution: L entries loaded this many steps ahead
 
 // Workgroup barrier that orders LDS only: a pivot step does not wait for
@@ -66,6 +66,12 @@ struct CoarseArgs {
   double* work;  // nsamples * (nU * (ncx+1) + 1) doubles (one launch's samples)
 };
 
+// Entry of an element matrix with trial index tr and test index te: the
+// packed symmetric form, or the 16 row-major entries S[trial][test] of the
+// Petrov-Galerkin local stiffness (eq. stiffness_local_petrov).
+template <bool PG>
+__device__ __forceinline__ double sget(const double* Sk, int tr, int te);
+
 __device__ __forceinline__ double selem(const double* Sk, int i, int j) {
   // packed upper triangle 00,01,02,03,11,12,13,22,23,33
   if (i > j) {
@@ -75,6 +81,15 @@ __device__ __forceinline__ double selem(const double* Sk, int i, int j) {
   }
   const int base = i == 0 ? 0 : i == 1 ? 4 : i == 2 ? 7 : 9;
   return Sk[base + (j - i)];
+}
+
+template <>
+__device__ __forceinline__ double sget<false>(const double* Sk, int tr, int te) {
+  return selem(Sk, tr, te);
+}
+template <>
+__device__ __forceinline__ double sget<true>(const double* Sk, int tr, int te) {
+  return Sk[4 * tr + te];
 }
 
 // L entries of backward step j for lane `lam`, zero where the lane's index is
@@ -109,18 +124,26 @@ __device__ __forceinline__ BackStep back_loads(const double* Lc, int64_t zero, i
   return r;
 }
 
-// NQ = trailing-triangle entries per lane, >= B (B+1) / (2 * 64); NQ = 4
-// serves B <= 44.
-template <int NQ>
+// NQ = trailing entries per lane: >= B (B+1) / (2 * 256) for the symmetric
+// triangle (NQ = 4 serves B <= 44), >= B^2 / 256 for the Petrov-Galerkin
+// square.  PG: element matrices of 16 entries S[trial][test], the coarse
+// matrix G[test node][trial node] is non-symmetric and is factored G = L U
+// without pivoting (the pivot row goes to the next phase beside the pivot
+// column; the backward pass solves U x = y in the form x = z - (D^{-1} U - I) x
+// with z = D^{-1} y, the same recurrence as L^T x = D^{-1} y).
+template <int NQ, bool PG>
 __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs args) {
+  constexpr int ES = PG ? 16 : 10;  // doubles per element matrix
+  constexpr int NE = (COARSE_BMAX * ES + COARSE_THREADS - 1) / COARSE_THREADS;  // element-row prefetch
   extern __shared__ double smem[];
   const int ncx = args.ncx, ncy = args.ncy;
   const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, B = ncx, WN = B + 1, FN = B + 2;
   double* Wn = smem;         // WN*WN: row r in slot r % WN, column c in slot c % WN
   double* F = Wn + WN * WN;  // FN: forward-substituted rhs, row r in slot r % FN
-  double* Ec = F + FN;       // 4 x ncx x 10: ring of element rows of S (row e in slot e % 4)
+  double* Ec = F + FN;       // 3 x ncx x ES: ring of element rows of S (row e in slot e % 3)
   __shared__ int bad;
   __shared__ double colv[2][COARSE_BMAX];  // colv[j & 1][t - 1] = W(j + t, j), t = 1..B
+  __shared__ double rowv[2][PG ? COARSE_BMAX : 1];  // PG: rowv[j & 1][t - 1] = W(j, j + t)
   __shared__ double pinv[2];               // pinv[j & 1] = 1 / d_j
   const int tid = threadIdx.x;
   const int Mc = ncx * ncy;
@@ -135,10 +158,14 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = tid + COARSE_THREADS * q;
-    int io = 0;
-    while ((io + 1) * (io + 2) / 2 <= t) ++io;
-    const bool used = t < B * (B + 1) / 2;
-    tik[q] = used ? (io | ((t - io * (io + 1) / 2) << 8)) : B;
+    if (PG) {
+      tik[q] = t < B * B ? ((t / B) | ((t % B) << 8)) : B;
+    } else {
+      int io = 0;
+      while ((io + 1) * (io + 2) / 2 <= t) ++io;
+      const bool used = t < B * (B + 1) / 2;
+      tik[q] = used ? (io | ((t - io * (io + 1) / 2) << 8)) : B;
+    }
   }
 
   // one sample per workgroup: its slice of the workspace must survive until
@@ -146,34 +173,34 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
   {
     const int64_t s = blockIdx.x;
     if (s >= args.nsamples) return;
-    const double* Ss = args.S + s * (int64_t)Mc * 10;
+    const double* Ss = args.S + s * (int64_t)Mc * ES;
     double* Us = args.U + s * (int64_t)nU;
     for (int i = tid; i < WN * WN; i += blockDim.x) Wn[i] = 0.0;
     if (tid == 0) bad = 0;
-    // Element rows of S go through an LDS ring.  Node row iy uses element rows
-    // iy and iy + 1.  Rows 0..3 are loaded here; the first node of node row
-    // iy >= 2 stores element row iy + 2 (prefetched into registers at node
-    // row iy - 1) into the slot of row iy - 2, which only node rows up to
-    // iy - 2 used, and prefetches element row iy + 3.
-    double epre[COARSE_NE];
+    // Element rows of S go through an LDS ring of three.  Node row iy uses
+    // element rows iy and iy + 1.  Rows 0..2 are loaded here; the first node
+    // of node row iy >= 1 stores element row iy + 2 (prefetched into
+    // registers a node row earlier) into the slot of row iy - 1, which only
+    // node rows up to iy - 1 used, and prefetches element row iy + 3.
+    double epre[NE];
     auto erow_fetch = [&](int e) {
 #pragma unroll
-      for (int k = 0; k < COARSE_NE; ++k) {
+      for (int k = 0; k < NE; ++k) {
         const int t = tid + COARSE_THREADS * k;
-        epre[k] = (e < ncy && t < ncx * 10) ? Ss[(int64_t)e * ncx * 10 + t] : 0.0;
+        epre[k] = (e < ncy && t < ncx * ES) ? Ss[(int64_t)e * ncx * ES + t] : 0.0;
       }
     };
     auto erow_store = [&](int e) {
 #pragma unroll
-      for (int k = 0; k < COARSE_NE; ++k) {
+      for (int k = 0; k < NE; ++k) {
         const int t = tid + COARSE_THREADS * k;
-        if (e < ncy && t < ncx * 10) Ec[(e % 4) * ncx * 10 + t] = epre[k];
+        if (e < ncy && t < ncx * ES) Ec[(e % 3) * ncx * ES + t] = epre[k];
       }
     };
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 3; ++e)
       if (e < ncy)
-        for (int t = tid; t < ncx * 10; t += blockDim.x) Ec[(e % 4) * ncx * 10 + t] = Ss[(int64_t)e * ncx * 10 + t];
-    erow_fetch(4);
+        for (int t = tid; t < ncx * ES; t += blockDim.x) Ec[e * ncx * ES + t] = Ss[(int64_t)e * ncx * ES + t];
+    erow_fetch(3);
 
     // load of row r (the last thread keeps the next row's value)
     auto node_load = [&](int r) -> double {
@@ -191,28 +218,47 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     // elements SW=(px-1,py-1), SE=(px,py-1), NW=(px-1,py), NE=(px,py) see it as
     // local node 2, 3, 1, 0 respectively.  The entry at offset B (the SW
     // coupling, column r - B) also goes to colB, the next pivot's column.
-    auto insert_row = [&](int r, double* colB) {
+    // PG: the column above the diagonal, G[r - t][r], enters with the row
+    // (and its entry at distance B goes to rowB, the next pivot's row).
+    auto insert_row = [&](int r, double* colB, double* rowB) {
       const int ix = r % nix, iy = r / nix, px = ix + 1, py = iy + 1;
-      if (ix == 0 && iy >= 2) {
+      if (ix == 0 && iy >= 1) {
         erow_store(iy + 2);
         erow_fetch(iy + 3);
       }
-      const double* eS = Ec + ((py - 1) % 4) * ncx * 10;
-      const double* eN = Ec + (py % 4) * ncx * 10;
-      const double* sSW = eS + (px - 1) * 10;
-      const double* sSE = eS + px * 10;
-      const double* sNW = eN + (px - 1) * 10;
-      const double* sNE = eN + px * 10;
+      const double* eS = Ec + ((py - 1) % 3) * ncx * ES;
+      const double* eN = Ec + (py % 3) * ncx * ES;
+      const double* sSW = eS + (px - 1) * ES;
+      const double* sSE = eS + px * ES;
+      const double* sNW = eN + (px - 1) * ES;
+      const double* sNE = eN + px * ES;
       for (int t = tid; t <= B; t += COARSE_THREADS) {
-        double v = 0.0;
-        if (t == 0) v += (selem(sSW, 2, 2) + selem(sSE, 3, 3)) + (selem(sNW, 1, 1) + selem(sNE, 0, 0));
-        if (t == 1 && ix >= 1) v += selem(sSW, 2, 3) + selem(sNW, 1, 0);
-        if (t == nix - 1 && iy >= 1 && ix <= nix - 2) v += selem(sSE, 3, 1);
-        if (t == nix && iy >= 1) v += selem(sSW, 2, 1) + selem(sSE, 3, 0);
-        if (t == nix + 1 && iy >= 1 && ix >= 1) v += selem(sSW, 2, 0);
+        // v = G[r][r - t] (test r, trial r - t), u = G[r - t][r]; local
+        // indices of r and of the neighbour in each shared element
+        double v = 0.0, u = 0.0;
+        if (t == 0)
+          v += (sget<PG>(sSW, 2, 2) + sget<PG>(sSE, 3, 3)) + (sget<PG>(sNW, 1, 1) + sget<PG>(sNE, 0, 0));
+        if (t == 1 && ix >= 1) {
+          v += sget<PG>(sSW, 3, 2) + sget<PG>(sNW, 0, 1);
+          u += sget<PG>(sSW, 2, 3) + sget<PG>(sNW, 1, 0);
+        }
+        if (t == nix - 1 && iy >= 1 && ix <= nix - 2) {
+          v += sget<PG>(sSE, 1, 3);
+          u += sget<PG>(sSE, 3, 1);
+        }
+        if (t == nix && iy >= 1) {
+          v += sget<PG>(sSW, 1, 2) + sget<PG>(sSE, 0, 3);
+          u += sget<PG>(sSW, 2, 1) + sget<PG>(sSE, 3, 0);
+        }
+        if (t == nix + 1 && iy >= 1 && ix >= 1) {
+          v += sget<PG>(sSW, 0, 2);
+          u += sget<PG>(sSW, 2, 0);
+        }
         if (r - t >= 0) {
           Wn[(r % WN) * WN + ((r - t) % WN)] = v;  // every entry of the row, once
+          if (PG && t > 0) Wn[((r - t) % WN) * WN + (r % WN)] = u;
           if (t == B && colB) colB[B - 1] = v;
+          if (PG && t == B && rowB) rowB[B - 1] = u;
         }
       }
       if (tid == COARSE_THREADS - 1) {
@@ -223,11 +269,14 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
 
     const int r0 = B < nU - 1 ? B : nU - 1;
     for (int r = 0; r <= r0; ++r) {
-      insert_row(r, nullptr);
+      insert_row(r, nullptr, nullptr);
       __syncthreads();
     }
     // pivot 0's column and 1/d_0
-    for (int t = 1 + tid; t <= r0; t += COARSE_THREADS) colv[0][t - 1] = Wn[t * WN];
+    for (int t = 1 + tid; t <= r0; t += COARSE_THREADS) {
+      colv[0][t - 1] = Wn[t * WN];
+      if (PG) rowv[0][t - 1] = Wn[t];
+    }
     if (tid == 0) {
       const double d = Wn[0];
       pinv[0] = 1.0 / d;
@@ -251,17 +300,17 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
         for (int q = 0; q < NQ; ++q) {
           const int io = tik[q] & 255, ko = tik[q] >> 8;
           idx[q] = wrap(jj + 1 + io, WN) * WN + wrap(jj + 1 + ko, WN);
-          wv[q] = io < cnt ? Wn[idx[q]] : 0.0;
+          wv[q] = (io < cnt && ko < cnt) ? Wn[idx[q]] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int io = tik[q] & 255, ko = tik[q] >> 8;
-          if (io < cnt) wv[q] -= colv[b][io] * inv * colv[b][ko];
+          if (io < cnt && ko < cnt) wv[q] -= colv[b][io] * inv * (PG ? rowv[b][ko] : colv[b][ko]);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int io = tik[q] & 255, ko = tik[q] >> 8;
-          if (io < cnt) {
+          if (io < cnt && ko < cnt) {
             Wn[idx[q]] = wv[q];
             if (ko == 0) {
               if (io > 0) {
@@ -270,6 +319,8 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
                 pinv[b ^ 1] = 1.0 / wv[q];
                 if (!(wv[q] > 0.0)) bad = 1;
               }
+            } else if (PG && io == 0) {
+              rowv[b ^ 1][ko - 1] = wv[q];
             }
           }
         }
@@ -278,7 +329,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       // pivot above it has been applied in an earlier phase)
       for (int t = 1 + tid; t <= cnt; t += COARSE_THREADS) {
         const double l = colv[b][t - 1] * inv;
-        Lc[(int64_t)j * WN + t] = l;
+        Lc[(int64_t)j * WN + t] = PG ? rowv[b][t - 1] * inv : l;  // PG: (D^{-1} U)_{j, j+t}
         F[(j + t) % FN] -= l * F[j % FN];
       }
       if (tid == 0) {
@@ -287,7 +338,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       }
       // the row entering the window takes the slot of row j (its last reader
       // was the phase before); its F slot is that of row j - 1
-      if (j + 1 + B < nU) insert_row(j + 1 + B, colv[b ^ 1]);
+      if (j + 1 + B < nU) insert_row(j + 1 + B, colv[b ^ 1], PG ? rowv[b ^ 1] : nullptr);
       COARSE_SYNC();
     }
     if (tid == 0 && args.status) args.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
@@ -371,9 +422,9 @@ __global__ void qoi_kernel(int64_t N, int nU, const double* U, double* mean, dou
   if (var) var[i] = m2 - m1 * m1;
 }
 
-size_t coarse_lds_bytes(int ncx) {
+size_t coarse_lds_bytes(int ncx, bool pg) {
   const int WN = ncx + 1;
-  return sizeof(double) * ((size_t)WN * WN + (size_t)WN + 1 + 40 * (size_t)ncx);
+  return sizeof(double) * ((size_t)WN * WN + (size_t)WN + 1 + 3 * (size_t)ncx * (pg ? 16 : 10));
 }
 
 int64_t coarse_grid(int64_t nsamples) { return nsamples < 4096 ? nsamples : 4096; }
@@ -382,28 +433,40 @@ int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
   return coarse_grid(nsamples) * ((int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1) + 1);
 }
 
-hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
-                         double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
+static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
+                                    double* mean, double* var, int32_t* status, double* work, hipStream_t st,
+                                    bool pg) {
   const int nU = (ncx - 1) * (ncy - 1);
-  if (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ || ncx > COARSE_BMAX) return hipErrorInvalidValue;
+  if (pg ? ncx > COARSE_PG_BMAX : (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ || ncx > COARSE_BMAX))
+    return hipErrorInvalidValue;
+  const int ES = pg ? 16 : 10;
   if (N > 0 && nU > 0) {
-    const int need = (ncx * (ncx + 1) / 2 + COARSE_THREADS - 1) / COARSE_THREADS;
-    const size_t lds = coarse_lds_bytes(ncx);
-    const int64_t chunk = coarse_grid(N);  // samples per launch pair: the workspace holds their L factors
+    const int need = pg ? (ncx * ncx + COARSE_THREADS - 1) / COARSE_THREADS
+                        : (ncx * (ncx + 1) / 2 + COARSE_THREADS - 1) / COARSE_THREADS;
+    const size_t lds = coarse_lds_bytes(ncx, pg);
+    const int64_t chunk = coarse_grid(N);  // samples per launch pair: the workspace holds their factors
     for (int64_t c = 0; c < N; c += chunk) {
       const int64_t n = N - c < chunk ? N - c : chunk;
-      CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * 10, load, U + c * (int64_t)nU,
+      CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * ES, load, U + c * (int64_t)nU,
                    status ? status + c : nullptr, work};
-      if (need <= 4)
-        hipLaunchKernelGGL(coarse_solve_kernel<4>, dim3((unsigned)n), dim3(COARSE_THREADS), lds, st, a);
-      else
-        hipLaunchKernelGGL(coarse_solve_kernel<COARSE_NQ>, dim3((unsigned)n), dim3(COARSE_THREADS), lds, st, a);
+      const dim3 grid((unsigned)n), block(COARSE_THREADS);
+      if (pg) {
+        if (need <= 4)
+          hipLaunchKernelGGL((coarse_solve_kernel<4, true>), grid, block, lds, st, a);
+        else
+          hipLaunchKernelGGL((coarse_solve_kernel<16, true>), grid, block, lds, st, a);
+      } else {
+        if (need <= 4)
+          hipLaunchKernelGGL((coarse_solve_kernel<4, false>), grid, block, lds, st, a);
+        else
+          hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false>), grid, block, lds, st, a);
+      }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       if (ncx > 64)
-        hipLaunchKernelGGL(coarse_back_kernel<true>, dim3((unsigned)n), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(coarse_back_kernel<true>, grid, dim3(64), 0, st, a);
       else
-        hipLaunchKernelGGL(coarse_back_kernel<false>, dim3((unsigned)n), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(coarse_back_kernel<false>, grid, dim3(64), 0, st, a);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -413,6 +476,17 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
+                         double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
+  return launch_coarse_any(ncx, ncy, N, S, load, U, mean, var, status, work, st, false);
+}
+
+// Petrov-Galerkin coarse system: S16 [N][ncx*ncy][16], S[trial][test] per element.
+hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
+                            double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
+  return launch_coarse_any(ncx, ncy, N, S16, load, U, mean, var, status, work, st, true);
 }
 
 }  // namespace stomsfem

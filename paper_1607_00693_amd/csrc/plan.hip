@@ -21,7 +21,7 @@ hipError_t launch_upscale_any(const UpArgs& args, int a_dtype, hipStream_t st);
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
                          double* var, int32_t* status, double* work, hipStream_t st);
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples);
-size_t coarse_lds_bytes(int ncx);
+size_t coarse_lds_bytes(int ncx, bool pg);
 hipError_t launch_coef_bumps(int64_t nsamples, int nfine, const double* xi, int nxi, int g, double rho, double eps,
                              double base, double amp, double beta, void* a, int a_dtype, hipStream_t st);
 hipError_t launch_coef_features(int64_t nsamples, int nfine, const int32_t* map, int nfeat, const double* xi, int nxi,
@@ -132,7 +132,7 @@ int stomsfem_plan_create(const stomsfem_stage* stages, int32_t nstage, stomsfem_
     if (s.m < 1 || s.m > 48) return pfail(STOMSFEM_EINVAL, w + "m must be in 1..48");
     if (s.nsamples < 1) return pfail(STOMSFEM_EINVAL, w + "nsamples must be >= 1");
     if (s.a_dtype != STOMSFEM_F64 && s.a_dtype != STOMSFEM_F32) return pfail(STOMSFEM_EINVAL, w + "bad a_dtype");
-    if (coarse_lds_bytes(s.ncx) > 64 * 1024) return pfail(STOMSFEM_EINVAL, w + "coarse mesh too large");
+    if (coarse_lds_bytes(s.ncx, false) > 64 * 1024) return pfail(STOMSFEM_EINVAL, w + "coarse mesh too large");
     if (!s.xi) return pfail(STOMSFEM_EINVAL, w + "xi is NULL");
     if (s.family == STOMSFEM_FAMILY_BUMPS) {
       if (s.bumps.g < 1 || s.nxi < s.bumps.g * s.bumps.g || !(s.bumps.rho > 0) || !(s.bumps.eps > 0))

@@ -1,0 +1,323 @@
+// Oversampled local upscaling with the Petrov-Galerkin stiffness (Sec. 2.2,
+// remark on oversampling; eq. stiffness_local_petrov).
+//
+// For the coarse element K the cell problems (eq. MsFEB) are solved on a
+// patch of M = m + 2o fine cells per side around K (moved inside the domain
+// at its edges), with the bilinear nodal functions g^j of the patch corners
+// as boundary data: psi^j, j = 0..3, psi^3 = 1 - psi^0 - psi^1 - psi^2.  All
+// the Petrov-Galerkin stiffness needs of them is linear in psi^j, so it comes
+// out of the same sliding-window LDL^T as the plain path, with test vectors
+// carried through the forward substitution beside the three data sets
+// f^j = -K_IB g^j:
+//   psi^j(x_k) = e_k . K_II^{-1} f^j          (corner x_k of K inside the patch)
+//   A[j][l]    = psi^j . r^l,  r^l = K^K p^l  (K^K: fine stiffness of K's
+//                elements; p^l: K's bilinear nodal functions)
+// and, with K_II = L D L^T, u . K_II^{-1} v = sum_k (L^{-1}u)_k (L^{-1}v)_k / d_k.
+// C = Psi^{-T} makes phi^i = sum_j C[i][j] psi^j nodal at K's corners, and
+// S[l][l'] = int_K a grad phi^l . grad p^l' = (C A)[l][l'].
+//
+// One wavefront per pair: the patch coefficients, the (M+1) x (M+1) circular
+// band window and the ten right-hand-side columns live in LDS; the rank-1
+// update of each pivot is spread over the 64 lanes; no workgroup barriers.
+#include "common.h"
+
+namespace stomsfem {
+
+#define OS_WAVE_SYNC()                                     \
+  do {                                                     \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                       \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+  } while (0)
+
+constexpr int OS_NV = 10;    // columns: f^0..2, corner tests 0..3, r^0..2
+constexpr int OS_MAXM = 32;  // largest patch (band half-width)
+constexpr int OS_EP = 32;    // epilogue scratch per wavefront (doubles)
+
+struct OsArgs {
+  UpArgs up;  // up.m = m; up.S = S16 output [npairs][16]
+  int32_t o;  // fine cells added on each side of K
+};
+
+// first fine cell (one axis) of the patch of coarse element k
+__host__ __device__ inline int os_origin(int k, int m, int o, int nf) {
+  int x0 = k * m - o;
+  if (x0 > nf - (m + 2 * o)) x0 = nf - (m + 2 * o);
+  return x0 < 0 ? 0 : x0;
+}
+
+__host__ __device__ inline int os_lds_doubles(int M) {
+  const int WN = M + 1;
+  return M * M + WN * WN + WN * OS_NV + OS_EP;
+}
+
+// x mod w for 0 <= x < 2w
+__device__ __forceinline__ int os_wrap(int x, int w) { return x >= w ? x - w : x; }
+
+// r^l = (K^K p^l) at patch node (px, py): the elements of K around the node
+// (SW, SE, NW, NE see it as local node 2, 3, 1, 0), each a_e K_ref p^l_e.
+__device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, int M, const double* Ap) {
+  double v = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ex = px - 1 + (e & 1), ey = py - 1 + (e >> 1);
+    if (ex < cx || ex >= cx + m || ey < cy || ey >= cy + m) continue;
+    const int al = e == 0 ? 2 : e == 1 ? 3 : e == 2 ? 1 : 0;
+    double s = 0.0;
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+      const int bx = ex + (be == 1 || be == 2), by = ey + (be >= 2);
+      s += kref(al, be) * pcorner(l, bx - cx, by - cy, m);
+    }
+    v += Ap[ey * M + ex] * s;
+  }
+  return v;
+}
+
+// NQ >= B (B + 1) / (2 * 64): trailing-triangle entries per lane.
+template <typename TA, int NQ>
+__global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
+  extern __shared__ double smem[];
+  const int m = args.up.m, o = args.o, M = m + 2 * o, n = M - 1, NI = n * n, B = M, WN = B + 1;
+  const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* Ap = smem + wave * os_lds_doubles(M);  // patch coefficients [M][M]
+  double* Wn = Ap + M * M;                       // window, (r, c) at [r % WN][c % WN]
+  double* R = Wn + WN * WN;                      // right-hand sides, row r at [r % WN][OS_NV]
+  double* Ep = R + WN * OS_NV;                   // epilogue scratch
+  const int64_t p = (int64_t)blockIdx.x * waves + wave;
+  if (p >= args.up.npairs) return;  // the whole wavefront; no workgroup barrier follows
+  const int ncx = args.up.ncx, ncy = args.up.ncy, Mc = ncx * ncy;
+  const int64_t s = p / Mc;
+  const int K = (int)(p - s * Mc), kx = K % ncx, ky = K / ncx;
+  const int nfx = ncx * m, nfy = ncy * m;
+  const int x0 = os_origin(kx, m, o, nfx), y0 = os_origin(ky, m, o, nfy);
+  const int cx = kx * m - x0, cy = ky * m - y0;  // K's lower-left node in patch nodes
+  const TA* a = (const TA*)args.up.a + s * (int64_t)nfy * nfx;
+  for (int i = lane; i < M * M; i += 64) Ap[i] = ld(a, (int64_t)(y0 + i / M) * nfx + x0 + i % M);
+  for (int i = lane; i < WN * WN; i += 64) Wn[i] = 0.0;
+  for (int i = lane; i < WN * OS_NV; i += 64) R[i] = 0.0;
+  // this lane's entries (io >= ko) of the B x B trailing triangle
+  int tik[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = lane + 64 * q;
+    int io = 0;
+    while ((io + 1) * (io + 2) / 2 <= t) ++io;
+    tik[q] = t < B * (B + 1) / 2 ? (io | ((t - io * (io + 1) / 2) << 8)) : B;
+  }
+  OS_WAVE_SYNC();
+
+  // original row r of K_II (lanes 0..B: band entry at distance lane) and its
+  // ten right-hand sides (lanes B+1..B+10)
+  auto insert_row = [&](int r) {
+    const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+    const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
+    const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
+    if (lane <= B) {
+      const int t = lane;
+      double v = 0.0;
+      if (t == 0) v += (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+      if (t == 1 && ix >= 1) v += -(aSW + aNW) * (1.0 / 6.0);
+      if (t == n - 1 && iy >= 1 && ix <= n - 2) v += -aSE * (1.0 / 3.0);
+      if (t == n && iy >= 1) v += -(aSW + aSE) * (1.0 / 6.0);
+      if (t == n + 1 && iy >= 1 && ix >= 1) v += -aSW * (1.0 / 3.0);
+      if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;
+    } else if (lane <= B + OS_NV) {
+      const int v = lane - B - 1;
+      double val = 0.0;
+      if (v < 3) {
+        // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q)
+        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+        const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+        const double ks[8] = {-(aSW + aNW) / 6.0, -(aSE + aNE) / 6.0, -(aSW + aSE) / 6.0, -(aNW + aNE) / 6.0,
+                              -aSW / 3.0,         -aSE / 3.0,         -aNW / 3.0,         -aNE / 3.0};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int qx = px + dxs[q], qy = py + dys[q];
+          if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * pcorner(v, qx, qy, M);
+        }
+      } else if (v < 7) {
+        const int k = v - 3;  // corner k of K (CCW from lower left)
+        const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
+        val = (px == kpx && py == kpy) ? 1.0 : 0.0;
+      } else {
+        val = os_rK(v - 7, px, py, cx, cy, m, M, Ap);
+      }
+      R[(r % WN) * OS_NV + v] = val;
+    }
+  };
+
+  const int r0 = B < NI ? B : NI;
+  for (int r = 0; r < r0; ++r) insert_row(r);
+  OS_WAVE_SYNC();
+  // lanes 0..20 accumulate Y[jv][tv] = f^jv . K_II^{-1} (test column 3 + tv)
+  const int jv = lane / 7, tv = 3 + lane % 7;
+  double yacc = 0.0;
+  bool bad = false;
+  for (int j = 0; j < NI; ++j) {
+    if (j + B < NI) {
+      insert_row(j + B);
+      OS_WAVE_SYNC();
+    }
+    const int jj = j % WN;
+    const double d = Wn[jj * WN + jj];
+    bad = bad || !(d > 0.0);
+    const double inv = 1.0 / d;
+    const int cnt = (j + B < NI - 1 ? j + B : NI - 1) - j;
+    if (lane < 21) yacc += R[jj * OS_NV + jv] * R[jj * OS_NV + tv] * inv;
+    double wv[NQ];
+    int idx[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int io = tik[q] & 255, ko = tik[q] >> 8;
+      const int ri = os_wrap(jj + 1 + io, WN), rk = os_wrap(jj + 1 + ko, WN);
+      idx[q] = ri * WN + rk;
+      wv[q] = io < cnt ? Wn[idx[q]] - Wn[ri * WN + jj] * inv * Wn[rk * WN + jj] : 0.0;
+    }
+    for (int e = lane; e < cnt * OS_NV; e += 64) {
+      const int t = 1 + e / OS_NV, v = e - (t - 1) * OS_NV;
+      const int rt = os_wrap(jj + t, WN);
+      R[rt * OS_NV + v] -= Wn[rt * WN + jj] * inv * R[jj * OS_NV + v];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if ((tik[q] & 255) < cnt) Wn[idx[q]] = wv[q];
+    OS_WAVE_SYNC();
+  }
+
+  // g^j . r^l over K's nodes on the patch boundary (K touches it only at the
+  // edges of the domain, where the patch is moved inside)
+  double bt[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) bt[q] = 0.0;
+  for (int id = lane; id < (m + 1) * (m + 1); id += 64) {
+    const int ax = cx + id % (m + 1), ay = cy + id / (m + 1);
+    if (!(ax == 0 || ax == M || ay == 0 || ay == M)) continue;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double rl = os_rK(l, ax, ay, cx, cy, m, M, Ap);
+#pragma unroll
+      for (int jb = 0; jb < 3; ++jb) bt[3 * jb + l] += pcorner(jb, ax, ay, M) * rl;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+    for (int off = 32; off > 0; off >>= 1) bt[q] += __shfl_xor(bt[q], off, 64);
+  if (lane < 21) Ep[lane] = yacc;
+  OS_WAVE_SYNC();
+  if (lane == 0) {
+    // Psi[k][j] = psi^j(x_k); corners on the patch boundary carry the data
+    double Psi[4][4], A[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
+      const bool onb = kpx == 0 || kpx == M || kpy == 0 || kpy == M;
+      double sum = 0.0;
+#pragma unroll
+      for (int jb = 0; jb < 3; ++jb) {
+        Psi[k][jb] = onb ? pcorner(jb, kpx, kpy, M) : Ep[jb * 7 + k];
+        sum += Psi[k][jb];
+      }
+      Psi[k][3] = 1.0 - sum;
+    }
+    // A[j][l] = int_K a grad psi^j . grad p^l; row and column 3 from the
+    // partitions of unity of psi and p
+#pragma unroll
+    for (int jb = 0; jb < 3; ++jb) {
+      double rs = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        A[jb][l] = bt[3 * jb + l] + Ep[jb * 7 + 4 + l];
+        rs += A[jb][l];
+      }
+      A[jb][3] = -rs;
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l) A[3][l] = -(A[0][l] + A[1][l] + A[2][l]);
+    // C = (Psi^T)^{-1}: Gauss-Jordan with partial pivoting on [Psi^T | I]
+    double G[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) G[i][c] = c < 4 ? Psi[c][i] : (c - 4 == i ? 1.0 : 0.0);
+    // (every index compile-time: the row interchange is a select per entry)
+    bool sing = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int pr = c;
+      double best = fabs(G[c][c]);
+#pragma unroll
+      for (int i = c + 1; i < 4; ++i)
+        if (fabs(G[i][c]) > best) {
+          best = fabs(G[i][c]);
+          pr = i;
+        }
+#pragma unroll
+      for (int i = c + 1; i < 4; ++i) {
+        const bool sw = i == pr;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const double t = G[c][cc];
+          G[c][cc] = sw ? G[i][cc] : t;
+          G[i][cc] = sw ? t : G[i][cc];
+        }
+      }
+      sing = sing || !(fabs(G[c][c]) > 0.0);
+      const double iv = 1.0 / G[c][c];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) G[c][cc] *= iv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i == c) continue;
+        const double f = G[i][c];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) G[i][cc] -= f * G[c][cc];
+      }
+    }
+    double* out = args.up.S + p * 16;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+      for (int lp = 0; lp < 4; ++lp) {
+        double v = 0.0;
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) v += G[l][4 + jb] * A[jb][lp];
+        out[4 * l + lp] = v;
+      }
+    if (args.up.status) args.up.status[p] = (bad || sing) ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+  }
+}
+
+size_t upscale_os_lds_bytes(int m, int o, int waves) {
+  return sizeof(double) * (size_t)os_lds_doubles(m + 2 * o) * waves;
+}
+
+int upscale_os_waves(int m, int o) { return m + 2 * o <= 24 ? 4 : 2; }
+
+bool upscale_os_supports(int m, int o) { return m >= 1 && o >= 0 && m + 2 * o >= 2 && m + 2 * o <= OS_MAXM; }
+
+template <typename TA>
+static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
+  const int M = args.up.m + 2 * args.o;
+  const int waves = upscale_os_waves(args.up.m, args.o);
+  const int64_t blocks = (args.up.npairs + waves - 1) / waves;
+  const size_t lds = upscale_os_lds_bytes(args.up.m, args.o, waves);
+  const int need = (M * (M + 1) / 2 + 63) / 64;
+  const dim3 grid((unsigned)blocks), block(64 * waves);
+  if (need <= 3)
+    hipLaunchKernelGGL((upscale_os_kernel<TA, 3>), grid, block, lds, st, args);
+  else if (need <= 5)
+    hipLaunchKernelGGL((upscale_os_kernel<TA, 5>), grid, block, lds, st, args);
+  else
+    hipLaunchKernelGGL((upscale_os_kernel<TA, 9>), grid, block, lds, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st) {
+  if (!upscale_os_supports(up.m, o)) return hipErrorInvalidValue;
+  if (up.npairs == 0) return hipSuccess;
+  const OsArgs args{up, o};
+  return a_dtype == STOMSFEM_F32 ? launch_os_t<float>(args, st) : launch_os_t<double>(args, st);
+}
+
+}  // namespace stomsfem

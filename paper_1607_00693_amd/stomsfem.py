@@ -85,6 +85,8 @@ def lib():
         "stomsfem_upscale": (C.c_int, [C.POINTER(Batch), i32, i32, i32, vp]),
         "stomsfem_upscale_reference": (C.c_int, [C.POINTER(Batch), i32, vp]),
         "stomsfem_coarse_solve": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
+        "stomsfem_coarse_solve_pg": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
+        "stomsfem_upscale_os": (C.c_int, [vp, i32, vp]),
         "stomsfem_workspace_reserve": (C.c_int, [i64]),
         "stomsfem_reduce": (C.c_int, [C.POINTER(Batch), i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_reduce_apply": (C.c_int, [vp, C.POINTER(Batch), i32, vp]),
@@ -164,10 +166,11 @@ def coef_bumps(xi: torch.Tensor, nfine: int, g: int, rho: float, eps: float, bas
     return out
 
 
-def make_batch(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor, status: torch.Tensor | None) -> Batch:
+def make_batch(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor, status: torch.Tensor | None,
+               entries: int = 10) -> Batch:
     N = a.shape[0]
     assert a.shape[1:] == (ncy * m, ncx * m), f"a has shape {tuple(a.shape)}"
-    assert S.dtype == torch.float64 and S.shape == (N, ncx * ncy, 10)
+    assert S.dtype == torch.float64 and S.shape == (N, ncx * ncy, entries)
     if status is not None:
         assert status.dtype == torch.int32 and status.shape == (N, ncx * ncy)
     return Batch(ncx, ncy, m, _DT[a.dtype], N, _ptr(a), _ptr(S), _ptr(status))
@@ -217,6 +220,39 @@ def coarse_solve(S: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None 
         assert load.dtype == torch.float64 and load.shape == (ncx * ncy, 4)
     _check("stomsfem_coarse_solve", lib().stomsfem_coarse_solve(
         ncx, ncy, N, _ptr(S), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
+    return U, qoi_mean, qoi_var
+
+
+def upscale_os(a: torch.Tensor, ncx: int, ncy: int, m: int, oversample: int, S: torch.Tensor | None = None,
+               status: torch.Tensor | None = None, stream=None):
+    """Oversampled Petrov-Galerkin stiffness S[N][ncy*ncx][16] (row-major [trial][test])."""
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, ncx * ncy, 16), dtype=torch.float64, device=a.device)
+    assert S.is_contiguous()
+    b = make_batch(a, ncx, ncy, m, S, status, entries=16)
+    _check("stomsfem_upscale_os", lib().stomsfem_upscale_os(C.byref(b), oversample, _stream(stream)))
+    return S
+
+
+def coarse_solve_pg(S16: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None = None,
+                    U: torch.Tensor | None = None, qoi_mean: torch.Tensor | None = None,
+                    qoi_var: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+    """Coarse solutions of the Petrov-Galerkin system from S16[N][ncy*ncx][16]."""
+    N = S16.shape[0]
+    assert S16.dtype == torch.float64 and S16.shape == (N, ncx * ncy, 16) and S16.is_contiguous()
+    nU = (ncx - 1) * (ncy - 1)
+    dev = S16.device
+    if U is None:
+        U = torch.empty((N, nU), dtype=torch.float64, device=dev)
+    if qoi_mean is None:
+        qoi_mean = torch.empty(nU, dtype=torch.float64, device=dev)
+    if qoi_var is None:
+        qoi_var = torch.empty(nU, dtype=torch.float64, device=dev)
+    if load is not None:
+        assert load.dtype == torch.float64 and load.shape == (ncx * ncy, 4)
+    _check("stomsfem_coarse_solve_pg", lib().stomsfem_coarse_solve_pg(
+        ncx, ncy, N, _ptr(S16), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
     return U, qoi_mean, qoi_var
 
 

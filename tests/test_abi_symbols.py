@@ -62,6 +62,14 @@ def test_host_validation_without_gpu():
     assert lib.stomsfem_autotune(None, ctypes.c_int32(1), None, None) == -1
     lib.stomsfem_plan_create.restype = ctypes.c_int
     assert lib.stomsfem_plan_create(None, ctypes.c_int32(0), None) == -1
+    # oversampling / Petrov-Galerkin entry points
+    lib.stomsfem_upscale_os.restype = ctypes.c_int
+    assert lib.stomsfem_upscale_os(None, ctypes.c_int32(4), None) == -1
+    assert b"NULL batch" in lib.stomsfem_last_error()
+    lib.stomsfem_coarse_solve_pg.restype = ctypes.c_int
+    rc = lib.stomsfem_coarse_solve_pg(ctypes.c_int32(65), ctypes.c_int32(3), ctypes.c_int64(1), None, None, None,
+                                      None, None, None, None)
+    assert rc == -1 and b"ncx <= 64" in lib.stomsfem_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

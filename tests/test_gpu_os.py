@@ -1,0 +1,194 @@
+"""GPU parity of oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2,
+remark on oversampling; eq. stiffness_local_petrov) and of the non-symmetric
+coarse solve, through the C-ABI, against the CPU oracle.
+
+Tolerances: per pair max |S - S_ref| <= 1e-10 max |S_ref| (FP64 on both
+sides; the GPU forms the corner values and the Galerkin products from the
+Schur complement with test vectors, the oracle from the solved fields, so the
+two differ by rounding only: ~1e-14 measured on CPU emulation); coarse
+solutions per sample ||U - U_ref|| <= 1e-10 ||U_ref||."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1607_00693_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STOL = 1e-10
+
+
+def say(msg):
+    print(f"[gpu-os] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sm():
+    from paper_1607_00693_amd import stomsfem
+
+    assert torch.cuda.is_available()
+    stomsfem.lib()
+    return stomsfem
+
+
+def s_relerr(S, Sref):
+    S, Sref = np.asarray(S), np.asarray(Sref)
+    return (np.abs(S - Sref).max(-1) / np.abs(Sref).max(-1)).max()
+
+
+def _bumps(sm, orc, wl, N, seed):
+    xi = W.uniform_xi(N, wl.nxi, seed)
+    a = sm.coef_bumps(torch.from_numpy(xi).cuda(), wl.nfine, **wl.coef_params())
+    return a, orc.coef_bumps(xi, wl.nfine, **wl.coef_params())
+
+
+@pytest.mark.parametrize("o", [0, 4, 8])
+def test_mesh8_matches_oracle(sm, orc, o):
+    wl = W.MESH8
+    N = 3
+    say(f"mesh8 oversample={o} N={N}")
+    a, a_ref = _bumps(sm, orc, wl, N, 1101 + o)
+    status = torch.full((N, wl.M), 99, dtype=torch.int32, device="cuda")
+    S = sm.upscale_os(a, wl.nc, wl.nc, wl.m, o, status=status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    S_ref, _ = orc.upscale_os(a_ref, wl.nc, wl.nc, wl.m, o)
+    err = s_relerr(S.cpu().numpy(), S_ref)
+    say(f"  S rel err {err:.2e}")
+    assert err <= STOL
+    if o == 0:
+        # no oversampling: the unpacked MsFEM stiffness of the plain path
+        Sp = sm.upscale(a, wl.nc, wl.nc, wl.m)
+        torch.cuda.synchronize()
+        assert s_relerr(S.cpu().numpy(), orc.unpack(Sp.cpu().numpy()).reshape(N, wl.M, 16)) <= STOL
+
+
+@pytest.mark.parametrize("m,o,ncx,ncy,N", [(6, 3, 5, 3, 1), (4, 2, 3, 7, 2), (16, 8, 4, 3, 1), (8, 12, 4, 4, 1),
+                                           (2, 1, 9, 2, 3)])
+def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
+    # non-square meshes, pair counts that leave the last workgroup partly
+    # empty, patches of M = 4 ... 32 (every trailing-entry count per lane),
+    # patches moved inside the domain on all four sides
+    say(f"ragged m={m} o={o} {ncx}x{ncy} N={N}")
+    a_ref = W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1200 + m + o)
+    a = torch.from_numpy(a_ref).cuda()
+    S = sm.upscale_os(a, ncx, ncy, m, o)
+    torch.cuda.synchronize()
+    S_ref, _ = orc.upscale_os(a_ref, ncx, ncy, m, o)
+    err = s_relerr(S.cpu().numpy(), S_ref)
+    say(f"  S rel err {err:.2e}")
+    assert err <= STOL
+
+
+def test_float32_coefficients(sm, orc):
+    m, o, ncx, ncy, N = 8, 4, 4, 4, 2
+    a32 = torch.from_numpy(W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1300)).float().cuda()
+    S = sm.upscale_os(a32, ncx, ncy, m, o)
+    torch.cuda.synchronize()
+    S_ref, _ = orc.upscale_os(a32.double().cpu().numpy(), ncx, ncy, m, o)
+    assert s_relerr(S.cpu().numpy(), S_ref) <= STOL
+
+
+def test_non_positive_coefficient_sets_status(sm):
+    m, o, ncx, ncy = 4, 2, 3, 3
+    a = torch.from_numpy(W.uniform_array((2, ncy * m, ncx * m), 0.5, 2.0, 1301)).cuda()
+    a[1] = -a[1]
+    status = torch.full((2, ncx * ncy), 99, dtype=torch.int32, device="cuda")
+    sm.upscale_os(a, ncx, ncy, m, o, status=status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert (st[0] == 0).all() and (st[1] == sm.ENOTSPD).all()
+
+
+def test_mesh8_end_to_end_pg(sm, orc):
+    # local Petrov-Galerkin stiffness -> non-symmetric coarse solve -> QoI
+    wl = W.MESH8
+    o, N = 4, 16
+    say(f"mesh8 end to end, oversample={o}, N={N}")
+    a, a_ref = _bumps(sm, orc, wl, N, 1102)
+    S = sm.upscale_os(a, wl.nc, wl.nc, wl.m, o)
+    status = torch.full((N,), 99, dtype=torch.int32, device="cuda")
+    U, mean, var = sm.coarse_solve_pg(S, wl.nc, wl.nc, status=status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    S_ref, _ = orc.upscale_os(a_ref, wl.nc, wl.nc, wl.m, o)
+    U_ref, mean_ref, var_ref = orc.coarse_solve_pg(S_ref, wl.nc, wl.nc)
+    U = U.cpu().numpy()
+    err = (np.linalg.norm(U - U_ref, axis=1) / np.linalg.norm(U_ref, axis=1)).max()
+    say(f"  U rel err {err:.2e}")
+    assert err <= 1e-10
+    np.testing.assert_allclose(mean.cpu().numpy(), mean_ref, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(var.cpu().numpy(), var_ref, rtol=1e-7, atol=1e-12 * np.abs(mean_ref).max() ** 2)
+
+
+@pytest.mark.parametrize("ncx,ncy,N", [(8, 8, 3), (33, 5, 2), (64, 64, 2), (5, 40, 2), (2, 2, 3)])
+def test_coarse_pg_against_oracle(sm, orc, ncx, ncy, N):
+    # synthetic non-symmetric element matrices (a K_Q1 plus a perturbation
+    # with zero row sums) so that every band size, including the 64 x 64
+    # coarse mesh, is covered without running the oracle's cell solves
+    say(f"coarse pg {ncx}x{ncy} N={N}")
+    K = orc.q1_kref()
+    rng = np.random.default_rng(1400 + ncx + ncy)
+    A = rng.uniform(0.3, 4.0, size=(N, ncx * ncy, 1, 1))
+    E = rng.normal(size=(N, ncx * ncy, 4, 4)) * 0.15 * A
+    E -= E.mean(axis=3, keepdims=True)
+    S16 = (A * K + E).reshape(N, ncx * ncy, 16)
+    load = rng.uniform(0.5, 1.5, size=(ncx * ncy, 4))
+    U, mean, _ = sm.coarse_solve_pg(torch.from_numpy(S16).cuda(), ncx, ncy, load=torch.from_numpy(load).cuda())
+    torch.cuda.synchronize()
+    U_ref, mean_ref, _ = orc.coarse_solve_pg(S16, ncx, ncy, load.reshape(-1))
+    U = U.cpu().numpy()
+    err = (np.linalg.norm(U - U_ref, axis=1) / np.linalg.norm(U_ref, axis=1)).max()
+    say(f"  U rel err {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_coarse_pg_symmetric_input_matches_cholesky_path(sm, orc):
+    wl = W.MESH8
+    N = 4
+    a, _ = _bumps(sm, orc, wl, N, 1103)
+    S10 = sm.upscale(a, wl.nc, wl.nc, wl.m)
+    S16 = sm.upscale_os(a, wl.nc, wl.nc, wl.m, 0)
+    U10, _, _ = sm.coarse_solve(S10, wl.nc, wl.nc)
+    U16, _, _ = sm.coarse_solve_pg(S16, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(U16.cpu().numpy(), U10.cpu().numpy(), rtol=1e-11, atol=0)
+
+
+def test_invalid_arguments(sm):
+    for m, o, nc in ((8, 13, 2), (8, -1, 2), (4, 8, 2)):  # patch > 32, negative, patch > domain
+        a = torch.zeros((1, nc * m, nc * m), dtype=torch.float64, device="cuda")
+        with pytest.raises(sm.StomsfemError) as e:
+            sm.upscale_os(a, nc, nc, m, o)
+        assert e.value.code == sm.EINVAL
+    S16 = torch.zeros((1, 65 * 2, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError):
+        sm.coarse_solve_pg(S16, 65, 2)
+    # empty batch
+    S = sm.upscale_os(torch.zeros((0, 16, 16), dtype=torch.float64, device="cuda"), 2, 2, 8, 4)
+    assert S.shape == (0, 4, 16)
+
+
+def test_full_size_sampled(sm, orc):
+    # the throughput shape (8 x 8 mesh, H/h = 8, 16384 samples, oversampling
+    # ratio 2) in the launch configuration of the benchmark; sampled pairs
+    # against the oracle's cell-by-cell computation
+    wl = W.MESH8
+    N, o = 16384, 4
+    say(f"full size N={N} oversample={o}")
+    xi = W.uniform_xi(N, wl.nxi, wl.seed)
+    a = sm.coef_bumps(torch.from_numpy(xi).cuda(), wl.nfine, **wl.coef_params())
+    status = torch.full((N, wl.M), 99, dtype=torch.int32, device="cuda")
+    S = sm.upscale_os(a, wl.nc, wl.nc, wl.m, o, status=status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    S = S.cpu().numpy()
+    rng = np.random.default_rng(7)
+    for s in rng.choice(N, 6, replace=False):
+        a_s = orc.coef_bumps(xi[s:s + 1], wl.nfine, **wl.coef_params())[0]
+        for K in rng.choice(wl.M, 4, replace=False):
+            ref = orc.cell_S_os(a_s, wl.m, o, int(K) % wl.nc, int(K) // wl.nc).reshape(16)
+            assert np.abs(S[s, K] - ref).max() <= STOL * np.abs(ref).max(), (s, K)
