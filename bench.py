@@ -280,6 +280,66 @@ def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((
     return out
 
 
+def os_flops_per_pair(m: int, o: int) -> float:
+    """FP64 operations of the oversampled Petrov-Galerkin cell computation for
+    one pair (an FMA counts 2), patch of M = m + 2o cells: per pivot with c
+    active rows, the rank-1 window update c(c+1)/2 FMA, 1 div, the forward
+    step of the ten right-hand sides 10c FMA and the 21 Schur products 42;
+    20 ops per interior row for its stencil, lifts and tests; the 4x4
+    recombination (about 300)."""
+    M = m + 2 * o
+    n = M - 1
+    NI = n * n
+    f = 0.0
+    for j in range(NI):
+        c = min(M, NI - 1 - j)
+        f += c * (c + 1) + 1 + 20 * c + 42
+    return f + 20 * NI + 300
+
+
+def measure_oversampling(log, N=16384):
+    """Oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2 remark,
+    eq. stiffness_local_petrov) on the 8x8 coarse mesh, H/h = 8: patches of
+    16 and 24 fine cells per side (oversampling ratios 2 and 3), then the
+    non-symmetric coarse solve; against the plain path (no oversampling) at
+    the same shape.  The change of the coarse solution that oversampling
+    makes is reported as information (the resonance effect itself is a test
+    of the oracle)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.MESH8
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, wl.seed)).cuda()
+    a = sm.coef_bumps(xi, wl.nfine, **wl.coef_params())
+    S_pl = torch.empty((N, wl.M, 10), dtype=torch.float64, device="cuda")
+    t_pl = _timed(lambda: sm.upscale(a, wl.nc, wl.nc, wl.m, S=S_pl))
+    U_pl, _, _ = sm.coarse_solve(S_pl, wl.nc, wl.nc)
+    t_cpl = _timed(lambda: sm.coarse_solve(S_pl, wl.nc, wl.nc, U=U_pl))
+    out = {"workload": f"8x8 coarse, H/h=8, {N} samples (bump family, the 8x8 mesh's xi seed)",
+           "plain": {"upscale_ms": t_pl * 1e3, "coarse_ms": t_cpl * 1e3, "pairs_per_s": N * wl.M / t_pl}}
+    for o in (wl.m // 2, wl.m):
+        M = wl.m + 2 * o
+        S = torch.empty((N, wl.M, 16), dtype=torch.float64, device="cuda")
+        st = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+        t_os = _timed(lambda: sm.upscale_os(a, wl.nc, wl.nc, wl.m, o, S=S, status=st), reps=3)
+        U, _, _ = sm.coarse_solve_pg(S, wl.nc, wl.nc)
+        t_cpg = _timed(lambda: sm.coarse_solve_pg(S, wl.nc, wl.nc, U=U), reps=3)
+        fl = os_flops_per_pair(wl.m, o)
+        d = torch.linalg.norm(U - U_pl, dim=1) / torch.linalg.norm(U_pl, dim=1)
+        key = f"ratio_{M // wl.m}"
+        out[key] = {"patch_cells": M, "oversample_cells": o,
+                    "upscale_ms": t_os * 1e3, "coarse_pg_ms": t_cpg * 1e3,
+                    "pairs_per_s": N * wl.M / t_os, "vs_plain_upscale": t_pl / t_os,
+                    "flops_per_pair": fl, "achieved_tflops": fl * N * wl.M / t_os / 1e12,
+                    "fp64_peak_frac": fl * N * wl.M / t_os / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                    "non_ok_pairs": int((st != 0).sum().item()),
+                    "max_rel_change_of_U_vs_plain": float(d.max().item())}
+        log(f"oversampling ratio {M // wl.m}: {out[key]}")
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -535,6 +595,9 @@ def main():
         out["accelerations"]["fp32_solve_fp64_refinement_bench_mesh"] = mixed
         print("[bench] channels-and-inclusions workload through a graph plan", file=sys.stderr, flush=True)
         out["channels64_plan"] = measure_channels(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print("[bench] oversampled Petrov-Galerkin upscaling at the 8x8 mesh", file=sys.stderr, flush=True)
+        out["oversampled_petrov_galerkin"] = measure_oversampling(
+            lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -46,17 +46,26 @@ __host__ __device__ inline int os_origin(int k, int m, int o, int nf) {
   return x0 < 0 ? 0 : x0;
 }
 
-__host__ __device__ inline int os_lds_doubles(int M) {
+__host__ __device__ inline int os_lds_doubles(int m, int M) {
   const int WN = M + 1;
-  return M * M + WN * WN + WN * OS_NV + OS_EP;
+  return M * M + WN * WN + WN * OS_NV + OS_EP + 3 * (m + 1) * (m + 1) + 3 * 4 * M;
 }
 
 // x mod w for 0 <= x < 2w
 __device__ __forceinline__ int os_wrap(int x, int w) { return x >= w ? x - w : x; }
 
+// Bilinear corner function p^l (l = 0..2) at node (px, py) of a grid with
+// 1/size = rs (a multiplication where pcorner divides: equal for powers of
+// two, within an ulp otherwise).
+__device__ __forceinline__ double os_pc(int l, int px, int py, double rs) {
+  const double x = px * rs, y = py * rs;
+  return l == 0 ? (1.0 - x) * (1.0 - y) : l == 1 ? x * (1.0 - y) : x * y;
+}
+
 // r^l = (K^K p^l) at patch node (px, py): the elements of K around the node
 // (SW, SE, NW, NE see it as local node 2, 3, 1, 0), each a_e K_ref p^l_e.
 __device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, int M, const double* Ap) {
+  const double rm = 1.0 / m;
   double v = 0.0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -67,7 +76,7 @@ __device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, int
 #pragma unroll
     for (int be = 0; be < 4; ++be) {
       const int bx = ex + (be == 1 || be == 2), by = ey + (be >= 2);
-      s += kref(al, be) * pcorner(l, bx - cx, by - cy, m);
+      s += kref(al, be) * os_pc(l, bx - cx, by - cy, rm);
     }
     v += Ap[ey * M + ex] * s;
   }
@@ -80,10 +89,12 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   extern __shared__ double smem[];
   const int m = args.up.m, o = args.o, M = m + 2 * o, n = M - 1, NI = n * n, B = M, WN = B + 1;
   const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* Ap = smem + wave * os_lds_doubles(M);  // patch coefficients [M][M]
-  double* Wn = Ap + M * M;                       // window, (r, c) at [r % WN][c % WN]
-  double* R = Wn + WN * WN;                      // right-hand sides, row r at [r % WN][OS_NV]
-  double* Ep = R + WN * OS_NV;                   // epilogue scratch
+  double* Ap = smem + wave * os_lds_doubles(m, M);  // patch coefficients [M][M]
+  double* Wn = Ap + M * M;                          // window, (r, c) at [r % WN][c % WN]
+  double* R = Wn + WN * WN;                         // right-hand sides, row r at [r % WN][OS_NV]
+  double* Ep = R + WN * OS_NV;                      // epilogue scratch
+  double* Rk = Ep + OS_EP;                          // r^l at K's nodes [3][(m+1)^2]
+  double* Fb = Rk + 3 * (m + 1) * (m + 1);          // lifts f^v of the rows next to the boundary [M*M][3]
   const int64_t p = (int64_t)blockIdx.x * waves + wave;
   if (p >= args.up.npairs) return;  // the whole wavefront; no workgroup barrier follows
   const int ncx = args.up.ncx, ncy = args.up.ncy, Mc = ncx * ncy;
@@ -96,6 +107,48 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   for (int i = lane; i < M * M; i += 64) Ap[i] = ld(a, (int64_t)(y0 + i / M) * nfx + x0 + i % M);
   for (int i = lane; i < WN * WN; i += 64) Wn[i] = 0.0;
   for (int i = lane; i < WN * OS_NV; i += 64) R[i] = 0.0;
+  OS_WAVE_SYNC();
+  const int mm = m + 1;
+  for (int i = lane; i < 3 * mm * mm; i += 64) {
+    const int l = i / (mm * mm), id = i - l * mm * mm;
+    Rk[i] = os_rK(l, cx + id % mm, cy + id / mm, cx, cy, m, M, Ap);
+  }
+  const double rM = 1.0 / M;
+  // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q) for the rows
+  // next to the patch boundary, indexed by the row's position on that ring
+  const int nring = n == 1 ? 1 : 4 * (n - 1);
+  for (int i = lane; i < 3 * nring; i += 64) {
+    const int v = i / nring, b = i - v * nring;
+    int ix, iy;  // ring position b -> node: bottom, right, top, left (corners once)
+    if (n == 1) { ix = 0; iy = 0; }
+    else if (b < n - 1) { ix = b; iy = 0; }
+    else if (b < 2 * (n - 1)) { ix = n - 1; iy = b - (n - 1); }
+    else if (b < 3 * (n - 1)) { ix = n - 1 - (b - 2 * (n - 1)); iy = n - 1; }
+    else { ix = 0; iy = n - 1 - (b - 3 * (n - 1)); }
+    const int px = ix + 1, py = iy + 1;
+    const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
+    const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
+    const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+    const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+    const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0), -(aSW + aSE) * (1.0 / 6.0),
+                          -(aNW + aNE) * (1.0 / 6.0), -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
+                          -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
+    double val = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int qx = px + dxs[q], qy = py + dys[q];
+      if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * os_pc(v, qx, qy, rM);
+    }
+    Fb[b * 3 + v] = val;
+  }
+  // ring position of an interior node next to the boundary
+  auto ring_pos = [&](int ix, int iy) {
+    if (n == 1) return 0;
+    if (iy == 0) return ix;
+    if (ix == n - 1) return (n - 1) + iy;
+    if (iy == n - 1) return 2 * (n - 1) + (n - 1 - ix);
+    return 3 * (n - 1) + (n - 1 - iy);
+  };
   // this lane's entries (io >= ko) of the B x B trailing triangle
   int tik[NQ];
 #pragma unroll
@@ -107,10 +160,14 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   }
   OS_WAVE_SYNC();
 
-  // original row r of K_II (lanes 0..B: band entry at distance lane) and its
-  // ten right-hand sides (lanes B+1..B+10)
-  auto insert_row = [&](int r) {
-    const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+  // original row r = iy n + ix of K_II, in window slot rs (lanes 0..B: band
+  // entry at distance lane) and its ten right-hand sides (lanes B+1..B+10)
+  auto insert_row = [&](int r, int rs, int ix, int iy) {
+    const int px = ix + 1, py = iy + 1;
+    // wave-uniform: only rows next to the patch boundary have lifts, only
+    // nodes of K carry r^l
+    const bool nearb = ix == 0 || ix == n - 1 || iy == 0 || iy == n - 1;
+    const bool inK = px >= cx && px <= cx + m && py >= cy && py <= cy + m;
     const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
     const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
     if (lane <= B) {
@@ -121,48 +178,48 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
       if (t == n - 1 && iy >= 1 && ix <= n - 2) v += -aSE * (1.0 / 3.0);
       if (t == n && iy >= 1) v += -(aSW + aSE) * (1.0 / 6.0);
       if (t == n + 1 && iy >= 1 && ix >= 1) v += -aSW * (1.0 / 3.0);
-      if (r - t >= 0) Wn[(r % WN) * WN + ((r - t) % WN)] = v;
+      if (r - t >= 0) Wn[rs * WN + (rs - t >= 0 ? rs - t : rs - t + WN)] = v;
     } else if (lane <= B + OS_NV) {
       const int v = lane - B - 1;
       double val = 0.0;
       if (v < 3) {
-        // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q)
-        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-        const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
-        const double ks[8] = {-(aSW + aNW) / 6.0, -(aSE + aNE) / 6.0, -(aSW + aSE) / 6.0, -(aNW + aNE) / 6.0,
-                              -aSW / 3.0,         -aSE / 3.0,         -aNW / 3.0,         -aNE / 3.0};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int qx = px + dxs[q], qy = py + dys[q];
-          if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * pcorner(v, qx, qy, M);
-        }
+        if (nearb) val = Fb[ring_pos(ix, iy) * 3 + v];
       } else if (v < 7) {
         const int k = v - 3;  // corner k of K (CCW from lower left)
         const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
         val = (px == kpx && py == kpy) ? 1.0 : 0.0;
-      } else {
-        val = os_rK(v - 7, px, py, cx, cy, m, M, Ap);
+      } else if (inK) {
+        val = Rk[(v - 7) * mm * mm + (py - cy) * mm + (px - cx)];
       }
-      R[(r % WN) * OS_NV + v] = val;
+      R[rs * OS_NV + v] = val;
     }
   };
 
   const int r0 = B < NI ? B : NI;
-  for (int r = 0; r < r0; ++r) insert_row(r);
+  for (int r = 0; r < r0; ++r) insert_row(r, r, r % n, r / n);
   OS_WAVE_SYNC();
+  // the row entering at pivot j is j + B: slot (j + B) mod WN = (j - 1) mod WN,
+  // node (eix, eiy), both advanced incrementally
+  int eix = B % n, eiy = B / n;
   // lanes 0..20 accumulate Y[jv][tv] = f^jv . K_II^{-1} (test column 3 + tv)
   const int jv = lane / 7, tv = 3 + lane % 7;
   double yacc = 0.0;
   bool bad = false;
-  for (int j = 0; j < NI; ++j) {
+  for (int j = 0, jj = 0; j < NI; ++j, jj = jj + 1 == WN ? 0 : jj + 1) {
     if (j + B < NI) {
-      insert_row(j + B);
+      insert_row(j + B, jj == 0 ? WN - 1 : jj - 1, eix, eiy);
       OS_WAVE_SYNC();
+      if (++eix == n) {
+        eix = 0;
+        ++eiy;
+      }
     }
-    const int jj = j % WN;
     const double d = Wn[jj * WN + jj];
     bad = bad || !(d > 0.0);
-    const double inv = 1.0 / d;
+    // 1/d from the hardware estimate and two Newton steps (full FP64 accuracy)
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = __builtin_fma(inv, __builtin_fma(-d, inv, 1.0), inv);
+    inv = __builtin_fma(inv, __builtin_fma(-d, inv, 1.0), inv);
     const int cnt = (j + B < NI - 1 ? j + B : NI - 1) - j;
     if (lane < 21) yacc += R[jj * OS_NV + jv] * R[jj * OS_NV + tv] * inv;
     double wv[NQ];
@@ -195,9 +252,9 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
     if (!(ax == 0 || ax == M || ay == 0 || ay == M)) continue;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      const double rl = os_rK(l, ax, ay, cx, cy, m, M, Ap);
+      const double rl = Rk[l * mm * mm + id];
 #pragma unroll
-      for (int jb = 0; jb < 3; ++jb) bt[3 * jb + l] += pcorner(jb, ax, ay, M) * rl;
+      for (int jb = 0; jb < 3; ++jb) bt[3 * jb + l] += os_pc(jb, ax, ay, rM) * rl;
     }
   }
 #pragma unroll
@@ -215,7 +272,7 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
       double sum = 0.0;
 #pragma unroll
       for (int jb = 0; jb < 3; ++jb) {
-        Psi[k][jb] = onb ? pcorner(jb, kpx, kpy, M) : Ep[jb * 7 + k];
+        Psi[k][jb] = onb ? os_pc(jb, kpx, kpy, rM) : Ep[jb * 7 + k];
         sum += Psi[k][jb];
       }
       Psi[k][3] = 1.0 - sum;
@@ -289,10 +346,25 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
 }
 
 size_t upscale_os_lds_bytes(int m, int o, int waves) {
-  return sizeof(double) * (size_t)os_lds_doubles(m + 2 * o) * waves;
+  return sizeof(double) * (size_t)os_lds_doubles(m, m + 2 * o) * waves;
 }
 
-int upscale_os_waves(int m, int o) { return m + 2 * o <= 24 ? 4 : 2; }
+// wavefronts (pairs) per workgroup: within 64 KB of LDS, the count that puts
+// the most wavefronts on a CU's 160 KB (the larger one on a tie)
+int upscale_os_waves(int m, int o) {
+  int best = 1;
+  size_t best_waves = 0;
+  for (int w = 1; w <= 4; ++w) {
+    const size_t b = upscale_os_lds_bytes(m, o, w);
+    if (b > 64 * 1024) break;
+    const size_t on_cu = (160 * 1024 / b) * w;
+    if (on_cu >= best_waves) {
+      best_waves = on_cu;
+      best = w;
+    }
+  }
+  return best;
+}
 
 bool upscale_os_supports(int m, int o) { return m >= 1 && o >= 0 && m + 2 * o >= 2 && m + 2 * o <= OS_MAXM; }
 
