@@ -33,7 +33,8 @@ namespace stomsfem {
 constexpr int COARSE_THREADS = 256;
 constexpr int COARSE_NQ = 12;  // largest NQ: B (B+1)/2 <= 3072
 constexpr int COARSE_BMAX = 72;
-constexpr int COARSE_PG_BMAX = 64;  // Petrov-Galerkin: full B x B trailing square, <= 16 entries per lane
+constexpr int COARSE_PG_BMAX = 64;
+constexpr int COARSE_SMALL_B = 32;  // largest band served by the one-wavefront workgroup  // Petrov-Galerkin: full B x B trailing square, <= 16 entries per lane
 constexpr int COARSE_PD = 8;  // backward substitution: L entries loaded this many steps ahead
 
 // Workgroup barrier that orders LDS only: a pivot step does not wait for
@@ -131,10 +132,14 @@ __device__ __forceinline__ BackStep back_loads(const double* Lc, int64_t zero, i
 // without pivoting (the pivot row goes to the next phase beside the pivot
 // column; the backward pass solves U x = y in the form x = z - (D^{-1} U - I) x
 // with z = D^{-1} y, the same recurrence as L^T x = D^{-1} y).
-template <int NQ, bool PG>
-__global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs args) {
+// TH threads per workgroup: 256, or one wavefront (64) for coarse meshes with
+// ncx <= 32, where a pivot step has too little work to amortise a
+// multi-wavefront barrier.
+template <int NQ, bool PG, int TH>
+__global__ __launch_bounds__(TH) void coarse_solve_kernel(CoarseArgs args) {
   constexpr int ES = PG ? 16 : 10;  // doubles per element matrix
-  constexpr int NE = (COARSE_BMAX * ES + COARSE_THREADS - 1) / COARSE_THREADS;  // element-row prefetch
+  constexpr int BMX = TH == 64 ? COARSE_SMALL_B : COARSE_BMAX;
+  constexpr int NE = (BMX * ES + TH - 1) / TH;  // element-row prefetch
   extern __shared__ double smem[];
   const int ncx = args.ncx, ncy = args.ncy;
   const int nix = ncx - 1, niy = ncy - 1, nU = nix * niy, B = ncx, WN = B + 1, FN = B + 2;
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
   int tik[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int t = tid + COARSE_THREADS * q;
+    const int t = tid + TH * q;
     if (PG) {
       tik[q] = t < B * B ? ((t / B) | ((t % B) << 8)) : B;
     } else {
@@ -186,14 +191,14 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
     auto erow_fetch = [&](int e) {
 #pragma unroll
       for (int k = 0; k < NE; ++k) {
-        const int t = tid + COARSE_THREADS * k;
+        const int t = tid + TH * k;
         epre[k] = (e < ncy && t < ncx * ES) ? Ss[(int64_t)e * ncx * ES + t] : 0.0;
       }
     };
     auto erow_store = [&](int e) {
 #pragma unroll
       for (int k = 0; k < NE; ++k) {
-        const int t = tid + COARSE_THREADS * k;
+        const int t = tid + TH * k;
         if (e < ncy && t < ncx * ES) Ec[(e % 3) * ncx * ES + t] = epre[k];
       }
     };
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       return (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
              (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
     };
-    double bnext = tid == COARSE_THREADS - 1 ? node_load(0) : 0.0;
+    double bnext = tid == TH - 1 ? node_load(0) : 0.0;
     __syncthreads();
 
     // Row r of the coarse system: node (ix, iy) = grid node (px, py); its four
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       const double* sSE = eS + px * ES;
       const double* sNW = eN + (px - 1) * ES;
       const double* sNE = eN + px * ES;
-      for (int t = tid; t <= B; t += COARSE_THREADS) {
+      for (int t = tid; t <= B; t += TH) {
         // v = G[r][r - t] (test r, trial r - t), u = G[r - t][r]; local
         // indices of r and of the neighbour in each shared element
         double v = 0.0, u = 0.0;
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
           if (PG && t == B && rowB) rowB[B - 1] = u;
         }
       }
-      if (tid == COARSE_THREADS - 1) {
+      if (tid == TH - 1) {
         F[r % FN] = bnext;
         bnext = node_load(r + 1);
       }
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       __syncthreads();
     }
     // pivot 0's column and 1/d_0
-    for (int t = 1 + tid; t <= r0; t += COARSE_THREADS) {
+    for (int t = 1 + tid; t <= r0; t += TH) {
       colv[0][t - 1] = Wn[t * WN];
       if (PG) rowv[0][t - 1] = Wn[t];
     }
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void coarse_solve_kernel(CoarseArgs
       }
       // forward substitution step and column j of L (F[j] is final: every
       // pivot above it has been applied in an earlier phase)
-      for (int t = 1 + tid; t <= cnt; t += COARSE_THREADS) {
+      for (int t = 1 + tid; t <= cnt; t += TH) {
         const double l = colv[b][t - 1] * inv;
         Lc[(int64_t)j * WN + t] = PG ? rowv[b][t - 1] * inv : l;  // PG: (D^{-1} U)_{j, j+t}
         F[(j + t) % FN] -= l * F[j % FN];
@@ -405,21 +410,59 @@ __global__ __launch_bounds__(64) void coarse_back_kernel(CoarseArgs args) {
 }
 
 // qoi_mean[i] = (1/N) sum_s U[s][i]; qoi_var[i] = (1/N) sum_s U^2 - mean^2.
-// Fixed summation order over s (bitwise reproducible).
-__global__ void qoi_kernel(int64_t N, int nU, const double* U, double* mean, double* var) {
+// Two passes with a fixed summation order (bitwise reproducible): partial
+// sums over chunks of CS samples (64 unknowns per workgroup, the four
+// wavefronts taking every fourth sample of the chunk, combined in order),
+// then the chunks in order.  Reads are coalesced along the unknowns.
+constexpr int QOI_TY = 4;
+
+__global__ __launch_bounds__(64 * QOI_TY) void qoi_partial_kernel(int64_t N, int nU, int64_t CS, const double* U,
+                                                                  double* part) {
+  __shared__ double sh[2][QOI_TY][64];
+  const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + x;
+  const int64_t c = blockIdx.y, s0 = c * CS, s1 = s0 + CS < N ? s0 + CS : N;
+  double m1 = 0.0, m2 = 0.0;
+  if (i < nU)
+    for (int64_t s = s0 + y; s < s1; s += QOI_TY) {
+      const double u = U[s * nU + i];
+      m1 += u;
+      m2 += u * u;
+    }
+  sh[0][y][x] = m1;
+  sh[1][y][x] = m2;
+  __syncthreads();
+  if (y == 0 && i < nU) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < QOI_TY; ++k) {
+      a += sh[0][k][x];
+      b += sh[1][k][x];
+    }
+    part[(c * nU + i) * 2] = a;
+    part[(c * nU + i) * 2 + 1] = b;
+  }
+}
+
+__global__ void qoi_final_kernel(int64_t N, int nU, int64_t nch, const double* part, double* mean, double* var) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nU) return;
   double m1 = 0.0, m2 = 0.0;
-  for (int64_t s = 0; s < N; ++s) {
-    const double u = U[s * nU + i];
-    m1 += u;
-    m2 += u * u;
+  for (int64_t c = 0; c < nch; ++c) {
+    m1 += part[(c * nU + i) * 2];
+    m2 += part[(c * nU + i) * 2 + 1];
   }
   const double inv = N > 0 ? 1.0 / (double)N : 0.0;
   m1 *= inv;
   m2 *= inv;
   if (mean) mean[i] = m1;
   if (var) var[i] = m2 - m1 * m1;
+}
+
+// samples per QoI chunk: at most 1024 chunks
+static int64_t qoi_chunk(int64_t N) {
+  const int64_t cs = (N + 1023) / 1024;
+  return cs < 64 ? 64 : cs;
 }
 
 size_t coarse_lds_bytes(int ncx, bool pg) {
@@ -441,25 +484,38 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
     return hipErrorInvalidValue;
   const int ES = pg ? 16 : 10;
   if (N > 0 && nU > 0) {
-    const int need = pg ? (ncx * ncx + COARSE_THREADS - 1) / COARSE_THREADS
-                        : (ncx * (ncx + 1) / 2 + COARSE_THREADS - 1) / COARSE_THREADS;
+    const bool small = ncx <= COARSE_SMALL_B;
+    const int TH = small ? 64 : COARSE_THREADS;
+    const int need = pg ? (ncx * ncx + TH - 1) / TH : (ncx * (ncx + 1) / 2 + TH - 1) / TH;
     const size_t lds = coarse_lds_bytes(ncx, pg);
     const int64_t chunk = coarse_grid(N);  // samples per launch pair: the workspace holds their factors
     for (int64_t c = 0; c < N; c += chunk) {
       const int64_t n = N - c < chunk ? N - c : chunk;
       CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * ES, load, U + c * (int64_t)nU,
                    status ? status + c : nullptr, work};
-      const dim3 grid((unsigned)n), block(COARSE_THREADS);
-      if (pg) {
+      const dim3 grid((unsigned)n), block(TH);
+      if (small) {
+        if (pg) {
+          if (need <= 4)
+            hipLaunchKernelGGL((coarse_solve_kernel<4, true, 64>), grid, block, lds, st, a);
+          else
+            hipLaunchKernelGGL((coarse_solve_kernel<16, true, 64>), grid, block, lds, st, a);
+        } else {
+          if (need <= 2)
+            hipLaunchKernelGGL((coarse_solve_kernel<2, false, 64>), grid, block, lds, st, a);
+          else
+            hipLaunchKernelGGL((coarse_solve_kernel<9, false, 64>), grid, block, lds, st, a);
+        }
+      } else if (pg) {
         if (need <= 4)
-          hipLaunchKernelGGL((coarse_solve_kernel<4, true>), grid, block, lds, st, a);
+          hipLaunchKernelGGL((coarse_solve_kernel<4, true, COARSE_THREADS>), grid, block, lds, st, a);
         else
-          hipLaunchKernelGGL((coarse_solve_kernel<16, true>), grid, block, lds, st, a);
+          hipLaunchKernelGGL((coarse_solve_kernel<16, true, COARSE_THREADS>), grid, block, lds, st, a);
       } else {
         if (need <= 4)
-          hipLaunchKernelGGL((coarse_solve_kernel<4, false>), grid, block, lds, st, a);
+          hipLaunchKernelGGL((coarse_solve_kernel<4, false, COARSE_THREADS>), grid, block, lds, st, a);
         else
-          hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false>), grid, block, lds, st, a);
+          hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false, COARSE_THREADS>), grid, block, lds, st, a);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -472,7 +528,17 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
     }
   }
   if ((mean || var) && nU > 0) {
-    hipLaunchKernelGGL(qoi_kernel, dim3((nU + 255) / 256), dim3(256), 0, st, N, nU, U, mean, var);
+    // the partial sums reuse the workspace of the factors (idle once the
+    // backward passes, queued before on the same stream, are done):
+    // 2 nch nU <= 3 min(N, 4096) nU doubles
+    const int64_t CS = qoi_chunk(N), nch = N > 0 ? (N + CS - 1) / CS : 0;
+    if (nch > 0) {
+      hipLaunchKernelGGL(qoi_partial_kernel, dim3((unsigned)((nU + 63) / 64), (unsigned)nch), dim3(64 * QOI_TY), 0,
+                         st, N, nU, CS, U, work);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(qoi_final_kernel, dim3((nU + 255) / 256), dim3(256), 0, st, N, nU, nch, work, mean, var);
     return hipGetLastError();
   }
   return hipSuccess;
