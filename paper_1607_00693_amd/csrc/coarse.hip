@@ -30,8 +30,8 @@
 
 namespace stomsfem {
 
-constexpr int COARSE_THREADS = 256;
-constexpr int COARSE_NQ = 12;  // largest NQ: B (B+1)/2 <= 3072
+constexpr int COARSE_THREADS = 1024;
+constexpr int COARSE_NQ = 3;  // largest NQ: B (B+1)/2 <= 3072
 constexpr int COARSE_BMAX = 72;
 constexpr int COARSE_PG_BMAX = 64;
 constexpr int COARSE_SMALL_B = 32;  // largest band served by the one-wavefront workgroup  // Petrov-Galerkin: full B x B trailing square, <= 16 entries per lane
@@ -132,13 +132,16 @@ __device__ __forceinline__ BackStep back_loads(const double* Lc, int64_t zero, i
 // without pivoting (the pivot row goes to the next phase beside the pivot
 // column; the backward pass solves U x = y in the form x = z - (D^{-1} U - I) x
 // with z = D^{-1} y, the same recurrence as L^T x = D^{-1} y).
-// TH threads per workgroup: 256, or one wavefront (64) for coarse meshes with
+// TH threads per workgroup: one wavefront (64) for coarse meshes with
 // ncx <= 32, where a pivot step has too little work to amortise a
-// multi-wavefront barrier.
+// multi-wavefront barrier; 1024 above (three trailing entries per thread,
+// four wavefronts per SIMD to overlap the latency of a pivot step, which is
+// what bounds a batch of a few hundred samples with one workgroup per CU).
 template <int NQ, bool PG, int TH>
 __global__ __launch_bounds__(TH) void coarse_solve_kernel(CoarseArgs args) {
   constexpr int ES = PG ? 16 : 10;  // doubles per element matrix
   constexpr int BMX = TH == 64 ? COARSE_SMALL_B : COARSE_BMAX;
+  static_assert(TH == 64 || TH == COARSE_THREADS, "workgroup sizes");
   constexpr int NE = (BMX * ES + TH - 1) / TH;  // element-row prefetch
   extern __shared__ double smem[];
   const int ncx = args.ncx, ncy = args.ncy;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(TH) void coarse_solve_kernel(CoarseArgs args) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int io = tik[q] & 255, ko = tik[q] >> 8;
-          idx[q] = wrap(jj + 1 + io, WN) * WN + wrap(jj + 1 + ko, WN);
+          idx[q] = __umul24(wrap(jj + 1 + io, WN), WN) + wrap(jj + 1 + ko, WN);  // 24-bit: full rate
           wv[q] = (io < cnt && ko < cnt) ? Wn[idx[q]] : 0.0;
         }
 #pragma unroll
@@ -507,15 +510,9 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
             hipLaunchKernelGGL((coarse_solve_kernel<9, false, 64>), grid, block, lds, st, a);
         }
       } else if (pg) {
-        if (need <= 4)
-          hipLaunchKernelGGL((coarse_solve_kernel<4, true, COARSE_THREADS>), grid, block, lds, st, a);
-        else
-          hipLaunchKernelGGL((coarse_solve_kernel<16, true, COARSE_THREADS>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((coarse_solve_kernel<4, true, COARSE_THREADS>), grid, block, lds, st, a);
       } else {
-        if (need <= 4)
-          hipLaunchKernelGGL((coarse_solve_kernel<4, false, COARSE_THREADS>), grid, block, lds, st, a);
-        else
-          hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false, COARSE_THREADS>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false, COARSE_THREADS>), grid, block, lds, st, a);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
