@@ -15,8 +15,8 @@
 // the Chebyshev-Lobatto barycentric weights (Berrut & Trefethen 2004) with
 // the node polynomial multiplied through, so an evaluation exactly on a node
 // needs no special case and constants are reproduced exactly.  S_K is then
-// sum_c prod_i l_{d_i}(x_i) T_K[c]: the two fastest variables are unrolled,
-// the two slowest are runtime loops.
+// sum_c prod_i l_{d_i}(x_i) T_K[c]: the two fastest variables are unrolled
+// (only the fastest above five nodes), the others are runtime loops.
 #include "ri.h"
 
 namespace stomsfem {
@@ -144,6 +144,32 @@ __device__ __forceinline__ void inner_sum(const table_t* T, double w, const doub
   }
 }
 
+// Sum over the two fastest variables for NN > 5: only the fastest is
+// unrolled (NN x 10 table values per block instead of NN^2 x 10, which
+// would exceed the scalar registers and serialise the scalar loads).
+template <int NN>
+__device__ __forceinline__ void inner_sum_rows(const table_t* T, double w, const double (&c2)[NN],
+                                               const double (&c3)[NN], double (&acc)[10]) {
+  double c2r[NN];
+#pragma unroll
+  for (int q = 0; q < NN; ++q) c2r[q] = c2[q];
+#pragma unroll 1
+  for (int d2 = 0; d2 < NN; ++d2) {
+    inner_sum<NN, 1>(T + (int64_t)d2 * NN * 10, w * c2r[0], c2, c3, acc);
+    shift_down<NN>(c2r);
+  }
+}
+
+// two fastest variables: unrolled (NN <= 5) or a loop over the second
+template <int NN>
+__device__ __forceinline__ void inner_sum2(const table_t* T, double w, const double (&c2)[NN],
+                                           const double (&c3)[NN], double (&acc)[10]) {
+  if constexpr (NN > 5)  // measured: at five nodes the full unroll is 4% faster
+    inner_sum_rows<NN>(T, w, c2, c3, acc);
+  else
+    inner_sum<NN, 2>(T, w, c2, c3, acc);
+}
+
 template <int NN, int KV>
 __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_KMAX], double lo,
                                         double hi, double (&acc)[10]) {
@@ -155,12 +181,14 @@ __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_K
   if constexpr (KV >= 4) lobatto_basis<NN>(x[KV - 4], lo, hi, c0);
   constexpr int K2 = KV < 2 ? KV : 2;
   constexpr int inner = K2 == 0 ? 1 : (K2 == 1 ? NN : NN * NN);
-  if constexpr (KV <= 2) {
+  if constexpr (KV == 2) {
+    inner_sum2<NN>(T, 1.0, c2, c3, acc);
+  } else if constexpr (KV < 2) {
     inner_sum<NN, K2>(T, 1.0, c2, c3, acc);
   } else if constexpr (KV == 3) {
 #pragma unroll 1
     for (int d1 = 0; d1 < NN; ++d1) {
-      inner_sum<NN, 2>(T + (int64_t)d1 * inner * 10, c1[0], c2, c3, acc);
+      inner_sum2<NN>(T + (int64_t)d1 * inner * 10, c1[0], c2, c3, acc);
       shift_down<NN>(c1);
     }
   } else {
@@ -171,7 +199,7 @@ __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_K
       for (int q = 0; q < NN; ++q) c1r[q] = c1[q];
 #pragma unroll 1
       for (int d1 = 0; d1 < NN; ++d1) {
-        inner_sum<NN, 2>(T + (int64_t)(d0 * NN + d1) * inner * 10, c0[0] * c1r[0], c2, c3, acc);
+        inner_sum2<NN>(T + (int64_t)(d0 * NN + d1) * inner * 10, c0[0] * c1r[0], c2, c3, acc);
         shift_down<NN>(c1r);
       }
       shift_down<NN>(c0);
