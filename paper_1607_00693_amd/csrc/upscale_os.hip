@@ -385,9 +385,14 @@ static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
   return hipGetLastError();
 }
 
+bool upscale_os_tiled_supports(int m, int o);
+hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+
 hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st) {
   if (!upscale_os_supports(up.m, o)) return hipErrorInvalidValue;
   if (up.npairs == 0) return hipSuccess;
+  // 16-cell patches: the register-tiled kernel (six pairs per wavefront)
+  if (upscale_os_tiled_supports(up.m, o)) return launch_upscale_os_tiled(up, o, a_dtype, st);
   const OsArgs args{up, o};
   return a_dtype == STOMSFEM_F32 ? launch_os_t<float>(args, st) : launch_os_t<double>(args, st);
 }

@@ -67,11 +67,12 @@ def test_mesh8_matches_oracle(sm, orc, o):
 
 
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(6, 3, 5, 3, 1), (4, 2, 3, 7, 2), (16, 8, 4, 3, 1), (8, 12, 4, 4, 1),
-                                           (2, 1, 9, 2, 3)])
+                                           (2, 1, 9, 2, 3), (4, 6, 4, 5, 2), (2, 7, 9, 8, 1), (8, 4, 5, 3, 3)])
 def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
     # non-square meshes, pair counts that leave the last workgroup partly
     # empty, patches of M = 4 ... 32 (every trailing-entry count per lane),
-    # patches moved inside the domain on all four sides
+    # patches moved inside the domain on all four sides; M = 16 with three
+    # different splits m + 2o (the register-tiled kernel)
     say(f"ragged m={m} o={o} {ncx}x{ncy} N={N}")
     a_ref = W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1200 + m + o)
     a = torch.from_numpy(a_ref).cuda()
@@ -92,8 +93,9 @@ def test_float32_coefficients(sm, orc):
     assert s_relerr(S.cpu().numpy(), S_ref) <= STOL
 
 
-def test_non_positive_coefficient_sets_status(sm):
-    m, o, ncx, ncy = 4, 2, 3, 3
+@pytest.mark.parametrize("m,o", [(4, 2), (8, 4)])
+def test_non_positive_coefficient_sets_status(sm, m, o):
+    ncx, ncy = 3, 3
     a = torch.from_numpy(W.uniform_array((2, ncy * m, ncx * m), 0.5, 2.0, 1301)).cuda()
     a[1] = -a[1]
     status = torch.full((2, ncx * ncy), 99, dtype=torch.int32, device="cuda")
