@@ -12,7 +12,8 @@
 //   1. T lanes build the entering rows (stencil, lifts, tests);
 //   2. the lane holding the diagonal tile factors it, forward-substitutes
 //      the ten columns of its rows and accumulates the 21 Schur products
-//      f^jv . K_II^{-1} t (one column at a time: few registers);
+//      f^jv . K_II^{-1} t (one column at a time: few registers), in its
+//      registers for T = 4 and in the pair's LDS block for larger tiles;
 //   3. the panel rows are solved against the unit factor by the ten lanes,
 //      which also apply the panel to the rows' ten right-hand sides;
 //   4. every lane applies the rank-T update to its tile.
@@ -33,8 +34,7 @@ constexpr int OT_G = 10;                 // lanes per pair
 constexpr int OT_SLOTS = 64 / OT_G;      // pairs per wavefront (6)
 constexpr int OT_NV = 10;                // columns: lifts f^0..2, corner tests 0..3, r^0..2
 constexpr int OT_NY = 21;                // Schur products f^jv . K_II^{-1} (column 3 + tv)
-constexpr int OT_RED = OT_NY + 9 + 1;    // reduced values: Y, boundary terms, bad flag
-constexpr int OT_RW = 16;                // values per reduction round (two rounds)
+constexpr int OT_RED = 9 + 1;            // reduced over the lanes: boundary terms, bad flag
 
 struct OtArgs {
   UpArgs up;
@@ -46,8 +46,9 @@ struct OtLdsCore {
   static constexpr int NT = OT_NT, FW = NT * T;
   union {
     double pw[T][NT][T];     // panel rows: pw[k][R'][i] = W(row R'*T+i of the panel, column k)
-    double red[OT_G][OT_RW];   // final reduction (after the last panel), two rounds
+    double red[OT_G][OT_RED];  // final reduction (after the last panel)
   };
+  double Y[OT_NY];            // Schur products f^jv . K_II^{-1} t, accumulated by the diagonal lane
   double L[T * (T - 1) / 2];  // strict lower part of the unit factor of the diagonal tile
   double invd[T];             // 1 / d_k
   double fr[T][2];            // entering rows: diagonal and W couplings
@@ -134,9 +135,14 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
   constexpr double rM = 1.0 / M;
 
   double tile[T][T];
-  double Y[OT_NY];
+  // small tiles leave room for the Schur products in registers (the diagonal
+  // lane's critical path then has no LDS round trip for them); larger tiles
+  // accumulate them in LDS, one writer per panel
+  constexpr bool YR = T <= 4;
+  double Yr[YR ? OT_NY : 1];
 #pragma unroll
-  for (int t = 0; t < OT_NY; ++t) Y[t] = 0.0;
+  for (int t = 0; t < (YR ? OT_NY : 1); ++t) Yr[t] = 0.0;
+  for (int t = g; t < OT_NY; t += OT_G) sh.Y[t] = 0.0;
   bool bad = false;
 
   // coefficients of the four elements around the node of row r (patch frame)
@@ -302,6 +308,7 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
           for (int kk = 0; kk < k; ++kk) x -= tile[k][kk] * col[kk];
           col[k] = x;
         }
+        double y3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < T; ++k) {
           const double z = col[k] * sh.invd[k];
@@ -309,9 +316,18 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
             zf[k][v] = z;
           } else {
 #pragma unroll
-            for (int jv = 0; jv < 3; ++jv) Y[jv * 7 + (v - 3)] += zf[k][jv] * col[k];
+            for (int jv = 0; jv < 3; ++jv) y3[jv] += zf[k][jv] * col[k];
           }
           sh.f[(T * J + k) % FW][v] = z;
+        }
+        if (v >= 3) {
+#pragma unroll
+          for (int jv = 0; jv < 3; ++jv) {
+            if constexpr (YR)
+              Yr[jv * 7 + (v - 3)] += y3[jv];
+            else
+              sh.Y[jv * 7 + (v - 3)] += y3[jv];
+          }
         }
       }
     } else if (C == J) {
@@ -417,34 +433,37 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
     }
   }
 
-  // ---- reduce the ten lanes' partial sums (two rounds through LDS), then
+  // ---- reduce the ten lanes' boundary terms and flags through LDS, then
   //      lane 0 of the pair forms the 4x4 recombination ----
-  double vals[OT_RED], tot[OT_RED];
+  if constexpr (YR) {
+    // the diagonal lanes (P == Q) add their register sums in turn
+#pragma unroll 1
+    for (int h = 0; h < NT; ++h) {
+      if (P == Q && P == h) {
 #pragma unroll
-  for (int t = 0; t < OT_NY; ++t) vals[t] = Y[t];
+        for (int t = 0; t < OT_NY; ++t) sh.Y[t] += Yr[t];
+      }
+      OT_WAVE_SYNC();
+    }
+  }
+  double tot[OT_RED];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) vals[OT_NY + t] = bt[t];
-  vals[OT_RED - 1] = bad ? 1.0 : 0.0;
+  for (int t = 0; t < 9; ++t) sh.red[g][t] = bt[t];
+  sh.red[g][OT_RED - 1] = bad ? 1.0 : 0.0;
+  OT_WAVE_SYNC();
+  if (g == 0) {
 #pragma unroll
-  for (int rnd = 0; rnd < 2; ++rnd) {
-    OT_WAVE_SYNC();  // the previous readers of the union are done
-#pragma unroll
-    for (int t = 0; t < OT_RW; ++t)
-      if (rnd * OT_RW + t < OT_RED) sh.red[g][t] = vals[rnd * OT_RW + t];
-    OT_WAVE_SYNC();
-    if (g == 0) {
-#pragma unroll
-      for (int t = 0; t < OT_RW; ++t)
-        if (rnd * OT_RW + t < OT_RED) {
-          double v = 0.0;
-          for (int h = 0; h < OT_G; ++h) v += sh.red[h][t];
-          tot[rnd * OT_RW + t] = v;
-        }
+    for (int t = 0; t < OT_RED; ++t) {
+      double v = 0.0;
+      for (int h = 0; h < OT_G; ++h) v += sh.red[h][t];
+      tot[t] = v;
     }
   }
   if (g == 0 && valid) {
-    const double* Ys = tot;
-    const double* Bs = tot + OT_NY;
+    double Ys[OT_NY];
+#pragma unroll
+    for (int t = 0; t < OT_NY; ++t) Ys[t] = sh.Y[t];
+    const double* Bs = tot;
     const bool anybad = tot[OT_RED - 1] != 0.0;
     double Psi[4][4], A[4][4];
 #pragma unroll
@@ -525,17 +544,25 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
   }
 }
 
-bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16; }
+bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16 || m + 2 * o == 24; }
+
+template <int M, int T>
+static void launch_ot(const OtArgs& args, int a_dtype, hipStream_t st) {
+  const int64_t blocks = (args.up.npairs + OT_SLOTS - 1) / OT_SLOTS;
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL((upscale_os_tiled_kernel<M, T, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+  else
+    hipLaunchKernelGGL((upscale_os_tiled_kernel<M, T, double>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+}
 
 hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st) {
   if (!upscale_os_tiled_supports(up.m, o)) return hipErrorInvalidValue;
   if (up.npairs == 0) return hipSuccess;
   const OtArgs args{up, o};
-  const int64_t blocks = (up.npairs + OT_SLOTS - 1) / OT_SLOTS;
-  if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL((upscale_os_tiled_kernel<16, 4, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+  if (up.m + 2 * o == 16)
+    launch_ot<16, 4>(args, a_dtype, st);
   else
-    hipLaunchKernelGGL((upscale_os_tiled_kernel<16, 4, double>), dim3((unsigned)blocks), dim3(64), 0, st, args);
+    launch_ot<24, 6>(args, a_dtype, st);
   return hipGetLastError();
 }
 

@@ -67,12 +67,13 @@ def test_mesh8_matches_oracle(sm, orc, o):
 
 
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(6, 3, 5, 3, 1), (4, 2, 3, 7, 2), (16, 8, 4, 3, 1), (8, 12, 4, 4, 1),
-                                           (2, 1, 9, 2, 3), (4, 6, 4, 5, 2), (2, 7, 9, 8, 1), (8, 4, 5, 3, 3)])
+                                           (2, 1, 9, 2, 3), (4, 6, 4, 5, 2), (2, 7, 9, 8, 1), (8, 4, 5, 3, 3),
+                                           (8, 8, 4, 3, 2), (4, 10, 6, 7, 1), (6, 9, 5, 4, 1)])
 def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
     # non-square meshes, pair counts that leave the last workgroup partly
     # empty, patches of M = 4 ... 32 (every trailing-entry count per lane),
-    # patches moved inside the domain on all four sides; M = 16 with three
-    # different splits m + 2o (the register-tiled kernel)
+    # patches moved inside the domain on all four sides; M = 16 and 24 with
+    # three different splits m + 2o each (the register-tiled kernel)
     say(f"ragged m={m} o={o} {ncx}x{ncy} N={N}")
     a_ref = W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1200 + m + o)
     a = torch.from_numpy(a_ref).cuda()
@@ -93,7 +94,7 @@ def test_float32_coefficients(sm, orc):
     assert s_relerr(S.cpu().numpy(), S_ref) <= STOL
 
 
-@pytest.mark.parametrize("m,o", [(4, 2), (8, 4)])
+@pytest.mark.parametrize("m,o", [(4, 2), (8, 4), (8, 8)])
 def test_non_positive_coefficient_sets_status(sm, m, o):
     ncx, ncy = 3, 3
     a = torch.from_numpy(W.uniform_array((2, ncy * m, ncx * m), 0.5, 2.0, 1301)).cuda()
