@@ -340,6 +340,95 @@ def measure_oversampling(log, N=16384):
     return out
 
 
+def measure_collocation(log, wl=None, level=4, errors=True, plain_chunk=1024):
+    """Sparse-grid stochastic collocation with search-and-plug-in
+    dictionaries (Sec. 3.3, global SC methods; Sec. 5.1, second experiment)
+    on a bump-family mesh (default 8x8, H/h = 8, 16 uniform variables), the
+    level-`level` Smolyak Clenshaw-Curtis grid: offline dictionaries, then
+    the online stage for every collocation point (search and plug-in, coarse
+    solve, weighted quadrature) against the plain path at the same points
+    (coefficients from the node values, upscaling, coarse solve, quadrature;
+    timed on the first `plain_chunk` points and scaled to all of them when
+    there are more); the ratio is the online saving 1/R of eq. SConlinecost.
+    With `errors`: the quadrature error of the lower levels and of Monte
+    Carlo with as many samples as the level-(level-1) grid, both against the
+    level-`level` estimate."""
+    import math
+
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = wl or W.MESH8
+    fam = sm.bump_family(wl)
+    lv, nl = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, fam)
+    nU = (wl.nc - 1) ** 2
+    t0 = time.perf_counter()
+    dg, w = sm.sparse_grid(wl.nxi, level)
+    t_grid = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = sm.sc_build(wl.nc, wl.nc, wl.m, lv, fam, level, dg)
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t0
+    n = len(w)
+    dgd, wd = torch.from_numpy(dg).cuda(), torch.from_numpy(w).cuda()
+    S = torch.empty((n, wl.M, 10), dtype=torch.float64, device="cuda")
+    U = torch.empty((n, nU), dtype=torch.float64, device="cuda")
+
+    def online():
+        sm.sc_apply(model, dgd, S=S)
+        sm.coarse_solve(S, wl.nc, wl.nc, U=U)
+        return sm.quadrature(U, wd)
+
+    t_on = _timed(online)
+    mean, var = online()
+    t_apply = _timed(lambda: sm.sc_apply(model, dgd, S=S))
+    t_quad = _timed(lambda: sm.quadrature(U, wd))
+    npl = min(n, plain_chunk)
+    xi = torch.cos(math.pi * dgd[:npl].double() / 2 ** level)  # node values on [-1, 1]
+    Sp, Up = S[:npl], U[:npl]
+
+    def plain():
+        a = sm.coef_bumps(xi, wl.nfine, **wl.coef_params())
+        sm.upscale(a, wl.nc, wl.nc, wl.m, S=Sp)
+        sm.coarse_solve(Sp, wl.nc, wl.nc, U=Up)
+        return sm.quadrature(Up, wd[:npl])
+
+    t_plain = _timed(plain, reps=3) * n / npl
+    diff = float((S[:npl] - sm.sc_apply(model, dgd[:npl])).abs().max().item())  # S holds the plain S here
+    dict_rows = 0
+    for K in range(wl.M):
+        cols = [int(j) for j in lv[K][:nl[K]]]
+        dict_rows += len({tuple(r) for r in dg[:, cols].tolist()}) if cols else 1
+    out = {"workload": (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nxi} uniform variables (bump family), "
+                        f"Smolyak Clenshaw-Curtis level {level}"),
+           "points": n, "dictionary_entries": dict_rows, "grid_s": t_grid, "offline_s": t_off,
+           "online_ms": t_on * 1e3, "online_points_per_s": n / t_on, "search_plug_in_ms": t_apply * 1e3,
+           "search_plug_in_GB_per_s": n * wl.M * 80 / t_apply / 1e9, "quadrature_ms": t_quad * 1e3,
+           "plain_ms": t_plain * 1e3, "plain_timed_points": npl, "online_saving_vs_plain": t_plain / t_on,
+           "max_abs_S_diff_plug_in_vs_plain": diff,
+           "max_mean": float(mean.abs().max().item()), "max_std": float(var.clamp(min=0).sqrt().max().item())}
+    if errors:
+        err = {}
+        for L in range(1, level):
+            dl, wlv = sm.sparse_grid(wl.nxi, L)
+            dl = torch.from_numpy(dl * (2 ** level // 2 ** max(L, 1))).cuda()
+            SL = sm.sc_apply(model, dl)
+            UL, _, _ = sm.coarse_solve(SL, wl.nc, wl.nc)
+            mL, _ = sm.quadrature(UL, torch.from_numpy(wlv).cuda())
+            err[f"level_{L}"] = {"points": int(len(wlv)), "err": float(torch.linalg.norm(mL - mean).item())}
+        nmc = err[f"level_{level - 1}"]["points"]
+        xmc = torch.from_numpy(W.uniform_xi(nmc, wl.nxi, wl.seed + 77)).cuda()
+        Smc = sm.upscale(sm.coef_bumps(xmc, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+        _, mmc, _ = sm.coarse_solve(Smc, wl.nc, wl.nc)
+        err["monte_carlo"] = {"points": nmc, "err": float(torch.linalg.norm(mmc - mean).item())}
+        out["quadrature_error_vs_top_level"] = err
+    log(f"collocation: {out}")
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -598,6 +687,11 @@ def main():
         print("[bench] oversampled Petrov-Galerkin upscaling at the 8x8 mesh", file=sys.stderr, flush=True)
         out["oversampled_petrov_galerkin"] = measure_oversampling(
             lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print("[bench] sparse-grid collocation with dictionaries at the 8x8 mesh", file=sys.stderr, flush=True)
+        lg = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
+        from paper_1607_00693_amd import workloads as W
+        out["sparse_grid_collocation"] = {"mesh8_level4": measure_collocation(lg, plain_chunk=1 << 20),
+                                          "bench_mesh_level2": measure_collocation(lg, W.MESH32, 2, errors=False)}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

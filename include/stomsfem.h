@@ -374,6 +374,59 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
                           int32_t* status, int64_t* nfallback, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Sparse-grid stochastic collocation with search-and-plug-in dictionaries
+ * (Sec. 3.3, global SC methods: eq. sparseintegration, the variance formula
+ * after it, eqs. SCofflinecost and SConlinecost; Sec. 5.1, second
+ * experiment).  The random variables are independent and uniform on a box.
+ *
+ * stomsfem_sparse_grid (host only, needs no GPU): the Smolyak sparse grid
+ * of level `level` (0..8) in `dim` variables built from the nested
+ * Clenshaw-Curtis rules (level 1: the midpoint; level i >= 2: 2^(i-1) + 1
+ * points cos(pi j / 2^(i-1)) with the classical Clenshaw-Curtis weights),
+ * with weights for the uniform probability measure (they sum to 1; some
+ * are negative).  Points are integer digits c in 0..D, D = 2^max(level, 1),
+ * standing for the node value lo + (cos(pi c / D) + 1)(hi - lo)/2 of the box
+ * [lo, hi]; rows are in lexicographic order of the digits.  *npoints always
+ * receives the number of points; with digits and weights both NULL nothing
+ * else is written, otherwise digits (host [npoints][dim], may be NULL) and
+ * weights (host [npoints], may be NULL) are filled and capacity must be at
+ * least *npoints.  EINVAL for bad sizes or more than 2e6 terms in the
+ * combination formula (binom(dim + level, level)).
+ *
+ * stomsfem_sc_build (offline): for the collocation points digits (host
+ * [npoints][g*g], level `level`, box [lo, hi]) and the patches' local
+ * variables (local_vars host [M][4] as for stomsfem_interp_build), the
+ * dictionary of every patch K: its distinct local points (the points'
+ * digits at K's local variables) and S_K at each, computed on the GPU by the
+ * plain path (bump family `fam`, local variables at their node values, every
+ * other variable 0, which does not change a on K).  1 <= m <= 48.  The
+ * model owns its device memory (stomsfem_model_free); it cannot be saved.
+ * Synchronises `stream`.  ENOTSPD if a cell problem fails.
+ *
+ * stomsfem_sc_apply (online search and plug-in): S device [npoints][M][10]
+ * for digits device [npoints][nxi] (nxi >= g*g, the same level): every
+ * (point, patch) looks its local point up in the patch's dictionary by
+ * bisection and copies the stored S_K.  status device [npoints][M] or NULL:
+ * 0 = found, 1 = the local point is not in the dictionary (S set to NaN).
+ * Asynchronous on `stream`.
+ *
+ * stomsfem_quadrature: the collocation estimates mean[i] = sum_p w_p U[p][i]
+ * and var[i] = sum_p w_p U[p][i]^2 - mean[i]^2 for U device [npoints][nu]
+ * and weights w device [npoints]; mean, var device [nu] (either may be
+ * NULL).  Summation in a fixed order (bitwise reproducible).  Uses the
+ * library workspace; asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+int stomsfem_sparse_grid(int32_t dim, int32_t level, int64_t capacity, int64_t* npoints, int32_t* digits,
+                         double* weights);
+int stomsfem_sc_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                      const stomsfem_bump_family* fam, int32_t level, double lo, double hi, const int32_t* digits,
+                      int64_t npoints, stomsfem_model** model, void* stream);
+int stomsfem_sc_apply(const stomsfem_model* model, const int32_t* digits, int32_t nxi, int64_t npoints, double* S,
+                      int32_t* status, void* stream);
+int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32_t nu, double* mean, double* var,
+                        void* stream);
+
+/* ------------------------------------------------------------------------
  * Execution plans.  A stage is one batch of samples taken through the whole
  * path: coefficient generation from xi, local upscaling (FP64), coarse
  * assembly and solve with the Petrov-Galerkin load for f = 1, and the Monte
@@ -470,7 +523,8 @@ typedef struct {
 
 int stomsfem_model_save(const stomsfem_model* model, const char* path);
 int stomsfem_model_load(const char* path, stomsfem_model** model);
-/* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation;
+/* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
+ * 4 = sparse-grid collocation dictionaries;
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

@@ -18,6 +18,7 @@
 #include "mlp.h"
 #include "ri.h"
 #include "mixed.h"
+#include "sc.h"
 
 namespace stomsfem {
 hipError_t launch_upscale_small(const UpArgs& args, int a_dtype, hipStream_t st, int block);
@@ -221,6 +222,10 @@ struct stomsfem_model {
   int64_t* pairs = nullptr;   // [chunk]
   double* Sc = nullptr;       // [chunk][10]
   int32_t* stc = nullptr;     // [chunk]
+  // sparse-grid collocation dictionaries (kind 4): rows, off, nlv, lv, table
+  // as above; keys of the local points, increasing within each patch
+  int64_t* keys = nullptr;    // [rows]
+  int32_t sc_level = 0;
 };
 
 namespace {
@@ -255,6 +260,7 @@ void model_release(stomsfem_model* md) {
   hipFree(md->pairs);
   hipFree(md->Sc);
   hipFree(md->stc);
+  hipFree(md->keys);
   hipSetDevice(cur);
   delete md;
 }
@@ -1117,6 +1123,204 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
   g_interp_pairs += (uint64_t)need;
   g_interp_fallbacks += n;
   return ri_plain_pairs(model, model->list, (int64_t)n, xi, nxi, S, status, 1, st);
+}
+
+// ---------------------------------------------------------------------------
+// sparse-grid collocation with search-and-plug-in dictionaries
+// ---------------------------------------------------------------------------
+int stomsfem_sparse_grid(int32_t dim, int32_t level, int64_t capacity, int64_t* npoints, int32_t* digits,
+                         double* weights) {
+  if (!npoints) return fail(STOMSFEM_EINVAL, "sparse_grid: NULL npoints");
+  *npoints = 0;
+  if (dim < 1 || level < 0 || level > SC_LEVEL_MAX)
+    return fail(STOMSFEM_EINVAL, "sparse_grid: need dim >= 1 and 0 <= level <= 8");
+  if (sc_term_count(dim, level, 2000000) > 2000000)
+    return fail(STOMSFEM_EINVAL, "sparse_grid: more than 2e6 terms in the combination formula");
+  std::vector<int32_t> dg;
+  std::vector<double> w;
+  sc_build_grid(dim, level, dg, w);
+  *npoints = (int64_t)w.size();
+  if (!digits && !weights) return STOMSFEM_OK;
+  if (capacity < *npoints) return fail(STOMSFEM_EINVAL, "sparse_grid: capacity smaller than the number of points");
+  if (digits) std::memcpy(digits, dg.data(), sizeof(int32_t) * dg.size());
+  if (weights) std::memcpy(weights, w.data(), sizeof(double) * w.size());
+  return STOMSFEM_OK;
+}
+
+int stomsfem_sc_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                      const stomsfem_bump_family* fam, int32_t level, double lo, double hi, const int32_t* digits,
+                      int64_t npoints, stomsfem_model** model, void* stream) {
+  if (!local_vars || !fam || !model || !digits) return fail(STOMSFEM_EINVAL, "sc_build: NULL argument");
+  *model = nullptr;
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 48) return fail(STOMSFEM_EINVAL, "sc_build: need 1 <= m <= 48");
+  if (level < 0 || level > SC_LEVEL_MAX) return fail(STOMSFEM_EINVAL, "sc_build: need 0 <= level <= 8");
+  if (npoints < 1) return fail(STOMSFEM_EINVAL, "sc_build: need at least one collocation point");
+  if (!(lo < hi)) return fail(STOMSFEM_EINVAL, "sc_build: need lo < hi");
+  if (fam->g < 1 || !(fam->rho > 0) || !(fam->eps > 0)) return fail(STOMSFEM_EINVAL, "sc_build: bad family");
+  const int Mc = ncx * ncy, nxi = fam->g * fam->g, D = sc_digit_base(level);
+  for (int64_t i = 0; i < npoints * nxi; ++i)
+    if (digits[i] < 0 || digits[i] > D) return fail(STOMSFEM_EINVAL, "sc_build: a digit is outside 0..2^max(level,1)");
+  std::vector<int32_t> nlv(Mc);
+  std::vector<int64_t> off(Mc + 1, 0), keys;
+  for (int K = 0; K < Mc; ++K) {
+    int k = 0;
+    while (k < RI_KMAX && local_vars[K * RI_KMAX + k] >= 0) ++k;
+    for (int i = 0; i < RI_KMAX; ++i) {
+      const int32_t j = local_vars[K * RI_KMAX + i];
+      if ((i < k && j >= nxi) || (i >= k && j != -1))
+        return fail(STOMSFEM_EINVAL, "sc_build: local variables must be < g*g, -1 padded at the end");
+      if (i > 0 && i < k && j <= local_vars[K * RI_KMAX + i - 1])
+        return fail(STOMSFEM_EINVAL, "sc_build: local variables of a patch must be increasing");
+    }
+    nlv[K] = k;
+    // search structure: the distinct local points of K, as sorted keys
+    std::vector<int64_t> kk((size_t)npoints);
+    for (int64_t p = 0; p < npoints; ++p) {
+      int64_t key = 0;
+      for (int i = 0; i < k; ++i) key = key * (D + 1) + digits[p * nxi + local_vars[K * RI_KMAX + i]];
+      kk[(size_t)p] = key;
+    }
+    std::sort(kk.begin(), kk.end());
+    kk.erase(std::unique(kk.begin(), kk.end()), kk.end());
+    keys.insert(keys.end(), kk.begin(), kk.end());
+    off[K + 1] = (int64_t)keys.size();
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 4;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->fam = *fam;
+  md->lo = lo;
+  md->hi = hi;
+  md->sc_level = level;
+  md->rows = off[Mc];
+  md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->keys, sizeof(int64_t) * (size_t)md->rows);
+  A((void**)&md->table, sizeof(double) * (size_t)md->rows * 10);
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+  A((void**)&md->xin, sizeof(double) * (size_t)md->chunk * nxi);
+  A((void**)&md->pairs, sizeof(int64_t) * (size_t)md->chunk);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "sc_build: device allocation failed");
+  }
+  e = hipMemcpy(md->lv, local_vars, sizeof(int32_t) * Mc * RI_KMAX, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->keys, keys.data(), sizeof(int64_t) * keys.size(), hipMemcpyHostToDevice);
+  // offline stage: S_K at every dictionary entry by the plain path, with the
+  // local variables at their node values and every other variable 0
+  std::vector<double> node(D + 1);
+  for (int c = 0; c <= D; ++c) node[c] = lo + (std::cos(M_PI * (double)c / (double)D) + 1.0) * 0.5 * (hi - lo);
+  std::vector<double> xh;
+  std::vector<int64_t> ph;
+  std::vector<int32_t> sth;
+  int bad = 0, K = 0;
+  for (int64_t start = 0; e == hipSuccess && start < md->rows; start += md->chunk) {
+    const int64_t cnt = std::min(md->chunk, md->rows - start);
+    xh.assign((size_t)cnt * nxi, 0.0);
+    ph.resize(cnt);
+    for (int64_t i = 0; i < cnt; ++i) {
+      const int64_t row = start + i;
+      while (off[K + 1] <= row) ++K;
+      int64_t key = keys[row];
+      for (int v = nlv[K] - 1; v >= 0; --v) {
+        xh[(size_t)i * nxi + local_vars[K * RI_KMAX + v]] = node[key % (D + 1)];
+        key /= (D + 1);
+      }
+      ph[i] = i * Mc + K;
+    }
+    e = hipMemcpyAsync(md->xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(md->pairs, ph.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    RegenArgs r{};
+    r.ncx = ncx;
+    r.ncy = ncy;
+    r.m = m;
+    r.nxi = nxi;
+    r.bp = bump_params(*fam);
+    r.pairs = md->pairs;
+    r.count = cnt;
+    r.xi = md->xin;
+    r.out = md->blk;
+    e = launch_regen_blocks(r, st);
+    if (e != hipSuccess) break;
+    UpArgs u{};
+    u.nsamples = cnt;
+    u.ncx = u.ncy = 1;
+    u.m = m;
+    u.npairs = cnt;
+    u.a = md->blk;
+    u.S = md->table + start * 10;
+    u.status = md->stc;
+    e = launch_upscale_any(u, STOMSFEM_F64, st);
+    if (e != hipSuccess) break;
+    sth.resize(cnt);
+    e = hipMemcpyAsync(sth.data(), md->stc, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // also keeps xh, ph alive for the copies
+    for (int64_t i = 0; e == hipSuccess && i < cnt; ++i) bad |= sth[i] != 0;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "sc_build");
+  }
+  if (bad) {
+    model_release(md);
+    return fail(STOMSFEM_ENOTSPD, "sc_build: a cell problem at a collocation point is not positive definite");
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_sc_apply(const stomsfem_model* model, const int32_t* digits, int32_t nxi, int64_t npoints, double* S,
+                      int32_t* status, void* stream) {
+  if (!model || model->kind != 4) return fail(STOMSFEM_EINVAL, "sc_apply: not a collocation model");
+  if (npoints < 0 || nxi < model->fam.g * model->fam.g)
+    return fail(STOMSFEM_EINVAL, "sc_apply: npoints < 0 or nxi smaller than the family's g*g");
+  if (npoints == 0) return STOMSFEM_OK;
+  if (!device_ptr(digits) || !device_ptr(S)) return fail(STOMSFEM_EINVAL, "sc_apply: digits and S must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "sc_apply: status must be a device pointer");
+  ScApplyArgs a{};
+  a.npatch = model->ncx * model->ncy;
+  a.nxi = nxi;
+  a.D = sc_digit_base(model->sc_level);
+  a.npoints = npoints;
+  a.digits = digits;
+  a.lv = model->lv;
+  a.nlv = model->nlv;
+  a.off = model->off;
+  a.keys = model->keys;
+  a.table = model->table;
+  a.S = S;
+  a.status = status;
+  hipError_t e = launch_sc_apply(a, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "sc_apply launch");
+}
+
+int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32_t nu, double* mean, double* var,
+                        void* stream) {
+  if (npoints < 1 || nu < 1) return fail(STOMSFEM_EINVAL, "quadrature: need npoints >= 1 and nu >= 1");
+  if (!device_ptr(U) || !device_ptr(w)) return fail(STOMSFEM_EINVAL, "quadrature: U and w must be device pointers");
+  if ((mean && !device_ptr(mean)) || (var && !device_ptr(var)))
+    return fail(STOMSFEM_EINVAL, "quadrature: mean and var must be device pointers");
+  void* work = nullptr;
+  int rc = workspace_get(sizeof(double) * (size_t)sc_quad_work_doubles(npoints, nu), &work);
+  if (rc != STOMSFEM_OK) return rc;
+  hipError_t e = launch_sc_quadrature(U, w, npoints, nu, mean, var, (double*)work, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "quadrature launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,233 @@
+// Sparse-grid stochastic collocation with search-and-plug-in dictionaries
+// (Sec. 3.3, global SC methods, eqs. sparseintegration, SCofflinecost,
+// SConlinecost).
+//
+// Host: the Smolyak combination of nested Clenshaw-Curtis rules.  The
+// level-i rule has n_i = 1 (i = 1, the midpoint) or 2^(i-1) + 1 points
+// cos(pi j / N), N = n_i - 1, with the classical weights
+//   w_j = (c_j / N) (1 - sum_{k=1}^{N/2} b_k cos(2 pi k j / N) / (4k^2 - 1)),
+// c_j = 1 at the ends and 2 inside, b_k = 1 at k = N/2 and 2 below (for the
+// integral over [-1, 1]; halved here for the uniform probability measure).
+// A(L, d) is the sum over multi-indices i >= 1 with max(0, L-d+1) <= |i|-d
+// <= L of (-1)^(L+d-|i|) binom(d-1, L+d-|i|) times the tensor rule; the
+// rules are nested, so each tensor point is a point of the finest grid of
+// the level (digit c <-> cos(pi c / D), D = 2^max(L, 1)) and its weights
+// from every term add up.
+//
+// Device, online stage: sc_apply_kernel, one thread per (point, patch):
+// the local point's key (the point's digits at the patch's local variables
+// in mixed radix D + 1) is searched by bisection among the patch's sorted
+// dictionary keys and the stored S_K is copied out (80 B written per pair).
+// sc_quad_*: the weighted sums of U and U^2 over the points, in chunks of
+// points (64 unknowns per workgroup, four wavefronts over the chunk's
+// points, combined in order), then the chunks in order: a fixed order.
+#include "sc.h"
+
+#include <cmath>
+#include <map>
+
+namespace stomsfem {
+
+int64_t sc_term_count(int dim, int level, int64_t cap) {
+  // binom(dim + level, level) by the product formula, saturated
+  double b = 1.0;
+  for (int r = 1; r <= level; ++r) {
+    b = b * (double)(dim + r) / (double)r;
+    if (b > (double)cap) return cap + 1;
+  }
+  return (int64_t)std::llround(b);
+}
+
+static void cc_rule(int i, int D, std::vector<int32_t>& dig, std::vector<double>& w) {
+  dig.clear();
+  w.clear();
+  if (i == 1) {
+    dig.push_back(D / 2);
+    w.push_back(1.0);
+    return;
+  }
+  const int N = 1 << (i - 1);
+  for (int j = 0; j <= N; ++j) {
+    double s = 0.0;
+    for (int k = 1; k <= N / 2; ++k) {
+      const double bk = (k == N / 2) ? 1.0 : 2.0;
+      s += bk * std::cos(2.0 * M_PI * (double)k * (double)j / (double)N) / (4.0 * k * k - 1.0);
+    }
+    const double cj = (j == 0 || j == N) ? 1.0 : 2.0;
+    dig.push_back(j * (D / N));
+    w.push_back(0.5 * cj / N * (1.0 - s));
+  }
+}
+
+static int64_t binom64(int n, int r) {
+  int64_t b = 1;
+  for (int k = 1; k <= r; ++k) b = b * (n - r + k) / k;
+  return b;
+}
+
+void sc_build_grid(int dim, int level, std::vector<int32_t>& digits, std::vector<double>& weights) {
+  const int D = sc_digit_base(level);
+  std::vector<std::vector<int32_t>> rd(level + 2);
+  std::vector<std::vector<double>> rw(level + 2);
+  for (int i = 1; i <= level + 1; ++i) cc_rule(i, D, rd[i], rw[i]);
+  std::map<std::vector<int32_t>, double> acc;
+  std::vector<int> idx(dim, 1);
+  std::vector<int32_t> pt(dim);
+  std::vector<int> pos(dim);
+  const int lo_extra = level - dim + 1 > 0 ? level - dim + 1 : 0;
+  // every multi-index with sum(i_k - 1) <= level, by a recursive walk
+  auto visit = [&](int extra) {
+    if (extra < lo_extra) return;
+    const double c = ((level - extra) % 2 ? -1.0 : 1.0) * (double)binom64(dim - 1, level - extra);
+    // tensor product of the rules idx[0..dim-1]
+    for (int k = 0; k < dim; ++k) pos[k] = 0;
+    while (true) {
+      double wt = c;
+      for (int k = 0; k < dim; ++k) {
+        pt[k] = rd[idx[k]][pos[k]];
+        wt *= rw[idx[k]][pos[k]];
+      }
+      acc[pt] += wt;
+      int k = dim - 1;
+      while (k >= 0 && ++pos[k] == (int)rd[idx[k]].size()) pos[k--] = 0;
+      if (k < 0) break;
+    }
+  };
+  // depth-first over dimensions distributing the extra levels
+  auto rec = [&](auto&& self, int k, int used) -> void {
+    if (k == dim) {
+      visit(used);
+      return;
+    }
+    for (int e = 0; used + e <= level; ++e) {
+      idx[k] = 1 + e;
+      self(self, k + 1, used + e);
+    }
+    idx[k] = 1;
+  };
+  rec(rec, 0, 0);
+  digits.clear();
+  weights.clear();
+  digits.reserve(acc.size() * (size_t)dim);
+  weights.reserve(acc.size());
+  for (const auto& kv : acc) {
+    digits.insert(digits.end(), kv.first.begin(), kv.first.end());
+    weights.push_back(kv.second);
+  }
+}
+
+__global__ __launch_bounds__(256) void sc_apply_kernel(ScApplyArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.npoints * a.npatch) return;
+  const int64_t p = t / a.npatch;
+  const int K = (int)(t - p * a.npatch);
+  const int k = a.nlv[K];
+  const int32_t* dg = a.digits + p * a.nxi;
+  int64_t key = 0;
+  bool ok = true;
+  for (int i = 0; i < k; ++i) {
+    const int32_t c = dg[a.lv[K * 4 + i]];
+    ok = ok && c >= 0 && c <= a.D;
+    key = key * (a.D + 1) + c;
+  }
+  int64_t lo = a.off[K], hi = a.off[K + 1] - 1, row = -1;
+  while (ok && lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int64_t km = a.keys[mid];
+    if (km == key) {
+      row = mid;
+      break;
+    }
+    if (km < key) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  double* out = a.S + t * 10;
+  if (row >= 0) {
+    const double* src = a.table + row * 10;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) out[q] = src[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) out[q] = __builtin_nan("");
+  }
+  if (a.status) a.status[t] = row >= 0 ? 0 : 1;
+}
+
+hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
+  const int64_t n = a.npoints * a.npatch;
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sc_apply_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+static int64_t quad_chunk(int64_t npoints) {
+  int64_t ch = 256;
+  while ((npoints + ch - 1) / ch > 65535) ch *= 2;
+  return ch;
+}
+
+int64_t sc_quad_work_doubles(int64_t npoints, int nu) {
+  const int64_t ch = quad_chunk(npoints);
+  return ((npoints + ch - 1) / ch) * (int64_t)nu * 2;
+}
+
+__global__ __launch_bounds__(256) void sc_quad_partial_kernel(const double* __restrict__ U,
+                                                              const double* __restrict__ w, int64_t npoints, int nu,
+                                                              int64_t ch, double* __restrict__ work) {
+  __shared__ double red[4][64][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int64_t c = blockIdx.y;
+  const int64_t p0 = c * ch, p1 = p0 + ch < npoints ? p0 + ch : npoints;
+  double s1 = 0.0, s2 = 0.0;
+  if (i < nu) {
+    for (int64_t p = p0 + wv; p < p1; p += 4) {
+      const double u = U[p * nu + i], wp = w[p];
+      s1 += wp * u;
+      s2 += wp * u * u;
+    }
+  }
+  red[wv][lane][0] = s1;
+  red[wv][lane][1] = s2;
+  __syncthreads();
+  if (wv == 0 && i < nu) {
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      t1 += red[v][lane][0];
+      t2 += red[v][lane][1];
+    }
+    work[(c * nu + i) * 2] = t1;
+    work[(c * nu + i) * 2 + 1] = t2;
+  }
+}
+
+__global__ __launch_bounds__(64) void sc_quad_final_kernel(const double* __restrict__ work, int64_t nchunks, int nu,
+                                                           double* __restrict__ mean, double* __restrict__ var) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= nu) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    s1 += work[(c * nu + i) * 2];
+    s2 += work[(c * nu + i) * 2 + 1];
+  }
+  if (mean) mean[i] = s1;
+  if (var) var[i] = s2 - s1 * s1;
+}
+
+hipError_t launch_sc_quadrature(const double* U, const double* w, int64_t npoints, int nu, double* mean, double* var,
+                                double* work, hipStream_t st) {
+  const int64_t ch = quad_chunk(npoints);
+  const int64_t nchunks = (npoints + ch - 1) / ch;
+  const unsigned bx = (unsigned)((nu + 63) / 64);
+  hipLaunchKernelGGL(sc_quad_partial_kernel, dim3(bx, (unsigned)nchunks), dim3(256), 0, st, U, w, npoints, nu, ch,
+                     work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sc_quad_final_kernel, dim3(bx), dim3(64), 0, st, work, nchunks, nu, mean, var);
+  return hipGetLastError();
+}
+
+}  // namespace stomsfem

@@ -118,6 +118,11 @@ def lib():
         "stomsfem_interp_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl,
                                             C.POINTER(vp), vp]),
         "stomsfem_interp_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
+        "stomsfem_sparse_grid": (C.c_int, [i32, i32, i64, C.POINTER(i64), vp, vp]),
+        "stomsfem_sc_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl, vp, i64,
+                                        C.POINTER(vp), vp]),
+        "stomsfem_sc_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, vp]),
+        "stomsfem_quadrature": (C.c_int, [vp, vp, i64, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -440,6 +445,61 @@ def interp_apply(model: Model, xi: torch.Tensor, S: torch.Tensor | None = None, 
     _check("stomsfem_interp_apply", lib().stomsfem_interp_apply(
         model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), C.byref(nfb), _stream(stream)))
     return S, nfb.value
+
+
+def sparse_grid(dim: int, level: int):
+    """Smolyak Clenshaw-Curtis grid (host): (digits int32 [n][dim], weights [n])."""
+    import numpy as np
+
+    n = C.c_int64(0)
+    _check("stomsfem_sparse_grid", lib().stomsfem_sparse_grid(dim, level, 0, C.byref(n), None, None))
+    dg = np.zeros((n.value, dim), dtype=np.int32)
+    w = np.zeros(n.value, dtype=np.float64)
+    _check("stomsfem_sparse_grid", lib().stomsfem_sparse_grid(
+        dim, level, n.value, C.byref(n), dg.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
+    return dg, w
+
+
+def sc_build(ncx: int, ncy: int, m: int, lv, fam: BumpFamily, level: int, digits, lo: float = -1.0,
+             hi: float = 1.0, stream=None) -> Model:
+    """Offline dictionaries of S at the distinct local collocation points of
+    every patch for the collocation points `digits` (host int32 [n][g*g])."""
+    import numpy as np
+
+    lv = np.ascontiguousarray(lv, dtype=np.int32)
+    assert lv.shape == (ncx * ncy, MLP_KIN)
+    dg = np.ascontiguousarray(digits, dtype=np.int32)
+    h = C.c_void_p()
+    _check("stomsfem_sc_build", lib().stomsfem_sc_build(
+        ncx, ncy, m, lv.ctypes.data_as(C.c_void_p), C.byref(fam), level, lo, hi, dg.ctypes.data_as(C.c_void_p),
+        dg.shape[0], C.byref(h), _stream(stream)))
+    return Model(h, ncx, ncy, m)
+
+
+def sc_apply(model: Model, digits: torch.Tensor, S: torch.Tensor | None = None, status: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """Online search and plug-in: S [n][M][10] for digits (device int32 [n][nxi])."""
+    assert digits.dtype == torch.int32 and digits.is_contiguous()
+    n = digits.shape[0]
+    if S is None:
+        S = torch.empty((n, model.ncx * model.ncy, 10), dtype=torch.float64, device=digits.device)
+    _check("stomsfem_sc_apply", lib().stomsfem_sc_apply(
+        model.handle, _ptr(digits), digits.shape[1], n, _ptr(S), _ptr(status), _stream(stream)))
+    return S
+
+
+def quadrature(U: torch.Tensor, w: torch.Tensor, mean: torch.Tensor | None = None, var: torch.Tensor | None = None,
+               stream=None):
+    """Collocation estimates (sum_p w_p U_p, sum_p w_p U_p^2 - mean^2)."""
+    assert U.dtype == torch.float64 and w.dtype == torch.float64 and U.is_contiguous()
+    n, nu = U.shape
+    if mean is None:
+        mean = torch.empty(nu, dtype=torch.float64, device=U.device)
+    if var is None:
+        var = torch.empty(nu, dtype=torch.float64, device=U.device)
+    _check("stomsfem_quadrature", lib().stomsfem_quadrature(_ptr(U), _ptr(w), n, nu, _ptr(mean), _ptr(var),
+                                                           _stream(stream)))
+    return mean, var
 
 
 def feature_map(nfine: int, kind: torch.Tensor, x0: torch.Tensor, y0: torch.Tensor, size: torch.Tensor,
