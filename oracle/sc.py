@@ -159,3 +159,81 @@ def sc_direct(nc: int, m: int, fam: dict, digits: np.ndarray, level: int, lo: fl
     if np.any(st != 0):
         raise RuntimeError("plain solve failed at a collocation point")
     return S
+
+
+# ---------------------------------------------------------------------------
+# Sparse-grid interpolation of S_K in the local variables (Sec. 3.1 with the
+# sparse node sets of Sec. 3.3 and Sec. 5.3): Smolyak's combination of tensor
+# Lagrange interpolants on the nested Clenshaw-Curtis nodes,
+#   I(L, k) f = sum over the terms of A(L, k) of c_i (U_i1 x ... x U_ik) f,
+# U_i the one-dimensional Lagrange interpolant through the level-i nodes
+# (level 1: the constant through the midpoint).  Its nodes are the points
+# of the level-L sparse grid in k variables.
+# ---------------------------------------------------------------------------
+def level_nodes(i: int) -> np.ndarray:
+    """The level-i nested Clenshaw-Curtis nodes on [-1, 1]: cos(pi j / (n-1))."""
+    return cc_rule(i)[0]
+
+
+def smolyak_interp(values: dict, k: int, level: int, t: np.ndarray) -> np.ndarray:
+    """The Smolyak interpolant at the points t [N][k] (coordinates on
+    [-1, 1]) of nodal values `values` {digits tuple: array [E]} on the
+    level-`level` grid in k variables; [N][E]."""
+    t = np.atleast_2d(np.asarray(t, dtype=np.float64))
+    N = t.shape[0]
+    D = digit_base(level)
+    E = len(next(iter(values.values())))
+    out = np.zeros((N, E))
+    if k == 0:
+        return out + values[()][None, :]
+    for c, idx in smolyak_terms(k, level):
+        bases = []
+        digs = []
+        for d, i in enumerate(idx):
+            nodes = level_nodes(i)
+            bases.append(ri.lagrange_basis(t[:, d], nodes) if len(nodes) > 1 else np.ones((N, 1)))
+            n = len(nodes)
+            digs.append([D // 2] if n == 1 else [j * D // (n - 1) for j in range(n)])
+        for js in itertools.product(*[range(len(g)) for g in digs]):
+            w = np.full(N, float(c))
+            for d, j in enumerate(js):
+                w = w * bases[d][:, j]
+            out += w[:, None] * values[tuple(digs[d][j] for d, j in enumerate(js))][None, :]
+    return out
+
+
+def sgi_offline(nc: int, m: int, fam: dict, local_vars: list[list[int]], level: int, lo: float = -1.0,
+                hi: float = 1.0) -> dict:
+    """Per patch K with k local variables: S_K at the level-`level` sparse
+    grid in k variables (plain cell solves, non-local variables 0)."""
+    nxi = fam["g"] ** 2
+    tables = {}
+    for K, lv in enumerate(local_vars):
+        dg, _ = sparse_grid(len(lv), level) if lv else (np.zeros((1, 0), dtype=np.int64), None)
+        xs = np.zeros((len(dg), nxi))
+        for i, j in enumerate(lv):
+            xs[:, j] = node_values(dg[:, i], level, lo, hi)
+        S = ri.patch_S(xs, K, nc, m, fam)
+        tables[K] = {tuple(int(v) for v in row): S[r] for r, row in enumerate(dg)}
+    return dict(tables=tables, local_vars=local_vars, level=level, lo=lo, hi=hi)
+
+
+def sgi_online(model: dict, xi: np.ndarray, nc: int, m: int, fam: dict):
+    """S [N][M][10] and the fallback mask [N][M]: the interpolant where every
+    local variable lies in [lo, hi], the plain path elsewhere."""
+    xi = np.atleast_2d(xi)
+    N, M = xi.shape[0], nc * nc
+    lo, hi = model["lo"], model["hi"]
+    S = np.zeros((N, M, 10))
+    fb = np.zeros((N, M), dtype=bool)
+    for K in range(M):
+        lv = model["local_vars"][K]
+        x = xi[:, lv]
+        inside = np.all((x >= lo) & (x <= hi), axis=1)
+        if np.any(inside):
+            t = 2.0 * (x[inside] - lo) / (hi - lo) - 1.0
+            S[inside, K] = smolyak_interp(model["tables"][K], len(lv), model["level"], t)
+        if np.any(~inside):
+            S[~inside, K] = ri.patch_S(xi[~inside], K, nc, m, fam)
+        fb[:, K] = ~inside
+    return S, fb

@@ -5,7 +5,10 @@ Clenshaw-Curtis weights, hand-derived small grids (tests/golden), the point
 counts that follow from the numbers of new points per nested level, exact
 integration of polynomials of total degree <= 2L + 1 (Novak and Ritter), the
 plain path at every collocation point, and a Monte Carlo estimate of the
-same expectation."""
+same expectation; and of the sparse-grid interpolant in the local variables:
+nodal reproduction, the Smolyak polynomial space, the one-variable Lagrange
+interpolant, convergence beyond the tensor grid, and the plain path outside
+the box."""
 import os
 
 import numpy as np
@@ -139,3 +142,91 @@ def test_collocation_converges_to_the_expectation():
     se = U.std(axis=0) / np.sqrt(N)
     assert np.all(np.abs(U.mean(axis=0) - means[4]) < 4.5 * se)
     assert err[2] < 0.1 * se.max()
+
+
+# ---- sparse-grid interpolation in the local variables ----
+@pytest.mark.parametrize("k,level", [(1, 3), (2, 3), (3, 2), (4, 2)])
+def test_interpolant_reproduces_nodal_values(k, level):
+    # nested nodes: the Smolyak interpolant is an interpolant
+    dg, _ = sc.sparse_grid(k, level)
+    rng = np.random.default_rng(k * 10 + level)
+    vals = {tuple(int(v) for v in r): rng.normal(size=3) for r in dg}
+    t = np.cos(np.pi * dg / sc.digit_base(level))
+    got = sc.smolyak_interp(vals, k, level, t)
+    np.testing.assert_allclose(got, [vals[tuple(int(v) for v in r)] for r in dg], rtol=0, atol=1e-13)
+
+
+def _min_level(a):
+    # lowest nested level whose node count exceeds the degree a
+    i = 1
+    while sc.cc_npoints(i) - 1 < a:
+        i += 1
+    return i
+
+
+@pytest.mark.parametrize("k,level", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_interpolant_polynomial_exactness(k, level):
+    # exact on x^a whenever sum_d (level(a_d) - 1) <= L, the Smolyak space
+    # (Barthelmann, Novak and Ritter); not exact just outside it
+    import itertools
+    dg, _ = sc.sparse_grid(k, level)
+    X = np.cos(np.pi * dg / sc.digit_base(level))
+    t = np.random.default_rng(3).uniform(-1, 1, size=(40, k))
+    for a in itertools.product(range(10), repeat=k):
+        need = sum(_min_level(ad) - 1 for ad in a)
+        if need > level + 1:
+            continue
+        vals = {tuple(int(v) for v in r): np.array([np.prod(x ** np.array(a))]) for r, x in zip(dg, X)}
+        err = np.abs(sc.smolyak_interp(vals, k, level, t)[:, 0] - np.prod(t ** np.array(a), axis=1)).max()
+        if need <= level:
+            assert err < 1e-12, (a, err)
+        elif sum(a) == max(a):  # one variable of too high a degree
+            assert err > 1e-6, (a, err)
+
+
+def test_one_variable_is_the_lagrange_interpolant_on_the_finest_nodes():
+    dg, _ = sc.sparse_grid(1, 3)
+    x = np.cos(np.pi * dg[:, 0] / 8)
+    f = np.exp(x) * np.sin(3 * x)
+    vals = {(int(d),): np.array([v]) for d, v in zip(dg[:, 0], f)}
+    t = np.linspace(-1, 1, 37)
+    ref = np.polyval(np.polyfit(x, f, len(x) - 1), t)
+    np.testing.assert_allclose(sc.smolyak_interp(vals, 1, 3, t[:, None])[:, 0], ref, rtol=0, atol=1e-12)
+
+
+def test_interpolant_of_the_patch_stiffness_converges_faster_than_the_tensor_grid():
+    # a patch with four local variables of the 8x8 mesh: level 4 (401 nodes)
+    # beats the 5^4 = 625-node tensor interpolant, and levels 2..5 converge
+    from oracle import ri
+    wl = W.MESH8
+    fam = _fam()
+    lv = ri.local_vars_bumps(wl.nc, wl.m, fam["g"], fam["rho"])
+    K = [i for i, l in enumerate(lv) if len(l) == 4][0]
+    only = [lv[K] if k == K else [] for k in range(wl.M)]
+    xi = np.zeros((100, wl.nxi))
+    xi[:, lv[K]] = np.random.default_rng(5).uniform(-1, 1, size=(100, 4))
+    Sref = ri.patch_S(xi, K, wl.nc, wl.m, fam)
+    err = {}
+    for L in (2, 3, 4, 5):
+        model = sc.sgi_offline(wl.nc, wl.m, fam, only, L)
+        S = sc.smolyak_interp(model["tables"][K], 4, L, xi[:, lv[K]])
+        err[L] = np.abs(S - Sref).max() / np.abs(Sref).max()
+    assert err[2] > err[3] > err[4] > err[5] and err[5] < 1e-9, err
+    tens = ri.ri_offline(wl.nc, wl.m, fam, lv, 5, -1, 1, patches=[K])
+    et = np.abs(ri.ri_eval(tens["tables"][K], tens["nodes"], xi[:, lv[K]]) - Sref).max() / np.abs(Sref).max()
+    assert err[4] < 0.1 * et, (err[4], et)
+
+
+def test_interpolation_outside_the_box_is_the_plain_path():
+    from oracle import core, ri
+    wl = W.MESH8
+    fam = _fam()
+    lv = ri.local_vars_bumps(wl.nc, wl.m, fam["g"], fam["rho"])
+    model = sc.sgi_offline(wl.nc, wl.m, fam, lv, 2, lo=-0.5, hi=0.5)
+    xi = W.uniform_xi(6, wl.nxi, 31)
+    S, fb = sc.sgi_online(model, xi, wl.nc, wl.m, fam)
+    a = core.coef_bumps(xi, wl.nfine, **fam)
+    Sp, _, _ = core.upscale(a, wl.nc, wl.nc, wl.m)
+    assert fb.any() and (~fb).any()
+    np.testing.assert_array_equal(S[fb], Sp[fb])
+    assert np.abs(S[~fb] - Sp[~fb]).max() < 0.05 * np.abs(Sp).max()
