@@ -427,6 +427,34 @@ int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32
                         void* stream);
 
 /* ------------------------------------------------------------------------
+ * Sparse-grid interpolation of the upscaled stiffness in the local variables
+ * (Sec. 3.1 with the sparse node sets of Sec. 3.3 and Sec. 5.3).
+ *
+ * stomsfem_sgi_build (offline): for every patch K with k_K <= 4 local
+ * variables (local_vars host [M][4] as for stomsfem_interp_build), S_K at the
+ * nodes of the level-`level` (0..5) Smolyak Clenshaw-Curtis grid in k_K
+ * variables on the box [lo, hi] (node values as for stomsfem_sparse_grid),
+ * computed on the GPU by the plain path (bump family `fam`, every other
+ * variable 0).  1 <= m <= 48.  The model owns its device memory; it cannot be
+ * saved.  Synchronises `stream`.  ENOTSPD if a node's cell problem fails.
+ *
+ * stomsfem_sgi_apply (online): S device [nsamples][M][10] for xi device
+ * [nsamples][nxi]: Smolyak's combination of tensor Lagrange interpolants on
+ * the nested nodes, evaluated in FP64 at the pair's local variables; pairs
+ * with a local variable outside [lo, hi] (or NaN) are computed by the plain
+ * path from xi.  status device [nsamples][M] or NULL: 0 = interpolated,
+ * 1 = computed plainly, STOMSFEM_ENOTSPD from such a solve.  *nfallback
+ * (host, may be NULL) receives the number of plainly computed pairs.  At most
+ * 65535 coarse elements.  Synchronises `stream` once; may grow a
+ * model-owned buffer (a synchronous allocation).
+ * ------------------------------------------------------------------------ */
+int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                       const stomsfem_bump_family* fam, int32_t level, double lo, double hi, stomsfem_model** model,
+                       void* stream);
+int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                       int32_t* status, int64_t* nfallback, void* stream);
+
+/* ------------------------------------------------------------------------
  * Execution plans.  A stage is one batch of samples taken through the whole
  * path: coefficient generation from xi, local upscaling (FP64), coarse
  * assembly and solve with the Petrov-Galerkin load for f = 1, and the Monte
@@ -524,7 +552,7 @@ typedef struct {
 int stomsfem_model_save(const stomsfem_model* model, const char* path);
 int stomsfem_model_load(const char* path, stomsfem_model** model);
 /* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
- * 4 = sparse-grid collocation dictionaries;
+ * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation;
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

@@ -226,6 +226,15 @@ struct stomsfem_model {
   // as above; keys of the local points, increasing within each patch
   int64_t* keys = nullptr;    // [rows]
   int32_t sc_level = 0;
+  // sparse-grid interpolation (kind 5): rows, off, nlv, lv, table, list and
+  // the chunk buffers as for kind 3, plus the combination entries
+  double* cb_coef = nullptr;
+  uint32_t* cb_boff = nullptr;
+  int32_t* cb_row = nullptr;
+  double* sg_nodes = nullptr;  // [nb]
+  int32_t sg_nb = 0, sg_kmax = 0;
+  int32_t sg_lofs[SGI_LEVEL_MAX + 3] = {};
+  int32_t sg_kofs[6] = {};
 };
 
 namespace {
@@ -261,6 +270,10 @@ void model_release(stomsfem_model* md) {
   hipFree(md->Sc);
   hipFree(md->stc);
   hipFree(md->keys);
+  hipFree(md->cb_coef);
+  hipFree(md->cb_boff);
+  hipFree(md->cb_row);
+  hipFree(md->sg_nodes);
   hipSetDevice(cur);
   delete md;
 }
@@ -1128,6 +1141,64 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
 // ---------------------------------------------------------------------------
 // sparse-grid collocation with search-and-plug-in dictionaries
 // ---------------------------------------------------------------------------
+// S_K at every table row of a dictionary or interpolation model by the plain
+// path: rows of patch K are off[K] .. off[K+1]-1; fill(row, K, x) sets the
+// row's local variables in x (the other nxi entries are 0).  Chunks of
+// md->chunk pairs; synchronises st per chunk (for the status read).
+static int solve_table_rows(stomsfem_model* md, int nxi, const std::vector<int64_t>& off,
+                            const std::function<void(int64_t, int, double*)>& fill, hipStream_t st, const char* who) {
+  const int Mc = md->ncx * md->ncy;
+  std::vector<double> xh;
+  std::vector<int64_t> ph;
+  std::vector<int32_t> sth;
+  int bad = 0, K = 0;
+  hipError_t e = hipSuccess;
+  for (int64_t start = 0; e == hipSuccess && start < md->rows; start += md->chunk) {
+    const int64_t cnt = std::min(md->chunk, md->rows - start);
+    xh.assign((size_t)cnt * nxi, 0.0);
+    ph.resize(cnt);
+    for (int64_t i = 0; i < cnt; ++i) {
+      const int64_t row = start + i;
+      while (off[K + 1] <= row) ++K;
+      fill(row, K, xh.data() + (size_t)i * nxi);
+      ph[i] = i * Mc + K;
+    }
+    e = hipMemcpyAsync(md->xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(md->pairs, ph.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    RegenArgs r{};
+    r.ncx = md->ncx;
+    r.ncy = md->ncy;
+    r.m = md->m;
+    r.nxi = nxi;
+    r.bp = bump_params(md->fam);
+    r.pairs = md->pairs;
+    r.count = cnt;
+    r.xi = md->xin;
+    r.out = md->blk;
+    e = launch_regen_blocks(r, st);
+    if (e != hipSuccess) break;
+    UpArgs u{};
+    u.nsamples = cnt;
+    u.ncx = u.ncy = 1;
+    u.m = md->m;
+    u.npairs = cnt;
+    u.a = md->blk;
+    u.S = md->table + start * 10;
+    u.status = md->stc;
+    e = launch_upscale_any(u, STOMSFEM_F64, st);
+    if (e != hipSuccess) break;
+    sth.resize(cnt);
+    e = hipMemcpyAsync(sth.data(), md->stc, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // also keeps xh, ph alive for the copies
+    for (int64_t i = 0; e == hipSuccess && i < cnt; ++i) bad |= sth[i] != 0;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, who);
+  if (bad) return fail(STOMSFEM_ENOTSPD, std::string(who) + ": a cell problem at a table node is not positive definite");
+  return STOMSFEM_OK;
+}
+
 int stomsfem_sparse_grid(int32_t dim, int32_t level, int64_t capacity, int64_t* npoints, int32_t* digits,
                          double* weights) {
   if (!npoints) return fail(STOMSFEM_EINVAL, "sparse_grid: NULL npoints");
@@ -1224,62 +1295,21 @@ int stomsfem_sc_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_
   // local variables at their node values and every other variable 0
   std::vector<double> node(D + 1);
   for (int c = 0; c <= D; ++c) node[c] = lo + (std::cos(M_PI * (double)c / (double)D) + 1.0) * 0.5 * (hi - lo);
-  std::vector<double> xh;
-  std::vector<int64_t> ph;
-  std::vector<int32_t> sth;
-  int bad = 0, K = 0;
-  for (int64_t start = 0; e == hipSuccess && start < md->rows; start += md->chunk) {
-    const int64_t cnt = std::min(md->chunk, md->rows - start);
-    xh.assign((size_t)cnt * nxi, 0.0);
-    ph.resize(cnt);
-    for (int64_t i = 0; i < cnt; ++i) {
-      const int64_t row = start + i;
-      while (off[K + 1] <= row) ++K;
+  if (e == hipSuccess) {
+    const int rc = solve_table_rows(md, nxi, off, [&](int64_t row, int K, double* x) {
       int64_t key = keys[row];
       for (int v = nlv[K] - 1; v >= 0; --v) {
-        xh[(size_t)i * nxi + local_vars[K * RI_KMAX + v]] = node[key % (D + 1)];
+        x[local_vars[K * RI_KMAX + v]] = node[key % (D + 1)];
         key /= (D + 1);
       }
-      ph[i] = i * Mc + K;
+    }, st, "sc_build");
+    if (rc != STOMSFEM_OK) {
+      model_release(md);
+      return rc;
     }
-    e = hipMemcpyAsync(md->xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(md->pairs, ph.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) break;
-    RegenArgs r{};
-    r.ncx = ncx;
-    r.ncy = ncy;
-    r.m = m;
-    r.nxi = nxi;
-    r.bp = bump_params(*fam);
-    r.pairs = md->pairs;
-    r.count = cnt;
-    r.xi = md->xin;
-    r.out = md->blk;
-    e = launch_regen_blocks(r, st);
-    if (e != hipSuccess) break;
-    UpArgs u{};
-    u.nsamples = cnt;
-    u.ncx = u.ncy = 1;
-    u.m = m;
-    u.npairs = cnt;
-    u.a = md->blk;
-    u.S = md->table + start * 10;
-    u.status = md->stc;
-    e = launch_upscale_any(u, STOMSFEM_F64, st);
-    if (e != hipSuccess) break;
-    sth.resize(cnt);
-    e = hipMemcpyAsync(sth.data(), md->stc, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);  // also keeps xh, ph alive for the copies
-    for (int64_t i = 0; e == hipSuccess && i < cnt; ++i) bad |= sth[i] != 0;
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
+  } else {
     model_release(md);
     return hip_fail(e, "sc_build");
-  }
-  if (bad) {
-    model_release(md);
-    return fail(STOMSFEM_ENOTSPD, "sc_build: a cell problem at a collocation point is not positive definite");
   }
   *model = md;
   return STOMSFEM_OK;
@@ -1321,6 +1351,220 @@ int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32
   if (rc != STOMSFEM_OK) return rc;
   hipError_t e = launch_sc_quadrature(U, w, npoints, nu, mean, var, (double*)work, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "quadrature launch");
+}
+
+int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars,
+                       const stomsfem_bump_family* fam, int32_t level, double lo, double hi, stomsfem_model** model,
+                       void* stream) {
+  if (!local_vars || !fam || !model) return fail(STOMSFEM_EINVAL, "sgi_build: NULL argument");
+  *model = nullptr;
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 48) return fail(STOMSFEM_EINVAL, "sgi_build: need 1 <= m <= 48");
+  if (level < 0 || level > SGI_LEVEL_MAX) return fail(STOMSFEM_EINVAL, "sgi_build: need 0 <= level <= 5");
+  if (!(lo < hi)) return fail(STOMSFEM_EINVAL, "sgi_build: need lo < hi");
+  if (fam->g < 1 || !(fam->rho > 0) || !(fam->eps > 0)) return fail(STOMSFEM_EINVAL, "sgi_build: bad family");
+  const int Mc = ncx * ncy, nxi = fam->g * fam->g, D = sc_digit_base(level);
+  std::vector<int32_t> nlv(Mc);
+  int kmax = 1;
+  for (int K = 0; K < Mc; ++K) {
+    int k = 0;
+    while (k < RI_KMAX && local_vars[K * RI_KMAX + k] >= 0) ++k;
+    for (int i = 0; i < RI_KMAX; ++i) {
+      const int32_t j = local_vars[K * RI_KMAX + i];
+      if ((i < k && j >= nxi) || (i >= k && j != -1))
+        return fail(STOMSFEM_EINVAL, "sgi_build: local variables must be < g*g, -1 padded at the end");
+      if (i > 0 && i < k && j <= local_vars[K * RI_KMAX + i - 1])
+        return fail(STOMSFEM_EINVAL, "sgi_build: local variables of a patch must be increasing");
+    }
+    nlv[K] = k;
+    kmax = std::max(kmax, k);
+  }
+  // the level-L grid in k variables (k = 1..4; k = 0: the one empty point)
+  std::vector<int32_t> gdig[RI_KMAX + 1];
+  int64_t npts[RI_KMAX + 1] = {1, 0, 0, 0, 0};
+  for (int k = 1; k <= RI_KMAX; ++k) {
+    std::vector<double> gw;
+    sc_build_grid(k, level, gdig[k], gw);
+    npts[k] = (int64_t)gw.size();
+  }
+  // one-dimensional nodes of every level, level i at lofs[i]
+  int32_t lofs[SGI_LEVEL_MAX + 3] = {};
+  std::vector<double> nodes{0.0};
+  for (int i = 2; i <= level + 1; ++i) {
+    const int n = (1 << (i - 1)) + 1;
+    lofs[i] = (int32_t)nodes.size();
+    for (int j = 0; j < n; ++j) nodes.push_back(std::cos(M_PI * (double)j / (double)(n - 1)));
+  }
+  const int nb = (int)nodes.size();
+  // combination entries per k: (coefficient, basis offsets, row)
+  std::vector<double> cc;
+  std::vector<uint32_t> cbo;
+  std::vector<int32_t> crow;
+  int32_t kofs[6] = {};
+  bool missing = false;
+  for (int k = 0; k <= RI_KMAX; ++k) {
+    kofs[k] = (int32_t)cc.size();
+    if (k == 0) {
+      cc.push_back(1.0);
+      cbo.push_back(0u);
+      crow.push_back(0);
+      continue;
+    }
+    std::map<std::vector<int32_t>, int32_t> rowof;
+    for (int64_t r = 0; r < npts[k]; ++r)
+      rowof[std::vector<int32_t>(gdig[k].begin() + r * k, gdig[k].begin() + (r + 1) * k)] = (int32_t)r;
+    std::vector<int32_t> dg(k);
+    std::vector<int> pos(k);
+    sc_smolyak_terms(k, level, [&](double c, const std::vector<int>& idx) {
+      for (int d = 0; d < k; ++d) pos[d] = 0;
+      while (true) {
+        uint32_t bo = 0;
+        for (int d = 0; d < k; ++d) {
+          const int n = idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1;
+          dg[d] = n == 1 ? D / 2 : pos[d] * (D / (n - 1));
+          bo |= (uint32_t)(lofs[idx[d]] + pos[d]) << (8 * d);
+        }
+        const auto it = rowof.find(dg);
+        missing = missing || it == rowof.end();
+        cc.push_back(c);
+        cbo.push_back(bo);
+        crow.push_back(it == rowof.end() ? 0 : it->second);
+        int d = k - 1;
+        while (d >= 0 && ++pos[d] == (idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1)) pos[d--] = 0;
+        if (d < 0) break;
+      }
+    });
+  }
+  kofs[RI_KMAX + 1] = (int32_t)cc.size();
+  if (missing) return fail(STOMSFEM_EINVAL, "sgi_build: a tensor node of the combination is not a grid node");
+  std::vector<int64_t> off(Mc + 1, 0);
+  for (int K = 0; K < Mc; ++K) off[K + 1] = off[K] + npts[nlv[K]];
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 5;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->fam = *fam;
+  md->lo = lo;
+  md->hi = hi;
+  md->sc_level = level;
+  md->rows = off[Mc];
+  md->sg_nb = nb;
+  md->sg_kmax = kmax;
+  std::memcpy(md->sg_lofs, lofs, sizeof(lofs));
+  std::memcpy(md->sg_kofs, kofs, sizeof(kofs));
+  md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->table, sizeof(double) * (size_t)md->rows * 10);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+  A((void**)&md->xin, sizeof(double) * (size_t)md->chunk * nxi);
+  A((void**)&md->pairs, sizeof(int64_t) * (size_t)md->chunk);
+  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  A((void**)&md->cb_coef, sizeof(double) * cc.size());
+  A((void**)&md->cb_boff, sizeof(uint32_t) * cbo.size());
+  A((void**)&md->cb_row, sizeof(int32_t) * crow.size());
+  A((void**)&md->sg_nodes, sizeof(double) * nodes.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "sgi_build: device allocation failed");
+  }
+  e = hipMemcpy(md->lv, local_vars, sizeof(int32_t) * Mc * RI_KMAX, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->cb_coef, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->cb_boff, cbo.data(), sizeof(uint32_t) * cbo.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->cb_row, crow.data(), sizeof(int32_t) * crow.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->sg_nodes, nodes.data(), sizeof(double) * nodes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "sgi_build");
+  }
+  const int rc = solve_table_rows(md, nxi, off, [&](int64_t row, int K, double* x) {
+    const int k = nlv[K];
+    const int64_t r = row - off[K];
+    for (int v = 0; v < k; ++v) {
+      const int32_t c = gdig[k][r * k + v];
+      x[local_vars[K * RI_KMAX + v]] = lo + (std::cos(M_PI * (double)c / (double)D) + 1.0) * 0.5 * (hi - lo);
+    }
+  }, st, "sgi_build");
+  if (rc != STOMSFEM_OK) {
+    model_release(md);
+    return rc;
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
+                       int32_t* status, int64_t* nfallback, void* stream) {
+  if (nfallback) *nfallback = 0;
+  if (!model || model->kind != 5) return fail(STOMSFEM_EINVAL, "sgi_apply: not a sparse-grid interpolation model");
+  if (nsamples < 0 || nxi < model->fam.g * model->fam.g)
+    return fail(STOMSFEM_EINVAL, "sgi_apply: nsamples < 0 or nxi smaller than the family's g*g");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi) || !device_ptr(S)) return fail(STOMSFEM_EINVAL, "sgi_apply: xi and S must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "sgi_apply: status must be a device pointer");
+  const int Mc = model->ncx * model->ncy;
+  if (Mc > 65535) return fail(STOMSFEM_EINVAL, "sgi_apply: at most 65535 coarse elements");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = nsamples * Mc;
+  if (model->list_cap < need) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+      hipFree(model->list);
+      model->list = nullptr;
+      model->list_cap = 0;
+      e = hipMalloc(&model->list, sizeof(int64_t) * need);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STOMSFEM_ENOMEM, "sgi_apply: fallback list allocation failed");
+    }
+    model->list_cap = need;
+  }
+  SgiApplyArgs a{};
+  a.npatch = Mc;
+  a.nxi = nxi;
+  a.level = model->sc_level;
+  a.nb = model->sg_nb;
+  a.kmax = model->sg_kmax;
+  a.nsamples = nsamples;
+  a.lo = model->lo;
+  a.hi = model->hi;
+  a.table = model->table;
+  a.off = model->off;
+  a.lv = model->lv;
+  a.nlv = model->nlv;
+  a.nodes = model->sg_nodes;
+  std::memcpy(a.lofs, model->sg_lofs, sizeof(a.lofs));
+  std::memcpy(a.kofs, model->sg_kofs, sizeof(a.kofs));
+  a.cb_coef = model->cb_coef;
+  a.cb_boff = model->cb_boff;
+  a.cb_row = model->cb_row;
+  a.xi = xi;
+  a.S = S;
+  a.status = status;
+  a.list = model->list;
+  a.list_count = model->counter;
+  hipError_t e = launch_zero_u64(model->counter, st);
+  if (e == hipSuccess) e = launch_sgi_apply(a, st);
+  unsigned long long n = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "sgi_apply");
+  if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "sgi_apply: fallback count out of range");
+  if (nfallback) *nfallback = (int64_t)n;
+  return ri_plain_pairs(model, model->list, (int64_t)n, xi, nxi, S, status, 1, st);
 }
 
 // ---------------------------------------------------------------------------

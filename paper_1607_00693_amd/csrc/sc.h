@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace stomsfem {
@@ -22,6 +23,34 @@ int64_t sc_term_count(int dim, int level, int64_t cap);
 // variables for the uniform probability measure: digits (row-major
 // [n][dim], lexicographic order) and weights [n].
 void sc_build_grid(int dim, int level, std::vector<int32_t>& digits, std::vector<double>& weights);
+
+// Every term of the combination formula: term(coefficient, multi-index).
+void sc_smolyak_terms(int dim, int level, const std::function<void(double, const std::vector<int>&)>& term);
+
+// Sparse-grid interpolation in the local variables (levels 0..SGI_LEVEL_MAX).
+constexpr int SGI_LEVEL_MAX = 5;  // 33 nodes per variable at most
+struct SgiApplyArgs {
+  int32_t npatch, nxi, level, nb, kmax;
+  int64_t nsamples;
+  double lo, hi;
+  const double* table;        // [rows][10]
+  const int64_t* off;         // [npatch + 1]
+  const int32_t* lv;          // [npatch][4]
+  const int32_t* nlv;         // [npatch]
+  const double* nodes;        // [nb]: level-i nodes at lofs[i] ...
+  int32_t lofs[SGI_LEVEL_MAX + 3];
+  int32_t kofs[6];            // combination entries of k local variables: kofs[k] .. kofs[k+1]
+  const double* cb_coef;      // [entries]
+  const uint32_t* cb_boff;    // [entries]: basis offset of variable d in bits 8d..8d+7
+  const int32_t* cb_row;      // [entries]: row in the patch's table
+  const double* xi;           // [nsamples][nxi]
+  double* S;                  // [nsamples][npatch][10]
+  int32_t* status;            // [nsamples][npatch] or null
+  int64_t* list;
+  unsigned long long* list_count;
+};
+size_t sgi_lds_bytes(int kmax, int nb);
+hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st);
 
 struct ScApplyArgs {
   int32_t npatch, nxi, D;

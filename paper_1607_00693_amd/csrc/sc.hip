@@ -24,6 +24,7 @@
 #include "sc.h"
 
 #include <cmath>
+#include <functional>
 #include <map>
 
 namespace stomsfem {
@@ -65,20 +66,34 @@ static int64_t binom64(int n, int r) {
   return b;
 }
 
+void sc_smolyak_terms(int dim, int level, const std::function<void(double, const std::vector<int>&)>& term) {
+  std::vector<int> idx(dim, 1);
+  const int lo_extra = level - dim + 1 > 0 ? level - dim + 1 : 0;
+  // depth-first over dimensions distributing the extra levels
+  auto rec = [&](auto&& self, int k, int used) -> void {
+    if (k == dim) {
+      if (used >= lo_extra)
+        term(((level - used) % 2 ? -1.0 : 1.0) * (double)binom64(dim - 1, level - used), idx);
+      return;
+    }
+    for (int e = 0; used + e <= level; ++e) {
+      idx[k] = 1 + e;
+      self(self, k + 1, used + e);
+    }
+    idx[k] = 1;
+  };
+  rec(rec, 0, 0);
+}
+
 void sc_build_grid(int dim, int level, std::vector<int32_t>& digits, std::vector<double>& weights) {
   const int D = sc_digit_base(level);
   std::vector<std::vector<int32_t>> rd(level + 2);
   std::vector<std::vector<double>> rw(level + 2);
   for (int i = 1; i <= level + 1; ++i) cc_rule(i, D, rd[i], rw[i]);
   std::map<std::vector<int32_t>, double> acc;
-  std::vector<int> idx(dim, 1);
   std::vector<int32_t> pt(dim);
   std::vector<int> pos(dim);
-  const int lo_extra = level - dim + 1 > 0 ? level - dim + 1 : 0;
-  // every multi-index with sum(i_k - 1) <= level, by a recursive walk
-  auto visit = [&](int extra) {
-    if (extra < lo_extra) return;
-    const double c = ((level - extra) % 2 ? -1.0 : 1.0) * (double)binom64(dim - 1, level - extra);
+  sc_smolyak_terms(dim, level, [&](double c, const std::vector<int>& idx) {
     // tensor product of the rules idx[0..dim-1]
     for (int k = 0; k < dim; ++k) pos[k] = 0;
     while (true) {
@@ -92,20 +107,7 @@ void sc_build_grid(int dim, int level, std::vector<int32_t>& digits, std::vector
       while (k >= 0 && ++pos[k] == (int)rd[idx[k]].size()) pos[k--] = 0;
       if (k < 0) break;
     }
-  };
-  // depth-first over dimensions distributing the extra levels
-  auto rec = [&](auto&& self, int k, int used) -> void {
-    if (k == dim) {
-      visit(used);
-      return;
-    }
-    for (int e = 0; used + e <= level; ++e) {
-      idx[k] = 1 + e;
-      self(self, k + 1, used + e);
-    }
-    idx[k] = 1;
-  };
-  rec(rec, 0, 0);
+  });
   digits.clear();
   weights.clear();
   digits.reserve(acc.size() * (size_t)dim);
@@ -159,6 +161,86 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sc_apply_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---- sparse-grid interpolation: sgi_apply_kernel ----
+// One workgroup = one patch K (blockIdx.y) and 64 samples (one per lane), so
+// the patch's table and the combination list are read at wave-uniform
+// addresses.  Each lane first evaluates, for every local variable d and
+// every level i <= L+1, the Lagrange basis of the level-i nodes at its t_d
+// in barycentric product form
+//   P_j = w_j prod_{e != j} (t - t_e),  l_j = P_j / sum_e P_e,
+// w_j = (-1)^j (halved at both ends), the Chebyshev-Lobatto weights (exact on
+// a node, no division by zero; level 1: l_0 = 1), into its LDS row
+// B[d][lofs[i] + j].  Then S_K(t) = sum over the combination entries of
+// coef * prod_d B[d][boff_d] * T_K[row].  Lanes with a local variable
+// outside [lo, hi] (or NaN) are listed for the plain path instead.
+__global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
+  extern __shared__ double sgi_lds[];
+  const int lane = threadIdx.x;
+  const int K = blockIdx.y;
+  const int64_t s = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = s < a.nsamples;
+  const int k = a.nlv[K];
+  double* B = sgi_lds + (size_t)lane * a.kmax * a.nb;
+  bool inside = valid;
+  for (int d = 0; d < k; ++d) {
+    const double x = valid ? a.xi[s * a.nxi + a.lv[K * 4 + d]] : 0.0;
+    inside = inside && (x >= a.lo && x <= a.hi);
+    const double t = 2.0 * (x - a.lo) / (a.hi - a.lo) - 1.0;
+    double* Bd = B + d * a.nb;
+    Bd[0] = 1.0;  // level 1
+    for (int i = 2; i <= a.level + 1; ++i) {
+      const int n = (1 << (i - 1)) + 1, o = a.lofs[i];
+      double sum = 0.0;
+      for (int j = 0; j < n; ++j) {
+        double P = (j & 1) ? -1.0 : 1.0;
+        if (j == 0 || j == n - 1) P *= 0.5;
+        for (int e = 0; e < n; ++e)
+          if (e != j) P *= t - a.nodes[o + e];
+        Bd[o + j] = P;
+        sum += P;
+      }
+      const double r = 1.0 / sum;
+      for (int j = 0; j < n; ++j) Bd[o + j] *= r;
+    }
+  }
+  const int64_t p = s * a.npatch + K;
+  if (valid && !inside) {
+    const unsigned long long slot = atomicAdd(a.list_count, 1ull);
+    a.list[slot] = p;
+  }
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  const double* T = a.table + a.off[K] * 10;
+  const int c1 = a.kofs[k + 1];
+  for (int c = a.kofs[k]; c < c1; ++c) {
+    double w = a.cb_coef[c];
+    const uint32_t bo = a.cb_boff[c];
+    for (int d = 0; d < k; ++d) w *= B[d * a.nb + ((bo >> (8 * d)) & 255u)];
+    const double* Tr = T + (int64_t)a.cb_row[c] * 10;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] += w * Tr[q];
+  }
+  if (valid && inside) {
+    double* So = a.S + p * 10;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) So[q] = acc[q];
+    if (a.status) a.status[p] = 0;
+  }
+}
+
+size_t sgi_lds_bytes(int kmax, int nb) { return (size_t)64 * (kmax > 0 ? kmax : 1) * nb * sizeof(double); }
+
+hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st) {
+  if (a.nsamples == 0) return hipSuccess;
+  const size_t lds = sgi_lds_bytes(a.kmax, a.nb);
+  hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
+  hipLaunchKernelGGL(sgi_apply_kernel, grid, dim3(64), lds, st, a);
   return hipGetLastError();
 }
 

@@ -123,6 +123,9 @@ def lib():
                                         C.POINTER(vp), vp]),
         "stomsfem_sc_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, vp]),
         "stomsfem_quadrature": (C.c_int, [vp, vp, i64, i32, vp, vp, vp]),
+        "stomsfem_sgi_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl, C.POINTER(vp),
+                                         vp]),
+        "stomsfem_sgi_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -486,6 +489,34 @@ def sc_apply(model: Model, digits: torch.Tensor, S: torch.Tensor | None = None, 
     _check("stomsfem_sc_apply", lib().stomsfem_sc_apply(
         model.handle, _ptr(digits), digits.shape[1], n, _ptr(S), _ptr(status), _stream(stream)))
     return S
+
+
+def sgi_build(ncx: int, ncy: int, m: int, lv, fam: BumpFamily, level: int, lo: float = -1.0, hi: float = 1.0,
+              stream=None) -> Model:
+    """Offline sparse-grid interpolation: S at the level-`level` Smolyak
+    Clenshaw-Curtis nodes of every patch's local variables."""
+    import numpy as np
+
+    lv = np.ascontiguousarray(lv, dtype=np.int32)
+    assert lv.shape == (ncx * ncy, MLP_KIN)
+    h = C.c_void_p()
+    _check("stomsfem_sgi_build", lib().stomsfem_sgi_build(
+        ncx, ncy, m, lv.ctypes.data_as(C.c_void_p), C.byref(fam), level, lo, hi, C.byref(h), _stream(stream)))
+    return Model(h, ncx, ncy, m)
+
+
+def sgi_apply(model: Model, xi: torch.Tensor, S: torch.Tensor | None = None, status: torch.Tensor | None = None,
+              stream=None):
+    """Online sparse-grid interpolation S[N][M][10]; returns (S, number of
+    pairs computed by the plain path because a local variable left the box)."""
+    assert xi.dtype == torch.float64
+    N = xi.shape[0]
+    if S is None:
+        S = torch.empty((N, model.ncx * model.ncy, 10), dtype=torch.float64, device=xi.device)
+    nfb = C.c_int64(0)
+    _check("stomsfem_sgi_apply", lib().stomsfem_sgi_apply(
+        model.handle, _ptr(xi), xi.shape[1], N, _ptr(S), _ptr(status), C.byref(nfb), _stream(stream)))
+    return S, nfb.value
 
 
 def quadrature(U: torch.Tensor, w: torch.Tensor, mean: torch.Tensor | None = None, var: torch.Tensor | None = None,
