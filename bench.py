@@ -111,12 +111,13 @@ def _timed(fn, reps=5):
     return (time.perf_counter() - t) / reps
 
 
-def measure_interpolation(wl, xi, S_plain, t_plain_ms, nn_list, log):
+def measure_interpolation(wl, xi, S_plain, t_plain_ms, nn_list, log, sg_levels=()):
     """Random interpolation (Sec. 3.1) on the benchmark mesh: offline node
     solves, then the online evaluation from xi, against the plain path from xi
     (coefficient generation + upscaling, t_plain_ms).  Reports throughput,
     ratio, the largest error of S relative to max|S| per pair, and the worst
-    per-sample relative error of the coarse solution."""
+    per-sample relative error of the coarse solution; tensor grids of nn
+    nodes per variable, and Smolyak sparse grids of the given levels."""
     import numpy as np
     import torch
 
@@ -149,6 +150,26 @@ def measure_interpolation(wl, xi, S_plain, t_plain_ms, nn_list, log):
         log(f"interpolation nn={nn}: {out[f'nodes_{nn}']}")
         model.free()
         del S_ri
+    for level in sg_levels:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = sm.sgi_build(wl.nc, wl.nc, wl.m, lv, fam, level)
+        t_off = time.perf_counter() - t0
+        S_sg = torch.empty_like(S_plain)
+        t_on = _timed(lambda: sm.sgi_apply(model, xi, S=S_sg), reps=3)
+        scale = S_plain.abs().amax(dim=2, keepdim=True)
+        s_err = float(((S_sg - S_plain).abs() / scale).max())
+        U_sg, _, _ = sm.coarse_solve(S_sg, wl.nc, wl.nc)
+        u_err = float((torch.linalg.norm(U_sg - U_pl, dim=1) / torch.linalg.norm(U_pl, dim=1)).max())
+        nodes = {k: (1 if k == 0 else len(sm.sparse_grid(k, level)[1])) for k in set(nl.tolist())}
+        out[f"sparse_level_{level}"] = {
+            "offline_s": t_off, "node_solves": int(sum(nodes[int(k)] for k in nl)),
+            "nodes_per_patch_4_vars": nodes.get(4), "pairs_per_s": pairs / t_on,
+            "plain_pairs_per_s": pairs / (t_plain_ms * 1e-3), "ratio": t_plain_ms * 1e-3 / t_on,
+            "max_S_rel_err": s_err, "max_coarse_rel_err": u_err}
+        log(f"sparse-grid interpolation level={level}: {out[f'sparse_level_{level}']}")
+        model.free()
+        del S_sg
     return out
 
 
@@ -478,7 +499,7 @@ def measure_accelerations(log):
     S_pl = sm.upscale(a64, wl.nc, wl.nc, wl.m)
     t_pl = _timed(lambda: (sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), out=a64),
                            sm.upscale(a64, wl.nc, wl.nc, wl.m, S=S_pl)))
-    out["random_interpolation"] = measure_interpolation(wl, xi, S_pl, t_pl * 1e3, (5, 7), log)
+    out["random_interpolation"] = measure_interpolation(wl, xi, S_pl, t_pl * 1e3, (5, 7), log, sg_levels=(4, 5))
     out["random_interpolation"]["workload"] = (f"8x8 coarse, H/h=8, {N} samples, Chebyshev-Lobatto tensor "
                                                "nodes per local variable (k<=4), FP64")
     del a64
@@ -654,10 +675,12 @@ def main():
     if not args.no_accelerations:
         print("[bench] random interpolation at the benchmark mesh", file=sys.stderr, flush=True)
         ri_out = measure_interpolation(wl, xi, S, t_gen + t_up, (5, 7),
-                                       lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+                                       lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
+                                       sg_levels=(4, 5))
         ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
-                              "Chebyshev-Lobatto tensor nodes per local variable (k<=4), FP64; plain side = "
-                              "coefficient generation + upscaling kernels")
+                              "Chebyshev-Lobatto tensor nodes per local variable (k<=4) and Smolyak "
+                              "Clenshaw-Curtis sparse grids, FP64; plain side = coefficient generation + "
+                              "upscaling kernels")
         print("[bench] learned surrogate at the benchmark mesh", file=sys.stderr, flush=True)
         sur_out = measure_surrogate(wl, xi, S, t_gen + t_up,
                                     lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))

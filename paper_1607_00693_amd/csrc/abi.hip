@@ -230,11 +230,11 @@ struct stomsfem_model {
   // the chunk buffers as for kind 3, plus the combination entries
   double* cb_coef = nullptr;
   uint32_t* cb_boff = nullptr;
-  int32_t* cb_row = nullptr;
+  int32_t* cb_rows = nullptr;  // per k: entry offsets of the table rows
   double* sg_nodes = nullptr;  // [nb]
   int32_t sg_nb = 0, sg_kmax = 0;
   int32_t sg_lofs[SGI_LEVEL_MAX + 3] = {};
-  int32_t sg_kofs[6] = {};
+  int32_t sg_rofs[6] = {};
 };
 
 namespace {
@@ -272,7 +272,7 @@ void model_release(stomsfem_model* md) {
   hipFree(md->keys);
   hipFree(md->cb_coef);
   hipFree(md->cb_boff);
-  hipFree(md->cb_row);
+  hipFree(md->cb_rows);
   hipFree(md->sg_nodes);
   hipSetDevice(cur);
   delete md;
@@ -1395,20 +1395,23 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
     for (int j = 0; j < n; ++j) nodes.push_back(std::cos(M_PI * (double)j / (double)(n - 1)));
   }
   const int nb = (int)nodes.size();
-  // combination entries per k: (coefficient, basis offsets, row)
+  // combination entries per k: (coefficient, basis offsets), grouped by the
+  // table row of their node; per k the row offsets into the entries
   std::vector<double> cc;
   std::vector<uint32_t> cbo;
-  std::vector<int32_t> crow;
-  int32_t kofs[6] = {};
+  std::vector<int32_t> rows_all;
+  int32_t rofs[6] = {};
   bool missing = false;
   for (int k = 0; k <= RI_KMAX; ++k) {
-    kofs[k] = (int32_t)cc.size();
+    rofs[k] = (int32_t)rows_all.size();
     if (k == 0) {
+      rows_all.push_back((int32_t)cc.size());
       cc.push_back(1.0);
       cbo.push_back(0u);
-      crow.push_back(0);
+      rows_all.push_back((int32_t)cc.size());
       continue;
     }
+    std::vector<std::vector<std::pair<double, uint32_t>>> byrow((size_t)npts[k]);
     std::map<std::vector<int32_t>, int32_t> rowof;
     for (int64_t r = 0; r < npts[k]; ++r)
       rowof[std::vector<int32_t>(gdig[k].begin() + r * k, gdig[k].begin() + (r + 1) * k)] = (int32_t)r;
@@ -1425,16 +1428,22 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
         }
         const auto it = rowof.find(dg);
         missing = missing || it == rowof.end();
-        cc.push_back(c);
-        cbo.push_back(bo);
-        crow.push_back(it == rowof.end() ? 0 : it->second);
+        byrow[it == rowof.end() ? 0 : it->second].emplace_back(c, bo);
         int d = k - 1;
         while (d >= 0 && ++pos[d] == (idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1)) pos[d--] = 0;
         if (d < 0) break;
       }
     });
+    for (int64_t r = 0; r < npts[k]; ++r) {
+      rows_all.push_back((int32_t)cc.size());
+      for (const auto& en : byrow[(size_t)r]) {
+        cc.push_back(en.first);
+        cbo.push_back(en.second);
+      }
+    }
+    rows_all.push_back((int32_t)cc.size());
   }
-  kofs[RI_KMAX + 1] = (int32_t)cc.size();
+  rofs[RI_KMAX + 1] = (int32_t)rows_all.size();
   if (missing) return fail(STOMSFEM_EINVAL, "sgi_build: a tensor node of the combination is not a grid node");
   std::vector<int64_t> off(Mc + 1, 0);
   for (int K = 0; K < Mc; ++K) off[K + 1] = off[K] + npts[nlv[K]];
@@ -1453,7 +1462,7 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
   md->sg_nb = nb;
   md->sg_kmax = kmax;
   std::memcpy(md->sg_lofs, lofs, sizeof(lofs));
-  std::memcpy(md->sg_kofs, kofs, sizeof(kofs));
+  std::memcpy(md->sg_rofs, rofs, sizeof(rofs));
   md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
   hipError_t e = hipSuccess;
   auto A = [&](void** ptr, size_t bytes) {
@@ -1471,7 +1480,7 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
   A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
   A((void**)&md->cb_coef, sizeof(double) * cc.size());
   A((void**)&md->cb_boff, sizeof(uint32_t) * cbo.size());
-  A((void**)&md->cb_row, sizeof(int32_t) * crow.size());
+  A((void**)&md->cb_rows, sizeof(int32_t) * rows_all.size());
   A((void**)&md->sg_nodes, sizeof(double) * nodes.size());
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1483,7 +1492,8 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
   if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->cb_coef, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->cb_boff, cbo.data(), sizeof(uint32_t) * cbo.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(md->cb_row, crow.data(), sizeof(int32_t) * crow.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->cb_rows, rows_all.data(), sizeof(int32_t) * rows_all.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->sg_nodes, nodes.data(), sizeof(double) * nodes.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     model_release(md);
@@ -1547,10 +1557,10 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
   a.nlv = model->nlv;
   a.nodes = model->sg_nodes;
   std::memcpy(a.lofs, model->sg_lofs, sizeof(a.lofs));
-  std::memcpy(a.kofs, model->sg_kofs, sizeof(a.kofs));
+  std::memcpy(a.rofs, model->sg_rofs, sizeof(a.rofs));
   a.cb_coef = model->cb_coef;
   a.cb_boff = model->cb_boff;
-  a.cb_row = model->cb_row;
+  a.cb_rows = model->cb_rows;
   a.xi = xi;
   a.S = S;
   a.status = status;

@@ -39,10 +39,10 @@ struct SgiApplyArgs {
   const int32_t* nlv;         // [npatch]
   const double* nodes;        // [nb]: level-i nodes at lofs[i] ...
   int32_t lofs[SGI_LEVEL_MAX + 3];
-  int32_t kofs[6];            // combination entries of k local variables: kofs[k] .. kofs[k+1]
-  const double* cb_coef;      // [entries]
+  int32_t rofs[6];            // row starts of k local variables: cb_rows[rofs[k] .. rofs[k+1]-1]
+  const double* cb_coef;      // [entries], grouped by table row
   const uint32_t* cb_boff;    // [entries]: basis offset of variable d in bits 8d..8d+7
-  const int32_t* cb_row;      // [entries]: row in the patch's table
+  const int32_t* cb_rows;     // per k: npts_k + 1 entry offsets (entries of row r: [r], [r+1])
   const double* xi;           // [nsamples][nxi]
   double* S;                  // [nsamples][npatch][10]
   int32_t* status;            // [nsamples][npatch] or null

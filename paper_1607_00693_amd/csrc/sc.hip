@@ -172,10 +172,16 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
 // in barycentric product form
 //   P_j = w_j prod_{e != j} (t - t_e),  l_j = P_j / sum_e P_e,
 // w_j = (-1)^j (halved at both ends), the Chebyshev-Lobatto weights (exact on
-// a node, no division by zero; level 1: l_0 = 1), into its LDS row
-// B[d][lofs[i] + j].  Then S_K(t) = sum over the combination entries of
-// coef * prod_d B[d][boff_d] * T_K[row].  Lanes with a local variable
-// outside [lo, hi] (or NaN) are listed for the plain path instead.
+// a node, no division by zero; level 1: l_0 = 1), into LDS at
+// [(d nb + lofs[i] + j) 64 + lane] (lane-interleaved: no bank conflicts).
+// Then S_K(t) = sum over the table rows r of W_r(t) T_K[r], W_r the sum over
+// the combination entries of node r of coef * prod_d B[d][boff_d] (entries
+// are grouped by row, so each table row is read once, at a sequential
+// address, and no load address depends on an earlier load).  Lanes with a local variable
+// outside [lo, hi] (or NaN) are listed for the plain path instead.  Every
+// global store (and the list's atomic) comes after the loop, so the
+// wave-uniform loads of the loop are not clobbered and go through the
+// scalar cache.
 __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
   extern __shared__ double sgi_lds[];
   const int lane = threadIdx.x;
@@ -183,13 +189,13 @@ __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
   const int64_t s = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = s < a.nsamples;
   const int k = a.nlv[K];
-  double* B = sgi_lds + (size_t)lane * a.kmax * a.nb;
+  double* B = sgi_lds + lane;  // B[e * 64] = basis value e of this lane
   bool inside = valid;
   for (int d = 0; d < k; ++d) {
     const double x = valid ? a.xi[s * a.nxi + a.lv[K * 4 + d]] : 0.0;
     inside = inside && (x >= a.lo && x <= a.hi);
     const double t = 2.0 * (x - a.lo) / (a.hi - a.lo) - 1.0;
-    double* Bd = B + d * a.nb;
+    double* Bd = B + d * a.nb * 64;
     Bd[0] = 1.0;  // level 1
     for (int i = 2; i <= a.level + 1; ++i) {
       const int n = (1 << (i - 1)) + 1, o = a.lofs[i];
@@ -199,36 +205,42 @@ __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
         if (j == 0 || j == n - 1) P *= 0.5;
         for (int e = 0; e < n; ++e)
           if (e != j) P *= t - a.nodes[o + e];
-        Bd[o + j] = P;
+        Bd[(o + j) * 64] = P;
         sum += P;
       }
       const double r = 1.0 / sum;
-      for (int j = 0; j < n; ++j) Bd[o + j] *= r;
+      for (int j = 0; j < n; ++j) Bd[(o + j) * 64] *= r;
     }
   }
   const int64_t p = s * a.npatch + K;
-  if (valid && !inside) {
-    const unsigned long long slot = atomicAdd(a.list_count, 1ull);
-    a.list[slot] = p;
-  }
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = 0.0;
   const double* T = a.table + a.off[K] * 10;
-  const int c1 = a.kofs[k + 1];
-  for (int c = a.kofs[k]; c < c1; ++c) {
-    double w = a.cb_coef[c];
-    const uint32_t bo = a.cb_boff[c];
-    for (int d = 0; d < k; ++d) w *= B[d * a.nb + ((bo >> (8 * d)) & 255u)];
-    const double* Tr = T + (int64_t)a.cb_row[c] * 10;
+  const int32_t* rs = a.cb_rows + a.rofs[k];  // entries of row r: rs[r] .. rs[r+1]-1
+  const int nr = a.rofs[k + 1] - a.rofs[k] - 1;
+  int c = rs[0];
+  for (int r = 0; r < nr; ++r) {
+    const int c1 = rs[r + 1];
+    double wr = 0.0;
+    for (; c < c1; ++c) {
+      double w = a.cb_coef[c];
+      const uint32_t bo = a.cb_boff[c];
+      for (int d = 0; d < k; ++d) w *= B[(d * a.nb + (int)((bo >> (8 * d)) & 255u)) * 64];
+      wr += w;
+    }
+    const double* Tr = T + (int64_t)r * 10;
 #pragma unroll
-    for (int q = 0; q < 10; ++q) acc[q] += w * Tr[q];
+    for (int q = 0; q < 10; ++q) acc[q] += wr * Tr[q];
   }
   if (valid && inside) {
     double* So = a.S + p * 10;
 #pragma unroll
     for (int q = 0; q < 10; ++q) So[q] = acc[q];
     if (a.status) a.status[p] = 0;
+  } else if (valid) {
+    const unsigned long long slot = atomicAdd(a.list_count, 1ull);
+    a.list[slot] = p;
   }
 }
 
