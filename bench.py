@@ -450,6 +450,66 @@ def measure_collocation(log, wl=None, level=4, errors=True, plain_chunk=1024):
     return out
 
 
+def measure_two_level(log, n_H=16384, n_h=512):
+    """Two-level Monte Carlo (Sec. 4.1.1, the remark with eqs. MCmean2level
+    and mseML) on the 8x8 mesh, H/h = 8: n_H coarse StoMsFEM samples
+    (coefficients, upscaling, coarse solve), n_h independent samples with both
+    the coarse and the fine-grid (64 x 64) FEM solution, and the estimator.
+    Reports the times, the per-sample cost ratio of the coarse and fine
+    solves, the estimated sampling part of the MSE, the discretisation bias
+    of the coarse-only mean that the correction removes, and the cost of a
+    fine-grid-only MC with the same sampling error (from the sample
+    variances)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.MESH8
+    xH = torch.from_numpy(W.uniform_xi(n_H, wl.nxi, wl.seed + 11)).cuda()
+    xh = torch.from_numpy(W.uniform_xi(n_h, wl.nxi, wl.seed + 12)).cuda()
+    nU = (wl.nc - 1) ** 2
+    U_H = torch.empty((n_H, nU), dtype=torch.float64, device="cuda")
+    U_Hh = torch.empty((n_h, nU), dtype=torch.float64, device="cuda")
+    u_f = torch.empty((n_h, (wl.nfine - 1) ** 2), dtype=torch.float64, device="cuda")
+
+    def coarse(x, U):
+        a = sm.coef_bumps(x, wl.nfine, **wl.coef_params())
+        sm.coarse_solve(sm.upscale(a, wl.nc, wl.nc, wl.m), wl.nc, wl.nc, U=U)
+        return a
+
+    def fine():
+        a = coarse(xh, U_Hh)
+        sm.fine_solve(a, u=u_f)
+
+    t_H = _timed(lambda: coarse(xH, U_H), reps=3)
+    t_h = _timed(fine, reps=3)
+    t_est = _timed(lambda: sm.two_level_mc(U_H, U_Hh, u_f, wl.nc, wl.m))
+    a_h = sm.coef_bumps(xh, wl.nfine, **wl.coef_params())
+    t_fine_only = _timed(lambda: sm.fine_solve(a_h, u=u_f), reps=3)
+    coarse(xh, U_Hh)
+    sm.fine_solve(a_h, u=u_f)
+    mean, var_H, var_d = sm.two_level_mc(U_H, U_Hh, u_f, wl.nc, wl.m)
+    torch.cuda.synchronize()
+    H2 = 1.0 / wl.nc**2
+    mse = H2 * float((var_H / n_H + var_d / n_h).sum())
+    # fine-grid-only MC with the same sampling error: var[u_h] ~ var[u_H]
+    n_fine_equiv = H2 * float(var_H.sum()) / mse
+    cost_fine_only = n_fine_equiv * t_h / n_h
+    out = {"workload": f"8x8 coarse, H/h=8 (fine 64x64), {n_H} coarse + {n_h} fine samples (bump family)",
+           "coarse_ms": t_H * 1e3, "fine_ms": t_h * 1e3, "fine_solve_ms": t_fine_only * 1e3,
+           "fine_solves_per_s": n_h / t_fine_only, "estimator_ms": t_est * 1e3,
+           "coarse_per_sample_us": t_H / n_H * 1e6, "fine_per_sample_us": t_h / n_h * 1e6,
+           "sampling_mse": mse, "rms_sampling_error": mse ** 0.5,
+           "coarse_only_bias_max": float((U_H.mean(dim=0) - mean).abs().max().item()),
+           "var_ratio_d_over_H": float(var_d.sum().item() / var_H.sum().item()),
+           "fine_only_mc_samples_for_same_error": n_fine_equiv,
+           "fine_only_mc_ms_for_same_error": cost_fine_only * 1e3,
+           "two_level_ms": (t_H + t_h + t_est) * 1e3}
+    log(f"two-level MC: {out}")
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -715,6 +775,8 @@ def main():
         from paper_1607_00693_amd import workloads as W
         out["sparse_grid_collocation"] = {"mesh8_level4": measure_collocation(lg, plain_chunk=1 << 20),
                                           "bench_mesh_level2": measure_collocation(lg, W.MESH32, 2, errors=False)}
+        print("[bench] two-level Monte Carlo at the 8x8 mesh", file=sys.stderr, flush=True)
+        out["two_level_mc"] = measure_two_level(lg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -209,6 +209,34 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
                              double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Fine-grid FEM and the two-level Monte Carlo estimator (Sec. 4.1.1, the
+ * remark with eqs. MCmean2level and mseML).
+ *
+ * stomsfem_fine_solve: the global Q1 FEM on the nfine x nfine fine mesh of
+ * [0,1]^2 (2 <= nfine <= 64) with the piecewise-constant coefficient a
+ * (device [nsamples][nfine][nfine], FP64, element row-major, y outer), f = 1
+ * and zero Dirichlet data: u device [nsamples][(nfine-1)^2], interior fine
+ * nodes in natural order.  It is the coarse system of the m = 1 upscaled
+ * elements (S = a_e K_Q1, load h^2/4 per element node) and runs the upscaling
+ * and coarse-solve kernels in chunks of samples.  status device [nsamples]
+ * or NULL: ENOTSPD if a pivot is not positive (e.g. a <= 0).  Uses the
+ * library workspace; asynchronous on `stream`.
+ *
+ * stomsfem_two_level_mc: per interior coarse node i of the nc x nc mesh,
+ * mean[i] = M[U_H][i] + M[u_h - U_Hh][i] over the two sample sets (U_H device
+ * [n_H][(nc-1)^2]; U_Hh device [n_h][(nc-1)^2] and u_fine device
+ * [n_h][(nc m-1)^2] of the same second set), u_h taken at the fine node
+ * (px m, py m) of coarse node (px, py); var_H[i] and var_d[i] the sample
+ * variances (1/N normalisation) of U_H and of u_h - U_Hh, from which the
+ * sampling part of the MSE is H^2 sum_i (var_H/n_H + var_d/n_h).  Any output
+ * may be NULL.  Fixed summation order.  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double* u, int32_t* status,
+                        void* stream);
+int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, const double* u_fine, int64_t n_h,
+                          int32_t nc, int32_t m, double* mean, double* var_H, double* var_d, void* stream);
+
+/* ------------------------------------------------------------------------
  * Reduced-basis acceleration (Sec. 3.2: eqs. KLphi, localRB, localRBsystem,
  * RBaffine/localAF; Algorithms 3 and 4).
  *

@@ -31,6 +31,8 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
                             double* mean, double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+hipError_t launch_two_level(const double* UH, int64_t nH, const double* UHh, const double* uf, int64_t nh, int nc,
+                            int m, double* mean, double* var_H, double* var_d, hipStream_t st);
 bool upscale_os_supports(int m, int o);
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples);
 size_t coarse_lds_bytes(int ncx, bool pg);
@@ -443,6 +445,55 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
   hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
                                (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve launch");
+}
+
+int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double* u, int32_t* status,
+                        void* stream) {
+  if (nfine < 2 || nfine > 64 || nsamples < 0) return fail(STOMSFEM_EINVAL, "fine_solve: need 2 <= nfine <= 64");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(a) || !device_ptr(u)) return fail(STOMSFEM_EINVAL, "fine_solve: a and u must be device pointers");
+  if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "fine_solve: status must be a device pointer");
+  // the fine FEM is the coarse system of the m = 1 upscaled elements
+  // a_e K_Q1 on the nfine x nfine mesh, with the load h^2/4 per element node
+  const int64_t per = (int64_t)nfine * nfine, nU = (int64_t)(nfine - 1) * (nfine - 1);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nsamples, (int64_t{1} << 27) / (per * 80)));
+  const size_t s_doubles = (size_t)chunk * per * 10;
+  const size_t w_doubles = (size_t)coarse_work_doubles(nfine, nfine, chunk);
+  void* ws = nullptr;
+  int rc = workspace_get(sizeof(double) * (s_doubles + w_doubles), &ws);
+  if (rc != STOMSFEM_OK) return rc;
+  double* Sbuf = (double*)ws;
+  double* work = Sbuf + s_doubles;
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t start = 0; start < nsamples; start += chunk) {
+    const int64_t cnt = std::min(chunk, nsamples - start);
+    UpArgs up{};
+    up.nsamples = cnt;
+    up.ncx = up.ncy = nfine;
+    up.m = 1;
+    up.npairs = cnt * per;
+    up.a = a + start * per;
+    up.S = Sbuf;
+    up.status = nullptr;
+    hipError_t e = launch_upscale_any(up, STOMSFEM_F64, st);
+    if (e == hipSuccess)
+      e = launch_coarse(nfine, nfine, cnt, Sbuf, nullptr, u + start * nU, nullptr, nullptr,
+                        status ? status + start : nullptr, work, st);
+    if (e != hipSuccess) return hip_fail(e, "fine_solve launch");
+  }
+  return STOMSFEM_OK;
+}
+
+int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, const double* u_fine, int64_t n_h,
+                          int32_t nc, int32_t m, double* mean, double* var_H, double* var_d, void* stream) {
+  if (n_H < 1 || n_h < 1 || nc < 2 || m < 1 || (int64_t)nc * m > 65536)
+    return fail(STOMSFEM_EINVAL, "two_level_mc: need n_H, n_h >= 1, nc >= 2, m >= 1");
+  if (!device_ptr(U_H) || !device_ptr(U_Hh) || !device_ptr(u_fine))
+    return fail(STOMSFEM_EINVAL, "two_level_mc: U_H, U_Hh and u_fine must be device pointers");
+  if ((mean && !device_ptr(mean)) || (var_H && !device_ptr(var_H)) || (var_d && !device_ptr(var_d)))
+    return fail(STOMSFEM_EINVAL, "two_level_mc: outputs must be device pointers");
+  hipError_t e = launch_two_level(U_H, n_H, U_Hh, u_fine, n_h, nc, m, mean, var_H, var_d, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "two_level_mc launch");
 }
 
 int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* stream) {

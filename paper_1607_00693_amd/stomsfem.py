@@ -126,6 +126,8 @@ def lib():
         "stomsfem_sgi_build": (C.c_int, [i32, i32, i32, vp, C.POINTER(BumpFamily), i32, dbl, dbl, C.POINTER(vp),
                                          vp]),
         "stomsfem_sgi_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
+        "stomsfem_fine_solve": (C.c_int, [vp, i32, i64, vp, vp, vp]),
+        "stomsfem_two_level_mc": (C.c_int, [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -229,6 +231,30 @@ def coarse_solve(S: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None 
     _check("stomsfem_coarse_solve", lib().stomsfem_coarse_solve(
         ncx, ncy, N, _ptr(S), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
     return U, qoi_mean, qoi_var
+
+
+def fine_solve(a: torch.Tensor, u: torch.Tensor | None = None, status: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Fine-grid FEM solutions u[N][(nfine-1)^2] for a[N][nfine][nfine] (FP64)."""
+    assert a.dtype == torch.float64 and a.is_contiguous() and a.shape[1] == a.shape[2]
+    N, nf = a.shape[0], a.shape[1]
+    if u is None:
+        u = torch.empty((N, (nf - 1) ** 2), dtype=torch.float64, device=a.device)
+    _check("stomsfem_fine_solve", lib().stomsfem_fine_solve(_ptr(a), nf, N, _ptr(u), _ptr(status), _stream(stream)))
+    return u
+
+
+def two_level_mc(U_H: torch.Tensor, U_Hh: torch.Tensor, u_fine: torch.Tensor, nc: int, m: int, stream=None):
+    """Two-level MC estimate (mean, var_H, var_d) at the interior coarse nodes."""
+    for t in (U_H, U_Hh, u_fine):
+        assert t.dtype == torch.float64 and t.is_contiguous()
+    assert U_Hh.shape[0] == u_fine.shape[0] and u_fine.shape[1] == (nc * m - 1) ** 2
+    nU = (nc - 1) ** 2
+    out = [torch.empty(nU, dtype=torch.float64, device=U_H.device) for _ in range(3)]
+    _check("stomsfem_two_level_mc", lib().stomsfem_two_level_mc(
+        _ptr(U_H), U_H.shape[0], _ptr(U_Hh), _ptr(u_fine), U_Hh.shape[0], nc, m, *[_ptr(t) for t in out],
+        _stream(stream)))
+    return tuple(out)
 
 
 def upscale_os(a: torch.Tensor, ncx: int, ncy: int, m: int, oversample: int, S: torch.Tensor | None = None,
