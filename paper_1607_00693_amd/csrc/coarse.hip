@@ -479,6 +479,118 @@ int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
   return coarse_grid(nsamples) * ((int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1) + 1);
 }
 
+// Small square coarse meshes (ncx = ncy = NC <= 8, the symmetric system):
+// one lane per sample.  With NU = (NC-1)^2 unknowns and half-bandwidth
+// B = NC (couplings at offsets 1, NC-2, NC-1, NC), every row, window slot
+// and band offset is a compile-time constant, so the factor window lives in
+// registers.  Row r is assembled from the four elements around its node as
+// in coarse_solve_kernel, then eliminated by Crout's LDL^T,
+//   u_rc = A_rc - sum_{j<c} u_rj l_cj,  l_rc = u_rc / d_c,  d_r = A_rr - sum_c l_rc u_rc,
+// with the forward substitution y_r = b_r - sum_c l_rc y_c alongside.  The
+// band of L and z = D^{-1} y go to the workspace at [(r B + k) n + s] and
+// [(NU B + r) n + s] (coalesced across the lanes), and the backward pass
+// x_r = z_r - sum_{i=r+1}^{r+B} l_ir x_i reads them back.  Status ENOTSPD if
+// a pivot is not positive (or NaN).
+template <int NC>
+__global__ __launch_bounds__(64) void coarse_lane_kernel(CoarseArgs a) {
+  constexpr int n = NC - 1, NU = n * n, B = NC;
+  const int64_t s = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (s >= a.nsamples) return;
+  const int64_t ns = a.nsamples;
+  const double* Ss = a.S + s * (int64_t)(NC * NC * 10);
+  // workspace cursors: the band of L in store order (r B + k), then z
+  double* wl = a.work + s;
+  double* wz = a.work + (int64_t)NU * B * ns + s;
+  const double H = 1.0 / NC;
+  double Lw[B + 1][B];  // Lw[c % (B+1)][k] = l_{c, c-1-k}
+  double Di[B + 1];     // 1 / d_c
+  double Yw[B + 1];     // y_c
+  bool bad = false;
+#pragma clang loop unroll(full)
+  for (int r = 0; r < NU; ++r) {
+    // keeps each row's element-matrix loads next to their use (hoisting all
+    // of them ahead of the elimination would exhaust the registers)
+    asm volatile("" ::: "memory");
+    const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+    const double* sSW = Ss + ((py - 1) * NC + (px - 1)) * 10;
+    const double* sSE = Ss + ((py - 1) * NC + px) * 10;
+    const double* sNW = Ss + (py * NC + (px - 1)) * 10;
+    const double* sNE = Ss + (py * NC + px) * 10;
+    double ar[B + 1];  // ar[t] = A[r][r - t]
+#pragma unroll
+    for (int t = 0; t <= B; ++t) ar[t] = 0.0;
+    ar[0] = (selem(sSW, 2, 2) + selem(sSE, 3, 3)) + (selem(sNW, 1, 1) + selem(sNE, 0, 0));
+    if (ix >= 1) ar[1] += selem(sSW, 3, 2) + selem(sNW, 0, 1);
+    if (iy >= 1 && ix <= n - 2) ar[n - 1] += selem(sSE, 1, 3);
+    if (iy >= 1) ar[n] += selem(sSW, 1, 2) + selem(sSE, 0, 3);
+    if (iy >= 1 && ix >= 1) ar[n + 1] += selem(sSW, 0, 2);
+    double b = H * H;
+    if (a.load) {
+      const double* L = a.load;
+      b = (L[((py - 1) * NC + (px - 1)) * 4 + 2] + L[((py - 1) * NC + px) * 4 + 3]) +
+          (L[(py * NC + (px - 1)) * 4 + 1] + L[(py * NC + px) * 4 + 0]);
+    }
+    double lr[B], ur[B];  // k: column c = r - 1 - k
+#pragma unroll
+    for (int k = B - 1; k >= 0; --k) {
+      const int c = r - 1 - k;
+      if (c < 0) {
+        lr[k] = ur[k] = 0.0;
+        continue;
+      }
+      double v = ar[k + 1];
+#pragma unroll
+      for (int k2 = B - 1; k2 > k; --k2) {
+        if (r - 1 - k2 < 0) continue;
+        v -= ur[k2] * Lw[c % (B + 1)][k2 - k - 1];  // l_{c, j}, j = r - 1 - k2
+      }
+      ur[k] = v;
+      lr[k] = v * Di[c % (B + 1)];
+    }
+    double d = ar[0], y = b;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      if (r - 1 - k < 0) continue;
+      d -= lr[k] * ur[k];
+      y -= lr[k] * Yw[(r - 1 - k) % (B + 1)];
+    }
+    bad = bad || !(d > 0.0);
+    const double di = 1.0 / d;
+    Di[r % (B + 1)] = di;
+    Yw[r % (B + 1)] = y;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      Lw[r % (B + 1)][k] = lr[k];
+      *wl = lr[k];
+      wl += ns;
+    }
+    *wz = y * di;
+    wz += ns;
+  }
+  double X[B + 1];  // x_i, slot i % (B+1)
+#pragma clang loop unroll(full)
+  for (int r = NU - 1; r >= 0; --r) {
+    asm volatile("" ::: "memory");
+    wz -= ns;
+    double x = *wz;
+    // l_{i r} for i = r+1 .. r+B sits at index i B + (i - 1 - r): stride B + 1
+    const double* li = a.work + ((int64_t)r * B + B) * ns + s;
+#pragma unroll
+    for (int i = r + 1; i <= r + B; ++i) {
+      if (i < NU) x -= *li * X[i % (B + 1)];
+      li += (B + 1) * ns;
+    }
+    X[r % (B + 1)] = x;
+    a.U[s * NU + r] = x;
+  }
+  if (a.status) a.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+}
+
+template <int NC>
+static void launch_lane(const CoarseArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(coarse_lane_kernel<NC>, dim3((unsigned)((a.nsamples + 63) / 64)), dim3(64), 0, st, a);
+}
+
 static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                                     double* mean, double* var, int32_t* status, double* work, hipStream_t st,
                                     bool pg) {
@@ -496,6 +608,21 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
       const int64_t n = N - c < chunk ? N - c : chunk;
       CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * ES, load, U + c * (int64_t)nU,
                    status ? status + c : nullptr, work};
+      if (!pg && ncx == ncy && ncx <= 8) {
+        // one lane per sample (the workspace holds n (nU (ncx+1) + 1) doubles)
+        switch (ncx) {
+          case 2: launch_lane<2>(a, st); break;
+          case 3: launch_lane<3>(a, st); break;
+          case 4: launch_lane<4>(a, st); break;
+          case 5: launch_lane<5>(a, st); break;
+          case 6: launch_lane<6>(a, st); break;
+          case 7: launch_lane<7>(a, st); break;
+          default: launch_lane<8>(a, st); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        continue;
+      }
       const dim3 grid((unsigned)n), block(TH);
       if (small) {
         if (pg) {
