@@ -475,8 +475,16 @@ size_t coarse_lds_bytes(int ncx, bool pg) {
 
 int64_t coarse_grid(int64_t nsamples) { return nsamples < 4096 ? nsamples : 4096; }
 
+// Samples per launch: 4096 workgroups for the workgroup-per-sample kernels;
+// the one-lane-per-sample kernel of small square meshes takes up to 65536
+// (1024 wavefronts; its workspace is about 3.5 KB per sample).
+static int64_t coarse_chunk(int ncx, int ncy, int64_t nsamples) {
+  const int64_t cap = (ncx == ncy && ncx <= 8) ? 65536 : 4096;
+  return nsamples < cap ? nsamples : cap;
+}
+
 int64_t coarse_work_doubles(int ncx, int ncy, int64_t nsamples) {
-  return coarse_grid(nsamples) * ((int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1) + 1);
+  return coarse_chunk(ncx, ncy, nsamples) * ((int64_t)(ncx - 1) * (ncy - 1) * (ncx + 1) + 1);
 }
 
 // Small square coarse meshes (ncx = ncy = NC <= 8, the symmetric system):
@@ -603,7 +611,8 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
     const int TH = small ? 64 : COARSE_THREADS;
     const int need = pg ? (ncx * ncx + TH - 1) / TH : (ncx * (ncx + 1) / 2 + TH - 1) / TH;
     const size_t lds = coarse_lds_bytes(ncx, pg);
-    const int64_t chunk = coarse_grid(N);  // samples per launch pair: the workspace holds their factors
+    // samples per launch (pair): the workspace holds their factors
+    const int64_t chunk = (!pg && ncx == ncy && ncx <= 8) ? coarse_chunk(ncx, ncy, N) : coarse_grid(N);
     for (int64_t c = 0; c < N; c += chunk) {
       const int64_t n = N - c < chunk ? N - c : chunk;
       CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * ES, load, U + c * (int64_t)nU,
