@@ -3,18 +3,21 @@
 //   mean[i]  = (1/N_H) sum_s U_H[s][i] + (1/N_h) sum_s (u_h[s][f(i)] - U_Hh[s][i]),
 //   var_H[i] = M[U_H^2] - M[U_H]^2,  var_d[i] = M[d^2] - M[d]^2,
 // d = u_h - U_Hh, f(i) the fine interior node at coarse node (px, py):
-// (py m - 1)(nc m - 1) + (px m - 1).  One workgroup per 64 nodes, four
-// wavefronts over the samples combined in order (a fixed summation order).
+// (py m - 1)(nc m - 1) + (px m - 1).  One workgroup per 64 nodes, sixteen
+// wavefronts over the samples (each with four loads in flight), combined in
+// order: a fixed summation order.
 #include "common.h"
 
 namespace stomsfem {
 
-__global__ __launch_bounds__(256) void two_level_kernel(const double* __restrict__ UH, int64_t nH,
+constexpr int TL_WAVES = 16;
+
+__global__ __launch_bounds__(64 * TL_WAVES) void two_level_kernel(const double* __restrict__ UH, int64_t nH,
                                                         const double* __restrict__ UHh,
                                                         const double* __restrict__ uf, int64_t nh, int nc, int m,
                                                         double* __restrict__ mean, double* __restrict__ var_H,
                                                         double* __restrict__ var_d) {
-  __shared__ double red[4][64][4];
+  __shared__ double red[TL_WAVES][64][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int n1 = nc - 1, nU = n1 * n1;
   const int i = blockIdx.x * 64 + lane;
@@ -23,12 +26,14 @@ __global__ __launch_bounds__(256) void two_level_kernel(const double* __restrict
     const int px = i % n1 + 1, py = i / n1 + 1;
     const int64_t nf1 = (int64_t)nc * m - 1;
     const int64_t fi = (py * (int64_t)m - 1) * nf1 + (px * (int64_t)m - 1);
-    for (int64_t s = wv; s < nH; s += 4) {
+#pragma unroll 4
+    for (int64_t s = wv; s < nH; s += TL_WAVES) {
       const double u = UH[s * nU + i];
       s1H += u;
       s2H += u * u;
     }
-    for (int64_t s = wv; s < nh; s += 4) {
+#pragma unroll 4
+    for (int64_t s = wv; s < nh; s += TL_WAVES) {
       const double d = uf[s * nf1 * nf1 + fi] - UHh[s * nU + i];
       s1d += d;
       s2d += d * d;
@@ -41,8 +46,7 @@ __global__ __launch_bounds__(256) void two_level_kernel(const double* __restrict
   __syncthreads();
   if (wv == 0 && i < nU) {
     double t[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < TL_WAVES; ++v)
 #pragma unroll
       for (int q = 0; q < 4; ++q) t[q] += red[v][lane][q];
     const double mH = t[0] / (double)nH, md = t[2] / (double)nh;
@@ -55,7 +59,8 @@ __global__ __launch_bounds__(256) void two_level_kernel(const double* __restrict
 hipError_t launch_two_level(const double* UH, int64_t nH, const double* UHh, const double* uf, int64_t nh, int nc,
                             int m, double* mean, double* var_H, double* var_d, hipStream_t st) {
   const int nU = (nc - 1) * (nc - 1);
-  hipLaunchKernelGGL(two_level_kernel, dim3((unsigned)((nU + 63) / 64)), dim3(256), 0, st, UH, nH, UHh, uf, nh, nc, m,
+  hipLaunchKernelGGL(two_level_kernel, dim3((unsigned)((nU + 63) / 64)), dim3(64 * TL_WAVES), 0, st, UH, nH, UHh, uf,
+                     nh, nc, m,
                      mean, var_H, var_d);
   return hipGetLastError();
 }
