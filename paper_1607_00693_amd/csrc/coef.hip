@@ -22,7 +22,10 @@ struct CoefArgs {
 // One workgroup per 16 x 16 tile of one sample.  The oscillating factor is
 // separable, sin(2 pi x/eps) sin(2 pi y/eps), so its sines are evaluated once
 // per tile row and column (32 instead of 512 per tile) and shared in LDS;
-// every value is computed by the same expressions as the per-element form.
+// when the whole tile lies in one bump cell (always on meshes whose bump
+// cells are a multiple of 16 elements wide) the candidate bumps are the same
+// for every element, so the cell is passed as a uniform value; every value
+// is computed by the same expressions as the per-element form.
 constexpr int COEF_TILE = 16;
 
 template <typename T>
@@ -48,10 +51,16 @@ __global__ __launch_bounds__(256) void coef_bumps_kernel(CoefArgs c, int tiles_x
       sy[lane - COEF_TILE] = sin(2.0 * M_PI * y / c.eps);
     }
     __syncthreads();
+    // the tile's first and last element centroids in each direction
+    const int x1 = min(tx * COEF_TILE + COEF_TILE - 1, c.nfine - 1), y1 = min(ty * COEF_TILE + COEF_TILE - 1, c.nfine - 1);
+    const int cx0 = bump_cell((tx * COEF_TILE + 0.5) * h, c.g), cx1 = bump_cell((x1 + 0.5) * h, c.g);
+    const int cy0 = bump_cell((ty * COEF_TILE + 0.5) * h, c.g), cy1 = bump_cell((y1 + 0.5) * h, c.g);
+    const bool one_cell = cx0 == cx1 && cy0 == cy1;
     const int ix = tx * COEF_TILE + (lane % COEF_TILE), iy = ty * COEF_TILE + lane / COEF_TILE;
     if (ix < c.nfine && iy < c.nfine) {
       const double x = (ix + 0.5) * h, y = (iy + 0.5) * h;
-      const double field = bump_field(x, y, c.xi + s * c.nxi, bp);
+      const double field = one_cell ? bump_field_cell(x, y, c.xi + s * c.nxi, bp, cx0, cy0)
+                                    : bump_field(x, y, c.xi + s * c.nxi, bp);
       const double osc = c.base + c.amp * sx[lane % COEF_TILE] * sy[lane / COEF_TILE];
       ((T*)c.a)[(s * c.nfine + iy) * (int64_t)c.nfine + ix] = (T)(osc * exp(c.beta * field));
     }

@@ -92,10 +92,13 @@ struct BumpParams {
 // are visited, in increasing index order.
 // (Multiplications by 1/g and 1/rho^2 replace the divisions: exact when g
 // and rho are powers of two, within an ulp otherwise.)
-__device__ __forceinline__ double bump_field(double x, double y, const double* xs, const BumpParams& bp) {
+// The same sum for a point whose centre cell (bx, by) the caller supplies
+// (a workgroup whose points share one cell passes it as a uniform value, so
+// the loop bounds and the xi loads are uniform too).
+__device__ __forceinline__ double bump_field_cell(double x, double y, const double* xs, const BumpParams& bp, int bx,
+                                                  int by) {
   const double ginv = 1.0 / bp.g, rinv2 = 1.0 / (bp.rho * bp.rho);
   const int reach = (int)ceil(bp.rho * bp.g);
-  const int bx = min((int)(x * bp.g), bp.g - 1), by = min((int)(y * bp.g), bp.g - 1);
   double field = 0.0;
   for (int jy = max(by - reach, 0); jy <= min(by + reach, bp.g - 1); ++jy) {
     const double cy = (jy + 0.5) * ginv, dy2 = (y - cy) * (y - cy);
@@ -106,6 +109,13 @@ __device__ __forceinline__ double bump_field(double x, double y, const double* x
     }
   }
   return field;
+}
+
+// centre cell of a point along one axis
+__device__ __forceinline__ int bump_cell(double x, int g) { return min((int)(x * g), g - 1); }
+
+__device__ __forceinline__ double bump_field(double x, double y, const double* xs, const BumpParams& bp) {
+  return bump_field_cell(x, y, xs, bp, bump_cell(x, bp.g), bump_cell(y, bp.g));
 }
 
 // a(x, xi) of the bump family at the point (x, y).
