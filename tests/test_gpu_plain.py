@@ -43,6 +43,21 @@ def u_relerr(U, Uref):
     return (np.linalg.norm(U - Uref, axis=-1) / np.linalg.norm(Uref, axis=-1)).max()
 
 
+@pytest.mark.parametrize("nfine,g,rho", [(100, 3, 0.3), (40, 3, 0.2), (24, 2, 0.4), (64, 4, 0.25)])
+def test_coefficients_on_tiles_inside_and_across_bump_cells(sm, orc, nfine, g, rho):
+    # bump cells of 33.3, 13.3, 12 and 16 elements: 16 x 16 tiles that lie in
+    # one cell and tiles that straddle two, partial tiles at the edge, FP64
+    # and FP32 storage
+    xi = W.uniform_xi(3, g * g, 1950 + nfine)
+    prm = dict(g=g, rho=rho, eps=1.0 / 32, base=2.0, amp=1.8, beta=0.5)
+    a_ref = orc.coef_bumps(xi, nfine, **prm)
+    a = sm.coef_bumps(torch.from_numpy(xi).cuda(), nfine, **prm)
+    a32 = sm.coef_bumps(torch.from_numpy(xi).cuda(), nfine, dtype=torch.float32, **prm)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(a.cpu().numpy(), a_ref, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(a32.cpu().numpy(), a_ref.astype(np.float32), rtol=1e-7, atol=0)
+
+
 def test_mesh8_end_to_end(sm, orc):
     wl = W.MESH8
     say(f"mesh8 end to end: N={wl.nsamples} nc={wl.nc} m={wl.m}")
