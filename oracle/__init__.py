@@ -5,7 +5,8 @@ checked against.  Only the test-suite, the smoke check and the CPU-baseline
 leg of the benchmark may import it; the product package never does, and the
 two share no code.  See ``stomsfem_oracle.c`` for the plain path and
 ``rb.py`` / ``ri.py`` / ``mlp.py`` for the accelerations, ``sc.py`` for
-sparse-grid collocation with dictionaries and ``twolevel.py`` for the
-two-level Monte Carlo estimator.
+sparse-grid collocation with dictionaries, ``twolevel.py`` for the
+two-level Monte Carlo estimator and ``gauss.py`` for the Gaussian medium
+and its local KL parametrization.
 """
 from .core import *  # noqa: F401,F403

@@ -1,0 +1,96 @@
+"""The short-correlation Gaussian medium of Sec. 5.3 and its local KL
+parametrization (Sec. 2.1, eqs. domainpar, localCov, localKL,
+local_KL_truncation).  Test infrastructure only (see package doc).
+
+Medium.  kappa = 0.1 + exp(beta) (eq. mediaEx2), beta a centred Gaussian
+field with covariance exp(-|x1-y1|^2/l1^2 - |x2-y2|^2/l2^2) (eq. betaCov).
+Sampling by the randomized spectral method: with wave vectors w_j whose
+components are N(0, 2/l^2) (the covariance is the characteristic function
+of that normal law) and phases phi_j uniform on [0, 2 pi),
+  beta(x) = sqrt(2/J) sum_j cos(w_j . x + phi_j),
+which has exactly this covariance for any J and is Gaussian as J grows.
+The draws come in as standard normals z and uniforms u: w_j = sqrt(2) (z_j1/l1,
+z_j2/l2), phi_j = 2 pi u_j.  The field is taken at element centroids.
+
+Local KL.  The patches are the coarse elements (non-overlapping, eq.
+domainpar).  On the m x m centroids of a patch the discrete eigenproblem of
+the covariance matrix C (dense, m^2 x m^2) with the L2 inner product h^2 sum
+gives eigenvalues lambda = h^2 mu and modes f = v / h for the eigenpairs
+(mu, v) of C (v of unit length), so that
+  xi_k = (1/sqrt(lambda_k)) int (beta - 0) f_k = v_k . beta / sqrt(mu_k),
+  beta ~ sum_{k <= K} sqrt(mu_k) xi_k v_k     (eqs. localKL, local_KL_truncation),
+the KL being applied to the Gaussian field beta (kappa is non-affine in xi).
+The covariance is translation invariant, so one set of modes serves every
+patch.  Outside the box |xi_k| <= 3 the interpolant is not used (the plain
+path is); for independent standard normal xi_k the probability of that is
+1 - P(|Z| <= 3)^K.
+"""
+from __future__ import annotations
+
+from math import erf, sqrt
+
+import numpy as np
+
+
+def field(z: np.ndarray, u: np.ndarray, nfine: int, l1: float, l2: float) -> np.ndarray:
+    """beta [N][nfine][nfine] (rows = y) at the element centroids."""
+    N, J, _ = z.shape
+    c = (np.arange(nfine) + 0.5) / nfine
+    X, Y = np.meshgrid(c, c)
+    out = np.zeros((N, nfine, nfine))
+    for s in range(N):
+        acc = np.zeros((nfine, nfine))
+        for j in range(J):
+            w1 = sqrt(2.0) * z[s, j, 0] / l1
+            w2 = sqrt(2.0) * z[s, j, 1] / l2
+            acc += np.cos(w1 * X + w2 * Y + 2.0 * np.pi * u[s, j])
+        out[s] = sqrt(2.0 / J) * acc
+    return out
+
+
+def kappa(beta: np.ndarray) -> np.ndarray:
+    return 0.1 + np.exp(beta)
+
+
+def patch_covariance(m: int, h: float, l1: float, l2: float) -> np.ndarray:
+    """Dense covariance of beta between the m^2 centroids of one patch
+    (row-major: index = iy m + ix)."""
+    c = (np.arange(m) + 0.5) * h
+    X, Y = np.meshgrid(c, c)
+    x, y = X.ravel(), Y.ravel()
+    return np.exp(-((x[:, None] - x[None, :]) ** 2) / l1**2 - ((y[:, None] - y[None, :]) ** 2) / l2**2)
+
+
+def local_kl(m: int, h: float, l1: float, l2: float, K: int):
+    """(mu [K], V [K][m][m], captured fraction) of the K largest eigenpairs
+    of the dense patch covariance (numpy eigh as the library step)."""
+    C = patch_covariance(m, h, l1, l2)
+    mu, V = np.linalg.eigh(C)
+    order = np.argsort(mu)[::-1]
+    mu, V = mu[order], V[:, order]
+    return mu[:K], V[:, :K].T.reshape(K, m, m), float(mu[:K].sum() / mu.sum())
+
+
+def project(beta: np.ndarray, nc: int, m: int, mu: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """xi [N][nc*nc][K] of every patch (element K = ky nc + kx)."""
+    N = beta.shape[0]
+    Kt = len(mu)
+    xi = np.zeros((N, nc * nc, Kt))
+    for ky in range(nc):
+        for kx in range(nc):
+            blk = beta[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m].reshape(N, -1)
+            for k in range(Kt):
+                xi[:, ky * nc + kx, k] = blk @ V[k].ravel() / np.sqrt(mu[k])
+    return xi
+
+
+def truncated_kappa_blocks(xi: np.ndarray, mu: np.ndarray, V: np.ndarray, K: int) -> np.ndarray:
+    """kappa on every (sample, patch) from its first K local parameters:
+    [N][P][m][m] = 0.1 + exp(sum_{k<K} sqrt(mu_k) xi_k V_k)."""
+    b = np.einsum("npk,kij->npij", xi[:, :, :K] * np.sqrt(mu[:K]), V[:K])
+    return 0.1 + np.exp(b)
+
+
+def outside_probability(K: int, box: float = 3.0) -> float:
+    """1 - P(|Z| <= box)^K for independent standard normals."""
+    return 1.0 - erf(box / sqrt(2.0)) ** K

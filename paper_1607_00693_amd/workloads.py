@@ -152,3 +152,44 @@ def batch_m(wl: ChannelWorkload = CHANNELS64) -> np.ndarray:
     """H/h of each batch, drawn uniformly from wl.m_choices."""
     rng = np.random.default_rng(wl.m_seed)
     return np.asarray(wl.m_choices)[rng.integers(0, len(wl.m_choices), size=wl.nbatch)].astype(np.int32)
+
+
+@dataclasses.dataclass(frozen=True)
+class GaussWorkload:
+    """Stand-in for the short-correlation Gaussian medium of Sec. 5.3:
+    kappa = 0.1 + exp(beta), beta a centred Gaussian field with covariance
+    exp(-dx^2/l1^2 - dy^2/l2^2), sampled by the randomized spectral method
+    with nterms cosines; coarse elements of H = 1/nc span H/l2 = 2
+    correlation lengths in y (the paper's oversampled patch of 2H with
+    l2 = H: two lengths; four local KL terms then hold >= 99%)."""
+    name: str = "gauss16"
+    nc: int = 16
+    m: int = 16
+    l1: float = 1.0
+    l2: float = 1.0 / 32
+    nterms: int = 256
+    nsamples: int = 1024
+    kl_terms: int = 4
+    box: float = 3.0
+    seed: int = 5005
+
+    @property
+    def nfine(self) -> int:
+        return self.nc * self.m
+
+    @property
+    def M(self) -> int:
+        return self.nc * self.nc
+
+
+GAUSS16 = GaussWorkload()
+
+
+def spectral_draws(nsamples: int, nterms: int, seed: int):
+    """Random numbers of the spectral method: standard normals z
+    [nsamples][nterms][2] (the wave vectors before scaling) and uniforms u
+    [nsamples][nterms] on [0, 1) (the phases before scaling by 2 pi)."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(size=(nsamples, nterms, 2))
+    u = rng.uniform(0.0, 1.0, size=(nsamples, nterms))
+    return z, u

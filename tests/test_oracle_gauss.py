@@ -1,0 +1,86 @@
+"""Pins of the oracle's Gaussian medium and local KL parametrization (Sec.
+5.3 with Sec. 2.1's local KL, eqs. localKL and local_KL_truncation): the
+paper's fallback probability, the spectral field's variance and covariance
+against eq. betaCov (Monte Carlo), the dense local KL against the separable
+product of one-dimensional eigenproblems, orthonormal modes and the trace,
+exact recovery of synthesized parameters, the mean truncation error against
+the discarded eigenvalues, and the fallback rate of the spectral field."""
+import numpy as np
+import pytest
+
+from oracle import gauss
+from paper_1607_00693_amd import workloads as W
+
+
+def test_fallback_probability_is_the_papers():
+    # Sec. 5.3: four local parameters, box [-3, 3], interpolation used with
+    # probability 0.9892 and the fine solve with probability 0.0108
+    assert round(gauss.outside_probability(4, 3.0), 4) == 0.0108
+    assert round(1 - gauss.outside_probability(4, 3.0), 4) == 0.9892
+
+
+def test_spectral_field_has_the_gaussian_covariance():
+    l1, l2, nf, N = 0.5, 0.1, 32, 600
+    z, u = W.spectral_draws(N, 128, 71)
+    b = gauss.field(z, u, nf, l1, l2)
+    se = np.sqrt(2.0 / N)
+    assert abs(b.var(axis=0).mean() - 1.0) < 4.5 * se / 8  # averaged over the grid
+    assert abs(b.mean()) < 0.1
+    h = 1.0 / nf
+    for d in (1, 2, 4):
+        cx = (b[:, :, :-d] * b[:, :, d:]).mean()
+        cy = (b[:, :-d, :] * b[:, d:, :]).mean()
+        assert abs(cx - np.exp(-(d * h) ** 2 / l1**2)) < 0.1
+        assert abs(cy - np.exp(-(d * h) ** 2 / l2**2)) < 0.1
+
+
+def test_local_kl_is_the_separable_product():
+    m, h, l1, l2 = 12, 1.0 / 96, 1.0, 1.0 / 48
+    mu, V, frac = gauss.local_kl(m, h, l1, l2, 8)
+    c = (np.arange(m) + 0.5) * h
+    ex = np.linalg.eigvalsh(np.exp(-((c[:, None] - c[None, :]) ** 2) / l1**2))
+    ey = np.linalg.eigvalsh(np.exp(-((c[:, None] - c[None, :]) ** 2) / l2**2))
+    prod = np.sort(np.outer(ex, ey).ravel())[::-1]
+    np.testing.assert_allclose(mu, prod[:8], rtol=1e-10, atol=1e-12 * prod[0])
+    G = V.reshape(8, -1) @ V.reshape(8, -1).T
+    np.testing.assert_allclose(G, np.eye(8), atol=1e-12)
+    assert abs(prod.sum() - m * m) < 1e-9 * m * m  # unit variance: trace = m^2
+    assert 0.99 < frac < 1.0
+
+
+def test_projection_recovers_synthesized_parameters():
+    nc, m, K = 3, 8, 5
+    mu, V, _ = gauss.local_kl(m, 1.0 / (nc * m), 1.0, 1.0 / 48, K)
+    xi = np.random.default_rng(3).normal(size=(2, nc * nc, K))
+    beta = np.zeros((2, nc * m, nc * m))
+    for ky in range(nc):
+        for kx in range(nc):
+            beta[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m] = np.einsum(
+                "nk,kij->nij", xi[:, ky * nc + kx] * np.sqrt(mu), V)
+    np.testing.assert_allclose(gauss.project(beta, nc, m, mu, V), xi, rtol=0, atol=1e-12)
+
+
+def test_truncation_error_matches_the_discarded_spectrum_and_the_fallback_rate():
+    wl = W.GAUSS16
+    nc, m = 8, wl.m  # half the mesh, same element size and correlation lengths
+    nf = nc * m
+    # the workload's correlation lengths in element units, on a mesh of nc x nc elements of [0, 1]
+    l1, l2 = wl.l1 * wl.nc / nc, wl.l2 * wl.nc / nc
+    mu_all, V_all, _ = gauss.local_kl(m, 1.0 / nf, l1, l2, 8)
+    N = 120
+    z, u = W.spectral_draws(N, wl.nterms, 72)
+    beta = gauss.field(z, u, nf, l1, l2)
+    xi_all = gauss.project(beta, nc, m, mu_all, V_all)
+    # mean squared truncation error of beta per patch = sum of the discarded mu
+    for K in (2, 4, 6):
+        b_K = np.einsum("npk,kij->npij", xi_all[:, :, :K] * np.sqrt(mu_all[:K]), V_all[:K])
+        blocks = np.stack([beta[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m]
+                           for ky in range(nc) for kx in range(nc)], axis=1)
+        mse = ((blocks - b_K) ** 2).sum(axis=(2, 3)).mean()
+        ref = m * m - mu_all[:K].sum()  # trace (unit variance) minus the kept part
+        assert abs(mse - ref) < 0.15 * ref + 1e-12, (K, mse, ref)
+    # pairs with a parameter outside [-3, 3] among the first four
+    out = (np.abs(xi_all[:, :, :4]) > 3.0).any(axis=2)
+    p = gauss.outside_probability(4)
+    n = out.size
+    assert abs(out.mean() - p) < 4.5 * np.sqrt(p * (1 - p) / n) + 0.003
