@@ -510,6 +510,62 @@ def measure_two_level(log, n_H=16384, n_h=512):
     return out
 
 
+def measure_gauss(log, N=1024, n_trunc=64):
+    """The short-correlation Gaussian medium (Sec. 5.3) on a 16x16 coarse
+    mesh with H/h = 16 and its local KL on the coarse elements: field
+    generation (randomized spectral method, 256 terms) and projection to the
+    local parameters for N samples; the rate of pairs with a parameter
+    outside [-3, 3] among the four kept ones against 1 - P(|Z| <= 3)^4 =
+    0.0108; and, on n_trunc samples, the error of S and of the coarse
+    solution when kappa is replaced by its truncated local KL with K terms
+    (eq. local_KL_truncation)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.GAUSS16
+    z, u = W.spectral_draws(N, wl.nterms, wl.seed)
+    z, u = torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda()
+    t_field = _timed(lambda: sm.coef_gauss(z, u, wl.nfine, wl.l1, wl.l2, with_beta=True), reps=3)
+    kap, beta = sm.coef_gauss(z, u, wl.nfine, wl.l1, wl.l2, with_beta=True)
+    Kmax = 8
+    mu, V, cap = sm.local_kl(wl.m, 1.0 / wl.nfine, wl.l1, wl.l2, Kmax)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    mu4, V4 = mu_d[:wl.kl_terms].contiguous(), V_d[:wl.kl_terms].contiguous()
+    t_proj = _timed(lambda: sm.kl_project(beta, wl.nc, wl.m, mu4, V4, wl.box))
+    _, _, count = sm.kl_project(beta, wl.nc, wl.m, mu4, V4, wl.box)
+    pairs = N * wl.M
+    rate = int(count.item()) / pairs
+    p_ref = 1.0 - math.erf(wl.box / math.sqrt(2.0)) ** wl.kl_terms
+    n = n_trunc
+    xi, _, _ = sm.kl_project(beta[:n].contiguous(), wl.nc, wl.m, mu_d, V_d, wl.box)
+    S_full = sm.upscale(kap[:n].contiguous(), wl.nc, wl.nc, wl.m)
+    U_full, _, _ = sm.coarse_solve(S_full, wl.nc, wl.nc)
+    scale = S_full.abs().amax(dim=2)
+    trunc = {}
+    for K in (1, 2, 3, 4, 6, 8):
+        S_t = sm.upscale(sm.kl_blocks(xi, mu_d, V_d, K), 1, 1, wl.m).reshape(n, wl.M, 10)
+        U_t, _, _ = sm.coarse_solve(S_t, wl.nc, wl.nc)
+        trunc[f"K_{K}"] = {
+            "captured": float(mu[:K].sum() / (wl.m * wl.m)),
+            "max_S_rel_err": float(((S_t - S_full).abs().amax(dim=2) / scale).max().item()),
+            "max_coarse_rel_err": float((torch.linalg.norm(U_t - U_full, dim=1) /
+                                         torch.linalg.norm(U_full, dim=1)).max().item())}
+    out = {"workload": (f"kappa = 0.1 + exp(beta), Gaussian beta (l1={wl.l1}, l2={wl.l2}, {wl.nterms} spectral "
+                        f"terms), {wl.nc}x{wl.nc} coarse, H/h={wl.m}, local KL on the coarse elements"),
+           "samples": N, "field_ms": t_field * 1e3, "field_elements_per_s": N * wl.nfine**2 / t_field,
+           "projection_ms": t_proj * 1e3, "pairs_per_s_projection": pairs / t_proj,
+           "kept_fraction_4_terms": float(mu[:4].sum() / (wl.m * wl.m)),
+           "outside_rate": rate, "outside_rate_gaussian": p_ref,
+           "truncation": trunc}
+    log(f"gaussian medium: {out}")
+    return out
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -777,6 +833,8 @@ def main():
                                           "bench_mesh_level2": measure_collocation(lg, W.MESH32, 2, errors=False)}
         print("[bench] two-level Monte Carlo at the 8x8 mesh", file=sys.stderr, flush=True)
         out["two_level_mc"] = measure_two_level(lg)
+        print("[bench] Gaussian medium and local KL", file=sys.stderr, flush=True)
+        out["gaussian_local_kl"] = measure_gauss(lg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

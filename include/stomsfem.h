@@ -209,6 +209,50 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
                              double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The short-correlation Gaussian medium of Sec. 5.3 (eqs. mediaEx2,
+ * betaCov) and its local KL parametrization on the coarse elements (Sec. 2.1,
+ * eqs. domainpar, localKL, local_KL_truncation).
+ *
+ * stomsfem_coef_gauss: kappa = 0.1 + exp(beta) at the element centroids of
+ * the nfine x nfine grid, beta(x) = sqrt(2/J) sum_j cos(w_j . x + phi_j)
+ * (randomized spectral method for the covariance
+ * exp(-dx^2/l1^2 - dy^2/l2^2)) with w_j = sqrt(2) (z[s][j][0]/l1,
+ * z[s][j][1]/l2) and phi_j = 2 pi u[s][j]; z device [nsamples][J][2]
+ * (standard normals), u device [nsamples][J] (uniform on [0, 1)), 1 <= J =
+ * nterms <= 1024.  kappa device [nsamples][nfine][nfine]; beta (same shape)
+ * may be NULL.  Asynchronous.
+ *
+ * stomsfem_local_kl (host only, needs no GPU): the K (<= 16) leading
+ * eigenpairs of the covariance of beta between the m x m element centroids
+ * (spacing h) of one coarse element: mu (host [K], descending) and unit
+ * modes (host [K][m][m], row = y), from the separable structure (products
+ * of the eigenpairs of the two one-dimensional m x m covariance matrices);
+ * the discrete KL is beta ~ sum_k sqrt(mu_k) xi_k modes_k with
+ * xi_k = modes_k . beta / sqrt(mu_k).  captured (host, may be NULL) = the
+ * kept fraction of the trace.  Mode signs are arbitrary.
+ *
+ * stomsfem_kl_project: xi device [nsamples][nc*nc][K] of every (sample,
+ * coarse element) from beta device [nsamples][nc m][nc m] with mu, modes
+ * (device copies of the local_kl outputs); outside device [nsamples][nc*nc]
+ * (may be NULL) = 1 where some |xi_k| > box; count (device uint64, may be
+ * NULL) receives the number of such pairs (cleared first).  Asynchronous.
+ *
+ * stomsfem_kl_blocks: the truncated coefficient 0.1 + exp(sum_{k < Kuse}
+ * sqrt(mu_k) xi_k modes_k) on every pair's element, blocks device
+ * [npairs][m][m], from xi device [npairs][K]; the blocks are a batch of
+ * 1 x 1 meshes for stomsfem_upscale.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+int stomsfem_coef_gauss(int64_t nsamples, int32_t nfine, int32_t nterms, const double* z, const double* u, double l1,
+                        double l2, double* beta, double* kappa, void* stream);
+int stomsfem_local_kl(int32_t m, double h, double l1, double l2, int32_t K, double* mu, double* modes,
+                      double* captured);
+int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* beta, int32_t K, const double* mu,
+                        const double* modes, double box, double* xi, int32_t* outside, uint64_t* count,
+                        void* stream);
+int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const double* xi, const double* mu,
+                       const double* modes, double* blocks, void* stream);
+
+/* ------------------------------------------------------------------------
  * Fine-grid FEM and the two-level Monte Carlo estimator (Sec. 4.1.1, the
  * remark with eqs. MCmean2level and mseML).
  *

@@ -31,6 +31,14 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
                             double* mean, double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+hipError_t launch_gauss_field(int64_t nsamples, int nfine, int J, const double* z, const double* u, double l1,
+                              double l2, double* beta, double* kappa, hipStream_t st);
+void local_kl_modes(int m, double h, double l1, double l2, int K, double* mu, double* modes, double* captured);
+hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double* beta, const double* mu,
+                             const double* modes, double box, double* xi, int32_t* outside,
+                             unsigned long long* count, hipStream_t st);
+hipError_t launch_kl_blocks(int64_t npairs, int m, int Kuse, int K, const double* xi, const double* mu,
+                            const double* modes, double* blocks, hipStream_t st);
 hipError_t launch_two_level(const double* UH, int64_t nH, const double* UHh, const double* uf, int64_t nh, int nc,
                             int m, double* mean, double* var_H, double* var_d, hipStream_t st);
 bool upscale_os_supports(int m, int o);
@@ -494,6 +502,54 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
     return fail(STOMSFEM_EINVAL, "two_level_mc: outputs must be device pointers");
   hipError_t e = launch_two_level(U_H, n_H, U_Hh, u_fine, n_h, nc, m, mean, var_H, var_d, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "two_level_mc launch");
+}
+
+int stomsfem_coef_gauss(int64_t nsamples, int32_t nfine, int32_t nterms, const double* z, const double* u, double l1,
+                        double l2, double* beta, double* kappa, void* stream) {
+  if (nsamples < 0 || nfine < 1 || nterms < 1 || nterms > 1024 || !(l1 > 0) || !(l2 > 0))
+    return fail(STOMSFEM_EINVAL, "coef_gauss: need nfine >= 1, 1 <= nterms <= 1024, l1, l2 > 0");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(z) || !device_ptr(u) || !device_ptr(kappa) || (beta && !device_ptr(beta)))
+    return fail(STOMSFEM_EINVAL, "coef_gauss: z, u, kappa (and beta) must be device pointers");
+  hipError_t e = launch_gauss_field(nsamples, nfine, nterms, z, u, l1, l2, beta, kappa, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coef_gauss launch");
+}
+
+int stomsfem_local_kl(int32_t m, double h, double l1, double l2, int32_t K, double* mu, double* modes,
+                      double* captured) {
+  if (m < 1 || m > 64 || K < 1 || K > 16 || K > m * m || !(h > 0) || !(l1 > 0) || !(l2 > 0))
+    return fail(STOMSFEM_EINVAL, "local_kl: need 1 <= m <= 64, 1 <= K <= min(16, m*m), h, l1, l2 > 0");
+  if (!mu || !modes) return fail(STOMSFEM_EINVAL, "local_kl: NULL output");
+  local_kl_modes(m, h, l1, l2, K, mu, modes, captured);
+  return STOMSFEM_OK;
+}
+
+int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* beta, int32_t K, const double* mu,
+                        const double* modes, double box, double* xi, int32_t* outside, uint64_t* count,
+                        void* stream) {
+  if (nsamples < 0 || nc < 1 || m < 1 || K < 1 || K > 16 || K > m * m || !(box > 0))
+    return fail(STOMSFEM_EINVAL, "kl_project: need nc, m >= 1, 1 <= K <= min(16, m*m), box > 0");
+  if (!device_ptr(beta) || !device_ptr(mu) || !device_ptr(modes) || !device_ptr(xi) ||
+      (outside && !device_ptr(outside)) || (count && !device_ptr(count)))
+    return fail(STOMSFEM_EINVAL, "kl_project: arrays must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (count) e = launch_zero_u64((unsigned long long*)count, st);
+  if (e == hipSuccess)
+    e = launch_kl_project(nsamples * (int64_t)nc * nc, nc, m, K, beta, mu, modes, box, xi, outside,
+                          (unsigned long long*)count, st);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "kl_project launch");
+}
+
+int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const double* xi, const double* mu,
+                       const double* modes, double* blocks, void* stream) {
+  if (npairs < 0 || m < 1 || K < 1 || K > 16 || Kuse < 0 || Kuse > K)
+    return fail(STOMSFEM_EINVAL, "kl_blocks: need m >= 1, 1 <= K <= 16, 0 <= Kuse <= K");
+  if (npairs == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi) || !device_ptr(mu) || !device_ptr(modes) || !device_ptr(blocks))
+    return fail(STOMSFEM_EINVAL, "kl_blocks: arrays must be device pointers");
+  hipError_t e = launch_kl_blocks(npairs, m, Kuse, K, xi, mu, modes, blocks, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "kl_blocks launch");
 }
 
 int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* stream) {

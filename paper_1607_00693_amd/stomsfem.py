@@ -128,6 +128,10 @@ def lib():
         "stomsfem_sgi_apply": (C.c_int, [vp, vp, i32, i64, vp, vp, C.POINTER(i64), vp]),
         "stomsfem_fine_solve": (C.c_int, [vp, i32, i64, vp, vp, vp]),
         "stomsfem_two_level_mc": (C.c_int, [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp]),
+        "stomsfem_coef_gauss": (C.c_int, [i64, i32, i32, vp, vp, dbl, dbl, vp, vp, vp]),
+        "stomsfem_local_kl": (C.c_int, [i32, dbl, dbl, dbl, i32, vp, vp, vp]),
+        "stomsfem_kl_project": (C.c_int, [i64, i32, i32, vp, i32, vp, vp, dbl, vp, vp, vp, vp]),
+        "stomsfem_kl_blocks": (C.c_int, [i64, i32, i32, i32, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,6 +235,55 @@ def coarse_solve(S: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None 
     _check("stomsfem_coarse_solve", lib().stomsfem_coarse_solve(
         ncx, ncy, N, _ptr(S), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
     return U, qoi_mean, qoi_var
+
+
+def coef_gauss(z: torch.Tensor, u: torch.Tensor, nfine: int, l1: float, l2: float, with_beta: bool = False,
+               stream=None):
+    """Gaussian medium kappa[N][nfine][nfine] (and beta if asked) from the
+    spectral draws z[N][J][2], u[N][J]."""
+    assert z.dtype == torch.float64 and u.dtype == torch.float64 and z.is_contiguous() and u.is_contiguous()
+    N, J = u.shape
+    kappa = torch.empty((N, nfine, nfine), dtype=torch.float64, device=z.device)
+    beta = torch.empty_like(kappa) if with_beta else None
+    _check("stomsfem_coef_gauss", lib().stomsfem_coef_gauss(N, nfine, J, _ptr(z), _ptr(u), l1, l2, _ptr(beta),
+                                                           _ptr(kappa), _stream(stream)))
+    return (kappa, beta) if with_beta else kappa
+
+
+def local_kl(m: int, h: float, l1: float, l2: float, K: int):
+    """Host local KL of one coarse element: (mu [K], modes [K][m][m], captured)."""
+    import numpy as np
+
+    mu = np.zeros(K)
+    modes = np.zeros((K, m, m))
+    cap = C.c_double(0.0)
+    _check("stomsfem_local_kl", lib().stomsfem_local_kl(m, h, l1, l2, K, mu.ctypes.data_as(C.c_void_p),
+                                                       modes.ctypes.data_as(C.c_void_p), C.byref(cap)))
+    return mu, modes, cap.value
+
+
+def kl_project(beta: torch.Tensor, nc: int, m: int, mu: torch.Tensor, modes: torch.Tensor, box: float = 3.0,
+               stream=None):
+    """(xi [N][nc*nc][K], outside [N][nc*nc] int32, number of outside pairs)."""
+    N = beta.shape[0]
+    K = mu.shape[0]
+    xi = torch.empty((N, nc * nc, K), dtype=torch.float64, device=beta.device)
+    outside = torch.empty((N, nc * nc), dtype=torch.int32, device=beta.device)
+    count = torch.zeros(1, dtype=torch.int64, device=beta.device)
+    _check("stomsfem_kl_project", lib().stomsfem_kl_project(N, nc, m, _ptr(beta), K, _ptr(mu), _ptr(modes), box,
+                                                           _ptr(xi), _ptr(outside), _ptr(count), _stream(stream)))
+    return xi, outside, count
+
+
+def kl_blocks(xi: torch.Tensor, mu: torch.Tensor, modes: torch.Tensor, Kuse: int, stream=None) -> torch.Tensor:
+    """Truncated-KL coefficient blocks [npairs][m][m] for xi [..][K]."""
+    K = mu.shape[0]
+    m = modes.shape[-1]
+    x = xi.reshape(-1, K)
+    blocks = torch.empty((x.shape[0], m, m), dtype=torch.float64, device=xi.device)
+    _check("stomsfem_kl_blocks", lib().stomsfem_kl_blocks(x.shape[0], m, Kuse, K, _ptr(x), _ptr(mu), _ptr(modes),
+                                                         _ptr(blocks), _stream(stream)))
+    return blocks
 
 
 def fine_solve(a: torch.Tensor, u: torch.Tensor | None = None, status: torch.Tensor | None = None,

@@ -1,0 +1,125 @@
+"""The Gaussian medium of Sec. 5.3 and its local KL parametrization on the
+GPU against the oracle: the spectral field and kappa, the projection to local
+parameters (modes from each side's own eigensolve, signs aligned), the
+out-of-box flags and count, the truncated non-affine coefficient, the
+upscaled stiffness on it, and the fallback rate at the workload's scale.
+
+Tolerances: beta 1e-12 absolute (sums of up to 256 FP64 cosines of O(1)
+arguments on both sides); kappa, xi and the truncated blocks 1e-10
+relative; S 1e-10 relative per pair (the plain-path bound)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import core, gauss
+from paper_1607_00693_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-gauss] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sm():
+    from paper_1607_00693_amd import stomsfem
+    assert torch.cuda.is_available()
+    stomsfem.lib()
+    return stomsfem
+
+
+@pytest.mark.parametrize("N,nf,J", [(2, 48, 64), (3, 40, 7), (1, 256, 256)])
+def test_field_matches_oracle(sm, N, nf, J):
+    say(f"field N={N} nf={nf} J={J}")
+    z, u = W.spectral_draws(N, J, 2000 + nf)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, 1.0, 1.0 / 32,
+                              with_beta=True)
+    b_ref = gauss.field(z, u, nf, 1.0, 1.0 / 32)
+    assert np.abs(beta.cpu().numpy() - b_ref).max() < 1e-12
+    np.testing.assert_allclose(kap.cpu().numpy(), gauss.kappa(b_ref), rtol=1e-10, atol=0)
+
+
+def _setup(sm, wl, N, seed, K=None):
+    K = K or wl.kl_terms
+    z, u = W.spectral_draws(N, wl.nterms, seed)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), wl.nfine, wl.l1, wl.l2,
+                              with_beta=True)
+    mu, V, _ = sm.local_kl(wl.m, 1.0 / wl.nfine, wl.l1, wl.l2, K)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    return z, u, kap, beta, mu, V, mu_d, V_d
+
+
+def test_projection_and_truncated_coefficient_match_oracle(sm):
+    wl = W.GAUSS16
+    N, K = 3, 6
+    z, u, kap, beta, mu, V, mu_d, V_d = _setup(sm, wl, N, 2101, K)
+    xi, outside, count = sm.kl_project(beta, wl.nc, wl.m, mu_d, V_d, wl.box)
+    b_ref = gauss.field(z, u, wl.nfine, wl.l1, wl.l2)
+    mu_r, V_r, _ = gauss.local_kl(wl.m, 1.0 / wl.nfine, wl.l1, wl.l2, K)
+    xi_r = gauss.project(b_ref, wl.nc, wl.m, mu_r, V_r)
+    sign = np.sign(np.einsum("kij,kij->k", V, V_r))
+    xi = xi.cpu().numpy()
+    np.testing.assert_allclose(xi, xi_r * sign, rtol=0, atol=1e-10 * np.abs(xi_r).max())
+    out_r = (np.abs(xi_r) > wl.box).any(axis=2)
+    assert (outside.cpu().numpy() == out_r).all() and int(count.item()) == int(out_r.sum())
+    for Kuse in (1, 4, 6):
+        blk = sm.kl_blocks(torch.from_numpy(xi).cuda(), mu_d, V_d, Kuse).cpu().numpy()
+        ref = gauss.truncated_kappa_blocks(xi_r, mu_r, V_r, Kuse).reshape(blk.shape)
+        np.testing.assert_allclose(blk, ref, rtol=1e-10, atol=0)
+
+
+def test_stiffness_on_the_truncated_coefficient(sm):
+    # S of the truncated (non-affine) coefficient through the plain upscaling
+    # kernels on 1 x 1 meshes, and S of the sample itself; both against the
+    # oracle, and the truncation error falling with the number of terms
+    wl = W.GAUSS16
+    N, K = 2, 6
+    z, u, kap, beta, mu, V, mu_d, V_d = _setup(sm, wl, N, 2102, K)
+    xi, _, _ = sm.kl_project(beta, wl.nc, wl.m, mu_d, V_d, wl.box)
+    S_full = sm.upscale(kap, wl.nc, wl.nc, wl.m).cpu().numpy().reshape(-1, 10)
+    k_ref = gauss.kappa(gauss.field(z, u, wl.nfine, wl.l1, wl.l2))
+    S_full_ref, _, _ = core.upscale(k_ref, wl.nc, wl.nc, wl.m)
+    S_full_ref = S_full_ref.reshape(-1, 10)
+    scale = np.abs(S_full_ref).max(axis=1)
+    assert (np.abs(S_full - S_full_ref).max(axis=1) / scale).max() < 1e-10
+    err = []
+    for Kuse in (1, 2, 4, 6):
+        blk = sm.kl_blocks(xi, mu_d, V_d, Kuse)
+        S_t = sm.upscale(blk, 1, 1, wl.m).cpu().numpy().reshape(-1, 10)
+        S_t_ref, _, _ = core.upscale(blk.cpu().numpy(), 1, 1, wl.m)
+        assert (np.abs(S_t - S_t_ref.reshape(-1, 10)).max(axis=1) / scale).max() < 1e-10
+        err.append((np.abs(S_t - S_full).max(axis=1) / scale).max())
+    say(f"  truncation error of S for 1, 2, 4, 6 terms: {err}")
+    assert err[0] > err[1] > err[2] > err[3]
+
+
+def test_fallback_rate_at_the_workload_scale(sm):
+    wl = W.GAUSS16
+    N = 256
+    say(f"fallback rate N={N}")
+    _, _, _, beta, mu, V, mu_d, V_d = _setup(sm, wl, N, 2103)
+    _, outside, count = sm.kl_project(beta, wl.nc, wl.m, mu_d, V_d, wl.box)
+    n = N * wl.M
+    rate = int(count.item()) / n
+    p = gauss.outside_probability(wl.kl_terms, wl.box)
+    say(f"  rate {rate:.4f} against {p:.4f}")
+    assert int(outside.sum().item()) == int(count.item())
+    assert abs(rate - p) < 4.5 * np.sqrt(p * (1 - p) / n) + 0.003
+
+
+def test_invalid_arguments(sm):
+    wl = W.GAUSS16
+    z = torch.zeros((1, 4, 2), dtype=torch.float64, device="cuda")
+    u = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError):
+        sm.coef_gauss(z, u, 16, 0.0, 1.0)
+    with pytest.raises(ValueError):  # the binding passes device memory only
+        sm.coef_gauss(z.cpu(), u.cpu(), 16, 1.0, 1.0)
+    mu = torch.ones(17, dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError):
+        sm.kl_project(torch.zeros((1, 32, 32), dtype=torch.float64, device="cuda"), 2, 16, mu,
+                      torch.zeros((17, 16, 16), dtype=torch.float64, device="cuda"))
