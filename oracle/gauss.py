@@ -94,3 +94,47 @@ def truncated_kappa_blocks(xi: np.ndarray, mu: np.ndarray, V: np.ndarray, K: int
 def outside_probability(K: int, box: float = 3.0) -> float:
     """1 - P(|Z| <= box)^K for independent standard normals."""
     return 1.0 - erf(box / sqrt(2.0)) ** K
+
+
+# ---------------------------------------------------------------------------
+# Interpolation of S in the local KL parameters (Sec. 5.3 with Sec. 3.1):
+# one table serves every coarse element (the covariance is translation
+# invariant, so every element has the same modes): S at the tensor
+# Chebyshev-Gauss-Lobatto nodes of [-box, box]^K, computed by the plain path
+# on the truncated coefficient of each node; online, the tensor Lagrange
+# interpolant at the pair's parameters, or the plain path on the sample's own
+# kappa block when a parameter lies outside the box.
+# ---------------------------------------------------------------------------
+def kl_interp_offline(m: int, mu: np.ndarray, V: np.ndarray, nn: int, box: float = 3.0) -> dict:
+    import itertools
+
+    from . import core, ri
+
+    K = len(mu)
+    nodes = ri.cgl_nodes(nn, -box, box)
+    xi_nodes = np.array([[nodes[d] for d in digits] for digits in itertools.product(range(nn), repeat=K)])
+    blocks = truncated_kappa_blocks(xi_nodes[None], mu, V, K)[0]  # [nn^K][m][m]
+    S, st, _ = core.upscale(blocks, 1, 1, m)
+    if np.any(st != 0):
+        raise RuntimeError("plain solve failed at a node")
+    return dict(table=S[:, 0, :], nodes=nodes, box=box, K=K)
+
+
+def kl_interp_online(model: dict, xi: np.ndarray, kap: np.ndarray, nc: int, m: int):
+    """(S [N][nc*nc][10], fallback mask [N][nc*nc])."""
+    from . import core, ri
+
+    N, P, K = xi.shape
+    box = model["box"]
+    S = np.zeros((N, P, 10))
+    fb = ~np.all(np.abs(xi) <= box, axis=2)
+    for p in range(P):
+        inside = ~fb[:, p]
+        if np.any(inside):
+            S[inside, p] = ri.ri_eval(model["table"], model["nodes"], xi[inside, p])
+        if np.any(~inside):
+            ky, kx = p // nc, p % nc
+            blk = np.ascontiguousarray(kap[~inside, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m])
+            Sp, _, _ = core.upscale(blk, 1, 1, m)
+            S[~inside, p] = Sp[:, 0, :]
+    return S, fb

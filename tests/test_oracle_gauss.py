@@ -84,3 +84,34 @@ def test_truncation_error_matches_the_discarded_spectrum_and_the_fallback_rate()
     p = gauss.outside_probability(4)
     n = out.size
     assert abs(out.mean() - p) < 4.5 * np.sqrt(p * (1 - p) / n) + 0.003
+
+
+def test_interpolation_on_the_local_parameters():
+    # the table interpolant converges to the truncated-coefficient S inside
+    # the box, the interpolation error stays below the truncation error (the
+    # paper's observation in Sec. 5.3), and out-of-box pairs are the plain
+    # solve of the sample's own coefficient
+    from oracle import core
+    nc, m, K = 4, 8, 4
+    nf = nc * m
+    l1, l2 = 1.0, 2.0 / (nc * 2 * 2)  # two correlation lengths per element, as in the workload
+    mu, V, _ = gauss.local_kl(m, 1.0 / nf, l1, l2, K)
+    z, u = W.spectral_draws(6, 128, 73)
+    beta = gauss.field(z, u, nf, l1, l2)
+    kap = gauss.kappa(beta)
+    xi = gauss.project(beta, nc, m, mu, V)
+    S_trunc, _, _ = core.upscale(gauss.truncated_kappa_blocks(xi, mu, V, K).reshape(-1, m, m), 1, 1, m)
+    S_trunc = S_trunc.reshape(6, nc * nc, 10)
+    S_full, _, _ = core.upscale(kap, nc, nc, m)
+    err = {}
+    for nn in (3, 5, 7):
+        model = gauss.kl_interp_offline(m, mu, V, nn)
+        S, fb = gauss.kl_interp_online(model, xi, kap, nc, m)
+        ins = ~fb
+        sc = np.abs(S_full).max(axis=2)
+        err[nn] = (np.abs(S - S_trunc).max(axis=2)[ins] / sc[ins]).max()
+        if fb.any():
+            np.testing.assert_array_equal(S[fb], S_full[fb])
+    assert err[3] > err[5] > err[7], err
+    trunc = (np.abs(S_trunc - S_full).max(axis=2) / np.abs(S_full).max(axis=2))[~fb].max()
+    assert err[7] < 0.1 * trunc, (err[7], trunc)
