@@ -555,8 +555,39 @@ def measure_gauss(log, N=1024, n_trunc=64):
             "max_S_rel_err": float(((S_t - S_full).abs().amax(dim=2) / scale).max().item()),
             "max_coarse_rel_err": float((torch.linalg.norm(U_t - U_full, dim=1) /
                                          torch.linalg.norm(U_full, dim=1)).max().item())}
+    # interpolation in the four local parameters (7 and 9 Lobatto nodes each)
+    # with the plain path on the sample's own coefficient outside [-3, 3]
+    xi4, _, _ = sm.kl_project(beta, wl.nc, wl.m, mu4, V4, wl.box)
+    S_all = sm.upscale(kap, wl.nc, wl.nc, wl.m)
+    torch.cuda.synchronize()
+    t_plain = _timed(lambda: sm.upscale(kap, wl.nc, wl.nc, wl.m, S=S_all), reps=3)
+    sc_all = S_all.abs().amax(dim=2)
+    S_t4 = sm.upscale(sm.kl_blocks(xi4[:n].contiguous(), mu4, V4, wl.kl_terms), 1, 1, wl.m).reshape(n, wl.M, 10)
+    U_t4, _, _ = sm.coarse_solve(S_t4, wl.nc, wl.nc)
+    interp = {}
+    for nn in (7, 9):
+        t0 = time.perf_counter()
+        model = sm.kl_interp_build(wl.nc, wl.nc, wl.m, mu4, V4, nn, wl.box)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        S_int = torch.empty((N, wl.M, 10), dtype=torch.float64, device="cuda")
+        t_int = _timed(lambda: sm.kl_interp_apply(model, xi4, kap, S=S_int), reps=3)
+        _, nfb = sm.kl_interp_apply(model, xi4, kap, S=S_int)
+        U_int, _, _ = sm.coarse_solve(S_int[:n].contiguous(), wl.nc, wl.nc)
+        interp[f"nodes_{nn}"] = {
+            "table_rows": nn ** 4, "build_s": t_build, "apply_ms": t_int * 1e3,
+            "pairs_per_s": pairs / t_int, "plain_pairs_per_s": pairs / t_plain, "ratio_vs_plain": t_plain / t_int,
+            "plain_fallback_pairs": nfb, "fallback_rate": nfb / pairs,
+            "max_S_rel_err_vs_sample": float(((S_int - S_all).abs().amax(dim=2) / sc_all).max().item()),
+            "max_S_rel_err_vs_truncated": float(((S_int[:n] - S_t4).abs().amax(dim=2) / sc_all[:n]).max().item()),
+            "max_coarse_rel_err_vs_sample": float((torch.linalg.norm(U_int - U_full, dim=1) /
+                                                   torch.linalg.norm(U_full, dim=1)).max().item()),
+            "max_coarse_rel_err_vs_truncated": float((torch.linalg.norm(U_int - U_t4, dim=1) /
+                                                      torch.linalg.norm(U_t4, dim=1)).max().item())}
+        model.free()
     out = {"workload": (f"kappa = 0.1 + exp(beta), Gaussian beta (l1={wl.l1}, l2={wl.l2}, {wl.nterms} spectral "
                         f"terms), {wl.nc}x{wl.nc} coarse, H/h={wl.m}, local KL on the coarse elements"),
+           "interpolation_in_kl_parameters": interp,
            "samples": N, "field_ms": t_field * 1e3, "field_elements_per_s": N * wl.nfine**2 / t_field,
            "projection_ms": t_proj * 1e3, "pairs_per_s_projection": pairs / t_proj,
            "kept_fraction_4_terms": float(mu[:4].sum() / (wl.m * wl.m)),

@@ -252,6 +252,7 @@ int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* b
 int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const double* xi, const double* mu,
                        const double* modes, double* blocks, void* stream);
 
+
 /* ------------------------------------------------------------------------
  * Fine-grid FEM and the two-level Monte Carlo estimator (Sec. 4.1.1, the
  * remark with eqs. MCmean2level and mseML).
@@ -526,6 +527,29 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
 int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, double* S,
                        int32_t* status, int64_t* nfallback, void* stream);
 
+/* Interpolation of S in the local KL parameters (Sec. 5.3 with Sec. 3.1).
+ *
+ * stomsfem_kl_interp_build (offline): one table for every coarse element of
+ * the ncx x ncy mesh (the covariance is translation invariant, so all
+ * elements share mu, modes: device copies of the stomsfem_local_kl outputs,
+ * K <= 4): S at the nnodes^K (2 <= nnodes <= 9) tensor Chebyshev-Gauss-
+ * Lobatto nodes of [-box, box]^K (node ordering as stomsfem_interp_build),
+ * computed by the plain path on the truncated coefficient of each node.
+ * Synchronises `stream`; the model owns its device memory.
+ *
+ * stomsfem_kl_interp_apply (online): S device [nsamples][M][10] for the
+ * local parameters xi device [nsamples][M][K] (from stomsfem_kl_project): the
+ * tensor Lagrange interpolant where every parameter lies in [-box, box];
+ * elsewhere (or NaN) the plain path on the sample's own coefficient block
+ * from kappa device [nsamples][ncy m][ncx m] (FP64).  status device
+ * [nsamples][M] or NULL: 0 = interpolated, 1 = computed plainly, ENOTSPD from
+ * such a solve; *nfallback (host, may be NULL) = the number of plainly
+ * computed pairs.  Synchronises `stream` once; may grow a model-owned buffer. */
+int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, const double* mu, const double* modes,
+                             int32_t nnodes, double box, stomsfem_model** model, void* stream);
+int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
+                             double* S, int32_t* status, int64_t* nfallback, void* stream);
+
 /* ------------------------------------------------------------------------
  * Execution plans.  A stage is one batch of samples taken through the whole
  * path: coefficient generation from xi, local upscaling (FP64), coarse
@@ -624,7 +648,8 @@ typedef struct {
 int stomsfem_model_save(const stomsfem_model* model, const char* path);
 int stomsfem_model_load(const char* path, stomsfem_model** model);
 /* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
- * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation;
+ * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation,
+ * 6 = interpolation in the local KL parameters;
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

@@ -552,6 +552,182 @@ int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "kl_blocks launch");
 }
 
+int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, const double* mu, const double* modes,
+                             int32_t nnodes, double box, stomsfem_model** model, void* stream) {
+  if (!model) return fail(STOMSFEM_EINVAL, "kl_interp_build: NULL model");
+  *model = nullptr;
+  if (ncx < 1 || ncy < 1 || m < 1 || m > 48 || K < 1 || K > RI_KMAX || nnodes < RI_NN_MIN || nnodes > RI_NN_MAX ||
+      !(box > 0))
+    return fail(STOMSFEM_EINVAL, "kl_interp_build: need 1 <= m <= 48, 1 <= K <= 4, 2 <= nnodes <= 9, box > 0");
+  if (!device_ptr(mu) || !device_ptr(modes)) return fail(STOMSFEM_EINVAL, "kl_interp_build: mu and modes on device");
+  const int Mc = ncx * ncy;
+  int64_t rows = 1;
+  for (int i = 0; i < K; ++i) rows *= nnodes;
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 6;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->nn = nnodes;
+  md->lo = -box;
+  md->hi = box;
+  md->rows = rows;
+  md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  double* xin = nullptr;
+  double* blk = nullptr;
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->table, sizeof(double) * (size_t)rows * 10);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  A((void**)&xin, sizeof(double) * (size_t)rows * K);
+  A((void**)&blk, sizeof(double) * (size_t)rows * m * m);
+  int32_t* stn = nullptr;
+  A((void**)&stn, sizeof(int32_t) * (size_t)rows);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(xin);
+    hipFree(blk);
+    hipFree(stn);
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "kl_interp_build: device allocation failed");
+  }
+  // every element reads the one table: local variables = its own K parameters
+  std::vector<int32_t> lv((size_t)Mc * RI_KMAX, -1), nlv(Mc, K);
+  std::vector<int64_t> off(Mc + 1, 0);
+  for (int p = 0; p < Mc; ++p)
+    for (int k = 0; k < K; ++k) lv[(size_t)p * RI_KMAX + k] = p * K + k;
+  off[Mc] = rows;
+  std::vector<double> xh((size_t)rows * K);
+  for (int64_t r = 0; r < rows; ++r) {
+    int64_t c = r;
+    for (int v = K - 1; v >= 0; --v) {  // variable 0 slowest
+      const int d = (int)(c % nnodes);
+      c /= nnodes;
+      xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)d / (double)(nnodes - 1)) + 1.0) * box;
+    }
+  }
+  e = hipMemcpy(md->lv, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_kl_blocks(rows, m, K, K, xin, mu, modes, blk, st);
+  if (e == hipSuccess) {
+    UpArgs u{};
+    u.nsamples = rows;
+    u.ncx = u.ncy = 1;
+    u.m = m;
+    u.npairs = rows;
+    u.a = blk;
+    u.S = md->table;
+    u.status = stn;
+    e = launch_upscale_any(u, STOMSFEM_F64, st);
+  }
+  std::vector<int32_t> sth((size_t)rows);
+  if (e == hipSuccess) e = hipMemcpyAsync(sth.data(), stn, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(xin);
+  hipFree(blk);
+  hipFree(stn);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "kl_interp_build");
+  }
+  for (int64_t r = 0; r < rows; ++r)
+    if (sth[(size_t)r] != 0) {
+      model_release(md);
+      return fail(STOMSFEM_ENOTSPD, "kl_interp_build: a cell problem at a node is not positive definite");
+    }
+  md->lv_max = K;  // parameters per element
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
+                             double* S, int32_t* status, int64_t* nfallback, void* stream) {
+  if (nfallback) *nfallback = 0;
+  if (!model || model->kind != 6) return fail(STOMSFEM_EINVAL, "kl_interp_apply: not a KL interpolation model");
+  if (nsamples < 0) return fail(STOMSFEM_EINVAL, "kl_interp_apply: nsamples < 0");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(xi) || !device_ptr(kappa) || !device_ptr(S) || (status && !device_ptr(status)))
+    return fail(STOMSFEM_EINVAL, "kl_interp_apply: arrays must be device pointers");
+  const int Mc = model->ncx * model->ncy, K = model->lv_max;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = nsamples * Mc;
+  if (model->list_cap < need) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+      hipFree(model->list);
+      model->list = nullptr;
+      model->list_cap = 0;
+      e = hipMalloc(&model->list, sizeof(int64_t) * need);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STOMSFEM_ENOMEM, "kl_interp_apply: fallback list allocation failed");
+    }
+    model->list_cap = need;
+  }
+  RiApplyArgs a{};
+  a.npatch = Mc;
+  a.nxi = Mc * K;
+  a.nn = model->nn;
+  a.nsamples = nsamples;
+  a.lo = model->lo;
+  a.hi = model->hi;
+  a.table = model->table;
+  a.off = model->off;
+  a.lv = model->lv;
+  a.nlv = model->nlv;
+  a.xi = xi;
+  a.S = S;
+  a.status = status;
+  a.list = model->list;
+  a.list_count = model->counter;
+  hipError_t e = launch_zero_u64(model->counter, st);
+  if (e == hipSuccess) e = launch_ri_apply(a, st);
+  unsigned long long n = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "kl_interp_apply");
+  if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "kl_interp_apply: fallback count out of range");
+  if (nfallback) *nfallback = (int64_t)n;
+  // out-of-box pairs: the plain path on the sample's own coefficient block
+  UpArgs full{};
+  full.nsamples = nsamples;
+  full.ncx = model->ncx;
+  full.ncy = model->ncy;
+  full.m = model->m;
+  full.a = kappa;
+  for (int64_t start = 0; start < (int64_t)n; start += model->chunk) {
+    const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
+    e = launch_gather_blocks(full, STOMSFEM_F64, model->list + start, cnt, model->blk, st);
+    if (e == hipSuccess) {
+      UpArgs u{};
+      u.nsamples = cnt;
+      u.ncx = u.ncy = 1;
+      u.m = model->m;
+      u.npairs = cnt;
+      u.a = model->blk;
+      u.S = model->Sc;
+      u.status = model->stc;
+      e = launch_upscale_any(u, STOMSFEM_F64, st);
+    }
+    if (e == hipSuccess) e = launch_scatter_pairs(model->list + start, cnt, model->Sc, model->stc, S, status, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "kl_interp_apply: plain solve launch");
+  }
+  return STOMSFEM_OK;
+}
+
 int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* stream) {
   if (!batch) return fail(STOMSFEM_EINVAL, "upscale_os: NULL batch");
   int rc = check_batch(*batch, 0);

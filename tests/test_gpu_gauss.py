@@ -123,3 +123,30 @@ def test_invalid_arguments(sm):
     with pytest.raises(sm.StomsfemError):
         sm.kl_project(torch.zeros((1, 32, 32), dtype=torch.float64, device="cuda"), 2, 16, mu,
                       torch.zeros((17, 16, 16), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("nn,box", [(5, 3.0), (4, 1.2)])
+def test_interpolation_on_the_local_parameters_matches_oracle(sm, nn, box):
+    # each side builds its own modes and table; S per pair does not depend on
+    # the modes' signs.  The narrow box sends many pairs to the plain path.
+    wl = W.GAUSS16
+    N, K = 3, wl.kl_terms
+    say(f"KL interpolation nn={nn} box={box}")
+    z, u, kap, beta, mu, V, mu_d, V_d = _setup(sm, wl, N, 2104 + nn, K)
+    xi, outside, count = sm.kl_project(beta, wl.nc, wl.m, mu_d, V_d, box)
+    model = sm.kl_interp_build(wl.nc, wl.nc, wl.m, mu_d, V_d, nn, box)
+    st = torch.full((N, wl.M), 99, dtype=torch.int32, device="cuda")
+    S, nfb = sm.kl_interp_apply(model, xi, kap, status=st)
+    torch.cuda.synchronize()
+    b_ref = gauss.field(z, u, wl.nfine, wl.l1, wl.l2)
+    mu_r, V_r, _ = gauss.local_kl(wl.m, 1.0 / wl.nfine, wl.l1, wl.l2, K)
+    xi_r = gauss.project(b_ref, wl.nc, wl.m, mu_r, V_r)
+    orc = gauss.kl_interp_offline(wl.m, mu_r, V_r, nn, box)
+    S_ref, fb = gauss.kl_interp_online(orc, xi_r, gauss.kappa(b_ref), wl.nc, wl.m)
+    st = st.cpu().numpy()
+    assert nfb == int(fb.sum()) == int(count.item())
+    assert (st[fb] == 1).all() and (st[~fb] == 0).all()
+    S = S.cpu().numpy()
+    err = (np.abs(S - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
+    say(f"  {int(fb.sum())} plain pairs, S rel err {err:.2e}")
+    assert err < 1e-10
