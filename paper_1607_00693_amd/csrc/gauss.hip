@@ -5,17 +5,23 @@
 // gauss_field_kernel: beta(x) = sqrt(2/J) sum_j cos(w_j . x + phi_j) at the
 // element centroids (the randomized spectral method: w_j = sqrt(2) (z_j1/l1,
 // z_j2/l2) has the normal law whose characteristic function is the
-// covariance, phi_j = 2 pi u_j), kappa = 0.1 + exp(beta).  One workgroup per
-// 16 x 16 tile of one sample; the sample's J terms are staged in LDS.
+// covariance, phi_j = 2 pi u_j), kappa = 0.1 + exp(beta).  Each term is a
+// plane wave, so along a column of centroids it is Re(e^{i theta_0} r^k) with
+// r = e^{i w_j2 h}: one thread walks a strip of GF_RY rows of one column with
+// one sincos per term and one complex rotation per row (no cosine per
+// element).  The rotation keeps |r^k| = 1 to rounding, so the error grows
+// only linearly in the strip length.  A workgroup covers 64 columns x
+// 4 strips of one sample; the sample's terms (w, phi, r) are staged in LDS.
 //
 // Local KL (host): the patch covariance exp(-dx^2/l1^2 - dy^2/l2^2) on the
 // m x m centroids is the Kronecker product of two m x m matrices, so its
 // eigenpairs are the products of the one-dimensional ones (cyclic Jacobi);
 // the K largest products give mu_k and the modes v_k = vy (x) vx.
 //
-// kl_project_kernel: one wavefront per (sample, element): xi_k = v_k . beta /
-// sqrt(mu_k), lanes over the element's m^2 values, partial sums combined
-// through LDS in a fixed order; pairs with |xi_k| > box for some k are counted.
+// kl_project_kernel: one wavefront per (sample, element), four per workgroup:
+// xi_k = v_k . beta / sqrt(mu_k), lanes over the element's m^2 values, the
+// partial sums combined by a butterfly of lane shuffles (a fixed order);
+// pairs with |xi_k| > box for some k are flagged and counted.
 // kl_blocks_kernel: kappa of the first K' terms on every pair's block,
 // 0.1 + exp(sum_k sqrt(mu_k) xi_k v_k), one thread per element.
 #include <cmath>
@@ -25,7 +31,9 @@
 
 namespace stomsfem {
 
-constexpr int GF_TILE = 16;
+constexpr int GF_TX = 64;     // columns per workgroup, one per lane
+constexpr int GF_SY = 4;      // strips per workgroup, one per wavefront
+constexpr int GF_RY = 32;     // rows per strip
 constexpr int GF_JMAX = 1024;  // spectral terms per sample
 constexpr int KL_KMAX = 16;    // local KL terms
 
@@ -33,44 +41,71 @@ __global__ __launch_bounds__(256) void gauss_field_kernel(int64_t nsamples, int 
                                                           const double* __restrict__ z,
                                                           const double* __restrict__ u, double l1, double l2,
                                                           double* __restrict__ beta, double* __restrict__ kappa,
-                                                          int tiles_x) {
-  __shared__ double w1s[GF_JMAX], w2s[GF_JMAX], phs[GF_JMAX];
-  const int64_t tiles = (int64_t)tiles_x * tiles_x;
+                                                          int tiles_x, int tiles_y) {
+  __shared__ double2 ws[GF_JMAX];   // (w1, w2)
+  __shared__ double2 rs[GF_JMAX];   // r = (cos, sin)(w2 h)
+  __shared__ double phs[GF_JMAX];
+  const int64_t tiles = (int64_t)tiles_x * tiles_y;
   const int64_t nblk = nsamples * tiles;
   const double h = 1.0 / nfine, amp = sqrt(2.0 / J);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, strip = threadIdx.x >> 6;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int64_t s = b / tiles;
     const int tt = (int)(b - s * tiles);
     const int tx = tt % tiles_x, ty = tt / tiles_x;
     __syncthreads();  // the previous tile's readers are done
-    for (int j = lane; j < J; j += 256) {
-      w1s[j] = sqrt(2.0) * z[(s * J + j) * 2] / l1;
-      w2s[j] = sqrt(2.0) * z[(s * J + j) * 2 + 1] / l2;
+    for (int j = threadIdx.x; j < J; j += 256) {
+      const double w1 = sqrt(2.0) * z[(s * J + j) * 2] / l1;
+      const double w2 = sqrt(2.0) * z[(s * J + j) * 2 + 1] / l2;
+      double sn, cs;
+      sincos(w2 * h, &sn, &cs);
+      ws[j] = make_double2(w1, w2);
+      rs[j] = make_double2(cs, sn);
       phs[j] = 2.0 * M_PI * u[s * J + j];
     }
     __syncthreads();
-    const int ix = tx * GF_TILE + (lane % GF_TILE), iy = ty * GF_TILE + lane / GF_TILE;
-    if (ix < nfine && iy < nfine) {
-      const double x = (ix + 0.5) * h, y = (iy + 0.5) * h;
-      double acc = 0.0;
-      for (int j = 0; j < J; ++j) acc += cos(w1s[j] * x + w2s[j] * y + phs[j]);
-      const double bv = amp * acc;
-      const int64_t o = (s * nfine + iy) * (int64_t)nfine + ix;
-      if (beta) beta[o] = bv;
-      kappa[o] = 0.1 + exp(bv);
+    const int ix = tx * GF_TX + lane, iy0 = (ty * GF_SY + strip) * GF_RY;
+    const double x = (ix + 0.5) * h, y0 = (iy0 + 0.5) * h;
+    double acc[GF_RY];
+#pragma unroll
+    for (int k = 0; k < GF_RY; ++k) acc[k] = 0.0;
+    for (int j = 0; j < J; ++j) {
+      const double2 w = ws[j], r = rs[j];
+      double re, im;
+      sincos(w.x * x + w.y * y0 + phs[j], &im, &re);
+      acc[0] += re;
+#pragma unroll
+      for (int k = 1; k < GF_RY; ++k) {
+        const double nre = re * r.x - im * r.y;
+        im = re * r.y + im * r.x;
+        re = nre;
+        acc[k] += re;
+      }
+    }
+    if (ix < nfine) {
+#pragma unroll
+      for (int k = 0; k < GF_RY; ++k) {
+        const int iy = iy0 + k;
+        if (iy < nfine) {
+          const double bv = amp * acc[k];
+          const int64_t o = (s * nfine + iy) * (int64_t)nfine + ix;
+          if (beta) beta[o] = bv;
+          kappa[o] = 0.1 + exp(bv);
+        }
+      }
     }
   }
 }
 
 hipError_t launch_gauss_field(int64_t nsamples, int nfine, int J, const double* z, const double* u, double l1,
                               double l2, double* beta, double* kappa, hipStream_t st) {
-  const int tiles_x = (nfine + GF_TILE - 1) / GF_TILE;
-  int64_t blocks = nsamples * (int64_t)tiles_x * tiles_x;
+  if (J < 1 || J > GF_JMAX) return hipErrorInvalidValue;
+  const int tiles_x = (nfine + GF_TX - 1) / GF_TX, tiles_y = (nfine + GF_SY * GF_RY - 1) / (GF_SY * GF_RY);
+  int64_t blocks = nsamples * (int64_t)tiles_x * tiles_y;
   if (blocks == 0) return hipSuccess;
   if (blocks > (1 << 20)) blocks = 1 << 20;
   hipLaunchKernelGGL(gauss_field_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nsamples, nfine, J, z, u, l1, l2,
-                     beta, kappa, tiles_x);
+                     beta, kappa, tiles_x, tiles_y);
   return hipGetLastError();
 }
 
@@ -147,18 +182,21 @@ void local_kl_modes(int m, double h, double l1, double l2, int K, double* mu, do
   if (captured) *captured = kept / total;
 }
 
-__global__ __launch_bounds__(64) void kl_project_kernel(int64_t npairs, int nc, int m, int K,
-                                                        const double* __restrict__ beta,
-                                                        const double* __restrict__ mu,
-                                                        const double* __restrict__ modes, double box,
-                                                        double* __restrict__ xi, int32_t* __restrict__ outside,
-                                                        unsigned long long* count) {
-  __shared__ double part[KL_KMAX][64];
-  const int lane = threadIdx.x;
-  const int64_t p = blockIdx.x;
+constexpr int KL_WPB = 4;  // pairs (wavefronts) per workgroup
+
+__global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs, int nc, int m, int K,
+                                                                 const double* __restrict__ beta,
+                                                                 const double* __restrict__ mu,
+                                                                 const double* __restrict__ modes, double box,
+                                                                 double* __restrict__ xi,
+                                                                 int32_t* __restrict__ outside,
+                                                                 unsigned long long* count) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * KL_WPB + (threadIdx.x >> 6);
+  if (p >= npairs) return;  // whole wavefronts only; the kernel has no barrier
   const int64_t M = (int64_t)nc * nc, s = p / M;
   const int K0 = (int)(p - s * M), kx = K0 % nc, ky = K0 / nc;
-  const int64_t nf = (int64_t)nc * m;
+  const int64_t nf = (int64_t)nc * m, mm = (int64_t)m * m;
   const double* B = beta + s * nf * nf + (int64_t)ky * m * nf + (int64_t)kx * m;
   double acc[KL_KMAX];
 #pragma unroll
@@ -167,23 +205,22 @@ __global__ __launch_bounds__(64) void kl_project_kernel(int64_t npairs, int nc, 
     const double b = B[(int64_t)(e / m) * nf + (e % m)];
 #pragma unroll
     for (int k = 0; k < KL_KMAX; ++k)
-      if (k < K) acc[k] += b * modes[(int64_t)k * m * m + e];
+      if (k < K) acc[k] += b * modes[k * mm + e];
   }
+  // butterfly over the 64 lanes (a fixed order; every lane ends with the sum)
+  bool out = false;
 #pragma unroll
-  for (int k = 0; k < KL_KMAX; ++k)
-    if (k < K) part[k][lane] = acc[k];
-  __syncthreads();
-  if (lane < K) {
-    double t = 0.0;
-    for (int l = 0; l < 64; ++l) t += part[lane][l];
-    const double x = t / sqrt(mu[lane]);
-    xi[p * K + lane] = x;
-    part[lane][0] = x;
+  for (int k = 0; k < KL_KMAX; ++k) {
+    if (k < K) {
+      double t = acc[k];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+      const double x = t / sqrt(mu[k]);
+      if (lane == k) xi[p * K + k] = x;
+      out = out || !(fabs(x) <= box);
+    }
   }
-  __syncthreads();
   if (lane == 0) {
-    bool out = false;
-    for (int k = 0; k < K; ++k) out = out || !(fabs(part[k][0]) <= box);
     if (outside) outside[p] = out ? 1 : 0;
     if (out && count) atomicAdd(count, 1ull);
   }
@@ -193,9 +230,11 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double*
                              const double* modes, double box, double* xi, int32_t* outside,
                              unsigned long long* count, hipStream_t st) {
   if (npairs == 0) return hipSuccess;
-  if (npairs > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kl_project_kernel, dim3((unsigned)npairs), dim3(64), 0, st, npairs, nc, m, K, beta, mu, modes,
-                     box, xi, outside, count);
+  if (K < 1 || K > KL_KMAX) return hipErrorInvalidValue;
+  const int64_t nb = (npairs + KL_WPB - 1) / KL_WPB;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kl_project_kernel, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K, beta, mu,
+                     modes, box, xi, outside, count);
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ def sm():
     return stomsfem
 
 
-@pytest.mark.parametrize("N,nf,J", [(2, 48, 64), (3, 40, 7), (1, 256, 256)])
+@pytest.mark.parametrize("N,nf,J", [(2, 48, 64), (3, 40, 7), (1, 256, 256), (2, 200, 33), (1, 97, 1024)])
 def test_field_matches_oracle(sm, N, nf, J):
     say(f"field N={N} nf={nf} J={J}")
     z, u = W.spectral_draws(N, J, 2000 + nf)
@@ -70,6 +70,25 @@ def test_projection_and_truncated_coefficient_match_oracle(sm):
         blk = sm.kl_blocks(torch.from_numpy(xi).cuda(), mu_d, V_d, Kuse).cpu().numpy()
         ref = gauss.truncated_kappa_blocks(xi_r, mu_r, V_r, Kuse).reshape(blk.shape)
         np.testing.assert_allclose(blk, ref, rtol=1e-10, atol=0)
+
+
+def test_projection_ragged(sm):
+    # 27 pairs (the last workgroup of four wavefronts part empty), 5 x 5
+    # elements, three terms
+    nc, m, K, N = 3, 5, 3, 3
+    l1, l2 = 0.5, 0.1
+    z, u = W.spectral_draws(N, 40, 2111)
+    beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nc * m, l1, l2,
+                         with_beta=True)[1]
+    mu, V, _ = sm.local_kl(m, 1.0 / (nc * m), l1, l2, K)
+    xi, outside, count = sm.kl_project(beta, nc, m, torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda(), 1.0)
+    mu_r, V_r, _ = gauss.local_kl(m, 1.0 / (nc * m), l1, l2, K)
+    xi_r = gauss.project(gauss.field(z, u, nc * m, l1, l2), nc, m, mu_r, V_r)
+    sign = np.sign(np.einsum("kij,kij->k", V, V_r))
+    np.testing.assert_allclose(xi.cpu().numpy(), xi_r * sign, rtol=0, atol=1e-10 * np.abs(xi_r).max())
+    out_r = (np.abs(xi_r) > 1.0).any(axis=2)
+    assert (outside.cpu().numpy() == out_r).all() and int(count.item()) == int(out_r.sum())
+    assert out_r.any() and (~out_r).any()
 
 
 def test_stiffness_on_the_truncated_coefficient(sm):
