@@ -1728,6 +1728,9 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
   }
   rofs[RI_KMAX + 1] = (int32_t)rows_all.size();
   if (missing) return fail(STOMSFEM_EINVAL, "sgi_build: a tensor node of the combination is not a grid node");
+  // the kernel reads SGI_BATCH entries at a time: pad past the last row
+  cc.insert(cc.end(), SGI_BATCH - 1, 0.0);
+  cbo.insert(cbo.end(), SGI_BATCH - 1, 0u);
   std::vector<int64_t> off(Mc + 1, 0);
   for (int K = 0; K < Mc; ++K) off[K + 1] = off[K] + npts[nlv[K]];
   hipStream_t st = (hipStream_t)stream;

@@ -165,35 +165,41 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
 }
 
 // ---- sparse-grid interpolation: sgi_apply_kernel ----
-// One workgroup = one patch K (blockIdx.y) and 64 samples (one per lane), so
-// the patch's table and the combination list are read at wave-uniform
-// addresses.  Each lane first evaluates, for every local variable d and
-// every level i <= L+1, the Lagrange basis of the level-i nodes at its t_d
-// in barycentric product form
+// One workgroup = one patch K (blockIdx.y) and 64 samples (one per lane of
+// each of its SGI_WAVES wavefronts), so the patch's table and the
+// combination list are read at wave-uniform addresses.  The lanes first
+// evaluate, for every local variable d and every level i <= L+1, the
+// Lagrange basis of the level-i nodes at the sample's t_d in barycentric
+// product form
 //   P_j = w_j prod_{e != j} (t - t_e),  l_j = P_j / sum_e P_e,
 // w_j = (-1)^j (halved at both ends), the Chebyshev-Lobatto weights (exact on
 // a node, no division by zero; level 1: l_0 = 1), into LDS at
-// [(d nb + lofs[i] + j) 64 + lane] (lane-interleaved: no bank conflicts).
-// Then S_K(t) = sum over the table rows r of W_r(t) T_K[r], W_r the sum over
-// the combination entries of node r of coef * prod_d B[d][boff_d] (entries
-// are grouped by row, so each table row is read once, at a sequential
-// address, and no load address depends on an earlier load).  Lanes with a local variable
-// outside [lo, hi] (or NaN) are listed for the plain path instead.  Every
-// global store (and the list's atomic) comes after the loop, so the
-// wave-uniform loads of the loop are not clobbered and go through the
-// scalar cache.
-__global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
+// [(d nb + lofs[i] + j) 64 + lane] (lane-interleaved: no bank conflicts);
+// wavefront w takes the variables d = w, w + SGI_WAVES, ...  The bases are
+// shared by the workgroup's wavefronts, which split the table rows into
+// SGI_WAVES consecutive ranges: S_K(t) = sum over the table rows r of
+// W_r(t) T_K[r], W_r the sum over the combination entries of node r of
+// coef * prod_d B[d][boff_d] (entries are grouped by row, so each table row
+// is read once, at a sequential address, and no load address depends on an
+// earlier load).  The wavefronts' partial sums are added in wavefront order
+// through LDS (over the bases, after a barrier), and the first wavefront
+// stores.  Lanes with a local variable outside [lo, hi] (or NaN) are listed
+// for the plain path instead.  Every global store (and the list's atomic)
+// comes after the loop, so the wave-uniform loads of the loop are not
+// clobbered and go through the scalar cache.
+__global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs a) {
   extern __shared__ double sgi_lds[];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int K = blockIdx.y;
   const int64_t s = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = s < a.nsamples;
   const int k = a.nlv[K];
-  double* B = sgi_lds + lane;  // B[e * 64] = basis value e of this lane
+  double* B = sgi_lds + lane;  // B[e * 64] = basis value e of this lane's sample
   bool inside = valid;
   for (int d = 0; d < k; ++d) {
     const double x = valid ? a.xi[s * a.nxi + a.lv[K * 4 + d]] : 0.0;
     inside = inside && (x >= a.lo && x <= a.hi);
+    if (d % SGI_WAVES != wave) continue;
     const double t = 2.0 * (x - a.lo) / (a.hi - a.lo) - 1.0;
     double* Bd = B + d * a.nb * 64;
     Bd[0] = 1.0;  // level 1
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
       for (int j = 0; j < n; ++j) Bd[(o + j) * 64] *= r;
     }
   }
+  __syncthreads();
   const int64_t p = s * a.npatch + K;
   double acc[10];
 #pragma unroll
@@ -219,20 +226,46 @@ __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
   const double* T = a.table + a.off[K] * 10;
   const int32_t* rs = a.cb_rows + a.rofs[k];  // entries of row r: rs[r] .. rs[r+1]-1
   const int nr = a.rofs[k + 1] - a.rofs[k] - 1;
-  int c = rs[0];
-  for (int r = 0; r < nr; ++r) {
+  const int r0 = (int)((int64_t)nr * wave / SGI_WAVES), r1 = (int)((int64_t)nr * (wave + 1) / SGI_WAVES);
+  int c = rs[r0];
+  for (int r = r0; r < r1; ++r) {
     const int c1 = rs[r + 1];
     double wr = 0.0;
-    for (; c < c1; ++c) {
-      double w = a.cb_coef[c];
-      const uint32_t bo = a.cb_boff[c];
-      for (int d = 0; d < k; ++d) w *= B[(d * a.nb + (int)((bo >> (8 * d)) & 255u)) * 64];
-      wr += w;
+    // SGI_BATCH entries at a time, so that their LDS reads are in flight
+    // together; the entry arrays carry SGI_BATCH - 1 padding entries, and
+    // entries past the row's end count as zero (the sum keeps its order)
+    for (; c < c1; c += SGI_BATCH) {
+      double w[SGI_BATCH];
+      uint32_t bo[SGI_BATCH];
+#pragma unroll
+      for (int u = 0; u < SGI_BATCH; ++u) {
+        w[u] = c + u < c1 ? a.cb_coef[c + u] : 0.0;
+        bo[u] = a.cb_boff[c + u];
+      }
+      for (int d = 0; d < k; ++d)
+#pragma unroll
+        for (int u = 0; u < SGI_BATCH; ++u) w[u] *= B[(d * a.nb + (int)((bo[u] >> (8 * d)) & 255u)) * 64];
+#pragma unroll
+      for (int u = 0; u < SGI_BATCH; ++u) wr += w[u];
     }
+    c = c1;
     const double* Tr = T + (int64_t)r * 10;
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] += wr * Tr[q];
   }
+  // partial sums of wavefronts 1.. into LDS (the bases are no longer read)
+  __syncthreads();
+  double* red = sgi_lds + lane;  // red[((w - 1) * 10 + q) * 64]
+  if (wave > 0) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) red[((wave - 1) * 10 + q) * 64] = acc[q];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w = 1; w < SGI_WAVES; ++w)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] += red[((w - 1) * 10 + q) * 64];
   if (valid && inside) {
     double* So = a.S + p * 10;
 #pragma unroll
@@ -244,7 +277,11 @@ __global__ __launch_bounds__(64) void sgi_apply_kernel(SgiApplyArgs a) {
   }
 }
 
-size_t sgi_lds_bytes(int kmax, int nb) { return (size_t)64 * (kmax > 0 ? kmax : 1) * nb * sizeof(double); }
+size_t sgi_lds_bytes(int kmax, int nb) {
+  const size_t bases = (size_t)64 * (kmax > 0 ? kmax : 1) * nb * sizeof(double);
+  const size_t red = (size_t)64 * (SGI_WAVES - 1) * 10 * sizeof(double);
+  return bases > red ? bases : red;
+}
 
 hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st) {
   if (a.nsamples == 0) return hipSuccess;
@@ -252,7 +289,7 @@ hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
-  hipLaunchKernelGGL(sgi_apply_kernel, grid, dim3(64), lds, st, a);
+  hipLaunchKernelGGL(sgi_apply_kernel, grid, dim3(64 * SGI_WAVES), lds, st, a);
   return hipGetLastError();
 }
 
