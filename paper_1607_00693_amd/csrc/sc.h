@@ -30,7 +30,6 @@ void sc_smolyak_terms(int dim, int level, const std::function<void(double, const
 // Sparse-grid interpolation in the local variables (levels 0..SGI_LEVEL_MAX).
 constexpr int SGI_LEVEL_MAX = 5;  // 33 nodes per variable at most
 constexpr int SGI_BATCH = 4;      // combination entries evaluated together (entry arrays padded by 3)
-constexpr int SGI_WAVES = 4;      // wavefronts per workgroup sharing one set of bases
 struct SgiApplyArgs {
   int32_t npatch, nxi, level, nb, kmax;
   int64_t nsamples;
@@ -51,7 +50,7 @@ struct SgiApplyArgs {
   int64_t* list;
   unsigned long long* list_count;
 };
-size_t sgi_lds_bytes(int kmax, int nb);
+size_t sgi_lds_bytes(int kmax, int nb, int level);
 hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st);
 
 struct ScApplyArgs {

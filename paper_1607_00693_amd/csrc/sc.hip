@@ -166,7 +166,8 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
 
 // ---- sparse-grid interpolation: sgi_apply_kernel ----
 // One workgroup = one patch K (blockIdx.y) and 64 samples (one per lane of
-// each of its SGI_WAVES wavefronts), so the patch's table and the
+// each of its SGI_WAVES wavefronts: 8 up to level 4, 16 at level 5, where
+// the bases take twice the LDS), so the patch's table and the
 // combination list are read at wave-uniform addresses.  The lanes first
 // evaluate, for every local variable d and every level i <= L+1, the
 // Lagrange basis of the level-i nodes at the sample's t_d in barycentric
@@ -187,6 +188,7 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
 // for the plain path instead.  Every global store (and the list's atomic)
 // comes after the loop, so the wave-uniform loads of the loop are not
 // clobbered and go through the scalar cache.
+template <int SGI_WAVES>
 __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs a) {
   extern __shared__ double sgi_lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -277,20 +279,28 @@ __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs 
   }
 }
 
-size_t sgi_lds_bytes(int kmax, int nb) {
+static int sgi_waves(int level) { return level >= 5 ? 16 : 8; }
+
+size_t sgi_lds_bytes(int kmax, int nb, int level) {
   const size_t bases = (size_t)64 * (kmax > 0 ? kmax : 1) * nb * sizeof(double);
-  const size_t red = (size_t)64 * (SGI_WAVES - 1) * 10 * sizeof(double);
+  const size_t red = (size_t)64 * (sgi_waves(level) - 1) * 10 * sizeof(double);
   return bases > red ? bases : red;
+}
+
+template <int NW>
+static hipError_t launch_sgi(const SgiApplyArgs& a, hipStream_t st) {
+  const size_t lds = sgi_lds_bytes(a.kmax, a.nb, a.level);
+  hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
+  hipLaunchKernelGGL(sgi_apply_kernel<NW>, grid, dim3(64 * NW), lds, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st) {
   if (a.nsamples == 0) return hipSuccess;
-  const size_t lds = sgi_lds_bytes(a.kmax, a.nb);
-  hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
-  hipLaunchKernelGGL(sgi_apply_kernel, grid, dim3(64 * SGI_WAVES), lds, st, a);
-  return hipGetLastError();
+  return sgi_waves(a.level) == 16 ? launch_sgi<16>(a, st) : launch_sgi<8>(a, st);
 }
 
 static int64_t quad_chunk(int64_t npoints) {
