@@ -43,11 +43,14 @@ def u_relerr(U, Uref):
     return (np.linalg.norm(U - Uref, axis=-1) / np.linalg.norm(Uref, axis=-1)).max()
 
 
-@pytest.mark.parametrize("nfine,g,rho", [(100, 3, 0.3), (40, 3, 0.2), (24, 2, 0.4), (64, 4, 0.25)])
+@pytest.mark.parametrize("nfine,g,rho", [(100, 3, 0.3), (40, 3, 0.2), (24, 2, 0.4), (64, 4, 0.25), (256, 8, 0.125),
+                                         (1024, 8, 0.125), (96, 3, 0.1)])
 def test_coefficients_on_tiles_inside_and_across_bump_cells(sm, orc, nfine, g, rho):
-    # bump cells of 33.3, 13.3, 12 and 16 elements: 16 x 16 tiles that lie in
-    # one cell and tiles that straddle two, partial tiles at the edge, FP64
-    # and FP32 storage
+    # bump cells of 33.3, 13.3, 12, 16, 32, 128 (the benchmark mesh) and 32
+    # elements: 16 x 16 tiles that lie in one cell (where the bumps whose disc
+    # misses the tile are skipped; rho = 0.1 leaves some tiles with only their
+    # own cell's bump) and tiles that straddle two, partial tiles at the edge,
+    # FP64 and FP32 storage
     xi = W.uniform_xi(3, g * g, 1950 + nfine)
     prm = dict(g=g, rho=rho, eps=1.0 / 32, base=2.0, amp=1.8, beta=0.5)
     a_ref = orc.coef_bumps(xi, nfine, **prm)
