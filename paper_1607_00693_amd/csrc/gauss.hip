@@ -287,6 +287,78 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs,
   }
 }
 
+// Elements of m <= 16 (every row of a lane's column in one step of four):
+// persistent wavefronts that keep their lane's mode values in registers and
+// take pairs p = w, w + (number of wavefronts), ...  The same products and
+// sums in the same order as kl_project_kernel.
+template <int KT>
+__global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t npairs, int nc, int m, int K,
+                                                                       const double* __restrict__ beta,
+                                                                       const double* __restrict__ mu,
+                                                                       const double* __restrict__ modes, double box,
+                                                                       double* __restrict__ xi,
+                                                                       int32_t* __restrict__ outside,
+                                                                       unsigned long long* count) {
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63;
+  const int64_t nf = (int64_t)nc * m, mm = (int64_t)m * m;
+  const int rpi = 64 / m, c0 = lane % m, r0 = lane / m;
+  bool rok[U];
+  int64_t roff[U];
+  double mv[U][KT];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = r0 + u * rpi;
+    rok[u] = r0 < rpi && r < m;
+    roff[u] = rok[u] ? (int64_t)r * nf + c0 : 0;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) mv[u][k] = (rok[u] && k < K) ? modes[k * mm + r * m + c0] : 0.0;
+  }
+  const double sq = lane < K ? sqrt(mu[lane]) : 1.0;
+  const uint32_t M = (uint32_t)nc * (uint32_t)nc;
+  const int64_t nw = (int64_t)gridDim.x * KL_WPB;
+  for (int64_t p = (int64_t)blockIdx.x * KL_WPB + (threadIdx.x >> 6); p < npairs; p += nw) {
+    const uint32_t pu = (uint32_t)p;
+    const int64_t s = pu / M;
+    const int K0 = (int)(pu - (uint32_t)s * M), kx = K0 % nc, ky = K0 / nc;
+    const double* B = beta + s * nf * nf + (int64_t)ky * m * nf + (int64_t)kx * m;
+    double bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) bv[u] = rok[u] ? B[roff[u]] : 0.0;
+    double acc[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (rok[u]) {
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < K) acc[k] += bv[u] * mv[u][k];
+      }
+    double tk = 0.0;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < K) {
+        double t = acc[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        tk = lane == k ? t : tk;
+      }
+    }
+    bool mine_out = false;
+    if (lane < K) {
+      const double x = tk / sq;
+      xi[p * K + lane] = x;
+      mine_out = !(fabs(x) <= box);
+    }
+    const bool out = __any(mine_out);
+    if (lane == 0) {
+      if (outside) outside[p] = out ? 1 : 0;
+      if (out && count) atomicAdd(count, 1ull);
+    }
+  }
+}
+
 hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double* beta, const double* mu,
                              const double* modes, double box, double* xi, int32_t* outside,
                              unsigned long long* count, hipStream_t st) {
@@ -294,7 +366,11 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double*
   if (K < 1 || K > KL_KMAX) return hipErrorInvalidValue;
   if (npairs > 0xffffffffLL) return hipErrorInvalidValue;
   const int64_t nb = (npairs + KL_WPB - 1) / KL_WPB;
-  if (K <= 4)
+  if (K <= 4 && m <= 16) {
+    const unsigned nbp = (unsigned)(nb < 2048 ? nb : 2048);  // persistent: about eight wavefronts per CU
+    hipLaunchKernelGGL(kl_project_small_kernel<4>, dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K, beta, mu,
+                       modes, box, xi, outside, count);
+  } else if (K <= 4)
     hipLaunchKernelGGL(kl_project_kernel<4>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K, beta,
                        mu, modes, box, xi, outside, count);
   else

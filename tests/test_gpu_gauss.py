@@ -91,6 +91,23 @@ def test_projection_ragged(sm):
     assert out_r.any() and (~out_r).any()
 
 
+@pytest.mark.parametrize("nc,m,K", [(2, 20, 3), (1, 70, 2), (3, 16, 4), (2, 8, 7)])
+def test_projection_kernels_on_generated_modes(sm, nc, m, K):
+    # the projection alone, on seeded modes and eigenvalues (any vectors
+    # serve): elements of 20 and 70 cells (rows over several steps, columns
+    # wider than a wavefront), 16 (the persistent kernel) and K > 4
+    N = 3
+    beta = W.uniform_array((N, nc * m, nc * m), -2.0, 2.0, 2120 + m)
+    V = W.uniform_array((K, m, m), -1.0, 1.0, 2130 + m) / m
+    mu = W.uniform_array((K,), 0.5, 2.0, 2140 + m)
+    xi, outside, count = sm.kl_project(torch.from_numpy(beta).cuda(), nc, m, torch.from_numpy(mu).cuda(),
+                                       torch.from_numpy(V).cuda(), 1.0)
+    xi_r = gauss.project(beta, nc, m, mu, V)
+    np.testing.assert_allclose(xi.cpu().numpy(), xi_r, rtol=0, atol=1e-12 * np.abs(xi_r).max())
+    out_r = (np.abs(xi_r) > 1.0).any(axis=2)
+    assert (outside.cpu().numpy() == out_r).all() and int(count.item()) == int(out_r.sum())
+
+
 def test_stiffness_on_the_truncated_coefficient(sm):
     # S of the truncated (non-affine) coefficient through the plain upscaling
     # kernels on 1 x 1 meshes, and S of the sample itself; both against the
