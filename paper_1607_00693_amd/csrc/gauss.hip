@@ -12,11 +12,12 @@
 // form of the cosine recurrence (d_{k+1} = d_k + lambda c_k, c_{k+1} = c_k +
 // d_{k+1}, lambda = -4 sin^2(a/2), d_1 = -2 sin(a/2) sin(theta_0 + a/2)),
 // which stays accurate as a -> 0 where the three-term form
-// c_{k+1} = 2 cos(a) c_k - c_{k-1} loses digits.  Terms with cos a < 0 take
-// the complex rotation by e^{i a} instead (five operations per row).  Both
-// keep the error within a few ulp per row (1e-14 on beta at 256 terms and
-// 32-row strips).  A workgroup covers 64 columns x 4 strips of one sample;
-// the sample's terms are staged in LDS.
+// c_{k+1} = 2 cos(a) c_k - c_{k-1} loses digits.  The angle is first reduced
+// to [-pi/2, pi/2]: with a = a' + pi (mod 2 pi), c_k = (-1)^k cos(theta_0 +
+// k a'), so such terms run the same recurrence on a' and add the odd rows
+// with a minus sign.  beta stays within 2.5e-14 of the direct cosines at 256
+// terms and 64-row strips.  A workgroup covers 64 columns x 4 strips of one
+// sample; the sample's terms are staged in LDS.
 //
 // Local KL (host): the patch covariance exp(-dx^2/l1^2 - dy^2/l2^2) on the
 // m x m centroids is the Kronecker product of two m x m matrices, so its
@@ -38,7 +39,7 @@ namespace stomsfem {
 
 constexpr int GF_TX = 64;     // columns per workgroup, one per lane
 constexpr int GF_SY = 4;      // strips per workgroup, one per wavefront
-constexpr int GF_RY = 32;     // rows per strip
+constexpr int GF_RY = 64;     // rows per strip
 constexpr int GF_JMAX = 1024;  // spectral terms per sample
 constexpr int KL_KMAX = 16;    // local KL terms
 
@@ -48,9 +49,8 @@ __global__ __launch_bounds__(256) void gauss_field_kernel(int64_t nsamples, int 
                                                           double* __restrict__ beta, double* __restrict__ kappa,
                                                           int tiles_x, int tiles_y) {
   __shared__ double2 ws[GF_JMAX];   // (w1, w2)
-  __shared__ double2 rs[GF_JMAX];   // (cos a, sin a), a = w2 h
-  __shared__ double2 hs[GF_JMAX];   // (sin a/2, cos a/2)
-  __shared__ double phs[GF_JMAX];
+  __shared__ double2 hs[GF_JMAX];   // (sin a'/2, cos a'/2), a' = w2 h reduced to [-pi/2, pi/2]
+  __shared__ double2 ps[GF_JMAX];   // (phi, sign of the odd rows)
   const int64_t tiles = (int64_t)tiles_x * tiles_y;
   const int64_t nblk = nsamples * tiles;
   const double h = 1.0 / nfine, amp = sqrt(2.0 / J);
@@ -63,13 +63,14 @@ __global__ __launch_bounds__(256) void gauss_field_kernel(int64_t nsamples, int 
     for (int j = threadIdx.x; j < J; j += 256) {
       const double w1 = sqrt(2.0) * z[(s * J + j) * 2] / l1;
       const double w2 = sqrt(2.0) * z[(s * J + j) * 2 + 1] / l2;
-      double sn, cs, snh, csh;
-      sincos(w2 * h, &sn, &cs);
-      sincos(0.5 * (w2 * h), &snh, &csh);
+      const double al = remainder(w2 * h, 2.0 * M_PI);  // [-pi, pi]
+      const bool alt = fabs(al) > 0.5 * M_PI;
+      const double alp = alt ? al - copysign(M_PI, al) : al;
+      double snh, csh;
+      sincos(0.5 * alp, &snh, &csh);
       ws[j] = make_double2(w1, w2);
-      rs[j] = make_double2(cs, sn);
       hs[j] = make_double2(snh, csh);
-      phs[j] = 2.0 * M_PI * u[s * J + j];
+      ps[j] = make_double2(2.0 * M_PI * u[s * J + j], alt ? -1.0 : 1.0);
     }
     __syncthreads();
     const int ix = tx * GF_TX + lane, iy0 = (ty * GF_SY + strip) * GF_RY;
@@ -78,29 +79,17 @@ __global__ __launch_bounds__(256) void gauss_field_kernel(int64_t nsamples, int 
 #pragma unroll
     for (int k = 0; k < GF_RY; ++k) acc[k] = 0.0;
     for (int j = 0; j < J; ++j) {
-      const double2 w = ws[j], r = rs[j];
+      const double2 w = ws[j], hh = hs[j], pp = ps[j];
       double c, sn;
-      sincos(w.x * x + w.y * y0 + phs[j], &sn, &c);
+      sincos(w.x * x + w.y * y0 + pp.x, &sn, &c);
       acc[0] += c;
-      if (r.x >= 0.0) {  // the same branch for the whole workgroup
-        const double2 hh = hs[j];
-        const double lam = -4.0 * hh.x * hh.x;
-        double d = -2.0 * hh.x * (sn * hh.y + c * hh.x);
+      const double lam = -4.0 * hh.x * hh.x;
+      double d = -2.0 * hh.x * (sn * hh.y + c * hh.x);
 #pragma unroll
-        for (int k = 1; k < GF_RY; ++k) {
-          c += d;
-          acc[k] += c;
-          d = __builtin_fma(lam, c, d);
-        }
-      } else {
-        double re = c, im = sn;
-#pragma unroll
-        for (int k = 1; k < GF_RY; ++k) {
-          const double nre = re * r.x - im * r.y;
-          im = re * r.y + im * r.x;
-          re = nre;
-          acc[k] += re;
-        }
+      for (int k = 1; k < GF_RY; ++k) {
+        c += d;
+        acc[k] = (k & 1) ? __builtin_fma(pp.y, c, acc[k]) : acc[k] + c;
+        d = __builtin_fma(lam, c, d);
       }
     }
     if (ix < nfine) {
