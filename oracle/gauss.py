@@ -21,7 +21,9 @@ gives eigenvalues lambda = h^2 mu and modes f = v / h for the eigenpairs
   beta ~ sum_{k <= K} sqrt(mu_k) xi_k v_k     (eqs. localKL, local_KL_truncation),
 the KL being applied to the Gaussian field beta (kappa is non-affine in xi).
 The covariance is translation invariant, so one set of modes serves every
-patch.  Outside the box |xi_k| <= 3 the interpolant is not used (the plain
+patch; the same holds for the oversampled patches of Sec. 2.2 (side m + 2o,
+moved inside the domain at its edge), the domains on which Sec. 5.3 takes the
+local KL.  Outside the box |xi_k| <= 3 the interpolant is not used (the plain
 path is); for independent standard normal xi_k the probability of that is
 1 - P(|Z| <= 3)^K.
 """
@@ -79,6 +81,31 @@ def project(beta: np.ndarray, nc: int, m: int, mu: np.ndarray, V: np.ndarray) ->
     for ky in range(nc):
         for kx in range(nc):
             blk = beta[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m].reshape(N, -1)
+            for k in range(Kt):
+                xi[:, ky * nc + kx, k] = blk @ V[k].ravel() / np.sqrt(mu[k])
+    return xi
+
+
+def project_patches(beta: np.ndarray, nc: int, m: int, o: int, mu: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """xi [N][nc*nc][K] on the oversampled patches (Sec. 2.2: side m + 2o
+    fine cells around each coarse element, moved inside the domain where it
+    would stick out, so every patch has the same shape and one set of modes
+    of side m + 2o serves all of them).  o = 0 gives project()."""
+    N = beta.shape[0]
+    nf = nc * m
+    P = m + 2 * o
+    if P > nf:
+        raise ValueError("the oversampled patch is larger than the domain")
+    Kt = len(mu)
+
+    def origin(k):
+        return min(max(k * m - o, 0), nf - P)
+
+    xi = np.zeros((N, nc * nc, Kt))
+    for ky in range(nc):
+        for kx in range(nc):
+            x0, y0 = origin(kx), origin(ky)
+            blk = beta[:, y0:y0 + P, x0:x0 + P].reshape(N, -1)
             for k in range(Kt):
                 xi[:, ky * nc + kx, k] = blk @ V[k].ravel() / np.sqrt(mu[k])
     return xi

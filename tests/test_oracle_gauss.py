@@ -60,6 +60,50 @@ def test_projection_recovers_synthesized_parameters():
     np.testing.assert_allclose(gauss.project(beta, nc, m, mu, V), xi, rtol=0, atol=1e-12)
 
 
+def test_projection_on_oversampled_patches():
+    # patches of side m + 2o around each element, moved inside the domain:
+    # with nc = 4, m = 8, o = 4 the patch origins along an axis are 0, 4, 12,
+    # 16 (elements 0 and 3 are pushed in from -4 and 20).  Parameters
+    # synthesized on one element's patch (random field elsewhere) come back,
+    # which a wrong origin or a transposed patch would break; o = 0 is the
+    # element projection.
+    nc, m, o, K = 4, 8, 4, 5
+    P, nf = m + 2 * o, nc * m
+    mu, V, _ = gauss.local_kl(P, 1.0 / nf, 1.0, 1.0 / 24, K)
+    rng = np.random.default_rng(5)
+    for (kx, ky), (x0, y0) in {(0, 0): (0, 0), (1, 2): (4, 12), (3, 1): (16, 4), (2, 3): (12, 16)}.items():
+        beta = rng.normal(size=(2, nf, nf))
+        xs = rng.normal(size=(2, K))
+        beta[:, y0:y0 + P, x0:x0 + P] = np.einsum("nk,kij->nij", xs * np.sqrt(mu), V)
+        xi = gauss.project_patches(beta, nc, m, o, mu, V)
+        np.testing.assert_allclose(xi[:, ky * nc + kx], xs, rtol=0, atol=1e-12)
+    mu0, V0, _ = gauss.local_kl(m, 1.0 / nf, 1.0, 1.0 / 24, K)
+    beta = rng.normal(size=(2, nf, nf))
+    np.testing.assert_allclose(gauss.project_patches(beta, nc, m, 0, mu0, V0), gauss.project(beta, nc, m, mu0, V0),
+                               rtol=0, atol=1e-13)
+    with pytest.raises(ValueError):
+        gauss.project_patches(beta, 1, m, o, mu, V)
+
+
+def test_oversampled_patch_kl_in_the_papers_geometry():
+    # Sec. 5.3: the local KL on the oversampled domain of side 2H with l2 = H
+    # (two correlation lengths across), four terms.  The kept fraction of the
+    # patch variance and the rate of pairs with a parameter outside [-3, 3]
+    # against 1 - P(|Z| <= 3)^4 = 0.0108 on spectral samples.
+    nc, m = 8, 8
+    o = m // 2
+    P, nf = m + 2 * o, nc * m
+    l1, l2 = 1.0, 1.0 / nc
+    mu, V, cap = gauss.local_kl(P, 1.0 / nf, l1, l2, 4)
+    assert 0.985 < mu.sum() / (P * P) < 0.997  # "about 99%" with four terms
+    N = 100
+    z, u = W.spectral_draws(N, 256, 73)
+    xi = gauss.project_patches(gauss.field(z, u, nf, l1, l2), nc, m, o, mu, V)
+    out = (np.abs(xi) > 3.0).any(axis=2)
+    p = gauss.outside_probability(4)
+    assert abs(out.mean() - p) < 4.5 * np.sqrt(p * (1 - p) / out.size) + 0.003
+
+
 def test_truncation_error_matches_the_discarded_spectrum_and_the_fallback_rate():
     wl = W.GAUSS16
     nc, m = 8, wl.m  # half the mesh, same element size and correlation lengths
