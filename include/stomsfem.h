@@ -237,6 +237,16 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
  * (may be NULL) = 1 where some |xi_k| > box; count (device uint64, may be
  * NULL) receives the number of such pairs (cleared first).  Asynchronous.
  *
+ * stomsfem_kl_project_patches: the same on the oversampled patches of
+ * Sec. 2.2, the domains on which Sec. 5.3 takes the local KL: the patch of
+ * coarse element (kx, ky) is the element widened by `oversample` fine cells
+ * on each side, moved inside the domain where it would stick out (first
+ * cell along an axis: min(max(k m - oversample, 0), nc m - (m + 2
+ * oversample))), so every patch has side m + 2 oversample and modes device
+ * [K][m + 2 oversample][m + 2 oversample] (local_kl with that side) serve
+ * all of them.  oversample = 0 is stomsfem_kl_project.  EINVAL if
+ * oversample < 0 or the patch is wider than the domain.
+ *
  * stomsfem_kl_blocks: the truncated coefficient 0.1 + exp(sum_{k < Kuse}
  * sqrt(mu_k) xi_k modes_k) on every pair's element, blocks device
  * [npairs][m][m], from xi device [npairs][K]; the blocks are a batch of
@@ -249,6 +259,9 @@ int stomsfem_local_kl(int32_t m, double h, double l1, double l2, int32_t K, doub
 int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* beta, int32_t K, const double* mu,
                         const double* modes, double box, double* xi, int32_t* outside, uint64_t* count,
                         void* stream);
+int stomsfem_kl_project_patches(int64_t nsamples, int32_t nc, int32_t m, int32_t oversample, const double* beta,
+                                int32_t K, const double* mu, const double* modes, double box, double* xi,
+                                int32_t* outside, uint64_t* count, void* stream);
 int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const double* xi, const double* mu,
                        const double* modes, double* blocks, void* stream);
 

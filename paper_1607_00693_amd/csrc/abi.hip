@@ -34,7 +34,7 @@ hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t s
 hipError_t launch_gauss_field(int64_t nsamples, int nfine, int J, const double* z, const double* u, double l1,
                               double l2, double* beta, double* kappa, hipStream_t st);
 void local_kl_modes(int m, double h, double l1, double l2, int K, double* mu, double* modes, double* captured);
-hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double* beta, const double* mu,
+hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const double* beta, const double* mu,
                              const double* modes, double box, double* xi, int32_t* outside,
                              unsigned long long* count, hipStream_t st);
 hipError_t launch_kl_blocks(int64_t npairs, int m, int Kuse, int K, const double* xi, const double* mu,
@@ -524,21 +524,37 @@ int stomsfem_local_kl(int32_t m, double h, double l1, double l2, int32_t K, doub
   return STOMSFEM_OK;
 }
 
-int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* beta, int32_t K, const double* mu,
-                        const double* modes, double box, double* xi, int32_t* outside, uint64_t* count,
-                        void* stream) {
-  if (nsamples < 0 || nc < 1 || m < 1 || K < 1 || K > 16 || K > m * m || !(box > 0))
-    return fail(STOMSFEM_EINVAL, "kl_project: need nc, m >= 1, 1 <= K <= min(16, m*m), box > 0");
+static int kl_project_any(const char* name, int64_t nsamples, int32_t nc, int32_t m, int32_t o, const double* beta,
+                          int32_t K, const double* mu, const double* modes, double box, double* xi, int32_t* outside,
+                          uint64_t* count, void* stream) {
+  const int64_t P = (int64_t)m + 2 * (int64_t)o;
+  if (nsamples < 0 || nc < 1 || m < 1 || o < 0 || P > (int64_t)nc * m || K < 1 || K > 16 || K > P * P || !(box > 0))
+    return fail(STOMSFEM_EINVAL, std::string(name) +
+                                     ": need nc, m >= 1, 0 <= oversample, m + 2 oversample <= nc m, "
+                                     "1 <= K <= min(16, (m + 2 oversample)^2), box > 0");
   if (!device_ptr(beta) || !device_ptr(mu) || !device_ptr(modes) || !device_ptr(xi) ||
       (outside && !device_ptr(outside)) || (count && !device_ptr(count)))
-    return fail(STOMSFEM_EINVAL, "kl_project: arrays must be device pointers");
+    return fail(STOMSFEM_EINVAL, std::string(name) + ": arrays must be device pointers");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (count) e = launch_zero_u64((unsigned long long*)count, st);
   if (e == hipSuccess)
-    e = launch_kl_project(nsamples * (int64_t)nc * nc, nc, m, K, beta, mu, modes, box, xi, outside,
+    e = launch_kl_project(nsamples * (int64_t)nc * nc, nc, m, o, K, beta, mu, modes, box, xi, outside,
                           (unsigned long long*)count, st);
-  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "kl_project launch");
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, (std::string(name) + " launch").c_str());
+}
+
+int stomsfem_kl_project(int64_t nsamples, int32_t nc, int32_t m, const double* beta, int32_t K, const double* mu,
+                        const double* modes, double box, double* xi, int32_t* outside, uint64_t* count,
+                        void* stream) {
+  return kl_project_any("kl_project", nsamples, nc, m, 0, beta, K, mu, modes, box, xi, outside, count, stream);
+}
+
+int stomsfem_kl_project_patches(int64_t nsamples, int32_t nc, int32_t m, int32_t oversample, const double* beta,
+                                int32_t K, const double* mu, const double* modes, double box, double* xi,
+                                int32_t* outside, uint64_t* count, void* stream) {
+  return kl_project_any("kl_project_patches", nsamples, nc, m, oversample, beta, K, mu, modes, box, xi, outside,
+                        count, stream);
 }
 
 int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const double* xi, const double* mu,

@@ -25,7 +25,9 @@
 // the K largest products give mu_k and the modes v_k = vy (x) vx.
 //
 // kl_project_kernel: one wavefront per (sample, element), four per workgroup:
-// xi_k = v_k . beta / sqrt(mu_k), lanes over the element's m^2 values, the
+// xi_k = v_k . beta / sqrt(mu_k), lanes over the values of the element or of
+// its oversampled patch (side m + 2o, Sec. 2.2, the domain on which Sec. 5.3
+// takes the local KL), the
 // partial sums combined by a butterfly of lane shuffles (a fixed order);
 // pairs with |xi_k| > box for some k are flagged and counted.
 // kl_blocks_kernel: kappa of the first K' terms on every pair's block,
@@ -194,9 +196,17 @@ void local_kl_modes(int m, double h, double l1, double l2, int K, double* mu, do
 
 constexpr int KL_WPB = 4;  // pairs (wavefronts) per workgroup
 
+// First fine cell (one axis) of the patch of coarse element k: the element
+// widened by o cells on each side (Sec. 2.2), moved inside [0, nf) where it
+// would stick out, so every patch has side m + 2o.
+__device__ __forceinline__ int kl_patch_origin(int k, int m, int o, int nf) {
+  const int x0 = k * m - o, hi = nf - (m + 2 * o);
+  return x0 > hi ? hi : (x0 < 0 ? 0 : x0);
+}
+
 // KT: compile-time bound on K (the loops over the terms are unrolled to it)
 template <int KT>
-__global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs, int nc, int m, int K,
+__global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs, int nc, int m, int o, int K,
                                                                  const double* __restrict__ beta,
                                                                  const double* __restrict__ mu,
                                                                  const double* __restrict__ modes, double box,
@@ -210,43 +220,45 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs,
   const uint32_t M = (uint32_t)nc * (uint32_t)nc, pu = (uint32_t)p;
   const int64_t s = pu / M;
   const int K0 = (int)(pu - (uint32_t)s * M), kx = K0 % nc, ky = K0 / nc;
-  const int64_t nf = (int64_t)nc * m, mm = (int64_t)m * m;
-  const double* B = beta + s * nf * nf + (int64_t)ky * m * nf + (int64_t)kx * m;
+  const int P = m + 2 * o;  // patch side (the element itself when o = 0)
+  const int64_t nf = (int64_t)nc * m, mm = (int64_t)P * P;
+  const double* B = beta + s * nf * nf + (int64_t)kl_patch_origin(ky, m, o, (int)nf) * nf +
+                    kl_patch_origin(kx, m, o, (int)nf);
   double acc[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) acc[k] = 0.0;
-  // lanes as rpi rows of cw columns of the element (one division per lane)
-  const int cw = m < 64 ? m : 64, rpi = 64 / cw;
+  // lanes as rpi rows of cw columns of the patch (one division per lane)
+  const int cw = P < 64 ? P : 64, rpi = 64 / cw;
   const int c0 = lane % cw, r0 = lane / cw;
   if (r0 < rpi) {
     // four rows per step so that a wavefront has four loads in flight
     constexpr int U = 4;
-    for (int rb = r0; rb < m; rb += U * rpi) {
+    for (int rb = r0; rb < P; rb += U * rpi) {
       double bv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int r = rb + u * rpi;
-        bv[u] = (r < m && c0 < m) ? B[(int64_t)r * nf + c0] : 0.0;
+        bv[u] = (r < P && c0 < P) ? B[(int64_t)r * nf + c0] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int r = rb + u * rpi;
-        if (r < m) {
+        if (r < P) {
 #pragma unroll
           for (int k = 0; k < KT; ++k)
-            if (k < K) acc[k] += bv[u] * modes[k * mm + r * m + c0];
+            if (k < K) acc[k] += bv[u] * modes[k * mm + r * P + c0];
         }
       }
       // columns beyond the first 64 (elements wider than a wavefront)
-      for (int c = c0 + cw; c < m; c += cw)
+      for (int c = c0 + cw; c < P; c += cw)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int r = rb + u * rpi;
-          if (r < m) {
+          if (r < P) {
             const double b = B[(int64_t)r * nf + c];
 #pragma unroll
             for (int k = 0; k < KT; ++k)
-              if (k < K) acc[k] += b * modes[k * mm + r * m + c];
+              if (k < K) acc[k] += b * modes[k * mm + r * P + c];
           }
         }
     }
@@ -276,12 +288,12 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs,
   }
 }
 
-// Elements of m <= 16 (every row of a lane's column in one step of four):
+// Patches of side <= 16 (every row of a lane's column in one step of four):
 // persistent wavefronts that keep their lane's mode values in registers and
 // take pairs p = w, w + (number of wavefronts), ...  The same products and
 // sums in the same order as kl_project_kernel.
 template <int KT>
-__global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t npairs, int nc, int m, int K,
+__global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t npairs, int nc, int m, int o, int K,
                                                                        const double* __restrict__ beta,
                                                                        const double* __restrict__ mu,
                                                                        const double* __restrict__ modes, double box,
@@ -290,18 +302,19 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t n
                                                                        unsigned long long* count) {
   constexpr int U = 4;
   const int lane = threadIdx.x & 63;
-  const int64_t nf = (int64_t)nc * m, mm = (int64_t)m * m;
-  const int rpi = 64 / m, c0 = lane % m, r0 = lane / m;
+  const int P = m + 2 * o;
+  const int64_t nf = (int64_t)nc * m, mm = (int64_t)P * P;
+  const int rpi = 64 / P, c0 = lane % P, r0 = lane / P;
   bool rok[U];
   int64_t roff[U];
   double mv[U][KT];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int r = r0 + u * rpi;
-    rok[u] = r0 < rpi && r < m;
+    rok[u] = r0 < rpi && r < P;
     roff[u] = rok[u] ? (int64_t)r * nf + c0 : 0;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) mv[u][k] = (rok[u] && k < K) ? modes[k * mm + r * m + c0] : 0.0;
+    for (int k = 0; k < KT; ++k) mv[u][k] = (rok[u] && k < K) ? modes[k * mm + r * P + c0] : 0.0;
   }
   const double sq = lane < K ? sqrt(mu[lane]) : 1.0;
   const uint32_t M = (uint32_t)nc * (uint32_t)nc;
@@ -310,7 +323,8 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t n
     const uint32_t pu = (uint32_t)p;
     const int64_t s = pu / M;
     const int K0 = (int)(pu - (uint32_t)s * M), kx = K0 % nc, ky = K0 / nc;
-    const double* B = beta + s * nf * nf + (int64_t)ky * m * nf + (int64_t)kx * m;
+    const double* B = beta + s * nf * nf + (int64_t)kl_patch_origin(ky, m, o, (int)nf) * nf +
+                      kl_patch_origin(kx, m, o, (int)nf);
     double bv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) bv[u] = rok[u] ? B[roff[u]] : 0.0;
@@ -348,22 +362,22 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t n
   }
 }
 
-hipError_t launch_kl_project(int64_t npairs, int nc, int m, int K, const double* beta, const double* mu,
+hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const double* beta, const double* mu,
                              const double* modes, double box, double* xi, int32_t* outside,
                              unsigned long long* count, hipStream_t st) {
   if (npairs == 0) return hipSuccess;
-  if (K < 1 || K > KL_KMAX) return hipErrorInvalidValue;
+  if (K < 1 || K > KL_KMAX || o < 0 || m + 2 * o > nc * m) return hipErrorInvalidValue;
   if (npairs > 0xffffffffLL) return hipErrorInvalidValue;
   const int64_t nb = (npairs + KL_WPB - 1) / KL_WPB;
-  if (K <= 4 && m <= 16) {
+  if (K <= 4 && m + 2 * o <= 16) {
     const unsigned nbp = (unsigned)(nb < 2048 ? nb : 2048);  // persistent: about eight wavefronts per CU
-    hipLaunchKernelGGL(kl_project_small_kernel<4>, dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K, beta, mu,
-                       modes, box, xi, outside, count);
+    hipLaunchKernelGGL(kl_project_small_kernel<4>, dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K, beta,
+                       mu, modes, box, xi, outside, count);
   } else if (K <= 4)
-    hipLaunchKernelGGL(kl_project_kernel<4>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K, beta,
+    hipLaunchKernelGGL(kl_project_kernel<4>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K, beta,
                        mu, modes, box, xi, outside, count);
   else
-    hipLaunchKernelGGL(kl_project_kernel<KL_KMAX>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, K,
+    hipLaunchKernelGGL(kl_project_kernel<KL_KMAX>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K,
                        beta, mu, modes, box, xi, outside, count);
   return hipGetLastError();
 }

@@ -131,6 +131,7 @@ def lib():
         "stomsfem_coef_gauss": (C.c_int, [i64, i32, i32, vp, vp, dbl, dbl, vp, vp, vp]),
         "stomsfem_local_kl": (C.c_int, [i32, dbl, dbl, dbl, i32, vp, vp, vp]),
         "stomsfem_kl_project": (C.c_int, [i64, i32, i32, vp, i32, vp, vp, dbl, vp, vp, vp, vp]),
+        "stomsfem_kl_project_patches": (C.c_int, [i64, i32, i32, i32, vp, i32, vp, vp, dbl, vp, vp, vp, vp]),
         "stomsfem_kl_blocks": (C.c_int, [i64, i32, i32, i32, vp, vp, vp, vp, vp]),
         "stomsfem_kl_interp_build": (C.c_int, [i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_kl_interp_apply": (C.c_int, [vp, vp, vp, i64, vp, vp, C.POINTER(i64), vp]),
@@ -265,15 +266,22 @@ def local_kl(m: int, h: float, l1: float, l2: float, K: int):
 
 
 def kl_project(beta: torch.Tensor, nc: int, m: int, mu: torch.Tensor, modes: torch.Tensor, box: float = 3.0,
-               stream=None):
-    """(xi [N][nc*nc][K], outside [N][nc*nc] int32, number of outside pairs)."""
+               stream=None, oversample: int = 0):
+    """(xi [N][nc*nc][K], outside [N][nc*nc] int32, number of outside pairs).
+    oversample > 0: on the oversampled patches of side m + 2 oversample
+    (modes of that side)."""
     N = beta.shape[0]
     K = mu.shape[0]
     xi = torch.empty((N, nc * nc, K), dtype=torch.float64, device=beta.device)
     outside = torch.empty((N, nc * nc), dtype=torch.int32, device=beta.device)
     count = torch.zeros(1, dtype=torch.int64, device=beta.device)
-    _check("stomsfem_kl_project", lib().stomsfem_kl_project(N, nc, m, _ptr(beta), K, _ptr(mu), _ptr(modes), box,
-                                                           _ptr(xi), _ptr(outside), _ptr(count), _stream(stream)))
+    if oversample == 0:
+        _check("stomsfem_kl_project", lib().stomsfem_kl_project(N, nc, m, _ptr(beta), K, _ptr(mu), _ptr(modes), box,
+                                                               _ptr(xi), _ptr(outside), _ptr(count), _stream(stream)))
+    else:
+        _check("stomsfem_kl_project_patches",
+               lib().stomsfem_kl_project_patches(N, nc, m, oversample, _ptr(beta), K, _ptr(mu), _ptr(modes), box,
+                                                 _ptr(xi), _ptr(outside), _ptr(count), _stream(stream)))
     return xi, outside, count
 
 

@@ -32,13 +32,17 @@ def sm():
     return stomsfem
 
 
-@pytest.mark.parametrize("N,nf,J", [(2, 48, 64), (3, 40, 7), (1, 256, 256), (2, 200, 33), (1, 97, 1024)])
-def test_field_matches_oracle(sm, N, nf, J):
-    say(f"field N={N} nf={nf} J={J}")
+@pytest.mark.parametrize("N,nf,J,l2", [(2, 48, 64, 1 / 32), (3, 40, 7, 1 / 32), (1, 256, 256, 1 / 32),
+                                       (2, 200, 33, 1 / 32), (1, 97, 1024, 1 / 32), (1, 128, 64, 1 / 512),
+                                       (1, 70, 16, 2.0)])
+def test_field_matches_oracle(sm, N, nf, J, l2):
+    # l2 = 1/512: angle steps w2 h of several radians (most terms reduced by
+    # pi); l2 = 2: steps near zero
+    say(f"field N={N} nf={nf} J={J} l2={l2}")
     z, u = W.spectral_draws(N, J, 2000 + nf)
-    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, 1.0, 1.0 / 32,
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, 1.0, l2,
                               with_beta=True)
-    b_ref = gauss.field(z, u, nf, 1.0, 1.0 / 32)
+    b_ref = gauss.field(z, u, nf, 1.0, l2)
     assert np.abs(beta.cpu().numpy() - b_ref).max() < 1e-12
     np.testing.assert_allclose(kap.cpu().numpy(), gauss.kappa(b_ref), rtol=1e-10, atol=0)
 
@@ -106,6 +110,34 @@ def test_projection_kernels_on_generated_modes(sm, nc, m, K):
     np.testing.assert_allclose(xi.cpu().numpy(), xi_r, rtol=0, atol=1e-12 * np.abs(xi_r).max())
     out_r = (np.abs(xi_r) > 1.0).any(axis=2)
     assert (outside.cpu().numpy() == out_r).all() and int(count.item()) == int(out_r.sum())
+
+
+@pytest.mark.parametrize("nc,m,o,K", [(4, 8, 4, 4), (16, 16, 8, 4), (3, 6, 2, 6), (2, 5, 0, 3)])
+def test_projection_on_oversampled_patches(sm, nc, m, o, K):
+    # patches of side m + 2o moved inside the domain (corner, edge and
+    # interior origins), on seeded modes: side 16 (persistent kernel), 32 (the
+    # workload's 2H patches), 10 with K = 6, and o = 0
+    N, P = 3, m + 2 * o
+    say(f"patch projection nc={nc} m={m} o={o} K={K}")
+    beta = W.uniform_array((N, nc * m, nc * m), -2.0, 2.0, 2150 + P)
+    V = W.uniform_array((K, P, P), -1.0, 1.0, 2160 + P) / P
+    mu = W.uniform_array((K,), 0.5, 2.0, 2170 + P)
+    xi, outside, count = sm.kl_project(torch.from_numpy(beta).cuda(), nc, m, torch.from_numpy(mu).cuda(),
+                                       torch.from_numpy(V).cuda(), 1.0, oversample=o)
+    xi_r = gauss.project_patches(beta, nc, m, o, mu, V)
+    np.testing.assert_allclose(xi.cpu().numpy(), xi_r, rtol=0, atol=1e-12 * np.abs(xi_r).max())
+    out_r = (np.abs(xi_r) > 1.0).any(axis=2)
+    assert (outside.cpu().numpy() == out_r).all() and int(count.item()) == int(out_r.sum())
+
+
+def test_patch_projection_rejects_a_patch_wider_than_the_domain(sm):
+    beta = torch.zeros((1, 16, 16), dtype=torch.float64, device="cuda")
+    mu = torch.ones(2, dtype=torch.float64, device="cuda")
+    V = torch.zeros((2, 24, 24), dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError):
+        sm.kl_project(beta, 2, 8, mu, V, 3.0, oversample=8)
+    with pytest.raises(sm.StomsfemError):
+        sm.kl_project(beta, 2, 8, mu, V, 3.0, oversample=-1)
 
 
 def test_stiffness_on_the_truncated_coefficient(sm):
