@@ -165,3 +165,76 @@ def kl_interp_online(model: dict, xi: np.ndarray, kap: np.ndarray, nc: int, m: i
             Sp, _, _ = core.upscale(blk, 1, 1, m)
             S[~inside, p] = Sp[:, 0, :]
     return S, fb
+
+
+# --- interpolation of the oversampled Petrov-Galerkin stiffness in the
+# --- parameters of the oversampled patch (Secs. 2.2, 3.1 and 5.3)
+
+
+def patch_origin(k: int, m: int, o: int, nf: int) -> int:
+    """First fine cell (one axis) of the oversampled patch of element k."""
+    return min(max(k * m - o, 0), nf - (m + 2 * o))
+
+
+def element_class(k: int, m: int, o: int, nc: int) -> int:
+    """Where element k sits in its patch along one axis: its offset from the
+    patch origin is 0, o or 2o (for 1 <= o <= m), class 0, 1 or 2."""
+    return (k * m - patch_origin(k, m, o, nc * m)) // o
+
+
+def os_S_embedded(blocks: np.ndarray, m: int, o: int, cx: int, cy: int) -> np.ndarray:
+    """[n][16] oversampled Petrov-Galerkin stiffness of an element at class
+    (cx, cy) whose patch coefficient is blocks[i] ([n][m+2o][m+2o]): the
+    patch placed in a 3 x 3-element mesh (where element (cx, cy) has that
+    class; the rest of that mesh is 1 and is never read by the cell problems,
+    which live on the patch), element (cx, cy) of it."""
+    from . import core
+
+    P, nf3 = m + 2 * o, 3 * m
+    x0, y0 = patch_origin(cx, m, o, nf3), patch_origin(cy, m, o, nf3)
+    out = np.zeros((len(blocks), 16))
+    for i, blk in enumerate(blocks):
+        f = np.ones((nf3, nf3))
+        f[y0:y0 + P, x0:x0 + P] = blk
+        out[i] = core.cell_S_os(f, m, o, cx, cy).ravel()
+    return out
+
+
+def kl_interp_os_offline(m: int, o: int, mu: np.ndarray, V: np.ndarray, nn: int, box: float = 3.0) -> dict:
+    """Tables of the 16 entries at the nn^K Lobatto tensor nodes of the patch
+    parameters, one per element class: at a node the patch coefficient is the
+    truncated local KL 0.1 + exp(sum_k sqrt(mu_k) xi_k V_k) (side m + 2o)."""
+    import itertools
+
+    from . import ri
+
+    if not 1 <= o <= m:
+        raise ValueError("need 1 <= o <= m")
+    K = len(mu)
+    nodes = ri.cgl_nodes(nn, -box, box)
+    xi_nodes = np.array([[nodes[d] for d in digits] for digits in itertools.product(range(nn), repeat=K)])
+    blocks = truncated_kappa_blocks(xi_nodes[None], mu, V, K)[0]
+    tables = {(cx, cy): os_S_embedded(blocks, m, o, cx, cy) for cy in range(3) for cx in range(3)}
+    return dict(tables=tables, nodes=nodes, box=box, K=K, m=m, o=o)
+
+
+def kl_interp_os_online(model: dict, xi: np.ndarray, kap: np.ndarray, nc: int):
+    """(S16 [N][nc*nc][16], fallback mask [N][nc*nc]) from the patch
+    parameters xi [N][nc*nc][K]: inside the box the interpolant of the
+    element's class table, outside it the oversampled stiffness of the
+    sample's own coefficient kap [N][nc m][nc m]."""
+    from . import core, ri
+
+    m, o, box = model["m"], model["o"], model["box"]
+    N, M, K = xi.shape
+    S = np.zeros((N, M, 16))
+    fb = ~np.all(np.abs(xi) <= box, axis=2)
+    for p in range(M):
+        kx, ky = p % nc, p // nc
+        cls = (element_class(kx, m, o, nc), element_class(ky, m, o, nc))
+        inside = ~fb[:, p]
+        if np.any(inside):
+            S[inside, p] = ri.ri_eval(model["tables"][cls], model["nodes"], xi[inside, p])
+        for s in np.nonzero(~inside)[0]:
+            S[s, p] = core.cell_S_os(kap[s], m, o, kx, ky).ravel()
+    return S, fb

@@ -159,3 +159,65 @@ def test_interpolation_on_the_local_parameters():
     assert err[3] > err[5] > err[7], err
     trunc = (np.abs(S_trunc - S_full).max(axis=2) / np.abs(S_full).max(axis=2))[~fb].max()
     assert err[7] < 0.1 * trunc, (err[7], trunc)
+
+
+def test_oversampled_stiffness_depends_on_the_patch_and_its_class_only():
+    # the oversampled stiffness of an element, computed on the whole field,
+    # equals the one of its patch placed in a 3 x 3-element mesh at the
+    # element's class (corner, edge, interior elements): the embedding the
+    # interpolation tables are built on
+    from oracle import core
+    nc, m, o = 4, 8, 4
+    P, nf = m + 2 * o, nc * m
+    a = np.exp(np.random.default_rng(11).normal(size=(nf, nf)))
+    assert [gauss.element_class(k, m, o, nc) for k in range(nc)] == [0, 1, 1, 2]
+    for kx, ky in [(0, 0), (1, 2), (3, 3), (2, 0), (3, 1)]:
+        x0, y0 = gauss.patch_origin(kx, m, o, nf), gauss.patch_origin(ky, m, o, nf)
+        full = core.cell_S_os(a, m, o, kx, ky).ravel()
+        emb = gauss.os_S_embedded(a[None, y0:y0 + P, x0:x0 + P], m, o, gauss.element_class(kx, m, o, nc),
+                                  gauss.element_class(ky, m, o, nc))[0]
+        np.testing.assert_allclose(emb, full, rtol=0, atol=1e-12 * np.abs(full).max())
+
+
+def test_oversampled_interpolation_in_the_patch_parameters():
+    # nodal exactness (the interpolant at a node is the oversampled stiffness
+    # of the truncated coefficient there, on the real mesh), convergence in
+    # the number of nodes, and the sample's own stiffness outside the box
+    from oracle import core
+    nc, m, o, K = 4, 8, 4, 3
+    P, nf = m + 2 * o, nc * m
+    mu, V, _ = gauss.local_kl(P, 1.0 / nf, 1.0, 1.0 / 8, K)
+    models = {nn: gauss.kl_interp_os_offline(m, o, mu, V, nn, box=2.0) for nn in (3, 5)}
+    nodes = models[3]["nodes"]
+    # a node's parameters on element (1, 2): its patch carries the truncated KL
+    xn = np.array([nodes[0], nodes[1], nodes[2]])
+    blk = gauss.truncated_kappa_blocks(xn[None, None], mu, V, K)[0, 0]
+    a = np.ones((nf, nf))
+    x0, y0 = gauss.patch_origin(1, m, o, nf), gauss.patch_origin(2, m, o, nf)
+    a[y0:y0 + P, x0:x0 + P] = blk
+    xi = np.zeros((1, nc * nc, K))
+    xi[0, 2 * nc + 1] = xn
+    S, fb = gauss.kl_interp_os_online(models[3], xi, a[None], nc)
+    ref = core.cell_S_os(a, m, o, 1, 2).ravel()
+    np.testing.assert_allclose(S[0, 2 * nc + 1], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    # convergence at random parameters inside the box, interior and corner classes
+    rng = np.random.default_rng(12)
+    xr = rng.uniform(-2.0, 2.0, size=(6, K))
+    blocks = gauss.truncated_kappa_blocks(xr[:, None], mu, V, K)[:, 0]
+    err = {}
+    for nn, md in models.items():
+        e = 0.0
+        for cls in [(1, 1), (0, 2)]:
+            ref = gauss.os_S_embedded(blocks, m, o, *cls)
+            from oracle import ri
+            got = ri.ri_eval(md["tables"][cls], md["nodes"], xr)
+            e = max(e, float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()))
+        err[nn] = e
+    assert err[5] < 0.2 * err[3] and err[5] < 1e-2, err
+    # outside the box: the sample's own oversampled stiffness
+    xi_out = np.full((1, nc * nc, K), 5.0)
+    a2 = np.exp(rng.normal(size=(1, nf, nf)))
+    S2, fb2 = gauss.kl_interp_os_online(models[3], xi_out, a2, nc)
+    assert fb2.all()
+    S_ref, _ = core.upscale_os(a2, nc, nc, m, o)
+    np.testing.assert_allclose(S2, S_ref, rtol=0, atol=1e-12 * np.abs(S_ref).max())
