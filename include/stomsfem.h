@@ -557,11 +557,30 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
  * from kappa device [nsamples][ncy m][ncx m] (FP64).  status device
  * [nsamples][M] or NULL: 0 = interpolated, 1 = computed plainly, ENOTSPD from
  * such a solve; *nfallback (host, may be NULL) = the number of plainly
- * computed pairs.  Synchronises `stream` once; may grow a model-owned buffer. */
+ * computed pairs.  Synchronises `stream` once; may grow a model-owned buffer.
+ *
+ * stomsfem_kl_interp_os_build (offline): the same for the oversampled
+ * Petrov-Galerkin stiffness (Sec. 2.2) in the parameters of the oversampled
+ * patches, the setting of Sec. 5.3: mu, modes of side m + 2 oversample (from
+ * stomsfem_local_kl with that side), 1 <= oversample <= m, m + 2 oversample
+ * <= 32, square mesh.  An element's patch is moved inside the domain at the
+ * edge, so along each axis the element sits at offset 0, oversample or
+ * 2 oversample in it (first, interior, last elements); one table of the 16
+ * entries (row-major [trial][test], as stomsfem_upscale_os) per pair of
+ * offsets, nine in all.  A node's entries are those of an element with that
+ * offset whose patch coefficient is the node's truncated local KL, computed
+ * by the oversampling kernels on 3 x 3-element meshes.  The model is kind 7;
+ * stomsfem_kl_interp_apply then writes S device [nsamples][M][16], xi from
+ * stomsfem_kl_project_patches, and computes the out-of-box pairs by the
+ * oversampling kernels on the sample's own patch.  ENOTSPD if a node's cell
+ * problem fails. */
 int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, const double* mu, const double* modes,
                              int32_t nnodes, double box, stomsfem_model** model, void* stream);
 int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
                              double* S, int32_t* status, int64_t* nfallback, void* stream);
+int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
+                                const double* mu, const double* modes, int32_t nnodes, double box,
+                                stomsfem_model** model, void* stream);
 
 /* ------------------------------------------------------------------------
  * Execution plans.  A stage is one batch of samples taken through the whole
@@ -662,7 +681,8 @@ int stomsfem_model_save(const stomsfem_model* model, const char* path);
 int stomsfem_model_load(const char* path, stomsfem_model** model);
 /* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
  * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation,
- * 6 = interpolation in the local KL parameters;
+ * 6 = interpolation in the local KL parameters; 7 = the same for the oversampled
+ * Petrov-Galerkin stiffness;
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

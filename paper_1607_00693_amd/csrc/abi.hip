@@ -39,6 +39,11 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const 
                              unsigned long long* count, hipStream_t st);
 hipError_t launch_kl_blocks(int64_t npairs, int m, int Kuse, int K, const double* xi, const double* mu,
                             const double* modes, double* blocks, hipStream_t st);
+hipError_t launch_embed_patch(int64_t count, int nc, int m, int o, int cx, int cy, const double* blocks,
+                              const double* kappa, const int64_t* pairs, double* fields, hipStream_t st);
+hipError_t launch_pick_class(int64_t count, int nc, int m, int o, int cx, int cy, const int64_t* pairs,
+                             const double* S9, const int32_t* st9, double* dst, int64_t dst_row0,
+                             int32_t* dst_status, int32_t code, hipStream_t st);
 hipError_t launch_two_level(const double* UH, int64_t nH, const double* UHh, const double* uf, int64_t nh, int nc,
                             int m, double* mean, double* var_H, double* var_d, hipStream_t st);
 bool upscale_os_supports(int m, int o);
@@ -245,6 +250,9 @@ struct stomsfem_model {
   int32_t sg_nb = 0, sg_kmax = 0;
   int32_t sg_lofs[SGI_LEVEL_MAX + 3] = {};
   int32_t sg_rofs[6] = {};
+  // KL interpolation (kind 6; kind 7 = of the oversampled Petrov-Galerkin
+  // stiffness: nine class tables of 16 entries, os_o cells of oversampling)
+  int32_t os_o = 0;
 };
 
 namespace {
@@ -668,10 +676,140 @@ int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, con
   return STOMSFEM_OK;
 }
 
+int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
+                                const double* mu, const double* modes, int32_t nnodes, double box,
+                                stomsfem_model** model, void* stream) {
+  if (!model) return fail(STOMSFEM_EINVAL, "kl_interp_os_build: NULL model");
+  *model = nullptr;
+  const int o = oversample, P = m + 2 * oversample;
+  if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m ||
+      K < 1 || K > RI_KMAX || nnodes < RI_NN_MIN || nnodes > RI_NN_MAX || !(box > 0))
+    return fail(STOMSFEM_EINVAL,
+                "kl_interp_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
+                "domain, "
+                "1 <= K <= 4, 2 <= nnodes <= 9, box > 0");
+  if (!device_ptr(mu) || !device_ptr(modes))
+    return fail(STOMSFEM_EINVAL, "kl_interp_os_build: mu and modes on device");
+  const int Mc = ncx * ncy;
+  int64_t rows = 1;
+  for (int i = 0; i < K; ++i) rows *= nnodes;
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 7;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->os_o = o;
+  md->nn = nnodes;
+  md->lo = -box;
+  md->hi = box;
+  md->rows = rows;
+  // a chunk of 3 x 3 meshes: fields [chunk][3m][3m] of at most 32 MB
+  md->chunk = std::max<int64_t>(64, std::min<int64_t>(16384, (int64_t{1} << 22) / (9 * (int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  double* xin = nullptr;
+  double* nblk = nullptr;
+  int32_t* stn = nullptr;
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->table, sizeof(double) * (size_t)rows * 9 * 16);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * 9 * m * m);
+  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 9 * 16);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk * 9);
+  A((void**)&xin, sizeof(double) * (size_t)rows * K);
+  A((void**)&nblk, sizeof(double) * (size_t)rows * P * P);
+  A((void**)&stn, sizeof(int32_t) * (size_t)rows * 9);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(xin);
+    hipFree(nblk);
+    hipFree(stn);
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "kl_interp_os_build: device allocation failed");
+  }
+  // every element reads the table of its class with its own K parameters
+  auto cls = [&](int k, int nc) {
+    const int nf = nc * m;
+    int x0 = k * m - o;
+    if (x0 > nf - P) x0 = nf - P;
+    if (x0 < 0) x0 = 0;
+    return (k * m - x0) / o;
+  };
+  std::vector<int32_t> lv((size_t)Mc * RI_KMAX, -1), nlv(Mc, K);
+  std::vector<int64_t> off(Mc + 1, 0);
+  for (int p = 0; p < Mc; ++p) {
+    for (int k = 0; k < K; ++k) lv[(size_t)p * RI_KMAX + k] = p * K + k;
+    off[p] = (int64_t)(cls(p / ncx, ncy) * 3 + cls(p % ncx, ncx)) * rows;
+  }
+  off[Mc] = 9 * rows;
+  std::vector<double> xh((size_t)rows * K);
+  for (int64_t r = 0; r < rows; ++r) {
+    int64_t c = r;
+    for (int v = K - 1; v >= 0; --v) {  // variable 0 slowest
+      const int d = (int)(c % nnodes);
+      c /= nnodes;
+      xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)d / (double)(nnodes - 1)) + 1.0) * box;
+    }
+  }
+  e = hipMemcpy(md->lv, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice);
+  // the patch coefficient at every node: the truncated local KL on side P
+  if (e == hipSuccess) e = launch_kl_blocks(rows, P, K, K, xin, mu, modes, nblk, st);
+  for (int c = 0; c < 9 && e == hipSuccess; ++c) {
+    const int cx = c % 3, cy = c / 3;
+    for (int64_t start = 0; start < rows && e == hipSuccess; start += md->chunk) {
+      const int64_t cnt = std::min<int64_t>(md->chunk, rows - start);
+      e = launch_embed_patch(cnt, 3, m, o, cx, cy, nblk + start * P * P, nullptr, nullptr, md->blk, st);
+      if (e == hipSuccess) {
+        UpArgs u{};
+        u.nsamples = cnt;
+        u.ncx = u.ncy = 3;
+        u.m = m;
+        u.npairs = cnt * 9;
+        u.a = md->blk;
+        u.S = md->Sc;
+        u.status = md->stc;
+        e = launch_upscale_os(u, o, STOMSFEM_F64, st);
+      }
+      if (e == hipSuccess)
+        e = launch_pick_class(cnt, 3, m, o, cx, cy, nullptr, md->Sc, md->stc, md->table, c * rows + start,
+                              stn + c * rows + start, 0, st);
+    }
+  }
+  std::vector<int32_t> sth((size_t)rows * 9);
+  if (e == hipSuccess) e = hipMemcpyAsync(sth.data(), stn, sizeof(int32_t) * rows * 9, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(xin);
+  hipFree(nblk);
+  hipFree(stn);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "kl_interp_os_build");
+  }
+  for (int64_t r = 0; r < rows * 9; ++r)
+    if (sth[(size_t)r] != 0) {
+      model_release(md);
+      return fail(STOMSFEM_ENOTSPD, "kl_interp_os_build: a cell problem at a node failed");
+    }
+  md->lv_max = K;
+  *model = md;
+  return STOMSFEM_OK;
+}
+
 int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
                              double* S, int32_t* status, int64_t* nfallback, void* stream) {
   if (nfallback) *nfallback = 0;
-  if (!model || model->kind != 6) return fail(STOMSFEM_EINVAL, "kl_interp_apply: not a KL interpolation model");
+  if (!model || (model->kind != 6 && model->kind != 7))
+    return fail(STOMSFEM_EINVAL, "kl_interp_apply: not a KL interpolation model");
+  const bool os = model->kind == 7;
   if (nsamples < 0) return fail(STOMSFEM_EINVAL, "kl_interp_apply: nsamples < 0");
   if (nsamples == 0) return STOMSFEM_OK;
   if (!device_ptr(xi) || !device_ptr(kappa) || !device_ptr(S) || (status && !device_ptr(status)))
@@ -697,6 +835,7 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
   a.npatch = Mc;
   a.nxi = Mc * K;
   a.nn = model->nn;
+  a.ne = os ? 16 : 10;
   a.nsamples = nsamples;
   a.lo = model->lo;
   a.hi = model->hi;
@@ -717,6 +856,31 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
   if (e != hipSuccess) return hip_fail(e, "kl_interp_apply");
   if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "kl_interp_apply: fallback count out of range");
   if (nfallback) *nfallback = (int64_t)n;
+  if (os) {
+    // out-of-box pairs: the oversampled stiffness of the sample's own patch,
+    // placed in 3 x 3 meshes at the element's class
+    const int m = model->m, o = model->os_o;
+    for (int64_t start = 0; start < (int64_t)n; start += model->chunk) {
+      const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
+      e = launch_embed_patch(cnt, model->ncx, m, o, 0, 0, nullptr, kappa, model->list + start, model->blk, st);
+      if (e == hipSuccess) {
+        UpArgs u{};
+        u.nsamples = cnt;
+        u.ncx = u.ncy = 3;
+        u.m = m;
+        u.npairs = cnt * 9;
+        u.a = model->blk;
+        u.S = model->Sc;
+        u.status = model->stc;
+        e = launch_upscale_os(u, o, STOMSFEM_F64, st);
+      }
+      if (e == hipSuccess)
+        e = launch_pick_class(cnt, model->ncx, m, o, 0, 0, model->list + start, model->Sc, model->stc, S, 0, status,
+                              1, st);
+      if (e != hipSuccess) return hip_fail(e, "kl_interp_apply: oversampled solve launch");
+    }
+    return STOMSFEM_OK;
+  }
   // out-of-box pairs: the plain path on the sample's own coefficient block
   UpArgs full{};
   full.nsamples = nsamples;

@@ -39,14 +39,15 @@ struct RegenArgs {
 // are appended to list (count via *list_count) for the plain solve.
 struct RiApplyArgs {
   int32_t npatch, nxi, nn;
+  int32_t ne;           // entries per table row and per S: 10 (symmetric) or 16 (Petrov-Galerkin); 0 = 10
   int64_t nsamples;
   double lo, hi;
-  const double* table;  // [rows][10]
+  const double* table;  // [rows][ne]
   const int64_t* off;
   const int32_t* lv;
   const int32_t* nlv;
   const double* xi;     // [nsamples][nxi]
-  double* S;            // [nsamples][npatch][10]
+  double* S;            // [nsamples][npatch][ne]
   int32_t* status;      // [nsamples][npatch] or nullptr
   int64_t* list;
   unsigned long long* list_count;
@@ -55,9 +56,9 @@ struct RiApplyArgs {
 hipError_t launch_ri_nodes(const RiNodeArgs& a, hipStream_t st);
 hipError_t launch_regen_blocks(const RegenArgs& a, hipStream_t st);
 hipError_t launch_ri_apply(const RiApplyArgs& a, hipStream_t st);
-// S[pairs[i]] = Sc[i], status[pairs[i]] = (stc[i] != 0 ? stc[i] : code).
+// S[pairs[i]] = Sc[i] (ne entries each), status[pairs[i]] = (stc[i] != 0 ? stc[i] : code).
 hipError_t launch_scatter_pairs(const int64_t* pairs, int64_t count, const double* Sc, const int32_t* stc,
-                                double* S, int32_t* status, int32_t code, hipStream_t st);
+                                double* S, int32_t* status, int32_t code, hipStream_t st, int ne = 10);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st);
 
 }  // namespace stomsfem

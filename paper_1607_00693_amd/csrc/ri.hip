@@ -68,11 +68,12 @@ __global__ __launch_bounds__(256) void regen_blocks_kernel(RegenArgs a) {
 __global__ __launch_bounds__(256) void scatter_pairs_kernel(const int64_t* __restrict__ pairs, int64_t count,
                                                             const double* __restrict__ Sc,
                                                             const int32_t* __restrict__ stc, double* __restrict__ S,
-                                                            int32_t* __restrict__ status, int32_t code) {
+                                                            int32_t* __restrict__ status, int32_t code,
+                                                            int ne) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   const int64_t p = pairs[i];
-  for (int q = 0; q < 10; ++q) S[p * 10 + q] = Sc[i * 10 + q];
+  for (int q = 0; q < ne; ++q) S[p * ne + q] = Sc[i * ne + q];
   if (status) status[p] = stc[i] != 0 ? stc[i] : code;
 }
 
@@ -115,20 +116,20 @@ __device__ __forceinline__ void lobatto_basis(double x, double lo, double hi, do
   for (int d = 0; d < NN; ++d) c[d] *= inv;
 }
 
-// acc += w * sum_{d2, d3} c2[d2] c3[d3] T[(d2 NN + d3) 10 + e]  (two fastest
-// variables; K2 = how many of them are present, 0..2).
-template <int NN, int K2>
+// acc += w * sum_{d2, d3} c2[d2] c3[d3] T[(d2 NN + d3) NE + e]  (two fastest
+// variables; K2 = how many of them are present, 0..2; NE entries per row).
+template <int NN, int K2, int NE>
 __device__ __forceinline__ void inner_sum(const table_t* T, double w, const double (&c2)[NN],
-                                          const double (&c3)[NN], double (&acc)[10]) {
+                                          const double (&c3)[NN], double (&acc)[NE]) {
   if constexpr (K2 == 0) {
 #pragma unroll
-    for (int e = 0; e < 10; ++e) acc[e] = fma(w, T[e], acc[e]);
+    for (int e = 0; e < NE; ++e) acc[e] = fma(w, T[e], acc[e]);
   } else if constexpr (K2 == 1) {
 #pragma unroll
     for (int d = 0; d < NN; ++d) {
       const double wd = w * c3[d];
 #pragma unroll
-      for (int e = 0; e < 10; ++e) acc[e] = fma(wd, T[d * 10 + e], acc[e]);
+      for (int e = 0; e < NE; ++e) acc[e] = fma(wd, T[d * NE + e], acc[e]);
     }
   } else {
 #pragma unroll
@@ -138,41 +139,41 @@ __device__ __forceinline__ void inner_sum(const table_t* T, double w, const doub
       for (int d3 = 0; d3 < NN; ++d3) {
         const double wd = w2 * c3[d3];
 #pragma unroll
-        for (int e = 0; e < 10; ++e) acc[e] = fma(wd, T[(d2 * NN + d3) * 10 + e], acc[e]);
+        for (int e = 0; e < NE; ++e) acc[e] = fma(wd, T[(d2 * NN + d3) * NE + e], acc[e]);
       }
     }
   }
 }
 
 // Sum over the two fastest variables for NN > 5: only the fastest is
-// unrolled (NN x 10 table values per block instead of NN^2 x 10, which
+// unrolled (NN x NE table values per block instead of NN^2 x NE, which
 // would exceed the scalar registers and serialise the scalar loads).
-template <int NN>
+template <int NN, int NE>
 __device__ __forceinline__ void inner_sum_rows(const table_t* T, double w, const double (&c2)[NN],
-                                               const double (&c3)[NN], double (&acc)[10]) {
+                                               const double (&c3)[NN], double (&acc)[NE]) {
   double c2r[NN];
 #pragma unroll
   for (int q = 0; q < NN; ++q) c2r[q] = c2[q];
 #pragma unroll 1
   for (int d2 = 0; d2 < NN; ++d2) {
-    inner_sum<NN, 1>(T + (int64_t)d2 * NN * 10, w * c2r[0], c2, c3, acc);
+    inner_sum<NN, 1, NE>(T + (int64_t)d2 * NN * NE, w * c2r[0], c2, c3, acc);
     shift_down<NN>(c2r);
   }
 }
 
 // two fastest variables: unrolled (NN <= 5) or a loop over the second
-template <int NN>
+template <int NN, int NE>
 __device__ __forceinline__ void inner_sum2(const table_t* T, double w, const double (&c2)[NN],
-                                           const double (&c3)[NN], double (&acc)[10]) {
+                                           const double (&c3)[NN], double (&acc)[NE]) {
   if constexpr (NN > 5)  // measured: at five nodes the full unroll is 4% faster
-    inner_sum_rows<NN>(T, w, c2, c3, acc);
+    inner_sum_rows<NN, NE>(T, w, c2, c3, acc);
   else
-    inner_sum<NN, 2>(T, w, c2, c3, acc);
+    inner_sum<NN, 2, NE>(T, w, c2, c3, acc);
 }
 
-template <int NN, int KV>
+template <int NN, int KV, int NE>
 __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_KMAX], double lo,
-                                        double hi, double (&acc)[10]) {
+                                        double hi, double (&acc)[NE]) {
   double c0[NN], c1[NN], c2[NN], c3[NN];
   // variables are consumed from the fastest: the last one pairs with c3
   if constexpr (KV >= 1) lobatto_basis<NN>(x[KV - 1], lo, hi, c3);
@@ -182,13 +183,13 @@ __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_K
   constexpr int K2 = KV < 2 ? KV : 2;
   constexpr int inner = K2 == 0 ? 1 : (K2 == 1 ? NN : NN * NN);
   if constexpr (KV == 2) {
-    inner_sum2<NN>(T, 1.0, c2, c3, acc);
+    inner_sum2<NN, NE>(T, 1.0, c2, c3, acc);
   } else if constexpr (KV < 2) {
-    inner_sum<NN, K2>(T, 1.0, c2, c3, acc);
+    inner_sum<NN, K2, NE>(T, 1.0, c2, c3, acc);
   } else if constexpr (KV == 3) {
 #pragma unroll 1
     for (int d1 = 0; d1 < NN; ++d1) {
-      inner_sum2<NN>(T + (int64_t)d1 * inner * 10, c1[0], c2, c3, acc);
+      inner_sum2<NN, NE>(T + (int64_t)d1 * inner * NE, c1[0], c2, c3, acc);
       shift_down<NN>(c1);
     }
   } else {
@@ -199,7 +200,7 @@ __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_K
       for (int q = 0; q < NN; ++q) c1r[q] = c1[q];
 #pragma unroll 1
       for (int d1 = 0; d1 < NN; ++d1) {
-        inner_sum2<NN>(T + (int64_t)(d0 * NN + d1) * inner * 10, c0[0] * c1r[0], c2, c3, acc);
+        inner_sum2<NN, NE>(T + (int64_t)(d0 * NN + d1) * inner * NE, c0[0] * c1r[0], c2, c3, acc);
         shift_down<NN>(c1r);
       }
       shift_down<NN>(c0);
@@ -210,7 +211,7 @@ __device__ __forceinline__ void ri_eval(const table_t* T, const double (&x)[RI_K
 // Grid: ceil(nsamples / 256) x npatch workgroups in one dimension, remapped
 // so that all workgroups of one patch run on the same XCD (workgroups are
 // dealt to the 8 XCDs round-robin), which keeps each table in one L2.
-template <int NN>
+template <int NN, int NE>
 __global__ __launch_bounds__(256) void ri_apply_kernel(RiApplyArgs a, int64_t nblk_s, int64_t nwork) {
   const int64_t b = blockIdx.x;
   const int64_t per_xcd = (int64_t)gridDim.x / 8;
@@ -234,20 +235,20 @@ __global__ __launch_bounds__(256) void ri_apply_kernel(RiApplyArgs a, int64_t nb
     a.list[slot] = p;
     return;  // S and status are written by the plain solve
   }
-  const table_t* T = (const table_t*)(a.table + a.off[K] * 10);
-  double acc[10];
+  const table_t* T = (const table_t*)(a.table + a.off[K] * NE);
+  double acc[NE];
 #pragma unroll
-  for (int e = 0; e < 10; ++e) acc[e] = 0.0;
+  for (int e = 0; e < NE; ++e) acc[e] = 0.0;
   switch (k) {
-    case 0: ri_eval<NN, 0>(T, x, a.lo, a.hi, acc); break;
-    case 1: ri_eval<NN, 1>(T, x, a.lo, a.hi, acc); break;
-    case 2: ri_eval<NN, 2>(T, x, a.lo, a.hi, acc); break;
-    case 3: ri_eval<NN, 3>(T, x, a.lo, a.hi, acc); break;
-    default: ri_eval<NN, 4>(T, x, a.lo, a.hi, acc); break;
+    case 0: ri_eval<NN, 0, NE>(T, x, a.lo, a.hi, acc); break;
+    case 1: ri_eval<NN, 1, NE>(T, x, a.lo, a.hi, acc); break;
+    case 2: ri_eval<NN, 2, NE>(T, x, a.lo, a.hi, acc); break;
+    case 3: ri_eval<NN, 3, NE>(T, x, a.lo, a.hi, acc); break;
+    default: ri_eval<NN, 4, NE>(T, x, a.lo, a.hi, acc); break;
   }
-  double* So = a.S + p * 10;
+  double* So = a.S + p * NE;
 #pragma unroll
-  for (int e = 0; e < 10; ++e) So[e] = acc[e];
+  for (int e = 0; e < NE; ++e) So[e] = acc[e];
   if (a.status) a.status[p] = 0;
 }
 
@@ -265,10 +266,10 @@ hipError_t launch_regen_blocks(const RegenArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_scatter_pairs(const int64_t* pairs, int64_t count, const double* Sc, const int32_t* stc, double* S,
-                                int32_t* status, int32_t code, hipStream_t st) {
+                                int32_t* status, int32_t code, hipStream_t st, int ne) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(scatter_pairs_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, pairs, count, Sc,
-                     stc, S, status, code);
+                     stc, S, status, code, ne);
   return hipGetLastError();
 }
 
@@ -282,7 +283,12 @@ static hipError_t launch_apply_nn(const RiApplyArgs& a, hipStream_t st) {
   const int64_t nblk_s = (a.nsamples + 255) / 256;
   const int64_t nwork = nblk_s * a.npatch;
   const int64_t grid = (nwork + 7) / 8 * 8;
-  hipLaunchKernelGGL(ri_apply_kernel<NN>, dim3((unsigned)grid), dim3(256), 0, st, a, nblk_s, nwork);
+  if (a.ne == 16)
+    hipLaunchKernelGGL((ri_apply_kernel<NN, 16>), dim3((unsigned)grid), dim3(256), 0, st, a, nblk_s, nwork);
+  else if (a.ne == 0 || a.ne == 10)
+    hipLaunchKernelGGL((ri_apply_kernel<NN, 10>), dim3((unsigned)grid), dim3(256), 0, st, a, nblk_s, nwork);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -134,6 +134,7 @@ def lib():
         "stomsfem_kl_project_patches": (C.c_int, [i64, i32, i32, i32, vp, i32, vp, vp, dbl, vp, vp, vp, vp]),
         "stomsfem_kl_blocks": (C.c_int, [i64, i32, i32, i32, vp, vp, vp, vp, vp]),
         "stomsfem_kl_interp_build": (C.c_int, [i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
+        "stomsfem_kl_interp_os_build": (C.c_int, [i32, i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_kl_interp_apply": (C.c_int, [vp, vp, vp, i64, vp, vp, C.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
@@ -297,20 +298,31 @@ def kl_blocks(xi: torch.Tensor, mu: torch.Tensor, modes: torch.Tensor, Kuse: int
 
 
 def kl_interp_build(ncx: int, ncy: int, m: int, mu: torch.Tensor, modes: torch.Tensor, nnodes: int,
-                    box: float = 3.0, stream=None) -> Model:
-    """Offline: S at the tensor Lobatto nodes of the local KL parameters (one table for all elements)."""
+                    box: float = 3.0, stream=None, oversample: int = 0) -> Model:
+    """Offline: S at the tensor Lobatto nodes of the local KL parameters (one
+    table for all elements); oversample > 0: the oversampled Petrov-Galerkin
+    stiffness (16 entries) in the parameters of the oversampled patches (modes
+    of side m + 2 oversample), one table per element class."""
     h = C.c_void_p()
-    _check("stomsfem_kl_interp_build", lib().stomsfem_kl_interp_build(
-        ncx, ncy, m, mu.shape[0], _ptr(mu), _ptr(modes), nnodes, box, C.byref(h), _stream(stream)))
-    return Model(h, ncx, ncy, m)
+    if oversample == 0:
+        _check("stomsfem_kl_interp_build", lib().stomsfem_kl_interp_build(
+            ncx, ncy, m, mu.shape[0], _ptr(mu), _ptr(modes), nnodes, box, C.byref(h), _stream(stream)))
+    else:
+        _check("stomsfem_kl_interp_os_build", lib().stomsfem_kl_interp_os_build(
+            ncx, ncy, m, oversample, mu.shape[0], _ptr(mu), _ptr(modes), nnodes, box, C.byref(h), _stream(stream)))
+    md = Model(h, ncx, ncy, m)
+    md.entries = 16 if oversample else 10
+    return md
 
 
 def kl_interp_apply(model: Model, xi: torch.Tensor, kappa: torch.Tensor, S: torch.Tensor | None = None,
                     status: torch.Tensor | None = None, stream=None):
-    """Online: (S [N][M][10], number of pairs solved plainly from kappa)."""
+    """Online: (S [N][M][10] (16 for an oversampled model), number of pairs
+    computed from kappa)."""
     N = xi.shape[0]
     if S is None:
-        S = torch.empty((N, model.ncx * model.ncy, 10), dtype=torch.float64, device=xi.device)
+        S = torch.empty((N, model.ncx * model.ncy, getattr(model, "entries", 10)), dtype=torch.float64,
+                        device=xi.device)
     nfb = C.c_int64(0)
     _check("stomsfem_kl_interp_apply", lib().stomsfem_kl_interp_apply(
         model.handle, _ptr(xi), _ptr(kappa), N, _ptr(S), _ptr(status), C.byref(nfb), _stream(stream)))

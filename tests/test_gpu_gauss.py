@@ -218,3 +218,53 @@ def test_interpolation_on_the_local_parameters_matches_oracle(sm, nn, box):
     err = (np.abs(S - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
     say(f"  {int(fb.sum())} plain pairs, S rel err {err:.2e}")
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("K,nn,box", [(3, 3, 3.0), (4, 4, 1.0)])
+def test_oversampled_interpolation_matches_oracle(sm, K, nn, box):
+    # interpolation of the oversampled Petrov-Galerkin stiffness in the patch
+    # parameters: nine class tables (4 x 4 mesh, patches of 16 cells around
+    # elements of 8), each side with its own modes; the narrow box sends many
+    # pairs to the oversampled solve of the sample's own patch
+    nc, m, o, N = 4, 8, 4, 3
+    P, nf = m + 2 * o, nc * m
+    l1, l2 = 1.0, 1.0 / 8
+    say(f"oversampled KL interpolation K={K} nn={nn} box={box}")
+    z, u = W.spectral_draws(N, 64, 2180 + nn)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, l1, l2, with_beta=True)
+    mu, V, _ = sm.local_kl(P, 1.0 / nf, l1, l2, K)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    xi, _, count = sm.kl_project(beta, nc, m, mu_d, V_d, box, oversample=o)
+    model = sm.kl_interp_build(nc, nc, m, mu_d, V_d, nn, box, oversample=o)
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S, nfb = sm.kl_interp_apply(model, xi, kap, status=st)
+    torch.cuda.synchronize()
+    assert S.shape == (N, nc * nc, 16)
+    b_ref = gauss.field(z, u, nf, l1, l2)
+    mu_r, V_r, _ = gauss.local_kl(P, 1.0 / nf, l1, l2, K)
+    xi_r = gauss.project_patches(b_ref, nc, m, o, mu_r, V_r)
+    orc = gauss.kl_interp_os_offline(m, o, mu_r, V_r, nn, box)
+    S_ref, fb = gauss.kl_interp_os_online(orc, xi_r, gauss.kappa(b_ref), nc)
+    st = st.cpu().numpy()
+    assert nfb == int(fb.sum()) == int(count.item())
+    assert (st[fb] == 1).all() and (st[~fb] == 0).all()
+    if box < 3:
+        assert fb.any() and (~fb).any()
+    S = S.cpu().numpy()
+    err = (np.abs(S - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
+    say(f"  {int(fb.sum())} oversampled solves, S rel err {err:.2e}")
+    assert err < 1e-10
+    # the fallback pairs agree with the oversampling kernels on the whole field
+    S_os = sm.upscale_os(kap, nc, nc, m, o).cpu().numpy()
+    np.testing.assert_allclose(S[fb], S_os[fb], rtol=0, atol=1e-10 * np.abs(S_os).max())
+
+
+def test_oversampled_interpolation_rejects_bad_shapes(sm):
+    mu = torch.ones(2, dtype=torch.float64, device="cuda")
+    V = torch.zeros((2, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError):  # oversampling wider than the element
+        sm.kl_interp_build(4, 4, 4, mu, V, 3, 3.0, oversample=6)
+    with pytest.raises(sm.StomsfemError):  # not square
+        sm.kl_interp_build(4, 3, 8, mu, V, 3, 3.0, oversample=4)
+    with pytest.raises(sm.StomsfemError):  # patch wider than the domain
+        sm.kl_interp_build(1, 1, 8, mu, V, 3, 3.0, oversample=4)
