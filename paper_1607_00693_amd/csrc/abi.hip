@@ -30,7 +30,9 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
                          double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
                             double* mean, double* var, int32_t* status, double* work, hipStream_t st);
-hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+// list != nullptr: only the batch's pairs list[i] (i < nlist), S and status compact at i
+hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st, const int64_t* list = nullptr,
+                             int64_t nlist = 0);
 hipError_t launch_gauss_field(int64_t nsamples, int nfine, int J, const double* z, const double* u, double l1,
                               double l2, double* beta, double* kappa, hipStream_t st);
 void local_kl_modes(int m, double h, double l1, double l2, int K, double* mu, double* modes, double* captured);
@@ -39,11 +41,10 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const 
                              unsigned long long* count, hipStream_t st);
 hipError_t launch_kl_blocks(int64_t npairs, int m, int Kuse, int K, const double* xi, const double* mu,
                             const double* modes, double* blocks, hipStream_t st);
-hipError_t launch_embed_patch(int64_t count, int nc, int m, int o, int cx, int cy, const double* blocks,
-                              const double* kappa, const int64_t* pairs, double* fields, hipStream_t st);
-hipError_t launch_pick_class(int64_t count, int nc, int m, int o, int cx, int cy, const int64_t* pairs,
-                             const double* S9, const int32_t* st9, double* dst, int64_t dst_row0,
-                             int32_t* dst_status, int32_t code, hipStream_t st);
+hipError_t launch_embed_patch(int64_t count, int m, int o, int cx, int cy, const double* blocks, double* fields,
+                              hipStream_t st);
+hipError_t launch_pick_class(int64_t count, int cx, int cy, const double* S9, const int32_t* st9, double* dst,
+                             int32_t* dst_status, hipStream_t st);
 hipError_t launch_two_level(const double* UH, int64_t nH, const double* UHh, const double* uf, int64_t nh, int nc,
                             int m, double* mean, double* var_H, double* var_d, hipStream_t st);
 bool upscale_os_supports(int m, int o);
@@ -767,7 +768,7 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
     const int cx = c % 3, cy = c / 3;
     for (int64_t start = 0; start < rows && e == hipSuccess; start += md->chunk) {
       const int64_t cnt = std::min<int64_t>(md->chunk, rows - start);
-      e = launch_embed_patch(cnt, 3, m, o, cx, cy, nblk + start * P * P, nullptr, nullptr, md->blk, st);
+      e = launch_embed_patch(cnt, m, o, cx, cy, nblk + start * P * P, md->blk, st);
       if (e == hipSuccess) {
         UpArgs u{};
         u.nsamples = cnt;
@@ -780,8 +781,8 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
         e = launch_upscale_os(u, o, STOMSFEM_F64, st);
       }
       if (e == hipSuccess)
-        e = launch_pick_class(cnt, 3, m, o, cx, cy, nullptr, md->Sc, md->stc, md->table, c * rows + start,
-                              stn + c * rows + start, 0, st);
+        e = launch_pick_class(cnt, cx, cy, md->Sc, md->stc, md->table + (c * rows + start) * 16,
+                              stn + c * rows + start, st);
     }
   }
   std::vector<int32_t> sth((size_t)rows * 9);
@@ -857,26 +858,22 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
   if (n > (unsigned long long)need) return fail(STOMSFEM_EHIP, "kl_interp_apply: fallback count out of range");
   if (nfallback) *nfallback = (int64_t)n;
   if (os) {
-    // out-of-box pairs: the oversampled stiffness of the sample's own patch,
-    // placed in 3 x 3 meshes at the element's class
-    const int m = model->m, o = model->os_o;
+    // out-of-box pairs: the oversampling kernels on the sample's own field,
+    // for the listed pairs only
+    UpArgs full{};
+    full.nsamples = nsamples;
+    full.ncx = model->ncx;
+    full.ncy = model->ncy;
+    full.m = model->m;
+    full.npairs = nsamples * Mc;
+    full.a = kappa;
+    full.S = model->Sc;
+    full.status = model->stc;
     for (int64_t start = 0; start < (int64_t)n; start += model->chunk) {
       const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
-      e = launch_embed_patch(cnt, model->ncx, m, o, 0, 0, nullptr, kappa, model->list + start, model->blk, st);
-      if (e == hipSuccess) {
-        UpArgs u{};
-        u.nsamples = cnt;
-        u.ncx = u.ncy = 3;
-        u.m = m;
-        u.npairs = cnt * 9;
-        u.a = model->blk;
-        u.S = model->Sc;
-        u.status = model->stc;
-        e = launch_upscale_os(u, o, STOMSFEM_F64, st);
-      }
+      e = launch_upscale_os(full, model->os_o, STOMSFEM_F64, st, model->list + start, cnt);
       if (e == hipSuccess)
-        e = launch_pick_class(cnt, model->ncx, m, o, 0, 0, model->list + start, model->Sc, model->stc, S, 0, status,
-                              1, st);
+        e = launch_scatter_pairs(model->list + start, cnt, model->Sc, model->stc, S, status, 1, st, 16);
       if (e != hipSuccess) return hip_fail(e, "kl_interp_apply: oversampled solve launch");
     }
     return STOMSFEM_OK;

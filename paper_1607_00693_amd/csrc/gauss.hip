@@ -391,16 +391,9 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const 
 // element's patch origin (the rest of the mesh 1, never read by the cell
 // problems) gives the element's stiffness through the ordinary oversampling
 // kernels.  embed_patch_kernel: item i of fields [count][3m][3m] takes
-// blocks[i] ([P][P]) at class (cx, cy) when pairs is null, else the patch of
-// pair pairs[i] = s M + K cut from kappa [nsamples][nc m][nc m] at K's class.
-__device__ __forceinline__ int os_class(int k, int m, int o, int nf) {
-  return (k * m - kl_patch_origin(k, m, o, nf)) / o;
-}
-
-__global__ __launch_bounds__(256) void embed_patch_kernel(int64_t count, int nc, int m, int o, int cx, int cy,
+// blocks[i] ([P][P]) at class (cx, cy).
+__global__ __launch_bounds__(256) void embed_patch_kernel(int64_t count, int m, int o, int cx, int cy,
                                                           const double* __restrict__ blocks,
-                                                          const double* __restrict__ kappa,
-                                                          const int64_t* __restrict__ pairs,
                                                           double* __restrict__ fields) {
   const int P = m + 2 * o, n3 = 3 * m;
   const int64_t per = (int64_t)n3 * n3;
@@ -408,77 +401,41 @@ __global__ __launch_bounds__(256) void embed_patch_kernel(int64_t count, int nc,
   if (t >= count * per) return;
   const int64_t i = t / per;
   const int e = (int)(t - i * per), y = e / n3, x = e - (e / n3) * n3;
-  int ccx = cx, ccy = cy;
-  const double* src;
-  int64_t ld;
-  if (pairs) {
-    const int nf = nc * m;
-    const int64_t M = (int64_t)nc * nc, pp = pairs[i], s = pp / M;
-    const int K = (int)(pp - s * M), kx = K % nc, ky = K / nc;
-    const int X0 = kl_patch_origin(kx, m, o, nf), Y0 = kl_patch_origin(ky, m, o, nf);
-    ccx = (kx * m - X0) / o;
-    ccy = (ky * m - Y0) / o;
-    src = kappa + s * (int64_t)nf * nf + (int64_t)Y0 * nf + X0;
-    ld = nf;
-  } else {
-    src = blocks + i * (int64_t)P * P;
-    ld = P;
-  }
-  const int x0 = kl_patch_origin(ccx, m, o, n3), y0 = kl_patch_origin(ccy, m, o, n3);
+  const int x0 = kl_patch_origin(cx, m, o, n3), y0 = kl_patch_origin(cy, m, o, n3);
   const bool in = x >= x0 && x < x0 + P && y >= y0 && y < y0 + P;
-  fields[t] = in ? src[(int64_t)(y - y0) * ld + (x - x0)] : 1.0;
+  fields[t] = in ? blocks[i * (int64_t)P * P + (int64_t)(y - y0) * P + (x - x0)] : 1.0;
 }
 
 // The class element's 16 entries of each 3 x 3 mesh (S9 [count][9][16],
-// st9 [count][9]): into dst row pairs[i] (class from the pair) or dst_row0 + i
-// (class (cx, cy)); the status (nonzero kept, else code) into dst_status at
-// pairs[i] or i.
-__global__ __launch_bounds__(256) void pick_class_kernel(int64_t count, int nc, int m, int o, int cx, int cy,
-                                                         const int64_t* __restrict__ pairs,
-                                                         const double* __restrict__ S9,
+// st9 [count][9]) into dst [count][16] and its status into dst_status [count].
+__global__ __launch_bounds__(256) void pick_class_kernel(int64_t count, int cx, int cy, const double* __restrict__ S9,
                                                          const int32_t* __restrict__ st9, double* __restrict__ dst,
-                                                         int64_t dst_row0, int32_t* __restrict__ dst_status,
-                                                         int32_t code) {
+                                                         int32_t* __restrict__ dst_status) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
-  int ccx = cx, ccy = cy;
-  int64_t d = dst_row0 + i, ds = i;
-  if (pairs) {
-    const int nf = nc * m;
-    const int64_t M = (int64_t)nc * nc, pp = pairs[i], s = pp / M;
-    const int K = (int)(pp - s * M);
-    ccx = os_class(K % nc, m, o, nf);
-    ccy = os_class(K / nc, m, o, nf);
-    d = ds = pp;
-  }
-  const int e = ccy * 3 + ccx;
+  const int e = cy * 3 + cx;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) dst[d * 16 + q] = S9[(i * 9 + e) * 16 + q];
-  if (dst_status) {
-    const int32_t sv = st9[i * 9 + e];
-    dst_status[ds] = sv != 0 ? sv : code;
-  }
+  for (int q = 0; q < 16; ++q) dst[i * 16 + q] = S9[(i * 9 + e) * 16 + q];
+  dst_status[i] = st9[i * 9 + e];
 }
 
-hipError_t launch_embed_patch(int64_t count, int nc, int m, int o, int cx, int cy, const double* blocks,
-                              const double* kappa, const int64_t* pairs, double* fields, hipStream_t st) {
+hipError_t launch_embed_patch(int64_t count, int m, int o, int cx, int cy, const double* blocks, double* fields,
+                              hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  if (o < 1 || o > m || (!pairs && (cx < 0 || cx > 2 || cy < 0 || cy > 2))) return hipErrorInvalidValue;
+  if (o < 1 || o > m || cx < 0 || cx > 2 || cy < 0 || cy > 2) return hipErrorInvalidValue;
   const int64_t n = count * 9 * (int64_t)m * m;
   const int64_t nb = (n + 255) / 256;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(embed_patch_kernel, dim3((unsigned)nb), dim3(256), 0, st, count, nc, m, o, cx, cy, blocks, kappa,
-                     pairs, fields);
+  hipLaunchKernelGGL(embed_patch_kernel, dim3((unsigned)nb), dim3(256), 0, st, count, m, o, cx, cy, blocks, fields);
   return hipGetLastError();
 }
 
-hipError_t launch_pick_class(int64_t count, int nc, int m, int o, int cx, int cy, const int64_t* pairs,
-                             const double* S9, const int32_t* st9, double* dst, int64_t dst_row0,
-                             int32_t* dst_status, int32_t code, hipStream_t st) {
+hipError_t launch_pick_class(int64_t count, int cx, int cy, const double* S9, const int32_t* st9, double* dst,
+                             int32_t* dst_status, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  if (o < 1 || o > m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pick_class_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, nc, m, o, cx,
-                     cy, pairs, S9, st9, dst, dst_row0, dst_status, code);
+  if (cx < 0 || cx > 2 || cy < 0 || cy > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pick_class_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, cx, cy, S9,
+                     st9, dst, dst_status);
   return hipGetLastError();
 }
 

@@ -37,6 +37,9 @@ constexpr int OS_EP = 32;    // epilogue scratch per wavefront (doubles)
 struct OsArgs {
   UpArgs up;  // up.m = m; up.S = S16 output [npairs][16]
   int32_t o;  // fine cells added on each side of K
+  // optional: solve only the pairs list[i], i < nlist, into S[i], status[i]
+  const int64_t* list;
+  int64_t nlist;
 };
 
 // first fine cell (one axis) of the patch of coarse element k
@@ -95,8 +98,9 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   double* Ep = R + WN * OS_NV;                      // epilogue scratch
   double* Rk = Ep + OS_EP;                          // r^l at K's nodes [3][(m+1)^2]
   double* Fb = Rk + 3 * (m + 1) * (m + 1);          // lifts f^v of the rows next to the boundary [M*M][3]
-  const int64_t p = (int64_t)blockIdx.x * waves + wave;
-  if (p >= args.up.npairs) return;  // the whole wavefront; no workgroup barrier follows
+  const int64_t io = (int64_t)blockIdx.x * waves + wave;  // output slot
+  if (io >= (args.list ? args.nlist : args.up.npairs)) return;  // the whole wavefront; no workgroup barrier follows
+  const int64_t p = args.list ? args.list[io] : io;
   const int ncx = args.up.ncx, ncy = args.up.ncy, Mc = ncx * ncy;
   const int64_t s = p / Mc;
   const int K = (int)(p - s * Mc), kx = K % ncx, ky = K / ncx;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
         for (int cc = 0; cc < 8; ++cc) G[i][cc] -= f * G[c][cc];
       }
     }
-    double* out = args.up.S + p * 16;
+    double* out = args.up.S + io * 16;
 #pragma unroll
     for (int l = 0; l < 4; ++l)
 #pragma unroll
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
         for (int jb = 0; jb < 4; ++jb) v += G[l][4 + jb] * A[jb][lp];
         out[4 * l + lp] = v;
       }
-    if (args.up.status) args.up.status[p] = (bad || sing) ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+    if (args.up.status) args.up.status[io] = (bad || sing) ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
   }
 }
 
@@ -372,7 +376,7 @@ template <typename TA>
 static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
   const int M = args.up.m + 2 * args.o;
   const int waves = upscale_os_waves(args.up.m, args.o);
-  const int64_t blocks = (args.up.npairs + waves - 1) / waves;
+  const int64_t blocks = ((args.list ? args.nlist : args.up.npairs) + waves - 1) / waves;
   const size_t lds = upscale_os_lds_bytes(args.up.m, args.o, waves);
   const int need = (M * (M + 1) / 2 + 63) / 64;
   const dim3 grid((unsigned)blocks), block(64 * waves);
@@ -386,14 +390,18 @@ static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
 }
 
 bool upscale_os_tiled_supports(int m, int o);
-hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st);
+hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st, const int64_t* list,
+                                   int64_t nlist);
 
-hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st) {
+// list != nullptr: only the pairs list[i] (i < nlist) of the batch, their
+// S and status written compactly at i.
+hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st, const int64_t* list,
+                             int64_t nlist) {
   if (!upscale_os_supports(up.m, o)) return hipErrorInvalidValue;
-  if (up.npairs == 0) return hipSuccess;
-  // 16-cell patches: the register-tiled kernel (six pairs per wavefront)
-  if (upscale_os_tiled_supports(up.m, o)) return launch_upscale_os_tiled(up, o, a_dtype, st);
-  const OsArgs args{up, o};
+  if ((list ? nlist : up.npairs) <= 0) return hipSuccess;
+  // 16- and 24-cell patches: the register-tiled kernel (six pairs per wavefront)
+  if (upscale_os_tiled_supports(up.m, o)) return launch_upscale_os_tiled(up, o, a_dtype, st, list, nlist);
+  const OsArgs args{up, o, list, nlist};
   return a_dtype == STOMSFEM_F32 ? launch_os_t<float>(args, st) : launch_os_t<double>(args, st);
 }
 

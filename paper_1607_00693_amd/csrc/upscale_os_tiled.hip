@@ -39,6 +39,9 @@ constexpr int OT_RED = 9 + 1;            // reduced over the lanes: boundary ter
 struct OtArgs {
   UpArgs up;
   int32_t o;
+  // optional: solve only the pairs list[i], i < nlist, into S[i], status[i]
+  const int64_t* list;
+  int64_t nlist;
 };
 
 template <int T>
@@ -121,9 +124,11 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
   const int P = g >= 6 ? 3 : g >= 3 ? 2 : g >= 1 ? 1 : 0;
   const int Q = g - P * (P + 1) / 2;
 
-  int64_t p = (int64_t)blockIdx.x * OT_SLOTS + q;
-  const bool valid = p < args.up.npairs;
-  if (!valid) p = args.up.npairs - 1;
+  const int64_t nout = args.list ? args.nlist : args.up.npairs;
+  int64_t io = (int64_t)blockIdx.x * OT_SLOTS + q;  // output slot
+  const bool valid = io < nout;
+  if (!valid) io = nout - 1;
+  const int64_t p = args.list ? args.list[io] : io;
   const int m = args.up.m, o = args.o;
   const int ncx = args.up.ncx, ncy = args.up.ncy, Mc = ncx * ncy;
   const int64_t s = p / Mc;
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
         for (int cc = 0; cc < 8; ++cc) G[i][cc] -= f * G[c][cc];
       }
     }
-    double* out = args.up.S + p * 16;
+    double* out = args.up.S + io * 16;
 #pragma unroll
     for (int l = 0; l < 4; ++l)
 #pragma unroll
@@ -540,7 +545,7 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
         for (int jb = 0; jb < 4; ++jb) v += G[l][4 + jb] * A[jb][lp];
         out[4 * l + lp] = v;
       }
-    if (args.up.status) args.up.status[p] = (anybad || sing) ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+    if (args.up.status) args.up.status[io] = (anybad || sing) ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
   }
 }
 
@@ -548,17 +553,18 @@ bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16 || m + 2 *
 
 template <int M, int T>
 static void launch_ot(const OtArgs& args, int a_dtype, hipStream_t st) {
-  const int64_t blocks = (args.up.npairs + OT_SLOTS - 1) / OT_SLOTS;
+  const int64_t blocks = ((args.list ? args.nlist : args.up.npairs) + OT_SLOTS - 1) / OT_SLOTS;
   if (a_dtype == STOMSFEM_F32)
     hipLaunchKernelGGL((upscale_os_tiled_kernel<M, T, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
   else
     hipLaunchKernelGGL((upscale_os_tiled_kernel<M, T, double>), dim3((unsigned)blocks), dim3(64), 0, st, args);
 }
 
-hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st) {
+hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStream_t st, const int64_t* list,
+                                   int64_t nlist) {
   if (!upscale_os_tiled_supports(up.m, o)) return hipErrorInvalidValue;
-  if (up.npairs == 0) return hipSuccess;
-  const OtArgs args{up, o};
+  if ((list ? nlist : up.npairs) <= 0) return hipSuccess;
+  const OtArgs args{up, o, list, nlist};
   if (up.m + 2 * o == 16)
     launch_ot<16, 4>(args, a_dtype, st);
   else
