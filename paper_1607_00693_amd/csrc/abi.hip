@@ -869,8 +869,12 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
     full.a = kappa;
     full.S = model->Sc;
     full.status = model->stc;
-    for (int64_t start = 0; start < (int64_t)n; start += model->chunk) {
-      const int64_t cnt = std::min<int64_t>(model->chunk, (int64_t)n - start);
+    // Sc, stc hold chunk 3 x 3 meshes of the build: 9 chunk pairs here (one
+    // launch for all of them is what matters: each pair is a long dependent
+    // elimination, so launches in sequence add their latencies)
+    const int64_t fchunk = 9 * model->chunk;
+    for (int64_t start = 0; start < (int64_t)n; start += fchunk) {
+      const int64_t cnt = std::min<int64_t>(fchunk, (int64_t)n - start);
       e = launch_upscale_os(full, model->os_o, STOMSFEM_F64, st, model->list + start, cnt);
       if (e == hipSuccess)
         e = launch_scatter_pairs(model->list + start, cnt, model->Sc, model->stc, S, status, 1, st, 16);
