@@ -218,12 +218,32 @@ def kl_interp_os_offline(m: int, o: int, mu: np.ndarray, V: np.ndarray, nn: int,
     return dict(tables=tables, nodes=nodes, box=box, K=K, m=m, o=o)
 
 
+def kl_sgi_os_offline(m: int, o: int, mu: np.ndarray, V: np.ndarray, level: int, box: float = 3.0) -> dict:
+    """The same tables at the nodes of the level-`level` Smolyak sparse grid
+    (nested Clenshaw-Curtis) in the K patch parameters on [-box, box]^K: the
+    node set of the Chebyshev-Lobatto sparse-grid interpolation of Sec. 5.3."""
+    from . import sc
+
+    if not 1 <= o <= m:
+        raise ValueError("need 1 <= o <= m")
+    K = len(mu)
+    dg, _ = sc.sparse_grid(K, level)
+    xs = np.stack([sc.node_values(dg[:, i], level, -box, box) for i in range(K)], axis=1)
+    blocks = truncated_kappa_blocks(xs[None], mu, V, K)[0]
+    tables = {}
+    for cy in range(3):
+        for cx in range(3):
+            S = os_S_embedded(blocks, m, o, cx, cy)
+            tables[(cx, cy)] = {tuple(int(v) for v in row): S[r] for r, row in enumerate(dg)}
+    return dict(tables=tables, level=level, box=box, K=K, m=m, o=o, sparse=True)
+
+
 def kl_interp_os_online(model: dict, xi: np.ndarray, kap: np.ndarray, nc: int):
     """(S16 [N][nc*nc][16], fallback mask [N][nc*nc]) from the patch
     parameters xi [N][nc*nc][K]: inside the box the interpolant of the
-    element's class table, outside it the oversampled stiffness of the
+    element's class table (tensor Lagrange, or Smolyak for a sparse-grid model), outside it the oversampled stiffness of the
     sample's own coefficient kap [N][nc m][nc m]."""
-    from . import core, ri
+    from . import core, ri, sc
 
     m, o, box = model["m"], model["o"], model["box"]
     N, M, K = xi.shape
@@ -234,7 +254,10 @@ def kl_interp_os_online(model: dict, xi: np.ndarray, kap: np.ndarray, nc: int):
         cls = (element_class(kx, m, o, nc), element_class(ky, m, o, nc))
         inside = ~fb[:, p]
         if np.any(inside):
-            S[inside, p] = ri.ri_eval(model["tables"][cls], model["nodes"], xi[inside, p])
+            if model.get("sparse"):
+                S[inside, p] = sc.smolyak_interp(model["tables"][cls], K, model["level"], xi[inside, p] / box)
+            else:
+                S[inside, p] = ri.ri_eval(model["tables"][cls], model["nodes"], xi[inside, p])
         for s in np.nonzero(~inside)[0]:
             S[s, p] = core.cell_S_os(kap[s], m, o, kx, ky).ravel()
     return S, fb

@@ -221,3 +221,45 @@ def test_oversampled_interpolation_in_the_patch_parameters():
     assert fb2.all()
     S_ref, _ = core.upscale_os(a2, nc, nc, m, o)
     np.testing.assert_allclose(S2, S_ref, rtol=0, atol=1e-12 * np.abs(S_ref).max())
+
+
+def test_oversampled_sparse_grid_interpolation():
+    # the Smolyak interpolant on the sparse grid of the patch parameters:
+    # nodal exactness against the oversampled stiffness of the truncated
+    # coefficient, and convergence from level 2 to level 4 (29 -> 137 ->
+    # ... nodes in 3 variables) at random points, for an interior and a
+    # corner class
+    from oracle import ri, sc
+    nc, m, o, K = 4, 8, 4, 3
+    P, nf = m + 2 * o, nc * m
+    mu, V, _ = gauss.local_kl(P, 1.0 / nf, 1.0, 1.0 / 8, K)
+    box = 2.0
+    md = {L: gauss.kl_sgi_os_offline(m, o, mu, V, L, box) for L in (2, 3, 4)}
+    dg, _ = sc.sparse_grid(K, 3)
+    r = 7
+    x = np.array([sc.node_values(dg[r:r + 1, i], 3, -box, box)[0] for i in range(K)])
+    blk = gauss.truncated_kappa_blocks(x[None, None], mu, V, K)[:, 0]
+    for cls in [(1, 1), (0, 2)]:
+        ref = gauss.os_S_embedded(blk, m, o, *cls)[0]
+        got = sc.smolyak_interp(md[3]["tables"][cls], K, 3, (x / box)[None])[0]
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    xr = np.random.default_rng(13).uniform(-box, box, size=(6, K))
+    blocks = gauss.truncated_kappa_blocks(xr[:, None], mu, V, K)[:, 0]
+    err = {}
+    for L, model in md.items():
+        e = 0.0
+        for cls in [(1, 1), (0, 2)]:
+            ref = gauss.os_S_embedded(blocks, m, o, *cls)
+            got = sc.smolyak_interp(model["tables"][cls], K, L, xr / box)
+            e = max(e, float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()))
+        err[L] = e
+    assert err[4] < 0.3 * err[2] and err[4] < 1e-2, err
+    # online: interior pairs through the sparse tables, the rest as before
+    xi = np.zeros((1, nc * nc, K))
+    xi[0, 5] = x
+    xi[0, 6] = 3.0
+    a = np.exp(np.random.default_rng(14).normal(size=(1, nf, nf)))
+    S, fb = gauss.kl_interp_os_online(md[3], xi, a, nc)
+    assert fb[0, 6] and not fb[0, 5]
+    ref = gauss.os_S_embedded(blk, m, o, gauss.element_class(1, m, o, nc), gauss.element_class(1, m, o, nc))[0]
+    np.testing.assert_allclose(S[0, 5], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
