@@ -573,7 +573,17 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
  * stomsfem_kl_interp_apply then writes S device [nsamples][M][16], xi from
  * stomsfem_kl_project_patches, and computes the out-of-box pairs by the
  * oversampling kernels on the sample's own patch.  ENOTSPD if a node's cell
- * problem fails. */
+ * problem fails.
+ *
+ * stomsfem_kl_sgi_os_build (offline): the same tables at the nodes of the
+ * level-`level` (0..5) Smolyak sparse grid with nested Clenshaw-Curtis
+ * (Chebyshev-Lobatto) nodes in the K patch parameters on [-box, box]^K (node
+ * set as stomsfem_sparse_grid; 401 nodes at level 4 and 1105 at level 5 for
+ * K = 4, the paper's "about 1000"), evaluated online by Smolyak's
+ * combination of tensor Lagrange interpolants (as stomsfem_sgi_apply).  The
+ * model is kind 8 and is applied by stomsfem_kl_interp_apply exactly as
+ * kind 7 (S device [nsamples][M][16], the same fallback).  At most 65535
+ * coarse elements. */
 int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, const double* mu, const double* modes,
                              int32_t nnodes, double box, stomsfem_model** model, void* stream);
 int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
@@ -581,6 +591,8 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
 int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
                                 const double* mu, const double* modes, int32_t nnodes, double box,
                                 stomsfem_model** model, void* stream);
+int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K, const double* mu,
+                             const double* modes, int32_t level, double box, stomsfem_model** model, void* stream);
 
 /* ------------------------------------------------------------------------
  * Execution plans.  A stage is one batch of samples taken through the whole
@@ -682,7 +694,7 @@ int stomsfem_model_load(const char* path, stomsfem_model** model);
 /* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
  * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation,
  * 6 = interpolation in the local KL parameters; 7 = the same for the oversampled
- * Petrov-Galerkin stiffness;
+ * Petrov-Galerkin stiffness; 8 = the latter on a sparse grid;
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

@@ -677,6 +677,132 @@ int stomsfem_kl_interp_build(int32_t ncx, int32_t ncy, int32_t m, int32_t K, con
   return STOMSFEM_OK;
 }
 
+// The level-L sparse grid in k = 1..4 variables (k = 0: the one empty
+// point), the one-dimensional nodes of every level (level i at lofs[i]) and
+// Smolyak's combination entries (coefficient, basis offsets) per k, grouped
+// by the table row of their node, with per-k row offsets; `missing` is set if
+// a tensor node of the combination is not a grid node.  Entries padded by
+// SGI_BATCH - 1 for the kernel's batched reads.
+struct SgiComb {
+  std::vector<int32_t> gdig[RI_KMAX + 1];
+  int64_t npts[RI_KMAX + 1] = {1, 0, 0, 0, 0};
+  int32_t lofs[SGI_LEVEL_MAX + 3] = {};
+  std::vector<double> nodes;
+  std::vector<double> cc;
+  std::vector<uint32_t> cbo;
+  std::vector<int32_t> rows_all;
+  int32_t rofs[6] = {};
+  bool missing = false;
+  int D = 1;
+};
+
+static void sgi_combination(int level, SgiComb& C) {
+  const int D = sc_digit_base(level);
+  C.D = D;
+  auto& gdig = C.gdig;
+  auto& npts = C.npts;
+  auto& lofs = C.lofs;
+  auto& nodes = C.nodes;
+  auto& cc = C.cc;
+  auto& cbo = C.cbo;
+  auto& rows_all = C.rows_all;
+  auto& rofs = C.rofs;
+  bool missing = false;
+  // the level-L grid in k variables (k = 1..4; k = 0: the one empty point)
+  for (int k = 1; k <= RI_KMAX; ++k) {
+    std::vector<double> gw;
+    sc_build_grid(k, level, gdig[k], gw);
+    npts[k] = (int64_t)gw.size();
+  }
+  // one-dimensional nodes of every level, level i at lofs[i]
+  nodes.assign(1, 0.0);
+  for (int i = 2; i <= level + 1; ++i) {
+    const int n = (1 << (i - 1)) + 1;
+    lofs[i] = (int32_t)nodes.size();
+    for (int j = 0; j < n; ++j) nodes.push_back(std::cos(M_PI * (double)j / (double)(n - 1)));
+  }
+  // combination entries per k: (coefficient, basis offsets), grouped by the
+  // table row of their node; per k the row offsets into the entries
+  for (int k = 0; k <= RI_KMAX; ++k) {
+    rofs[k] = (int32_t)rows_all.size();
+    if (k == 0) {
+      rows_all.push_back((int32_t)cc.size());
+      cc.push_back(1.0);
+      cbo.push_back(0u);
+      rows_all.push_back((int32_t)cc.size());
+      continue;
+    }
+    std::vector<std::vector<std::pair<double, uint32_t>>> byrow((size_t)npts[k]);
+    std::map<std::vector<int32_t>, int32_t> rowof;
+    for (int64_t r = 0; r < npts[k]; ++r)
+      rowof[std::vector<int32_t>(gdig[k].begin() + r * k, gdig[k].begin() + (r + 1) * k)] = (int32_t)r;
+    std::vector<int32_t> dg(k);
+    std::vector<int> pos(k);
+    sc_smolyak_terms(k, level, [&](double c, const std::vector<int>& idx) {
+      for (int d = 0; d < k; ++d) pos[d] = 0;
+      while (true) {
+        uint32_t bo = 0;
+        for (int d = 0; d < k; ++d) {
+          const int n = idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1;
+          dg[d] = n == 1 ? D / 2 : pos[d] * (D / (n - 1));
+          bo |= (uint32_t)(lofs[idx[d]] + pos[d]) << (8 * d);
+        }
+        const auto it = rowof.find(dg);
+        missing = missing || it == rowof.end();
+        byrow[it == rowof.end() ? 0 : it->second].emplace_back(c, bo);
+        int d = k - 1;
+        while (d >= 0 && ++pos[d] == (idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1)) pos[d--] = 0;
+        if (d < 0) break;
+      }
+    });
+    for (int64_t r = 0; r < npts[k]; ++r) {
+      rows_all.push_back((int32_t)cc.size());
+      for (const auto& en : byrow[(size_t)r]) {
+        cc.push_back(en.first);
+        cbo.push_back(en.second);
+      }
+    }
+    rows_all.push_back((int32_t)cc.size());
+  }
+  rofs[RI_KMAX + 1] = (int32_t)rows_all.size();
+  C.missing = missing;
+  cc.insert(cc.end(), SGI_BATCH - 1, 0.0);
+  cbo.insert(cbo.end(), SGI_BATCH - 1, 0u);
+}
+
+// The nine class tables of an oversampled KL interpolation model (kinds 7,
+// 8): md->table [9][rows][16] from the node parameters xin (device [rows][K]):
+// the truncated local KL on the patch (nblk: device [rows][P][P] scratch),
+// placed in 3 x 3-element meshes at each class, the oversampling kernels, the
+// class element's entries; statuses into stn (device [9 rows]).
+static hipError_t os_class_tables(stomsfem_model* md, int64_t rows, int K, const double* xin, const double* mu,
+                                  const double* modes, double* nblk, int32_t* stn, hipStream_t st) {
+  const int m = md->m, o = md->os_o, P = m + 2 * o;
+  hipError_t e = launch_kl_blocks(rows, P, K, K, xin, mu, modes, nblk, st);
+  for (int c = 0; c < 9 && e == hipSuccess; ++c) {
+    const int cx = c % 3, cy = c / 3;
+    for (int64_t start = 0; start < rows && e == hipSuccess; start += md->chunk) {
+      const int64_t cnt = std::min<int64_t>(md->chunk, rows - start);
+      e = launch_embed_patch(cnt, m, o, cx, cy, nblk + start * P * P, md->blk, st);
+      if (e == hipSuccess) {
+        UpArgs u{};
+        u.nsamples = cnt;
+        u.ncx = u.ncy = 3;
+        u.m = m;
+        u.npairs = cnt * 9;
+        u.a = md->blk;
+        u.S = md->Sc;
+        u.status = md->stc;
+        e = launch_upscale_os(u, o, STOMSFEM_F64, st);
+      }
+      if (e == hipSuccess)
+        e = launch_pick_class(cnt, cx, cy, md->Sc, md->stc, md->table + (c * rows + start) * 16,
+                              stn + c * rows + start, st);
+    }
+  }
+  return e;
+}
+
 int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
                                 const double* mu, const double* modes, int32_t nnodes, double box,
                                 stomsfem_model** model, void* stream) {
@@ -762,29 +888,7 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
   if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice);
-  // the patch coefficient at every node: the truncated local KL on side P
-  if (e == hipSuccess) e = launch_kl_blocks(rows, P, K, K, xin, mu, modes, nblk, st);
-  for (int c = 0; c < 9 && e == hipSuccess; ++c) {
-    const int cx = c % 3, cy = c / 3;
-    for (int64_t start = 0; start < rows && e == hipSuccess; start += md->chunk) {
-      const int64_t cnt = std::min<int64_t>(md->chunk, rows - start);
-      e = launch_embed_patch(cnt, m, o, cx, cy, nblk + start * P * P, md->blk, st);
-      if (e == hipSuccess) {
-        UpArgs u{};
-        u.nsamples = cnt;
-        u.ncx = u.ncy = 3;
-        u.m = m;
-        u.npairs = cnt * 9;
-        u.a = md->blk;
-        u.S = md->Sc;
-        u.status = md->stc;
-        e = launch_upscale_os(u, o, STOMSFEM_F64, st);
-      }
-      if (e == hipSuccess)
-        e = launch_pick_class(cnt, cx, cy, md->Sc, md->stc, md->table + (c * rows + start) * 16,
-                              stn + c * rows + start, st);
-    }
-  }
+  if (e == hipSuccess) e = os_class_tables(md, rows, K, xin, mu, modes, nblk, stn, st);
   std::vector<int32_t> sth((size_t)rows * 9);
   if (e == hipSuccess) e = hipMemcpyAsync(sth.data(), stn, sizeof(int32_t) * rows * 9, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -805,12 +909,129 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
   return STOMSFEM_OK;
 }
 
+int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K, const double* mu,
+                             const double* modes, int32_t level, double box, stomsfem_model** model, void* stream) {
+  if (!model) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: NULL model");
+  *model = nullptr;
+  const int o = oversample, P = m + 2 * oversample;
+  if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m || K < 1 ||
+      K > RI_KMAX || level < 0 || level > SGI_LEVEL_MAX || !(box > 0))
+    return fail(STOMSFEM_EINVAL,
+                "kl_sgi_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
+                "domain, 1 <= K <= 4, 0 <= level <= 5, box > 0");
+  if (!device_ptr(mu) || !device_ptr(modes)) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: mu and modes on device");
+  const int Mc = ncx * ncy;
+  if (Mc > 65535) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: at most 65535 coarse elements");
+  SgiComb C;
+  sgi_combination(level, C);
+  if (C.missing) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: a tensor node of the combination is not a grid node");
+  const int64_t rows = C.npts[K];
+  hipStream_t st = (hipStream_t)stream;
+  auto* md = new stomsfem_model();
+  md->kind = 8;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->os_o = o;
+  md->lo = -box;
+  md->hi = box;
+  md->rows = rows;
+  md->sc_level = level;
+  md->sg_nb = (int32_t)C.nodes.size();
+  md->sg_kmax = K;
+  std::memcpy(md->sg_lofs, C.lofs, sizeof(C.lofs));
+  std::memcpy(md->sg_rofs, C.rofs, sizeof(C.rofs));
+  md->chunk = std::max<int64_t>(64, std::min<int64_t>(16384, (int64_t{1} << 22) / (9 * (int64_t)m * m)));
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  double* xin = nullptr;
+  double* nblk = nullptr;
+  int32_t* stn = nullptr;
+  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
+  A((void**)&md->nlv, sizeof(int32_t) * Mc);
+  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
+  A((void**)&md->table, sizeof(double) * (size_t)rows * 9 * 16);
+  A((void**)&md->counter, sizeof(unsigned long long));
+  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * 9 * m * m);
+  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 9 * 16);
+  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk * 9);
+  A((void**)&md->cb_coef, sizeof(double) * C.cc.size());
+  A((void**)&md->cb_boff, sizeof(uint32_t) * C.cbo.size());
+  A((void**)&md->cb_rows, sizeof(int32_t) * C.rows_all.size());
+  A((void**)&md->sg_nodes, sizeof(double) * C.nodes.size());
+  A((void**)&xin, sizeof(double) * (size_t)rows * K);
+  A((void**)&nblk, sizeof(double) * (size_t)rows * P * P);
+  A((void**)&stn, sizeof(int32_t) * (size_t)rows * 9);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(xin);
+    hipFree(nblk);
+    hipFree(stn);
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "kl_sgi_os_build: device allocation failed");
+  }
+  auto cls = [&](int k) {
+    const int nf = ncx * m;
+    int x0 = k * m - o;
+    if (x0 > nf - P) x0 = nf - P;
+    if (x0 < 0) x0 = 0;
+    return (k * m - x0) / o;
+  };
+  std::vector<int32_t> lv((size_t)Mc * RI_KMAX, -1), nlv(Mc, K);
+  std::vector<int64_t> off(Mc + 1, 0);
+  for (int p = 0; p < Mc; ++p) {
+    for (int k = 0; k < K; ++k) lv[(size_t)p * RI_KMAX + k] = p * K + k;
+    off[p] = (int64_t)(cls(p / ncx) * 3 + cls(p % ncx)) * rows;
+  }
+  off[Mc] = 9 * rows;
+  // grid nodes: Chebyshev-Lobatto points of the finest level, by digit
+  std::vector<double> xh((size_t)rows * K);
+  for (int64_t r = 0; r < rows; ++r)
+    for (int v = 0; v < K; ++v) {
+      const int32_t c = C.gdig[K][r * K + v];
+      xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)c / (double)C.D) + 1.0) * box;
+    }
+  e = hipMemcpy(md->lv, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(md->cb_coef, C.cc.data(), sizeof(double) * C.cc.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->cb_boff, C.cbo.data(), sizeof(uint32_t) * C.cbo.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->cb_rows, C.rows_all.data(), sizeof(int32_t) * C.rows_all.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->sg_nodes, C.nodes.data(), sizeof(double) * C.nodes.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = os_class_tables(md, rows, K, xin, mu, modes, nblk, stn, st);
+  std::vector<int32_t> sth((size_t)rows * 9);
+  if (e == hipSuccess) e = hipMemcpyAsync(sth.data(), stn, sizeof(int32_t) * rows * 9, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(xin);
+  hipFree(nblk);
+  hipFree(stn);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "kl_sgi_os_build");
+  }
+  for (int64_t r = 0; r < rows * 9; ++r)
+    if (sth[(size_t)r] != 0) {
+      model_release(md);
+      return fail(STOMSFEM_ENOTSPD, "kl_sgi_os_build: a cell problem at a node failed");
+    }
+  md->lv_max = K;
+  *model = md;
+  return STOMSFEM_OK;
+}
+
 int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
                              double* S, int32_t* status, int64_t* nfallback, void* stream) {
   if (nfallback) *nfallback = 0;
-  if (!model || (model->kind != 6 && model->kind != 7))
+  if (!model || (model->kind != 6 && model->kind != 7 && model->kind != 8))
     return fail(STOMSFEM_EINVAL, "kl_interp_apply: not a KL interpolation model");
-  const bool os = model->kind == 7;
+  const bool os = model->kind == 7 || model->kind == 8;
   if (nsamples < 0) return fail(STOMSFEM_EINVAL, "kl_interp_apply: nsamples < 0");
   if (nsamples == 0) return STOMSFEM_OK;
   if (!device_ptr(xi) || !device_ptr(kappa) || !device_ptr(S) || (status && !device_ptr(status)))
@@ -850,7 +1071,37 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
   a.list = model->list;
   a.list_count = model->counter;
   hipError_t e = launch_zero_u64(model->counter, st);
-  if (e == hipSuccess) e = launch_ri_apply(a, st);
+  if (e == hipSuccess && model->kind == 8) {
+    // Smolyak interpolant on the sparse grid (every element has K variables)
+    SgiApplyArgs g{};
+    g.ne = 16;
+    g.npatch = Mc;
+    g.nxi = Mc * K;
+    g.level = model->sc_level;
+    g.nb = model->sg_nb;
+    g.kmax = model->sg_kmax;
+    g.nsamples = nsamples;
+    g.lo = model->lo;
+    g.hi = model->hi;
+    g.table = model->table;
+    g.off = model->off;
+    g.lv = model->lv;
+    g.nlv = model->nlv;
+    g.nodes = model->sg_nodes;
+    std::memcpy(g.lofs, model->sg_lofs, sizeof(g.lofs));
+    std::memcpy(g.rofs, model->sg_rofs, sizeof(g.rofs));
+    g.cb_coef = model->cb_coef;
+    g.cb_boff = model->cb_boff;
+    g.cb_rows = model->cb_rows;
+    g.xi = xi;
+    g.S = S;
+    g.status = status;
+    g.list = model->list;
+    g.list_count = model->counter;
+    e = launch_sgi_apply(g, st);
+  } else if (e == hipSuccess) {
+    e = launch_ri_apply(a, st);
+  }
   unsigned long long n = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1842,76 +2093,19 @@ int stomsfem_sgi_build(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local
     nlv[K] = k;
     kmax = std::max(kmax, k);
   }
-  // the level-L grid in k variables (k = 1..4; k = 0: the one empty point)
-  std::vector<int32_t> gdig[RI_KMAX + 1];
-  int64_t npts[RI_KMAX + 1] = {1, 0, 0, 0, 0};
-  for (int k = 1; k <= RI_KMAX; ++k) {
-    std::vector<double> gw;
-    sc_build_grid(k, level, gdig[k], gw);
-    npts[k] = (int64_t)gw.size();
-  }
-  // one-dimensional nodes of every level, level i at lofs[i]
-  int32_t lofs[SGI_LEVEL_MAX + 3] = {};
-  std::vector<double> nodes{0.0};
-  for (int i = 2; i <= level + 1; ++i) {
-    const int n = (1 << (i - 1)) + 1;
-    lofs[i] = (int32_t)nodes.size();
-    for (int j = 0; j < n; ++j) nodes.push_back(std::cos(M_PI * (double)j / (double)(n - 1)));
-  }
+  SgiComb C;
+  sgi_combination(level, C);
+  const auto& gdig = C.gdig;
+  const auto& npts = C.npts;
+  const auto& lofs = C.lofs;
+  const auto& nodes = C.nodes;
+  const auto& cc = C.cc;
+  const auto& cbo = C.cbo;
+  const auto& rows_all = C.rows_all;
+  const auto& rofs = C.rofs;
+  const bool missing = C.missing;
   const int nb = (int)nodes.size();
-  // combination entries per k: (coefficient, basis offsets), grouped by the
-  // table row of their node; per k the row offsets into the entries
-  std::vector<double> cc;
-  std::vector<uint32_t> cbo;
-  std::vector<int32_t> rows_all;
-  int32_t rofs[6] = {};
-  bool missing = false;
-  for (int k = 0; k <= RI_KMAX; ++k) {
-    rofs[k] = (int32_t)rows_all.size();
-    if (k == 0) {
-      rows_all.push_back((int32_t)cc.size());
-      cc.push_back(1.0);
-      cbo.push_back(0u);
-      rows_all.push_back((int32_t)cc.size());
-      continue;
-    }
-    std::vector<std::vector<std::pair<double, uint32_t>>> byrow((size_t)npts[k]);
-    std::map<std::vector<int32_t>, int32_t> rowof;
-    for (int64_t r = 0; r < npts[k]; ++r)
-      rowof[std::vector<int32_t>(gdig[k].begin() + r * k, gdig[k].begin() + (r + 1) * k)] = (int32_t)r;
-    std::vector<int32_t> dg(k);
-    std::vector<int> pos(k);
-    sc_smolyak_terms(k, level, [&](double c, const std::vector<int>& idx) {
-      for (int d = 0; d < k; ++d) pos[d] = 0;
-      while (true) {
-        uint32_t bo = 0;
-        for (int d = 0; d < k; ++d) {
-          const int n = idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1;
-          dg[d] = n == 1 ? D / 2 : pos[d] * (D / (n - 1));
-          bo |= (uint32_t)(lofs[idx[d]] + pos[d]) << (8 * d);
-        }
-        const auto it = rowof.find(dg);
-        missing = missing || it == rowof.end();
-        byrow[it == rowof.end() ? 0 : it->second].emplace_back(c, bo);
-        int d = k - 1;
-        while (d >= 0 && ++pos[d] == (idx[d] == 1 ? 1 : (1 << (idx[d] - 1)) + 1)) pos[d--] = 0;
-        if (d < 0) break;
-      }
-    });
-    for (int64_t r = 0; r < npts[k]; ++r) {
-      rows_all.push_back((int32_t)cc.size());
-      for (const auto& en : byrow[(size_t)r]) {
-        cc.push_back(en.first);
-        cbo.push_back(en.second);
-      }
-    }
-    rows_all.push_back((int32_t)cc.size());
-  }
-  rofs[RI_KMAX + 1] = (int32_t)rows_all.size();
   if (missing) return fail(STOMSFEM_EINVAL, "sgi_build: a tensor node of the combination is not a grid node");
-  // the kernel reads SGI_BATCH entries at a time: pad past the last row
-  cc.insert(cc.end(), SGI_BATCH - 1, 0.0);
-  cbo.insert(cbo.end(), SGI_BATCH - 1, 0u);
   std::vector<int64_t> off(Mc + 1, 0);
   for (int K = 0; K < Mc; ++K) off[K + 1] = off[K] + npts[nlv[K]];
   hipStream_t st = (hipStream_t)stream;

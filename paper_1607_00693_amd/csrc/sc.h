@@ -31,6 +31,7 @@ void sc_smolyak_terms(int dim, int level, const std::function<void(double, const
 constexpr int SGI_LEVEL_MAX = 5;  // 33 nodes per variable at most
 constexpr int SGI_BATCH = 4;      // combination entries evaluated together (entry arrays padded by 3)
 struct SgiApplyArgs {
+  int32_t ne;  // entries per table row and per S: 10 (symmetric) or 16 (Petrov-Galerkin); 0 = 10
   int32_t npatch, nxi, level, nb, kmax;
   int64_t nsamples;
   double lo, hi;
@@ -50,7 +51,7 @@ struct SgiApplyArgs {
   int64_t* list;
   unsigned long long* list_count;
 };
-size_t sgi_lds_bytes(int kmax, int nb, int level);
+size_t sgi_lds_bytes(int kmax, int nb, int level, int ne);
 hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st);
 
 struct ScApplyArgs {

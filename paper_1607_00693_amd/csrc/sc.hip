@@ -188,7 +188,7 @@ hipError_t launch_sc_apply(const ScApplyArgs& a, hipStream_t st) {
 // for the plain path instead.  Every global store (and the list's atomic)
 // comes after the loop, so the wave-uniform loads of the loop are not
 // clobbered and go through the scalar cache.
-template <int SGI_WAVES>
+template <int SGI_WAVES, int NE>
 __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs a) {
   extern __shared__ double sgi_lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -222,10 +222,10 @@ __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs 
   }
   __syncthreads();
   const int64_t p = s * a.npatch + K;
-  double acc[10];
+  double acc[NE];
 #pragma unroll
-  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  const double* T = a.table + a.off[K] * 10;
+  for (int q = 0; q < NE; ++q) acc[q] = 0.0;
+  const double* T = a.table + a.off[K] * NE;
   const int32_t* rs = a.cb_rows + a.rofs[k];  // entries of row r: rs[r] .. rs[r+1]-1
   const int nr = a.rofs[k + 1] - a.rofs[k] - 1;
   const int r0 = (int)((int64_t)nr * wave / SGI_WAVES), r1 = (int)((int64_t)nr * (wave + 1) / SGI_WAVES);
@@ -251,27 +251,27 @@ __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs 
       for (int u = 0; u < SGI_BATCH; ++u) wr += w[u];
     }
     c = c1;
-    const double* Tr = T + (int64_t)r * 10;
+    const double* Tr = T + (int64_t)r * NE;
 #pragma unroll
-    for (int q = 0; q < 10; ++q) acc[q] += wr * Tr[q];
+    for (int q = 0; q < NE; ++q) acc[q] += wr * Tr[q];
   }
   // partial sums of wavefronts 1.. into LDS (the bases are no longer read)
   __syncthreads();
-  double* red = sgi_lds + lane;  // red[((w - 1) * 10 + q) * 64]
+  double* red = sgi_lds + lane;  // red[((w - 1) * NE + q) * 64]
   if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < 10; ++q) red[((wave - 1) * 10 + q) * 64] = acc[q];
+    for (int q = 0; q < NE; ++q) red[((wave - 1) * NE + q) * 64] = acc[q];
   }
   __syncthreads();
   if (wave > 0) return;
 #pragma unroll
   for (int w = 1; w < SGI_WAVES; ++w)
 #pragma unroll
-    for (int q = 0; q < 10; ++q) acc[q] += red[((w - 1) * 10 + q) * 64];
+    for (int q = 0; q < NE; ++q) acc[q] += red[((w - 1) * NE + q) * 64];
   if (valid && inside) {
-    double* So = a.S + p * 10;
+    double* So = a.S + p * NE;
 #pragma unroll
-    for (int q = 0; q < 10; ++q) So[q] = acc[q];
+    for (int q = 0; q < NE; ++q) So[q] = acc[q];
     if (a.status) a.status[p] = 0;
   } else if (valid) {
     const unsigned long long slot = atomicAdd(a.list_count, 1ull);
@@ -281,26 +281,29 @@ __global__ __launch_bounds__(64 * SGI_WAVES) void sgi_apply_kernel(SgiApplyArgs 
 
 static int sgi_waves(int level) { return level >= 5 ? 16 : 8; }
 
-size_t sgi_lds_bytes(int kmax, int nb, int level) {
+size_t sgi_lds_bytes(int kmax, int nb, int level, int ne) {
   const size_t bases = (size_t)64 * (kmax > 0 ? kmax : 1) * nb * sizeof(double);
-  const size_t red = (size_t)64 * (sgi_waves(level) - 1) * 10 * sizeof(double);
+  const size_t red = (size_t)64 * (sgi_waves(level) - 1) * ne * sizeof(double);
   return bases > red ? bases : red;
 }
 
-template <int NW>
+template <int NW, int NE>
 static hipError_t launch_sgi(const SgiApplyArgs& a, hipStream_t st) {
-  const size_t lds = sgi_lds_bytes(a.kmax, a.nb, a.level);
-  hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  const size_t lds = sgi_lds_bytes(a.kmax, a.nb, a.level, NE);
+  hipError_t e = hipFuncSetAttribute((const void*)sgi_apply_kernel<NW, NE>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
-  hipLaunchKernelGGL(sgi_apply_kernel<NW>, grid, dim3(64 * NW), lds, st, a);
+  hipLaunchKernelGGL((sgi_apply_kernel<NW, NE>), grid, dim3(64 * NW), lds, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_sgi_apply(const SgiApplyArgs& a, hipStream_t st) {
   if (a.nsamples == 0) return hipSuccess;
-  return sgi_waves(a.level) == 16 ? launch_sgi<16>(a, st) : launch_sgi<8>(a, st);
+  const bool w16 = sgi_waves(a.level) == 16;
+  if (a.ne == 16) return w16 ? launch_sgi<16, 16>(a, st) : launch_sgi<8, 16>(a, st);
+  if (a.ne != 0 && a.ne != 10) return hipErrorInvalidValue;
+  return w16 ? launch_sgi<16, 10>(a, st) : launch_sgi<8, 10>(a, st);
 }
 
 static int64_t quad_chunk(int64_t npoints) {

@@ -135,6 +135,7 @@ def lib():
         "stomsfem_kl_blocks": (C.c_int, [i64, i32, i32, i32, vp, vp, vp, vp, vp]),
         "stomsfem_kl_interp_build": (C.c_int, [i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_kl_interp_os_build": (C.c_int, [i32, i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
+        "stomsfem_kl_sgi_os_build": (C.c_int, [i32, i32, i32, i32, i32, vp, vp, i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_kl_interp_apply": (C.c_int, [vp, vp, vp, i64, vp, vp, C.POINTER(i64), vp]),
     }
     for name, (res, args) in sig.items():
@@ -298,13 +299,19 @@ def kl_blocks(xi: torch.Tensor, mu: torch.Tensor, modes: torch.Tensor, Kuse: int
 
 
 def kl_interp_build(ncx: int, ncy: int, m: int, mu: torch.Tensor, modes: torch.Tensor, nnodes: int,
-                    box: float = 3.0, stream=None, oversample: int = 0) -> Model:
+                    box: float = 3.0, stream=None, oversample: int = 0, level: int | None = None) -> Model:
     """Offline: S at the tensor Lobatto nodes of the local KL parameters (one
     table for all elements); oversample > 0: the oversampled Petrov-Galerkin
     stiffness (16 entries) in the parameters of the oversampled patches (modes
-    of side m + 2 oversample), one table per element class."""
+    of side m + 2 oversample), one table per element class; with `level`, at
+    the nodes of that sparse grid instead (nnodes is then unused)."""
     h = C.c_void_p()
-    if oversample == 0:
+    if level is not None:
+        if oversample < 1:
+            raise ValueError("the sparse-grid tables are for the oversampled stiffness (oversample >= 1)")
+        _check("stomsfem_kl_sgi_os_build", lib().stomsfem_kl_sgi_os_build(
+            ncx, ncy, m, oversample, mu.shape[0], _ptr(mu), _ptr(modes), level, box, C.byref(h), _stream(stream)))
+    elif oversample == 0:
         _check("stomsfem_kl_interp_build", lib().stomsfem_kl_interp_build(
             ncx, ncy, m, mu.shape[0], _ptr(mu), _ptr(modes), nnodes, box, C.byref(h), _stream(stream)))
     else:

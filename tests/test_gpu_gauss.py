@@ -268,3 +268,36 @@ def test_oversampled_interpolation_rejects_bad_shapes(sm):
         sm.kl_interp_build(4, 3, 8, mu, V, 3, 3.0, oversample=4)
     with pytest.raises(sm.StomsfemError):  # patch wider than the domain
         sm.kl_interp_build(1, 1, 8, mu, V, 3, 3.0, oversample=4)
+
+
+@pytest.mark.parametrize("K,level,box", [(3, 2, 3.0), (4, 3, 1.0), (2, 5, 2.0)])
+def test_oversampled_sparse_grid_interpolation_matches_oracle(sm, K, level, box):
+    # the oversampled stiffness on the sparse grid of the patch parameters
+    # (levels 2, 3 and 5: eight and sixteen wavefronts per workgroup), each
+    # side with its own modes and grid; the narrow box forces fallbacks
+    nc, m, o, N = 4, 8, 4, 3
+    P, nf = m + 2 * o, nc * m
+    l1, l2 = 1.0, 1.0 / 8
+    say(f"oversampled sparse-grid KL interpolation K={K} level={level} box={box}")
+    z, u = W.spectral_draws(N, 64, 2190 + level)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, l1, l2, with_beta=True)
+    mu, V, _ = sm.local_kl(P, 1.0 / nf, l1, l2, K)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    xi, _, count = sm.kl_project(beta, nc, m, mu_d, V_d, box, oversample=o)
+    model = sm.kl_interp_build(nc, nc, m, mu_d, V_d, 0, box, oversample=o, level=level)
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S, nfb = sm.kl_interp_apply(model, xi, kap, status=st)
+    torch.cuda.synchronize()
+    b_ref = gauss.field(z, u, nf, l1, l2)
+    mu_r, V_r, _ = gauss.local_kl(P, 1.0 / nf, l1, l2, K)
+    xi_r = gauss.project_patches(b_ref, nc, m, o, mu_r, V_r)
+    orc = gauss.kl_sgi_os_offline(m, o, mu_r, V_r, level, box)
+    S_ref, fb = gauss.kl_interp_os_online(orc, xi_r, gauss.kappa(b_ref), nc)
+    st = st.cpu().numpy()
+    assert nfb == int(fb.sum()) == int(count.item())
+    assert (st[fb] == 1).all() and (st[~fb] == 0).all()
+    if box < 2:
+        assert fb.any() and (~fb).any()
+    err = (np.abs(S.cpu().numpy() - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
+    say(f"  {int(fb.sum())} oversampled solves, S rel err {err:.2e}")
+    assert err < 1e-10
