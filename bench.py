@@ -620,9 +620,12 @@ def measure_gauss(log, N=1024, n_trunc=64):
     sc_pl = S_pl.abs().amax(dim=2)
     U_pl, _, _ = sm.coarse_solve_pg(S_pl[:n_trunc].contiguous(), wl.nc, wl.nc)
     os_interp = {}
-    for nn in (5, 7):
+    # tensor grids of 5 and 7 nodes per parameter; sparse grids of levels 4
+    # and 5 (401 and 1105 nodes in four parameters)
+    for name, nn, level, nodes in (("nodes_5", 5, None, 5 ** 4), ("nodes_7", 7, None, 7 ** 4),
+                                   ("sparse_level_4", 0, 4, 401), ("sparse_level_5", 0, 5, 1105)):
         t0 = time.perf_counter()
-        model = sm.kl_interp_build(wl.nc, wl.nc, wl.m, mu_os_d, V_os_d, nn, wl.box, oversample=o)
+        model = sm.kl_interp_build(wl.nc, wl.nc, wl.m, mu_os_d, V_os_d, nn, wl.box, oversample=o, level=level)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
         S_i = torch.empty_like(S_pl)
@@ -630,8 +633,9 @@ def measure_gauss(log, N=1024, n_trunc=64):
         _, nfb = sm.kl_interp_apply(model, xi_os, kap_os, S=S_i)
         U_i, _, _ = sm.coarse_solve_pg(S_i[:n_trunc].contiguous(), wl.nc, wl.nc)
         ins = ~out_os.bool()
-        os_interp[f"nodes_{nn}"] = {
-            "table_rows": 9 * nn ** 4, "build_s": t_build, "apply_ms": t_i * 1e3, "pairs_per_s": pairs / t_i,
+        os_interp[name] = {
+            "nodes_per_class": nodes, "table_rows": 9 * nodes, "build_s": t_build, "apply_ms": t_i * 1e3,
+            "pairs_per_s": pairs / t_i,
             "oversampled_plain_pairs_per_s": pairs / t_pl, "ratio_vs_oversampled_plain": t_pl / t_i,
             "ratio_vs_oversampled_plain_with_field": (t_field + t_pl) / (t_field + t_proj_os + t_i),
             "fallback_pairs": nfb,
