@@ -579,7 +579,7 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
  * level-`level` (0..5) Smolyak sparse grid with nested Clenshaw-Curtis
  * (Chebyshev-Lobatto) nodes in the K patch parameters on [-box, box]^K (node
  * set as stomsfem_sparse_grid; 401 nodes at level 4 and 1105 at level 5 for
- * K = 4, the paper's "about 1000"), evaluated online by Smolyak's
+ * K = 4, close to the node count of Sec. 5.3), evaluated online by Smolyak's
  * combination of tensor Lagrange interpolants (as stomsfem_sgi_apply).  The
  * model is kind 8 and is applied by stomsfem_kl_interp_apply exactly as
  * kind 7 (S device [nsamples][M][16], the same fallback).  At most 65535

@@ -95,7 +95,7 @@ def test_oversampled_patch_kl_in_the_papers_geometry():
     P, nf = m + 2 * o, nc * m
     l1, l2 = 1.0, 1.0 / nc
     mu, V, cap = gauss.local_kl(P, 1.0 / nf, l1, l2, 4)
-    assert 0.985 < mu.sum() / (P * P) < 0.997  # "about 99%" with four terms
+    assert 0.985 < mu.sum() / (P * P) < 0.997  # four terms keep roughly 99% (Sec. 5.3)
     N = 100
     z, u = W.spectral_draws(N, 256, 73)
     xi = gauss.project_patches(gauss.field(z, u, nf, l1, l2), nc, m, o, mu, V)
