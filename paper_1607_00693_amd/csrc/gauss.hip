@@ -288,11 +288,12 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_kernel(int64_t npairs,
   }
 }
 
-// Patches of side <= 16 (every row of a lane's column in one step of four):
+// Patches of side <= 16 (U = 4) or <= 32 (U = 16): every row of a lane's
+// column in one step of U rows;
 // persistent wavefronts that keep their lane's mode values in registers and
 // take pairs p = w, w + (number of wavefronts), ...  The same products and
 // sums in the same order as kl_project_kernel.
-template <int KT>
+template <int KT, int U>
 __global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t npairs, int nc, int m, int o, int K,
                                                                        const double* __restrict__ beta,
                                                                        const double* __restrict__ mu,
@@ -300,7 +301,6 @@ __global__ __launch_bounds__(64 * KL_WPB) void kl_project_small_kernel(int64_t n
                                                                        double* __restrict__ xi,
                                                                        int32_t* __restrict__ outside,
                                                                        unsigned long long* count) {
-  constexpr int U = 4;
   const int lane = threadIdx.x & 63;
   const int P = m + 2 * o;
   const int64_t nf = (int64_t)nc * m, mm = (int64_t)P * P;
@@ -369,10 +369,13 @@ hipError_t launch_kl_project(int64_t npairs, int nc, int m, int o, int K, const 
   if (K < 1 || K > KL_KMAX || o < 0 || m + 2 * o > nc * m) return hipErrorInvalidValue;
   if (npairs > 0xffffffffLL) return hipErrorInvalidValue;
   const int64_t nb = (npairs + KL_WPB - 1) / KL_WPB;
+  const unsigned nbp = (unsigned)(nb < 2048 ? nb : 2048);  // persistent: about eight wavefronts per CU
   if (K <= 4 && m + 2 * o <= 16) {
-    const unsigned nbp = (unsigned)(nb < 2048 ? nb : 2048);  // persistent: about eight wavefronts per CU
-    hipLaunchKernelGGL(kl_project_small_kernel<4>, dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K, beta,
-                       mu, modes, box, xi, outside, count);
+    hipLaunchKernelGGL((kl_project_small_kernel<4, 4>), dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K,
+                       beta, mu, modes, box, xi, outside, count);
+  } else if (K <= 4 && m + 2 * o <= 32) {
+    hipLaunchKernelGGL((kl_project_small_kernel<4, 16>), dim3(nbp), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K,
+                       beta, mu, modes, box, xi, outside, count);
   } else if (K <= 4)
     hipLaunchKernelGGL(kl_project_kernel<4>, dim3((unsigned)nb), dim3(64 * KL_WPB), 0, st, npairs, nc, m, o, K, beta,
                        mu, modes, box, xi, outside, count);
