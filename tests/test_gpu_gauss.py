@@ -301,3 +301,33 @@ def test_oversampled_sparse_grid_interpolation_matches_oracle(sm, K, level, box)
     err = (np.abs(S.cpu().numpy() - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
     say(f"  {int(fb.sum())} oversampled solves, S rel err {err:.2e}")
     assert err < 1e-10
+
+
+def test_oversampled_interpolation_at_the_workload_scale_sampled(sm):
+    # the paper's geometry at the measured size: 16 x 16 mesh, H/h = 16,
+    # patches of 2H = 32 cells, l2 = H, four terms, all 1024 samples in one
+    # apply (sparse grid, level 3); whole samples (first, middle, last)
+    # against the oracle, interpolated and fallback pairs alike
+    wl = W.GAUSS16
+    o, l2, level = wl.m // 2, 1.0 / wl.nc, 3
+    P, nf = wl.m + 2 * o, wl.nfine
+    say("oversampled sparse-grid interpolation, workload scale")
+    z, u = W.spectral_draws(wl.nsamples, wl.nterms, 5011)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, wl.l1, l2, with_beta=True)
+    mu, V, _ = sm.local_kl(P, 1.0 / nf, wl.l1, l2, wl.kl_terms)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    xi, _, _ = sm.kl_project(beta, wl.nc, wl.m, mu_d, V_d, wl.box, oversample=o)
+    model = sm.kl_interp_build(wl.nc, wl.nc, wl.m, mu_d, V_d, 0, wl.box, oversample=o, level=level)
+    S, nfb = sm.kl_interp_apply(model, xi, kap)
+    torch.cuda.synchronize()
+    assert nfb > 0
+    ss = [0, wl.nsamples // 2, wl.nsamples - 1]
+    b_ref = gauss.field(z[ss], u[ss], nf, wl.l1, l2)
+    mu_r, V_r, _ = gauss.local_kl(P, 1.0 / nf, wl.l1, l2, wl.kl_terms)
+    orc = gauss.kl_sgi_os_offline(wl.m, o, mu_r, V_r, level, wl.box)
+    S_ref, fb = gauss.kl_interp_os_online(orc, gauss.project_patches(b_ref, wl.nc, wl.m, o, mu_r, V_r),
+                                          gauss.kappa(b_ref), wl.nc)
+    S = S.cpu().numpy()[ss]
+    err = (np.abs(S - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
+    say(f"  {int(fb.sum())} fallback pairs in the sampled samples, S rel err {err:.2e}")
+    assert err < 1e-10
