@@ -803,36 +803,15 @@ static hipError_t os_class_tables(stomsfem_model* md, int64_t rows, int K, const
   return e;
 }
 
-int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
-                                const double* mu, const double* modes, int32_t nnodes, double box,
-                                stomsfem_model** model, void* stream) {
-  if (!model) return fail(STOMSFEM_EINVAL, "kl_interp_os_build: NULL model");
-  *model = nullptr;
-  const int o = oversample, P = m + 2 * oversample;
-  if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m ||
-      K < 1 || K > RI_KMAX || nnodes < RI_NN_MIN || nnodes > RI_NN_MAX || !(box > 0))
-    return fail(STOMSFEM_EINVAL,
-                "kl_interp_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
-                "domain, "
-                "1 <= K <= 4, 2 <= nnodes <= 9, box > 0");
-  if (!device_ptr(mu) || !device_ptr(modes))
-    return fail(STOMSFEM_EINVAL, "kl_interp_os_build: mu and modes on device");
-  const int Mc = ncx * ncy;
-  int64_t rows = 1;
-  for (int i = 0; i < K; ++i) rows *= nnodes;
-  hipStream_t st = (hipStream_t)stream;
-  auto* md = new stomsfem_model();
-  md->kind = 7;
-  hipGetDevice(&md->device);
-  md->ncx = ncx;
-  md->ncy = ncy;
-  md->m = m;
-  md->os_o = o;
-  md->nn = nnodes;
-  md->lo = -box;
-  md->hi = box;
-  md->rows = rows;
-  // a chunk of 3 x 3 meshes: fields [chunk][3m][3m] of at most 32 MB
+// Common part of the oversampled KL interpolation builds (kinds 7 and 8):
+// md carries the mesh, m, os_o, lo/hi and rows (nodes per class); xh holds
+// the node parameters [rows][K].  Allocates the model buffers, sets every
+// element's table offset from its class, computes the nine class tables and
+// checks the node solves.  Releases md and reports on failure.
+static int os_kl_model_finish(stomsfem_model* md, int K, const std::vector<double>& xh, const double* mu,
+                              const double* modes, hipStream_t st, const char* name) {
+  const int ncx = md->ncx, ncy = md->ncy, m = md->m, o = md->os_o, P = m + 2 * o, Mc = ncx * ncy;
+  const int64_t rows = md->rows;
   md->chunk = std::max<int64_t>(64, std::min<int64_t>(16384, (int64_t{1} << 22) / (9 * (int64_t)m * m)));
   hipError_t e = hipSuccess;
   auto A = [&](void** ptr, size_t bytes) {
@@ -858,7 +837,7 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
     hipFree(nblk);
     hipFree(stn);
     model_release(md);
-    return fail(STOMSFEM_ENOMEM, "kl_interp_os_build: device allocation failed");
+    return fail(STOMSFEM_ENOMEM, std::string(name) + ": device allocation failed");
   }
   // every element reads the table of its class with its own K parameters
   auto cls = [&](int k, int nc) {
@@ -875,15 +854,6 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
     off[p] = (int64_t)(cls(p / ncx, ncy) * 3 + cls(p % ncx, ncx)) * rows;
   }
   off[Mc] = 9 * rows;
-  std::vector<double> xh((size_t)rows * K);
-  for (int64_t r = 0; r < rows; ++r) {
-    int64_t c = r;
-    for (int v = K - 1; v >= 0; --v) {  // variable 0 slowest
-      const int d = (int)(c % nnodes);
-      c /= nnodes;
-      xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)d / (double)(nnodes - 1)) + 1.0) * box;
-    }
-  }
   e = hipMemcpy(md->lv, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
@@ -897,16 +867,62 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
   hipFree(stn);
   if (e != hipSuccess) {
     model_release(md);
-    return hip_fail(e, "kl_interp_os_build");
+    return hip_fail(e, name);
   }
   for (int64_t r = 0; r < rows * 9; ++r)
     if (sth[(size_t)r] != 0) {
       model_release(md);
-      return fail(STOMSFEM_ENOTSPD, "kl_interp_os_build: a cell problem at a node failed");
+      return fail(STOMSFEM_ENOTSPD, std::string(name) + ": a cell problem at a node failed");
     }
   md->lv_max = K;
-  *model = md;
   return STOMSFEM_OK;
+}
+
+static stomsfem_model* os_kl_model(int kind, int ncx, int ncy, int m, int o, double box, int64_t rows) {
+  auto* md = new stomsfem_model();
+  md->kind = kind;
+  hipGetDevice(&md->device);
+  md->ncx = ncx;
+  md->ncy = ncy;
+  md->m = m;
+  md->os_o = o;
+  md->lo = -box;
+  md->hi = box;
+  md->rows = rows;
+  return md;
+}
+
+int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K,
+                                const double* mu, const double* modes, int32_t nnodes, double box,
+                                stomsfem_model** model, void* stream) {
+  if (!model) return fail(STOMSFEM_EINVAL, "kl_interp_os_build: NULL model");
+  *model = nullptr;
+  const int o = oversample, P = m + 2 * oversample;
+  if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m ||
+      K < 1 || K > RI_KMAX || nnodes < RI_NN_MIN || nnodes > RI_NN_MAX || !(box > 0))
+    return fail(STOMSFEM_EINVAL,
+                "kl_interp_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
+                "domain, "
+                "1 <= K <= 4, 2 <= nnodes <= 9, box > 0");
+  if (!device_ptr(mu) || !device_ptr(modes))
+    return fail(STOMSFEM_EINVAL, "kl_interp_os_build: mu and modes on device");
+  int64_t rows = 1;
+  for (int i = 0; i < K; ++i) rows *= nnodes;
+  auto* md = os_kl_model(7, ncx, ncy, m, o, box, rows);
+  md->nn = nnodes;
+  // tensor Lobatto nodes, variable 0 slowest
+  std::vector<double> xh((size_t)rows * K);
+  for (int64_t r = 0; r < rows; ++r) {
+    int64_t c = r;
+    for (int v = K - 1; v >= 0; --v) {
+      const int d = (int)(c % nnodes);
+      c /= nnodes;
+      xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)d / (double)(nnodes - 1)) + 1.0) * box;
+    }
+  }
+  const int rc = os_kl_model_finish(md, K, xh, mu, modes, (hipStream_t)stream, "kl_interp_os_build");
+  if (rc == STOMSFEM_OK) *model = md;
+  return rc;
 }
 
 int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversample, int32_t K, const double* mu,
@@ -920,73 +936,37 @@ int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversa
                 "kl_sgi_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
                 "domain, 1 <= K <= 4, 0 <= level <= 5, box > 0");
   if (!device_ptr(mu) || !device_ptr(modes)) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: mu and modes on device");
-  const int Mc = ncx * ncy;
-  if (Mc > 65535) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: at most 65535 coarse elements");
+  if (ncx * ncy > 65535) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: at most 65535 coarse elements");
   SgiComb C;
   sgi_combination(level, C);
   if (C.missing) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: a tensor node of the combination is not a grid node");
   const int64_t rows = C.npts[K];
-  hipStream_t st = (hipStream_t)stream;
-  auto* md = new stomsfem_model();
-  md->kind = 8;
-  hipGetDevice(&md->device);
-  md->ncx = ncx;
-  md->ncy = ncy;
-  md->m = m;
-  md->os_o = o;
-  md->lo = -box;
-  md->hi = box;
-  md->rows = rows;
+  auto* md = os_kl_model(8, ncx, ncy, m, o, box, rows);
   md->sc_level = level;
   md->sg_nb = (int32_t)C.nodes.size();
   md->sg_kmax = K;
   std::memcpy(md->sg_lofs, C.lofs, sizeof(C.lofs));
   std::memcpy(md->sg_rofs, C.rofs, sizeof(C.rofs));
-  md->chunk = std::max<int64_t>(64, std::min<int64_t>(16384, (int64_t{1} << 22) / (9 * (int64_t)m * m)));
-  hipError_t e = hipSuccess;
-  auto A = [&](void** ptr, size_t bytes) {
-    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
-  };
-  double* xin = nullptr;
-  double* nblk = nullptr;
-  int32_t* stn = nullptr;
-  A((void**)&md->lv, sizeof(int32_t) * Mc * RI_KMAX);
-  A((void**)&md->nlv, sizeof(int32_t) * Mc);
-  A((void**)&md->off, sizeof(int64_t) * (Mc + 1));
-  A((void**)&md->table, sizeof(double) * (size_t)rows * 9 * 16);
-  A((void**)&md->counter, sizeof(unsigned long long));
-  A((void**)&md->blk, sizeof(double) * (size_t)md->chunk * 9 * m * m);
-  A((void**)&md->Sc, sizeof(double) * (size_t)md->chunk * 9 * 16);
-  A((void**)&md->stc, sizeof(int32_t) * (size_t)md->chunk * 9);
-  A((void**)&md->cb_coef, sizeof(double) * C.cc.size());
-  A((void**)&md->cb_boff, sizeof(uint32_t) * C.cbo.size());
-  A((void**)&md->cb_rows, sizeof(int32_t) * C.rows_all.size());
-  A((void**)&md->sg_nodes, sizeof(double) * C.nodes.size());
-  A((void**)&xin, sizeof(double) * (size_t)rows * K);
-  A((void**)&nblk, sizeof(double) * (size_t)rows * P * P);
-  A((void**)&stn, sizeof(int32_t) * (size_t)rows * 9);
+  hipError_t e = hipMalloc((void**)&md->cb_coef, sizeof(double) * C.cc.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&md->cb_boff, sizeof(uint32_t) * C.cbo.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&md->cb_rows, sizeof(int32_t) * C.rows_all.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&md->sg_nodes, sizeof(double) * C.nodes.size());
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    hipFree(xin);
-    hipFree(nblk);
-    hipFree(stn);
     model_release(md);
     return fail(STOMSFEM_ENOMEM, "kl_sgi_os_build: device allocation failed");
   }
-  auto cls = [&](int k) {
-    const int nf = ncx * m;
-    int x0 = k * m - o;
-    if (x0 > nf - P) x0 = nf - P;
-    if (x0 < 0) x0 = 0;
-    return (k * m - x0) / o;
-  };
-  std::vector<int32_t> lv((size_t)Mc * RI_KMAX, -1), nlv(Mc, K);
-  std::vector<int64_t> off(Mc + 1, 0);
-  for (int p = 0; p < Mc; ++p) {
-    for (int k = 0; k < K; ++k) lv[(size_t)p * RI_KMAX + k] = p * K + k;
-    off[p] = (int64_t)(cls(p / ncx) * 3 + cls(p % ncx)) * rows;
+  e = hipMemcpy(md->cb_coef, C.cc.data(), sizeof(double) * C.cc.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->cb_boff, C.cbo.data(), sizeof(uint32_t) * C.cbo.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->cb_rows, C.rows_all.data(), sizeof(int32_t) * C.rows_all.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(md->sg_nodes, C.nodes.data(), sizeof(double) * C.nodes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "kl_sgi_os_build");
   }
-  off[Mc] = 9 * rows;
   // grid nodes: Chebyshev-Lobatto points of the finest level, by digit
   std::vector<double> xh((size_t)rows * K);
   for (int64_t r = 0; r < rows; ++r)
@@ -994,36 +974,9 @@ int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversa
       const int32_t c = C.gdig[K][r * K + v];
       xh[(size_t)r * K + v] = -box + (std::cos(M_PI * (double)c / (double)C.D) + 1.0) * box;
     }
-  e = hipMemcpy(md->lv, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(md->nlv, nlv.data(), sizeof(int32_t) * Mc, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(md->off, off.data(), sizeof(int64_t) * (Mc + 1), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(md->cb_coef, C.cc.data(), sizeof(double) * C.cc.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(md->cb_boff, C.cbo.data(), sizeof(uint32_t) * C.cbo.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(md->cb_rows, C.rows_all.data(), sizeof(int32_t) * C.rows_all.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(md->sg_nodes, C.nodes.data(), sizeof(double) * C.nodes.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(xin, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = os_class_tables(md, rows, K, xin, mu, modes, nblk, stn, st);
-  std::vector<int32_t> sth((size_t)rows * 9);
-  if (e == hipSuccess) e = hipMemcpyAsync(sth.data(), stn, sizeof(int32_t) * rows * 9, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(xin);
-  hipFree(nblk);
-  hipFree(stn);
-  if (e != hipSuccess) {
-    model_release(md);
-    return hip_fail(e, "kl_sgi_os_build");
-  }
-  for (int64_t r = 0; r < rows * 9; ++r)
-    if (sth[(size_t)r] != 0) {
-      model_release(md);
-      return fail(STOMSFEM_ENOTSPD, "kl_sgi_os_build: a cell problem at a node failed");
-    }
-  md->lv_max = K;
-  *model = md;
-  return STOMSFEM_OK;
+  const int rc = os_kl_model_finish(md, K, xh, mu, modes, (hipStream_t)stream, "kl_sgi_os_build");
+  if (rc == STOMSFEM_OK) *model = md;
+  return rc;
 }
 
 int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const double* kappa, int64_t nsamples,
