@@ -331,3 +331,29 @@ def test_oversampled_interpolation_at_the_workload_scale_sampled(sm):
     err = (np.abs(S - S_ref).max(axis=2) / np.abs(S_ref).max(axis=2)).max()
     say(f"  {int(fb.sum())} fallback pairs in the sampled samples, S rel err {err:.2e}")
     assert err < 1e-10
+
+
+@pytest.mark.parametrize("level", [None, 2])
+def test_oversampled_interpolation_nan_parameter_falls_back(sm, level):
+    # a NaN parameter is outside the box: that pair (and only that pair)
+    # takes the oversampled solve of the sample's own field, for the tensor
+    # and the sparse-grid tables
+    nc, m, o, K, N = 4, 8, 4, 3, 2
+    P, nf = m + 2 * o, nc * m
+    z, u = W.spectral_draws(N, 64, 2200)
+    kap, beta = sm.coef_gauss(torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda(), nf, 1.0, 1.0 / 8, with_beta=True)
+    mu, V, _ = sm.local_kl(P, 1.0 / nf, 1.0, 1.0 / 8, K)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    xi, out, _ = sm.kl_project(beta, nc, m, mu_d, V_d, 6.0, oversample=o)
+    assert int(out.sum()) == 0
+    xi[1, 6, 1] = float("nan")
+    model = sm.kl_interp_build(nc, nc, m, mu_d, V_d, 3, 6.0, oversample=o, level=level)
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S, nfb = sm.kl_interp_apply(model, xi, kap, status=st)
+    S_os = sm.upscale_os(kap, nc, nc, m, o)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert nfb == 1 and st[1, 6] == 1 and int((st != 0).sum()) == 1
+    ref = S_os[1, 6].cpu().numpy()
+    np.testing.assert_allclose(S[1, 6].cpu().numpy(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    assert np.isfinite(S.cpu().numpy()).all()
