@@ -363,7 +363,7 @@ def measure_oversampling(log, N=16384):
 
 def measure_collocation(log, wl=None, level=4, errors=True, plain_chunk=1024):
     """Sparse-grid stochastic collocation with search-and-plug-in
-    dictionaries (Sec. 3.3, global SC methods; Sec. 5.1, second experiment)
+    dictionaries (Sec. 4.1.2, global SC methods; Sec. 5.2)
     on a bump-family mesh (default 8x8, H/h = 8, 16 uniform variables), the
     level-`level` Smolyak Clenshaw-Curtis grid: offline dictionaries, then
     the online stage for every collocation point (search and plug-in, coarse

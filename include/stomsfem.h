@@ -30,6 +30,17 @@
  *    returns STOMSFEM_EHIP; faults inside kernels surface at the caller's next
  *    synchronising call.  stomsfem_last_error() gives a thread-local message.
  *  - Calls never print and never abort the process.
+ *  - Ordering of shared scratch memory.  Entry points that use the
+ *    library-owned workspace of a device (the coarse solves, the fine solve,
+ *    the refined FP32 upscaling, the collocation quadrature) order themselves:
+ *    each makes its stream wait for the previous such call's work (an event
+ *    recorded on that call's stream) before queueing its own, so calls on
+ *    different streams never use the workspace at the same time.  The same
+ *    holds for the scratch buffers of one model (fallback lists and chunk
+ *    buffers): every call that takes a model orders itself after the
+ *    previous call on that model.  Streams under graph capture skip this
+ *    ordering; graphs that capture such calls on several streams must order
+ *    them themselves.
  */
 #ifndef STOMSFEM_H
 #define STOMSFEM_H
@@ -57,7 +68,9 @@ enum {
   STOMSFEM_PREC_F64 = 0,           /* FP64 factorisation and energies */
   STOMSFEM_PREC_F32_REFINE64 = 1,  /* FP32 arithmetic where the entry point allows it, FP64 residuals/energies */
   STOMSFEM_PREC_BF16 = 2,          /* BF16 matrix-core products with FP32 accumulation (surrogate) */
-  STOMSFEM_PREC_AUTO = 3           /* stomsfem_upscale: the autotuner's choice for (m, a_dtype), else FP64 */
+  STOMSFEM_PREC_AUTO = 3,          /* stomsfem_upscale: the autotuner's choice for (m, a_dtype), else FP64 */
+  STOMSFEM_PREC_F32 = 4            /* plain FP32 arithmetic, no refinement: the reduced basis's matrix-core
+                                      stage and the surrogate's FP32 reference */
 };
 
 /* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
@@ -314,7 +327,7 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * stomsfem_reduce_apply (online, Algorithm 4): S_rb for every pair of
  * `batch` (same ncx, ncy, m as the training batch):
  *   [A, Fh, B] = a_K^T G_K,   S_ll' = B_ll' - Fh_l . A^{-1} Fh_l'
- * precision STOMSFEM_PREC_F32_REFINE64 (the default online stage, m = 8):
+ * precision STOMSFEM_PREC_F32 (the default online stage):
  * FP32 MFMA GEMM with FP32 accumulation, FP64 r x r solve;
  * STOMSFEM_PREC_F64: FP64 throughout (reference).  Per-pair status ENOTSPD
  * if the r x r system is not positive definite.  Asynchronous.
@@ -412,9 +425,29 @@ int stomsfem_mlp_standardization(const stomsfem_model* model, double* mu_host, d
 
 /* Raw network outputs Y device [nsamples][M][20] for xi device
  * [nsamples][nxi]; precision STOMSFEM_PREC_BF16 (matrix cores) or
- * STOMSFEM_PREC_F32_REFINE64 (FP32 reference). */
+ * STOMSFEM_PREC_F32 (FP32 reference). */
 int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
                          int32_t precision, void* stream);
+
+/* The surrogate's gate (the residual/uncertainty gate that decides between
+ * the network and the plain local solve; the counterpart of the out-of-range
+ * fallback in the remark after Algorithm 2, Sec. 3.1) applied to given raw
+ * network outputs, with the same device code the surrogate path runs after
+ * its forward pass.  Y device float [nsamples][M][20]: two heads of the 10
+ * standardised entries; xi device [nsamples][nxi], read only for the box test
+ * of the patch's local variables.  Per pair, with S_A and S_B the
+ * de-standardised heads and S = (S_A + S_B)/2:
+ *   residual    = max_l |sum_l' S_ll'| / max|S|,
+ *   uncertainty = max|S_A - S_B| / max|S|;
+ * accepted iff all 20 de-standardised values are finite, max|S| > 0, both
+ * signals are <= gate_tol and every local variable lies in the model's box.
+ * Outputs: S device [nsamples][M][10] = P S P (P = I - 1 1^T/4) where
+ * accepted, S elsewhere; status device int32 [nsamples][M] (0 accepted,
+ * 1 rejected) or NULL; gate device [nsamples][M][2] (residual, uncertainty;
+ * NaN when a de-standardised value is not finite) or NULL.  No audit and no
+ * fallback solve.  Asynchronous. */
+int stomsfem_mlp_gate(const stomsfem_model* model, const float* Y, const double* xi, int32_t nxi, int64_t nsamples,
+                      double gate_tol, double* S, int32_t* status, double* gate, void* stream);
 
 /* Surrogate upscaling with gate and plain fallback: S device
  * [nsamples][M][10]; status device [nsamples][M] or NULL: 0 = surrogate
@@ -461,9 +494,9 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
 
 /* ------------------------------------------------------------------------
  * Sparse-grid stochastic collocation with search-and-plug-in dictionaries
- * (Sec. 3.3, global SC methods: eq. sparseintegration, the variance formula
- * after it, eqs. SCofflinecost and SConlinecost; Sec. 5.1, second
- * experiment).  The random variables are independent and uniform on a box.
+ * (Sec. 4.1.2, global SC methods: eq. sparseintegration, the variance formula
+ * after it, eqs. SCofflinecost and SConlinecost; the collocation
+ * experiment of Sec. 5.2).  The random variables are independent and uniform on a box.
  *
  * stomsfem_sparse_grid (host only, needs no GPU): the Smolyak sparse grid
  * of level `level` (0..8) in `dim` variables built from the nested
@@ -514,7 +547,7 @@ int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32
 
 /* ------------------------------------------------------------------------
  * Sparse-grid interpolation of the upscaled stiffness in the local variables
- * (Sec. 3.1 with the sparse node sets of Sec. 3.3 and Sec. 5.3).
+ * (Sec. 3.1 with the sparse node sets of Sec. 4.1.2 and Sec. 5.3).
  *
  * stomsfem_sgi_build (offline): for every patch K with k_K <= 4 local
  * variables (local_vars host [M][4] as for stomsfem_interp_build), S_K at the

@@ -1,6 +1,6 @@
 """Global sparse-grid stochastic collocation with search-and-plug-in
-dictionaries (Sec. 3.3, global SC methods: eqs. sparseintegration,
-SCofflinecost, SConlinecost; Sec. 5.1, the second experiment).  Test
+dictionaries (Sec. 4.1.2, global SC methods: eqs. sparseintegration,
+SCofflinecost, SConlinecost; Sec. 5.2).  Test
 infrastructure only (see package doc).
 
 Quadrature.  The random variables are independent and uniform on the box
@@ -163,7 +163,7 @@ def sc_direct(nc: int, m: int, fam: dict, digits: np.ndarray, level: int, lo: fl
 
 # ---------------------------------------------------------------------------
 # Sparse-grid interpolation of S_K in the local variables (Sec. 3.1 with the
-# sparse node sets of Sec. 3.3 and Sec. 5.3): Smolyak's combination of tensor
+# sparse node sets of Sec. 4.1.2 and Sec. 5.3): Smolyak's combination of tensor
 # Lagrange interpolants on the nested Clenshaw-Curtis nodes,
 #   I(L, k) f = sum over the terms of A(L, k) of c_i (U_i1 x ... x U_ik) f,
 # U_i the one-dimensional Lagrange interpolant through the level-i nodes

@@ -77,37 +77,106 @@ int hip_fail(hipError_t e, const char* where) {
 struct Workspace {
   void* ptr = nullptr;
   size_t bytes = 0;
+  std::mutex lease;              // held by the call that uses the workspace
+  hipEvent_t done = nullptr;     // recorded on the last user's stream when its call ended
 };
 std::mutex g_ws_mutex;
 std::unordered_map<int, Workspace> g_ws;
 
-// Returns a device buffer of at least `bytes` on the current device, growing
-// the library workspace when needed (the growth is a synchronous hipMalloc).
-int workspace_get(size_t bytes, void** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  std::lock_guard<std::mutex> lk(g_ws_mutex);
-  Workspace& w = g_ws[dev];
-  if (w.bytes < bytes) {
-    if (w.ptr) {
-      e = hipDeviceSynchronize();
-      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-      hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.bytes = 0;
-    }
-    e = hipMalloc(&w.ptr, bytes);
-    if (e != hipSuccess) {
-      w.ptr = nullptr;
-      (void)hipGetLastError();
-      return fail(STOMSFEM_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    w.bytes = bytes;
+// Grows w to at least `bytes` (the caller holds w.lease).  Growth frees the
+// old buffer after a device synchronisation and is a synchronous hipMalloc.
+int workspace_grow(Workspace& w, size_t bytes) {
+  if (w.bytes >= bytes) return STOMSFEM_OK;
+  hipError_t e;
+  if (w.ptr) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
   }
-  *out = w.ptr;
+  e = hipMalloc(&w.ptr, bytes);
+  if (e != hipSuccess) {
+    w.ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(STOMSFEM_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  w.bytes = bytes;
   return STOMSFEM_OK;
 }
+
+Workspace* workspace_of_current_device(int* rc) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *rc = hip_fail(e, "hipGetDevice");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  *rc = STOMSFEM_OK;
+  return &g_ws[dev];  // nodes of an unordered_map never move
+}
+
+// Orders the calls that share one piece of scratch memory.  While an
+// OrderedUse lives, no other call holds the same mutex; its stream first
+// waits for the work queued by the previous holder (the event that holder
+// recorded on its own stream), and it records that event on its stream when
+// it ends.  Calls on different streams therefore use the memory one after the
+// other on the device instead of at the same time.  A stream under graph
+// capture skips the event (a captured graph orders its own work).
+class OrderedUse {
+ public:
+  OrderedUse() = default;
+  OrderedUse(const OrderedUse&) = delete;
+  OrderedUse& operator=(const OrderedUse&) = delete;
+  int begin(std::mutex& mu, hipEvent_t& ev, hipStream_t st) {
+    lk_ = std::unique_lock<std::mutex>(mu);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+      (void)hipGetLastError();
+      cs = hipStreamCaptureStatusNone;
+    }
+    if (cs != hipStreamCaptureStatusNone) return STOMSFEM_OK;
+    hipError_t e = hipSuccess;
+    if (!ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    else e = hipStreamWaitEvent(st, ev, 0);
+    if (e != hipSuccess) {
+      lk_.unlock();
+      return hip_fail(e, "stream ordering of shared scratch memory");
+    }
+    ev_ = &ev;
+    st_ = st;
+    return STOMSFEM_OK;
+  }
+  ~OrderedUse() {
+    if (ev_ && *ev_) (void)hipEventRecord(*ev_, st_);
+  }
+
+ private:
+  std::unique_lock<std::mutex> lk_;
+  hipEvent_t* ev_ = nullptr;
+  hipStream_t st_ = nullptr;
+};
+
+// The library workspace of the current device for one call, ordered against
+// every other call that uses it (OrderedUse).
+class WorkspaceLease {
+ public:
+  int acquire(size_t bytes, hipStream_t st, void** out) {
+    int rc = STOMSFEM_OK;
+    Workspace* w = workspace_of_current_device(&rc);
+    if (!w) return rc;
+    rc = use_.begin(w->lease, w->done, st);
+    if (rc != STOMSFEM_OK) return rc;
+    rc = workspace_grow(*w, bytes);
+    if (rc != STOMSFEM_OK) return rc;
+    *out = w->ptr;
+    return STOMSFEM_OK;
+  }
+
+ private:
+  OrderedUse use_;
+};
 
 // True when p is device (or managed) memory visible to the current device.
 bool device_ptr(const void* p) {
@@ -254,6 +323,9 @@ struct stomsfem_model {
   // KL interpolation (kind 6; kind 7 = of the oversampled Petrov-Galerkin
   // stiffness: nine class tables of 16 entries, os_o cells of oversampling)
   int32_t os_o = 0;
+  // ordering of the calls that use the model's scratch buffers (OrderedUse)
+  std::mutex order_mu;
+  hipEvent_t order_ev = nullptr;
 };
 
 namespace {
@@ -293,6 +365,7 @@ void model_release(stomsfem_model* md) {
   hipFree(md->cb_boff);
   hipFree(md->cb_rows);
   hipFree(md->sg_nodes);
+  if (md->order_ev) hipEventDestroy(md->order_ev);
   hipSetDevice(cur);
   delete md;
 }
@@ -353,7 +426,8 @@ static int upscale_refined(const stomsfem_batch& b, hipStream_t st) {
   const size_t off_stc = off_Sc + align256(sizeof(double) * 10 * (size_t)chunk);
   const size_t total = off_stc + align256(sizeof(int32_t) * (size_t)chunk);
   void* ws = nullptr;
-  int rc = workspace_get(total, &ws);
+  WorkspaceLease lease;
+  int rc = lease.acquire(total, st, &ws);
   if (rc != STOMSFEM_OK) return rc;
   char* base = (char*)ws;
   auto* counter = (unsigned long long*)base;
@@ -455,8 +529,10 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
     return fail(STOMSFEM_EINVAL, "coarse_solve: qoi outputs must be device pointers");
   if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "coarse_solve: status must be a device pointer");
   void* work = nullptr;
+  WorkspaceLease lease;
   if (nsamples > 0) {
-    int rc = workspace_get(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), &work);
+    int rc = lease.acquire(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), (hipStream_t)stream,
+                           &work);
     if (rc != STOMSFEM_OK) return rc;
   }
   hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
@@ -477,11 +553,12 @@ int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double
   const size_t s_doubles = (size_t)chunk * per * 10;
   const size_t w_doubles = (size_t)coarse_work_doubles(nfine, nfine, chunk);
   void* ws = nullptr;
-  int rc = workspace_get(sizeof(double) * (s_doubles + w_doubles), &ws);
+  hipStream_t st = (hipStream_t)stream;
+  WorkspaceLease lease;
+  int rc = lease.acquire(sizeof(double) * (s_doubles + w_doubles), st, &ws);
   if (rc != STOMSFEM_OK) return rc;
   double* Sbuf = (double*)ws;
   double* work = Sbuf + s_doubles;
-  hipStream_t st = (hipStream_t)stream;
   for (int64_t start = 0; start < nsamples; start += chunk) {
     const int64_t cnt = std::min(chunk, nsamples - start);
     UpArgs up{};
@@ -991,6 +1068,8 @@ int stomsfem_kl_interp_apply(stomsfem_model* model, const double* xi, const doub
     return fail(STOMSFEM_EINVAL, "kl_interp_apply: arrays must be device pointers");
   const int Mc = model->ncx * model->ncy, K = model->lv_max;
   hipStream_t st = (hipStream_t)stream;
+  OrderedUse order;  // the model's scratch buffers
+  if (int orc = order.begin(model->order_mu, model->order_ev, st); orc != STOMSFEM_OK) return orc;
   const int64_t need = nsamples * Mc;
   if (model->list_cap < need) {
     hipError_t e = hipStreamSynchronize(st);
@@ -1143,8 +1222,10 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
     return fail(STOMSFEM_EINVAL, "coarse_solve_pg: qoi outputs must be device pointers");
   if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "coarse_solve_pg: status must be a device pointer");
   void* work = nullptr;
+  WorkspaceLease lease;
   if (nsamples > 0) {
-    int rc = workspace_get(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), &work);
+    int rc = lease.acquire(sizeof(double) * (size_t)coarse_work_doubles(ncx, ncy, nsamples), (hipStream_t)stream,
+                           &work);
     if (rc != STOMSFEM_OK) return rc;
   }
   hipError_t e = launch_coarse_pg(ncx, ncy, nsamples, S16, load, U, qoi_mean, qoi_var, status, (double*)work,
@@ -1240,8 +1321,8 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
   if (rc != STOMSFEM_OK) return rc;
   if (batch->ncx != model->ncx || batch->ncy != model->ncy || batch->m != model->m)
     return fail(STOMSFEM_EINVAL, "reduce_apply: batch mesh differs from the model's");
-  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64)
-    return fail(STOMSFEM_EINVAL, "reduce_apply: bad precision");
+  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32)
+    return fail(STOMSFEM_EINVAL, "reduce_apply: precision must be STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32");
   const bool f64 = precision == STOMSFEM_PREC_F64;
   if (!f64 && model->m != 8) return fail(STOMSFEM_EINVAL, "reduce_apply: the MFMA online stage needs m = 8");
   if (batch->nsamples == 0) return STOMSFEM_OK;
@@ -1414,6 +1495,8 @@ int stomsfem_mlp_train(stomsfem_model* model, int32_t steps, float lr, const int
   if (perm && !device_ptr(perm)) return fail(STOMSFEM_EINVAL, "mlp_train: perm must be a device pointer");
   if (loss && !device_ptr(loss)) return fail(STOMSFEM_EINVAL, "mlp_train: loss must be a device pointer");
   if (steps == 0) return STOMSFEM_OK;
+  OrderedUse order;  // parameters and moments
+  if (int orc = order.begin(model->order_mu, model->order_ev, (hipStream_t)stream); orc != STOMSFEM_OK) return orc;
   MlpTrainArgs t{};
   t.npatch = model->ncx * model->ncy;
   t.ntrain = model->ntrain;
@@ -1476,14 +1559,16 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "surrogate: not a surrogate model");
   if (nsamples < 0 || nxi < 1) return fail(STOMSFEM_EINVAL, "surrogate: bad sizes");
   if (model->lv_max >= nxi) return fail(STOMSFEM_EINVAL, "surrogate: nxi smaller than the local variable indices");
-  if (precision != STOMSFEM_PREC_F32_REFINE64 && precision != STOMSFEM_PREC_BF16)
-    return fail(STOMSFEM_EINVAL, "surrogate: precision must be STOMSFEM_PREC_F32_REFINE64 (FP32) or STOMSFEM_PREC_BF16");
+  if (precision != STOMSFEM_PREC_F32 && precision != STOMSFEM_PREC_BF16)
+    return fail(STOMSFEM_EINVAL, "surrogate: precision must be STOMSFEM_PREC_F32 or STOMSFEM_PREC_BF16");
   if (nsamples == 0) return STOMSFEM_OK;
   if (!device_ptr(xi)) return fail(STOMSFEM_EINVAL, "surrogate: xi must be a device pointer");
   if ((Y && !device_ptr(Y)) || (S && !device_ptr(S)) || (status && !device_ptr(status)) ||
       (stats && !device_ptr(stats)))
     return fail(STOMSFEM_EINVAL, "surrogate: outputs must be device pointers");
   const int Mc = model->ncx * model->ncy;
+  OrderedUse order;  // the model's scratch buffers (fallback list, counter, chunk buffers)
+  if (int orc = order.begin(model->order_mu, model->order_ev, (hipStream_t)stream); orc != STOMSFEM_OK) return orc;
   if (S) {
     if (model->fam.g < 1 || model->fam.g * model->fam.g > nxi)
       return fail(STOMSFEM_EINVAL, "surrogate: the model's coefficient family does not match xi");
@@ -1569,6 +1654,35 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
                                      (unsigned long long*)stats, st);
   }
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "surrogate fallback launch");
+}
+
+int stomsfem_mlp_gate(const stomsfem_model* model, const float* Y, const double* xi, int32_t nxi, int64_t nsamples,
+                      double gate_tol, double* S, int32_t* status, double* gate, void* stream) {
+  if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "mlp_gate: not a surrogate model");
+  if (nsamples < 0 || nxi < 1) return fail(STOMSFEM_EINVAL, "mlp_gate: bad sizes");
+  if (model->lv_max >= nxi) return fail(STOMSFEM_EINVAL, "mlp_gate: nxi smaller than the local variable indices");
+  if (!(gate_tol >= 0)) return fail(STOMSFEM_EINVAL, "mlp_gate: gate_tol must be >= 0");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(Y) || !device_ptr(xi) || !device_ptr(S))
+    return fail(STOMSFEM_EINVAL, "mlp_gate: Y, xi and S must be device pointers");
+  if ((status && !device_ptr(status)) || (gate && !device_ptr(gate)))
+    return fail(STOMSFEM_EINVAL, "mlp_gate: status and gate must be device pointers");
+  MlpInferArgs a{};
+  a.npatch = model->ncx * model->ncy;
+  a.ncx = model->ncx;
+  a.nxi = nxi;
+  a.nsamples = nsamples;
+  a.lv = model->lv;
+  a.mu = model->mu;
+  a.sd = model->sd;
+  a.xi = xi;
+  a.box = model->box;
+  a.tau = gate_tol;
+  a.S = S;
+  a.status = status;
+  a.gate = gate;
+  hipError_t e = launch_mlp_gate(a, Y, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "mlp_gate launch");
 }
 
 int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
@@ -1762,6 +1876,8 @@ int stomsfem_interp_apply(stomsfem_model* model, const double* xi, int32_t nxi, 
   if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "interp_apply: status must be a device pointer");
   const int Mc = model->ncx * model->ncy;
   hipStream_t st = (hipStream_t)stream;
+  OrderedUse order;  // the model's scratch buffers
+  if (int orc = order.begin(model->order_mu, model->order_ev, st); orc != STOMSFEM_OK) return orc;
   const int64_t need = nsamples * Mc;
   if (model->list_cap < need) {
     hipError_t e = hipStreamSynchronize(st);
@@ -2015,7 +2131,8 @@ int stomsfem_quadrature(const double* U, const double* w, int64_t npoints, int32
   if ((mean && !device_ptr(mean)) || (var && !device_ptr(var)))
     return fail(STOMSFEM_EINVAL, "quadrature: mean and var must be device pointers");
   void* work = nullptr;
-  int rc = workspace_get(sizeof(double) * (size_t)sc_quad_work_doubles(npoints, nu), &work);
+  WorkspaceLease lease;
+  int rc = lease.acquire(sizeof(double) * (size_t)sc_quad_work_doubles(npoints, nu), (hipStream_t)stream, &work);
   if (rc != STOMSFEM_OK) return rc;
   hipError_t e = launch_sc_quadrature(U, w, npoints, nu, mean, var, (double*)work, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "quadrature launch");
@@ -2141,6 +2258,8 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
   const int Mc = model->ncx * model->ncy;
   if (Mc > 65535) return fail(STOMSFEM_EINVAL, "sgi_apply: at most 65535 coarse elements");
   hipStream_t st = (hipStream_t)stream;
+  OrderedUse order;  // the model's scratch buffers
+  if (int orc = order.begin(model->order_mu, model->order_ev, st); orc != STOMSFEM_OK) return orc;
   const int64_t need = nsamples * Mc;
   if (model->list_cap < need) {
     hipError_t e = hipStreamSynchronize(st);
@@ -2549,21 +2668,25 @@ int stomsfem_model_load(const char* path, stomsfem_model** model) {
 
 int stomsfem_workspace_reserve(int64_t bytes) {
   if (bytes < 0) return fail(STOMSFEM_EINVAL, "workspace_reserve: bytes < 0");
-  void* p = nullptr;
-  return bytes == 0 ? STOMSFEM_OK : workspace_get((size_t)bytes, &p);
+  if (bytes == 0) return STOMSFEM_OK;
+  int rc = STOMSFEM_OK;
+  Workspace* w = workspace_of_current_device(&rc);
+  if (!w) return rc;
+  std::lock_guard<std::mutex> lk(w->lease);
+  return workspace_grow(*w, (size_t)bytes);
 }
 
 int stomsfem_workspace_release(void) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  std::lock_guard<std::mutex> lk(g_ws_mutex);
-  auto it = g_ws.find(dev);
-  if (it != g_ws.end() && it->second.ptr) {
-    e = hipDeviceSynchronize();
+  int rc = STOMSFEM_OK;
+  Workspace* w = workspace_of_current_device(&rc);
+  if (!w) return rc;
+  std::lock_guard<std::mutex> lk(w->lease);
+  if (w->ptr) {
+    hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    hipFree(it->second.ptr);
-    g_ws.erase(it);
+    hipFree(w->ptr);
+    w->ptr = nullptr;
+    w->bytes = 0;
   }
   return STOMSFEM_OK;
 }

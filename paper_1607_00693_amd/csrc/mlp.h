@@ -72,11 +72,15 @@ struct MlpInferArgs {
   int32_t bump_g;
   double bump_rho, bump_eps, bump_base, bump_amp, bump_beta;
   int32_t m;            // fine cells per patch side; the fused fallback serves m = 8
+  double* gate;         // [nsamples][M][2] residual and uncertainty of the gate, or NULL
 };
 
 hipError_t launch_mlp_train(const MlpTrainArgs& a, bool train, hipStream_t st);
 hipError_t launch_mlp_data(const MlpDataArgs& d, hipStream_t st);
 hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st);
+// The gate alone on given raw outputs Y [nsamples][M][20] (a.S, a.status,
+// a.gate written; no audit, no fallback).
+hipError_t launch_mlp_gate(const MlpInferArgs& a, const float* Y, hipStream_t st);
 // Second half of the plain fallback for m != 8: the listed pairs' plain S
 // (Sc, stc, computed by the regular kernels on regenerated coefficients) is
 // compared with the prediction in S, stored, and counted as the fused

@@ -280,16 +280,23 @@ hipError_t launch_mlp_data(const MlpDataArgs& d, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Inference and gate
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gate_and_store(const MlpInferArgs& a, int K, int64_t s, const float* y, double* Sout,
-                                               int32_t* st, bool* fallback) {
-  const double* mu = a.mu + K * 10;
-  const double* sd = a.sd + K * 10;
+// The gate of one pair from its 20 raw outputs y (heads A and B): writes the
+// stored S (P S P if accepted, else the head mean), the residual and the
+// uncertainty, and returns acceptance.  A pair is accepted only if all 20
+// de-standardised values are finite, max|S| > 0, both signals are <= tau and
+// every local variable is inside the box; with a non-finite value the two
+// signals are NaN (comparisons are written so that NaN never passes).
+__device__ __forceinline__ bool gate_pair(const double* __restrict__ mu, const double* __restrict__ sd,
+                                          const float* y, bool inbox, double tau, double* Sout, double* resid_out,
+                                          double* unc_out) {
   double SA[10], SB[10], S[10];
   double scale = 0.0, unc = 0.0;
+  bool finite = true;
 #pragma unroll
   for (int q = 0; q < 10; ++q) {
     SA[q] = mu[q] + sd[q] * (double)y[q];
     SB[q] = mu[q] + sd[q] * (double)y[10 + q];
+    finite = finite && isfinite(SA[q]) && isfinite(SB[q]);
     S[q] = 0.5 * (SA[q] + SB[q]);
     scale = fmax(scale, fabs(S[q]));
     unc = fmax(unc, fabs(SA[q] - SB[q]));
@@ -303,13 +310,8 @@ __device__ __forceinline__ void gate_and_store(const MlpInferArgs& a, int K, int
     rs[i] = (s4[i][0] + s4[i][1]) + (s4[i][2] + s4[i][3]);
     resid = fmax(resid, fabs(rs[i]));
   }
-  bool inbox = true;
-  for (int c = 0; c < MLP_KIN; ++c) {
-    const int j = a.lv[K * MLP_KIN + c];
-    if (j >= 0 && !(fabs(a.xi[s * a.nxi + j]) <= a.box)) inbox = false;
-  }
-  const double tol = a.tau * scale;
-  const bool ok = inbox && resid <= tol && unc <= tol && scale > 0.0;
+  const double tol = tau * scale;
+  const bool ok = finite && inbox && scale > 0.0 && resid <= tol && unc <= tol;
   // P S P with P = I - 1 1^T / 4
   const double tot = (rs[0] + rs[1]) + (rs[2] + rs[3]);
   double pr[4][4];
@@ -321,10 +323,60 @@ __device__ __forceinline__ void gate_and_store(const MlpInferArgs& a, int K, int
                            pr[1][2], pr[1][3], pr[2][2], pr[2][3], pr[3][3]};
 #pragma unroll
   for (int q = 0; q < 10; ++q) Sout[q] = ok ? outv[q] : S[q];
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  *resid_out = finite && scale > 0.0 ? resid / scale : nan;
+  *unc_out = finite && scale > 0.0 ? unc / scale : nan;
+  return ok;
+}
+
+__device__ __forceinline__ bool local_vars_in_box(const MlpInferArgs& a, int K, int64_t s) {
+  bool inbox = true;
+  for (int c = 0; c < MLP_KIN; ++c) {
+    const int j = a.lv[K * MLP_KIN + c];
+    if (j >= 0 && !(fabs(a.xi[s * a.nxi + j]) <= a.box)) inbox = false;
+  }
+  return inbox;
+}
+
+__device__ __forceinline__ void gate_and_store(const MlpInferArgs& a, int K, int64_t s, const float* y, double* Sout,
+                                               int32_t* st, bool* fallback) {
   const int64_t p = s * a.npatch + K;
+  double resid, unc;
+  const bool ok = gate_pair(a.mu + K * 10, a.sd + K * 10, y, local_vars_in_box(a, K, s), a.tau, Sout, &resid, &unc);
+  if (a.gate) {
+    a.gate[2 * p] = resid;
+    a.gate[2 * p + 1] = unc;
+  }
   const bool audit = ok && ((uint64_t)p * 2654435761ull) % 100ull == 0ull;
   if (st) *st = ok ? (audit ? MLP_ST_AUDIT : MLP_ST_ACCEPTED) : MLP_ST_FALLBACK;
   *fallback = !ok || audit;
+}
+
+// The gate alone on given raw outputs Y [nsamples][M][20]: one thread per
+// pair; status 0 = accepted, 1 = rejected (no audit, no fallback).
+__global__ __launch_bounds__(256) void mlp_gate_kernel(MlpInferArgs a, const float* __restrict__ Yin) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.nsamples * a.npatch) return;
+  const int64_t s = p / a.npatch;
+  const int K = (int)(p - s * a.npatch);
+  float y[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) y[o] = Yin[p * NO + o];
+  double resid, unc;
+  const bool ok =
+      gate_pair(a.mu + K * 10, a.sd + K * 10, y, local_vars_in_box(a, K, s), a.tau, a.S + p * 10, &resid, &unc);
+  if (a.gate) {
+    a.gate[2 * p] = resid;
+    a.gate[2 * p + 1] = unc;
+  }
+  if (a.status) a.status[p] = ok ? MLP_ST_ACCEPTED : MLP_ST_FALLBACK;
+}
+
+hipError_t launch_mlp_gate(const MlpInferArgs& a, const float* Y, hipStream_t st) {
+  const int64_t n = a.nsamples * a.npatch;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mlp_gate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, Y);
+  return hipGetLastError();
 }
 
 __device__ __forceinline__ void push_fallback(const MlpInferArgs& a, int64_t p) {

@@ -1,5 +1,5 @@
 // Sparse-grid stochastic collocation with search-and-plug-in dictionaries
-// (Sec. 3.3, global SC methods): host construction of the Smolyak
+// (Sec. 4.1.2, global SC methods): host construction of the Smolyak
 // Clenshaw-Curtis grid, and the device kernels of the online stage.
 #pragma once
 #include <hip/hip_runtime.h>

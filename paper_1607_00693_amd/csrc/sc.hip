@@ -1,5 +1,5 @@
 // Sparse-grid stochastic collocation with search-and-plug-in dictionaries
-// (Sec. 3.3, global SC methods, eqs. sparseintegration, SCofflinecost,
+// (Sec. 4.1.2, global SC methods, eqs. sparseintegration, SCofflinecost,
 // SConlinecost).
 //
 // Host: the Smolyak combination of nested Clenshaw-Curtis rules.  The

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libstomsfem.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EVERSION = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
-PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO = 0, 1, 2, 3
+PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO, PREC_F32 = 0, 1, 2, 3, 4
 MLP_NPARAM = 9940
 MLP_BATCH = 32
 MLP_KIN = 4
@@ -100,6 +100,7 @@ def lib():
         "stomsfem_mlp_params": (C.c_int, [vp, vp, vp, vp]),
         "stomsfem_mlp_standardization": (C.c_int, [vp, vp, vp]),
         "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
+        "stomsfem_mlp_gate": (C.c_int, [vp, vp, vp, i32, i64, dbl, vp, vp, vp, vp]),
         "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
         "stomsfem_feature_map": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -452,7 +453,7 @@ def reduce(a_train: torch.Tensor, ncx: int, ncy: int, m: int, r_max: int = 8, ta
 
 
 def reduce_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,
-                 status: torch.Tensor | None = None, precision: int = PREC_F32_REFINE64, stream=None):
+                 status: torch.Tensor | None = None, precision: int = PREC_F32, stream=None):
     """Online reduced-basis upscaling S[N][M][10] for coefficient samples a."""
     N = a.shape[0]
     if S is None:
@@ -536,6 +537,19 @@ def mlp_predict(model: Model, xi: torch.Tensor, precision: int = PREC_BF16, stre
     _check("stomsfem_mlp_predict", lib().stomsfem_mlp_predict(model.handle, _ptr(xi), xi.shape[1], N, _ptr(Y),
                                                               precision, _stream(stream)))
     return Y
+
+
+def mlp_gate(model: Model, Y: torch.Tensor, xi: torch.Tensor, gate_tol: float = 1e-3, stream=None):
+    """The surrogate's gate on given raw outputs Y[N][M][20]: returns
+    (S[N][M][10], status[N][M] (0 accepted, 1 rejected), gate[N][M][2])."""
+    N = xi.shape[0]
+    M = model.ncx * model.ncy
+    S = torch.empty((N, M, 10), dtype=torch.float64, device=xi.device)
+    status = torch.empty((N, M), dtype=torch.int32, device=xi.device)
+    gate = torch.empty((N, M, 2), dtype=torch.float64, device=xi.device)
+    _check("stomsfem_mlp_gate", lib().stomsfem_mlp_gate(model.handle, _ptr(Y), _ptr(xi), xi.shape[1], N, gate_tol,
+                                                        _ptr(S), _ptr(status), _ptr(gate), _stream(stream)))
+    return S, status, gate
 
 
 def upscale_surrogate(model: Model, xi: torch.Tensor, gate_tol: float = 1e-3, precision: int = PREC_BF16,

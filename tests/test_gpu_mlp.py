@@ -6,7 +6,12 @@ Tolerances: FP32 gradients within 1e-4 of the FP64 oracle relative to the
 largest gradient entry of the patch (single-precision sums of 32 to 64
 terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
 units); BF16 forward (three-term bf16 splitting, FP32 accumulation) within 1e-3
-of FP32.
+of the FP64 oracle's forward pass; the standardisation within 1e-13 of the
+oracle's (FP64 on both sides, different summation orders); an FP32 Adam step
+within 2 float ulps of the FP64 oracle step from the same parameters and
+gradient; the gate on identical raw outputs: accept mask exact, residual and
+uncertainty within 1e-12 relative (both FP64 from the same FP32 outputs), the
+stored S within 1e-10 relative to max|S| of the pair.
 The end-to-end criterion is the coarse solution: surrogate within 1e-3
 (relative, per sample) of the plain FP64 path.
 """
@@ -83,7 +88,7 @@ def test_forward_fp32_and_bf16(sm, trained):
     say("forward FP32 vs oracle, BF16 vs FP32")
     xi = W.uniform_xi(64, wl.nxi, 1004)
     xi_d = torch.from_numpy(xi).cuda()
-    Y32 = sm.mlp_predict(model, xi_d, sm.PREC_F32_REFINE64).cpu().numpy()
+    Y32 = sm.mlp_predict(model, xi_d, sm.PREC_F32).cpu().numpy()
     Y16 = sm.mlp_predict(model, xi_d, sm.PREC_BF16).cpu().numpy()
     params = sm.mlp_params(model).cpu().numpy()
     for K in range(0, wl.M, 5):
@@ -93,6 +98,99 @@ def test_forward_fp32_and_bf16(sm, trained):
     d = np.abs(Y16 - Y32).max()
     say(f"max |Y_bf16 - Y_fp32| = {d:.3e} (standardised units)")
     assert d < 1e-3
+    # the production BF16 kernel against the FP64 oracle directly
+    worst = 0.0
+    for K in range(wl.M):
+        X = np.where(lv[K] >= 0, xi[:, np.maximum(lv[K], 0)], 0.0).astype(np.float32).astype(np.float64)
+        Yref, _ = mlp.forward(params[K].astype(np.float64), X, 4)
+        worst = max(worst, float(np.abs(Y16[:, K] - Yref).max() / max(1.0, np.abs(Yref).max())))
+    say(f"max |Y_bf16 - Y_oracle| = {worst:.3e}")
+    assert worst < 1e-3
+
+
+def test_gate_matches_oracle(sm, trained):
+    # identical raw outputs through the GPU gate and the oracle's gate: the
+    # trained network's own outputs plus planted NaN, +-inf, head
+    # disagreement, row-sum violation and out-of-box local variables
+    from oracle import mlp
+    wl, model, lv, nl = trained["wl"], trained["model"], trained["lv"], trained["nl"]
+    N = 256
+    say(f"gate vs oracle on {N} samples x {wl.M} patches")
+    xi = W.uniform_xi(N, wl.nxi, 1104)
+    xi[5, :] = 1.25    # every local variable out of the box
+    xi_d = torch.from_numpy(xi).cuda()
+    Y = sm.mlp_predict(model, xi_d, sm.PREC_BF16).cpu().numpy()
+    Y[1, :, 3] = np.nan
+    Y[2, :, 15] = np.inf
+    Y[3, :, 0] = -np.inf
+    Y[4, :, 12] += 0.05          # head B disagrees
+    Y[6, :, [1, 11]] += 0.05     # both heads: row sums off
+    Y[7, ::3, :] = 0.0           # the mean prediction
+    mu, sd = sm.mlp_standardization(model)
+    S_g, st_g, gate_g = sm.mlp_gate(model, torch.from_numpy(Y).cuda(), xi_d, 1e-3)
+    torch.cuda.synchronize()
+    S_g, st_g, gate_g = S_g.cpu().numpy(), st_g.cpu().numpy(), gate_g.cpu().numpy()
+    nacc = 0
+    for K in range(wl.M):
+        X = np.zeros((N, 4))
+        X[:, :nl[K]] = xi[:, lv[K, :nl[K]]]
+        ok, Sp, resid, unc = mlp.gate(Y[:, K].astype(np.float64), mu[K], sd[K], X, int(nl[K]), 1e-3)
+        np.testing.assert_array_equal(st_g[:, K] == 0, ok, err_msg=f"patch {K}")
+        for got, ref in ((gate_g[:, K, 0], resid), (gate_g[:, K, 1], unc)):
+            assert np.array_equal(np.isnan(got), np.isnan(ref)), K
+            f = ~np.isnan(ref)
+            assert np.all(np.abs(got[f] - ref[f]) <= 1e-12 * np.maximum(1.0, np.abs(ref[f]))), K
+        sc = np.abs(Sp).max(-1)
+        if ok.any():
+            assert (np.abs(S_g[ok, K] - Sp[ok]).max(-1) <= 1e-10 * sc[ok]).all(), K
+        rej = ~ok & np.isfinite(Y[:, K]).all(-1)
+        Sm = 0.5 * ((mu[K] + sd[K] * Y[rej, K, :10]) + (mu[K] + sd[K] * Y[rej, K, 10:]))
+        assert (np.abs(S_g[rej, K] - Sm).max(-1) <= 1e-12 * np.abs(Sm).max(-1)).all(), K
+        nacc += int(ok.sum())
+    assert not (st_g[1:4] == 0).any() and not (st_g[5] == 0).any()
+    say(f"gate agrees on all {N * wl.M} pairs ({nacc} accepted)")
+
+
+def test_standardization_and_adam_steps_match_oracle(sm, orc):
+    # FP64 standardisation of the training targets, then five FP32 Adam steps
+    # on one fixed minibatch, each against the oracle's FP64 step taken from
+    # the same parameters and the same (GPU) gradient
+    from oracle import mlp
+    wl = W.MESH8
+    model, lv, nl, init = _model(sm, wl, 21)
+    ntr = 32
+    xi_tr = W.uniform_xi(ntr, wl.nxi, 2204)
+    xi_d = torch.from_numpy(xi_tr).cuda()
+    S_tr = sm.upscale(sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    sm.mlp_set_data(model, xi_d, S_tr)
+    mu, sd = sm.mlp_standardization(model)
+    S_np = S_tr.cpu().numpy()
+    for K in range(wl.M):
+        mu_o, sd_o = mlp.standardize(S_np[:, K])
+        np.testing.assert_allclose(mu[K], mu_o, rtol=1e-13, atol=1e-15 * np.abs(mu_o).max())
+        np.testing.assert_allclose(sd[K], sd_o, rtol=1e-13, atol=1e-15 * np.abs(mu_o).max())
+    X = np.zeros((wl.M, ntr, 4), dtype=np.float32)
+    for K in range(wl.M):
+        X[K, :, :nl[K]] = xi_tr[:, lv[K, :nl[K]]]
+    T = ((S_np.transpose(1, 0, 2) - mu[:, None, :]) / sd[:, None, :]).astype(np.float32)
+    xb, tb = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    lr = 1e-3
+    m1 = np.zeros((wl.M, mlp.nparams(4)))
+    m2 = np.zeros_like(m1)
+    for t in range(1, 6):
+        before = sm.mlp_params(model).cpu().numpy().astype(np.float64)
+        g, _ = sm.mlp_grad(model, xb, tb)
+        g = g.cpu().numpy().astype(np.float64)
+        sm.mlp_train(model, 1, lr)
+        after = sm.mlp_params(model).cpu().numpy().astype(np.float64)
+        expect = np.empty_like(after)
+        for K in range(wl.M):
+            expect[K], m1[K], m2[K] = mlp.adam_step(before[K], g[K], m1[K], m2[K], t, lr)
+        ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
+        bad = np.abs(after - expect) > 2 * ulp + 1e-6 * np.abs(expect - before)
+        assert not bad.any(), (t, np.argwhere(bad)[:5])
+        assert np.abs(after - before).max() > 0.5 * lr
+    say("standardisation and 5 Adam steps agree with the oracle")
 
 
 def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
@@ -139,6 +237,41 @@ def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
     ts = timed(lambda: sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, S=S_sur))
     say(f"plain {N * wl.M / tp / 1e9:.2f} G pairs/s, surrogate {N * wl.M / ts / 1e9:.2f} G pairs/s, "
         f"gain {tp / ts:.2f}x")
+    # what the trained network gains: most pairs accepted, a faster path at
+    # the 1e-3 coarse-solution criterion asserted above
+    assert acc.mean() > 0.9
+    assert tp / ts > 1.5
+
+
+def test_surrogate_full_test_set_sampled_against_oracle(sm, orc, trained):
+    # the surrogate's full-size test run (65 536 samples of the 8x8 mesh, 4.19 M
+    # pairs, one launch); whole samples (first, last, six seeded) checked
+    # against the oracle: coarse solution within 1e-3 of the oracle's plain
+    # solution, recomputed pairs equal to the oracle's plain S within 1e-10
+    from oracle import core
+    wl, model = trained["wl"], trained["model"]
+    N = 65536
+    say(f"surrogate on the full test set: {N} samples x {wl.M} patches")
+    xi = W.uniform_xi(N, wl.nxi, 1004)
+    xi_d = torch.from_numpy(xi).cuda()
+    status = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    S_sur = sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, status=status)
+    U_s, _, _ = sm.coarse_solve(S_sur, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    pick = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(3104).choice(N, 6, replace=False)]))
+    st = status.cpu().numpy()[pick]
+    Ss = S_sur.cpu().numpy()[pick]
+    Us = U_s.cpu().numpy()[pick]
+    a_ref = core.coef_bumps(xi[pick], wl.nfine, **wl.coef_params())
+    S_ref, _, _ = core.upscale(a_ref, wl.nc, wl.nc, wl.m)
+    U_ref, _, _ = core.coarse_solve(S_ref, wl.nc, wl.nc)
+    rec = (st == 1) | (st == 2)
+    if rec.any():
+        d = np.abs(Ss[rec] - S_ref[rec]).max(-1) / np.abs(S_ref[rec]).max(-1)
+        assert d.max() < 1e-10
+    ue = np.linalg.norm(Us - U_ref, axis=1) / np.linalg.norm(U_ref, axis=1)
+    say(f"samples {pick.tolist()}: recomputed pairs {int(rec.sum())}, max U err vs oracle {ue.max():.2e}")
+    assert ue.max() < 1e-3
 
 
 def test_surrogate_mesh32_generic_fallback(sm):

@@ -47,7 +47,7 @@ def test_reduced_basis_model_roundtrip(sm, tmp_path):
         np.testing.assert_array_equal(again.export(which), model.export(which))
     xi = torch.from_numpy(W.uniform_xi(200, wl.nxi, 7103)).cuda()
     a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)
-    for prec in (sm.PREC_F32_REFINE64, sm.PREC_F64):
+    for prec in (sm.PREC_F32, sm.PREC_F64):
         S1 = sm.reduce_apply(model, a32, precision=prec)
         S2 = sm.reduce_apply(again, a32, precision=prec)
         torch.cuda.synchronize()

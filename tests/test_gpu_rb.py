@@ -109,3 +109,52 @@ def test_rb_coarse_solution_error(sm, orc, setup):
     U_plain, _, _ = orc.coarse_solve(S_plain, nc, nc)
     err = np.linalg.norm(U.cpu().numpy() - U_plain, axis=1) / np.linalg.norm(U_plain, axis=1)
     assert err.max() < 1e-3
+
+
+def test_rb_full_size_against_oracle(sm, orc):
+    # the reduced-basis workload at its own size: the whole 8x8 mesh, 256
+    # training samples per patch (seed 2003), 16 384 online samples (seed 1003)
+    # with FP32 coefficients through the FP32 MFMA stage in one launch;
+    # offline r and eigenvalues of every patch against the oracle, whole
+    # online samples (first, last, six seeded) against the oracle's S_rb (2e-4)
+    # and the oracle's plain coarse solution (1e-3)
+    from oracle import rb
+    wl = W.MESH8
+    nc, m = wl.nc, wl.m
+    ntr, N = 256, 16384
+    xi_tr = W.uniform_xi(ntr, wl.nxi, 2003)
+    a_tr = orc.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    say(f"full-size build: {nc}x{nc} mesh, m={m}, {ntr} training samples")
+    model = sm.reduce(torch.from_numpy(a_tr).cuda(), nc, nc, m, r_max=8, tail_tol=1e-6)
+    r = model.export("r")
+    lam = model.export("lambda")
+    orc_models = []
+    for K in range(nc * nc):
+        kx, ky = K % nc, K // nc
+        om = rb.rb_offline(a_tr[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m], r_max=8, tail_tol=1e-6)
+        assert r[K] == om["r"], K
+        ref = om["sigma"][:8] ** 2
+        np.testing.assert_allclose(lam[K, :8], ref, rtol=1e-8, atol=1e-12 * ref[0])
+        orc_models.append(om)
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1003)).cuda()
+    a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S = sm.reduce_apply(model, a32, status=st, precision=sm.PREC_F32)
+    U, _, _ = sm.coarse_solve(S, nc, nc)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    pick = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(3103).choice(N, 6, replace=False)]))
+    a = a32.cpu().numpy()[pick].astype(np.float64)
+    Sg = S.cpu().numpy()[pick]
+    S_rb = np.zeros_like(Sg)
+    for i in range(len(pick)):
+        for K in range(nc * nc):
+            kx, ky = K % nc, K // nc
+            S_rb[i, K] = rb.rb_online_S(orc_models[K], a[i, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m])
+    assert rel(Sg, S_rb) < 2e-4
+    S_plain, _, _ = orc.upscale(a, nc, nc, m)
+    U_plain, _, _ = orc.coarse_solve(S_plain, nc, nc)
+    ue = np.linalg.norm(U.cpu().numpy()[pick] - U_plain, axis=1) / np.linalg.norm(U_plain, axis=1)
+    say(f"samples {pick.tolist()}: S_rb err {rel(Sg, S_rb):.2e}, U err vs plain oracle {ue.max():.2e}")
+    assert ue.max() < 1e-3
+    model.free()

@@ -1,5 +1,5 @@
 """Sparse-grid stochastic collocation with search-and-plug-in dictionaries on
-the GPU (Sec. 3.3, global SC methods; Sec. 5.1, second experiment) against
+the GPU (Sec. 4.1.2, global SC methods; Sec. 5.2) against
 the oracle: the dictionaries' S at every collocation point, the weighted
 quadrature, the end-to-end mean and variance, points missing from a
 dictionary, and sampled points of the level-4 grid in 16 variables.

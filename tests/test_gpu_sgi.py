@@ -1,5 +1,5 @@
 """Sparse-grid interpolation of the upscaled stiffness in the local
-variables on the GPU (Sec. 3.1 with the sparse node sets of Sec. 3.3 and
+variables on the GPU (Sec. 3.1 with the sparse node sets of Sec. 4.1.2 and
 Sec. 5.3) against the oracle: the interpolant at random points, the plain
 path outside the box, the interpolation error against the plain path, and
 sampled pairs of the benchmark mesh.

@@ -76,3 +76,66 @@ def test_gate_accepts_exact_and_rejects_inconsistent(orc):
     assert list(ok2) == [False, False, False]
     assert unc2[0] > 1e-2 and resid2[1] > 1e-2
     assert mlp.gate(Y2, mu, sd, X2, 1, 1e-3)[0][2]   # out-of-box variable not local => accepted
+
+
+@pytest.mark.parametrize("lr", [0.01, 3e-4])
+def test_adam_constant_gradient_moves_lr_per_step(lr):
+    # Kingma & Ba: with a constant gradient g, both bias-corrected moment
+    # estimates are exact at every step (m_hat = g, v_hat = g^2), so each of
+    # the first t steps moves every parameter by -lr * sign(g) (eps = 0).  A
+    # slip in either moment update or either bias correction at t >= 2 breaks
+    # this.
+    from oracle import mlp
+    g = W.uniform_array(40, -3, 3, 51)
+    x0 = W.uniform_array(40, -1, 1, 52)
+    x, m1, m2 = x0.copy(), np.zeros(40), np.zeros(40)
+    for t in range(1, 8):
+        x, m1, m2 = mlp.adam_step(x, g, m1, m2, t, lr, eps=0.0)
+        np.testing.assert_allclose(x, x0 - t * lr * np.sign(g), rtol=0, atol=1e-12)
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    # the update depends on m_hat / sqrt(v_hat): scaling every gradient by
+    # c > 0 leaves the whole trajectory unchanged (eps = 0)
+    from oracle import mlp
+    gs = [W.uniform_array(30, -2, 2, 60 + t) for t in range(6)]
+    for c in (1e-3, 7.0):
+        xa, xb = np.zeros(30), np.zeros(30)
+        ma = [np.zeros(30), np.zeros(30)]
+        mb = [np.zeros(30), np.zeros(30)]
+        for t, g in enumerate(gs, start=1):
+            xa, ma[0], ma[1] = mlp.adam_step(xa, g, ma[0], ma[1], t, 1e-2, eps=0.0)
+            xb, mb[0], mb[1] = mlp.adam_step(xb, c * g, mb[0], mb[1], t, 1e-2, eps=0.0)
+            np.testing.assert_allclose(xb, xa, rtol=1e-12, atol=1e-15)
+
+
+def test_standardize_recovers_affine_targets_and_floors_constants():
+    # targets alpha_q + beta_q * u with u of mean 0 and population standard
+    # deviation 1 (u = +-1 alternating): mean alpha, std |beta| (1/N form,
+    # not 1/(N-1)); a constant entry gets the floor 1e-12 max(1, max|mean|)
+    from oracle import mlp
+    N = 50
+    u = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    alpha = W.uniform_array(10, -5, 5, 70)
+    beta = W.uniform_array(10, -2, 2, 71)
+    beta[3] = 0.0
+    S = alpha[None, :] + beta[None, :] * u[:, None]
+    mu, sd = mlp.standardize(S)
+    np.testing.assert_allclose(mu, alpha, rtol=0, atol=1e-14)
+    expect = np.abs(beta)
+    expect[3] = 1e-12 * max(1.0, np.abs(alpha).max())
+    np.testing.assert_allclose(sd, expect, rtol=1e-14, atol=0)
+
+
+def test_gate_rejects_non_finite_predictions():
+    # a NaN or an infinite de-standardised value must never be accepted
+    from oracle import mlp
+    mu = np.linspace(1.0, 2.0, 10)
+    sd = np.full(10, 0.1)
+    Y = np.zeros((4, 20))
+    Y[1, 3] = np.nan
+    Y[2, 15] = np.inf
+    Y[3, 0] = -np.inf
+    ok, _, resid, unc = mlp.gate(Y, mu, sd, np.zeros((4, 4)), 4, 1e30)
+    assert ok.tolist() == [True, False, False, False]
+    assert np.isnan(resid[1:]).all() and np.isnan(unc[1:]).all()

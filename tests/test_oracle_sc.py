@@ -1,6 +1,6 @@
 """Pins of the oracle's sparse-grid stochastic collocation with
-search-and-plug-in dictionaries (Sec. 3.3, global SC methods; Sec. 5.1, the
-second experiment) against facts fixed outside it: the classical
+search-and-plug-in dictionaries (Sec. 4.1.2, global SC methods; the
+collocation experiment of Sec. 5.2) against facts fixed outside it: the classical
 Clenshaw-Curtis weights, hand-derived small grids (tests/golden), the point
 counts that follow from the numbers of new points per nested level, exact
 integration of polynomials of total degree <= 2L + 1 (Novak and Ritter), the

@@ -1,5 +1,5 @@
 """The library's sparse-grid construction (host code, no GPU needed) against
-the oracle (Sec. 3.3, global SC methods), and host-side argument checks of
+the oracle (Sec. 4.1.2, global SC methods), and host-side argument checks of
 the collocation entry points.
 
 The two sides compute the Clenshaw-Curtis weights differently (the library
