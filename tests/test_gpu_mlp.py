@@ -8,8 +8,9 @@ terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
 units); BF16 forward (three-term bf16 splitting, FP32 accumulation) within 1e-3
 of the FP64 oracle's forward pass; the standardisation within 1e-13 of the
 oracle's (FP64 on both sides, different summation orders); an FP32 Adam step
-within 2 float ulps of the FP64 oracle step from the same parameters and
-gradient; the gate on identical raw outputs: accept mask exact, residual and
+within 2 float ulps plus 1e-4 of the step of the FP64 oracle step from the
+same parameters and gradient (the FP32 bias corrections 1 - beta^t carry
+relative errors of a few 1e-5 from cancellation); the gate on identical raw outputs: accept mask exact, residual and
 uncertainty within 1e-12 relative (both FP64 from the same FP32 outputs), the
 stored S within 1e-10 relative to max|S| of the pair.
 The end-to-end criterion is the coarse solution: surrogate within 1e-3
@@ -172,7 +173,7 @@ def test_standardization_and_adam_steps_match_oracle(sm, orc):
     X = np.zeros((wl.M, ntr, 4), dtype=np.float32)
     for K in range(wl.M):
         X[K, :, :nl[K]] = xi_tr[:, lv[K, :nl[K]]]
-    T = ((S_np.transpose(1, 0, 2) - mu[:, None, :]) / sd[:, None, :]).astype(np.float32)
+    T = np.ascontiguousarray(((S_np.transpose(1, 0, 2) - mu[:, None, :]) / sd[:, None, :]).astype(np.float32))
     xb, tb = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
     lr = 1e-3
     m1 = np.zeros((wl.M, mlp.nparams(4)))
@@ -187,7 +188,8 @@ def test_standardization_and_adam_steps_match_oracle(sm, orc):
         for K in range(wl.M):
             expect[K], m1[K], m2[K] = mlp.adam_step(before[K], g[K], m1[K], m2[K], t, lr)
         ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
-        bad = np.abs(after - expect) > 2 * ulp + 1e-6 * np.abs(expect - before)
+        # FP32 bias corrections 1 - beta^t lose ~3e-5 relative to cancellation
+        bad = np.abs(after - expect) > 2 * ulp + 1e-4 * np.abs(expect - before)
         assert not bad.any(), (t, np.argwhere(bad)[:5])
         assert np.abs(after - before).max() > 0.5 * lr
     say("standardisation and 5 Adam steps agree with the oracle")
