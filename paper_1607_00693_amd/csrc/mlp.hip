@@ -11,10 +11,11 @@
 //                            parameter by the thread that formed its
 //                            gradient, otherwise the raw gradient is written
 //                            (parity checks against the oracle).
-//   mlp_infer_bf16_kernel    BF16 MFMA (v_mfma_f32_16x16x16bf16_1k, FP32
+//   mlp_infer_bf16_kernel    BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
 //                            accumulation, three-term bf16 splitting of
-//                            weights and activations, FP32 bias + GELU)
-//                            inference, then the gate per pair;
+//                            weights and activations, activations kept in
+//                            registers, tabulated GELU) inference, then the
+//                            gate per pair;
 //   mlp_infer_f32_kernel     FP32 inference (reference for the BF16 one);
 //   mlp_fallback_kernel      plain solve (m = 8 lane kernel) of the pairs the
 //                            gate rejected plus a 1% audit of accepted ones,
@@ -441,57 +442,119 @@ __global__ __launch_bounds__(64) void mlp_infer_f32_kernel(MlpInferArgs a) {
   }
 }
 
-// BF16 MFMA inference.  Workgroup = 4 wavefronts x 16 samples of one patch.
+// BF16 MFMA inference (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
 // Every FP32 weight w and activation h is carried as two bf16 numbers,
 // w = w_hi + w_lo, h = h_hi + h_lo (w_hi = bf16(w), w_lo = bf16(w - w_hi)), and
 // each product is formed as h_hi w_hi + h_hi w_lo + h_lo w_hi on the matrix
-// cores with FP32 accumulation (the h_lo w_lo term is below FP32 rounding).
-// Weights are stored transposed (n-major) so that each lane's four
-// consecutive k are adjacent in LDS.
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// cores (the h_lo w_lo term is below 2^-16 relative), which keeps the layers
+// at about 16 significant bits.
+//
+// The layers are computed transposed, D = W^T H^T (rows = output neurons,
+// columns = 16 samples), so that the accumulator layout of one layer is the
+// B-operand layout of the next: for a 16 x 16 output tile, lane l holds
+// neurons 4(l/16) + v (v < 4) of sample l % 16; for a 32-wide k block the
+// B operand wants 8 k values of sample l % 16 in lane l, and the two output
+// tiles 2kb and 2kb+1 supply exactly 8 such values per lane.  The k order
+// inside the block is therefore a permutation (slot 8g + j holds neuron
+// 32kb + 4g + j for j < 4 and 32kb + 16 + 4g + (j - 4) otherwise, g = l / 16),
+// and the weights are staged once per workgroup in LDS in that permuted A
+// layout (16 bytes per lane and operand, one ds_read_b128).  Activations never
+// leave the registers; biases initialise the accumulators.
+//
+// GELU: Phi(z) is read from a table of piecewise quadratics on [-6, 6]
+// (step 1/64, interpolating Phi at both ends and the midpoint of each
+// interval; Phi from the FP64 erfc at the nodes), built in LDS by every
+// workgroup; the interpolation error is below 1e-7 and Phi is 0 or 1 to FP32
+// precision outside the range.  The erf form is evaluated exactly by the FP32
+// reference kernel and the training kernel.
+//
+// Workgroup = 8 wavefronts on one patch; a wavefront takes 64 samples (four
+// column tiles of 16), parks the 20 outputs of each sample in LDS and then
+// gates one sample per lane; rejected and audited pairs are appended to the
+// fallback list with one atomic per wavefront.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int BF_WAVES = 8;                 // wavefronts per workgroup
+constexpr int BF_TILE = 64 * BF_WAVES;      // samples per workgroup tile
+constexpr int BF_NOP = 32;                  // 20 outputs padded to two row tiles
+// A operands: layer 1 (4 row tiles x 1 k block), layers 2 and 3 (4 x 2),
+// layer 4 (2 x 2); each x {hi, lo} x 64 lanes x 8 bf16
+constexpr int BF_OPS_L1 = 0, BF_OPS_L2 = 4, BF_OPS_L3 = 12, BF_OPS_L4 = 20, BF_OPS = 24;
+constexpr int GT_N = 768;                   // GELU table intervals on [-6, 6]
+constexpr float GT_SCALE = 64.0f, GT_OFF = 384.0f;
+
+__device__ __forceinline__ float gelu_tab(const float4* __restrict__ tab, float z) {
+  float u = fmaf(z, GT_SCALE, GT_OFF);
+  u = fminf(fmaxf(u, 0.0f), (float)GT_N - 0.0009765625f);
+  const int i = (int)u;
+  const float t = __builtin_amdgcn_fractf(u);
+  const float4 c = tab[i];
+  return z * fmaf(t, fmaf(t, c.z, c.y), c.x);
 }
-__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-constexpr int BF_KIN = 16;  // layer-1 K padded to one MFMA K step
-constexpr int BF_NO = 32;   // 20 outputs padded to two N tiles
-constexpr int BF_LD = WD + 4;
+// split four consecutive activations of two tiles into hi/lo B operands
+__device__ __forceinline__ void split8(const f32x4_t& a, const f32x4_t& b, bf16x8_t& hi, bf16x8_t& lo) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const __bf16 ha = (__bf16)a[v], hb = (__bf16)b[v];
+    hi[v] = ha;
+    hi[4 + v] = hb;
+    lo[v] = (__bf16)(a[v] - (float)ha);
+    lo[4 + v] = (__bf16)(b[v] - (float)hb);
+  }
+}
 
-constexpr int BF_WAVES = 8;               // wavefronts per workgroup
-constexpr int BF_TILE = 16 * BF_WAVES;     // samples per tile
+__device__ __forceinline__ f32x4_t mma3(const bf16x8_t& ah, const bf16x8_t& al, const bf16x8_t& bh,
+                                        const bf16x8_t& bl, f32x4_t c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
 
 __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferArgs a) {
-  using s4 = __attribute__((__vector_size__(4 * sizeof(short)))) short;
-  using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const int K = blockIdx.y;
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
+  const int g = lane >> 4, col = lane & 15;
   constexpr int NT = 64 * BF_WAVES;
-  // [2] = hi, lo
-  __shared__ uint16_t W1t[2][WD][BF_KIN], W2t[2][WD][BF_LD], W3t[2][WD][BF_LD], W4t[2][BF_NO][BF_LD];
-  __shared__ float bias[3 * WD + BF_NO];
-  __shared__ uint16_t Hs[BF_WAVES][2][2][16][BF_LD];  // wave, ping-pong buffer, hi/lo, row, k
-  __shared__ float Ys[BF_WAVES][16][BF_NO + 1];
-  const float* P = a.params + (int64_t)K * MLP_NP;
-  auto split = [](float v, uint16_t& hi, uint16_t& lo) {
-    hi = to_bf16(v);
-    lo = to_bf16(v - from_bf16(hi));
-  };
-  for (int i = tid; i < WD * BF_KIN; i += NT) {
-    const int nn = i / BF_KIN, k = i % BF_KIN;
-    split(k < MLP_KIN ? P[MLP_OW1 + k * WD + nn] : 0.0f, W1t[0][nn][k], W1t[1][nn][k]);
+  __shared__ bf16x8_t WA[BF_OPS][2][64];      // [operand][hi/lo][lane]
+  __shared__ float4 tab[GT_N];
+  __shared__ float bias[3 * WD + BF_NOP];
+  // the per-sample outputs of the tiles; during set-up the same memory holds
+  // the patch's raw parameters
+  constexpr int YS_FLOATS = BF_WAVES * 64 * (NO + 1);
+  static_assert(YS_FLOATS >= MLP_NP + 4, "parameter staging must fit the output buffer");
+  __shared__ __align__(16) float ysbuf[YS_FLOATS];
+  float(*Ys)[64][NO + 1] = reinterpret_cast<float(*)[64][NO + 1]>(ysbuf);
+  const float* Pg = a.params + (int64_t)K * MLP_NP;
+  // ---- raw parameters into LDS with coalesced loads ----
+  for (int i = tid; i < MLP_NP; i += NT) ysbuf[i] = Pg[i];
+  __syncthreads();
+  const float* P = ysbuf;
+  // ---- stage the weights in the permuted A layout, split hi/lo ----
+  for (int e = tid; e < BF_OPS * 64 * 8; e += NT) {
+    const int j = e & 7, ln = (e >> 3) & 63, op = e >> 9;
+    const int i = ln & 15, gg = ln >> 4;
+    float v = 0.0f;
+    if (op < BF_OPS_L2) {  // layer 1: k slot = input index
+      const int nt = op, kin = 8 * gg + j;
+      if (kin < MLP_KIN) v = P[MLP_OW1 + kin * WD + 16 * nt + i];
+    } else {
+      const int L = op < BF_OPS_L3 ? 2 : (op < BF_OPS_L4 ? 3 : 4);
+      const int rel = op - (L == 2 ? BF_OPS_L2 : (L == 3 ? BF_OPS_L3 : BF_OPS_L4));
+      const int nt = rel >> 1, kb = rel & 1;
+      const int nin = 32 * kb + (j < 4 ? 4 * gg + j : 16 + 4 * gg + (j - 4));
+      const int nout = 16 * nt + i;
+      if (L == 2) v = P[MLP_OW2 + nin * WD + nout];
+      else if (L == 3) v = P[MLP_OW3 + nin * WD + nout];
+      else if (nout < NO) v = P[MLP_OW4 + nin * NO + nout];
+    }
+    const __bf16 h = (__bf16)v;
+    WA[op][0][ln][j] = h;
+    WA[op][1][ln][j] = (__bf16)(v - (float)h);
   }
-  for (int i = tid; i < WD * WD; i += NT) {
-    const int nn = i / WD, k = i % WD;
-    split(P[MLP_OW2 + k * WD + nn], W2t[0][nn][k], W2t[1][nn][k]);
-    split(P[MLP_OW3 + k * WD + nn], W3t[0][nn][k], W3t[1][nn][k]);
-  }
-  for (int i = tid; i < BF_NO * WD; i += NT) {
-    const int nn = i / WD, k = i % WD;
-    split(nn < NO ? P[MLP_OW4 + k * NO + nn] : 0.0f, W4t[0][nn][k], W4t[1][nn][k]);
-  }
-  for (int i = tid; i < 3 * WD + BF_NO; i += NT) {
+  for (int i = tid; i < 3 * WD + BF_NOP; i += NT) {
     float v;
     if (i < WD) v = P[MLP_OB1 + i];
     else if (i < 2 * WD) v = P[MLP_OB2 + i - WD];
@@ -499,128 +562,132 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
     else v = (i - 3 * WD) < NO ? P[MLP_OB4 + i - 3 * WD] : 0.0f;
     bias[i] = v;
   }
+  // ---- GELU table: quadratic through Phi at x0, x0 + h/2, x0 + h ----
+  for (int i = tid; i < GT_N; i += NT) {
+    const double h = 1.0 / GT_SCALE, x0 = -6.0 + i * h;
+    const double f0 = 0.5 * erfc(-x0 * 0.70710678118654752440);
+    const double fm = 0.5 * erfc(-(x0 + 0.5 * h) * 0.70710678118654752440);
+    const double f1 = 0.5 * erfc(-(x0 + h) * 0.70710678118654752440);
+    tab[i] = make_float4((float)f0, (float)(-3.0 * f0 + 4.0 * fm - f1), (float)(2.0 * f0 - 4.0 * fm + 2.0 * f1), 0.0f);
+  }
+  __syncthreads();
+  const int lv0 = a.lv[K * MLP_KIN + 0], lv1 = a.lv[K * MLP_KIN + 1], lv2 = a.lv[K * MLP_KIN + 2],
+            lv3 = a.lv[K * MLP_KIN + 3];
   const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-  __syncthreads();
-  // inputs of this wavefront's 16 samples (row = sample, k < 4 used)
-  const int64_t sbase = tile * BF_TILE + 16 * w;
-  for (int i = lane; i < 16 * BF_KIN; i += 64) {
-    const int r = i / BF_KIN, k = i % BF_KIN;
-    const int64_t s = sbase + r;
-    float v = 0.0f;
-    if (k < MLP_KIN && s < a.nsamples) {
-      const int j = a.lv[K * MLP_KIN + k];
-      v = j >= 0 ? (float)a.xi[s * a.nxi + j] : 0.0f;
-    }
-    split(v, Hs[w][0][0][r][k], Hs[w][0][1][r][k]);
-  }
-  __syncthreads();
-  const int row = lane & 15, kq = lane >> 4;  // A: row, k group; B: column, k group
-  auto loadA = [&](int buf, int part, int k0) {
-    s4 v;
+    const int64_t wbase = tile * BF_TILE + 64 * w;  // this wavefront's 64 samples
+    // the four column tiles of 16 samples go through each layer together:
+    // every A operand is read from LDS once per layer and used four times
+    bf16x8_t bh[4][2], bl[4][2];
+    f32x4_t acc[4][4];
+    const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (short)Hs[w][buf][part][row][k0 + 4 * kq + t];
-    return v;
-  };
-  auto store_act = [&](int buf, int ntile, const f4& c, int boff) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 4 * kq + v, col = 16 * ntile + (lane & 15);
-      split(gelu_f(c[v] + bias[boff + col]), Hs[w][buf][0][r][col], Hs[w][buf][1][r][col]);
+    for (int st = 0; st < 4; ++st) {
+      const int64_t s = wbase + 16 * st + col;
+      f32x4_t x4 = z4;  // layer-1 B operand: x in slots 0..3 of lane group 0
+      if (g == 0 && s < a.nsamples) {
+        const double* xs = a.xi + s * a.nxi;
+        x4[0] = lv0 >= 0 ? (float)xs[lv0] : 0.0f;
+        x4[1] = lv1 >= 0 ? (float)xs[lv1] : 0.0f;
+        x4[2] = lv2 >= 0 ? (float)xs[lv2] : 0.0f;
+        x4[3] = lv3 >= 0 ? (float)xs[lv3] : 0.0f;
+      }
+      split8(x4, z4, bh[st][0], bl[st][0]);
     }
-  };
-  auto mma3 = [](const s4& ah, const s4& al, const s4& bh, const s4& bl, f4 c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
-  };
-  // layer 1: [16 x 16] x [16 x 64]
-  {
-    const s4 ah = loadA(0, 0, 0), al = loadA(0, 1, 0);
-    f4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      s4 bh, bl;
+      const bf16x8_t ah = WA[BF_OPS_L1 + nt][0][lane], al = WA[BF_OPS_L1 + nt][1][lane];
+      f32x4_t b4;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        bh[t] = (short)W1t[0][16 * nt + row][4 * kq + t];
-        bl[t] = (short)W1t[1][16 * nt + row][4 * kq + t];
-      }
-      acc[nt] = mma3(ah, al, bh, bl, f4{0.f, 0.f, 0.f, 0.f});
+      for (int v = 0; v < 4; ++v) b4[v] = bias[16 * nt + 4 * g + v];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][0], bl[st][0], b4);
     }
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) store_act(1, nt, acc[nt], 0);
-  }
-  __syncthreads();
-  // layers 2 and 3: [16 x 64] x [64 x 64]
+    for (int L = 0; L < 2; ++L) {
 #pragma unroll
-  for (int layer = 0; layer < 2; ++layer) {
-    const int inb = layer == 0 ? 1 : 0, outb = layer == 0 ? 0 : 1;  // ping-pong activation buffers
-    f4 acc[4];
+      for (int st = 0; st < 4; ++st) {
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const s4 ah = loadA(inb, 0, 16 * kk), al = loadA(inb, 1, 16 * kk);
+          for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_tab(tab, acc[st][nt][v]);
+        split8(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
+        split8(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
+      }
+      const int ob = L == 0 ? BF_OPS_L2 : BF_OPS_L3;
+      const float* bs = bias + (L + 1) * WD;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        s4 bh, bl;
+        f32x4_t b4;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int nn = 16 * nt + row, k = 16 * kk + 4 * kq + t;
-          bh[t] = (short)(layer == 0 ? W2t[0][nn][k] : W3t[0][nn][k]);
-          bl[t] = (short)(layer == 0 ? W2t[1][nn][k] : W3t[1][nn][k]);
+        for (int v = 0; v < 4; ++v) b4[v] = bs[16 * nt + 4 * g + v];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc[st][nt] = b4;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          const bf16x8_t ah = WA[ob + 2 * nt + kb][0][lane], al = WA[ob + 2 * nt + kb][1][lane];
+#pragma unroll
+          for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
         }
-        acc[nt] = mma3(ah, al, bh, bl, acc[nt]);
       }
     }
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) store_act(outb, nt, acc[nt], (layer + 1) * WD);
+    for (int st = 0; st < 4; ++st) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_tab(tab, acc[st][nt][v]);
+      split8(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
+      split8(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      f32x4_t b4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b4[v] = bias[3 * WD + 16 * nt + 4 * g + v];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc[st][nt] = b4;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        const bf16x8_t ah = WA[BF_OPS_L4 + 2 * nt + kb][0][lane], al = WA[BF_OPS_L4 + 2 * nt + kb][1][lane];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = 16 * nt + 4 * g + v;
+          if (o < NO) Ys[w][16 * st + col][o] = acc[st][nt][v];
+        }
     __syncthreads();
-  }
-  // layer 4: [16 x 64] x [64 x 32], FP32 output + bias
-  {
-    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const s4 ah = loadA(1, 0, 16 * kk), al = loadA(1, 1, 16 * kk);
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        s4 bh, bl;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          bh[t] = (short)W4t[0][16 * nt + row][16 * kk + 4 * kq + t];
-          bl[t] = (short)W4t[1][16 * nt + row][16 * kk + 4 * kq + t];
-        }
-        acc[nt] = mma3(ah, al, bh, bl, acc[nt]);
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 4 * kq + v, col = 16 * nt + (lane & 15);
-        Ys[w][r][col] = acc[nt][v] + bias[3 * WD + col];
-      }
-  }
-  __syncthreads();
-  if (lane < 16) {
-    const int64_t s = sbase + lane;
+    // ---- one sample per lane: outputs, gate, fallback list ----
+    const int64_t s = wbase + lane;
+    bool fb = false;
     if (s < a.nsamples) {
       const int64_t p = s * a.npatch + K;
-      float y[NO];
+      float yv[NO];
 #pragma unroll
-      for (int o = 0; o < NO; ++o) y[o] = Ys[w][lane][o];
+      for (int o = 0; o < NO; ++o) yv[o] = Ys[w][lane][o];
       if (a.Y) {
-        for (int o = 0; o < NO; ++o) a.Y[p * NO + o] = y[o];
+        for (int o = 0; o < NO; ++o) a.Y[p * NO + o] = yv[o];
       }
-      if (a.S) {
-        bool fb;
-        gate_and_store(a, K, s, y, a.S + p * 10, a.status ? a.status + p : nullptr, &fb);
-        if (fb) push_fallback(a, p);
+      if (a.S) gate_and_store(a, K, s, yv, a.S + p * 10, a.status ? a.status + p : nullptr, &fb);
+    }
+    if (a.S) {
+      const unsigned long long mask = __ballot(fb);
+      if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd((unsigned long long*)a.count, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+        if (fb) a.list[base + __popcll(mask & ((1ull << lane) - 1ull))] = s * a.npatch + K;
       }
     }
-  }
+    __syncthreads();
   }  // tiles
 }
 
@@ -629,40 +696,85 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
-// Plain solve of the listed pairs (m = 8), coefficients regenerated from xi.
+// Plain solve of the listed pairs (m = 8), coefficients regenerated from xi,
+// one lane per pair.  The statistics are combined over the wavefront before
+// one atomic per counter.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(64) void mlp_fallback_kernel(MlpInferArgs a) {
   __shared__ double blk[64][64];
   const int lane = threadIdx.x;
   const unsigned long long count = *a.count;
   const double h = 1.0 / (a.ncx * 8);
   const BumpParams bp{a.bump_g, a.bump_rho, a.bump_eps, a.bump_base, a.bump_amp, a.bump_beta};
-  for (unsigned long long idx = (unsigned long long)blockIdx.x * 64 + lane; idx < count;
-       idx += (unsigned long long)gridDim.x * 64) {
-    const int64_t p = a.list[idx];
-    const int64_t s = p / a.npatch;
-    const int K = (int)(p - s * a.npatch);
-    const int kx = K % a.ncx, ky = K / a.ncx;
-    for (int e = 0; e < 64; ++e) {
-      const int ex = e % 8, ey = e / 8;
-      blk[lane][e] = bump_coef((kx * 8 + ex + 0.5) * h, (ky * 8 + ey + 0.5) * h, a.xi + s * a.nxi, bp);
+  // wavefront-uniform loop: every lane takes part in the statistics
+  for (unsigned long long base = (unsigned long long)blockIdx.x * 64; base < count;
+       base += (unsigned long long)gridDim.x * 64) {
+    const unsigned long long idx = base + lane;
+    bool rejected = false, audited = false;
+    double rel = 0.0;
+    if (idx < count) {
+      const int64_t p = a.list[idx];
+      const int64_t s = p / a.npatch;
+      const int K = (int)(p - s * a.npatch);
+      const int kx = K % a.ncx, ky = K / a.ncx;
+      // the coefficient of each fine element, as the coefficient kernel forms
+      // it (same operations, so the same bits); the oscillation's sines are
+      // shared by the element rows and columns of the patch
+      double sxv[8], syv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double xq = (kx * 8 + q + 0.5) * h, yq = (ky * 8 + q + 0.5) * h;
+        sxv[q] = sin(2.0 * M_PI * xq / bp.eps);
+        syv[q] = sin(2.0 * M_PI * yq / bp.eps);
+      }
+      const double* xs = a.xi + s * a.nxi;
+#pragma unroll
+      for (int ey = 0; ey < 8; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 8; ++ex) {
+          const double x = (kx * 8 + ex + 0.5) * h, y = (ky * 8 + ey + 0.5) * h;
+          const double field = bump_field(x, y, xs, bp);
+          const double osc = bp.base + bp.amp * sxv[ex] * syv[ey];
+          blk[lane][8 * ey + ex] = osc * exp(bp.beta * field);
+        }
+      double Sp[10];
+      int32_t st = 0;
+      small_cell_solve<8, double>(&blk[lane][0], 8, Sp, &st);
+      double* So = a.S + p * 10;
+      double err = 0.0, sc = 0.0;
+      for (int q = 0; q < 10; ++q) {
+        err = fmax(err, fabs(So[q] - Sp[q]));
+        sc = fmax(sc, fabs(Sp[q]));
+        So[q] = Sp[q];
+      }
+      rel = sc > 0 ? err / sc : 0.0;
+      audited = a.status && a.status[p] == MLP_ST_AUDIT;
+      rejected = !audited;
+      if (a.status) a.status[p] = st != STOMSFEM_OK ? st : (audited ? MLP_ST_AUDIT : MLP_ST_FALLBACK);
     }
-    double Sp[10];
-    int32_t st = 0;
-    small_cell_solve<8, double>(&blk[lane][0], 8, Sp, &st);
-    double* So = a.S + p * 10;
-    double err = 0.0, sc = 0.0;
-    for (int q = 0; q < 10; ++q) {
-      err = fmax(err, fabs(So[q] - Sp[q]));
-      sc = fmax(sc, fabs(Sp[q]));
-      So[q] = Sp[q];
-    }
-    const double rel = sc > 0 ? err / sc : 0.0;
-    const bool audited = a.status && a.status[p] == MLP_ST_AUDIT;
     if (a.stats) {
-      atomicAdd(&a.stats[audited ? 1 : 0], 1ull);
-      atomicMax(&a.stats[audited ? 3 : 2], (unsigned long long)__double_as_longlong(rel));
+      const unsigned long long nrej = __popcll(__ballot(rejected)), naud = __popcll(__ballot(audited));
+      const unsigned long long mrej = wave_max_u64(rejected ? (unsigned long long)__double_as_longlong(rel) : 0ull);
+      const unsigned long long maud = wave_max_u64(audited ? (unsigned long long)__double_as_longlong(rel) : 0ull);
+      if (lane == 0) {
+        if (nrej) {
+          atomicAdd(&a.stats[0], nrej);
+          atomicMax(&a.stats[2], mrej);
+        }
+        if (naud) {
+          atomicAdd(&a.stats[1], naud);
+          atomicMax(&a.stats[3], maud);
+        }
+      }
     }
-    if (a.status) a.status[p] = st != STOMSFEM_OK ? st : (audited ? MLP_ST_AUDIT : MLP_ST_FALLBACK);
   }
 }
 
@@ -704,7 +816,10 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
   }
   if (bf16) {
     const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
-    int64_t gx = (1024 + a.npatch - 1) / a.npatch;  // about four workgroups per CU in total
+    // one workgroup per CU (its LDS allows no second one): about 256 in all,
+    // each persistent over its patch's tiles, so the per-workgroup set-up
+    // (weights, GELU table) is paid once per CU
+    int64_t gx = (256 + a.npatch - 1) / a.npatch;
     if (gx > ntiles) gx = ntiles;
     if (gx < 1) gx = 1;
     hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3((unsigned)gx, (unsigned)a.npatch), dim3(64 * BF_WAVES), 0, st, a);
@@ -714,8 +829,10 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.S || a.m != 8) return e;
-  int64_t blocks = (a.nsamples * a.npatch + 63) / 64;
-  if (blocks > 2048) blocks = 2048;
+  // the listed count is known only on the device: enough wavefronts for
+  // about 3% of the pairs in one pass, looping beyond that
+  int64_t blocks = (a.nsamples * a.npatch / 32 + 63) / 64;
+  if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(mlp_fallback_kernel, dim3((unsigned)blocks), dim3(64), 0, st, a);
   return hipGetLastError();
