@@ -189,6 +189,24 @@ int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* st
 int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
                           double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve, arguments and outputs as stomsfem_coarse_solve, with its factor
+ * workspace and QoI partial sums in a fixed 64 MiB array of device memory
+ * that the library holds on every GPU it runs on, from module load until the
+ * process ends.  Samples are solved in chunks that fit that array, so any
+ * nsamples works; a mesh whose single sample needs more than 64 MiB
+ * ((ncx-1)(ncy-1)(ncx+1)+1 doubles) is rejected with EINVAL.  U and status
+ * are bit-identical to stomsfem_coarse_solve's; qoi_mean and qoi_var may
+ * differ in the last bits (the partial sums are grouped differently when the
+ * array is smaller than the default workspace).  Calls no allocating
+ * routine.  All calls on one GPU share the array and keep no state in it
+ * between calls: calls that overlap on one GPU (on different streams, or
+ * from different threads) race and give undefined results, so serialise
+ * them.  Asynchronous on `stream`. */
+int stomsfem_coarse_solve_noalloc(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
+                                  double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
+
 /* ------------------------------------------------------------------------
  * Oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2: remark on
  * oversampling, eq. stiffness_local_petrov; Sec. 4.1.1 for the coarse solve).

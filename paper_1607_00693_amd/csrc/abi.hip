@@ -30,6 +30,9 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
                          double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
                             double* mean, double* var, int32_t* status, double* work, hipStream_t st);
+hipError_t launch_coarse_capped(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
+                                double* mean, double* var, int32_t* status, double* work, int64_t work_cap,
+                                hipStream_t st);
 // list != nullptr: only the batch's pairs list[i] (i < nlist), S and status compact at i
 hipError_t launch_upscale_os(const UpArgs& up, int o, int a_dtype, hipStream_t st, const int64_t* list = nullptr,
                              int64_t nlist = 0);
@@ -538,6 +541,71 @@ int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const doub
   hipError_t e = launch_coarse(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, (double*)work,
                                (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve launch");
+}
+
+// ---------------------------------------------------------------------------
+// Coarse solve without allocation.  Its factor workspace is a fixed array in
+// device memory that every GPU running the library holds from module load to
+// process end.  `scratch` is a host-side stand-in: its device address on the
+// current device comes from hipGetSymbolAddress (once per device, kept in
+// g_scratch_ptr) and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t{8} << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};  // device -> address of `scratch` there (no host allocation)
+
+int scratch_device_ptr(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(STOMSFEM_EHIP, std::string("coarse_solve_noalloc: hipGetSymbolAddress of the scratch array failed: ") +
+                                     hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return STOMSFEM_OK;
+}
+}  // namespace
+
+int stomsfem_coarse_solve_noalloc(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
+                                  double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream) {
+  if (ncx < 1 || ncy < 1 || nsamples < 0) return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: bad sizes");
+  if (ncx > 1024 || ncy > 1024) return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: ncx, ncy must be <= 1024");
+  if (coarse_lds_bytes(ncx, false) > 64 * 1024)
+    return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: ncx too large for the LDS window");
+  const int64_t nU = (int64_t)(ncx - 1) * (ncy - 1);
+  if (nU == 0) return STOMSFEM_OK;
+  const int64_t per = nU * (ncx + 1) + 1;
+  if (per > NOALLOC_SCRATCH_DOUBLES || 2 * nU > NOALLOC_SCRATCH_DOUBLES)
+    return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: one sample of a " + std::to_string(ncx) + " x " +
+                                     std::to_string(ncy) + " coarse mesh needs " + std::to_string(8 * per) +
+                                     " bytes of scratch, more than the " +
+                                     std::to_string(8 * NOALLOC_SCRATCH_DOUBLES) + " bytes the library holds");
+  if (nsamples > 0 && (!device_ptr(S) || !device_ptr(U)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: S and U must be device pointers");
+  if (load && !device_ptr(load)) return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: load must be a device pointer");
+  if ((qoi_mean && !device_ptr(qoi_mean)) || (qoi_var && !device_ptr(qoi_var)))
+    return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: qoi outputs must be device pointers");
+  if (status && !device_ptr(status))
+    return fail(STOMSFEM_EINVAL, "coarse_solve_noalloc: status must be a device pointer");
+  double* work = nullptr;
+  int rc = scratch_device_ptr(&work);
+  if (rc != STOMSFEM_OK) return rc;
+  hipError_t e = launch_coarse_capped(ncx, ncy, nsamples, S, load, U, qoi_mean, qoi_var, status, work,
+                                      NOALLOC_SCRATCH_DOUBLES, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve_noalloc launch");
 }
 
 int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double* u, int32_t* status,

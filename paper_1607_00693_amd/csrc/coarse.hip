@@ -599,9 +599,12 @@ static void launch_lane(const CoarseArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(coarse_lane_kernel<NC>, dim3((unsigned)((a.nsamples + 63) / 64)), dim3(64), 0, st, a);
 }
 
+// work_cap = 0: the workspace holds coarse_work_doubles(ncx, ncy, N); else
+// it holds work_cap doubles, and the chunks of samples and of the QoI
+// partial sums are cut to fit (the caller has checked that one sample does).
 static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                                     double* mean, double* var, int32_t* status, double* work, hipStream_t st,
-                                    bool pg) {
+                                    bool pg, int64_t work_cap = 0) {
   const int nU = (ncx - 1) * (ncy - 1);
   if (pg ? ncx > COARSE_PG_BMAX : (ncx * (ncx + 1) / 2 > COARSE_THREADS * COARSE_NQ || ncx > COARSE_BMAX))
     return hipErrorInvalidValue;
@@ -612,7 +615,12 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
     const int need = pg ? (ncx * ncx + TH - 1) / TH : (ncx * (ncx + 1) / 2 + TH - 1) / TH;
     const size_t lds = coarse_lds_bytes(ncx, pg);
     // samples per launch (pair): the workspace holds their factors
-    const int64_t chunk = (!pg && ncx == ncy && ncx <= 8) ? coarse_chunk(ncx, ncy, N) : coarse_grid(N);
+    int64_t chunk = (!pg && ncx == ncy && ncx <= 8) ? coarse_chunk(ncx, ncy, N) : coarse_grid(N);
+    if (work_cap > 0) {
+      const int64_t per = (int64_t)nU * (ncx + 1) + 1;
+      if (per > work_cap) return hipErrorInvalidValue;
+      if (chunk > work_cap / per) chunk = work_cap / per;
+    }
     for (int64_t c = 0; c < N; c += chunk) {
       const int64_t n = N - c < chunk ? N - c : chunk;
       CoarseArgs a{ncx, ncy, n, S + c * (int64_t)ncx * ncy * ES, load, U + c * (int64_t)nU,
@@ -664,7 +672,13 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
     // the partial sums reuse the workspace of the factors (idle once the
     // backward passes, queued before on the same stream, are done):
     // 2 nch nU <= 3 min(N, 4096) nU doubles
-    const int64_t CS = qoi_chunk(N), nch = N > 0 ? (N + CS - 1) / CS : 0;
+    int64_t CS = qoi_chunk(N);
+    if (work_cap > 0 && N > 0) {  // 2 nch nU partial sums must fit
+      const int64_t nch_max = work_cap / (2 * (int64_t)nU);
+      if (nch_max < 1) return hipErrorInvalidValue;
+      if ((N + CS - 1) / CS > nch_max) CS = (N + nch_max - 1) / nch_max;
+    }
+    const int64_t nch = N > 0 ? (N + CS - 1) / CS : 0;
     if (nch > 0) {
       hipLaunchKernelGGL(qoi_partial_kernel, dim3((unsigned)((nU + 63) / 64), (unsigned)nch), dim3(64 * QOI_TY), 0,
                          st, N, nU, CS, U, work);
@@ -680,6 +694,15 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                          double* mean, double* var, int32_t* status, double* work, hipStream_t st) {
   return launch_coarse_any(ncx, ncy, N, S, load, U, mean, var, status, work, st, false);
+}
+
+// The same solve in a fixed workspace of work_cap doubles (samples and QoI
+// partial sums in chunks that fit).
+hipError_t launch_coarse_capped(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
+                                double* mean, double* var, int32_t* status, double* work, int64_t work_cap,
+                                hipStream_t st) {
+  if (work_cap < 1) return hipErrorInvalidValue;
+  return launch_coarse_any(ncx, ncy, N, S, load, U, mean, var, status, work, st, false, work_cap);
 }
 
 // Petrov-Galerkin coarse system: S16 [N][ncx*ncy][16], S[trial][test] per element.

@@ -101,6 +101,7 @@ def lib():
         "stomsfem_mlp_standardization": (C.c_int, [vp, vp, vp]),
         "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
         "stomsfem_mlp_gate": (C.c_int, [vp, vp, vp, i32, i64, dbl, vp, vp, vp, vp]),
+        "stomsfem_coarse_solve_noalloc": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
         "stomsfem_feature_map": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -371,6 +372,19 @@ def upscale_os(a: torch.Tensor, ncx: int, ncy: int, m: int, oversample: int, S: 
     b = make_batch(a, ncx, ncy, m, S, status, entries=16)
     _check("stomsfem_upscale_os", lib().stomsfem_upscale_os(C.byref(b), oversample, _stream(stream)))
     return S
+
+
+def coarse_solve_noalloc(S: torch.Tensor, ncx: int, ncy: int, U: torch.Tensor, qoi_mean: torch.Tensor | None = None,
+                         qoi_var: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                         load: torch.Tensor | None = None, stream=None):
+    """stomsfem_coarse_solve_noalloc: the coarse solve in the library's fixed
+    device scratch (the library allocates nothing; outputs are the caller's)."""
+    N = S.shape[0]
+    assert S.dtype == torch.float64 and S.shape == (N, ncx * ncy, 10)
+    assert U.dtype == torch.float64 and U.shape == (N, (ncx - 1) * (ncy - 1))
+    _check("stomsfem_coarse_solve_noalloc", lib().stomsfem_coarse_solve_noalloc(
+        ncx, ncy, N, _ptr(S), _ptr(load), _ptr(U), _ptr(qoi_mean), _ptr(qoi_var), _ptr(status), _stream(stream)))
+    return U, qoi_mean, qoi_var
 
 
 def coarse_solve_pg(S16: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None = None,

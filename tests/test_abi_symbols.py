@@ -94,3 +94,18 @@ def test_model_file_rejections_and_counters_on_host(tmp_path):
     assert e.value.code == stomsfem.EVERSION
     stomsfem.stats_reset()
     assert all(v == 0 for v in stomsfem.stats_get().values())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_noalloc_coarse_solve_validates_on_the_host():
+    # the entry point for callers that cannot allocate checks its arguments
+    # before touching a device: bad sizes, and a mesh beyond the coarse LDS window
+    lib = ctypes.CDLL(LIB)
+    f = lib.stomsfem_coarse_solve_noalloc
+    f.restype = ctypes.c_int
+    lib.stomsfem_last_error.restype = ctypes.c_char_p
+    args = [None] * 7
+    assert f(ctypes.c_int32(0), ctypes.c_int32(3), ctypes.c_int64(1), *args) == -1
+    assert b"bad sizes" in lib.stomsfem_last_error()
+    assert f(ctypes.c_int32(2000), ctypes.c_int32(3), ctypes.c_int64(1), *args) == -1
+    assert f(ctypes.c_int32(3), ctypes.c_int32(3), ctypes.c_int64(-1), *args) == -1
