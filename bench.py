@@ -50,6 +50,14 @@ def plain_flops_per_pair(m: int) -> float:
     return f
 
 
+def survey_flops_per_pair(m: int) -> float:
+    """The coarser count of the plain direct path per pair used for the
+    scope table's roofline estimate: banded factor n_I (b^2 + 2b), 3-rhs
+    solves 12 n_I b, band assembly 32 m^2, S 250 m (n_I = (m-1)^2, b = m)."""
+    nI, b = (m - 1) ** 2, m
+    return nI * (b * b + 2 * b) + 12 * nI * b + 32 * m * m + 250 * m
+
+
 def profiled_traffic_per_pair():
     """Calibrated HBM bytes per pair of the m = 32 upscaling kernel from the
     committed counter summary, or None when the kernel source has changed
@@ -68,13 +76,25 @@ def profiled_traffic_per_pair():
         return None
 
 
-def cpu_baseline(wl, budget_s: float = 15.0):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, budget_s: float = 25.0):
     import numpy as np
 
     import oracle
     from paper_1607_00693_amd import workloads as W
 
     threads = os.cpu_count() or 1
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
     nprobe = 2
     xi = W.uniform_xi(wl.nsamples, wl.nxi, wl.seed)
 
@@ -96,6 +116,8 @@ def cpu_baseline(wl, budget_s: float = 15.0):
         "kind": "oracle",
         "sample": f"first {ns} of {wl.nsamples} samples ({pairs} element-sample pairs): coefficient "
                   f"generation + upscaling + coarse solve, OpenMP over pairs, {t:.1f} s",
+        "cpu_model": _cpu_model(),
+        "build": "gcc -O3 -march=x86-64-v3 -fopenmp",
     }
 
 
@@ -298,6 +320,71 @@ def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((
            "audited": float((st == 2).float().mean()), "max_coarse_rel_err": u_err}
     log(f"surrogate on the benchmark mesh: {out}")
     mdl.free()
+    return out
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def measure_reduced_basis(wl, xi, S_plain, t_plain_ms, log, ntrain=40):
+    """Reduced basis (Sec. 3.2, Algorithms 3 and 4) on the benchmark mesh:
+    offline from ntrain plain training samples per patch (seed 2000 +
+    workload; the method of snapshots, with the snapshots from the refined
+    FP32/FP64 cell solver), then the FP32 matrix-core online stage on the
+    benchmark's own xi with FP32 coefficients, against the plain path from xi
+    (FP64 coefficient generation + upscaling, t_plain_ms)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    xi_tr = torch.from_numpy(W.uniform_xi(ntrain, wl.nxi, 2000 + wl.seed % 1000)).cuda()
+    a_tr = sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = sm.reduce(a_tr, wl.nc, wl.nc, wl.m, r_max=8, tail_tol=1e-6)
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t0
+    del a_tr
+    N = xi.shape[0]
+    a32 = torch.empty((N, wl.nfine, wl.nfine), dtype=torch.float32, device="cuda")
+    t_gen = _timed(lambda: sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), out=a32), reps=3)
+    S_rb = torch.empty_like(S_plain)
+    status = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sm.reduce_apply(model, a32, S=S_rb, status=status)
+    reps = 5
+    ev[0].record()
+    for _ in range(reps):
+        sm.reduce_apply(model, a32, S=S_rb, status=status)
+    ev[1].record()
+    ev[1].synchronize()
+    t_on = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    bad = int((status != 0).sum().item())
+    scale = S_plain.abs().amax(dim=2, keepdim=True)
+    s_err = float(((S_rb - S_plain).abs() / scale).max())
+    U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    U_r, _, _ = sm.coarse_solve(S_rb, wl.nc, wl.nc)
+    u_err = float((torch.linalg.norm(U_r - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())
+    pairs = N * wl.M
+    kd = ((wl.m * wl.m + 63) // 64) * 64
+    flops = 2.0 * kd * 80  # the GEMM row of one pair (padded table: 80 columns)
+    r = model.export("r")
+    out = {"workload": f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {ntrain} training samples/patch, r<=8 (tail 1e-6), "
+                       f"the benchmark's {N} samples with FP32 coefficients, FP32 MFMA GEMM "
+                       "[64 samples x m^2] x [m^2 x 80] per workgroup + FP64 8x8 solves",
+           "offline_s": t_off, "modes_min": int(r.min()), "modes_max": int(r.max()),
+           "online_ms": t_on * 1e3, "pairs_per_s": pairs / t_on,
+           "fp32_coef_generation_ms": t_gen * 1e3, "pairs_per_s_with_generation": pairs / (t_on + t_gen),
+           "plain_pairs_per_s": pairs / (t_plain_ms * 1e-3), "ratio": t_plain_ms * 1e-3 / t_on,
+           "ratio_with_generation": t_plain_ms * 1e-3 / (t_on + t_gen),
+           "mfma_flops_per_pair": flops, "achieved_tflops": flops * pairs / t_on / 1e12,
+           "fp32_mfma_peak_frac": flops * pairs / t_on / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+           "non_ok_pairs": bad, "max_S_rel_err": s_err, "max_coarse_rel_err": u_err}
+    log(f"reduced basis on the benchmark mesh: {out}")
+    model.free()
+    del a32, S_rb
+    torch.cuda.empty_cache()
     return out
 
 
@@ -761,6 +848,10 @@ def main():
     ap.add_argument("--nsamples", type=int, default=0, help="override the sample count (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of the extra measurements (ri_bench, rb_bench, surrogate_bench, "
+                         "mixed_bench, mesh8, channels, oversampling, collocation, two_level, gauss); "
+                         "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters in a profile)")
     args = ap.parse_args()
@@ -877,57 +968,72 @@ def main():
             "algorithmic_bytes": bytes_alg,
             "kernel": "local upscaling (FP64 VALU)",
             "flops_per_pair": plain_flops_per_pair(wl.m),
+            "frac_with_scope_table_count": survey_flops_per_pair(wl.m) * pairs / (t_up * 1e-3) / 1e12
+                                           / FP64_VALU_PEAK_TFLOPS,
+            "scope_table_flops_per_pair": survey_flops_per_pair(wl.m),
             "hbm_frac_algorithmic": bytes_alg / (t_up * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "cpu_baseline": None,
     }
     if not args.no_accelerations:
-        print("[bench] random interpolation at the benchmark mesh", file=sys.stderr, flush=True)
-        ri_out = measure_interpolation(wl, xi, S, t_gen + t_up, (5, 7),
-                                       lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
-                                       sg_levels=(4, 5))
-        ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
-                              "Chebyshev-Lobatto tensor nodes per local variable (k<=4) and Smolyak "
-                              "Clenshaw-Curtis sparse grids, FP64; plain side = coefficient generation + "
-                              "upscaling kernels")
-        print("[bench] learned surrogate at the benchmark mesh", file=sys.stderr, flush=True)
-        sur_out = measure_surrogate(wl, xi, S, t_gen + t_up,
-                                    lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print("[bench] FP32 factorisation + FP64 refinement on the first 64 samples", file=sys.stderr, flush=True)
-        ns = min(64, wl.nsamples)
-        a_sub, S_sub = a[:ns], S[:ns]
-        S_mx = torch.empty_like(S_sub)
-        st_mx = torch.empty((ns, wl.M), dtype=torch.int32, device=dev)
-        t_mx = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_mx, status=st_mx,
-                                               precision=stomsfem.PREC_F32_REFINE64), reps=2)
-        S_64 = torch.empty_like(S_sub)
-        t_64 = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_64), reps=2)
-        mixed = {"workload": f"first {ns} samples of the benchmark batch ({ns * wl.M} pairs)",
-                 "pairs_per_s": ns * wl.M / t_mx, "fp64_pairs_per_s": ns * wl.M / t_64, "ratio": t_64 / t_mx,
-                 "recomputed_fp64": int((st_mx == 1).sum().item()),
-                 "max_S_rel_err_vs_fp64": float(((S_mx - S_64).abs().amax(dim=2) / S_64.abs().amax(dim=2)).max())}
-        print(f"[bench] fp32+refinement: {mixed}", file=sys.stderr, flush=True)
+        lg = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
+        only = set(x for x in args.only.split(",") if x)
+        want = lambda name: not only or name in only  # noqa: E731
+        acc = {}
+        if want("ri_bench"):
+            lg("random interpolation at the benchmark mesh")
+            ri_out = measure_interpolation(wl, xi, S, t_gen + t_up, (5, 7), lg, sg_levels=(4, 5))
+            ri_out["workload"] = (f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.nsamples} samples (the benchmark's xi), "
+                                  "Chebyshev-Lobatto tensor nodes per local variable (k<=4) and Smolyak "
+                                  "Clenshaw-Curtis sparse grids, FP64; plain side = coefficient generation + "
+                                  "upscaling kernels")
+            acc["random_interpolation_bench_mesh"] = ri_out
+        if want("rb_bench"):
+            lg("reduced basis at the benchmark mesh")
+            acc["reduced_basis_bench_mesh"] = measure_reduced_basis(wl, xi, S, t_gen + t_up, lg)
+        if want("surrogate_bench"):
+            lg("learned surrogate at the benchmark mesh")
+            acc["learned_surrogate_bench_mesh"] = measure_surrogate(wl, xi, S, t_gen + t_up, lg)
+        if want("mixed_bench"):
+            lg("FP32 factorisation + FP64 refinement on the first 64 samples")
+            ns = min(64, wl.nsamples)
+            a_sub, S_sub = a[:ns], S[:ns]
+            S_mx = torch.empty_like(S_sub)
+            st_mx = torch.empty((ns, wl.M), dtype=torch.int32, device=dev)
+            t_mx = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_mx, status=st_mx,
+                                                   precision=stomsfem.PREC_F32_REFINE64), reps=2)
+            S_64 = torch.empty_like(S_sub)
+            t_64 = _timed(lambda: stomsfem.upscale(a_sub, wl.nc, wl.nc, wl.m, S=S_64), reps=2)
+            mixed = {"workload": f"first {ns} samples of the benchmark batch ({ns * wl.M} pairs)",
+                     "pairs_per_s": ns * wl.M / t_mx, "fp64_pairs_per_s": ns * wl.M / t_64, "ratio": t_64 / t_mx,
+                     "recomputed_fp64": int((st_mx == 1).sum().item()),
+                     "max_S_rel_err_vs_fp64": float(((S_mx - S_64).abs().amax(dim=2)
+                                                     / S_64.abs().amax(dim=2)).max())}
+            lg(f"fp32+refinement: {mixed}")
+            acc["fp32_solve_fp64_refinement_bench_mesh"] = mixed
         del a
         torch.cuda.empty_cache()
-        print("[bench] reduced basis and learned surrogate at the 8x8 mesh", file=sys.stderr, flush=True)
-        out["accelerations"] = measure_accelerations(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        out["accelerations"]["random_interpolation_bench_mesh"] = ri_out
-        out["accelerations"]["learned_surrogate_bench_mesh"] = sur_out
-        out["accelerations"]["fp32_solve_fp64_refinement_bench_mesh"] = mixed
-        print("[bench] channels-and-inclusions workload through a graph plan", file=sys.stderr, flush=True)
-        out["channels64_plan"] = measure_channels(lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print("[bench] oversampled Petrov-Galerkin upscaling at the 8x8 mesh", file=sys.stderr, flush=True)
-        out["oversampled_petrov_galerkin"] = measure_oversampling(
-            lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print("[bench] sparse-grid collocation with dictionaries at the 8x8 mesh", file=sys.stderr, flush=True)
-        lg = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
-        from paper_1607_00693_amd import workloads as W
-        out["sparse_grid_collocation"] = {"mesh8_level4": measure_collocation(lg, plain_chunk=1 << 20),
-                                          "bench_mesh_level2": measure_collocation(lg, W.MESH32, 2, errors=False)}
-        print("[bench] two-level Monte Carlo at the 8x8 mesh", file=sys.stderr, flush=True)
-        out["two_level_mc"] = measure_two_level(lg)
-        print("[bench] Gaussian medium and local KL", file=sys.stderr, flush=True)
-        out["gaussian_local_kl"] = measure_gauss(lg)
+        if want("mesh8"):
+            lg("reduced basis, interpolation and learned surrogate at the 8x8 mesh")
+            acc.update(measure_accelerations(lg))
+        out["accelerations"] = acc
+        if want("channels"):
+            lg("channels-and-inclusions workload through a graph plan")
+            out["channels64_plan"] = measure_channels(lg)
+        if want("oversampling"):
+            lg("oversampled Petrov-Galerkin upscaling at the 8x8 mesh")
+            out["oversampled_petrov_galerkin"] = measure_oversampling(lg)
+        if want("collocation"):
+            lg("sparse-grid collocation with dictionaries at the 8x8 mesh")
+            from paper_1607_00693_amd import workloads as W
+            out["sparse_grid_collocation"] = {"mesh8_level4": measure_collocation(lg, plain_chunk=1 << 20),
+                                              "bench_mesh_level2": measure_collocation(lg, W.MESH32, 2, errors=False)}
+        if want("two_level"):
+            lg("two-level Monte Carlo at the 8x8 mesh")
+            out["two_level_mc"] = measure_two_level(lg)
+        if want("gauss"):
+            lg("Gaussian medium and local KL")
+            out["gaussian_local_kl"] = measure_gauss(lg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -1306,13 +1306,18 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   if (!train || !model) return fail(STOMSFEM_EINVAL, "reduce: NULL argument");
   *model = nullptr;
   const stomsfem_batch& b = *train;
-  if (b.ncx < 1 || b.ncy < 1 || b.m < 2 || b.m > 16) return fail(STOMSFEM_EINVAL, "reduce: need 2 <= m <= 16");
+  if (b.ncx < 1 || b.ncy < 1 || b.m < 2 || b.m > 32) return fail(STOMSFEM_EINVAL, "reduce: need 2 <= m <= 32");
   if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, "reduce: bad a_dtype");
   if (b.nsamples < 1) return fail(STOMSFEM_EINVAL, "reduce: need at least one training sample");
   if (r_max < 1 || r_max > 8) return fail(STOMSFEM_EINVAL, "reduce: r_max must be in 1..8");
   if (!(tail_tol >= 0.0)) return fail(STOMSFEM_EINVAL, "reduce: tail_tol must be >= 0");
   if (!device_ptr(b.a)) return fail(STOMSFEM_EINVAL, "reduce: a is not a device pointer");
   const int m = b.m, nI = (m - 1) * (m - 1), Mc = b.ncx * b.ncy;
+  if (b.nsamples > 341 || (!rb_dual(m, (int)b.nsamples) && nI > 1024))
+    return fail(STOMSFEM_EINVAL, "reduce: the eigenproblem (the smaller of (m-1)^2 and 3 ntrain) must be <= 1024, "
+                                 "and ntrain <= 341");
+  if (b.nsamples * (int64_t)Mc > (int64_t{1} << 31))
+    return fail(STOMSFEM_EINVAL, "reduce: too many training pairs");
   hipStream_t st = (hipStream_t)stream;
   auto* md = new stomsfem_model();
   md->kind = 1;
@@ -1336,16 +1341,52 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   A((void**)&md->G32, sizeof(float) * (size_t)Mc * md->KD * md->PP);
   A((void**)&md->G64, sizeof(double) * (size_t)Mc * md->KD * md->PP);
   A((void**)&phi, sizeof(double) * (size_t)b.nsamples * Mc * 3 * nI);
-  A((void**)&work, sizeof(double) * (size_t)Mc * 4 * nI * nI);
+  A((void**)&work, sizeof(double) * (size_t)rb_work_doubles(b.ncx, b.ncy, m, (int)b.nsamples));
+  // snapshots through the refined kernel where the FP64 band does not fit LDS
+  const bool refined_phi = cell_phi_lds_bytes(m) > 64 * 1024;
+  int64_t* fail_list = nullptr;
+  unsigned long long* fail_count = nullptr;
+  if (refined_phi) {
+    A((void**)&fail_list, sizeof(int64_t) * (size_t)b.nsamples * Mc);
+    A((void**)&fail_count, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemsetAsync(fail_count, 0, sizeof(unsigned long long), st);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     hipFree(phi);
     hipFree(work);
+    hipFree(fail_list);
+    hipFree(fail_count);
     model_release(md);
     return fail(STOMSFEM_ENOMEM, "reduce: device allocation failed");
   }
   UpArgs up = to_args(b);
-  e = launch_cell_phi(up, b.a_dtype, phi, st);
+  up.S = nullptr;
+  up.status = nullptr;
+  unsigned long long nfail = 0;
+  if (refined_phi) {
+    MixedArgs ma{};
+    ma.up = up;
+    ma.tol = STOMSFEM_REFINE_TOL * 1e-2;
+    ma.max_iter = 2 * STOMSFEM_REFINE_MAXIT;
+    ma.list = fail_list;
+    ma.count = fail_count;
+    ma.phi = phi;
+    e = launch_upscale_mixed(ma, b.a_dtype, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nfail, fail_count, sizeof(nfail), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  } else {
+    e = launch_cell_phi(up, b.a_dtype, phi, st);
+  }
+  if (e == hipSuccess && nfail > 0) {
+    hipFree(phi);
+    hipFree(work);
+    hipFree(fail_list);
+    hipFree(fail_count);
+    model_release(md);
+    return fail(STOMSFEM_ENOCONV, "reduce: " + std::to_string(nfail) +
+                                      " training cell problems did not converge in the refined solver");
+  }
   if (e == hipSuccess) {
     RbBuildArgs ba{};
     ba.ncx = b.ncx;
@@ -1373,6 +1414,8 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   hipFree(phi);
   hipFree(work);
+  hipFree(fail_list);
+  hipFree(fail_count);
   if (e != hipSuccess) {
     model_release(md);
     return hip_fail(e, "reduce");
@@ -1392,7 +1435,8 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
   if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32)
     return fail(STOMSFEM_EINVAL, "reduce_apply: precision must be STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32");
   const bool f64 = precision == STOMSFEM_PREC_F64;
-  if (!f64 && model->m != 8) return fail(STOMSFEM_EINVAL, "reduce_apply: the MFMA online stage needs m = 8");
+  if (!f64 && (model->KD % 64 != 0 || model->PP != 80))
+    return fail(STOMSFEM_EINVAL, "reduce_apply: the model's table layout does not serve the MFMA stage (FP64 only)");
   if (batch->nsamples == 0) return STOMSFEM_OK;
   RbApplyArgs ra{};
   ra.up = to_args(*batch);

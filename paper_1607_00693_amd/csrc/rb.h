@@ -22,7 +22,7 @@ struct RbBuildArgs {
   const void* a;   // training coefficients [ntrain][ncy*m][ncx*m]
   int32_t a_dtype;
   const double* phi;   // [ntrain][M][3][nI]
-  double* work;        // [M][4][nI*nI]
+  double* work;        // rb_work_doubles(...) doubles
   double* Z;           // [M][nI][rmax]
   double* phibar;      // [M][3][nI]
   double* lambda;      // [M][nI] eigenvalues, descending
@@ -44,6 +44,10 @@ struct RbApplyArgs {
 hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStream_t st);
 size_t cell_phi_lds_bytes(int m);
 hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st);
+// Work doubles of the offline build and whether it takes the dual form (the
+// method of snapshots, 3 ntrain < (m-1)^2).
+int64_t rb_work_doubles(int ncx, int ncy, int m, int ntrain);
+bool rb_dual(int m, int ntrain);
 hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStream_t st);
 int rb_pad_p(int rmax);
 int rb_pad_kd(int m);

@@ -5,14 +5,21 @@
 //   cell_phi_kernel  -- the cell-problem solutions phi^l(xi_s), l = 0..2, on
 //                       the interior nodes (banded LDL^T in LDS, one
 //                       wavefront per pair, forward and backward solves);
-//   rb_build_kernel  -- one workgroup per patch: mean phibar^l, centred
-//                       snapshot Gram H = Psi Psi^T, energy matrix
-//                       E = K_II(abar) = L_E L_E^T with abar the training mean
-//                       of the coefficient, C = L_E^T H L_E (the Gram matrix of
-//                       the KL expansion in the energy inner product), cyclic
+//                       where that band does not fit LDS the refined
+//                       FP32/FP64 kernel of upscale_mixed.hip supplies them;
+//   rb_build_kernel  -- primal form (3 N_train >= nI), one workgroup per
+//                       patch: mean phibar^l, centred snapshot Gram
+//                       H = Psi Psi^T, energy matrix E = K_II(abar) =
+//                       L_E L_E^T with abar the training mean of the
+//                       coefficient, C = L_E^T H L_E (the Gram matrix of the
+//                       KL expansion in the energy inner product), cyclic
 //                       Jacobi eigen-decomposition C = V Lambda V^T, the tail
 //                       rule for r, modes Z = L_E^{-T} V_r (Z^T E Z = I), and
-//                       the element table G.
+//                       the element table G;
+//   rb_dual_*        -- dual form (3 N_train < nI, the method of snapshots):
+//                       W = E Psi, the ns x ns Gram C = Psi^T W in tiles,
+//                       its eigenpairs, modes z_q = Psi v_q / sqrt(lambda_q)
+//                       (the same KL subspace and eigenvalues), the table G.
 // The Q1 stiffness is affine in the per-element coefficient values
 // (K(a) = sum_e a_e K_e), which is the paper's affine structure taken at
 // element level: every quantity of the online Galerkin system is a linear
@@ -135,120 +142,34 @@ hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStre
 }
 
 // ---------------------------------------------------------------------------
-// Offline build, one workgroup per patch
+// Offline build
 // ---------------------------------------------------------------------------
 constexpr int RB_THREADS = 256;
+constexpr int RB_NMAX = 1024;  // largest eigenproblem (primal nI or dual 3 ntrain)
 
-template <typename TA>
-__global__ __launch_bounds__(RB_THREADS) void rb_build_kernel(RbBuildArgs b) {
-  const int K = blockIdx.x;
-  const int m = b.m, n = m - 1, nI = n * n, Mc = b.ncx * b.ncy, rmax = b.rmax;
+// Cyclic Jacobi on the symmetric n x n matrix H (global, overwritten by its
+// rotated form, whose diagonal ends up holding the eigenvalues); V receives
+// the eigenvectors as columns.  Rotations in the (p, q) planes (Golub and
+// Van Loan's symmetric Schur pair) until the off-diagonal mass is below
+// 1e-30 of the diagonal's.  Whole workgroup.
+__device__ void rb_jacobi(double* H, double* V, int n, int max_sweeps, double* red, double* rot) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int kx = K % b.ncx, ky = K / b.ncx;
-  const int64_t lda = (int64_t)b.ncx * m;
-  double* H = b.work + (int64_t)K * 4 * nI * nI;  // snapshot Gram, then C
-  double* E = H + nI * nI;                        // energy matrix, then its Cholesky factor L_E
-  double* V = E + nI * nI;                        // eigenvectors
-  double* T = V + nI * nI;                        // scratch
-  double* pbar = b.phibar + (int64_t)K * 3 * nI;
-  __shared__ double abar[64 * 64];
-  __shared__ double rot[3];
-  __shared__ double red[RB_THREADS];
-  __shared__ int order[1024];
-  __shared__ int rsel;
-
-  // 1. training means of the coefficient and of the snapshots
-  for (int e = tid; e < m * m; e += nt) {
-    const int ex = e % m, ey = e / m;
-    double acc = 0.0;
-    for (int s = 0; s < b.ntrain; ++s) {
-      const TA* a = (const TA*)b.a + (int64_t)s * (b.ncy * m) * lda;
-      acc += ld(a, (int64_t)(ky * m + ey) * lda + kx * m + ex);
-    }
-    abar[e] = acc / b.ntrain;
-  }
-  for (int i = tid; i < 3 * nI; i += nt) {
-    double acc = 0.0;
-    for (int s = 0; s < b.ntrain; ++s) acc += b.phi[((int64_t)s * Mc + K) * 3 * nI + i];
-    pbar[i] = acc / b.ntrain;
-  }
+  for (int ij = tid; ij < n * n; ij += nt) V[ij] = (ij / n == ij % n) ? 1.0 : 0.0;
   __syncthreads();
-  // 2. H = sum over centred snapshots (all samples, l = 0..2)
-  for (int ij = tid; ij < nI * nI; ij += nt) {
-    const int i = ij / nI, j = ij % nI;
-    if (j < i) continue;
-    double acc = 0.0;
-    for (int s = 0; s < b.ntrain; ++s) {
-      const double* ph = b.phi + ((int64_t)s * Mc + K) * 3 * nI;
-      for (int l = 0; l < 3; ++l) acc += (ph[l * nI + i] - pbar[l * nI + i]) * (ph[l * nI + j] - pbar[l * nI + j]);
-    }
-    H[i * nI + j] = acc;
-    H[j * nI + i] = acc;
-  }
-  // 3. E = K_II(abar), dense
-  for (int ij = tid; ij < nI * nI; ij += nt) E[ij] = 0.0;
-  __syncthreads();
-  for (int r = tid; r < nI; r += nt) {
-    const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
-    const double aSW = abar[iy * m + ix], aSE = abar[iy * m + ix + 1];
-    const double aNW = abar[(iy + 1) * m + ix], aNE = abar[(iy + 1) * m + ix + 1];
-    E[r * nI + r] = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
-    const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-    const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
-    const double ks[8] = {-(aSW + aNW) / 6.0, -(aSE + aNE) / 6.0, -(aSW + aSE) / 6.0, -(aNW + aNE) / 6.0,
-                          -aSW / 3.0,         -aSE / 3.0,         -aNW / 3.0,         -aNE / 3.0};
-    for (int q = 0; q < 8; ++q) {
-      const int qx = px + dxs[q], qy = py + dys[q];
-      if (qx >= 1 && qx <= n && qy >= 1 && qy <= n) E[r * nI + (qy - 1) * n + (qx - 1)] = ks[q];
-    }
-  }
-  __syncthreads();
-  // 4. E = L_E L_E^T in place (lower triangle), right looking
-  for (int j = 0; j < nI; ++j) {
-    if (tid == 0) E[j * nI + j] = sqrt(E[j * nI + j]);
-    __syncthreads();
-    const double ljj = E[j * nI + j];
-    for (int i = j + 1 + tid; i < nI; i += nt) E[i * nI + j] /= ljj;
-    __syncthreads();
-    for (int ik = tid; ik < (nI - j - 1) * (nI - j - 1); ik += nt) {
-      const int i = j + 1 + ik / (nI - j - 1), k = j + 1 + ik % (nI - j - 1);
-      if (k <= i) E[i * nI + k] -= E[i * nI + j] * E[k * nI + j];
-    }
-    __syncthreads();
-  }
-  // 5. C = L_E^T H L_E  (T = H L_E, then C = L_E^T T, stored in H)
-  for (int ij = tid; ij < nI * nI; ij += nt) {
-    const int i = ij / nI, j = ij % nI;
-    double acc = 0.0;
-    for (int k = j; k < nI; ++k) acc += H[i * nI + k] * E[k * nI + j];
-    T[ij] = acc;
-  }
-  __syncthreads();
-  for (int ij = tid; ij < nI * nI; ij += nt) {
-    const int i = ij / nI, j = ij % nI;
-    double acc = 0.0;
-    for (int k = i; k < nI; ++k) acc += E[k * nI + i] * T[k * nI + j];
-    H[ij] = acc;
-  }
-  for (int ij = tid; ij < nI * nI; ij += nt) V[ij] = (ij / nI == ij % nI) ? 1.0 : 0.0;
-  __syncthreads();
-  // symmetrise (rounding)
-  for (int ij = tid; ij < nI * nI; ij += nt) {
-    const int i = ij / nI, j = ij % nI;
+  for (int ij = tid; ij < n * n; ij += nt) {  // symmetrise (rounding)
+    const int i = ij / n, j = ij % n;
     if (j > i) {
-      const double v = 0.5 * (H[i * nI + j] + H[j * nI + i]);
-      H[i * nI + j] = v;
-      H[j * nI + i] = v;
+      const double v = 0.5 * (H[i * n + j] + H[j * n + i]);
+      H[i * n + j] = v;
+      H[j * n + i] = v;
     }
   }
   __syncthreads();
-  // 6. cyclic Jacobi: rotations in the (p, q) planes until the off-diagonal
-  //    mass is negligible against the diagonal
-  for (int sweep = 0; sweep < b.max_sweeps; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int ij = tid; ij < nI * nI; ij += nt) {
+    for (int ij = tid; ij < n * n; ij += nt) {
       const double v = H[ij] * H[ij];
-      if (ij / nI == ij % nI) dia += v; else off += v;
+      if (ij / n == ij % n) dia += v; else off += v;
     }
     red[tid] = off;
     __syncthreads();
@@ -267,13 +188,13 @@ __global__ __launch_bounds__(RB_THREADS) void rb_build_kernel(RbBuildArgs b) {
     const double dias = red[0];
     __syncthreads();
     if (!(offs > 1e-30 * dias)) break;
-    for (int p = 0; p < nI - 1; ++p)
-      for (int q = p + 1; q < nI; ++q) {
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
         if (tid == 0) {
-          const double apq = H[p * nI + q];
+          const double apq = H[p * n + q];
           double c = 1.0, s = 0.0;
           if (apq != 0.0) {
-            const double tau = (H[q * nI + q] - H[p * nI + p]) / (2.0 * apq);
+            const double tau = (H[q * n + q] - H[p * n + p]) / (2.0 * apq);
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
@@ -284,74 +205,67 @@ __global__ __launch_bounds__(RB_THREADS) void rb_build_kernel(RbBuildArgs b) {
         __syncthreads();
         const double c = rot[0], s = rot[1];
         if (s != 0.0) {
-          for (int k = tid; k < nI; k += nt) {
-            const double hp = H[k * nI + p], hq = H[k * nI + q];
-            H[k * nI + p] = c * hp - s * hq;
-            H[k * nI + q] = s * hp + c * hq;
-            const double vp = V[k * nI + p], vq = V[k * nI + q];
-            V[k * nI + p] = c * vp - s * vq;
-            V[k * nI + q] = s * vp + c * vq;
+          for (int k = tid; k < n; k += nt) {
+            const double hp = H[k * n + p], hq = H[k * n + q];
+            H[k * n + p] = c * hp - s * hq;
+            H[k * n + q] = s * hp + c * hq;
+            const double vp = V[k * n + p], vq = V[k * n + q];
+            V[k * n + p] = c * vp - s * vq;
+            V[k * n + q] = s * vp + c * vq;
           }
           __syncthreads();
-          for (int k = tid; k < nI; k += nt) {
-            const double hp = H[p * nI + k], hq = H[q * nI + k];
-            H[p * nI + k] = c * hp - s * hq;
-            H[q * nI + k] = s * hp + c * hq;
+          for (int k = tid; k < n; k += nt) {
+            const double hp = H[p * n + k], hq = H[q * n + k];
+            H[p * n + k] = c * hp - s * hq;
+            H[q * n + k] = s * hp + c * hq;
           }
         }
         __syncthreads();
       }
   }
-  // 7. eigenvalues in descending order and the tail rule
-  if (tid == 0) {
-    for (int i = 0; i < nI; ++i) order[i] = i;
-    for (int i = 0; i < nI; ++i) {  // selection sort (nI is small)
-      int best = i;
-      for (int j = i + 1; j < nI; ++j)
-        if (H[order[j] * nI + order[j]] > H[order[best] * nI + order[best]]) best = j;
-      const int t = order[i];
-      order[i] = order[best];
-      order[best] = t;
-    }
-    double tot = 0.0;
-    for (int i = 0; i < nI; ++i) tot += fmax(H[order[i] * nI + order[i]], 0.0);
-    int r = nI;
-    double tail = tot;
-    for (int q = 1; q <= nI; ++q) {
-      tail -= fmax(H[order[q - 1] * nI + order[q - 1]], 0.0);
-      const double rel = tot > 0 ? sqrt(fmax(tail, 0.0) / tot) : 0.0;
-      if (rel <= b.tail_tol) {
-        r = q;
-        break;
-      }
-    }
-    if (r > b.rcap) r = b.rcap;
-    if (r > rmax) r = rmax;
-    if (r > nI) r = nI;
-    rsel = r;
-    b.rK[K] = r;
-    for (int i = 0; i < nI; ++i) b.lambda[(int64_t)K * nI + i] = H[order[i] * nI + order[i]];
+}
+
+// Eigenvalues (the diagonal of the rotated H) in descending order into
+// order[] / lambda[0..nlam) (zeros beyond n), and the number of modes:
+// r = min(rcap, rmax, n, smallest r whose relative tail
+// sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol).  Thread 0; the
+// caller synchronises.
+__device__ int rb_sort_tail(const double* H, int n, int* order, double tail_tol, int rcap, int rmax, double* lambda,
+                            int nlam) {
+  for (int i = 0; i < n; ++i) order[i] = i;
+  for (int i = 0; i < n; ++i) {  // selection sort
+    int best = i;
+    for (int j = i + 1; j < n; ++j)
+      if (H[order[j] * n + order[j]] > H[order[best] * n + order[best]]) best = j;
+    const int t = order[i];
+    order[i] = order[best];
+    order[best] = t;
   }
-  __syncthreads();
-  const int r = rsel;
-  // 8. Z = L_E^{-T} V_r (backward substitution per column), zero beyond r
-  double* Zk = b.Z + (int64_t)K * nI * rmax;
-  for (int q = tid; q < rmax; q += nt) {
-    if (q >= r) {
-      for (int i = 0; i < nI; ++i) Zk[i * rmax + q] = 0.0;
-      continue;
-    }
-    const int col = order[q];
-    for (int i = nI - 1; i >= 0; --i) {
-      double v = V[i * nI + col];
-      for (int k = i + 1; k < nI; ++k) v -= E[k * nI + i] * Zk[k * rmax + q];
-      Zk[i * rmax + q] = v / E[i * nI + i];
+  double tot = 0.0;
+  for (int i = 0; i < n; ++i) tot += fmax(H[order[i] * n + order[i]], 0.0);
+  int r = n;
+  double tail = tot;
+  for (int q = 1; q <= n; ++q) {
+    tail -= fmax(H[order[q - 1] * n + order[q - 1]], 0.0);
+    const double rel = tot > 0 ? sqrt(fmax(tail, 0.0) / tot) : 0.0;
+    if (rel <= tail_tol) {
+      r = q;
+      break;
     }
   }
-  __syncthreads();
-  // 9. element table G
+  if (r > rcap) r = rcap;
+  if (r > rmax) r = rmax;
+  if (r > n) r = n;
+  for (int i = 0; i < nlam; ++i) lambda[i] = i < n ? H[order[i] * n + order[i]] : 0.0;
+  return r;
+}
+
+// Element table G of patch K from its modes Zk [nI][rmax] and means pbar
+// [3][nI] (see the header comment for the P coefficients).  Whole workgroup.
+__device__ void rb_g_table(const RbBuildArgs& b, int K, const double* Zk, const double* pbar) {
+  const int m = b.m, n = m - 1, nI = n * n, rmax = b.rmax;
   const int PP = b.PP, KD = b.KD, NA = rb_na(rmax);
-  for (int ep = tid; ep < KD * PP; ep += nt) {
+  for (int ep = threadIdx.x; ep < KD * PP; ep += blockDim.x) {
     const int e = ep / PP, pidx = ep % PP;
     double val = 0.0;
     if (e < m * m && pidx < rb_p(rmax)) {
@@ -389,12 +303,324 @@ __global__ __launch_bounds__(RB_THREADS) void rb_build_kernel(RbBuildArgs b) {
   }
 }
 
-hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st) {
+// Training means of the coefficient (abar, m*m values) and of the snapshots
+// (phibar).  Whole workgroup.
+template <typename TA>
+__device__ void rb_means(const RbBuildArgs& b, int K, double* abar, double* pbar) {
+  const int m = b.m, nI = (m - 1) * (m - 1), Mc = b.ncx * b.ncy;
+  const int kx = K % b.ncx, ky = K / b.ncx;
+  const int64_t lda = (int64_t)b.ncx * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int ex = e % m, ey = e / m;
+    double acc = 0.0;
+    for (int s = 0; s < b.ntrain; ++s) {
+      const TA* a = (const TA*)b.a + (int64_t)s * (b.ncy * m) * lda;
+      acc += ld(a, (int64_t)(ky * m + ey) * lda + kx * m + ex);
+    }
+    abar[e] = acc / b.ntrain;
+  }
+  for (int i = threadIdx.x; i < 3 * nI; i += blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < b.ntrain; ++s) acc += b.phi[((int64_t)s * Mc + K) * 3 * nI + i];
+    pbar[i] = acc / b.ntrain;
+  }
+}
+
+// The 9-point row of K_II(abar) at interior node r: diagonal in ks[8]'s
+// companion kc, the eight neighbour couplings ks[q] at offsets (dxs, dys).
+struct Stencil9 {
+  double kc, ks[8];
+};
+__device__ constexpr int RB_DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+__device__ constexpr int RB_DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+__device__ __forceinline__ Stencil9 rb_stencil(const double* abar, int m, int ix, int iy) {
+  const double aSW = abar[iy * m + ix], aSE = abar[iy * m + ix + 1];
+  const double aNW = abar[(iy + 1) * m + ix], aNE = abar[(iy + 1) * m + ix + 1];
+  Stencil9 st;
+  st.kc = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+  st.ks[0] = -(aSW + aNW) / 6.0;
+  st.ks[1] = -(aSE + aNE) / 6.0;
+  st.ks[2] = -(aSW + aSE) / 6.0;
+  st.ks[3] = -(aNW + aNE) / 6.0;
+  st.ks[4] = -aSW / 3.0;
+  st.ks[5] = -aSE / 3.0;
+  st.ks[6] = -aNW / 3.0;
+  st.ks[7] = -aNE / 3.0;
+  return st;
+}
+
+// Primal form (3 ntrain >= nI), one workgroup per patch: the nI x nI
+// snapshot Gram H = Psi Psi^T, E = K_II(abar) = L_E L_E^T (dense), the KL
+// matrix C = L_E^T H L_E, its eigenpairs, modes Z = L_E^{-T} V_r.
+template <typename TA>
+__global__ __launch_bounds__(RB_THREADS) void rb_build_kernel(RbBuildArgs b) {
+  const int K = blockIdx.x;
+  const int m = b.m, n = m - 1, nI = n * n, Mc = b.ncx * b.ncy, rmax = b.rmax;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* H = b.work + (int64_t)K * 4 * nI * nI;  // snapshot Gram, then C
+  double* E = H + nI * nI;                        // energy matrix, then its Cholesky factor L_E
+  double* V = E + nI * nI;                        // eigenvectors
+  double* T = V + nI * nI;                        // scratch
+  double* pbar = b.phibar + (int64_t)K * 3 * nI;
+  __shared__ double abar[64 * 64];
+  __shared__ double rot[3];
+  __shared__ double red[RB_THREADS];
+  __shared__ int order[RB_NMAX];
+  __shared__ int rsel;
+
+  // 1. training means of the coefficient and of the snapshots
+  rb_means<TA>(b, K, abar, pbar);
+  __syncthreads();
+  // 2. H = sum over centred snapshots (all samples, l = 0..2)
+  for (int ij = tid; ij < nI * nI; ij += nt) {
+    const int i = ij / nI, j = ij % nI;
+    if (j < i) continue;
+    double acc = 0.0;
+    for (int s = 0; s < b.ntrain; ++s) {
+      const double* ph = b.phi + ((int64_t)s * Mc + K) * 3 * nI;
+      for (int l = 0; l < 3; ++l) acc += (ph[l * nI + i] - pbar[l * nI + i]) * (ph[l * nI + j] - pbar[l * nI + j]);
+    }
+    H[i * nI + j] = acc;
+    H[j * nI + i] = acc;
+  }
+  // 3. E = K_II(abar), dense
+  for (int ij = tid; ij < nI * nI; ij += nt) E[ij] = 0.0;
+  __syncthreads();
+  for (int r = tid; r < nI; r += nt) {
+    const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+    const Stencil9 st = rb_stencil(abar, m, ix, iy);
+    E[r * nI + r] = st.kc;
+    for (int q = 0; q < 8; ++q) {
+      const int qx = px + RB_DX[q], qy = py + RB_DY[q];
+      if (qx >= 1 && qx <= n && qy >= 1 && qy <= n) E[r * nI + (qy - 1) * n + (qx - 1)] = st.ks[q];
+    }
+  }
+  __syncthreads();
+  // 4. E = L_E L_E^T in place (lower triangle), right looking
+  for (int j = 0; j < nI; ++j) {
+    if (tid == 0) E[j * nI + j] = sqrt(E[j * nI + j]);
+    __syncthreads();
+    const double ljj = E[j * nI + j];
+    for (int i = j + 1 + tid; i < nI; i += nt) E[i * nI + j] /= ljj;
+    __syncthreads();
+    for (int ik = tid; ik < (nI - j - 1) * (nI - j - 1); ik += nt) {
+      const int i = j + 1 + ik / (nI - j - 1), k = j + 1 + ik % (nI - j - 1);
+      if (k <= i) E[i * nI + k] -= E[i * nI + j] * E[k * nI + j];
+    }
+    __syncthreads();
+  }
+  // 5. C = L_E^T H L_E  (T = H L_E, then C = L_E^T T, stored in H)
+  for (int ij = tid; ij < nI * nI; ij += nt) {
+    const int i = ij / nI, j = ij % nI;
+    double acc = 0.0;
+    for (int k = j; k < nI; ++k) acc += H[i * nI + k] * E[k * nI + j];
+    T[ij] = acc;
+  }
+  __syncthreads();
+  for (int ij = tid; ij < nI * nI; ij += nt) {
+    const int i = ij / nI, j = ij % nI;
+    double acc = 0.0;
+    for (int k = i; k < nI; ++k) acc += E[k * nI + i] * T[k * nI + j];
+    H[ij] = acc;
+  }
+  __syncthreads();
+  // 6. eigenpairs of C
+  rb_jacobi(H, V, nI, b.max_sweeps, red, rot);
+  // 7. eigenvalues in descending order and the tail rule
+  if (tid == 0) {
+    rsel = rb_sort_tail(H, nI, order, b.tail_tol, b.rcap, rmax, b.lambda + (int64_t)K * nI, nI);
+    b.rK[K] = rsel;
+  }
+  __syncthreads();
+  const int r = rsel;
+  // 8. Z = L_E^{-T} V_r (backward substitution per column), zero beyond r
+  double* Zk = b.Z + (int64_t)K * nI * rmax;
+  for (int q = tid; q < rmax; q += nt) {
+    if (q >= r) {
+      for (int i = 0; i < nI; ++i) Zk[i * rmax + q] = 0.0;
+      continue;
+    }
+    const int col = order[q];
+    for (int i = nI - 1; i >= 0; --i) {
+      double v = V[i * nI + col];
+      for (int k = i + 1; k < nI; ++k) v -= E[k * nI + i] * Zk[k * rmax + q];
+      Zk[i * rmax + q] = v / E[i * nI + i];
+    }
+  }
+  __syncthreads();
+  // 9. element table G
+  rb_g_table(b, K, Zk, pbar);
+}
+
+// Dual form, the method of snapshots (3 ntrain < nI): with Psi the nI x ns
+// matrix of centred snapshots (ns = 3 ntrain, column c = 3 s + l), the KL
+// expansion in the energy inner product of E = K_II(abar) is the
+// eigen-decomposition of the ns x ns Gram matrix C = Psi^T E Psi = V Lambda
+// V^T (the same nonzero eigenvalues as the primal C = L_E^T Psi Psi^T L_E),
+// and the modes are z_q = Psi v_q / sqrt(lambda_q), so that Z^T E Z = I.
+// Three steps over the patches: W = E Psi (work layout [K][c][i]), the Gram
+// C = Psi^T W in 64 x 64 tiles, then per patch the eigenpairs, modes and G.
+struct RbDual {
+  int ns;
+  double* abar;  // [M][m*m]
+  double* W;     // [M][ns][nI]
+  double* C;     // [M][ns][ns]
+  double* V;     // [M][ns][ns]
+};
+
+__device__ __forceinline__ double rb_psi(const RbBuildArgs& b, int K, int c, int i, int nI) {
+  const int s = c / 3, l = c - 3 * (c / 3);
   const int Mc = b.ncx * b.ncy;
+  return b.phi[(((int64_t)s * Mc + K) * 3 + l) * nI + i] - b.phibar[((int64_t)K * 3 + l) * nI + i];
+}
+
+template <typename TA>
+__global__ __launch_bounds__(RB_THREADS) void rb_dual_means_kernel(RbBuildArgs b, RbDual d) {
+  const int K = blockIdx.x, m = b.m, nI = (m - 1) * (m - 1);
+  rb_means<TA>(b, K, d.abar + (int64_t)K * m * m, b.phibar + (int64_t)K * 3 * nI);
+}
+
+// W[c][i] = (E Psi)_{i c}: one thread per interior node i, all columns c.
+__global__ __launch_bounds__(RB_THREADS) void rb_dual_energy_kernel(RbBuildArgs b, RbDual d) {
+  const int K = blockIdx.y, m = b.m, n = m - 1, nI = n * n;
+  const int i = blockIdx.x * RB_THREADS + threadIdx.x;
+  if (i >= nI) return;
+  const int ix = i % n, iy = i / n, px = ix + 1, py = iy + 1;
+  const Stencil9 st = rb_stencil(d.abar + (int64_t)K * m * m, m, ix, iy);
+  int nb[8];
+  for (int q = 0; q < 8; ++q) {
+    const int qx = px + RB_DX[q], qy = py + RB_DY[q];
+    nb[q] = (qx >= 1 && qx <= n && qy >= 1 && qy <= n) ? (qy - 1) * n + (qx - 1) : -1;
+  }
+  double* W = d.W + (int64_t)K * d.ns * nI;
+  for (int c = 0; c < d.ns; ++c) {
+    double v = st.kc * rb_psi(b, K, c, i, nI);
+    for (int q = 0; q < 8; ++q)
+      if (nb[q] >= 0) v += st.ks[q] * rb_psi(b, K, c, nb[q], nI);
+    W[(int64_t)c * nI + i] = v;
+  }
+}
+
+// C = Psi^T W in 64 x 64 tiles (upper tiles computed, mirrored): the k loop
+// over the interior nodes in chunks of 32 staged in LDS; each thread
+// accumulates a 4 x 4 block of the tile.
+constexpr int RBG_T = 64, RBG_K = 32;
+__global__ __launch_bounds__(RB_THREADS) void rb_dual_gram_kernel(RbBuildArgs b, RbDual d) {
+  const int K = blockIdx.y, m = b.m, nI = (m - 1) * (m - 1), ns = d.ns;
+  const int nt = (ns + RBG_T - 1) / RBG_T;
+  int t = blockIdx.x, tc = 0;
+  while (t >= nt - tc) {  // upper-triangle tile index -> (tc, td), tc <= td
+    t -= nt - tc;
+    ++tc;
+  }
+  const int td = tc + t;
+  __shared__ double Ps[RBG_K][RBG_T + 1], Ws[RBG_K][RBG_T + 1];
+  const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+  const double* W = d.W + (int64_t)K * ns * nI;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < nI; k0 += RBG_K) {
+    for (int idx = tid; idx < RBG_K * RBG_T; idx += RB_THREADS) {
+      const int kk = idx % RBG_K, cc = idx / RBG_K;
+      const int c = tc * RBG_T + cc, dd = td * RBG_T + cc, i = k0 + kk;
+      Ps[kk][cc] = (c < ns && i < nI) ? rb_psi(b, K, c, i, nI) : 0.0;
+      Ws[kk][cc] = (dd < ns && i < nI) ? W[(int64_t)dd * nI + i] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < RBG_K; ++kk) {
+      double pv[4], wv[4];
+      for (int u = 0; u < 4; ++u) {
+        pv[u] = Ps[kk][4 * ty + u];
+        wv[u] = Ws[kk][4 * tx + u];
+      }
+      for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] += pv[u] * wv[v];
+    }
+    __syncthreads();
+  }
+  double* C = d.C + (int64_t)K * ns * ns;
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      const int c = tc * RBG_T + 4 * ty + u, dd = td * RBG_T + 4 * tx + v;
+      if (c < ns && dd < ns) {
+        C[(int64_t)c * ns + dd] = acc[u][v];
+        if (tc != td) C[(int64_t)dd * ns + c] = acc[u][v];
+      }
+    }
+}
+
+// Per patch: eigenpairs of C, the tail rule, modes z_q = Psi v_q /
+// sqrt(lambda_q) (zero beyond r), the element table.
+__global__ __launch_bounds__(RB_THREADS) void rb_dual_finish_kernel(RbBuildArgs b, RbDual d) {
+  const int K = blockIdx.x, m = b.m, nI = (m - 1) * (m - 1), ns = d.ns, rmax = b.rmax;
+  __shared__ double rot[3];
+  __shared__ double red[RB_THREADS];
+  __shared__ int order[RB_NMAX];
+  __shared__ int rsel;
+  double* C = d.C + (int64_t)K * ns * ns;
+  double* V = d.V + (int64_t)K * ns * ns;
+  rb_jacobi(C, V, ns, b.max_sweeps, red, rot);
+  if (threadIdx.x == 0) {
+    rsel = rb_sort_tail(C, ns, order, b.tail_tol, b.rcap, rmax, b.lambda + (int64_t)K * nI, nI);
+    b.rK[K] = rsel;
+  }
+  __syncthreads();
+  const int r = rsel;
+  double* Zk = b.Z + (int64_t)K * nI * rmax;
+  for (int iq = threadIdx.x; iq < nI * rmax; iq += blockDim.x) {
+    const int i = iq / rmax, q = iq % rmax;
+    double v = 0.0;
+    if (q < r) {
+      const int col = order[q];
+      const double lam = C[col * ns + col];
+      for (int c = 0; c < ns; ++c) v += rb_psi(b, K, c, i, nI) * V[(int64_t)c * ns + col];
+      v = lam > 0.0 ? v / sqrt(lam) : 0.0;
+    }
+    Zk[iq] = v;
+  }
+  __syncthreads();
+  rb_g_table(b, K, Zk, b.phibar + (int64_t)K * 3 * nI);
+}
+
+int64_t rb_work_doubles(int ncx, int ncy, int m, int ntrain) {
+  const int64_t Mc = (int64_t)ncx * ncy, nI = (int64_t)(m - 1) * (m - 1), ns = 3 * (int64_t)ntrain;
+  if (ns < nI) return Mc * ((int64_t)m * m + ns * nI + 2 * ns * ns);
+  return Mc * 4 * nI * nI;
+}
+
+bool rb_dual(int m, int ntrain) { return 3 * ntrain < (m - 1) * (m - 1); }
+
+hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st) {
+  const int Mc = b.ncx * b.ncy, m = b.m, nI = (m - 1) * (m - 1);
+  if (!rb_dual(m, b.ntrain)) {
+    if (nI > RB_NMAX) return hipErrorInvalidValue;
+    if (b.a_dtype == STOMSFEM_F32)
+      hipLaunchKernelGGL(rb_build_kernel<float>, dim3(Mc), dim3(RB_THREADS), 0, st, b);
+    else
+      hipLaunchKernelGGL(rb_build_kernel<double>, dim3(Mc), dim3(RB_THREADS), 0, st, b);
+    return hipGetLastError();
+  }
+  RbDual d{};
+  d.ns = 3 * b.ntrain;
+  if (d.ns > RB_NMAX) return hipErrorInvalidValue;
+  d.abar = b.work;
+  d.W = d.abar + (int64_t)Mc * m * m;
+  d.C = d.W + (int64_t)Mc * d.ns * nI;
+  d.V = d.C + (int64_t)Mc * d.ns * d.ns;
   if (b.a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL(rb_build_kernel<float>, dim3(Mc), dim3(RB_THREADS), 0, st, b);
+    hipLaunchKernelGGL(rb_dual_means_kernel<float>, dim3(Mc), dim3(RB_THREADS), 0, st, b, d);
   else
-    hipLaunchKernelGGL(rb_build_kernel<double>, dim3(Mc), dim3(RB_THREADS), 0, st, b);
+    hipLaunchKernelGGL(rb_dual_means_kernel<double>, dim3(Mc), dim3(RB_THREADS), 0, st, b, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rb_dual_energy_kernel, dim3((nI + RB_THREADS - 1) / RB_THREADS, Mc), dim3(RB_THREADS), 0, st, b,
+                     d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nt = (d.ns + RBG_T - 1) / RBG_T;
+  hipLaunchKernelGGL(rb_dual_gram_kernel, dim3(nt * (nt + 1) / 2, Mc), dim3(RB_THREADS), 0, st, b, d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rb_dual_finish_kernel, dim3(Mc), dim3(RB_THREADS), 0, st, b, d);
   return hipGetLastError();
 }
 
@@ -499,49 +725,56 @@ __global__ __launch_bounds__(64) void rb_apply_f64_kernel(RbApplyArgs ra) {
 }
 
 // FP32 MFMA online stage.  Workgroup = 4 wavefronts = 64 samples of one
-// patch.  C[64 x PP] = A[64 x KD] G[KD x PP] with v_mfma_f32_16x16x4f32
-// (wavefront w computes rows 16w..16w+15, all PP/16 column tiles); then one
+// patch.  C[64 x PP] = A[64 x KD] G[KD x PP] with v_mfma_f32_16x16x4f32 and
+// FP32 accumulation (wavefront w computes rows 16w..16w+15, all PP/16 column
+// tiles), the k dimension (the patch's m*m fine elements, padded to KD, a
+// multiple of 64) in chunks of 64 staged in LDS: the chunk's coefficient
+// rows of the 64 samples and its 64 rows of the patch's table.  Then one
 // lane per sample does the FP64 r x r solve.
 constexpr int RBA_SAMPLES = 64;
+constexpr int RBA_KC = 64;
 
-template <int RMAX, int KD, int PP, typename TA>
+template <int RMAX, int PP, typename TA>
 __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra) {
   using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const UpArgs& args = ra.up;
-  const int m = args.m, Mc = args.ncx * args.ncy;
+  const int m = args.m, mm = m * m, Mc = args.ncx * args.ncy, KD = ra.KD;
   const int K = blockIdx.y;
   const int64_t s0 = (int64_t)blockIdx.x * RBA_SAMPLES;
   const int64_t lda = (int64_t)args.ncx * m;
-  __shared__ float As[RBA_SAMPLES][KD + 4];
-  __shared__ float Gs[KD][PP];
+  __shared__ float As[RBA_SAMPLES][RBA_KC + 4];
+  __shared__ float Gs[RBA_KC][PP];
   __shared__ float Cs[RBA_SAMPLES][PP + 1];
   const int tid = threadIdx.x;
   const int kx = K % args.ncx, ky = K / args.ncx;
-  for (int idx = tid; idx < RBA_SAMPLES * KD; idx += 256) {
-    const int i = idx / KD, e = idx % KD;
-    const int64_t s = s0 + i;
-    float v = 0.0f;
-    if (s < args.nsamples && e < m * m) {
-      const TA* a = (const TA*)args.a + s * (int64_t)(args.ncy * m) * lda;
-      v = (float)ld(a, (int64_t)(ky * m + e / m) * lda + kx * m + e % m);
-    }
-    As[i][e] = v;
-  }
-  const float* G = ra.G32 + (int64_t)K * KD * PP;
-  for (int idx = tid; idx < KD * PP; idx += 256) Gs[idx / PP][idx % PP] = G[idx];
-  __syncthreads();
   const int w = tid / 64, lane = tid % 64;
   constexpr int NTILE = PP / 16;
   f4 acc[NTILE];
 #pragma unroll
   for (int t = 0; t < NTILE; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  const float* G = ra.G32 + (int64_t)K * KD * PP;
+  for (int e0 = 0; e0 < KD; e0 += RBA_KC) {
+    __syncthreads();  // the previous chunk's readers are done
+    for (int idx = tid; idx < RBA_SAMPLES * RBA_KC; idx += 256) {
+      const int i = idx / RBA_KC, e = e0 + idx % RBA_KC;
+      const int64_t s = s0 + i;
+      float v = 0.0f;
+      if (s < args.nsamples && e < mm) {
+        const TA* a = (const TA*)args.a + s * (int64_t)(args.ncy * m) * lda;
+        v = (float)ld(a, (int64_t)(ky * m + e / m) * lda + kx * m + e % m);
+      }
+      As[i][idx % RBA_KC] = v;
+    }
+    for (int idx = tid; idx < RBA_KC * PP; idx += 256) Gs[idx / PP][idx % PP] = G[(int64_t)e0 * PP + idx];
+    __syncthreads();
 #pragma unroll 4
-  for (int kk = 0; kk < KD / 4; ++kk) {
-    const float av = As[16 * w + (lane & 15)][4 * kk + (lane >> 4)];
+    for (int kk = 0; kk < RBA_KC / 4; ++kk) {
+      const float av = As[16 * w + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-    for (int t = 0; t < NTILE; ++t) {
-      const float bv = Gs[4 * kk + (lane >> 4)][16 * t + (lane & 15)];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      for (int t = 0; t < NTILE; ++t) {
+        const float bv = Gs[4 * kk + (lane >> 4)][16 * t + (lane & 15)];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -566,7 +799,7 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra) {
 }
 
 int rb_pad_p(int rmax) { return ((rb_p(rmax) + 15) / 16) * 16; }
-int rb_pad_kd(int m) { return ((m * m + 3) / 4) * 4; }
+int rb_pad_kd(int m) { return ((m * m + RBA_KC - 1) / RBA_KC) * RBA_KC; }
 
 hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStream_t st) {
   const UpArgs& u = ra.up;
@@ -580,12 +813,12 @@ hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStre
       hipLaunchKernelGGL((rb_apply_f64_kernel<8, double>), dim3((unsigned)blocks), dim3(64), 0, st, ra);
     return hipGetLastError();
   }
-  if (u.m != 8 || ra.KD != 64 || ra.PP != 80) return hipErrorInvalidValue;
+  if (ra.PP != 80 || ra.KD % RBA_KC != 0 || ra.KD < u.m * u.m) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((u.nsamples + RBA_SAMPLES - 1) / RBA_SAMPLES), (unsigned)(u.ncx * u.ncy));
   if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 64, 80, float>), grid, dim3(256), 0, st, ra);
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), grid, dim3(256), 0, st, ra);
   else
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 64, 80, double>), grid, dim3(256), 0, st, ra);
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), grid, dim3(256), 0, st, ra);
   return hipGetLastError();
 }
 

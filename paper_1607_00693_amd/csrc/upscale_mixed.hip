@@ -14,6 +14,9 @@
 //   4. S_ll' = sum_e a_e u^l_e . K_ref u^l'_e in FP64 (energy form): for an
 //      approximate u its error is e^l . K_II e^l', quadratic in the solution
 //      error; S^3 by the partition of unity as in the other kernels.
+// Optionally the refined solutions themselves are written out (the
+// reduced basis takes them as snapshots where the FP64 band does not fit
+// LDS), and S may then be skipped.
 // Pairs that do not converge within max_iter (or meet a non-positive FP32
 // pivot) are appended to a list for the FP64 path.
 //
@@ -193,6 +196,10 @@ __global__ __launch_bounds__(64) void upscale_mixed_kernel(MixedArgs args) {
     return;
   }
 
+  if (args.phi) {  // the refined cell solutions (interior nodes), e.g. as reduced-basis snapshots
+    for (int idx = lane; idx < 3 * NI; idx += 64) args.phi[p * 3 * NI + idx] = X[idx];
+  }
+  if (!up.S) return;
   // 4. S by the element energy sum, FP64
   double e6[6] = {0, 0, 0, 0, 0, 0};
   for (int e = lane; e < m * m; e += 64) {

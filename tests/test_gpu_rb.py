@@ -158,3 +158,50 @@ def test_rb_full_size_against_oracle(sm, orc):
     say(f"samples {pick.tolist()}: S_rb err {rel(Sg, S_rb):.2e}, U err vs plain oracle {ue.max():.2e}")
     assert ue.max() < 1e-3
     model.free()
+
+
+@pytest.mark.parametrize("m,nsub,ntr,form", [(16, 2, 80, "primal"), (16, 2, 24, "dual"), (32, 2, 40, "dual")])
+def test_rb_larger_cells_against_oracle(sm, orc, m, nsub, ntr, form):
+    # the reduced basis at H/h = 16 and 32 on nsub x nsub interior patches of
+    # the 32 x 32 bump workload's geometry (fine grid 32 m): the
+    # offline build in its primal form (3 ntrain >= (m-1)^2) and in the dual
+    # form (the method of snapshots, with the snapshots from the refined
+    # FP32/FP64 solver at m = 32), then both online stages against the oracle
+    from oracle import rb
+    wl = W.MESH32
+    nf = wl.nc * m
+    xi_tr = W.uniform_xi(ntr, wl.nxi, 2032 + m)
+    xi_te = W.uniform_xi(5, wl.nxi, 1032 + m)
+    cp = wl.coef_params()
+    o = 5 * m  # patches (5, 5).. of the mesh: up to four local variables each
+    a_tr = orc.coef_bumps(xi_tr, nf, **cp)[:, o:o + nsub * m, o:o + nsub * m].copy()
+    a_te = orc.coef_bumps(xi_te, nf, **cp)[:, o:o + nsub * m, o:o + nsub * m].copy()
+    say(f"m={m}: {form} build, {ntr} training samples, {nsub}x{nsub} patches")
+    model = sm.reduce(torch.from_numpy(a_tr).cuda(), nsub, nsub, m, r_max=8, tail_tol=1e-6)
+    r = model.export("r")
+    lam = model.export("lambda")
+    oms = []
+    for K in range(nsub * nsub):
+        kx, ky = K % nsub, K // nsub
+        om = rb.rb_offline(a_tr[:, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m], r_max=8, tail_tol=1e-6)
+        assert r[K] == om["r"], K
+        ref = om["sigma"][:8] ** 2
+        np.testing.assert_allclose(lam[K, :8], ref, rtol=1e-8, atol=1e-12 * ref[0])
+        oms.append(om)
+    S_ref = np.zeros((a_te.shape[0], nsub * nsub, 10))
+    for s in range(a_te.shape[0]):
+        for K in range(nsub * nsub):
+            kx, ky = K % nsub, K // nsub
+            S_ref[s, K] = rb.rb_online_S(oms[K], a_te[s, ky * m:(ky + 1) * m, kx * m:(kx + 1) * m])
+    S64 = sm.reduce_apply(model, torch.from_numpy(a_te).cuda(), precision=sm.PREC_F64).cpu().numpy()
+    st = torch.full((a_te.shape[0], nsub * nsub), 99, dtype=torch.int32, device="cuda")
+    S32 = sm.reduce_apply(model, torch.from_numpy(a_te).float().cuda(), status=st, precision=sm.PREC_F32)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    e64, e32 = rel(S64, S_ref), rel(S32.cpu().numpy(), S_ref.astype(np.float64))
+    S_plain, _, _ = orc.upscale(a_te, nsub, nsub, m)
+    say(f"m={m} {form}: r={r.tolist()}, FP64 online vs oracle {e64:.2e}, MFMA vs oracle {e32:.2e}, "
+        f"RB vs plain {rel(S64, S_plain):.2e}")
+    assert e64 < 1e-7
+    assert e32 < 2e-4
+    model.free()
