@@ -346,7 +346,7 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * `batch` (same ncx, ncy, m as the training batch):
  *   [A, Fh, B] = a_K^T G_K,   S_ll' = B_ll' - Fh_l . A^{-1} Fh_l'
  * precision STOMSFEM_PREC_F32 (the default online stage):
- * FP32 MFMA GEMM with FP32 accumulation, FP64 r x r solve;
+ * FP32 MFMA GEMM with FP32 accumulation, FP32 r x r solve;
  * STOMSFEM_PREC_F64: FP64 throughout (reference).  Per-pair status ENOTSPD
  * if the r x r system is not positive definite.  Asynchronous.
  * ------------------------------------------------------------------------ */

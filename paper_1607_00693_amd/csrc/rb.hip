@@ -33,7 +33,7 @@
 //     S_ll' = B_ll' - Fh_l . A^{-1} Fh_l'
 // (Galerkin identity: phi_rb = phibar + Z c with A c = -Fh).
 //
-// Online: rb_apply_mfma_kernel (FP32 MFMA 16x16x4, FP32 accumulation, FP64
+// Online: rb_apply_mfma_kernel (FP32 MFMA 16x16x4, FP32 accumulation, FP32
 // r x r solve) and rb_apply_f64_kernel (FP64 throughout, for parity checks).
 #include "rb.h"
 
@@ -628,13 +628,15 @@ hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st) {
 // Online stage
 // ---------------------------------------------------------------------------
 // r x r Cholesky of A (packed upper in v), solves with the three Fh columns,
-// S_ll' = B_ll' - Fh_l . A^{-1} Fh_l'.  All in FP64.  Returns false on a
-// non-positive pivot.
-template <int RMAX>
-__device__ __forceinline__ bool rb_small_solve(const double* v, int r, double S3[3][3]) {
+// S_ll' = B_ll' - Fh_l . A^{-1} Fh_l', in the arithmetic of T (FP64 for the
+// reference stage, FP32 after the FP32 matrix-core products: A is close to
+// the identity, since the modes are orthonormal in the energy of the
+// training mean).  Returns false on a non-positive pivot.
+template <int RMAX, typename T>
+__device__ __forceinline__ bool rb_small_solve(const T* v, int r, double S3[3][3]) {
   constexpr int NA = RMAX * (RMAX + 1) / 2;
-  double L[RMAX][RMAX];
-  double X[3][RMAX];
+  T L[RMAX][RMAX];
+  T X[3][RMAX];
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < RMAX; ++i)
@@ -644,31 +646,30 @@ __device__ __forceinline__ bool rb_small_solve(const double* v, int r, double S3
   for (int q = 0; q < RMAX; ++q)
 #pragma unroll
     for (int qp = q; qp < RMAX; ++qp) {
-      const double a = v[q * RMAX - q * (q - 1) / 2 + (qp - q)];
-      L[qp][q] = a;
+      L[qp][q] = v[q * RMAX - q * (q - 1) / 2 + (qp - q)];
     }
   // identity on the unused modes keeps the factorisation well defined
 #pragma unroll
   for (int q = 0; q < RMAX; ++q)
     if (q >= r) {
 #pragma unroll
-      for (int j = 0; j < RMAX; ++j) L[q][j] = (j == q) ? 1.0 : 0.0;
+      for (int j = 0; j < RMAX; ++j) L[q][j] = (j == q) ? T(1) : T(0);
 #pragma unroll
       for (int i = 0; i < RMAX; ++i)
-        if (i != q) L[i][q] = 0.0;
+        if (i != q) L[i][q] = T(0);
     }
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
-    double d = L[j][j];
+    T d = L[j][j];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-    ok = ok && d > 0.0;
-    const double ljj = sqrt(d);
+    ok = ok && d > T(0);
+    const T ljj = sqrt(d);
     L[j][j] = ljj;
-    const double inv = 1.0 / ljj;
+    const T inv = T(1) / ljj;
 #pragma unroll
     for (int i = j + 1; i < RMAX; ++i) {
-      double t = L[i][j];
+      T t = L[i][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
       L[i][j] = t * inv;
@@ -680,7 +681,7 @@ __device__ __forceinline__ bool rb_small_solve(const double* v, int r, double S3
   for (int l = 0; l < 3; ++l)
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) {
-      double t = (i < r) ? v[NA + l * RMAX + i] : 0.0;
+      T t = (i < r) ? v[NA + l * RMAX + i] : T(0);
 #pragma unroll
       for (int k = 0; k < i; ++k) t -= L[i][k] * X[l][k];
       X[l][i] = t / L[i][i];
@@ -688,11 +689,11 @@ __device__ __forceinline__ bool rb_small_solve(const double* v, int r, double S3
   const int ls[6] = {0, 0, 0, 1, 1, 2}, lps[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
-    double acc = v[NA + 3 * RMAX + t];
+    T acc = v[NA + 3 * RMAX + t];
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) acc -= X[ls[t]][i] * X[lps[t]][i];
-    S3[ls[t]][lps[t]] = acc;
-    S3[lps[t]][ls[t]] = acc;
+    S3[ls[t]][lps[t]] = (double)acc;
+    S3[lps[t]][ls[t]] = (double)acc;
   }
   return ok;
 }
@@ -719,78 +720,116 @@ __global__ __launch_bounds__(64) void rb_apply_f64_kernel(RbApplyArgs ra) {
     for (int q = 0; q < P; ++q) v[q] += ae * G[e * ra.PP + q];
   }
   double S3[3][3];
-  const bool ok = rb_small_solve<RMAX>(v, ra.rK[K], S3);
+  const bool ok = rb_small_solve<RMAX, double>(v, ra.rK[K], S3);
   store_packed(args.S + p * 10, S3);
   if (args.status) args.status[p] = ok ? STOMSFEM_OK : STOMSFEM_ENOTSPD;
 }
 
-// FP32 MFMA online stage.  Workgroup = 4 wavefronts = 64 samples of one
-// patch.  C[64 x PP] = A[64 x KD] G[KD x PP] with v_mfma_f32_16x16x4f32 and
-// FP32 accumulation (wavefront w computes rows 16w..16w+15, all PP/16 column
-// tiles), the k dimension (the patch's m*m fine elements, padded to KD, a
-// multiple of 64) in chunks of 64 staged in LDS: the chunk's coefficient
-// rows of the 64 samples and its 64 rows of the patch's table.  Then one
-// lane per sample does the FP64 r x r solve.
-constexpr int RBA_SAMPLES = 64;
+// FP32 MFMA online stage.  Workgroup = 4 wavefronts = 128 samples of one
+// patch.  C[128 x PP] = A[128 x KD] G[KD x PP] with v_mfma_f32_16x16x4f32 and
+// FP32 accumulation (wavefront w computes rows 32w..32w+31, two row tiles,
+// all PP/16 column tiles), the k dimension (the patch's m*m fine elements,
+// padded to KD, a multiple of 64) in chunks of 64 staged in LDS: the chunk's
+// coefficients of the 128 samples and its 64 rows of the patch's table,
+// the next chunk's coefficients loaded into registers while the current one
+// is multiplied.  Then one lane per sample does the FP32 r x r solve (the
+// result rows pass through LDS, in the space of the staging buffers).
+constexpr int RBA_SAMPLES = 128;
 constexpr int RBA_KC = 64;
+constexpr int RBA_LDA = RBA_KC + 4;
+constexpr int RBA_PF = RBA_SAMPLES * RBA_KC / 256;  // coefficients per thread and chunk
 
+// Workgroup order: one-dimensional grid of ntiles x M workgroups.  When a
+// patch's coefficient row is shorter than a 128-byte cache line, the patch
+// index runs fastest, so that neighbouring patches, which share the lines of
+// a sample, are read by one L2: the hardware deals consecutive workgroups
+// round-robin to the eight XCDs (each with its own L2), and the logical index
+// L = (b mod 8) (n / 8) + b / 8 gives each XCD a contiguous range.
+// Otherwise the sample tile runs fastest and consecutive workgroups share
+// the patch's table.
 template <int RMAX, int PP, typename TA>
-__global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra) {
+__global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int64_t ntiles, int patch_fast) {
   using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const UpArgs& args = ra.up;
   const int m = args.m, mm = m * m, Mc = args.ncx * args.ncy, KD = ra.KD;
-  const int K = blockIdx.y;
-  const int64_t s0 = (int64_t)blockIdx.x * RBA_SAMPLES;
+  const int64_t nb = ntiles * Mc, b = blockIdx.x;
+  const int64_t L = (patch_fast && nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int K = (int)(patch_fast ? L % Mc : L / ntiles);
+  const int64_t tile = patch_fast ? L / Mc : L % ntiles;
+  const int64_t s0 = tile * RBA_SAMPLES;
   const int64_t lda = (int64_t)args.ncx * m;
-  __shared__ float As[RBA_SAMPLES][RBA_KC + 4];
-  __shared__ float Gs[RBA_KC][PP];
-  __shared__ float Cs[RBA_SAMPLES][PP + 1];
+  constexpr int AS_FLOATS = RBA_SAMPLES * RBA_LDA, GS_FLOATS = RBA_KC * PP;
+  constexpr int CS_FLOATS = RBA_SAMPLES * (PP + 1);
+  constexpr int SM_FLOATS = (AS_FLOATS + GS_FLOATS) > CS_FLOATS ? (AS_FLOATS + GS_FLOATS) : CS_FLOATS;
+  __shared__ float smem[SM_FLOATS];
+  float(*As)[RBA_LDA] = reinterpret_cast<float(*)[RBA_LDA]>(smem);
+  float(*Gs)[PP] = reinterpret_cast<float(*)[PP]>(smem + AS_FLOATS);
+  float(*Cs)[PP + 1] = reinterpret_cast<float(*)[PP + 1]>(smem);
   const int tid = threadIdx.x;
   const int kx = K % args.ncx, ky = K / args.ncx;
   const int w = tid / 64, lane = tid % 64;
   constexpr int NTILE = PP / 16;
-  f4 acc[NTILE];
+  f4 acc[2][NTILE];
 #pragma unroll
-  for (int t = 0; t < NTILE; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) acc[h][t] = f4{0.f, 0.f, 0.f, 0.f};
   const float* G = ra.G32 + (int64_t)K * KD * PP;
-  for (int e0 = 0; e0 < KD; e0 += RBA_KC) {
-    __syncthreads();  // the previous chunk's readers are done
-    for (int idx = tid; idx < RBA_SAMPLES * RBA_KC; idx += 256) {
-      const int i = idx / RBA_KC, e = e0 + idx % RBA_KC;
+  // thread tid loads coefficient (i, e0 + c) for idx = tid + 256 q, i = idx / KC
+  auto load_chunk = [&](int e0, float (&v)[RBA_PF]) {
+#pragma unroll
+    for (int q = 0; q < RBA_PF; ++q) {
+      const int idx = tid + 256 * q, i = idx / RBA_KC, e = e0 + idx % RBA_KC;
       const int64_t s = s0 + i;
-      float v = 0.0f;
+      float x = 0.0f;
       if (s < args.nsamples && e < mm) {
         const TA* a = (const TA*)args.a + s * (int64_t)(args.ncy * m) * lda;
-        v = (float)ld(a, (int64_t)(ky * m + e / m) * lda + kx * m + e % m);
+        x = (float)ld(a, (int64_t)(ky * m + e / m) * lda + kx * m + e % m);
       }
-      As[i][idx % RBA_KC] = v;
+      v[q] = x;
+    }
+  };
+  float pf[RBA_PF];
+  load_chunk(0, pf);
+  for (int e0 = 0; e0 < KD; e0 += RBA_KC) {
+    __syncthreads();  // the previous chunk's readers are done
+#pragma unroll
+    for (int q = 0; q < RBA_PF; ++q) {
+      const int idx = tid + 256 * q;
+      As[idx / RBA_KC][idx % RBA_KC] = pf[q];
     }
     for (int idx = tid; idx < RBA_KC * PP; idx += 256) Gs[idx / PP][idx % PP] = G[(int64_t)e0 * PP + idx];
     __syncthreads();
+    if (e0 + RBA_KC < KD) load_chunk(e0 + RBA_KC, pf);  // in flight during the products
 #pragma unroll 4
     for (int kk = 0; kk < RBA_KC / 4; ++kk) {
-      const float av = As[16 * w + (lane & 15)][4 * kk + (lane >> 4)];
+      const float av0 = As[32 * w + (lane & 15)][4 * kk + (lane >> 4)];
+      const float av1 = As[32 * w + 16 + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
       for (int t = 0; t < NTILE; ++t) {
         const float bv = Gs[4 * kk + (lane >> 4)][16 * t + (lane & 15)];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        acc[0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv, acc[0][t], 0, 0, 0);
+        acc[1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv, acc[1][t], 0, 0, 0);
       }
     }
   }
+  __syncthreads();  // Cs overlays the staging buffers
 #pragma unroll
-  for (int t = 0; t < NTILE; ++t)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Cs[16 * w + 4 * (lane >> 4) + v][16 * t + (lane & 15)] = acc[t][v];
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cs[32 * w + 16 * h + 4 * (lane >> 4) + v][16 * t + (lane & 15)] = acc[h][t][v];
   __syncthreads();
   if (tid < RBA_SAMPLES) {
     const int64_t s = s0 + tid;
     if (s < args.nsamples) {
       constexpr int P = RMAX * (RMAX + 1) / 2 + 3 * RMAX + 6;
-      double v[P];
+      float v[P];
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = (double)Cs[tid][q];
+      for (int q = 0; q < P; ++q) v[q] = Cs[tid][q];
       double S3[3][3];
-      const bool ok = rb_small_solve<RMAX>(v, ra.rK[K], S3);
+      const bool ok = rb_small_solve<RMAX, float>(v, ra.rK[K], S3);
       const int64_t p = s * Mc + K;
       store_packed(args.S + p * 10, S3);
       if (args.status) args.status[p] = ok ? STOMSFEM_OK : STOMSFEM_ENOTSPD;
@@ -814,11 +853,16 @@ hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStre
     return hipGetLastError();
   }
   if (ra.PP != 80 || ra.KD % RBA_KC != 0 || ra.KD < u.m * u.m) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((u.nsamples + RBA_SAMPLES - 1) / RBA_SAMPLES), (unsigned)(u.ncx * u.ncy));
+  const int64_t ntiles = (u.nsamples + RBA_SAMPLES - 1) / RBA_SAMPLES, nb = ntiles * u.ncx * u.ncy;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  const int elem = a_dtype == STOMSFEM_F32 ? 4 : 8;
+  const int patch_fast = u.m * elem < 128 ? 1 : 0;
   if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), grid, dim3(256), 0, st, ra);
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
+                       patch_fast);
   else
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), grid, dim3(256), 0, st, ra);
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
+                       patch_fast);
   return hipGetLastError();
 }
 
