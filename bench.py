@@ -366,13 +366,23 @@ def measure_reduced_basis(wl, xi, S_plain, t_plain_ms, log, ntrain=40):
     U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
     U_r, _, _ = sm.coarse_solve(S_rb, wl.nc, wl.nc)
     u_err = float((torch.linalg.norm(U_r - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())
+    # control variate (the remark closing Sec. 5.3): E[u_H] from the reduced
+    # solution on all samples, corrected by the plain-minus-reduced mean on the
+    # first n2 of them (the two-level formula with the coarse nodes as "fine")
+    n2 = min(256, N)
+    cv_mean, var_r, var_d = sm.two_level_mc(U_r, U_r[:n2].contiguous(), U_p[:n2].contiguous(), wl.nc, 1)
+    plain_mean = U_p.mean(dim=0)
+    cv = {"n_reduced": N, "n_plain": n2,
+          "max_abs_err_vs_plain_mean": float((cv_mean - plain_mean).abs().max()),
+          "max_abs_err_uncorrected": float((U_r.mean(dim=0) - plain_mean).abs().max()),
+          "var_ratio_d_over_reduced": float(var_d.sum() / var_r.sum())}
     pairs = N * wl.M
     kd = ((wl.m * wl.m + 63) // 64) * 64
     flops = 2.0 * kd * 80  # the GEMM row of one pair (padded table: 80 columns)
     r = model.export("r")
     out = {"workload": f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {ntrain} training samples/patch, r<=8 (tail 1e-6), "
                        f"the benchmark's {N} samples with FP32 coefficients, FP32 MFMA GEMM "
-                       "[64 samples x m^2] x [m^2 x 80] per workgroup + FP64 8x8 solves",
+                       "[128 samples x m^2] x [m^2 x 80] per workgroup + FP32 8x8 solves",
            "offline_s": t_off, "modes_min": int(r.min()), "modes_max": int(r.max()),
            "online_ms": t_on * 1e3, "pairs_per_s": pairs / t_on,
            "fp32_coef_generation_ms": t_gen * 1e3, "pairs_per_s_with_generation": pairs / (t_on + t_gen),
@@ -380,12 +390,66 @@ def measure_reduced_basis(wl, xi, S_plain, t_plain_ms, log, ntrain=40):
            "ratio_with_generation": t_plain_ms * 1e-3 / (t_on + t_gen),
            "mfma_flops_per_pair": flops, "achieved_tflops": flops * pairs / t_on / 1e12,
            "fp32_mfma_peak_frac": flops * pairs / t_on / 1e12 / FP32_MFMA_PEAK_TFLOPS,
-           "non_ok_pairs": bad, "max_S_rel_err": s_err, "max_coarse_rel_err": u_err}
+           "non_ok_pairs": bad, "max_S_rel_err": s_err, "max_coarse_rel_err": u_err,
+           "control_variate": cv}
     log(f"reduced basis on the benchmark mesh: {out}")
     model.free()
     del a32, S_rb
     torch.cuda.empty_cache()
     return out
+
+
+def measure_two_level_bench(wl, S_plain, log, n_h=32):
+    """Two-level Monte Carlo (Sec. 4.1.1) on the benchmark mesh: the
+    benchmark's coarse solutions (N_H samples) and n_h independent samples
+    (seed 1900 + workload) solved both on the coarse mesh and on the full
+    fine grid by multigrid-preconditioned CG (relative residual 1e-12)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    xh = torch.from_numpy(W.uniform_xi(n_h, wl.nxi, 1900 + wl.seed % 1000)).cuda()
+    a_h = sm.coef_bumps(xh, wl.nfine, **wl.coef_params())
+    U_Hh, _, _ = sm.coarse_solve(sm.upscale(a_h, wl.nc, wl.nc, wl.m), wl.nc, wl.nc)
+    U_H, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    nf1 = wl.nfine - 1
+    u_f = torch.empty((n_h, nf1 * nf1), dtype=torch.float64, device="cuda")
+    iters = torch.empty(n_h, dtype=torch.int32, device="cuda")
+    status = torch.empty(n_h, dtype=torch.int32, device="cuda")
+    sm.fine_solve_pcg(a_h[:1], u=u_f[:1], iters=iters[:1], status=status[:1])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sm.fine_solve_pcg(a_h, u=u_f, iters=iters, status=status)
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    mean, var_H, var_d = sm.two_level_mc(U_H, U_Hh, u_f, wl.nc, wl.m)
+    N_H = U_H.shape[0]
+    H2 = 1.0 / wl.nc ** 2
+    mse = H2 * float((var_H / N_H + var_d / n_h).sum())
+    # fine-only Monte Carlo with the same sampling error needs N with
+    # H^2 sum var_fine / N = mse, var_fine ~ var_H
+    n_fine_only = H2 * float(var_H.sum()) / mse if mse > 0 else float("nan")
+    it = iters.cpu()
+    out = {"workload": f"{wl.nc}x{wl.nc} coarse, H/h={wl.m} (fine {wl.nfine}x{wl.nfine}), {N_H} coarse samples "
+                       f"(the benchmark's) + {n_h} fine samples, fine solves by multigrid-preconditioned CG",
+           "fine_solve_s": t_fine, "fine_solves_per_s": n_h / t_fine,
+           "pcg_iterations_min": int(it.min()), "pcg_iterations_max": int(it.max()),
+           "non_converged": int((status != 0).sum().item()),
+           "sampling_mse": mse, "var_ratio_d_over_H": float(var_d.sum() / var_H.sum()),
+           "max_coarse_minus_fine_mean": float((U_Hh.mean(dim=0) - u_f[:, _coarse_node_index(wl)].mean(dim=0))
+                                                .abs().max()),
+           "fine_only_mc_samples_for_same_error": n_fine_only,
+           "fine_only_mc_s_for_same_error": n_fine_only / (n_h / t_fine)}
+    log(f"two-level MC on the benchmark mesh: {out}")
+    del a_h, u_f
+    torch.cuda.empty_cache()
+    return out
+
+
+def _coarse_node_index(wl):
+    nf1 = wl.nc * wl.m - 1
+    return [(py * wl.m - 1) * nf1 + (px * wl.m - 1) for py in range(1, wl.nc) for px in range(1, wl.nc)]
 
 
 def os_flops_per_pair(m: int, o: int) -> float:
@@ -849,7 +913,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
-                    help="comma-separated subset of the extra measurements (ri_bench, rb_bench, surrogate_bench, "
+                    help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
                          "mixed_bench, mesh8, channels, oversampling, collocation, two_level, gauss); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
@@ -991,6 +1055,9 @@ def main():
         if want("rb_bench"):
             lg("reduced basis at the benchmark mesh")
             acc["reduced_basis_bench_mesh"] = measure_reduced_basis(wl, xi, S, t_gen + t_up, lg)
+        if want("two_level_bench"):
+            lg("two-level Monte Carlo at the benchmark mesh")
+            acc["two_level_mc_bench_mesh"] = measure_two_level_bench(wl, S, lg)
         if want("surrogate_bench"):
             lg("learned surrogate at the benchmark mesh")
             acc["learned_surrogate_bench_mesh"] = measure_surrogate(wl, xi, S, t_gen + t_up, lg)

@@ -302,14 +302,30 @@ int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const
  * remark with eqs. MCmean2level and mseML).
  *
  * stomsfem_fine_solve: the global Q1 FEM on the nfine x nfine fine mesh of
- * [0,1]^2 (2 <= nfine <= 64) with the piecewise-constant coefficient a
+ * [0,1]^2 (2 <= nfine <= 8192) with the piecewise-constant coefficient a
  * (device [nsamples][nfine][nfine], FP64, element row-major, y outer), f = 1
  * and zero Dirichlet data: u device [nsamples][(nfine-1)^2], interior fine
- * nodes in natural order.  It is the coarse system of the m = 1 upscaled
- * elements (S = a_e K_Q1, load h^2/4 per element node) and runs the upscaling
- * and coarse-solve kernels in chunks of samples.  status device [nsamples]
- * or NULL: ENOTSPD if a pivot is not positive (e.g. a <= 0).  Uses the
- * library workspace; asynchronous on `stream`.
+ * nodes in natural order.  For nfine <= 64 it is the coarse system of the
+ * m = 1 upscaled elements (S = a_e K_Q1, load h^2/4 per element node), run
+ * through the upscaling and banded coarse-solve kernels in chunks of samples
+ * (status: ENOTSPD if a pivot is not positive, e.g. a <= 0); for larger
+ * meshes it is stomsfem_fine_solve_pcg with tolerance
+ * STOMSFEM_FINE_PCG_TOL and at most STOMSFEM_FINE_PCG_MAXIT iterations
+ * (status: ENOCONV if not reached).  status device [nsamples] or NULL.  Uses
+ * the library workspace; asynchronous on `stream` for nfine <= 64, otherwise
+ * it synchronises `stream` every few iterations.
+ *
+ * stomsfem_fine_solve_pcg: the same system by conjugate gradients
+ * preconditioned with one geometric multigrid V-cycle per iteration
+ * (coefficients averaged over 2 x 2 elements per coarser level while the
+ * element count per side is even and >= 8, bilinear interpolation and its
+ * transpose, two damped-Jacobi sweeps before and after the coarse
+ * correction, thirty on the coarsest level; FP64 throughout), for every
+ * sample until ||b - K u||_2 <= tol ||b||_2 or max_iter iterations.  iters
+ * device int32 [nsamples] or NULL: the iterations each sample took; status
+ * device [nsamples] or NULL: OK or ENOCONV.  Samples in chunks of at most
+ * 64 (about 65 MB each at nfine = 1024, in the library workspace).  Reads a
+ * counter back every four iterations, so it synchronises `stream`.
  *
  * stomsfem_two_level_mc: per interior coarse node i of the nc x nc mesh,
  * mean[i] = M[U_H][i] + M[u_h - U_Hh][i] over the two sample sets (U_H device
@@ -320,8 +336,12 @@ int stomsfem_kl_blocks(int64_t npairs, int32_t m, int32_t Kuse, int32_t K, const
  * sampling part of the MSE is H^2 sum_i (var_H/n_H + var_d/n_h).  Any output
  * may be NULL.  Fixed summation order.  Asynchronous on `stream`.
  * ------------------------------------------------------------------------ */
+#define STOMSFEM_FINE_PCG_TOL 1e-12
+#define STOMSFEM_FINE_PCG_MAXIT 500
 int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double* u, int32_t* status,
                         void* stream);
+int stomsfem_fine_solve_pcg(const double* a, int32_t nfine, int64_t nsamples, double tol, int32_t max_iter,
+                            double* u, int32_t* iters, int32_t* status, void* stream);
 int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, const double* u_fine, int64_t n_h,
                           int32_t nc, int32_t m, double* mean, double* var_H, double* var_d, void* stream);
 

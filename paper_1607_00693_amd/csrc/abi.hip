@@ -30,6 +30,9 @@ hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const dou
                          double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
                             double* mean, double* var, int32_t* status, double* work, hipStream_t st);
+int64_t fine_pcg_doubles_per_sample(int nfine);
+hipError_t launch_fine_pcg(const double* a, int n, int64_t N, double tol, int max_iter, double* u, int32_t* iters,
+                           int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_capped(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U,
                                 double* mean, double* var, int32_t* status, double* work, int64_t work_cap,
                                 hipStream_t st);
@@ -608,9 +611,40 @@ int stomsfem_coarse_solve_noalloc(int32_t ncx, int32_t ncy, int64_t nsamples, co
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve_noalloc launch");
 }
 
+int stomsfem_fine_solve_pcg(const double* a, int32_t nfine, int64_t nsamples, double tol, int32_t max_iter,
+                            double* u, int32_t* iters, int32_t* status, void* stream) {
+  if (nfine < 2 || nfine > 8192 || nsamples < 0) return fail(STOMSFEM_EINVAL, "fine_solve_pcg: need 2 <= nfine <= 8192");
+  if (!(tol > 0.0) || max_iter < 1) return fail(STOMSFEM_EINVAL, "fine_solve_pcg: need tol > 0 and max_iter >= 1");
+  if (nsamples == 0) return STOMSFEM_OK;
+  if (!device_ptr(a) || !device_ptr(u)) return fail(STOMSFEM_EINVAL, "fine_solve_pcg: a and u must be device pointers");
+  if ((status && !device_ptr(status)) || (iters && !device_ptr(iters)))
+    return fail(STOMSFEM_EINVAL, "fine_solve_pcg: status and iters must be device pointers");
+  const int64_t per = fine_pcg_doubles_per_sample(nfine);
+  // samples per chunk: about 4 GiB of vectors, at most 64
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>({nsamples, (int64_t)64, (int64_t{1} << 29) / per}));
+  hipStream_t st = (hipStream_t)stream;
+  void* ws = nullptr;
+  WorkspaceLease lease;
+  int rc = lease.acquire(sizeof(double) * (size_t)per * chunk + sizeof(int32_t) * (size_t)chunk, st, &ws);
+  if (rc != STOMSFEM_OK) return rc;
+  double* work = (double*)ws;
+  int32_t* it_scratch = (int32_t*)(work + per * chunk);
+  const int64_t ncell = (int64_t)nfine * nfine, nU = (int64_t)(nfine - 1) * (nfine - 1);
+  for (int64_t start = 0; start < nsamples; start += chunk) {
+    const int64_t cnt = std::min(chunk, nsamples - start);
+    hipError_t e = launch_fine_pcg(a + start * ncell, nfine, cnt, tol, max_iter, u + start * nU,
+                                   iters ? iters + start : it_scratch, status ? status + start : nullptr, work, st);
+    if (e != hipSuccess) return hip_fail(e, "fine_solve_pcg");
+  }
+  return STOMSFEM_OK;
+}
+
 int stomsfem_fine_solve(const double* a, int32_t nfine, int64_t nsamples, double* u, int32_t* status,
                         void* stream) {
-  if (nfine < 2 || nfine > 64 || nsamples < 0) return fail(STOMSFEM_EINVAL, "fine_solve: need 2 <= nfine <= 64");
+  if (nfine > 64 && nfine <= 8192 && nsamples >= 0)  // beyond the direct solver's band window
+    return stomsfem_fine_solve_pcg(a, nfine, nsamples, STOMSFEM_FINE_PCG_TOL, STOMSFEM_FINE_PCG_MAXIT, u, nullptr,
+                                   status, stream);
+  if (nfine < 2 || nfine > 64 || nsamples < 0) return fail(STOMSFEM_EINVAL, "fine_solve: need 2 <= nfine <= 8192");
   if (nsamples == 0) return STOMSFEM_OK;
   if (!device_ptr(a) || !device_ptr(u)) return fail(STOMSFEM_EINVAL, "fine_solve: a and u must be device pointers");
   if (status && !device_ptr(status)) return fail(STOMSFEM_EINVAL, "fine_solve: status must be a device pointer");

@@ -102,6 +102,7 @@ def lib():
         "stomsfem_mlp_predict": (C.c_int, [vp, vp, i32, i64, vp, i32, vp]),
         "stomsfem_mlp_gate": (C.c_int, [vp, vp, vp, i32, i64, dbl, vp, vp, vp, vp]),
         "stomsfem_coarse_solve_noalloc": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
+        "stomsfem_fine_solve_pcg": (C.c_int, [vp, i32, i64, dbl, i32, vp, vp, vp, vp]),
         "stomsfem_upscale_surrogate": (C.c_int, [vp, vp, i32, i64, vp, vp, dbl, i32, vp, vp]),
         "stomsfem_workspace_release": (C.c_int, []),
         "stomsfem_feature_map": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -347,6 +348,23 @@ def fine_solve(a: torch.Tensor, u: torch.Tensor | None = None, status: torch.Ten
         u = torch.empty((N, (nf - 1) ** 2), dtype=torch.float64, device=a.device)
     _check("stomsfem_fine_solve", lib().stomsfem_fine_solve(_ptr(a), nf, N, _ptr(u), _ptr(status), _stream(stream)))
     return u
+
+
+def fine_solve_pcg(a: torch.Tensor, tol: float = 1e-12, max_iter: int = 500, u: torch.Tensor | None = None,
+                   iters: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+    """Fine-grid FEM solutions by multigrid-preconditioned CG: returns
+    (u[N][(nfine-1)^2], iters[N], status[N])."""
+    assert a.dtype == torch.float64 and a.is_contiguous() and a.shape[1] == a.shape[2]
+    N, nf = a.shape[0], a.shape[1]
+    if u is None:
+        u = torch.empty((N, (nf - 1) ** 2), dtype=torch.float64, device=a.device)
+    if iters is None:
+        iters = torch.empty(N, dtype=torch.int32, device=a.device)
+    if status is None:
+        status = torch.empty(N, dtype=torch.int32, device=a.device)
+    _check("stomsfem_fine_solve_pcg", lib().stomsfem_fine_solve_pcg(
+        _ptr(a), nf, N, tol, max_iter, _ptr(u), _ptr(iters), _ptr(status), _stream(stream)))
+    return u, iters, status
 
 
 def two_level_mc(U_H: torch.Tensor, U_Hh: torch.Tensor, u_fine: torch.Tensor, nc: int, m: int, stream=None):
