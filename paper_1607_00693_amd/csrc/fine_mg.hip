@@ -236,17 +236,26 @@ __global__ __launch_bounds__(FMG_TB) void fmg_direction_kernel(FmgCg c) {
   }
 }
 
-// per-sample scalar steps (one thread per sample; partials summed in order)
+// per-sample scalar steps (one workgroup per sample: thread t sums the
+// partials t, t + 256, ... in order, then a fixed tree; a fixed order)
 //   0: bb = sum, active = 1;   1: rz = sum, beta = 0 (first direction p = z);
 //   2: pq = sum, alpha = active ? rz / pq : 0;
 //   3: rr = sum, active &= rr > tol^2 bb (count, iterations);
 //   4: beta = active ? sum / rz : 0, rz = sum
 template <int STEP>
-__global__ void fmg_scalar_kernel(FmgCg c, int it) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= c.nsamples) return;
-  double v = 0.0;
-  for (int k = 0; k < c.nblk; ++k) v += c.part[s * c.nblk + k];
+__global__ __launch_bounds__(FMG_TB) void fmg_scalar_kernel(FmgCg c, int it) {
+  const int64_t s = blockIdx.x;
+  __shared__ double red[FMG_TB];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < c.nblk; k += FMG_TB) acc += c.part[s * c.nblk + k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = FMG_TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double v = red[0];
   if (STEP == 0) {
     c.bb[s] = v;
     c.active[s] = 1;
@@ -396,7 +405,8 @@ hipError_t launch_fine_pcg(const double* a, int n, int64_t N, double tol, int ma
   c.nactive = nactive_dev;
   c.tol2 = tol * tol;
   const dim3 gd((unsigned)c.nblk, (unsigned)N), b(FMG_TB);
-  const dim3 gs((unsigned)((N + 63) / 64)), bs(64);
+  const dim3 gs((unsigned)N), bs(FMG_TB);         // scalar steps: one workgroup per sample
+  const dim3 gst((unsigned)((N + 63) / 64)), bst(64);  // status: one thread per sample
   hipLaunchKernelGGL(fmg_cg_init_kernel, gd, b, 0, st, c);
   hipLaunchKernelGGL(fmg_scalar_kernel<0>, gs, bs, 0, st, c, 0);
   e = fmg_vcycle(lv, nlev, 0, N, st);
@@ -433,7 +443,7 @@ hipError_t launch_fine_pcg(const double* a, int n, int64_t N, double tol, int ma
     hipLaunchKernelGGL(fmg_scalar_kernel<4>, gs, bs, 0, st, c, it);
     hipLaunchKernelGGL(fmg_direction_kernel, gd, b, 0, st, c);
   }
-  if (status) hipLaunchKernelGGL(fmg_status_kernel, gs, bs, 0, st, c, status);
+  if (status) hipLaunchKernelGGL(fmg_status_kernel, gst, bst, 0, st, c, status);
   const int64_t nU = (int64_t)(n - 1) * (n - 1);
   hipLaunchKernelGGL(fmg_extract_kernel, dim3((unsigned)((N * nU + FMG_TB - 1) / FMG_TB)), b, 0, st,
                      (const double*)c.x, n, N, u);
