@@ -259,6 +259,39 @@ def test_oversampled_interpolation_matches_oracle(sm, K, nn, box):
     np.testing.assert_allclose(S[fb], S_os[fb], rtol=0, atol=1e-10 * np.abs(S_os).max())
 
 
+def test_oversampled_class_tables_match_elements_of_a_larger_mesh(sm):
+    # the premise of the class tables: an element's oversampled Petrov-Galerkin
+    # stiffness depends only on the coefficient of its patch and on where the
+    # element sits in the patch (offset 0, o or 2o along each axis), not on the
+    # mesh around it.  The truncated-KL block of one table node is written into
+    # the patch of an interior, an edge and two corner elements of a 6 x 6 mesh
+    # (1 elsewhere), the oversampling kernel solves the whole field, and each
+    # element's S is compared with the interpolant at that node, i.e. the
+    # class table's row (the Lagrange basis is 1 at its own node)
+    from oracle import core
+    nc, m, o, K, nn, box = 6, 8, 4, 3, 3, 3.0
+    P, nf = m + 2 * o, nc * m
+    mu, V, _ = sm.local_kl(P, 1.0 / nf, 1.0, 1.0 / 8, K)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    model = sm.kl_interp_build(nc, nc, m, mu_d, V_d, nn, box, oversample=o)
+    node = torch.tensor([[box, 0.0, -box]], dtype=torch.float64, device="cuda")  # Lobatto nodes of [-3, 3]
+    blk = sm.kl_blocks(node, mu_d, V_d, K)[0].cpu().numpy()
+    say("class tables against elements of a 6 x 6 mesh")
+    for ex, ey in ((2, 3), (0, 3), (0, 0), (5, 5)):
+        field = np.ones((1, nf, nf))
+        ox, oy = core.os_origin(ex, m, o, nf), core.os_origin(ey, m, o, nf)
+        field[0, oy:oy + P, ox:ox + P] = blk
+        fd = torch.from_numpy(field).cuda()
+        S_os = sm.upscale_os(fd, nc, nc, m, o)[0, ey * nc + ex].cpu().numpy()
+        xi = torch.zeros((1, nc * nc, K), dtype=torch.float64, device="cuda")
+        xi[0, ey * nc + ex] = node[0]
+        S_tab, _ = sm.kl_interp_apply(model, xi, fd)
+        S_tab = S_tab[0, ey * nc + ex].cpu().numpy()
+        err = np.abs(S_tab - S_os).max() / np.abs(S_os).max()
+        say(f"  element ({ex}, {ey}): rel diff {err:.2e}")
+        assert err < 1e-10
+
+
 def test_oversampled_interpolation_rejects_bad_shapes(sm):
     mu = torch.ones(2, dtype=torch.float64, device="cuda")
     V = torch.zeros((2, 16, 16), dtype=torch.float64, device="cuda")
