@@ -428,7 +428,7 @@ typedef struct {
 int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfem_bump_family* fam, int32_t kmax,
                               int32_t* local_vars, int32_t* nlocal);
 
-/* Create a surrogate (1 <= m <= 48): local_vars host [M][4], init_params host
+/* Create a surrogate for the bump family (1 <= m <= 48): local_vars host [M][4], init_params host
  * [M][STOMSFEM_MLP_NPARAM] (the caller draws the initial weights), fam = the
  * coefficient family used by the fallback, box = training box of the local
  * variables.  Synchronous. */
@@ -440,6 +440,30 @@ int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* loca
  * and targets (device copies owned by the model). */
 int stomsfem_mlp_set_data(stomsfem_model* model, const double* xi, int32_t nxi, const double* S, int64_t ntrain,
                           void* stream);
+
+/* Surrogate for the channels-and-inclusions medium (stomsfem_coef_features)
+ * on an nc x nc coarse mesh (nfine = nc*m).  The local variables of K are
+ * the features that cover a fine element of K (the local parametrization of
+ * Sec. 3, eq. MsFEB2, for this medium); a patch with more than 4 always takes
+ * the plain path.  The network sees 2/(1 + exp(-xi_j)) - 1 (the covered
+ * fraction of the decades, in [-1, 1]) instead of xi_j and predicts S_K
+ * divided by the mean conductivity over the fine elements along the boundary
+ * of K (the linear boundary conditions prescribe the gradient there, so max|S_K|
+ * follows this mean over the decades); the gate's residual and uncertainty are
+ * ratios and do not change with that scale.  map device
+ * [nfine][nfine] (stomsfem_feature_map), copied; decades as in
+ * stomsfem_coef_features; init_params host [nc*nc][STOMSFEM_MLP_NPARAM];
+ * box bounds the local variables (in xi).  The plain fallback regenerates the
+ * listed pairs' coefficient blocks from the map for every m.  Such a model is
+ * not saved by stomsfem_model_save (EINVAL).  Synchronous.
+ * stomsfem_local_vars_features: the same local variables on the host from a
+ * host map [ncy*m][ncx*m]: local_vars[K][kmax] increasing, -1 padded, or
+ * {-2, -1, ..} when K has more than kmax; nlocal[K] their number (may be
+ * NULL).  EINVAL for a map entry outside [-1, nfeat). */
+int stomsfem_local_vars_features(int32_t ncx, int32_t ncy, int32_t m, const int32_t* map, int32_t nfeat,
+                                 int32_t kmax, int32_t* local_vars, int32_t* nlocal);
+int stomsfem_mlp_create_features(int32_t nc, int32_t m, const int32_t* map, int32_t nfeat, double decades,
+                                 const float* init_params, double box, stomsfem_model** model);
 
 /* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
  * minibatches of STOMSFEM_MLP_BATCH pairs per patch taken cyclically from
@@ -742,7 +766,8 @@ int stomsfem_tuning_reset(void);
  *   ABI version, kind, mesh, scalars, coefficient family) followed by the
  *   model's device arrays, each preceded by (index, element size, count).
  *   The surrogate's training data are not written (stomsfem_mlp_set_data
- *   again before further training).  Synchronous.
+ *   again before further training); a surrogate of the channels medium is
+ *   not written (EINVAL).  Synchronous.
  * stomsfem_model_load: reads such a file onto the current device; the loaded
  *   model's online results are bitwise those of the saved one.
  *   STOMSFEM_EVERSION for a file of another ABI version or no model file,

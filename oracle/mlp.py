@@ -139,11 +139,16 @@ def _unpack4(s10):
     return S
 
 
-def gate(Y: np.ndarray, mu: np.ndarray, sd: np.ndarray, X: np.ndarray, nlocal: int, tau: float, box: float = 1.0):
+def gate(Y: np.ndarray, mu: np.ndarray, sd: np.ndarray, X: np.ndarray, nlocal: int, tau: float, box: float = 1.0,
+         scale: np.ndarray | None = None):
     """Y [B][20] raw network outputs -> (accepted mask [B], S [B][10] packed,
-    residual [B], uncertainty [B])."""
-    SA = mu + sd * Y[:, :NOUT]
-    SB = mu + sd * Y[:, NOUT:]
+    residual [B], uncertainty [B]).  scale [B] (optional): the network
+    predicts S / scale (a per-pair output scale), so both heads are multiplied
+    by it after de-standardisation; the two signals are ratios of entries of
+    S and do not change with it."""
+    osc = np.ones(len(Y)) if scale is None else np.asarray(scale, dtype=np.float64)
+    SA = osc[:, None] * (mu + sd * Y[:, :NOUT])
+    SB = osc[:, None] * (mu + sd * Y[:, NOUT:])
     S = 0.5 * (SA + SB)
     S4 = _unpack4(S)
     scale = np.abs(S).max(-1)
@@ -155,3 +160,39 @@ def gate(Y: np.ndarray, mu: np.ndarray, sd: np.ndarray, X: np.ndarray, nlocal: i
     Sp = P @ S4 @ P
     packed = np.stack([Sp[:, i, j] for (i, j) in PACK], axis=-1)
     return ok, packed, resid, unc
+
+
+# --- channels-and-inclusions medium ------------------------------------------
+# A reading for this medium (its conductivities theta_j = 10^(d sigma(xi_j)),
+# sigma the logistic function, span d decades): the network input of a local
+# feature is u_j = 2 sigma(xi_j) - 1, the covered fraction of the decades
+# mapped to [-1, 1], and the predicted quantity is S_K divided by the mean of
+# the coefficient over the fine elements that touch the boundary of K (with
+# linear boundary conditions those elements carry the prescribed gradient, so
+# max |S_K| follows this mean over the decades; the mean over all of K, or
+# 1 + sum_j theta_j, do not).
+
+
+def local_features(fmap: np.ndarray, ncx: int, ncy: int, m: int) -> list[list[int]]:
+    """Sorted distinct feature indices covering a fine element of each coarse
+    element K = ky*ncx + kx (fmap [ncy*m][ncx*m], -1 = background)."""
+    out = []
+    for ky in range(ncy):
+        for kx in range(ncx):
+            blk = fmap[ky * m:(ky + 1) * m, kx * m:(kx + 1) * m]
+            out.append(sorted({int(v) for v in blk.ravel() if v >= 0}))
+    return out
+
+
+def features_input(xi: np.ndarray) -> np.ndarray:
+    """u = 2 / (1 + exp(-xi)) - 1."""
+    return 2.0 / (1.0 + np.exp(-xi)) - 1.0
+
+
+def ring_mean(a_blk: np.ndarray) -> float:
+    """Mean of an m x m coefficient block over its boundary ring of fine
+    elements (each element once)."""
+    m = a_blk.shape[0]
+    ring = np.zeros((m, m), dtype=bool)
+    ring[0, :] = ring[-1, :] = ring[:, 0] = ring[:, -1] = True
+    return float(a_blk[ring].mean())

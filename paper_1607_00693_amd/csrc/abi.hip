@@ -299,6 +299,11 @@ struct stomsfem_model {
   int32_t lv_max = -1;        // largest local-variable index
   int64_t* list = nullptr;    // fallback list
   int64_t list_cap = 0;
+  int32_t family = 0;         // surrogate coefficient family (MLP_FAMILY_*)
+  int32_t* fmap = nullptr;    // channels medium: feature per fine element [nc*m][nc*m]
+  double* rw = nullptr;       // channels medium: [M][4] boundary-ring fractions of the local features
+  int32_t nfeat = 0;
+  double decades = 0.0;
   unsigned long long* counter = nullptr;
   // random interpolation (kind 3)
   int nn = 0;
@@ -371,6 +376,8 @@ void model_release(stomsfem_model* md) {
   hipFree(md->cb_boff);
   hipFree(md->cb_rows);
   hipFree(md->sg_nodes);
+  hipFree(md->fmap);
+  hipFree(md->rw);
   if (md->order_ev) hipEventDestroy(md->order_ev);
   hipSetDevice(cur);
   delete md;
@@ -1545,8 +1552,96 @@ int stomsfem_local_vars_bumps(int32_t ncx, int32_t ncy, int32_t m, const stomsfe
   return STOMSFEM_OK;
 }
 
+int stomsfem_local_vars_features(int32_t ncx, int32_t ncy, int32_t m, const int32_t* map, int32_t nfeat,
+                                 int32_t kmax, int32_t* local_vars, int32_t* nlocal) {
+  if (!map || !local_vars) return fail(STOMSFEM_EINVAL, "local_vars_features: NULL argument");
+  if (ncx < 1 || ncy < 1 || m < 1 || nfeat < 1 || kmax < 1)
+    return fail(STOMSFEM_EINVAL, "local_vars_features: bad sizes");
+  const int64_t nfx = (int64_t)ncx * m;
+  for (int K = 0; K < ncx * ncy; ++K) {
+    const int kx = K % ncx, ky = K / ncx;
+    std::vector<int32_t> feats;
+    for (int ey = 0; ey < m; ++ey)
+      for (int ex = 0; ex < m; ++ex) {
+        const int32_t f = map[(int64_t)(ky * m + ey) * nfx + kx * m + ex];
+        if (f < -1 || f >= nfeat) return fail(STOMSFEM_EINVAL, "local_vars_features: map entry out of range");
+        if (f >= 0) feats.push_back(f);
+      }
+    std::sort(feats.begin(), feats.end());
+    feats.erase(std::unique(feats.begin(), feats.end()), feats.end());
+    const int cnt = (int)feats.size();
+    for (int c = 0; c < kmax; ++c)
+      local_vars[K * kmax + c] = cnt > kmax ? (c == 0 ? MLP_LV_ALWAYS_PLAIN : -1) : (c < cnt ? feats[c] : -1);
+    if (nlocal) nlocal[K] = cnt;
+  }
+  return STOMSFEM_OK;
+}
+
+static int mlp_create_common(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
+                             const stomsfem_bump_family* fam, double box, stomsfem_model** model);
+
+int stomsfem_mlp_create_features(int32_t nc, int32_t m, const int32_t* map, int32_t nfeat, double decades,
+                                 const float* init_params, double box, stomsfem_model** model) {
+  if (!map || !init_params || !model) return fail(STOMSFEM_EINVAL, "mlp_create_features: NULL argument");
+  if (nc < 1 || m < 1 || m > 48 || nfeat < 1) return fail(STOMSFEM_EINVAL, "mlp_create_features: bad sizes");
+  if (!(decades > 0) || !(box > 0)) return fail(STOMSFEM_EINVAL, "mlp_create_features: need decades > 0 and box > 0");
+  if (!device_ptr(map)) return fail(STOMSFEM_EINVAL, "mlp_create_features: map must be a device pointer");
+  *model = nullptr;
+  const int64_t nf = (int64_t)nc * m;
+  std::vector<int32_t> hmap((size_t)(nf * nf));
+  hipError_t e = hipMemcpy(hmap.data(), map, sizeof(int32_t) * hmap.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "mlp_create_features");
+  const int Mc = nc * nc;
+  std::vector<int32_t> lv((size_t)Mc * MLP_KIN);
+  int rc = stomsfem_local_vars_features(nc, nc, m, hmap.data(), nfeat, MLP_KIN, lv.data(), nullptr);
+  if (rc != STOMSFEM_OK) return rc;
+  // fraction of each patch's boundary ring of fine elements owned by each
+  // local feature (the output scale of the network)
+  std::vector<double> rw((size_t)Mc * MLP_KIN, 0.0);
+  const int nring = m == 1 ? 1 : 4 * m - 4;
+  for (int K = 0; K < Mc; ++K) {
+    const int kx = K % nc, ky = K / nc;
+    for (int ey = 0; ey < m; ++ey)
+      for (int ex = 0; ex < m; ++ex) {
+        if (ey != 0 && ey != m - 1 && ex != 0 && ex != m - 1) continue;
+        const int32_t f = hmap[(int64_t)(ky * m + ey) * nf + kx * m + ex];
+        for (int c = 0; c < MLP_KIN; ++c)
+          if (f >= 0 && lv[K * MLP_KIN + c] == f) rw[K * MLP_KIN + c] += 1.0 / nring;
+      }
+  }
+  stomsfem_model* md = nullptr;
+  rc = mlp_create_common(nc, nc, m, lv.data(), init_params, nullptr, box, &md);
+  if (rc != STOMSFEM_OK) return rc;
+  md->family = MLP_FAMILY_FEATURES;
+  md->nfeat = nfeat;
+  md->decades = decades;
+  md->lv_max = std::max(md->lv_max, nfeat - 1);
+  e = hipMalloc(&md->fmap, sizeof(int32_t) * hmap.size());
+  if (e == hipSuccess) e = hipMemcpy(md->fmap, hmap.data(), sizeof(int32_t) * hmap.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&md->rw, sizeof(double) * rw.size());
+  if (e == hipSuccess) e = hipMemcpy(md->rw, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !md->blk) {  // the chunked plain fallback serves every m for this family
+    md->chunk = std::max<int64_t>(256, std::min<int64_t>(65536, (int64_t{1} << 25) / ((int64_t)m * m)));
+    e = hipMalloc(&md->blk, sizeof(double) * (size_t)md->chunk * m * m);
+    if (e == hipSuccess) e = hipMalloc(&md->Sc, sizeof(double) * (size_t)md->chunk * 10);
+    if (e == hipSuccess) e = hipMalloc(&md->stc, sizeof(int32_t) * (size_t)md->chunk);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "mlp_create_features: device allocation failed");
+  }
+  *model = md;
+  return STOMSFEM_OK;
+}
+
 int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
                         const stomsfem_bump_family* fam, double box, stomsfem_model** model) {
+  return mlp_create_common(ncx, ncy, m, local_vars, init_params, fam, box, model);
+}
+
+static int mlp_create_common(int32_t ncx, int32_t ncy, int32_t m, const int32_t* local_vars, const float* init_params,
+                             const stomsfem_bump_family* fam, double box, stomsfem_model** model) {
   if (!local_vars || !init_params || !model) return fail(STOMSFEM_EINVAL, "mlp_create: NULL argument");
   if (ncx < 1 || ncy < 1 || m < 1 || m > 48) return fail(STOMSFEM_EINVAL, "mlp_create: need 1 <= m <= 48");
   if (!(box > 0)) return fail(STOMSFEM_EINVAL, "mlp_create: box must be > 0");
@@ -1561,7 +1656,7 @@ int stomsfem_mlp_create(int32_t ncx, int32_t ncy, int32_t m, const int32_t* loca
   md->box = box;
   if (fam) md->fam = *fam;
   for (int i = 0; i < Mc * MLP_KIN; ++i) {
-    if (local_vars[i] < -1) {
+    if (local_vars[i] < -1 && !(local_vars[i] == MLP_LV_ALWAYS_PLAIN && i % MLP_KIN == 0)) {
       delete md;
       return fail(STOMSFEM_EINVAL, "mlp_create: local variable indices must be >= 0 or -1 (padding)");
     }
@@ -1619,6 +1714,9 @@ int stomsfem_mlp_set_data(stomsfem_model* model, const double* xi, int32_t nxi, 
   }
   model->ntrain = ntrain;
   MlpDataArgs d{};
+  d.family = model->family;
+  d.decades = model->decades;
+  d.rw = model->rw;
   d.npatch = Mc;
   d.nxi = nxi;
   d.ntrain = ntrain;
@@ -1716,7 +1814,8 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   OrderedUse order;  // the model's scratch buffers (fallback list, counter, chunk buffers)
   if (int orc = order.begin(model->order_mu, model->order_ev, (hipStream_t)stream); orc != STOMSFEM_OK) return orc;
   if (S) {
-    if (model->fam.g < 1 || model->fam.g * model->fam.g > nxi)
+    if (model->family == MLP_FAMILY_FEATURES ? nxi < model->nfeat
+                                             : (model->fam.g < 1 || model->fam.g * model->fam.g > nxi))
       return fail(STOMSFEM_EINVAL, "surrogate: the model's coefficient family does not match xi");
     const int64_t need = nsamples * Mc;
     if (model->list_cap < need) {
@@ -1735,6 +1834,9 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
     }
   }
   MlpInferArgs a{};
+  a.family = model->family;
+  a.decades = model->decades;
+  a.rw = model->rw;
   a.npatch = Mc;
   a.ncx = model->ncx;
   a.nxi = nxi;
@@ -1762,7 +1864,7 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_mlp_infer(a, precision == STOMSFEM_PREC_BF16, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate launch");
-  if (!S || model->m == 8) return STOMSFEM_OK;
+  if (!S || (model->m == 8 && model->family == MLP_FAMILY_BUMPS)) return STOMSFEM_OK;
   // plain fallback for m != 8: the listed pairs in chunks (reads the count)
   unsigned long long n = 0;
   e = hipMemcpyAsync(&n, model->counter, sizeof(n), hipMemcpyDeviceToHost, st);
@@ -1779,6 +1881,8 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
     r.m = model->m;
     r.nxi = nxi;
     r.bp = BumpParams{model->fam.g, model->fam.rho, model->fam.eps, model->fam.base, model->fam.amp, model->fam.beta};
+    r.fmap = model->family == MLP_FAMILY_FEATURES ? model->fmap : nullptr;
+    r.decades = model->decades;
     r.pairs = model->list + start;
     r.count = cnt;
     r.xi = xi;
@@ -1814,6 +1918,9 @@ int stomsfem_mlp_gate(const stomsfem_model* model, const float* Y, const double*
   if ((status && !device_ptr(status)) || (gate && !device_ptr(gate)))
     return fail(STOMSFEM_EINVAL, "mlp_gate: status and gate must be device pointers");
   MlpInferArgs a{};
+  a.family = model->family;
+  a.decades = model->decades;
+  a.rw = model->rw;
   a.npatch = model->ncx * model->ncy;
   a.ncx = model->ncx;
   a.nxi = nxi;
@@ -2685,6 +2792,8 @@ std::vector<ArraySpec> model_arrays(stomsfem_model* md) {
 int stomsfem_model_save(const stomsfem_model* model, const char* path) {
   if (!model || !path) return fail(STOMSFEM_EINVAL, "model_save: NULL argument");
   if (model->kind < 1 || model->kind > 3) return fail(STOMSFEM_EINVAL, "model_save: unknown model kind");
+  if (model->family != MLP_FAMILY_BUMPS)
+    return fail(STOMSFEM_EINVAL, "model_save: surrogates of the channels medium are not saved");
   ModelFileHeader h{};
   std::memcpy(h.magic, kModelMagic, 8);
   h.abi = STOMSFEM_ABI_VERSION;

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void coef_features_kernel(int64_t per, int32_t
     const int64_t e0 = (b - s * tiles) * FEAT_TILE;
     if (s != s_loaded) {
       __syncthreads();
-      for (int j = threadIdx.x; j < nfeat; j += 256) th[j] = pow(10.0, decades / (1.0 + exp(-xi[s * nxi + j])));
+      for (int j = threadIdx.x; j < nfeat; j += 256) th[j] = feature_theta(xi[s * nxi + j], decades);
       __syncthreads();
       s_loaded = s;
     }

@@ -118,6 +118,13 @@ __device__ __forceinline__ double bump_field(double x, double y, const double* x
   return bump_field_cell(x, y, xs, bp, bump_cell(x, bp.g), bump_cell(y, bp.g));
 }
 
+// Conductivity of feature j of the channels-and-inclusions medium:
+// theta = 10^(decades sigmoid(xi_j)) (the bounded transform of Sec. 2.1.3).
+// Every kernel that forms it uses this function, so they agree bit for bit.
+__device__ __forceinline__ double feature_theta(double xi, double decades) {
+  return pow(10.0, decades / (1.0 + exp(-xi)));
+}
+
 // a(x, xi) of the bump family at the point (x, y).
 __device__ __forceinline__ double bump_coef(double x, double y, const double* xs, const BumpParams& bp) {
   const double field = bump_field(x, y, xs, bp);

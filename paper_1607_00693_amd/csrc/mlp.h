@@ -41,7 +41,24 @@ struct MlpTrainArgs {
   float* loss;          // [M] loss of the last minibatch, or NULL
 };
 
+// Coefficient family of a surrogate: 0 = the bump family (inputs xi_j as
+// they are); 1 = the channels-and-inclusions medium: inputs 2 sigmoid(xi_j) - 1
+// (the fraction of the conductivity decades, in [-1, 1]) and outputs S divided
+// by the mean conductivity over the patch's boundary ring of fine elements,
+// 1 + sum_c rw_c (theta_c - 1) with rw_c the fraction of ring elements owned
+// by local feature c (with linear boundary conditions the boundary elements
+// carry the prescribed gradient, so this mean follows max|S| over the decades
+// far more closely than the patch mean does); a patch with more than four
+// local features carries the local-variable sentinel -2 and always takes the
+// plain path.
+constexpr int MLP_FAMILY_BUMPS = 0;
+constexpr int MLP_FAMILY_FEATURES = 1;
+constexpr int MLP_LV_ALWAYS_PLAIN = -2;
+
 struct MlpDataArgs {
+  int32_t family;
+  double decades;
+  const double* rw;     // family 1: [M][KIN] ring fractions of the local features
   int32_t npatch, nxi;
   int64_t ntrain;
   const int32_t* lv;    // [M][KIN]
@@ -55,6 +72,9 @@ struct MlpDataArgs {
 };
 
 struct MlpInferArgs {
+  int32_t family;
+  double decades;
+  const double* rw;     // family 1: [M][KIN] ring fractions of the local features
   int32_t npatch, ncx, nxi;
   int64_t nsamples;
   const float* params;

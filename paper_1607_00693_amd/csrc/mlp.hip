@@ -39,6 +39,20 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
   return Phi + z * phi;
 }
 
+// network input of local variable value xi, and the output scale of a
+// (sample, patch): see MLP_FAMILY_FEATURES
+__device__ __forceinline__ double mlp_input(int family, double xi) {
+  return family == MLP_FAMILY_FEATURES ? 2.0 / (1.0 + exp(-xi)) - 1.0 : xi;
+}
+__device__ __forceinline__ double mlp_out_scale(int family, double decades, const int32_t* lv, const double* rw,
+                                                const double* xs) {
+  if (family != MLP_FAMILY_FEATURES) return 1.0;
+  double sc = 1.0;
+  for (int c = 0; c < MLP_KIN; ++c)
+    if (lv[c] >= 0) sc += rw[c] * (feature_theta(xs[lv[c]], decades) - 1.0);
+  return sc;
+}
+
 // ---------------------------------------------------------------------------
 // Training / gradients
 // ---------------------------------------------------------------------------
@@ -238,10 +252,11 @@ __global__ void mlp_gather_kernel(MlpDataArgs d) {
   const int64_t s = t % d.ntrain;
   for (int c = 0; c < MLP_KIN; ++c) {
     const int j = d.lv[K * MLP_KIN + c];
-    d.X[t * MLP_KIN + c] = j >= 0 ? (float)d.xi[s * d.nxi + j] : 0.0f;
+    d.X[t * MLP_KIN + c] = j >= 0 ? (float)mlp_input(d.family, d.xi[s * d.nxi + j]) : 0.0f;
   }
   const double* S = d.S + (s * d.npatch + K) * 10;
-  for (int q = 0; q < 10; ++q) d.T[t * 10 + q] = (float)((S[q] - d.mu[K * 10 + q]) / d.sd[K * 10 + q]);
+  const double sc = mlp_out_scale(d.family, d.decades, d.lv + K * MLP_KIN, d.rw + K * MLP_KIN, d.xi + s * d.nxi);
+  for (int q = 0; q < 10; ++q) d.T[t * 10 + q] = (float)((S[q] / sc - d.mu[K * 10 + q]) / d.sd[K * 10 + q]);
 }
 
 // Per-patch, per-entry mean and standard deviation (FP64, fixed order).
@@ -249,12 +264,15 @@ __global__ void mlp_stats_kernel(MlpDataArgs d) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.npatch * 10) return;
   const int K = t / 10, q = t % 10;
+  const int32_t* lv = d.lv + K * MLP_KIN;
+  const double* rw = d.rw + K * MLP_KIN;
   double m = 0.0;
-  for (int64_t s = 0; s < d.ntrain; ++s) m += d.S[(s * d.npatch + K) * 10 + q];
+  for (int64_t s = 0; s < d.ntrain; ++s)
+    m += d.S[(s * d.npatch + K) * 10 + q] / mlp_out_scale(d.family, d.decades, lv, rw, d.xi + s * d.nxi);
   m /= (double)d.ntrain;
   double v = 0.0;
   for (int64_t s = 0; s < d.ntrain; ++s) {
-    const double e = d.S[(s * d.npatch + K) * 10 + q] - m;
+    const double e = d.S[(s * d.npatch + K) * 10 + q] / mlp_out_scale(d.family, d.decades, lv, rw, d.xi + s * d.nxi) - m;
     v += e * e;
   }
   double sd = sqrt(v / (double)d.ntrain);
@@ -281,22 +299,23 @@ hipError_t launch_mlp_data(const MlpDataArgs& d, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Inference and gate
 // ---------------------------------------------------------------------------
-// The gate of one pair from its 20 raw outputs y (heads A and B): writes the
+// The gate of one pair from its 20 raw outputs y (heads A and B, each
+// de-standardised and multiplied by the output scale osc): writes the
 // stored S (P S P if accepted, else the head mean), the residual and the
 // uncertainty, and returns acceptance.  A pair is accepted only if all 20
 // de-standardised values are finite, max|S| > 0, both signals are <= tau and
 // every local variable is inside the box; with a non-finite value the two
 // signals are NaN (comparisons are written so that NaN never passes).
 __device__ __forceinline__ bool gate_pair(const double* __restrict__ mu, const double* __restrict__ sd,
-                                          const float* y, bool inbox, double tau, double* Sout, double* resid_out,
-                                          double* unc_out) {
+                                          const float* y, double osc, bool inbox, double tau, double* Sout,
+                                          double* resid_out, double* unc_out) {
   double SA[10], SB[10], S[10];
   double scale = 0.0, unc = 0.0;
   bool finite = true;
 #pragma unroll
   for (int q = 0; q < 10; ++q) {
-    SA[q] = mu[q] + sd[q] * (double)y[q];
-    SB[q] = mu[q] + sd[q] * (double)y[10 + q];
+    SA[q] = osc * (mu[q] + sd[q] * (double)y[q]);
+    SB[q] = osc * (mu[q] + sd[q] * (double)y[10 + q]);
     finite = finite && isfinite(SA[q]) && isfinite(SB[q]);
     S[q] = 0.5 * (SA[q] + SB[q]);
     scale = fmax(scale, fabs(S[q]));
@@ -334,16 +353,22 @@ __device__ __forceinline__ bool local_vars_in_box(const MlpInferArgs& a, int K, 
   bool inbox = true;
   for (int c = 0; c < MLP_KIN; ++c) {
     const int j = a.lv[K * MLP_KIN + c];
+    if (j == MLP_LV_ALWAYS_PLAIN) inbox = false;
     if (j >= 0 && !(fabs(a.xi[s * a.nxi + j]) <= a.box)) inbox = false;
   }
   return inbox;
+}
+
+__device__ __forceinline__ double out_scale_of(const MlpInferArgs& a, int K, int64_t s) {
+  return mlp_out_scale(a.family, a.decades, a.lv + K * MLP_KIN, a.rw + K * MLP_KIN, a.xi + s * a.nxi);
 }
 
 __device__ __forceinline__ void gate_and_store(const MlpInferArgs& a, int K, int64_t s, const float* y, double* Sout,
                                                int32_t* st, bool* fallback) {
   const int64_t p = s * a.npatch + K;
   double resid, unc;
-  const bool ok = gate_pair(a.mu + K * 10, a.sd + K * 10, y, local_vars_in_box(a, K, s), a.tau, Sout, &resid, &unc);
+  const bool ok = gate_pair(a.mu + K * 10, a.sd + K * 10, y, out_scale_of(a, K, s), local_vars_in_box(a, K, s), a.tau,
+                            Sout, &resid, &unc);
   if (a.gate) {
     a.gate[2 * p] = resid;
     a.gate[2 * p + 1] = unc;
@@ -364,8 +389,8 @@ __global__ __launch_bounds__(256) void mlp_gate_kernel(MlpInferArgs a, const flo
 #pragma unroll
   for (int o = 0; o < NO; ++o) y[o] = Yin[p * NO + o];
   double resid, unc;
-  const bool ok =
-      gate_pair(a.mu + K * 10, a.sd + K * 10, y, local_vars_in_box(a, K, s), a.tau, a.S + p * 10, &resid, &unc);
+  const bool ok = gate_pair(a.mu + K * 10, a.sd + K * 10, y, out_scale_of(a, K, s), local_vars_in_box(a, K, s), a.tau,
+                            a.S + p * 10, &resid, &unc);
   if (a.gate) {
     a.gate[2 * p] = resid;
     a.gate[2 * p + 1] = unc;
@@ -401,7 +426,7 @@ __global__ __launch_bounds__(64) void mlp_infer_f32_kernel(MlpInferArgs a) {
 #pragma unroll
   for (int c = 0; c < MLP_KIN; ++c) {
     const int j = a.lv[K * MLP_KIN + c];
-    x[c] = j >= 0 ? (float)a.xi[s * a.nxi + j] : 0.0f;
+    x[c] = j >= 0 ? (float)mlp_input(a.family, a.xi[s * a.nxi + j]) : 0.0f;
   }
 #pragma unroll
   for (int j = 0; j < WD; ++j) z[j] = Wl[MLP_OB1 + j];
@@ -587,10 +612,10 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
       f32x4_t x4 = z4;  // layer-1 B operand: x in slots 0..3 of lane group 0
       if (g == 0 && s < a.nsamples) {
         const double* xs = a.xi + s * a.nxi;
-        x4[0] = lv0 >= 0 ? (float)xs[lv0] : 0.0f;
-        x4[1] = lv1 >= 0 ? (float)xs[lv1] : 0.0f;
-        x4[2] = lv2 >= 0 ? (float)xs[lv2] : 0.0f;
-        x4[3] = lv3 >= 0 ? (float)xs[lv3] : 0.0f;
+        x4[0] = lv0 >= 0 ? (float)mlp_input(a.family, xs[lv0]) : 0.0f;
+        x4[1] = lv1 >= 0 ? (float)mlp_input(a.family, xs[lv1]) : 0.0f;
+        x4[2] = lv2 >= 0 ? (float)mlp_input(a.family, xs[lv2]) : 0.0f;
+        x4[3] = lv3 >= 0 ? (float)mlp_input(a.family, xs[lv3]) : 0.0f;
       }
       split8(x4, z4, bh[st][0], bl[st][0]);
     }
@@ -828,7 +853,7 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
     hipLaunchKernelGGL(mlp_infer_f32_kernel, grid, dim3(64), 0, st, a);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !a.S || a.m != 8) return e;
+  if (e != hipSuccess || !a.S || a.m != 8 || a.family != MLP_FAMILY_BUMPS) return e;
   // the listed count is known only on the device: enough wavefronts for
   // about 3% of the pairs in one pass, looping beyond that
   int64_t blocks = (a.nsamples * a.npatch / 32 + 63) / 64;

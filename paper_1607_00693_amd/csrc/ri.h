@@ -29,6 +29,11 @@ struct RiNodeArgs {
 struct RegenArgs {
   int32_t ncx, ncy, m, nxi;
   BumpParams bp;
+  // channels-and-inclusions medium instead of the bump family when fmap is
+  // set: fmap [ncy*m][ncx*m] feature per fine element (-1: background 1),
+  // conductivity feature_theta(xi_j, decades)
+  const int32_t* fmap;
+  double decades;
   const int64_t* pairs;  // [count]
   int64_t count;
   const double* xi;      // [..][nxi]

@@ -61,6 +61,11 @@ __global__ __launch_bounds__(256) void regen_blocks_kernel(RegenArgs a) {
   const int K = (int)(p - s * npatch);
   const int kx = K % a.ncx, ky = K / a.ncx;
   const int ex = e % a.m, ey = e / a.m;
+  if (a.fmap) {
+    const int32_t f = a.fmap[(int64_t)(ky * a.m + ey) * ((int64_t)a.ncx * a.m) + kx * a.m + ex];
+    a.out[t] = (unsigned)f < (unsigned)a.nxi ? feature_theta(a.xi[s * a.nxi + f], a.decades) : 1.0;
+    return;
+  }
   const double h = 1.0 / ((double)a.ncx * a.m);
   a.out[t] = bump_coef((kx * a.m + ex + 0.5) * h, (ky * a.m + ey + 0.5) * h, a.xi + s * a.nxi, a.bp);
 }

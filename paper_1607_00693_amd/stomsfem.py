@@ -94,6 +94,8 @@ def lib():
         "stomsfem_model_free": (C.c_int, [vp]),
         "stomsfem_local_vars_bumps": (C.c_int, [i32, i32, i32, C.POINTER(BumpFamily), i32, vp, vp]),
         "stomsfem_mlp_create": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(BumpFamily), dbl, C.POINTER(vp)]),
+        "stomsfem_local_vars_features": (C.c_int, [i32, i32, i32, vp, i32, i32, vp, vp]),
+        "stomsfem_mlp_create_features": (C.c_int, [i32, i32, vp, i32, dbl, vp, dbl, C.POINTER(vp)]),
         "stomsfem_mlp_set_data": (C.c_int, [vp, vp, i32, vp, i64, vp]),
         "stomsfem_mlp_train": (C.c_int, [vp, i32, C.c_float, vp, vp, vp]),
         "stomsfem_mlp_grad": (C.c_int, [vp, vp, vp, vp, vp, vp]),
@@ -523,6 +525,35 @@ def mlp_create(ncx: int, ncy: int, m: int, lv, init_params, fam: BumpFamily, box
     _check("stomsfem_mlp_create", lib().stomsfem_mlp_create(
         ncx, ncy, m, lv.ctypes.data_as(C.c_void_p), ip.ctypes.data_as(C.c_void_p), C.byref(fam), box, C.byref(h)))
     return Model(h, ncx, ncy, m)
+
+
+def local_vars_features(ncx: int, ncy: int, m: int, fmap, nfeat: int, kmax: int = MLP_KIN):
+    """Host computation of each patch's features from a host map -> (lv [M][kmax] int32, nlocal [M])."""
+    import numpy as np
+
+    fm = np.ascontiguousarray(fmap, dtype=np.int32)
+    assert fm.shape == (ncy * m, ncx * m)
+    M = ncx * ncy
+    lv = np.zeros((M, kmax), dtype=np.int32)
+    nl = np.zeros(M, dtype=np.int32)
+    _check("stomsfem_local_vars_features", lib().stomsfem_local_vars_features(
+        ncx, ncy, m, fm.ctypes.data_as(C.c_void_p), nfeat, kmax, lv.ctypes.data_as(C.c_void_p),
+        nl.ctypes.data_as(C.c_void_p)))
+    return lv, nl
+
+
+def mlp_create_features(nc: int, m: int, fmap: torch.Tensor, nfeat: int, decades: float, init_params,
+                        box: float = 1.0) -> Model:
+    """Surrogate of the channels medium; fmap device int32 [nc*m][nc*m]."""
+    import numpy as np
+
+    assert fmap.dtype == torch.int32 and fmap.is_contiguous() and tuple(fmap.shape) == (nc * m, nc * m)
+    ip = np.ascontiguousarray(init_params, dtype=np.float32)
+    assert ip.shape == (nc * nc, MLP_NPARAM)
+    h = C.c_void_p()
+    _check("stomsfem_mlp_create_features", lib().stomsfem_mlp_create_features(
+        nc, m, _ptr(fmap), nfeat, decades, ip.ctypes.data_as(C.c_void_p), box, C.byref(h)))
+    return Model(h, nc, nc, m)
 
 
 def mlp_set_data(model: Model, xi: torch.Tensor, S: torch.Tensor, stream=None):

@@ -7,12 +7,13 @@ largest gradient entry of the patch (single-precision sums of 32 to 64
 terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
 units); BF16 forward (three-term bf16 splitting, FP32 accumulation) within 1e-3
 of the FP64 oracle's forward pass; the standardisation within 1e-13 of the
-oracle's (FP64 on both sides, different summation orders); an FP32 Adam step
-within 2 float ulps plus 1e-4 of the step of the FP64 oracle step from the
-same parameters and gradient (the FP32 bias corrections 1 - beta^t carry
-relative errors of a few 1e-5 from cancellation); the gate on identical raw outputs: accept mask exact, residual and
-uncertainty within 1e-12 relative (both FP64 from the same FP32 outputs), the
-stored S within 1e-10 relative to max|S| of the pair.
+oracle's (FP64 on both sides, different summation orders); five FP32 Adam
+steps within 2e-2 of the learning rate of the oracle's FP64 trajectory from
+the same seeded weights, on the components whose gradient stays above 1e-2
+of the patch maximum; the gate on identical raw outputs (built from the
+oracle's S and standardisation): accept mask exact, residual and uncertainty
+within 1e-12 relative, the stored S within 1e-10 relative to max|S| of the
+pair.  Every oracle input comes from the seeded generators or the oracle.
 The end-to-end criterion is the coarse solution: surrogate within 1e-3
 (relative, per sample) of the plain FP64 path.
 """
@@ -83,15 +84,17 @@ def trained(sm):
     return dict(wl=wl, model=model, lv=lv, nl=nl)
 
 
-def test_forward_fp32_and_bf16(sm, trained):
+def test_forward_fp32_and_bf16(sm):
+    # the network with its seeded initial weights (no GPU-trained parameters
+    # enter the oracle)
     from oracle import mlp
-    wl, model, lv = trained["wl"], trained["model"], trained["lv"]
+    wl = W.MESH8
+    model, lv, nl, params = _model(sm, wl, 4104)
     say("forward FP32 vs oracle, BF16 vs FP32")
     xi = W.uniform_xi(64, wl.nxi, 1004)
     xi_d = torch.from_numpy(xi).cuda()
     Y32 = sm.mlp_predict(model, xi_d, sm.PREC_F32).cpu().numpy()
     Y16 = sm.mlp_predict(model, xi_d, sm.PREC_BF16).cpu().numpy()
-    params = sm.mlp_params(model).cpu().numpy()
     for K in range(0, wl.M, 5):
         X = np.where(lv[K] >= 0, xi[:, np.maximum(lv[K], 0)], 0.0).astype(np.float32).astype(np.float64)
         Yref, _ = mlp.forward(params[K].astype(np.float64), X, 4)
@@ -107,27 +110,40 @@ def test_forward_fp32_and_bf16(sm, trained):
         worst = max(worst, float(np.abs(Y16[:, K] - Yref).max() / max(1.0, np.abs(Yref).max())))
     say(f"max |Y_bf16 - Y_oracle| = {worst:.3e}")
     assert worst < 1e-3
+    model.free()
 
 
-def test_gate_matches_oracle(sm, trained):
-    # identical raw outputs through the GPU gate and the oracle's gate: the
-    # trained network's own outputs plus planted NaN, +-inf, head
-    # disagreement, row-sum violation and out-of-box local variables
+def test_gate_matches_oracle(sm, orc):
+    # raw outputs built from the oracle's S and the oracle's standardisation
+    # (exact heads, seeded noise of three sizes) plus planted NaN, +-inf, head
+    # disagreement, row-sum violation and out-of-box local variables, through
+    # the GPU gate and the oracle's gate
     from oracle import mlp
-    wl, model, lv, nl = trained["wl"], trained["model"], trained["lv"], trained["nl"]
+    wl = W.MESH8
+    model, lv, nl, _ = _model(sm, wl, 31)
     N = 256
     say(f"gate vs oracle on {N} samples x {wl.M} patches")
     xi = W.uniform_xi(N, wl.nxi, 1104)
     xi[5, :] = 1.25    # every local variable out of the box
+    S, st0, _ = orc.upscale(orc.coef_bumps(xi, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    assert (st0 == 0).all()
     xi_d = torch.from_numpy(xi).cuda()
-    Y = sm.mlp_predict(model, xi_d, sm.PREC_BF16).cpu().numpy()
+    sm.mlp_set_data(model, xi_d, torch.from_numpy(np.ascontiguousarray(S)).cuda())
+    mu = np.zeros((wl.M, 10))
+    sd = np.zeros((wl.M, 10))
+    for K in range(wl.M):
+        mu[K], sd[K] = mlp.standardize(S[:, K])
+    T = (S - mu[None]) / sd[None]
+    Y = np.concatenate([T, T], axis=-1)
+    lvl = np.array([0.0, 1e-7, 1e-5, 1e-3])[np.arange(N) % 4]
+    Y = Y + lvl[:, None, None] * W.uniform_array(Y.shape, -1.0, 1.0, 1204)
     Y[1, :, 3] = np.nan
     Y[2, :, 15] = np.inf
     Y[3, :, 0] = -np.inf
     Y[4, :, 12] += 0.05          # head B disagrees
     Y[6, :, [1, 11]] += 0.05     # both heads: row sums off
     Y[7, ::3, :] = 0.0           # the mean prediction
-    mu, sd = sm.mlp_standardization(model)
+    Y = Y.astype(np.float32)
     S_g, st_g, gate_g = sm.mlp_gate(model, torch.from_numpy(Y).cuda(), xi_d, 1e-3)
     torch.cuda.synchronize()
     S_g, st_g, gate_g = S_g.cpu().numpy(), st_g.cpu().numpy(), gate_g.cpu().numpy()
@@ -149,49 +165,58 @@ def test_gate_matches_oracle(sm, trained):
         assert (np.abs(S_g[rej, K] - Sm).max(-1) <= 1e-12 * np.abs(Sm).max(-1)).all(), K
         nacc += int(ok.sum())
     assert not (st_g[1:4] == 0).any() and not (st_g[5] == 0).any()
+    assert (st_g[0] == 0).all()
     say(f"gate agrees on all {N * wl.M} pairs ({nacc} accepted)")
+    model.free()
 
 
 def test_standardization_and_adam_steps_match_oracle(sm, orc):
-    # FP64 standardisation of the training targets, then five FP32 Adam steps
-    # on one fixed minibatch, each against the oracle's FP64 step taken from
-    # the same parameters and the same (GPU) gradient
+    # FP64 standardisation of the oracle's training targets, then five FP32
+    # Adam steps on one fixed minibatch against the oracle's FP64 trajectory
     from oracle import mlp
     wl = W.MESH8
     model, lv, nl, init = _model(sm, wl, 21)
     ntr = 32
     xi_tr = W.uniform_xi(ntr, wl.nxi, 2204)
     xi_d = torch.from_numpy(xi_tr).cuda()
-    S_tr = sm.upscale(sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
-    sm.mlp_set_data(model, xi_d, S_tr)
+    S_np, st0, _ = orc.upscale(orc.coef_bumps(xi_tr, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m)
+    assert (st0 == 0).all()
+    sm.mlp_set_data(model, xi_d, torch.from_numpy(np.ascontiguousarray(S_np)).cuda())
     mu, sd = sm.mlp_standardization(model)
-    S_np = S_tr.cpu().numpy()
     for K in range(wl.M):
         mu_o, sd_o = mlp.standardize(S_np[:, K])
         np.testing.assert_allclose(mu[K], mu_o, rtol=1e-13, atol=1e-15 * np.abs(mu_o).max())
         np.testing.assert_allclose(sd[K], sd_o, rtol=1e-13, atol=1e-15 * np.abs(mu_o).max())
-    X = np.zeros((wl.M, ntr, 4), dtype=np.float32)
+    # the oracle's own trajectory from the seeded initial weights: its FP64
+    # gradients on the same minibatch (all 32 pairs, the oracle's targets),
+    # five Adam steps; the GPU takes five FP32 steps.  Compared on the
+    # components whose gradient stays above 1e-2 of the patch maximum at
+    # every step (there the FP32 gradient, within 1e-4 of the maximum, moves
+    # the normalised update by at most ~1e-2 of lr per step).
+    X = np.zeros((wl.M, ntr, 4))
     for K in range(wl.M):
         X[K, :, :nl[K]] = xi_tr[:, lv[K, :nl[K]]]
-    T = np.ascontiguousarray(((S_np.transpose(1, 0, 2) - mu[:, None, :]) / sd[:, None, :]).astype(np.float32))
-    xb, tb = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    X = X.astype(np.float32).astype(np.float64)
     lr = 1e-3
-    m1 = np.zeros((wl.M, mlp.nparams(4)))
-    m2 = np.zeros_like(m1)
+    p = init.astype(np.float64).copy()
+    m1 = np.zeros_like(p)
+    m2 = np.zeros_like(p)
+    well = np.ones(p.shape, dtype=bool)
     for t in range(1, 6):
-        before = sm.mlp_params(model).cpu().numpy().astype(np.float64)
-        g, _ = sm.mlp_grad(model, xb, tb)
-        g = g.cpu().numpy().astype(np.float64)
-        sm.mlp_train(model, 1, lr)
-        after = sm.mlp_params(model).cpu().numpy().astype(np.float64)
-        expect = np.empty_like(after)
         for K in range(wl.M):
-            expect[K], m1[K], m2[K] = mlp.adam_step(before[K], g[K], m1[K], m2[K], t, lr)
-        ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
-        # FP32 bias corrections 1 - beta^t lose ~3e-5 relative to cancellation
-        bad = np.abs(after - expect) > 2 * ulp + 1e-4 * np.abs(expect - before)
-        assert not bad.any(), (t, np.argwhere(bad)[:5])
-        assert np.abs(after - before).max() > 0.5 * lr
+            mu_o, sd_o = mlp.standardize(S_np[:, K])
+            T = ((S_np[:, K] - mu_o) / sd_o).astype(np.float32).astype(np.float64)
+            _, g = mlp.grad(p[K], X[K], T, 4)
+            well[K] &= np.abs(g) >= 1e-2 * np.abs(g).max()
+            p[K], m1[K], m2[K] = mlp.adam_step(p[K], g, m1[K], m2[K], t, lr)
+    sm.mlp_train(model, 5, lr)
+    got = sm.mlp_params(model).cpu().numpy().astype(np.float64)
+    d = np.abs(got - p)
+    say(f"5 Adam steps: {well.sum()} well-conditioned components, max diff {d[well].max() / lr:.2e} lr "
+        f"(all components {d.max() / lr:.2e} lr)")
+    assert well.sum() > 0.25 * well.size
+    assert d[well].max() <= 2e-2 * lr
+    assert np.abs(got - init).max() > 4 * lr
     say("standardisation and 5 Adam steps agree with the oracle")
 
 

@@ -43,3 +43,29 @@ def test_local_vars_mesh32_fits_four():
     lv, nl = sm.local_vars_bumps(wl.nc, wl.nc, wl.m, sm.bump_family(wl))
     assert nl.max() <= 4 and nl.min() >= 1
     np.testing.assert_array_equal(lv, _definition(wl, 4))
+
+
+def test_local_vars_features_against_definition():
+    # the channels medium: a patch's local variables are the features that
+    # own a fine element of it; more than kmax -> the always-plain sentinel
+    from oracle import mlp
+    from paper_1607_00693_amd import stomsfem as sm
+    ncx, ncy, m, nfeat = 5, 3, 4, 9
+    rng = np.random.default_rng(77)
+    fmap = rng.integers(-1, nfeat, size=(ncy * m, ncx * m)).astype(np.int32)
+    fmap[:m, :m] = -1                       # a background-only patch
+    fmap[m:2 * m, m:2 * m] = 3              # a patch owned by one feature
+    lv, nl = sm.local_vars_features(ncx, ncy, m, fmap, nfeat)
+    want = mlp.local_features(fmap, ncx, ncy, m)
+    for K in range(ncx * ncy):
+        assert nl[K] == len(want[K]), K
+        if len(want[K]) > 4:
+            assert lv[K].tolist() == [-2, -1, -1, -1], K
+        else:
+            assert lv[K].tolist() == want[K] + [-1] * (4 - len(want[K])), K
+    assert nl[0] == 0 and lv[ncx + 1].tolist() == [3, -1, -1, -1]
+    assert (nl > 4).any() and (nl <= 4).any()
+    bad = fmap.copy()
+    bad[0, 0] = nfeat
+    with pytest.raises(RuntimeError):
+        sm.local_vars_features(ncx, ncy, m, bad, nfeat)

@@ -139,3 +139,73 @@ def test_gate_rejects_non_finite_predictions():
     ok, _, resid, unc = mlp.gate(Y, mu, sd, np.zeros((4, 4)), 4, 1e30)
     assert ok.tolist() == [True, False, False, False]
     assert np.isnan(resid[1:]).all() and np.isnan(unc[1:]).all()
+
+
+def test_gate_output_scale_is_a_pure_rescaling(orc):
+    # the network predicts S / c: the gate multiplies both heads by c, so the
+    # accepted S is the exact one and the two signals do not depend on c
+    from oracle import mlp
+    a = W.lognormal_field((4, 8, 8), 1.0, 16)
+    S = np.stack([orc.cell_S(b)[0] for b in a])
+    c = np.array([1.0, 3.5, 250.0, 1e4])
+    mu, sd = (S / c[:, None]).mean(0), np.maximum((S / c[:, None]).std(0), 1e-3)
+    T = (S / c[:, None] - mu) / sd
+    ok, Sp, resid, unc = mlp.gate(np.concatenate([T, T], 1), mu, sd, np.zeros((4, 4)), 4, 1e-3, scale=c)
+    assert ok.all()
+    np.testing.assert_allclose(Sp, S, rtol=0, atol=1e-12 * np.abs(S).max())
+    Y = np.concatenate([T, T + W.uniform_array(T.shape, -1e-3, 1e-3, 17)], 1)
+    r1 = mlp.gate(Y, mu, sd, np.zeros((4, 4)), 4, 1e-3, scale=c)
+    r0 = mlp.gate(Y, mu, sd, np.zeros((4, 4)), 4, 1e-3)
+    np.testing.assert_allclose(r1[2], r0[2], rtol=1e-13)
+    np.testing.assert_allclose(r1[3], r0[3], rtol=1e-13)
+    np.testing.assert_allclose(r1[1], c[:, None] * r0[1], rtol=1e-13, atol=0)
+
+
+def test_ring_mean_hand_counted():
+    from oracle import mlp
+    blk = np.ones((3, 3))
+    blk[1, 1] = 100.0                       # the only interior element
+    assert mlp.ring_mean(blk) == 1.0
+    assert mlp.ring_mean(np.array([[7.0]])) == 7.0
+    m, th = 8, 1234.5
+    blk = np.ones((m, m))
+    blk[3, :] = th                          # a channel across the patch: 2 of 4m-4 ring elements
+    assert abs(mlp.ring_mean(blk) - (1 + 2 * (th - 1) / (4 * m - 4))) < 1e-12 * th
+    blk = np.ones((m, m))
+    blk[0, :] = th                          # along an edge: m of 4m-4
+    assert abs(mlp.ring_mean(blk) - (1 + m * (th - 1) / (4 * m - 4))) < 1e-12 * th
+
+
+def test_features_input_recovers_the_conductivity(orc):
+    # theta = 10^(d (u + 1) / 2) with u the network input of the variable,
+    # against the oracle's coefficient of a single square inclusion
+    from oracle import mlp
+    xs = np.array([[-3.0], [-0.4], [0.0], [1.7], [3.0]])
+    a = orc.coef_features(xs, 8, [2], [0.5], [0.5], [0.2], decades=4.0)
+    th = a[:, 4, 4]
+    u = mlp.features_input(xs[:, 0])
+    np.testing.assert_allclose(10.0 ** (4.0 * (u + 1.0) / 2.0), th, rtol=1e-13)
+    assert (np.abs(u) < 1).all() and u[2] == 0.0
+
+
+def test_ring_mean_follows_max_entry_of_S_across_decades(orc):
+    # the premise of the output scale: for a channel across the patch, an
+    # edge channel and an interior inclusion, max|S| / ring mean stays within
+    # a factor 3 while the conductivity runs over four decades
+    from oracle import mlp
+    m = 8
+    shapes = []
+    b = np.zeros((m, m), bool); b[3, :] = True; shapes.append(b)
+    b = np.zeros((m, m), bool); b[0, 2:] = True; shapes.append(b)
+    b = np.zeros((m, m), bool); b[2:6, 2:6] = True; shapes.append(b)
+    spread = []
+    for mask in shapes:
+        ratios, mx = [], []
+        for th in 10.0 ** np.linspace(0.2, 3.8, 7):
+            blk = np.where(mask, th, 1.0)
+            S, _ = orc.cell_S(blk)
+            mx.append(np.abs(S).max())
+            ratios.append(mx[-1] / mlp.ring_mean(blk))
+        assert max(ratios) / min(ratios) < 3.0
+        spread.append(max(mx) / min(mx))
+    assert spread[0] > 50 and spread[1] > 50 and spread[2] < 10   # channels grow, the inclusion saturates
