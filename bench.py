@@ -269,6 +269,136 @@ def measure_channels(log, reps=3):
     return out
 
 
+def measure_channels_surrogate(log, plain=None, ntrain=2048, schedule=((8000, 2e-3), (8000, 5e-4), (8000, 1e-4)),
+                               reps=3):
+    """Learned surrogate on the channels-and-inclusions workload (64 x 64
+    coarse mesh, 32 batches of 256 samples, H/h per batch from {8, 16, 32}):
+    one network per patch and per H/h, trained on ntrain plain solves of that
+    medium (FP64 coefficients); then, per batch, the gated BF16 surrogate with
+    the plain fallback (coefficient blocks of the listed pairs regenerated from
+    the feature map) followed by the FP64 coarse solve and the QoI.  Reports
+    the per-batch latency (submit to QoI ready, p50/p99 over reps x 32
+    batches, also per H/h), acceptance, and the coarse-solution error of every
+    sample against the plain FP64 path; plain = the per-H/h latencies of the
+    plain plan when given."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.CHANNELS64
+    dev = "cuda"
+    nc = wl.nc
+    kind, x0, y0, size = W.channel_geometry(wl)
+    g = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (kind, x0, y0, size)]
+    ms = W.batch_m(wl)
+    xi_all = torch.from_numpy(W.normal_xi(wl.nbatch * wl.batch, wl.nxi, wl.xi_seed)).to(dev)
+    models, fmaps, train = {}, {}, {}
+    for m in sorted(set(int(v) for v in ms)):
+        fmap = sm.feature_map(nc * m, *g)
+        fmaps[m] = fmap
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xi_tr = torch.from_numpy(W.normal_xi(ntrain, wl.nxi, 2005 + m)).to(dev)
+        S_tr = torch.empty((ntrain, wl.M, 10), dtype=torch.float64, device=dev)
+        for c0 in range(0, ntrain, 256):
+            a = sm.coef_features(fmap, wl.nxi, xi_tr[c0:c0 + 256], wl.decades)
+            sm.upscale(a, nc, nc, m, S=S_tr[c0:c0 + 256])
+            del a
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        mdl = sm.mlp_create_features(nc, m, fmap, wl.nxi, wl.decades, W.mlp_init(wl.M, 4005 + m), 3.0)
+        sm.mlp_set_data(mdl, xi_tr, S_tr)
+        perm = torch.from_numpy(W.permutation(ntrain, 5005 + m)).to(dev)
+        t0 = time.perf_counter()
+        for steps, lr in schedule:
+            sm.mlp_train(mdl, steps, lr, perm)
+        torch.cuda.synchronize()
+        train[m] = {"training_data_s": t_data, "train_s": time.perf_counter() - t0}
+        models[m] = mdl
+        del S_tr, xi_tr
+        log(f"channels surrogate: H/h={m} model trained ({train[m]})")
+    nU = (nc - 1) ** 2
+    stream = torch.cuda.current_stream()
+    bufs = []
+    for b in range(wl.nbatch):
+        bufs.append(dict(S=torch.empty((wl.batch, wl.M, 10), dtype=torch.float64, device=dev),
+                         st=torch.empty((wl.batch, wl.M), dtype=torch.int32, device=dev),
+                         U=torch.empty((wl.batch, nU), dtype=torch.float64, device=dev),
+                         qm=torch.empty(nU, dtype=torch.float64, device=dev),
+                         qv=torch.empty(nU, dtype=torch.float64, device=dev)))
+
+    def run(b):
+        xi = xi_all[b * wl.batch:(b + 1) * wl.batch]
+        o = bufs[b]
+        sm.upscale_surrogate(models[int(ms[b])], xi, 1e-3, sm.PREC_BF16, S=o["S"], status=o["st"])
+        sm.coarse_solve(o["S"], nc, nc, U=o["U"], qoi_mean=o["qm"], qoi_var=o["qv"])
+
+    for b in range(wl.nbatch):
+        run(b)
+    torch.cuda.synchronize()
+    lat = {int(m): [] for m in models}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for r in range(reps):
+        for b in range(wl.nbatch):
+            ev0.record(stream)
+            run(b)
+            ev1.record(stream)
+            ev1.synchronize()
+            lat[int(ms[b])].append(ev0.elapsed_time(ev1))
+        log(f"channels surrogate: latency rep {r} done")
+    # accuracy of every sample against the plain FP64 path (not timed)
+    acc_n = fb_n = au_n = 0
+    u_err = 0.0
+    u_err_m = {int(m): 0.0 for m in models}
+    for b in range(wl.nbatch):
+        m = int(ms[b])
+        xi = xi_all[b * wl.batch:(b + 1) * wl.batch]
+        a = sm.coef_features(fmaps[m], wl.nxi, xi, wl.decades)
+        S_p = sm.upscale(a, nc, nc, m)
+        del a
+        U_p, _, _ = sm.coarse_solve(S_p, nc, nc)
+        o = bufs[b]
+        e = float((torch.linalg.norm(o["U"] - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())
+        u_err = max(u_err, e)
+        u_err_m[m] = max(u_err_m[m], e)
+        st = o["st"]
+        acc_n += int((st == 0).sum())
+        fb_n += int((st == 1).sum())
+        au_n += int((st == 2).sum())
+        del S_p, U_p
+    for mdl in models.values():
+        mdl.free()
+    allv = np.concatenate([np.asarray(v) for v in lat.values()])
+    pairs = wl.nbatch * wl.batch * wl.M
+    tot = acc_n + fb_n + au_n
+    serial_ms = float(sum(np.median(v) * len(v) / reps for v in lat.values()))
+    out = {
+        "workload": f"64x64 coarse, {wl.nbatch} batches x {wl.batch} samples, H/h per batch from {{8,16,32}}, "
+                    f"40 channels + 40 squares, xi~N(0,1)^80; one network per patch and H/h (k<=4 -> 64x3 -> 2x10, "
+                    f"GELU), {ntrain} training samples, {sum(s for s, _ in schedule)} Adam steps; per batch: gated "
+                    f"BF16 surrogate (tau=1e-3, box [-3,3]) + plain fallback + FP64 coarse solve + QoI",
+        "training": {str(m): v for m, v in train.items()},
+        "batch_latency_ms": {"p50": float(np.percentile(allv, 50)), "p99": float(np.percentile(allv, 99)),
+                             "samples": int(allv.size)},
+        "batch_latency_ms_by_m": {str(m): {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))}
+                                  for m, v in sorted(lat.items())},
+        "serial_sum_ms": serial_ms,
+        "pairs_per_s": pairs / (serial_ms * 1e-3),
+        "accepted": acc_n / tot, "fallback": fb_n / tot, "audited": au_n / tot,
+        "max_coarse_rel_err": u_err,
+        "max_coarse_rel_err_by_m": {str(m): v for m, v in sorted(u_err_m.items())},
+    }
+    if plain:
+        pm = plain["batch_latency_ms_by_m"]
+        out["p50_ratio_plain_over_surrogate_by_m"] = {
+            k: pm[k]["p50"] / v["p50"] for k, v in out["batch_latency_ms_by_m"].items() if k in pm}
+        out["serial_ratio_plain_over_surrogate"] = plain["serial_sum_ms"] / serial_ms
+    log(f"channels surrogate: {out}")
+    return out
+
+
 def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((8000, 2e-3), (8000, 5e-4),
                                                                            (8000, 1e-4))):
     """Learned surrogate on the benchmark mesh: one MLP per patch trained on
@@ -914,7 +1044,7 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, channels, oversampling, collocation, two_level, gauss); "
+                         "mixed_bench, mesh8, channels, channels_surrogate, oversampling, collocation, two_level, gauss); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters in a profile)")
@@ -1084,9 +1214,13 @@ def main():
             lg("reduced basis, interpolation and learned surrogate at the 8x8 mesh")
             acc.update(measure_accelerations(lg))
         out["accelerations"] = acc
+        chan = None
         if want("channels"):
             lg("channels-and-inclusions workload through a graph plan")
-            out["channels64_plan"] = measure_channels(lg)
+            chan = out["channels64_plan"] = measure_channels(lg)
+        if want("channels_surrogate"):
+            lg("channels-and-inclusions workload with the learned surrogate")
+            out["channels64_surrogate"] = measure_channels_surrogate(lg, chan)
         if want("oversampling"):
             lg("oversampled Petrov-Galerkin upscaling at the 8x8 mesh")
             out["oversampled_petrov_galerkin"] = measure_oversampling(lg)

@@ -353,6 +353,365 @@ __global__ __launch_bounds__(TH) void coarse_solve_kernel(CoarseArgs args) {
   }
 }
 
+// Blocked forward pass for the symmetric system with 32 < B <= 64 (the
+// pivot-per-barrier kernel above is bound by the latency of its per-pivot
+// phase, not by arithmetic).  Panels of CB_NB pivots, 256 threads, one
+// barrier per panel, software-pipelined one panel deep:
+//   wavefront 0 applies the rank-CB_NB update of panel P-1 to the columns of
+//      panel P, then factors panel P: every lane factors the CB_NB x CB_NB
+//      diagonal block (broadcast LDS reads, no cross-lane traffic) and
+//      eliminates its two rows j0 + lane and j0 + 64 + lane with it; l, the
+//      unscaled entries of the rows below the panel, the block's l, 1/d and
+//      z = D^{-1} y go to LDS (double-buffered), and it does the forward
+//      substitution of the rhs.  It issues no global memory operation;
+//   wavefronts 1-2 apply the update of panel P-1 to the rest of the
+//      trailing triangle (columns past panel P), one 4 x 4 register tile per
+//      lane, two 16-byte LDS reads per factor and pivot; wavefront 2 also
+//      keeps the ring of element rows and the rhs of new rows;
+//   wavefront 3 writes panel P-1's columns of L (one contiguous block) and z,
+//      clears the slots of panel P-1's rows and writes into them the five
+//      nonzero entries of each row first touched by panel P+1.
+// Each entry receives the updates of its pivots in pivot order, each as
+// w - (a_ip / d_p) a_kp.  The band window keeps row r in slot r mod
+// (B + 2 NB) as [A_rr, A_r,r-1, ..., A_r,r-B]; element rows of S go through
+// an LDS ring of three.  Accesses of masked-off lanes go to a junk slot
+// instead of branching.  About 76 KB of LDS (gfx950 gives a workgroup up to
+// 160 KB).
+constexpr int CB_TH = 256;
+constexpr int CB_NB = 8;
+constexpr int CB_BMAX = 64;
+constexpr int CB_NE = (CB_BMAX * 10 + 63) / 64;  // element-row prefetch per lane of wavefront 2
+
+size_t coarse_blocked_lds_bytes(int ncx) {
+  const int WN = ncx + 2 * CB_NB;
+  return sizeof(double) * ((size_t)WN * (ncx + 1) + (size_t)WN + 3 * (size_t)ncx * 10);
+}
+
+__global__ __launch_bounds__(CB_TH) void coarse_blocked_kernel(CoarseArgs args) {
+  constexpr int NB = CB_NB;
+  extern __shared__ double smem[];
+  const int ncx = args.ncx, ncy = args.ncy;
+  const int nix = ncx - 1, nU = nix * (ncy - 1), B = ncx, WN = B + 2 * NB, BW = B + 1;
+  double* Wb = smem;         // WN x BW: Wb[slot(r) BW + (r - c)] = A[r][c]
+  double* F = Wb + WN * BW;  // WN: rhs, row r in slot(r)
+  double* Ec = F + WN;       // 3 x ncx x 10: element row e in slot e % 3
+  // per panel (buffer P & 1): Lp[pp][io] = l_{j0+NB+io, j0+pp} and Ap the
+  // unscaled entry, Lq[pp][i] = l_{j0+i, j0+pp} (i > pp), 1/d_p, z_p
+  __shared__ __align__(16) double Lp[2][NB][CB_BMAX];
+  __shared__ __align__(16) double Ap[2][NB][CB_BMAX];
+  __shared__ double Lq[2][NB][NB];
+  __shared__ double dq[2][NB], zq[2][NB];
+  __shared__ double Bk[NB][NB];  // the panel block after the previous panel's update (wavefront 0)
+  __shared__ double junk[64];    // target of the masked-off lanes' accesses
+  __shared__ double zero1;       // 0.0: the source of absent terms
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t s = blockIdx.x;
+  if (s >= args.nsamples) return;
+  const double* Ss = args.S + s * (int64_t)ncx * ncy * 10;
+  double* Us = args.U + s * (int64_t)nU;
+  double* Lc = args.work + s * ((int64_t)nU * BW + 1);  // column j: [1/d_j, l_{j+1,j}, ..., l_{j+B,j}]
+  const double H = 1.0 / ncx;
+  double* jk = &junk[lane];
+  if (tid == 0) {
+    Lc[(int64_t)nU * BW] = 0.0;
+    bad = 0;
+    zero1 = 0.0;
+  }
+  // x - WN while x >= WN, for 0 <= x < 3 WN
+  auto wrapn = [&](int x) {
+    x = x >= WN ? x - WN : x;
+    return x >= WN ? x - WN : x;
+  };
+  // this lane's 4 x 4 tile (wavefronts 1-2) of the triangle of rows and
+  // columns j0 + NB .. j0 + B - 1 (offsets 4 tr.., 4 tc.. from j0 + NB);
+  // tmask bit 4a+b: entry (4tr+a, 4tc+b) lies in it
+  const int TB = B - NB, nT = (TB + 3) / 4;
+  int tr = 0;
+  const int tix = lane + 64 * (wave - 1);
+  while ((tr + 1) * (tr + 2) / 2 <= tix) ++tr;
+  const int tc = tix - tr * (tr + 1) / 2;
+  const bool tile = (wave == 1 || wave == 2) && tr < nT;
+  unsigned tmask = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      if (4 * tr + a < TB && 4 * tc + b <= 4 * tr + a) tmask |= 1u << (4 * a + b);
+
+  auto node_load = [&](int r) -> double {
+    if (r >= nU) return 0.0;
+    const int px = r % nix + 1, py = r / nix + 1;
+    if (!args.load) return H * H;  // four elements, int_K p^l = H^2/4 each
+    const double* L = args.load;
+    return (L[((py - 1) * ncx + (px - 1)) * 4 + 2] + L[((py - 1) * ncx + px) * 4 + 3]) +
+           (L[(py * ncx + (px - 1)) * 4 + 1] + L[(py * ncx + px) * 4 + 0]);
+  };
+  // nonzero entry e (0..4) of row r: offset t in {0, 1, nix-1, nix, nix+1}
+  // (diagonal, W, SE, S, SW couplings) and its value, the sum of up to four
+  // element-matrix entries around the node as in coarse_solve_kernel (absent
+  // terms read an LDS zero, so every lane takes the same path)
+  auto nonzero = [&](int r, int e, int& t, double& v) {
+    const int ix = r % nix, iy = r / nix, px = ix + 1, py = iy + 1;
+    const double* eS = Ec + ((py - 1) % 3) * ncx * 10;
+    const double* eN = Ec + (py % 3) * ncx * 10;
+    const double* sSW = eS + (px - 1) * 10;
+    const double* sSE = eS + px * 10;
+    const double* sNW = eN + (px - 1) * 10;
+    const double* sNE = eN + px * 10;
+    const double* z = &zero1;
+    // packed indices: (0,0)=0 (0,1)=1 (0,2)=2 (0,3)=3 (1,1)=4 (1,2)=5 (1,3)=6 (2,2)=7 (2,3)=8 (3,3)=9
+    const double *pa = z, *pb = z, *pc = z, *pd = z;
+    t = e == 0 ? 0 : e == 1 ? 1 : e == 2 ? nix - 1 : e == 3 ? nix : nix + 1;
+    if (e == 0) {
+      pa = sSW + 7;  // (2,2)
+      pb = sSE + 9;  // (3,3)
+      pc = sNW + 4;  // (1,1)
+      pd = sNE + 0;  // (0,0)
+    }
+    const bool c1 = e == 1 && ix >= 1, c3 = e == 3 && iy >= 1;
+    pa = c1 ? sSW + 8 : c3 ? sSW + 5 : pa;  // (3,2) / (1,2)
+    pb = c1 ? sNW + 1 : c3 ? sSE + 3 : pb;  // (0,1) / (0,3)
+    pa = (e == 2 && iy >= 1 && ix <= nix - 2) ? sSE + 6 : pa;  // (1,3)
+    pa = (e == 4 && iy >= 1 && ix >= 1) ? sSW + 2 : pa;        // (0,2)
+    v = (*pa + *pb) + (*pc + *pd);
+  };
+  double epre[CB_NE];
+  auto erow_fetch = [&](int e) {  // wavefront 2
+#pragma unroll
+    for (int k = 0; k < CB_NE; ++k) {
+      const int t = lane + 64 * k;
+      epre[k] = (e < ncy && t < ncx * 10) ? Ss[(int64_t)e * ncx * 10 + t] : 0.0;
+    }
+  };
+  auto erow_store = [&](int e) {
+#pragma unroll
+    for (int k = 0; k < CB_NE; ++k) {
+      const int t = lane + 64 * k;
+      if (e < ncy && t < ncx * 10) Ec[(e % 3) * ncx * 10 + t] = epre[k];
+    }
+  };
+
+  // prologue: element rows 0..2, the cleared window, rows 0 .. NB+B-1 and
+  // their rhs
+  for (int e = 0; e < 3 && e < ncy; ++e)
+    for (int t = tid; t < ncx * 10; t += CB_TH) Ec[e * ncx * 10 + t] = Ss[(int64_t)e * ncx * 10 + t];
+  for (int i = tid; i < WN * BW; i += CB_TH) Wb[i] = 0.0;
+  int eld = ncy - 1 < 2 ? ncy - 1 : 2;  // highest element row in the ring
+  if (wave == 2) erow_fetch(eld + 1);
+  __syncthreads();
+  for (int i = tid; i < (NB + B) * 5; i += CB_TH) {
+    const int r = i / 5, e = i - 5 * r;
+    int t;
+    double v;
+    if (r < nU) {
+      nonzero(r, e, t, v);
+      if (r - t >= 0) Wb[r * BW + t] = v;
+    }
+  }
+  for (int r = tid; r < NB + B; r += CB_TH)
+    if (r < nU) F[r] = node_load(r);
+  double fnext = (wave == 2 && lane < NB) ? node_load(NB + B + lane) : 0.0;
+  __syncthreads();
+
+  int sj = 0;  // slot of row j0
+  for (int P = 0;; ++P) {
+    const int j0 = P * NB;
+    if (j0 - NB >= nU) break;
+    const int cb = P & 1, pb = cb ^ 1;  // buffers of panels P and P-1
+    if (wave == 0 && j0 < nU) {
+      // rows R1 = j0 + lane and R2 = j0 + 64 + lane; entry (R, j0 + k) in x[k]
+      const bool h1 = lane < NB + B && j0 + lane < nU;
+      const bool h2 = 64 + lane < NB + B && j0 + 64 + lane < nU;
+      const int s1 = wrapn(sj + lane), s2 = wrapn(sj + (64 + lane < NB + B ? 64 + lane : 0));
+      double x1[NB], x2[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const bool v1 = h1 && lane >= k && lane - k <= B, v2 = h2 && 64 + lane - k <= B;
+        const double y1 = *(v1 ? &Wb[s1 * BW + (lane - k)] : jk);
+        const double y2 = *(v2 ? &Wb[s2 * BW + (64 + lane - k)] : jk);
+        x1[k] = v1 ? y1 : 0.0;
+        x2[k] = v2 ? y2 : 0.0;
+      }
+      const double g1 = *(h1 ? &F[s1] : jk), g2 = *(h2 ? &F[s2] : jk);
+      double f1 = h1 ? g1 : 0.0, f2 = h2 ? g2 : 0.0;
+      if (P >= 1) {
+        // the update of panel P-1 on these columns: row j0 + lane is its
+        // row offset io = lane (rows j0 + 64 + lane are past its reach)
+        const bool in = lane < B;
+#pragma unroll
+        for (int pp = 0; pp < NB; ++pp) {
+          const double lv = *(in ? &Lp[pb][pp][lane] : jk);
+          const double l = in ? lv : 0.0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) x1[k] -= l * Ap[pb][pp][k];
+        }
+      }
+      // the diagonal block (rows and columns j0 .. j0 + NB - 1) and the rhs
+      // of its rows in every lane: lanes 0 .. NB-1 hold the block rows, the
+      // other lanes read them back (same addresses: broadcast); rows past nU
+      // are an identity block so that no pivot is zero there
+#pragma unroll
+      for (int k = 0; k < NB; ++k) *(lane < NB && k <= lane ? &Bk[lane][k] : jk) = x1[k];
+      double blk[NB][NB], fb[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const bool in = j0 + i < nU;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) blk[i][k] = in ? Bk[i][k] : (i == k ? 1.0 : 0.0);
+        const double v = *(in ? &F[wrapn(sj + i)] : jk);
+        fb[i] = in ? v : 0.0;
+      }
+      // every lane factors the block (right-looking, pivot order) and
+      // carries its own two rows along: entry (R, j0 + k) receives the
+      // update of pivot p as x - (x_p / d_p) A_{j0+k, p}, in pivot order
+      double dinv[NB], yv[NB], l1s[NB], l2s[NB];
+#pragma unroll
+      for (int pp = 0; pp < NB; ++pp) {
+        const double d = blk[pp][pp];
+        // 1/d: hardware reciprocal and two Newton steps (within an ulp or
+        // two; the pivot chain runs through it)
+        double inv = __builtin_amdgcn_rcp(d);
+        inv = fma(fma(-d, inv, 1.0), inv, inv);
+        inv = fma(fma(-d, inv, 1.0), inv, inv);
+        dinv[pp] = inv;
+        if (j0 + pp < nU && !(d > 0.0)) bad = 1;
+        const double y = fb[pp];
+        yv[pp] = y;
+#pragma unroll
+        for (int i = pp + 1; i < NB; ++i) {
+          const double li = blk[i][pp] * inv;
+          fb[i] -= li * y;
+#pragma unroll
+          for (int k = pp + 1; k <= i; ++k) blk[i][k] -= li * blk[k][pp];
+        }
+        const bool b1 = h1 && lane > pp && lane - pp <= B, b2 = h2 && 64 + lane - pp <= B;
+        const double l1 = b1 ? x1[pp] * inv : 0.0, l2 = b2 ? x2[pp] * inv : 0.0;
+        f1 -= l1 * y;
+        f2 -= l2 * y;
+#pragma unroll
+        for (int k = pp + 1; k < NB; ++k) {
+          x1[k] -= l1 * blk[k][pp];
+          x2[k] -= l2 * blk[k][pp];
+        }
+        l1s[pp] = l1;
+        l2s[pp] = l2;
+      }
+      // for the next step: the panel columns of the rows below the panel
+      // (their factor is zero where the entry is outside the band, and so is
+      // the entry), the block's factors, 1/d and z
+#pragma unroll
+      for (int pp = 0; pp < NB; ++pp) {
+        *(lane >= NB ? &Lp[cb][pp][lane - NB] : jk) = l1s[pp];
+        *(lane >= NB ? &Ap[cb][pp][lane - NB] : jk) = l1s[pp] != 0.0 ? x1[pp] : 0.0;
+        if (64 + lane - NB < B) {
+          Lp[cb][pp][64 + lane - NB] = l2s[pp];
+          Ap[cb][pp][64 + lane - NB] = l2s[pp] != 0.0 ? x2[pp] : 0.0;
+        }
+        *(lane < NB && lane > pp ? &Lq[cb][pp][lane] : jk) = l1s[pp];
+      }
+      if (lane < NB) {
+        double di = dinv[0], z = yv[0] * dinv[0];
+#pragma unroll
+        for (int pp = 1; pp < NB; ++pp) {
+          di = lane == pp ? dinv[pp] : di;
+          z = lane == pp ? yv[pp] * dinv[pp] : z;
+        }
+        dq[cb][lane] = di;
+        zq[cb][lane] = z;  // z_p = y_p / d_p, overwritten by x_p in the backward pass
+      }
+      if (h1 && lane >= NB) F[s1] = f1;
+      if (h2) F[s2] = f2;
+    }
+    if (tile && P >= 1) {
+      // update of panel P-1 on rows / columns j0 + NB + 4 tr.. / 4 tc..:
+      // offsets NB + 4 tr.. in its buffers
+      double w[4][4];
+      double* pa[4][4];
+      unsigned vm = tmask;  // entries inside the triangle and the system
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (j0 + NB + 4 * tr + a >= nU) vm &= ~(15u << (4 * a));
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int sa = wrapn(sj + NB + 4 * tr + a) * BW + 4 * (tr - tc) + a;  // slot(i) BW + (i - k) for b = 0
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pa[a][b] = (vm >> (4 * a + b) & 1u) ? &Wb[sa - b] : jk;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) w[a][b] = *pa[a][b];
+#pragma unroll
+      for (int pp = 0; pp < NB; ++pp) {
+        const double2 la = *reinterpret_cast<const double2*>(&Lp[pb][pp][NB + 4 * tr]);
+        const double2 lb = *reinterpret_cast<const double2*>(&Lp[pb][pp][NB + 4 * tr + 2]);
+        const double2 aa = *reinterpret_cast<const double2*>(&Ap[pb][pp][NB + 4 * tc]);
+        const double2 ab = *reinterpret_cast<const double2*>(&Ap[pb][pp][NB + 4 * tc + 2]);
+        const double l[4] = {la.x, la.y, lb.x, lb.y}, av[4] = {aa.x, aa.y, ab.x, ab.y};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) w[a][b] -= l[a] * av[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) *pa[a][b] = w[a][b];
+    }
+    const int rb = j0 + NB + B;  // rows first touched by panel P+1
+    const int so = wrapn(sj + WN - NB);  // slot of row j0 - NB: panel P-1's rows
+    if (wave == 2) {
+      // rhs of the new rows (prefetched a step ahead); element ring: the
+      // rows assembled in the next step need element rows up to
+      // iy(last) + 1, and the slot written here holds a row no longer read
+      if (lane < NB && rb + lane < nU) F[wrapn(so + lane)] = fnext;
+      fnext = lane < NB ? node_load(rb + lane + NB) : 0.0;
+      const int rl = j0 + 3 * NB + B - 1 < nU - 1 ? j0 + 3 * NB + B - 1 : nU - 1;
+      if (rl / nix + 1 > eld && eld + 1 < ncy) {
+        erow_store(eld + 1);
+        ++eld;
+        erow_fetch(eld + 1);
+      }
+    } else if (wave == 3) {
+      if (P >= 1) {
+        // columns j0 - NB .. j0 - 1 of L (a contiguous block of the
+        // workspace) and their z
+        const int jp = j0 - NB, ncol = nU - jp < NB ? nU - jp : NB;
+        double* Lb = Lc + (int64_t)jp * BW;
+#pragma unroll
+        for (int pp = 0; pp < NB; ++pp) {
+          if (pp < ncol) {
+            for (int t = lane; t < BW; t += 64) {
+              const double* src =
+                  t == 0 ? &dq[pb][pp] : (t < NB - pp ? &Lq[pb][pp][pp + t] : &Lp[pb][pp][t - (NB - pp)]);
+              Lb[pp * BW + t] = *src;
+            }
+          }
+        }
+        if (lane < ncol) Us[jp + lane] = zq[pb][lane];
+      }
+      // panel P-1's row slots: cleared, then the nonzeros of the rows first
+      // touched by panel P+1 (LDS operations of one wavefront complete in
+      // order)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double* row = Wb + wrapn(so + q) * BW;
+        for (int t = lane; t < BW; t += 64) row[t] = 0.0;
+      }
+      if (lane < 5 * NB) {
+        const int q = lane / 5, r = rb + q;
+        int t = 0;
+        double v = 0.0;
+        if (r < nU) nonzero(r, lane - 5 * q, t, v);
+        *(r < nU && r - t >= 0 ? &Wb[wrapn(so + q) * BW + t] : jk) = v;
+      }
+    }
+    sj = wrapn(sj + NB);
+    COARSE_SYNC();
+  }
+  if (tid == 0 && args.status) args.status[s] = bad ? STOMSFEM_ENOTSPD : STOMSFEM_OK;
+}
+
 // Backward substitution L^T x = z for the samples of one forward launch: one
 // wavefront per sample (workgroup slice blockIdx.x of the workspace).
 template <bool FAR>
@@ -468,7 +827,10 @@ static int64_t qoi_chunk(int64_t N) {
   return cs < 64 ? 64 : cs;
 }
 
+static bool use_blocked(int ncx, bool pg) { return !pg && ncx > COARSE_SMALL_B && ncx <= CB_BMAX; }
+
 size_t coarse_lds_bytes(int ncx, bool pg) {
+  if (use_blocked(ncx, pg)) return coarse_blocked_lds_bytes(ncx);
   const int WN = ncx + 1;
   return sizeof(double) * ((size_t)WN * WN + (size_t)WN + 1 + 3 * (size_t)ncx * (pg ? 16 : 10));
 }
@@ -655,6 +1017,12 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
         }
       } else if (pg) {
         hipLaunchKernelGGL((coarse_solve_kernel<4, true, COARSE_THREADS>), grid, block, lds, st, a);
+      } else if (use_blocked(ncx, pg)) {
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void*)coarse_blocked_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+            (int)coarse_blocked_lds_bytes(CB_BMAX));
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL(coarse_blocked_kernel, grid, dim3(CB_TH), lds, st, a);
       } else {
         hipLaunchKernelGGL((coarse_solve_kernel<COARSE_NQ, false, COARSE_THREADS>), grid, block, lds, st, a);
       }

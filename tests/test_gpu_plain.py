@@ -166,7 +166,8 @@ def test_empty_and_invalid_arguments(sm):
     assert rc == sm.EINVAL
 
 
-@pytest.mark.parametrize("ncx,ncy", [(2, 2), (5, 3), (3, 7), (16, 16)])
+@pytest.mark.parametrize("ncx,ncy", [(2, 2), (5, 3), (3, 7), (16, 16), (33, 33), (40, 36), (64, 64), (50, 3),
+                                     (37, 2), (66, 20)])
 def test_coarse_solve(sm, orc, ncx, ncy):
     N, m = 5, 4
     say(f"coarse solve ncx={ncx} ncy={ncy}")
