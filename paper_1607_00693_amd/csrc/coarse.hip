@@ -35,7 +35,7 @@ constexpr int COARSE_NQ = 3;  // largest NQ: B (B+1)/2 <= 3072
 constexpr int COARSE_BMAX = 72;
 constexpr int COARSE_PG_BMAX = 64;
 constexpr int COARSE_SMALL_B = 32;  // largest band served by the one-wavefront workgroup  // Petrov-Galerkin: full B x B trailing square, <= 16 entries per lane
-constexpr int COARSE_PD = 8;  // backward substitution: L entries loaded this many steps ahead
+constexpr int COARSE_PD = 32;  // backward substitution: L entries loaded this many steps ahead
 
 // Workgroup barrier that orders LDS only: a pivot step does not wait for
 // its global stores (retired L columns, y_j) to complete.
