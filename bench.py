@@ -195,6 +195,42 @@ def measure_interpolation(wl, xi, S_plain, t_plain_ms, nn_list, log, sg_levels=(
     return out
 
 
+def measure_coarse(log, meshes=(64, 48, 33), nsamples=256, reps=10):
+    """Batched FP64 coarse solve + QoI (eq. upscaleSUF, Sec. 4.1.1) alone on
+    the coarse meshes the blocked kernel serves, at the channels workload's
+    batch size: upscaled stiffness of a seeded log-normal medium at H/h = 4
+    (the solve does not depend on H/h), HIP-event time per batch on the
+    launching stream, algorithmic FP64 flops per sample nU (B^2 + 4B) for the
+    banded LDL^T with forward substitution plus 2 nU B for the backward pass."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for nc in meshes:
+        a = torch.from_numpy(W.lognormal_field((nsamples, nc * 4, nc * 4), 1.0, 5)).cuda()
+        S = sm.upscale(a, nc, nc, 4)
+        del a
+        U, qm, qv = sm.coarse_solve(S, nc, nc)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            sm.coarse_solve(S, nc, nc, U=U, qoi_mean=qm, qoi_var=qv)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        nU, B = (nc - 1) ** 2, nc
+        flops = nU * (B * B + 4 * B) + 2 * nU * B
+        out[f"{nc}x{nc}"] = {"samples": nsamples, "ms_per_batch": ms, "samples_per_s": nsamples / (ms * 1e-3),
+                             "flops_per_sample": flops,
+                             "fp64_frac": flops * nsamples / (ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS}
+        del S, U
+    log(f"coarse solve: {out}")
+    return out
+
+
 def measure_channels(log, reps=3):
     """High-contrast channels-and-inclusions workload: 64 x 64 coarse mesh,
     32 batches of 256 samples with H/h drawn per batch from {8, 16, 32}, FP32
@@ -1060,7 +1096,8 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, channels, channels_surrogate, oversampling, collocation, two_level, gauss); "
+                         "mixed_bench, mesh8, coarse_bench, channels, channels_surrogate, oversampling, collocation, "
+                         "two_level, gauss); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters in a profile)")
@@ -1230,6 +1267,9 @@ def main():
             lg("reduced basis, interpolation and learned surrogate at the 8x8 mesh")
             acc.update(measure_accelerations(lg))
         out["accelerations"] = acc
+        if want("coarse_bench"):
+            lg("batched coarse solve at 64x64, 48x48, 33x33")
+            out["coarse_solve_bench"] = measure_coarse(lg)
         chan = None
         if want("channels"):
             lg("channels-and-inclusions workload through a graph plan")
