@@ -37,6 +37,8 @@
 // r x r solve) and rb_apply_f64_kernel (FP64 throughout, for parity checks).
 #include "rb.h"
 
+#include <type_traits>
+
 namespace stomsfem {
 
 // ---------------------------------------------------------------------------
@@ -627,56 +629,56 @@ hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Online stage
 // ---------------------------------------------------------------------------
-// r x r Cholesky of A (packed upper in v), solves with the three Fh columns,
-// S_ll' = B_ll' - Fh_l . A^{-1} Fh_l', in the arithmetic of T (FP64 for the
-// reference stage, FP32 after the FP32 matrix-core products: A is close to
-// the identity, since the modes are orthonormal in the energy of the
-// training mean).  Returns false on a non-positive pivot.
+// r x r LDL^T of A (packed upper in v), forward solves with the three Fh
+// columns, S_ll' = B_ll' - Fh_l . A^{-1} Fh_l' = B_ll' - sum_i y_l[i] y_l'[i] / d_i
+// with L y_l = Fh_l (unit L), in the arithmetic of T (FP64 for the reference
+// stage, FP32 after the FP32 matrix-core products: A is close to the
+// identity, since the modes are orthonormal in the energy of the training
+// mean).  No square roots, and one reciprocal per pivot (FP32: the hardware
+// reciprocal, within an ulp, far below the FP32 products' error).  Returns
+// false on a non-positive pivot.
+template <typename T>
+__device__ __forceinline__ T rb_recip(T d) {
+  return T(1) / d;
+}
+template <>
+__device__ __forceinline__ float rb_recip<float>(float d) {
+  return __builtin_amdgcn_rcpf(d);
+}
 template <int RMAX, typename T>
 __device__ __forceinline__ bool rb_small_solve(const T* v, int r, double S3[3][3]) {
   constexpr int NA = RMAX * (RMAX + 1) / 2;
-  T L[RMAX][RMAX];
+  T L[RMAX][RMAX];  // lower part: A, then the unit factor's l_ij (i > j)
+  T U[RMAX][RMAX];  // u_ij = l_ij d_j (i > j)
+  T dinv[RMAX];
   T X[3][RMAX];
   bool ok = true;
-#pragma unroll
-  for (int i = 0; i < RMAX; ++i)
-#pragma unroll
-    for (int j = 0; j < RMAX; ++j) L[i][j] = 0.0;
 #pragma unroll
   for (int q = 0; q < RMAX; ++q)
 #pragma unroll
     for (int qp = q; qp < RMAX; ++qp) {
-      L[qp][q] = v[q * RMAX - q * (q - 1) / 2 + (qp - q)];
+      // identity on the unused modes keeps the factorisation well defined
+      const T a = v[q * RMAX - q * (q - 1) / 2 + (qp - q)];
+      L[qp][q] = (q < r && qp < r) ? a : (q == qp ? T(1) : T(0));
     }
-  // identity on the unused modes keeps the factorisation well defined
-#pragma unroll
-  for (int q = 0; q < RMAX; ++q)
-    if (q >= r) {
-#pragma unroll
-      for (int j = 0; j < RMAX; ++j) L[q][j] = (j == q) ? T(1) : T(0);
-#pragma unroll
-      for (int i = 0; i < RMAX; ++i)
-        if (i != q) L[i][q] = T(0);
-    }
+  // Crout LDL^T: u_ij = a_ij - sum_k u_ik l_jk, d_j = a_jj - sum_k u_jk l_jk
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
     T d = L[j][j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    for (int k = 0; k < j; ++k) d -= U[j][k] * L[j][k];
     ok = ok && d > T(0);
-    const T ljj = sqrt(d);
-    L[j][j] = ljj;
-    const T inv = T(1) / ljj;
+    const T inv = rb_recip<T>(d);
+    dinv[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < RMAX; ++i) {
-      T t = L[i][j];
+      T u = L[i][j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-      L[i][j] = t * inv;
+      for (int k = 0; k < j; ++k) u -= U[i][k] * L[j][k];
+      U[i][j] = u;
+      L[i][j] = u * inv;
     }
   }
-  // forward solves L y = Fh_l (only the forward half is needed:
-  // Fh_l . A^{-1} Fh_l' = y_l . y_l')
 #pragma unroll
   for (int l = 0; l < 3; ++l)
 #pragma unroll
@@ -684,14 +686,19 @@ __device__ __forceinline__ bool rb_small_solve(const T* v, int r, double S3[3][3
       T t = (i < r) ? v[NA + l * RMAX + i] : T(0);
 #pragma unroll
       for (int k = 0; k < i; ++k) t -= L[i][k] * X[l][k];
-      X[l][i] = t / L[i][i];
+      X[l][i] = t;
     }
   const int ls[6] = {0, 0, 0, 1, 1, 2}, lps[6] = {0, 1, 2, 1, 2, 2};
+  T Z[3][RMAX];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) Z[l][i] = X[l][i] * dinv[i];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
     T acc = v[NA + 3 * RMAX + t];
 #pragma unroll
-    for (int i = 0; i < RMAX; ++i) acc -= X[ls[t]][i] * X[lps[t]][i];
+    for (int i = 0; i < RMAX; ++i) acc -= Z[ls[t]][i] * X[lps[t]][i];
     S3[ls[t]][lps[t]] = (double)acc;
     S3[lps[t]][ls[t]] = (double)acc;
   }
@@ -761,7 +768,7 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
   constexpr int AS_FLOATS = RBA_SAMPLES * RBA_LDA, GS_FLOATS = RBA_KC * PP;
   constexpr int CS_FLOATS = RBA_SAMPLES * (PP + 1);
   constexpr int SM_FLOATS = (AS_FLOATS + GS_FLOATS) > CS_FLOATS ? (AS_FLOATS + GS_FLOATS) : CS_FLOATS;
-  __shared__ float smem[SM_FLOATS];
+  __shared__ __align__(16) float smem[SM_FLOATS];
   float(*As)[RBA_LDA] = reinterpret_cast<float(*)[RBA_LDA]>(smem);
   float(*Gs)[PP] = reinterpret_cast<float(*)[PP]>(smem + AS_FLOATS);
   float(*Cs)[PP + 1] = reinterpret_cast<float(*)[PP + 1]>(smem);
@@ -789,18 +796,62 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
       v[q] = x;
     }
   };
+  // m in {8, 16, 32} with FP32 coefficients: a chunk of 64 elements is
+  // 64 / m whole rows of the patch, so each sample's share comes in 16-byte
+  // loads (16 per sample and chunk: thread tid takes float4 f = idx % 16 of
+  // sample idx / 16, idx = tid + 256 q)
+  const bool vec = std::is_same<TA, float>::value && (m == 8 || m == 16 || m == 32);
+  const int lm = m == 8 ? 3 : m == 16 ? 4 : 5;
+  auto load_chunk_vec = [&](int e0, float (&v)[RBA_PF]) {
+#pragma unroll
+    for (int q = 0; q < RBA_PF / 4; ++q) {
+      const int idx = tid + 256 * q, i = idx >> 4, e = e0 + 4 * (idx & 15);
+      const int64_t s = s0 + i;
+      f4 x = f4{0.f, 0.f, 0.f, 0.f};
+      if (s < args.nsamples && e < mm) {
+        const float* a = (const float*)args.a + s * (int64_t)(args.ncy * m) * lda;
+        x = *reinterpret_cast<const f4*>(a + (int64_t)(ky * m + (e >> lm)) * lda + kx * m + (e & (m - 1)));
+      }
+      v[4 * q] = x[0];
+      v[4 * q + 1] = x[1];
+      v[4 * q + 2] = x[2];
+      v[4 * q + 3] = x[3];
+    }
+  };
   float pf[RBA_PF];
-  load_chunk(0, pf);
+  if (vec)
+    load_chunk_vec(0, pf);
+  else
+    load_chunk(0, pf);
   for (int e0 = 0; e0 < KD; e0 += RBA_KC) {
     __syncthreads();  // the previous chunk's readers are done
+    if (vec) {
 #pragma unroll
-    for (int q = 0; q < RBA_PF; ++q) {
-      const int idx = tid + 256 * q;
-      As[idx / RBA_KC][idx % RBA_KC] = pf[q];
+      for (int q = 0; q < RBA_PF / 4; ++q) {
+        const int idx = tid + 256 * q;
+        *reinterpret_cast<f4*>(&As[idx >> 4][4 * (idx & 15)]) = f4{pf[4 * q], pf[4 * q + 1], pf[4 * q + 2], pf[4 * q + 3]};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < RBA_PF; ++q) {
+        const int idx = tid + 256 * q;
+        As[idx / RBA_KC][idx % RBA_KC] = pf[q];
+      }
     }
-    for (int idx = tid; idx < RBA_KC * PP; idx += 256) Gs[idx / PP][idx % PP] = G[(int64_t)e0 * PP + idx];
+    // the chunk's 64 table rows: contiguous, PP a multiple of 4, 16-byte loads
+    static_assert(PP % 4 == 0 && (RBA_KC * PP) % (4 * 256) == 0, "table chunk in float4 per thread");
+#pragma unroll
+    for (int q = 0; q < RBA_KC * PP / (4 * 256); ++q) {
+      const int idx = 4 * (tid + 256 * q);
+      *reinterpret_cast<f4*>(&Gs[0][0] + idx) = *reinterpret_cast<const f4*>(G + (int64_t)e0 * PP + idx);
+    }
     __syncthreads();
-    if (e0 + RBA_KC < KD) load_chunk(e0 + RBA_KC, pf);  // in flight during the products
+    if (e0 + RBA_KC < KD) {  // in flight during the products
+      if (vec)
+        load_chunk_vec(e0 + RBA_KC, pf);
+      else
+        load_chunk(e0 + RBA_KC, pf);
+    }
 #pragma unroll 4
     for (int kk = 0; kk < RBA_KC / 4; ++kk) {
       const float av0 = As[32 * w + (lane & 15)][4 * kk + (lane >> 4)];
