@@ -75,7 +75,13 @@ enum {
 
 /* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
  * nodal functions p^l restricted to the element boundary. */
-enum { STOMSFEM_BC_LINEAR = 0 };
+/* Boundary data of the cell problems (Sec. 2.2 eq. MsFEB): linear (the
+ * bilinear nodal functions on the boundary of K), or oscillatory (named for
+ * Sec. 5.3 without a definition; here on each edge of K the 1-D discrete
+ * harmonic profile of the edge-adjacent fine elements, sum_{s>=t} 1/a_s /
+ * sum_s 1/a_s from the edge's first corner, which is exact for media layered
+ * across the edge and equals the linear data for a constant coefficient). */
+enum { STOMSFEM_BC_LINEAR = 0, STOMSFEM_BC_OSCILLATORY = 1 };
 
 #define STOMSFEM_ABI_VERSION 1
 
@@ -157,7 +163,10 @@ typedef struct {
  *               (m-1)^2 (4 m + 40) bytes of LDS per workgroup (161 KB at
  *               m = 32; EINVAL if the device allows less), uses the library
  *               workspace and synchronises `stream` once per batch.
- *   bc        : STOMSFEM_BC_LINEAR
+ *   bc        : STOMSFEM_BC_LINEAR, or STOMSFEM_BC_OSCILLATORY (any m <= 48,
+ *               FP64 only: served by the reference kernel, one workgroup per
+ *               pair, so much slower than the linear data's tuned kernels;
+ *               EINVAL with precision F32_REFINE64)
  * Per-pair status: STOMSFEM_OK; 1 = recomputed in FP64 because the
  * refinement did not converge (F32_REFINE64 only); STOMSFEM_ENOTSPD when a
  * pivot of the FP64 factorisation is not positive (a <= 0 or NaN somewhere
@@ -167,7 +176,8 @@ typedef struct {
 int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t precision, int32_t bc, void* stream);
 
 /* Same computation through the simple reference kernel (one workgroup per
- * pair, band window in LDS, any m); used to cross-check the tuned kernels. */
+ * pair, band window in LDS, any m); used to cross-check the tuned kernels.
+ * bc: STOMSFEM_BC_LINEAR or STOMSFEM_BC_OSCILLATORY. */
 int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -226,6 +226,7 @@ UpArgs to_args(const stomsfem_batch& b) {
   a.a = b.a;
   a.S = b.S;
   a.status = b.status;
+  a.bc = STOMSFEM_BC_LINEAR;
   return a;
 }
 
@@ -486,7 +487,10 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
   if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(STOMSFEM_EINVAL, "upscale: bad batch list");
   if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32_REFINE64 && precision != STOMSFEM_PREC_AUTO)
     return fail(STOMSFEM_EINVAL, "upscale: precision must be STOMSFEM_PREC_F64, _F32_REFINE64 or _AUTO");
-  if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale: only STOMSFEM_BC_LINEAR is available");
+  if (bc != STOMSFEM_BC_LINEAR && bc != STOMSFEM_BC_OSCILLATORY)
+    return fail(STOMSFEM_EINVAL, "upscale: bc must be STOMSFEM_BC_LINEAR or STOMSFEM_BC_OSCILLATORY");
+  if (bc == STOMSFEM_BC_OSCILLATORY && precision == STOMSFEM_PREC_F32_REFINE64)
+    return fail(STOMSFEM_EINVAL, "upscale: oscillatory boundary data are served by the FP64 reference kernel only");
   for (int i = 0; i < nbatch; ++i) {
     int rc = check_batch(batches[i], i);
     if (rc != STOMSFEM_OK) return rc;
@@ -506,6 +510,13 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
   for (int i = 0; i < nbatch; ++i) {
     const stomsfem_batch& b = batches[i];
     if (b.nsamples == 0) continue;
+    if (bc == STOMSFEM_BC_OSCILLATORY) {
+      UpArgs up = to_args(b);
+      up.bc = STOMSFEM_BC_OSCILLATORY;
+      hipError_t e = launch_upscale_ref(up, b.a_dtype, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "upscale launch");
+      continue;
+    }
     const int prec_b = precision == STOMSFEM_PREC_AUTO ? tuned_cfg(b.m, b.a_dtype).precision : precision;
     if (prec_b == STOMSFEM_PREC_F32_REFINE64) {
       int rc = upscale_refined(b, (hipStream_t)stream);
@@ -520,11 +531,14 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
 
 int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* stream) {
   if (!batch) return fail(STOMSFEM_EINVAL, "upscale_reference: NULL batch");
-  if (bc != STOMSFEM_BC_LINEAR) return fail(STOMSFEM_EINVAL, "upscale_reference: only STOMSFEM_BC_LINEAR");
+  if (bc != STOMSFEM_BC_LINEAR && bc != STOMSFEM_BC_OSCILLATORY)
+    return fail(STOMSFEM_EINVAL, "upscale_reference: bc must be STOMSFEM_BC_LINEAR or STOMSFEM_BC_OSCILLATORY");
   int rc = check_batch(*batch, 0);
   if (rc != STOMSFEM_OK) return rc;
   if (batch->nsamples == 0) return STOMSFEM_OK;
-  hipError_t e = launch_upscale_ref(to_args(*batch), batch->a_dtype, (hipStream_t)stream);
+  UpArgs up = to_args(*batch);
+  up.bc = bc;
+  hipError_t e = launch_upscale_ref(up, batch->a_dtype, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_reference launch");
 }
 

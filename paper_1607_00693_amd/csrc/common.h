@@ -15,6 +15,7 @@ struct UpArgs {
   const void* a;
   double* S;
   int32_t* status;
+  int32_t bc;         // boundary data of the cell problems: 0 linear, 1 oscillatory (reference kernel only)
 };
 
 // Row-major offset of the m x m block of coarse element K of sample s.

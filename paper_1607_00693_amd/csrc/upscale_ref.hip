@@ -4,7 +4,14 @@
 // eqs. MsFEB and stiffness_local), written for clarity: the coefficient block
 // and the (m+1) x (m+1) band window live in LDS and every pivot step is a
 // workgroup-wide rank-1 update between two barriers.  It exists to
-// cross-check the register-blocked kernels and to serve unusual m.
+// cross-check the register-blocked kernels and to serve unusual m, and it is
+// the kernel of the oscillatory boundary data: on each edge of K the 1-D
+// discrete harmonic profile of the edge-adjacent fine elements,
+//   u(t) = sum_{s >= t} 1/a_s / sum_s 1/a_s   (1 at t = 0, 0 at t = m),
+// taken by the corner at t = 0 as u and by the corner at t = m as 1 - u
+// (edges: bottom from corner 0 to 1, right from 1 to 2, top from 3 to 2,
+// left from 0 to 3).  The three data sets still sum with the fourth to 1 on
+// the boundary, so S 1 = 0 and the fourth row follows as before.
 #include "common.h"
 
 namespace stomsfem {
@@ -18,7 +25,9 @@ __global__ __launch_bounds__(REF_THREADS) void upscale_ref_kernel(UpArgs args) {
   double* A = smem;                 // m*m coefficient block
   double* Wn = A + m * m;           // WN*WN window, (r, c) at [r%WN][c%WN]
   double* F = Wn + WN * WN;         // WN*3
+  double* Gp = F + WN * 3;          // 4 x (m+1): oscillatory profiles u_e(t) per edge
   __shared__ double sbb_part[REF_THREADS / 64][6];
+  const bool osc = args.bc == STOMSFEM_BC_OSCILLATORY;
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int Mc = args.ncx * args.ncy;
@@ -34,15 +43,60 @@ __global__ __launch_bounds__(REF_THREADS) void upscale_ref_kernel(UpArgs args) {
     for (int i = tid; i < WN * 3; i += blockDim.x) F[i] = 0.0;
     if (tid == 0) bad = 0;
     __syncthreads();
+    if (osc && tid < 4) {
+      // edge tid: its m edge-adjacent element values, the suffix sums of
+      // their resistances, normalised
+      const int ed = tid;
+      auto ka = [&](int t) -> double {
+        return ed == 0 ? A[t] : ed == 1 ? A[t * m + (m - 1)] : ed == 2 ? A[(m - 1) * m + t] : A[t * m];
+      };
+      double tot = 0.0;
+      for (int t = 0; t < m; ++t) tot += 1.0 / ka(t);
+      for (int t = 0; t <= m; ++t) {
+        double r = 0.0;
+        for (int u = t; u < m; ++u) r += 1.0 / ka(u);
+        Gp[ed * (m + 1) + t] = r / tot;
+      }
+    }
+    __syncthreads();
+    // boundary value of data set l (< 3) at boundary node (qx, qy)
+    auto gval = [&](int l, int qx, int qy) -> double {
+      if (!osc) return pcorner(l, qx, qy, m);
+      if (qy == 0) return l == 0 ? Gp[qx] : l == 1 ? 1.0 - Gp[qx] : 0.0;
+      if (qx == m) return l == 1 ? Gp[(m + 1) + qy] : l == 2 ? 1.0 - Gp[(m + 1) + qy] : 0.0;
+      if (qy == m) return l == 2 ? 1.0 - Gp[2 * (m + 1) + qx] : 0.0;  // corner 3 takes u, corner 2 takes 1 - u
+      if (qx == 0) return l == 0 ? Gp[3 * (m + 1) + qy] : 0.0;         // corner 0 takes u, corner 3 takes 1 - u
+      return 0.0;
+    };
 
     // g . K_BB g' over the elements touching the boundary
     double sb[6] = {0, 0, 0, 0, 0, 0};
     for (int e = tid; e < m * m; e += blockDim.x) {
       const int ex = e % m, ey = e / m;
       if (!(ex == 0 || ey == 0 || ex == m - 1 || ey == m - 1)) continue;
+      if (!osc) {
+        int q = 0;
+        for (int l = 0; l < 3; ++l)
+          for (int lp = l; lp < 3; ++lp) sb[q++] += A[e] * bb_coef(l, lp, ex, ey, m);
+        continue;
+      }
+      // the element's boundary nodes (local order 0..3 counter-clockwise)
+      double gv[3][4];
+      bool onb[4];
+      for (int al = 0; al < 4; ++al) {
+        const int qx = ex + (al == 1 || al == 2), qy = ey + (al >= 2);
+        onb[al] = qx == 0 || qx == m || qy == 0 || qy == m;
+        for (int l = 0; l < 3; ++l) gv[l][al] = onb[al] ? gval(l, qx, qy) : 0.0;
+      }
       int q = 0;
       for (int l = 0; l < 3; ++l)
-        for (int lp = l; lp < 3; ++lp) sb[q++] += A[e] * bb_coef(l, lp, ex, ey, m);
+        for (int lp = l; lp < 3; ++lp) {
+          double t = 0.0;
+          for (int al = 0; al < 4; ++al)
+            for (int be = 0; be < 4; ++be)
+              if (onb[al] && onb[be]) t += gv[l][al] * kref(al, be) * gv[lp][be];
+          sb[q++] += A[e] * t;
+        }
     }
     for (int q = 0; q < 6; ++q) {
       double v = sb[q];
@@ -74,7 +128,7 @@ __global__ __launch_bounds__(REF_THREADS) void upscale_ref_kernel(UpArgs args) {
         for (int q = 0; q < 8; ++q) {
           const int qx = px + dxs[q], qy = py + dys[q];
           if (qx == 0 || qx == m || qy == 0 || qy == m)
-            for (int l = 0; l < 3; ++l) f[l] -= ks[q] * pcorner(l, qx, qy, m);
+            for (int l = 0; l < 3; ++l) f[l] -= ks[q] * gval(l, qx, qy);
         }
         for (int l = 0; l < 3; ++l) F[(r % WN) * 3 + l] = f[l];
       }
@@ -133,7 +187,7 @@ __global__ __launch_bounds__(REF_THREADS) void upscale_ref_kernel(UpArgs args) {
 
 size_t upscale_ref_lds_bytes(int m) {
   const int WN = m + 1;
-  return sizeof(double) * ((size_t)m * m + (size_t)WN * WN + (size_t)WN * 3);
+  return sizeof(double) * ((size_t)m * m + (size_t)WN * WN + (size_t)WN * 3 + 4 * (size_t)(m + 1));
 }
 
 hipError_t launch_upscale_ref(const UpArgs& args, int a_dtype, hipStream_t st) {

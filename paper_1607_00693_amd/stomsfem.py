@@ -21,7 +21,7 @@ PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO, PREC_F32 = 0, 1, 2, 3, 4
 MLP_NPARAM = 9940
 MLP_BATCH = 32
 MLP_KIN = 4
-BC_LINEAR = 0
+BC_LINEAR, BC_OSCILLATORY = 0, 1
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
@@ -201,13 +201,13 @@ def make_batch(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor, sta
 
 
 def upscale(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None,
-            status: torch.Tensor | None = None, precision: int = PREC_F64, stream=None):
+            status: torch.Tensor | None = None, precision: int = PREC_F64, stream=None, bc: int = BC_LINEAR):
     """Upscaled stiffness S[N][ncy*ncx][10] for one homogeneous batch."""
     N = a.shape[0]
     if S is None:
         S = torch.empty((N, ncx * ncy, 10), dtype=torch.float64, device=a.device)
     b = make_batch(a, ncx, ncy, m, S, status)
-    _check("stomsfem_upscale", lib().stomsfem_upscale(C.byref(b), 1, precision, BC_LINEAR, _stream(stream)))
+    _check("stomsfem_upscale", lib().stomsfem_upscale(C.byref(b), 1, precision, bc, _stream(stream)))
     return S
 
 
@@ -217,12 +217,12 @@ def upscale_batches(batches: list[Batch], precision: int = PREC_F64, stream=None
 
 
 def upscale_reference(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None,
-                      status: torch.Tensor | None = None, stream=None):
+                      status: torch.Tensor | None = None, stream=None, bc: int = BC_LINEAR):
     N = a.shape[0]
     if S is None:
         S = torch.empty((N, ncx * ncy, 10), dtype=torch.float64, device=a.device)
     b = make_batch(a, ncx, ncy, m, S, status)
-    _check("stomsfem_upscale_reference", lib().stomsfem_upscale_reference(C.byref(b), BC_LINEAR, _stream(stream)))
+    _check("stomsfem_upscale_reference", lib().stomsfem_upscale_reference(C.byref(b), bc, _stream(stream)))
     return S
 
 

@@ -225,3 +225,59 @@ def test_mesh32_full_batch_sampled(sm, orc):
     np.testing.assert_allclose(qm.cpu().numpy(), U.mean(dim=0).cpu().numpy(), rtol=1e-12, atol=0)
     sm.tuning_reset()
     del a
+
+
+@pytest.mark.parametrize("m,ncx,ncy", [(2, 3, 2), (5, 2, 3), (8, 4, 4), (13, 2, 2), (16, 3, 2), (32, 2, 2)])
+def test_oscillatory_boundary_data_match_oracle(sm, orc, m, ncx, ncy):
+    # the oscillatory cell-problem data through the reference kernel (and
+    # through stomsfem_upscale, which routes them there) against the oracle's
+    # own construction, FP64 and FP32 coefficients
+    N = 3
+    say(f"oscillatory boundary data m={m} mesh {ncx}x{ncy}")
+    a_np = W.lognormal_field((N, ncy * m, ncx * m), 1.5, 3000 + m)
+    S_ref, st_ref, _ = orc.upscale(a_np, ncx, ncy, m, bc=orc.BC_OSC)
+    assert (st_ref == 0).all()
+    a = torch.from_numpy(a_np).cuda()
+    S1 = sm.upscale_reference(a, ncx, ncy, m, bc=sm.BC_OSCILLATORY)
+    S2 = sm.upscale(a, ncx, ncy, m, bc=sm.BC_OSCILLATORY)
+    S_lin = sm.upscale(a, ncx, ncy, m)
+    torch.cuda.synchronize()
+    for S in (S1, S2):
+        Sg = S.cpu().numpy()
+        err = np.abs(Sg - S_ref).max(-1) / np.abs(S_ref).max(-1)
+        assert err.max() < 1e-10, err.max()
+    # the data differ from the linear ones on a heterogeneous medium
+    assert (S1 - S_lin).abs().max().item() > 1e-3 * S_lin.abs().max().item()
+    a32 = torch.from_numpy(a_np.astype(np.float32)).cuda()
+    S32 = sm.upscale(a32, ncx, ncy, m, bc=sm.BC_OSCILLATORY).cpu().numpy()
+    S_ref32, _, _ = orc.upscale(a_np.astype(np.float32).astype(np.float64), ncx, ncy, m, bc=orc.BC_OSC)
+    assert (np.abs(S32 - S_ref32).max(-1) / np.abs(S_ref32).max(-1)).max() < 1e-10
+
+
+def test_oscillatory_boundary_data_constant_and_layered(sm, orc):
+    # constant coefficient: the oscillatory data are the linear data; media
+    # layered across x: the oscillatory S equals the oracle's (whose
+    # upscaled x-conductivity is the harmonic mean, pinned on the CPU)
+    m, nc = 8, 2
+    a = torch.full((1, nc * m, nc * m), 2.5, dtype=torch.float64, device="cuda")
+    So = sm.upscale(a, nc, nc, m, bc=sm.BC_OSCILLATORY)
+    Sl = sm.upscale(a, nc, nc, m)
+    torch.cuda.synchronize()
+    assert (So - Sl).abs().max().item() < 1e-13 * Sl.abs().max().item()
+    lay = W.uniform_array((nc * m,), 0.1, 10.0, 3101)
+    a_np = np.tile(lay[None, :], (nc * m, 1))[None]
+    S_ref, _, _ = orc.upscale(a_np, nc, nc, m, bc=orc.BC_OSC)
+    Sg = sm.upscale(torch.from_numpy(np.ascontiguousarray(a_np)).cuda(), nc, nc, m, bc=sm.BC_OSCILLATORY)
+    torch.cuda.synchronize()
+    Sg = Sg.cpu().numpy()
+    assert (np.abs(Sg - S_ref).max(-1) / np.abs(S_ref).max(-1)).max() < 1e-10
+
+
+def test_oscillatory_boundary_data_rejects_refinement(sm):
+    a = torch.ones((1, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(sm.StomsfemError) as e:
+        sm.upscale(a, 1, 1, 8, precision=sm.PREC_F32_REFINE64, bc=sm.BC_OSCILLATORY)
+    assert e.value.code == sm.EINVAL
+    with pytest.raises(sm.StomsfemError) as e:
+        sm.upscale(a, 1, 1, 8, bc=7)
+    assert e.value.code == sm.EINVAL
