@@ -231,6 +231,84 @@ def measure_coarse(log, meshes=(64, 48, 33), nsamples=256, reps=10):
     return out
 
 
+def measure_queue(log, reps=3):
+    """One round of the channels workload's upscaling: a batch of 256 samples
+    at each H/h in {8, 16, 32} on the 64 x 64 coarse mesh (FP32 coefficients,
+    generated beforehand, FP64 solves), upscaled (a) by the per-m kernels one
+    after the other on one stream, (b) by the per-m kernels on three streams at
+    once (as the plan's graph branches run them), (c) by the one persistent
+    launch over all three batches (stomsfem_upscale_queue); each batch also
+    alone through its per-m kernel and through the persistent kernel.  S of
+    (c) is compared bit for bit with (a)."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.CHANNELS64
+    dev = "cuda"
+    kind, x0, y0, size = W.channel_geometry(wl)
+    g = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (kind, x0, y0, size)]
+    N = wl.batch
+    xi = torch.from_numpy(W.normal_xi(3 * N, wl.nxi, wl.xi_seed)).to(dev)
+    bt = {}
+    for i, m in enumerate((8, 16, 32)):
+        fm = sm.feature_map(wl.nc * m, *g)
+        a = sm.coef_features(fm, wl.nxi, xi[i * N:(i + 1) * N].contiguous(), wl.decades, dtype=torch.float32)
+        S = torch.empty((N, wl.M, 10), dtype=torch.float64, device=dev)
+        st = torch.empty((N, wl.M), dtype=torch.int32, device=dev)
+        bt[m] = (a, S, st, sm.make_batch(a, wl.nc, wl.nc, m, S, st))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def ev(f):
+        f()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    allb = [bt[m][3] for m in (8, 16, 32)]
+    alone = {}
+    for m in (8, 16, 32):
+        alone[str(m)] = {"per_m_kernel_ms": ev(lambda: sm.upscale_batches([bt[m][3]])),
+                         "persistent_kernel_ms": ev(lambda: sm.upscale_queue([bt[m][3]]))}
+    streams = [torch.cuda.Stream() for _ in range(3)]
+
+    def concurrent():
+        cur = torch.cuda.current_stream()
+        start = torch.cuda.Event()
+        start.record(cur)
+        for s_, b in zip(streams, allb):
+            s_.wait_event(start)
+            sm.upscale_batches([b], stream=s_)
+        for s_ in streams:
+            cur.wait_stream(s_)
+
+    t_seq = ev(lambda: sm.upscale_batches(allb))
+    t_conc = ev(concurrent)
+    t_q = ev(lambda: sm.upscale_queue(allb))
+    sm.upscale_batches(allb)
+    torch.cuda.synchronize()
+    ref = {m: bt[m][1].clone() for m in (8, 16, 32)}
+    sm.upscale_queue(allb)
+    torch.cuda.synchronize()
+    same = all(torch.equal(ref[m], bt[m][1]) for m in (8, 16, 32))
+    pairs = 3 * N * wl.M
+    out = {"workload": f"one round of the channels workload: 64x64 coarse, {N} samples at each H/h in {{8, 16, 32}}, "
+                       "FP32 coefficients generated beforehand, FP64 solves; upscaling only",
+           "sequential_ms": t_seq, "concurrent_streams_ms": t_conc, "persistent_queue_ms": t_q,
+           "persistent_over_concurrent": t_q / t_conc, "pairs_per_s_concurrent": pairs / (t_conc * 1e-3),
+           "pairs_per_s_persistent": pairs / (t_q * 1e-3), "each_batch_alone": alone,
+           "persistent_bitwise_equal": bool(same)}
+    log(f"mixed-H/h launches: {out}")
+    return out
+
+
 def measure_channels(log, reps=3):
     """High-contrast channels-and-inclusions workload: 64 x 64 coarse mesh,
     32 batches of 256 samples with H/h drawn per batch from {8, 16, 32}, FP32
@@ -1096,7 +1174,7 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, coarse_bench, channels, channels_surrogate, oversampling, collocation, "
+                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, collocation, "
                          "two_level, gauss); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
@@ -1270,6 +1348,9 @@ def main():
         if want("coarse_bench"):
             lg("batched coarse solve at 64x64, 48x48, 33x33")
             out["coarse_solve_bench"] = measure_coarse(lg)
+        if want("queue"):
+            lg("mixed H/h: per-m kernels (sequential, concurrent streams) against one persistent launch")
+            out["mixed_m_persistent_launch"] = measure_queue(lg)
         chan = None
         if want("channels"):
             lg("channels-and-inclusions workload through a graph plan")

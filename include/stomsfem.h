@@ -180,6 +180,20 @@ int stomsfem_upscale(const stomsfem_batch* batches, int32_t nbatch, int32_t prec
  * bc: STOMSFEM_BC_LINEAR or STOMSFEM_BC_OSCILLATORY. */
 int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* stream);
 
+/* The same computation as stomsfem_upscale (FP64 factorisation, linear
+ * boundary data) for batches of different m in ONE persistent launch: a
+ * single queue of work items spans all batches and every wavefront takes
+ * items with an atomic counter until the queue is empty.  An item is one
+ * wavefront's tile (6 pairs for m = 16 and 32, 64 pairs for m = 8); items are
+ * taken in decreasing order of cost (all m = 32 items, then m = 16, then
+ * m = 8), so the launch ends on the cheapest ones.  S and the per-pair status
+ * are bitwise those of stomsfem_upscale.
+ *   batches : host array of nbatch (1..8) descriptors, every m in {8, 16, 32}
+ *             (EINVAL otherwise), all with the same a_dtype
+ * Uses 8 bytes of the library-owned device workspace (ordered against the
+ * other workspace users, see above); asynchronous. */
+int stomsfem_upscale_queue(const stomsfem_batch* batches, int32_t nbatch, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched coarse solve and quantity of interest (Sec. 2.2 eq. upscaleSUF;
  * Petrov-Galerkin load of eq. stiffness_local_petrov; Monte Carlo estimators

@@ -26,6 +26,10 @@ hipError_t launch_upscale_ref(const UpArgs& args, int a_dtype, hipStream_t st);
 size_t upscale_ref_lds_bytes(int m);
 hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st, int waves);
 bool tiled_supports(int m);
+hipError_t launch_upscale_queue(const UpArgs* batches, int nb, int a_dtype, unsigned long long* counter,
+                                hipStream_t st);
+bool queue_supports(int m);
+int queue_max_batches();
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
                          double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
@@ -540,6 +544,32 @@ int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* st
   up.bc = bc;
   hipError_t e = launch_upscale_ref(up, batch->a_dtype, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_reference launch");
+}
+
+int stomsfem_upscale_queue(const stomsfem_batch* batches, int32_t nbatch, void* stream) {
+  if (nbatch < 1 || !batches) return fail(STOMSFEM_EINVAL, "upscale_queue: need at least one batch");
+  if (nbatch > queue_max_batches())
+    return fail(STOMSFEM_EINVAL, "upscale_queue: at most " + std::to_string(queue_max_batches()) + " batches");
+  std::vector<UpArgs> up;
+  int64_t pairs = 0;
+  for (int i = 0; i < nbatch; ++i) {
+    int rc = check_batch(batches[i], i);
+    if (rc != STOMSFEM_OK) return rc;
+    if (!queue_supports(batches[i].m))
+      return fail(STOMSFEM_EINVAL, "upscale_queue: batch " + std::to_string(i) + ": m must be 8, 16 or 32");
+    if (batches[i].a_dtype != batches[0].a_dtype)
+      return fail(STOMSFEM_EINVAL, "upscale_queue: every batch must have the same a_dtype");
+    up.push_back(to_args(batches[i]));
+    pairs += up.back().npairs;
+  }
+  if (pairs == 0) return STOMSFEM_OK;
+  WorkspaceLease lease;
+  void* ws = nullptr;
+  int rc = lease.acquire(256, (hipStream_t)stream, &ws);
+  if (rc != STOMSFEM_OK) return rc;
+  hipError_t e = launch_upscale_queue(up.data(), nbatch, batches[0].a_dtype, (unsigned long long*)ws,
+                                      (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_queue launch");
 }
 
 int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,

@@ -25,6 +25,7 @@
 //   4. every lane applies the rank-T update W_R D^{-1} W_C^T to its tile.
 // Communication inside a wavefront only (LDS plus wave-level ordering).
 #include "common.h"
+#include "small_cell.h"
 
 namespace stomsfem {
 
@@ -80,29 +81,25 @@ __device__ __forceinline__ double recip(double d) {
   return __builtin_fma(r, e, r);
 }
 
-template <int M, int T, typename TA, int WV>
-// Occupancy floor: at m = 16 four wavefronts per SIMD (the LDS limit) beat
-// the spill-free register allocation (two) by 40% even with spills; at m = 32
-// two wavefronts per SIMD without spills.
-__global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kernel(UpArgs args) {
+// One wavefront's tile of TL_SLOTS pairs: pairs wtile * TL_SLOTS + q, q <
+// TL_SLOTS; lds = the wavefront's TL_SLOTS per-pair blocks.  Lanes past the
+// ten-lane groups return at once.
+template <int M, int T, typename TA>
+__device__ __forceinline__ void tiled_wave(const UpArgs& args, int64_t wtile, int lane, TiledLds<M, T>* lds) {
   constexpr int NT = TL_NT;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
   constexpr int FW = NT * T;
   using Lds = TiledLds<M, T>;
-  __shared__ Lds lds_all[WV][TL_SLOTS];
 
-  // WV independent wavefronts per workgroup (a launch-shape choice only)
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
   if (lane >= TL_SLOTS * TL_G) return;
   const int q = lane / TL_G, g = lane - q * TL_G;
-  Lds& sh = lds_all[wave][q];
+  Lds& sh = lds[q];
   // residue pair {P, Q}, P >= Q, of this lane: g = P (P + 1) / 2 + Q
   const int P = g >= 6 ? 3 : g >= 3 ? 2 : g >= 1 ? 1 : 0;
   const int Q = g - P * (P + 1) / 2;
 
-  int64_t p = ((int64_t)blockIdx.x * WV + wave) * TL_SLOTS + q;
+  int64_t p = wtile * TL_SLOTS + q;
   const bool valid = p < args.npairs;
   if (!valid) p = args.npairs - 1;
   const int Mc = args.ncx * args.ncy;
@@ -436,6 +433,17 @@ __global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kern
   }
 }
 
+template <int M, int T, typename TA, int WV>
+// Occupancy floor: at m = 16 four wavefronts per SIMD (the LDS limit) beat
+// the spill-free register allocation (two) by 40% even with spills; at m = 32
+// two wavefronts per SIMD without spills.
+__global__ __launch_bounds__(64 * WV, (M == 16 ? 4 : 2)) void upscale_tiled_kernel(UpArgs args) {
+  __shared__ TiledLds<M, T> lds_all[WV][TL_SLOTS];
+  // WV independent wavefronts per workgroup (a launch-shape choice only)
+  const int wave = threadIdx.x >> 6;
+  tiled_wave<M, T, TA>(args, (int64_t)blockIdx.x * WV + wave, threadIdx.x & 63, lds_all[wave]);
+}
+
 bool tiled_supports(int m) { return m == 16 || m == 32; }
 
 template <int M, int T, int WV>
@@ -459,6 +467,122 @@ hipError_t launch_upscale_tiled(const UpArgs& args, int a_dtype, hipStream_t st,
   if (args.m == 16) return launch_tw<16, 4>(args, a_dtype, st, waves);
   if (args.m == 32) return launch_tw<32, 8>(args, a_dtype, st, waves);
   return hipErrorInvalidValue;
+}
+
+// ---- one persistent launch over batches of several m (8, 16, 32) ----
+//
+// A single queue of work items spans every batch; each wavefront takes the
+// next item with one atomic increment and loops until the queue is empty.  An
+// item is one wavefront's tile: TL_SLOTS pairs for m = 16 and 32 (the
+// register-tiled elimination above), 64 pairs for m = 8 (one pair per lane,
+// small_cell.h).  Items are numbered by decreasing cost -- every m = 32 item
+// first, then m = 16, then m = 8 -- so the costliest items are taken first and
+// the launch ends on the cheapest ones (longest-processing-time-first list
+// scheduling on the CUs).  Every pair runs the same device code as in the
+// per-m kernels, so S and the status are bitwise those of stomsfem_upscale.
+// Registers and LDS are the maximum over the three paths: two wavefronts per
+// SIMD, the m = 32 limits (m = 16 tiles run at half their own kernel's
+// occupancy, m = 8 lanes at their register limit).
+struct QueueBatch {
+  UpArgs args;
+  int64_t first;  // number of the batch's first item
+  int32_t m;
+};
+constexpr int QUEUE_MAXB = 8;
+struct QueueArgs {
+  QueueBatch b[QUEUE_MAXB];  // in item order: m = 32, then 16, then 8
+  int32_t nb;
+  int64_t total;             // items in all
+  unsigned long long* counter;
+};
+
+__global__ void queue_reset_kernel(unsigned long long* counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
+}
+
+template <typename TA>
+__global__ __launch_bounds__(128, 2) void upscale_queue_kernel(QueueArgs qa) {
+  // one union per wavefront, so that each wavefront's blocks stay its own
+  // whichever m its current item has
+  union WaveLds {
+    TiledLds<32, 8> l32[TL_SLOTS];
+    TiledLds<16, 4> l16[TL_SLOTS];
+  };
+  __shared__ WaveLds lds[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(qa.counter, 1ull);
+    // the item number is wavefront-uniform: keep it (and what follows from
+    // it) in scalar registers
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)it);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(it >> 32));
+    const int64_t item = (int64_t)(((uint64_t)hi << 32) | lo);
+    if (item >= qa.total) break;
+    int b = 0;
+    while (b + 1 < qa.nb && item >= qa.b[b + 1].first) ++b;
+    const UpArgs args = qa.b[b].args;
+    const int64_t local = item - qa.b[b].first;
+    const int m = qa.b[b].m;
+    if (m == 32) {
+      tiled_wave<32, 8, TA>(args, local, lane, lds[wave].l32);
+    } else if (m == 16) {
+      tiled_wave<16, 4, TA>(args, local, lane, lds[wave].l16);
+    } else {
+      const int64_t p = local * 64 + lane;
+      if (p < args.npairs) {
+        const int Mc = args.ncx * args.ncy;
+        const int64_t s = p / Mc;
+        const int K = (int)(p - s * Mc);
+        small_cell_solve<8, TA>((const TA*)args.a + block_offset(s, K, args.ncx, args.ncy, 8),
+                                (int64_t)args.ncx * 8, args.S + p * 10, args.status ? args.status + p : nullptr);
+      }
+    }
+  }
+}
+
+bool queue_supports(int m) { return m == 8 || m == 16 || m == 32; }
+int queue_max_batches() { return QUEUE_MAXB; }
+
+// batches: nb <= QUEUE_MAXB, every m in {8, 16, 32}, one coefficient type;
+// counter: 8 bytes of device memory, reset here on the stream.
+hipError_t launch_upscale_queue(const UpArgs* batches, int nb, int a_dtype, unsigned long long* counter,
+                                hipStream_t st) {
+  if (nb < 1 || nb > QUEUE_MAXB) return hipErrorInvalidValue;
+  QueueArgs qa{};
+  int64_t total = 0;
+  for (int mm : {32, 16, 8}) {
+    for (int i = 0; i < nb; ++i) {
+      if (!queue_supports(batches[i].m)) return hipErrorInvalidValue;
+      if (batches[i].m != mm || batches[i].npairs == 0) continue;
+      QueueBatch& q = qa.b[qa.nb++];
+      q.args = batches[i];
+      q.first = total;
+      q.m = mm;
+      const int64_t per = mm == 8 ? 64 : TL_SLOTS;
+      total += (batches[i].npairs + per - 1) / per;
+    }
+  }
+  if (total == 0) return hipSuccess;
+  qa.total = total;
+  qa.counter = counter;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = a_dtype == STOMSFEM_F32
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, upscale_queue_kernel<float>, 128, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, upscale_queue_kernel<double>, 128, 0);
+  if (e != hipSuccess) return e;
+  int64_t grid = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  const int64_t waves_needed = (total + 1) / 2;  // two wavefronts per workgroup
+  if (grid > waves_needed) grid = waves_needed;
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL(upscale_queue_kernel<float>, dim3((unsigned)grid), dim3(128), 0, st, qa);
+  else
+    hipLaunchKernelGGL(upscale_queue_kernel<double>, dim3((unsigned)grid), dim3(128), 0, st, qa);
+  return hipGetLastError();
 }
 
 }  // namespace stomsfem

@@ -84,6 +84,7 @@ def lib():
         "stomsfem_coef_bumps": (C.c_int, [i64, i32, vp, i32, i32, dbl, dbl, dbl, dbl, dbl, vp, i32, vp]),
         "stomsfem_upscale": (C.c_int, [C.POINTER(Batch), i32, i32, i32, vp]),
         "stomsfem_upscale_reference": (C.c_int, [C.POINTER(Batch), i32, vp]),
+        "stomsfem_upscale_queue": (C.c_int, [C.POINTER(Batch), i32, vp]),
         "stomsfem_coarse_solve": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_coarse_solve_pg": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_upscale_os": (C.c_int, [vp, i32, vp]),
@@ -214,6 +215,12 @@ def upscale(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None 
 def upscale_batches(batches: list[Batch], precision: int = PREC_F64, stream=None):
     arr = (Batch * len(batches))(*batches)
     _check("stomsfem_upscale", lib().stomsfem_upscale(arr, len(batches), precision, BC_LINEAR, _stream(stream)))
+
+
+def upscale_queue(batches: list[Batch], stream=None):
+    """One persistent launch over batches of m in {8, 16, 32}."""
+    arr = (Batch * len(batches))(*batches)
+    _check("stomsfem_upscale_queue", lib().stomsfem_upscale_queue(arr, len(batches), _stream(stream)))
 
 
 def upscale_reference(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tensor | None = None,
