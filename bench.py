@@ -928,7 +928,8 @@ def measure_gauss(log, N=1024, n_trunc=64):
     local parameters for N samples; the rate of pairs with a parameter
     outside [-3, 3] among the four kept ones against 1 - P(|Z| <= 3)^4 =
     0.0108; and, on n_trunc samples, the error of S and of the coarse
-    solution when kappa is replaced by its truncated local KL with K terms
+    solution (source b = 2 + x1 x2 as in Sec. 5.3, through the element loads)
+    when kappa is replaced by its truncated local KL with K terms
     (eq. local_KL_truncation); and the local KL in the paper's geometry, on
     the oversampled patches of side 2H with l2 = H (kept spectrum, out-of-box
     rate, projection throughput)."""
@@ -941,6 +942,7 @@ def measure_gauss(log, N=1024, n_trunc=64):
     from paper_1607_00693_amd import workloads as W
 
     wl = W.GAUSS16
+    gl = sm.element_loads(wl.nc, wl.nc)  # Sec. 5.3's source b = 2 + x1 x2
     z, u = W.spectral_draws(N, wl.nterms, wl.seed)
     z, u = torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda()
     t_field = _timed(lambda: sm.coef_gauss(z, u, wl.nfine, wl.l1, wl.l2, with_beta=True), reps=3)
@@ -957,12 +959,12 @@ def measure_gauss(log, N=1024, n_trunc=64):
     n = n_trunc
     xi, _, _ = sm.kl_project(beta[:n].contiguous(), wl.nc, wl.m, mu_d, V_d, wl.box)
     S_full = sm.upscale(kap[:n].contiguous(), wl.nc, wl.nc, wl.m)
-    U_full, _, _ = sm.coarse_solve(S_full, wl.nc, wl.nc)
+    U_full, _, _ = sm.coarse_solve(S_full, wl.nc, wl.nc, load=gl)
     scale = S_full.abs().amax(dim=2)
     trunc = {}
     for K in (1, 2, 3, 4, 6, 8):
         S_t = sm.upscale(sm.kl_blocks(xi, mu_d, V_d, K), 1, 1, wl.m).reshape(n, wl.M, 10)
-        U_t, _, _ = sm.coarse_solve(S_t, wl.nc, wl.nc)
+        U_t, _, _ = sm.coarse_solve(S_t, wl.nc, wl.nc, load=gl)
         trunc[f"K_{K}"] = {
             "captured": float(mu[:K].sum() / (wl.m * wl.m)),
             "max_S_rel_err": float(((S_t - S_full).abs().amax(dim=2) / scale).max().item()),
@@ -980,7 +982,7 @@ def measure_gauss(log, N=1024, n_trunc=64):
     S_t4 = sm.upscale(sm.kl_blocks(xi4[:n].contiguous(), mu4, V4, wl.kl_terms), 1, 1, wl.m).reshape(n, wl.M, 10)
     fb4 = out4[:n].bool()
     S_t4[fb4] = S_all[:n][fb4]
-    U_t4, _, _ = sm.coarse_solve(S_t4, wl.nc, wl.nc)
+    U_t4, _, _ = sm.coarse_solve(S_t4, wl.nc, wl.nc, load=gl)
     interp = {}
     for nn in (7, 9):
         t0 = time.perf_counter()
@@ -990,7 +992,7 @@ def measure_gauss(log, N=1024, n_trunc=64):
         S_int = torch.empty((N, wl.M, 10), dtype=torch.float64, device="cuda")
         t_int = _timed(lambda: sm.kl_interp_apply(model, xi4, kap, S=S_int), reps=3)
         _, nfb = sm.kl_interp_apply(model, xi4, kap, S=S_int)
-        U_int, _, _ = sm.coarse_solve(S_int[:n].contiguous(), wl.nc, wl.nc)
+        U_int, _, _ = sm.coarse_solve(S_int[:n].contiguous(), wl.nc, wl.nc, load=gl)
         interp[f"nodes_{nn}"] = {
             "table_rows": nn ** 4, "build_s": t_build, "apply_ms": t_int * 1e3,
             "pairs_per_s": pairs / t_int, "plain_pairs_per_s": pairs / t_plain, "ratio_vs_plain": t_plain / t_int,
@@ -1029,7 +1031,7 @@ def measure_gauss(log, N=1024, n_trunc=64):
     torch.cuda.synchronize()
     t_pl = _timed(lambda: sm.upscale_os(kap_os, wl.nc, wl.nc, wl.m, o, S=S_pl), reps=2)
     sc_pl = S_pl.abs().amax(dim=2)
-    U_pl, _, _ = sm.coarse_solve_pg(S_pl[:n_trunc].contiguous(), wl.nc, wl.nc)
+    U_pl, _, _ = sm.coarse_solve_pg(S_pl[:n_trunc].contiguous(), wl.nc, wl.nc, load=gl)
     os_interp = {}
     # tensor grids of 5 and 7 nodes per parameter; sparse grids of levels 4
     # and 5 (401 and 1105 nodes in four parameters)
@@ -1042,7 +1044,7 @@ def measure_gauss(log, N=1024, n_trunc=64):
         S_i = torch.empty_like(S_pl)
         t_i = _timed(lambda: sm.kl_interp_apply(model, xi_os, kap_os, S=S_i), reps=3)
         _, nfb = sm.kl_interp_apply(model, xi_os, kap_os, S=S_i)
-        U_i, _, _ = sm.coarse_solve_pg(S_i[:n_trunc].contiguous(), wl.nc, wl.nc)
+        U_i, _, _ = sm.coarse_solve_pg(S_i[:n_trunc].contiguous(), wl.nc, wl.nc, load=gl)
         ins = ~out_os.bool()
         os_interp[name] = {
             "nodes_per_class": nodes, "table_rows": 9 * nodes, "build_s": t_build, "apply_ms": t_i * 1e3,

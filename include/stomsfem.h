@@ -210,6 +210,18 @@ int stomsfem_upscale_queue(const stomsfem_batch* batches, int32_t nbatch, void* 
  *   status  : device out [nsamples] (OK or ENOTSPD), may be NULL
  * Uses library-owned device workspace (see stomsfem_workspace_reserve).
  * ------------------------------------------------------------------------ */
+/* Element loads of a bilinear source for the `load` argument of the coarse
+ * solves: b^K_l = int_K b p^l (the Petrov-Galerkin load of eq.
+ * stiffness_local_petrov with the coarse bilinear test functions) for
+ *   b(x, y) = f[0] + f[1] x + f[2] y + f[3] x y
+ * (Sec. 5.3 takes b = 2 + x1 x2, i.e. f = {2, 0, 0, 1}), square elements of
+ * side H = 1/ncx, element ky*ncx + kx = [kx H, (kx+1) H] x [ky H, (ky+1) H].
+ *   f    : host array of 4 finite coefficients (read during the call)
+ *   load : device out [ncy*ncx][4], local nodes counter-clockwise from the
+ *          lower-left corner
+ * Exact (2 x 2 Gauss rule on bilinear x bilinear).  Asynchronous. */
+int stomsfem_element_loads(int32_t ncx, int32_t ncy, const double* f, double* load, void* stream);
+
 int stomsfem_coarse_solve(int32_t ncx, int32_t ncy, int64_t nsamples, const double* S, const double* load,
                           double* U, double* qoi_mean, double* qoi_var, int32_t* status, void* stream);
 

@@ -30,6 +30,7 @@ hipError_t launch_upscale_queue(const UpArgs* batches, int nb, int a_dtype, unsi
                                 hipStream_t st);
 bool queue_supports(int m);
 int queue_max_batches();
+hipError_t launch_element_loads(int ncx, int ncy, const double* f, double* load, hipStream_t st);
 hipError_t launch_coarse(int ncx, int ncy, int64_t N, const double* S, const double* load, double* U, double* mean,
                          double* var, int32_t* status, double* work, hipStream_t st);
 hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, const double* load, double* U,
@@ -544,6 +545,17 @@ int stomsfem_upscale_reference(const stomsfem_batch* batch, int32_t bc, void* st
   up.bc = bc;
   hipError_t e = launch_upscale_ref(up, batch->a_dtype, (hipStream_t)stream);
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "upscale_reference launch");
+}
+
+int stomsfem_element_loads(int32_t ncx, int32_t ncy, const double* f, double* load, void* stream) {
+  if (ncx < 1 || ncy < 1 || (int64_t)ncx * ncy > (1 << 24))
+    return fail(STOMSFEM_EINVAL, "element_loads: ncx, ncy must be >= 1 (at most 2^24 elements)");
+  if (!f) return fail(STOMSFEM_EINVAL, "element_loads: f is NULL");
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(f[i])) return fail(STOMSFEM_EINVAL, "element_loads: f must be finite");
+  if (!device_ptr(load)) return fail(STOMSFEM_EINVAL, "element_loads: load is not a device pointer");
+  hipError_t e = launch_element_loads(ncx, ncy, f, load, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "element_loads launch");
 }
 
 int stomsfem_upscale_queue(const stomsfem_batch* batches, int32_t nbatch, void* stream) {

@@ -1079,4 +1079,36 @@ hipError_t launch_coarse_pg(int ncx, int ncy, int64_t N, const double* S16, cons
   return launch_coarse_any(ncx, ncy, N, S16, load, U, mean, var, status, work, st, true);
 }
 
+// Element loads b^K_l = int_K b p^l of a bilinear source
+// b = f00 + f10 x + f01 y + f11 x y (Sec. 5.3 takes 2 + x1 x2), for square
+// elements of side H = 1/ncx, local nodes counter-clockwise from the
+// lower-left corner.  b p^l is at most quadratic in each variable, so the
+// 2 x 2 Gauss rule on K is exact.  One thread per element.
+__global__ void element_loads_kernel(int ncx, int ncy, double f00, double f10, double f01, double f11,
+                                     double* __restrict__ load) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncx * ncy) return;
+  const double H = 1.0 / ncx;
+  const double x0 = (e % ncx) * H, y0 = (e / ncx) * H;
+  const double g[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+  double b[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const double s = g[i], t = g[j], x = x0 + H * s, y = y0 + H * t;
+      const double w = 0.25 * H * H * (f00 + f10 * x + f01 * y + f11 * x * y);
+      b[0] += w * (1.0 - s) * (1.0 - t);
+      b[1] += w * s * (1.0 - t);
+      b[2] += w * s * t;
+      b[3] += w * (1.0 - s) * t;
+    }
+  for (int l = 0; l < 4; ++l) load[4 * e + l] = b[l];
+}
+
+hipError_t launch_element_loads(int ncx, int ncy, const double* f, double* load, hipStream_t st) {
+  const int n = ncx * ncy;
+  hipLaunchKernelGGL(element_loads_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ncx, ncy, f[0], f[1], f[2], f[3],
+                     load);
+  return hipGetLastError();
+}
+
 }  // namespace stomsfem

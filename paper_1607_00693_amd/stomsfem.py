@@ -85,6 +85,7 @@ def lib():
         "stomsfem_upscale": (C.c_int, [C.POINTER(Batch), i32, i32, i32, vp]),
         "stomsfem_upscale_reference": (C.c_int, [C.POINTER(Batch), i32, vp]),
         "stomsfem_upscale_queue": (C.c_int, [C.POINTER(Batch), i32, vp]),
+        "stomsfem_element_loads": (C.c_int, [i32, i32, C.POINTER(dbl), vp, vp]),
         "stomsfem_coarse_solve": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_coarse_solve_pg": (C.c_int, [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
         "stomsfem_upscale_os": (C.c_int, [vp, i32, vp]),
@@ -231,6 +232,15 @@ def upscale_reference(a: torch.Tensor, ncx: int, ncy: int, m: int, S: torch.Tens
     b = make_batch(a, ncx, ncy, m, S, status)
     _check("stomsfem_upscale_reference", lib().stomsfem_upscale_reference(C.byref(b), bc, _stream(stream)))
     return S
+
+
+def element_loads(ncx: int, ncy: int, f=(2.0, 0.0, 0.0, 1.0), stream=None) -> torch.Tensor:
+    """Element loads [ncy*ncx][4] of the bilinear source f[0] + f[1] x + f[2] y + f[3] x y
+    (default: Sec. 5.3's 2 + x1 x2)."""
+    fa = (C.c_double * 4)(*[float(v) for v in f])
+    out = torch.empty((ncy * ncx, 4), dtype=torch.float64, device="cuda")
+    _check("stomsfem_element_loads", lib().stomsfem_element_loads(ncx, ncy, fa, _ptr(out), _stream(stream)))
+    return out
 
 
 def coarse_solve(S: torch.Tensor, ncx: int, ncy: int, load: torch.Tensor | None = None,

@@ -183,6 +183,46 @@ def test_coarse_solve(sm, orc, ncx, ncy):
         np.testing.assert_allclose(mean.cpu().numpy(), mean_ref, rtol=UTOL, atol=1e-300)
 
 
+@pytest.mark.parametrize("ncx,ncy", [(1, 1), (5, 3), (16, 16), (64, 64)])
+def test_element_loads_match_oracle(sm, ncx, ncy):
+    from oracle import loads
+    say(f"element loads {ncx}x{ncy}")
+    for f in ((2.0, 0.0, 0.0, 1.0), (0.3, -1.2, 0.7, 2.5), (1.0, 0.0, 0.0, 0.0)):
+        ref = loads.element_loads_bilinear(ncx, ncy, f)
+        got = sm.element_loads(ncx, ncy, f).cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max(), f
+
+
+def test_coarse_solve_with_the_paper_source(sm, orc):
+    # Sec. 5.3's source b = 2 + x1 x2 enters through the element loads; the
+    # oracle's coarse solve takes the oracle's loads, the GPU solve the GPU's
+    from oracle import loads
+    m, nc, N = 4, 6, 3
+    say("coarse solve with b = 2 + x1 x2")
+    a_np = W.lognormal_field((N, nc * m, nc * m), 1.0, 1300)
+    S_ref, _, _ = orc.upscale(a_np, nc, nc, m)
+    U_ref, mean_ref, _ = orc.coarse_solve(S_ref, nc, nc, load_vec=loads.element_loads_bilinear(nc, nc, (2, 0, 0, 1)))
+    U, mean, _ = sm.coarse_solve(torch.from_numpy(S_ref).cuda(), nc, nc, load=sm.element_loads(nc, nc))
+    torch.cuda.synchronize()
+    assert u_relerr(U.cpu().numpy(), U_ref) < UTOL
+    assert np.abs(mean.cpu().numpy() - mean_ref).max() <= 1e-10 * np.abs(mean_ref).max()
+    # the constant source's loads reproduce the default (NULL) load exactly
+    U1, _, _ = sm.coarse_solve(torch.from_numpy(S_ref).cuda(), nc, nc, load=sm.element_loads(nc, nc, (1, 0, 0, 0)))
+    U0, _, _ = sm.coarse_solve(torch.from_numpy(S_ref).cuda(), nc, nc)
+    torch.cuda.synchronize()
+    assert u_relerr(U1.cpu().numpy(), U0.cpu().numpy()) < 1e-14
+    # argument errors are caught on the host
+    import ctypes
+    out = torch.empty((4, 4), dtype=torch.float64, device="cuda")
+    bad = (ctypes.c_double * 4)(1.0, float("nan"), 0.0, 0.0)
+    assert sm.lib().stomsfem_element_loads(2, 2, bad, ctypes.c_void_p(out.data_ptr()), None) == sm.EINVAL
+    good = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 0.0)
+    assert sm.lib().stomsfem_element_loads(0, 2, good, ctypes.c_void_p(out.data_ptr()), None) == sm.EINVAL
+    host = torch.empty((4, 4), dtype=torch.float64)
+    assert sm.lib().stomsfem_element_loads(2, 2, good, ctypes.c_void_p(host.data_ptr()), None) == sm.EINVAL
+    assert sm.lib().stomsfem_element_loads(2, 2, None, ctypes.c_void_p(out.data_ptr()), None) == sm.EINVAL
+
+
 def test_coarse_two_by_two_closed_form(sm):
     # nc = 2, S = K_ref (a == 1), f = 1: U = 3/32
     say("coarse 2x2 closed form")
