@@ -34,6 +34,37 @@ def test_spectral_field_has_the_gaussian_covariance():
         assert abs(cy - np.exp(-(d * h) ** 2 / l2**2)) < 0.1
 
 
+def test_spectral_field_covariance_is_exact_under_quadrature():
+    # the covariance of one cosine term, averaged over its phase and over
+    # its wave vector, is E_w[cos(w . d)] = exp(-|d|^2 / l^2) exactly when w
+    # has the normal law N(0, 2/l^2) per component.  Replacing the random
+    # draws by a Gauss-Hermite rule in z (40 nodes, exact to rounding for
+    # this smooth integrand) and four equispaced phases (the phase average of
+    # cos(a + p) cos(b + p) is cos(a - b) / 2 exactly) makes the check
+    # deterministic, so any slip in the scaling of the wave vectors (a
+    # factor sqrt 2, l1 and l2 swapped) shows at every lag
+    l1, l2, nf = 0.5, 0.1, 32
+    zn, zw = np.polynomial.hermite_e.hermegauss(40)
+    zw = zw / np.sqrt(2.0 * np.pi)
+    phases = np.arange(4) / 4.0
+    h = 1.0 / nf
+    for axis, l in ((0, l1), (1, l2)):
+        z = np.zeros((len(zn) * 4, 1, 2))
+        u = np.zeros((len(zn) * 4, 1))
+        wts = np.zeros(len(zn) * 4)
+        for k in range(len(zn)):
+            for p in range(4):
+                z[4 * k + p, 0, axis] = zn[k]
+                u[4 * k + p, 0] = phases[p]
+                wts[4 * k + p] = zw[k] / 4.0
+        b = gauss.field(z, u, nf, l1, l2)  # one term: J = 1
+        line = b[:, 5, :] if axis == 0 else b[:, :, 7]
+        assert abs(np.einsum("s,sx->x", wts, line * line).max() - 1.0) < 1e-12
+        for d in range(1, 12):
+            cov = np.einsum("s,sx->x", wts, line[:, :-d] * line[:, d:])
+            assert np.abs(cov - np.exp(-(d * h) ** 2 / l**2)).max() < 1e-12, (axis, d)
+
+
 def test_local_kl_is_the_separable_product():
     m, h, l1, l2 = 12, 1.0 / 96, 1.0, 1.0 / 48
     mu, V, frac = gauss.local_kl(m, h, l1, l2, 8)
