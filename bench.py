@@ -569,6 +569,14 @@ def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((
     U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
     U_s, _, _ = sm.coarse_solve(S_su, wl.nc, wl.nc)
     u_err = float((torch.linalg.norm(U_s - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())
+    # the FP16 single-term kernel on the same networks and samples
+    t_h = _timed(lambda: sm.upscale_surrogate(mdl, xi, 1e-3, sm.PREC_F16, S=S_su, status=status), reps=3)
+    sth = status.cpu()
+    U_h, _, _ = sm.coarse_solve(S_su, wl.nc, wl.nc)
+    f16 = {"pairs_per_s": N * wl.M / t_h, "ratio": t_plain_ms * 1e-3 / t_h,
+           "accepted": float((sth == 0).float().mean()), "fallback": float((sth == 1).float().mean()),
+           "audited": float((sth == 2).float().mean()),
+           "max_coarse_rel_err": float((torch.linalg.norm(U_h - U_p, dim=1) / torch.linalg.norm(U_p, dim=1)).max())}
     pairs = N * wl.M
     out = {"workload": f"{wl.nc}x{wl.nc} coarse, H/h={wl.m}, {wl.M} per-patch MLPs (k<=4 -> 64x3 -> 2x10, GELU), "
                        f"{ntrain} training samples/patch, {sum(s for s, _ in schedule)} Adam steps, the benchmark's "
@@ -577,7 +585,7 @@ def measure_surrogate(wl, xi, S_plain, t_plain_ms, log, ntrain=2048, schedule=((
            "pairs_per_s": pairs / t_su, "plain_pairs_per_s": pairs / (t_plain_ms * 1e-3),
            "ratio": t_plain_ms * 1e-3 / t_su,
            "accepted": float((st == 0).float().mean()), "fallback": float((st == 1).float().mean()),
-           "audited": float((st == 2).float().mean()), "max_coarse_rel_err": u_err}
+           "audited": float((st == 2).float().mean()), "max_coarse_rel_err": u_err, "fp16_single_term": f16}
     log(f"surrogate on the benchmark mesh: {out}")
     mdl.free()
     return out
@@ -1154,12 +1162,19 @@ def measure_accelerations(log):
     t_pl = _timed(plain)
     t_su = _timed(lambda: sm.upscale_surrogate(mdl, xi, 1e-3, sm.PREC_BF16, S=S_su, status=status))
     st = status.cpu().numpy()
+    err_b = coarse_err(S_su, S_pl)
+    # the FP16 single-term kernel on the same networks and samples
+    t_h = _timed(lambda: sm.upscale_surrogate(mdl, xi, 1e-3, sm.PREC_F16, S=S_su, status=status))
+    sth = status.cpu().numpy()
     out["learned_surrogate"] = {
         "workload": f"8x8 coarse, H/h=8, 64 per-patch MLPs (k<=4 -> 64x3 -> 2x10, GELU), {ntr} training "
                     f"samples/patch, {N} test samples, gate tau=1e-3, BF16 MFMA (3-term split)",
         "train_s": t_train, "pairs_per_s": N * wl.M / t_su, "plain_pairs_per_s": N * wl.M / t_pl,
         "ratio": t_pl / t_su, "accepted": float((st == 0).mean()), "fallback": float((st == 1).mean()),
-        "audited": float((st == 2).mean()), "max_coarse_rel_err": coarse_err(S_su, S_pl)}
+        "audited": float((st == 2).mean()), "max_coarse_rel_err": err_b,
+        "fp16_single_term": {"pairs_per_s": N * wl.M / t_h, "ratio": t_pl / t_h,
+                             "accepted": float((sth == 0).mean()), "fallback": float((sth == 1).mean()),
+                             "audited": float((sth == 2).mean()), "max_coarse_rel_err": coarse_err(S_su, S_pl)}}
     log(f"learned surrogate: {out['learned_surrogate']}")
     mdl.free()
     return out

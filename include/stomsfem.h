@@ -69,12 +69,12 @@ enum {
   STOMSFEM_PREC_F32_REFINE64 = 1,  /* FP32 arithmetic where the entry point allows it, FP64 residuals/energies */
   STOMSFEM_PREC_BF16 = 2,          /* BF16 matrix-core products with FP32 accumulation (surrogate) */
   STOMSFEM_PREC_AUTO = 3,          /* stomsfem_upscale: the autotuner's choice for (m, a_dtype), else FP64 */
-  STOMSFEM_PREC_F32 = 4            /* plain FP32 arithmetic, no refinement: the reduced basis's matrix-core
+  STOMSFEM_PREC_F32 = 4,           /* plain FP32 arithmetic, no refinement: the reduced basis's matrix-core
                                       stage and the surrogate's FP32 reference */
+  STOMSFEM_PREC_F16 = 5            /* FP16 matrix-core products (single terms) with FP32 accumulation
+                                      (surrogate) */
 };
 
-/* Boundary data of the cell problems (Sec. 2.2, eq. MsFEB): the bilinear
- * nodal functions p^l restricted to the element boundary. */
 /* Boundary data of the cell problems (Sec. 2.2 eq. MsFEB): linear (the
  * bilinear nodal functions on the boundary of K), or oscillatory (named for
  * Sec. 5.3 without a definition; here on each edge of K the 1-D discrete
@@ -528,7 +528,8 @@ int stomsfem_mlp_params(stomsfem_model* model, float* dst, const float* src, voi
 int stomsfem_mlp_standardization(const stomsfem_model* model, double* mu_host, double* sd_host);
 
 /* Raw network outputs Y device [nsamples][M][20] for xi device
- * [nsamples][nxi]; precision STOMSFEM_PREC_BF16 (matrix cores) or
+ * [nsamples][nxi]; precision STOMSFEM_PREC_BF16 (matrix cores, three-term
+ * bf16 splitting), STOMSFEM_PREC_F16 (matrix cores, single fp16 terms) or
  * STOMSFEM_PREC_F32 (FP32 reference). */
 int stomsfem_mlp_predict(const stomsfem_model* model, const double* xi, int32_t nxi, int64_t nsamples, float* Y,
                          int32_t precision, void* stream);

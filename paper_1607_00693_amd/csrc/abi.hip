@@ -1859,8 +1859,8 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   if (!model || model->kind != 2) return fail(STOMSFEM_EINVAL, "surrogate: not a surrogate model");
   if (nsamples < 0 || nxi < 1) return fail(STOMSFEM_EINVAL, "surrogate: bad sizes");
   if (model->lv_max >= nxi) return fail(STOMSFEM_EINVAL, "surrogate: nxi smaller than the local variable indices");
-  if (precision != STOMSFEM_PREC_F32 && precision != STOMSFEM_PREC_BF16)
-    return fail(STOMSFEM_EINVAL, "surrogate: precision must be STOMSFEM_PREC_F32 or STOMSFEM_PREC_BF16");
+  if (precision != STOMSFEM_PREC_F32 && precision != STOMSFEM_PREC_BF16 && precision != STOMSFEM_PREC_F16)
+    return fail(STOMSFEM_EINVAL, "surrogate: precision must be STOMSFEM_PREC_F32, _BF16 or _F16");
   if (nsamples == 0) return STOMSFEM_OK;
   if (!device_ptr(xi)) return fail(STOMSFEM_EINVAL, "surrogate: xi must be a device pointer");
   if ((Y && !device_ptr(Y)) || (S && !device_ptr(S)) || (status && !device_ptr(status)) ||
@@ -1918,7 +1918,10 @@ static int mlp_infer_common(stomsfem_model* model, const double* xi, int32_t nxi
   a.bump_beta = model->fam.beta;
   a.m = model->m;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_mlp_infer(a, precision == STOMSFEM_PREC_BF16, st);
+  const int mode = precision == STOMSFEM_PREC_BF16 ? MLP_MODE_BF16
+                   : precision == STOMSFEM_PREC_F16  ? MLP_MODE_F16
+                                                     : MLP_MODE_F32;
+  hipError_t e = launch_mlp_infer(a, mode, st);
   if (e != hipSuccess) return hip_fail(e, "surrogate launch");
   if (!S || (model->m == 8 && model->family == MLP_FAMILY_BUMPS)) return STOMSFEM_OK;
   // plain fallback for m != 8: the listed pairs in chunks (reads the count)

@@ -97,7 +97,12 @@ struct MlpInferArgs {
 
 hipError_t launch_mlp_train(const MlpTrainArgs& a, bool train, hipStream_t st);
 hipError_t launch_mlp_data(const MlpDataArgs& d, hipStream_t st);
-hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st);
+// Inference variants: FP32 reference, BF16 matrix cores with three-term
+// splitting, FP16 matrix cores with single terms.
+constexpr int MLP_MODE_F32 = 0;
+constexpr int MLP_MODE_BF16 = 1;
+constexpr int MLP_MODE_F16 = 2;
+hipError_t launch_mlp_infer(const MlpInferArgs& a, int mode, hipStream_t st);
 // The gate alone on given raw outputs Y [nsamples][M][20] (a.S, a.status,
 // a.gate written; no audit, no fallback).
 hipError_t launch_mlp_gate(const MlpInferArgs& a, const float* Y, hipStream_t st);

@@ -11,11 +11,12 @@
 //                            parameter by the thread that formed its
 //                            gradient, otherwise the raw gradient is written
 //                            (parity checks against the oracle).
-//   mlp_infer_bf16_kernel    BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
-//                            accumulation, three-term bf16 splitting of
-//                            weights and activations, activations kept in
-//                            registers, tabulated GELU) inference, then the
-//                            gate per pair;
+//   mlp_infer_mma_kernel<F16> matrix-core inference (FP32 accumulation,
+//                            activations kept in registers, tabulated GELU),
+//                            then the gate per pair: BF16 with three-term
+//                            splitting of weights and activations
+//                            (v_mfma_f32_16x16x32_bf16), or FP16 single
+//                            terms (v_mfma_f32_16x16x32_f16);
 //   mlp_infer_f32_kernel     FP32 inference (reference for the BF16 one);
 //   mlp_fallback_kernel      plain solve (m = 8 lane kernel) of the pairs the
 //                            gate rejected plus a 1% audit of accepted ones,
@@ -467,13 +468,18 @@ __global__ __launch_bounds__(64) void mlp_infer_f32_kernel(MlpInferArgs a) {
   }
 }
 
-// BF16 MFMA inference (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+// Matrix-core inference, BF16 (v_mfma_f32_16x16x32_bf16) or FP16
+// (v_mfma_f32_16x16x32_f16), FP32 accumulation.
 //
 // Every FP32 weight w and activation h is carried as two bf16 numbers,
 // w = w_hi + w_lo, h = h_hi + h_lo (w_hi = bf16(w), w_lo = bf16(w - w_hi)), and
 // each product is formed as h_hi w_hi + h_hi w_lo + h_lo w_hi on the matrix
 // cores (the h_lo w_lo term is below 2^-16 relative), which keeps the layers
-// at about 16 significant bits.
+// at about 16 significant bits.  The FP16 variant carries every value as one
+// fp16 number and forms one product: its 11-bit significand (bf16 has 8) is
+// enough for the gate to accept as many pairs as with the three-term BF16
+// form on the trained networks, at a third of the matrix work, half the
+// operand registers and LDS (two workgroups per CU) and no splitting.
 //
 // The layers are computed transposed, D = W^T H^T (rows = output neurons,
 // columns = 16 samples), so that the accumulator layout of one layer is the
@@ -487,18 +493,18 @@ __global__ __launch_bounds__(64) void mlp_infer_f32_kernel(MlpInferArgs a) {
 // layout (16 bytes per lane and operand, one ds_read_b128).  Activations never
 // leave the registers; biases initialise the accumulators.
 //
-// GELU: Phi(z) is read from a table of piecewise quadratics on [-6, 6]
-// (step 1/64, interpolating Phi at both ends and the midpoint of each
-// interval; Phi from the FP64 erfc at the nodes), built in LDS by every
-// workgroup; the interpolation error is below 1e-7 and Phi is 0 or 1 to FP32
-// precision outside the range.  The erf form is evaluated exactly by the FP32
-// reference kernel and the training kernel.
+// GELU: Phi(z) interpolated linearly in an LDS table built by every
+// workgroup (gelu_lin: nodes 1/256 apart for BF16, 1/128 for FP16).  The erf
+// form is evaluated exactly by the FP32 reference kernel and the training
+// kernel.
 //
 // Workgroup = 8 wavefronts on one patch; a wavefront takes 64 samples (four
-// column tiles of 16), parks the 20 outputs of each sample in LDS and then
+// column tiles of 16, in one pass for BF16 and two for FP16), parks the 20
+// outputs of each sample in LDS and then
 // gates one sample per lane; rejected and audited pairs are appended to the
 // fallback list with one atomic per wavefront.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BF_WAVES = 8;                 // wavefronts per workgroup
@@ -507,17 +513,31 @@ constexpr int BF_NOP = 32;                  // 20 outputs padded to two row tile
 // A operands: layer 1 (4 row tiles x 1 k block), layers 2 and 3 (4 x 2),
 // layer 4 (2 x 2); each x {hi, lo} x 64 lanes x 8 bf16
 constexpr int BF_OPS_L1 = 0, BF_OPS_L2 = 4, BF_OPS_L3 = 12, BF_OPS_L4 = 20, BF_OPS = 24;
-constexpr int GT_N = 768;                   // GELU table intervals on [-6, 6]
-constexpr float GT_SCALE = 64.0f, GT_OFF = 384.0f;
 
-__device__ __forceinline__ float gelu_tab(const float4* __restrict__ tab, float z) {
-  float u = fmaf(z, GT_SCALE, GT_OFF);
-  u = fminf(fmaxf(u, 0.0f), (float)GT_N - 0.0009765625f);
+// GELU of the matrix-core kernels: Phi linear between nodes on [-6, 6] (value
+// and increment at each node, one 8-byte table read per activation; Phi from
+// the FP64 erfc at the nodes, 0 or 1 to FP32 precision outside the range).
+// FP16 variant: nodes 1/128 apart, interpolation error below 2e-6 in Phi, so
+// below 1.2e-5 in gelu(z) for |z| <= 6, far under the fp16 rounding
+// (2^-11 relative) the activations then take; 12 KB.
+// The BF16 variant, whose layers carry about 16 significant bits, uses
+// nodes 1/256 apart (error below 5e-7 in Phi, 3e-6 in gelu(z)) in 24 KB.
+template <bool F16>
+struct GeluLin {
+  static constexpr int N = F16 ? 1536 : 3072;  // intervals on [-6, 6]
+  static constexpr float SCALE = F16 ? 128.0f : 256.0f, OFF = 6.0f * SCALE;
+};
+template <bool F16>
+__device__ __forceinline__ float gelu_lin(const float2* __restrict__ tab, float z) {
+  using G = GeluLin<F16>;
+  float u = fmaf(z, G::SCALE, G::OFF);
+  u = fminf(fmaxf(u, 0.0f), (float)G::N - 0.0009765625f);
   const int i = (int)u;
   const float t = __builtin_amdgcn_fractf(u);
-  const float4 c = tab[i];
-  return z * fmaf(t, fmaf(t, c.z, c.y), c.x);
+  const float2 c = tab[i];
+  return z * fmaf(t, c.y, c.x);
 }
+
 
 // split four consecutive activations of two tiles into hi/lo B operands
 __device__ __forceinline__ void split8(const f32x4_t& a, const f32x4_t& b, bf16x8_t& hi, bf16x8_t& lo) {
@@ -538,13 +558,54 @@ __device__ __forceinline__ f32x4_t mma3(const bf16x8_t& ah, const bf16x8_t& al, 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferArgs a) {
-  const int K = blockIdx.y;
+// Operand types of the two matrix-core variants: BF16 carries every value as
+// hi + lo (two terms, three products), FP16 as one term (one product).
+template <bool F16>
+struct MmaOps {
+  typedef bf16x8_t V;
+  static constexpr int NS = 2;  // terms per value
+  __device__ static __forceinline__ void split(const f32x4_t& a, const f32x4_t& b, V& hi, V& lo) {
+    split8(a, b, hi, lo);
+  }
+  __device__ static __forceinline__ f32x4_t mma(const V& ah, const V& al, const V& bh, const V& bl, f32x4_t c) {
+    return mma3(ah, al, bh, bl, c);
+  }
+};
+template <>
+struct MmaOps<true> {
+  typedef f16x8_t V;
+  static constexpr int NS = 1;
+  __device__ static __forceinline__ void split(const f32x4_t& a, const f32x4_t& b, V& hi, V&) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      hi[v] = (_Float16)a[v];
+      hi[4 + v] = (_Float16)b[v];
+    }
+  }
+  __device__ static __forceinline__ f32x4_t mma(const V& ah, const V&, const V& bh, const V&, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
+  }
+};
+
+// Workgroups: gx tile groups x npatch patches, in an order that gives each
+// XCD (workgroups go to the XCDs round robin) a contiguous range of patches of
+// one tile group, so that the S rows of neighbouring patches of one sample
+// (adjacent in memory) are written through the same L2.
+template <bool F16>
+__global__ __launch_bounds__(64 * BF_WAVES, F16 ? 4 : 1) void mlp_infer_mma_kernel(MlpInferArgs a, int gx) {
+  using Ops = MmaOps<F16>;
+  using V = typename Ops::V;
+  constexpr int NS = Ops::NS;
+  constexpr int CT = F16 ? 2 : 4;  // column tiles per pass
+  const int nwg = gx * a.npatch;
+  const int b = blockIdx.x;
+  const int widx = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
+  const int K = widx % a.npatch, x0 = widx / a.npatch;
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
   const int g = lane >> 4, col = lane & 15;
   constexpr int NT = 64 * BF_WAVES;
-  __shared__ bf16x8_t WA[BF_OPS][2][64];      // [operand][hi/lo][lane]
-  __shared__ float4 tab[GT_N];
+  __shared__ V WA[BF_OPS][NS][64];      // [operand][term][lane]
+  __shared__ float2 tab[GeluLin<F16>::N];
   __shared__ float bias[3 * WD + BF_NOP];
   // the per-sample outputs of the tiles; during set-up the same memory holds
   // the patch's raw parameters
@@ -575,9 +636,16 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
       else if (L == 3) v = P[MLP_OW3 + nin * WD + nout];
       else if (nout < NO) v = P[MLP_OW4 + nin * NO + nout];
     }
-    const __bf16 h = (__bf16)v;
-    WA[op][0][ln][j] = h;
-    WA[op][1][ln][j] = (__bf16)(v - (float)h);
+    V* dst[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) dst[t] = &WA[op][t][ln];
+    if constexpr (NS == 2) {
+      const __bf16 h = (__bf16)v;
+      (*dst[0])[j] = h;
+      (*dst[1])[j] = (__bf16)(v - (float)h);
+    } else {
+      (*dst[0])[j] = (_Float16)v;
+    }
   }
   for (int i = tid; i < 3 * WD + BF_NOP; i += NT) {
     float v;
@@ -587,28 +655,31 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
     else v = (i - 3 * WD) < NO ? P[MLP_OB4 + i - 3 * WD] : 0.0f;
     bias[i] = v;
   }
-  // ---- GELU table: quadratic through Phi at x0, x0 + h/2, x0 + h ----
-  for (int i = tid; i < GT_N; i += NT) {
-    const double h = 1.0 / GT_SCALE, x0 = -6.0 + i * h;
+  // ---- GELU table: value and increment of Phi at each node ----
+  for (int i = tid; i < GeluLin<F16>::N; i += NT) {
+    const double h = 1.0 / GeluLin<F16>::SCALE, x0 = -6.0 + i * h;
     const double f0 = 0.5 * erfc(-x0 * 0.70710678118654752440);
-    const double fm = 0.5 * erfc(-(x0 + 0.5 * h) * 0.70710678118654752440);
     const double f1 = 0.5 * erfc(-(x0 + h) * 0.70710678118654752440);
-    tab[i] = make_float4((float)f0, (float)(-3.0 * f0 + 4.0 * fm - f1), (float)(2.0 * f0 - 4.0 * fm + 2.0 * f1), 0.0f);
+    tab[i] = make_float2((float)f0, (float)(f1 - f0));
   }
   __syncthreads();
   const int lv0 = a.lv[K * MLP_KIN + 0], lv1 = a.lv[K * MLP_KIN + 1], lv2 = a.lv[K * MLP_KIN + 2],
             lv3 = a.lv[K * MLP_KIN + 3];
   const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int64_t tile = x0; tile < ntiles; tile += gx) {
     const int64_t wbase = tile * BF_TILE + 64 * w;  // this wavefront's 64 samples
-    // the four column tiles of 16 samples go through each layer together:
-    // every A operand is read from LDS once per layer and used four times
-    bf16x8_t bh[4][2], bl[4][2];
-    f32x4_t acc[4][4];
+    // CT column tiles of 16 samples go through each layer together: every A
+    // operand is read from LDS once per layer and pass and used CT times
+    // (BF16: one pass of four tiles; FP16: two passes of two, which keeps
+    // the wavefront within the registers of four wavefronts per SIMD)
     const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t s = wbase + 16 * st + col;
+    for (int hf = 0; hf < 4 / CT; ++hf) {
+    V bh[CT][2], bl[CT][2];
+    f32x4_t acc[CT][4];
+#pragma unroll
+    for (int st = 0; st < CT; ++st) {
+      const int64_t s = wbase + 16 * (hf * CT + st) + col;
       f32x4_t x4 = z4;  // layer-1 B operand: x in slots 0..3 of lane group 0
       if (g == 0 && s < a.nsamples) {
         const double* xs = a.xi + s * a.nxi;
@@ -617,27 +688,27 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
         x4[2] = lv2 >= 0 ? (float)mlp_input(a.family, xs[lv2]) : 0.0f;
         x4[3] = lv3 >= 0 ? (float)mlp_input(a.family, xs[lv3]) : 0.0f;
       }
-      split8(x4, z4, bh[st][0], bl[st][0]);
+      Ops::split(x4, z4, bh[st][0], bl[st][0]);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const bf16x8_t ah = WA[BF_OPS_L1 + nt][0][lane], al = WA[BF_OPS_L1 + nt][1][lane];
+      const V ah = WA[BF_OPS_L1 + nt][0][lane], al = WA[BF_OPS_L1 + nt][NS - 1][lane];
       f32x4_t b4;
 #pragma unroll
       for (int v = 0; v < 4; ++v) b4[v] = bias[16 * nt + 4 * g + v];
 #pragma unroll
-      for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][0], bl[st][0], b4);
+      for (int st = 0; st < CT; ++st) acc[st][nt] = Ops::mma(ah, al, bh[st][0], bl[st][0], b4);
     }
 #pragma unroll
     for (int L = 0; L < 2; ++L) {
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
+      for (int st = 0; st < CT; ++st) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_tab(tab, acc[st][nt][v]);
-        split8(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
-        split8(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
+          for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_lin<F16>(tab, acc[st][nt][v]);
+        Ops::split(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
+        Ops::split(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
       }
       const int ob = L == 0 ? BF_OPS_L2 : BF_OPS_L3;
       const float* bs = bias + (L + 1) * WD;
@@ -647,23 +718,23 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
 #pragma unroll
         for (int v = 0; v < 4; ++v) b4[v] = bs[16 * nt + 4 * g + v];
 #pragma unroll
-        for (int st = 0; st < 4; ++st) acc[st][nt] = b4;
+        for (int st = 0; st < CT; ++st) acc[st][nt] = b4;
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-          const bf16x8_t ah = WA[ob + 2 * nt + kb][0][lane], al = WA[ob + 2 * nt + kb][1][lane];
+          const V ah = WA[ob + 2 * nt + kb][0][lane], al = WA[ob + 2 * nt + kb][NS - 1][lane];
 #pragma unroll
-          for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
+          for (int st = 0; st < CT; ++st) acc[st][nt] = Ops::mma(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
         }
       }
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
+    for (int st = 0; st < CT; ++st) {
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_tab(tab, acc[st][nt][v]);
-      split8(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
-      split8(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
+        for (int v = 0; v < 4; ++v) acc[st][nt][v] = gelu_lin<F16>(tab, acc[st][nt][v]);
+      Ops::split(acc[st][0], acc[st][1], bh[st][0], bl[st][0]);
+      Ops::split(acc[st][2], acc[st][3], bh[st][1], bl[st][1]);
     }
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -671,23 +742,24 @@ __global__ __launch_bounds__(64 * BF_WAVES) void mlp_infer_bf16_kernel(MlpInferA
 #pragma unroll
       for (int v = 0; v < 4; ++v) b4[v] = bias[3 * WD + 16 * nt + 4 * g + v];
 #pragma unroll
-      for (int st = 0; st < 4; ++st) acc[st][nt] = b4;
+      for (int st = 0; st < CT; ++st) acc[st][nt] = b4;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
-        const bf16x8_t ah = WA[BF_OPS_L4 + 2 * nt + kb][0][lane], al = WA[BF_OPS_L4 + 2 * nt + kb][1][lane];
+        const V ah = WA[BF_OPS_L4 + 2 * nt + kb][0][lane], al = WA[BF_OPS_L4 + 2 * nt + kb][NS - 1][lane];
 #pragma unroll
-        for (int st = 0; st < 4; ++st) acc[st][nt] = mma3(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
+        for (int st = 0; st < CT; ++st) acc[st][nt] = Ops::mma(ah, al, bh[st][kb], bl[st][kb], acc[st][nt]);
       }
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < CT; ++st)
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int o = 16 * nt + 4 * g + v;
-          if (o < NO) Ys[w][16 * st + col][o] = acc[st][nt][v];
+          if (o < NO) Ys[w][16 * (hf * CT + st) + col][o] = acc[st][nt][v];
         }
+    }  // passes
     __syncthreads();
     // ---- one sample per lane: outputs, gate, fallback list ----
     const int64_t s = wbase + lane;
@@ -734,7 +806,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 __global__ __launch_bounds__(64) void mlp_fallback_kernel(MlpInferArgs a) {
-  __shared__ double blk[64][64];
+  // one 8 x 8 coefficient block per lane; the pad of one double between the
+  // lanes' blocks puts the lanes' same-index entries on different LDS banks
+  // (with 64 doubles per lane every lane would hit the same bank)
+  __shared__ double blk[64][65];
   const int lane = threadIdx.x;
   const unsigned long long count = *a.count;
   const double h = 1.0 / (a.ncx * 8);
@@ -835,19 +910,25 @@ hipError_t launch_mlp_fallback_finish(const int64_t* list, int64_t count, const 
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const MlpInferArgs& a, bool bf16, hipStream_t st) {
+hipError_t launch_mlp_infer(const MlpInferArgs& a, int mode, hipStream_t st) {
   if (a.S) {
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)a.count, 1);
   }
-  if (bf16) {
+  if (mode == MLP_MODE_BF16 || mode == MLP_MODE_F16) {
     const int64_t ntiles = (a.nsamples + BF_TILE - 1) / BF_TILE;
-    // one workgroup per CU (its LDS allows no second one): about 256 in all,
-    // each persistent over its patch's tiles, so the per-workgroup set-up
-    // (weights, GELU table) is paid once per CU
-    int64_t gx = (256 + a.npatch - 1) / a.npatch;
+    // workgroups persistent over their patch's tiles, so the per-workgroup
+    // set-up (weights, GELU table) is paid once per workgroup: about one
+    // workgroup per CU slot (BF16: one per CU, its LDS allows no second one;
+    // FP16: two per CU)
+    const int64_t slots = mode == MLP_MODE_F16 ? 512 : 256;
+    int64_t gx = (slots + a.npatch - 1) / a.npatch;
     if (gx > ntiles) gx = ntiles;
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3((unsigned)gx, (unsigned)a.npatch), dim3(64 * BF_WAVES), 0, st, a);
+    const dim3 grid((unsigned)(gx * a.npatch));
+    if (mode == MLP_MODE_F16)
+      hipLaunchKernelGGL(mlp_infer_mma_kernel<true>, grid, dim3(64 * BF_WAVES), 0, st, a, (int)gx);
+    else
+      hipLaunchKernelGGL(mlp_infer_mma_kernel<false>, grid, dim3(64 * BF_WAVES), 0, st, a, (int)gx);
   } else {
     const dim3 grid((unsigned)((a.nsamples + 63) / 64), (unsigned)a.npatch);
     hipLaunchKernelGGL(mlp_infer_f32_kernel, grid, dim3(64), 0, st, a);

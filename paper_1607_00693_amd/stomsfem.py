@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libstomsfem.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, EVERSION = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
-PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO, PREC_F32 = 0, 1, 2, 3, 4
+PREC_F64, PREC_F32_REFINE64, PREC_BF16, PREC_AUTO, PREC_F32, PREC_F16 = 0, 1, 2, 3, 4, 5
 MLP_NPARAM = 9940
 MLP_BATCH = 32
 MLP_KIN = 4

@@ -6,7 +6,8 @@ Tolerances: FP32 gradients within 1e-4 of the FP64 oracle relative to the
 largest gradient entry of the patch (single-precision sums of 32 to 64
 terms); FP32 forward within 1e-5 of the oracle (absolute, standardised
 units); BF16 forward (three-term bf16 splitting, FP32 accumulation) within 1e-3
-of the FP64 oracle's forward pass; the standardisation within 1e-13 of the
+of the FP64 oracle's forward pass, FP16 forward (single fp16 terms) within
+16 u = 7.8e-3 (u = 2^-11, derived at the test); the standardisation within 1e-13 of the
 oracle's (FP64 on both sides, different summation orders); five FP32 Adam
 steps within 2e-2 of the learning rate of the oracle's FP64 trajectory from
 the same seeded weights, on the components whose gradient stays above 1e-2
@@ -110,6 +111,19 @@ def test_forward_fp32_and_bf16(sm):
         worst = max(worst, float(np.abs(Y16[:, K] - Yref).max() / max(1.0, np.abs(Yref).max())))
     say(f"max |Y_bf16 - Y_oracle| = {worst:.3e}")
     assert worst < 1e-3
+    # the FP16 single-term kernel against the oracle: inputs, weights and
+    # activations rounded to fp16 (unit roundoff u = 2^-11), products exact,
+    # FP32 sums; two roundings per product in each of four layers, with
+    # GELU's slope at most 1.13, bound the output error by about 8u times the
+    # scale of the outputs' terms; the test allows 16u = 7.8e-3
+    Yh = sm.mlp_predict(model, xi_d, sm.PREC_F16).cpu().numpy()
+    worst_h = 0.0
+    for K in range(wl.M):
+        X = np.where(lv[K] >= 0, xi[:, np.maximum(lv[K], 0)], 0.0).astype(np.float32).astype(np.float64)
+        Yref, _ = mlp.forward(params[K].astype(np.float64), X, 4)
+        worst_h = max(worst_h, float(np.abs(Yh[:, K] - Yref).max() / max(1.0, np.abs(Yref).max())))
+    say(f"max |Y_f16 - Y_oracle| = {worst_h:.3e}")
+    assert worst_h < 16 * 2.0**-11
     model.free()
 
 
@@ -268,6 +282,35 @@ def test_surrogate_gate_fallback_and_gain(sm, orc, trained):
     # the 1e-3 coarse-solution criterion asserted above
     assert acc.mean() > 0.9
     assert tp / ts > 1.5
+
+
+def test_surrogate_f16_gate_fallback(sm, orc, trained):
+    # the FP16 single-term kernel on the trained networks: the gate accepts as
+    # many pairs as with the three-term BF16 kernel (the precision of fp16 is
+    # enough for the gate's 1e-3), recomputed pairs are the plain path's bit
+    # for bit, the coarse solution within 1e-3 of the plain path's
+    wl, model = trained["wl"], trained["model"]
+    N = 16384
+    say(f"FP16 surrogate on {N} test samples")
+    xi_d = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1004)).cuda()
+    a = sm.coef_bumps(xi_d, wl.nfine, **wl.coef_params())
+    S_plain = sm.upscale(a, wl.nc, wl.nc, wl.m)
+    st_b = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    st_h = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_BF16, status=st_b)
+    S_h = sm.upscale_surrogate(model, xi_d, 1e-3, sm.PREC_F16, status=st_h)
+    U_p, _, _ = sm.coarse_solve(S_plain, wl.nc, wl.nc)
+    U_h, _, _ = sm.coarse_solve(S_h, wl.nc, wl.nc)
+    torch.cuda.synchronize()
+    sb, sh = st_b.cpu().numpy(), st_h.cpu().numpy()
+    Sp, Sh = S_plain.cpu().numpy(), S_h.cpu().numpy()
+    rec = sh != 0
+    assert np.array_equal(Sh[rec], Sp[rec])
+    ue = (np.linalg.norm(U_h.cpu().numpy() - U_p.cpu().numpy(), axis=1) / np.linalg.norm(U_p.cpu().numpy(), axis=1))
+    say(f"accepted: BF16 {(sb == 0).mean():.4f}, FP16 {(sh == 0).mean():.4f}; FP16 max U err {ue.max():.2e}")
+    assert abs((sh == 0).mean() - (sb == 0).mean()) < 5e-3
+    assert (sh == 0).mean() > 0.9
+    assert ue.max() < 1e-3
 
 
 def test_surrogate_full_test_set_sampled_against_oracle(sm, orc, trained):
