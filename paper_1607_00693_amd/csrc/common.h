@@ -96,6 +96,8 @@ struct BumpParams {
 // The same sum for a point whose centre cell (bx, by) the caller supplies
 // (a workgroup whose points share one cell passes it as a uniform value, so
 // the loop bounds and the xi loads are uniform too).
+// XS: stride between consecutive xi_j in memory (1 for a sample's row of xi).
+template <int XS = 1>
 __device__ __forceinline__ double bump_field_cell(double x, double y, const double* xs, const BumpParams& bp, int bx,
                                                   int by) {
   const double ginv = 1.0 / bp.g, rinv2 = 1.0 / (bp.rho * bp.rho);
@@ -106,7 +108,7 @@ __device__ __forceinline__ double bump_field_cell(double x, double y, const doub
     for (int jx = max(bx - reach, 0); jx <= min(bx + reach, bp.g - 1); ++jx) {
       const double cx = (jx + 0.5) * ginv;
       const double r2 = ((x - cx) * (x - cx) + dy2) * rinv2;
-      if (r2 < 1.0) field += xs[jy * bp.g + jx] * (1.0 - r2) * (1.0 - r2);
+      if (r2 < 1.0) field += xs[(jy * bp.g + jx) * XS] * (1.0 - r2) * (1.0 - r2);
     }
   }
   return field;
@@ -115,8 +117,9 @@ __device__ __forceinline__ double bump_field_cell(double x, double y, const doub
 // centre cell of a point along one axis
 __device__ __forceinline__ int bump_cell(double x, int g) { return min((int)(x * g), g - 1); }
 
+template <int XS = 1>
 __device__ __forceinline__ double bump_field(double x, double y, const double* xs, const BumpParams& bp) {
-  return bump_field_cell(x, y, xs, bp, bump_cell(x, bp.g), bump_cell(y, bp.g));
+  return bump_field_cell<XS>(x, y, xs, bp, bump_cell(x, bp.g), bump_cell(y, bp.g));
 }
 
 // Conductivity of feature j of the channels-and-inclusions medium:

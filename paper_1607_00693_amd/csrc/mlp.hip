@@ -558,6 +558,14 @@ __device__ __forceinline__ f32x4_t mma3(const bf16x8_t& ah, const bf16x8_t& al, 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
 }
 
+// Orders the LDS accesses of one wavefront across its lanes (a wave barrier
+// between release and acquire fences of wavefront scope).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Operand types of the two matrix-core variants: BF16 carries every value as
 // hi + lo (two terms, three products), FP16 as one term (one product).
 template <bool F16>
@@ -760,7 +768,10 @@ __global__ __launch_bounds__(64 * BF_WAVES, F16 ? 4 : 1) void mlp_infer_mma_kern
           if (o < NO) Ys[w][16 * (hf * CT + st) + col][o] = acc[st][nt][v];
         }
     }  // passes
-    __syncthreads();
+    // Ys[w] is this wavefront's alone: a wavefront-level barrier orders its
+    // writes before the reads of other lanes, and the wavefronts of the
+    // workgroup run through their tiles independently
+    wave_lds_sync();
     // ---- one sample per lane: outputs, gate, fallback list ----
     const int64_t s = wbase + lane;
     bool fb = false;
@@ -784,7 +795,7 @@ __global__ __launch_bounds__(64 * BF_WAVES, F16 ? 4 : 1) void mlp_infer_mma_kern
         if (fb) a.list[base + __popcll(mask & ((1ull << lane) - 1ull))] = s * a.npatch + K;
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // the reads of Ys[w] before the next tile's writes
   }  // tiles
 }
 
@@ -806,10 +817,13 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 __global__ __launch_bounds__(64) void mlp_fallback_kernel(MlpInferArgs a) {
-  // one 8 x 8 coefficient block per lane; the pad of one double between the
-  // lanes' blocks puts the lanes' same-index entries on different LDS banks
-  // (with 64 doubles per lane every lane would hit the same bank)
-  __shared__ double blk[64][65];
+  __shared__ double blk[64][64];  // one 8 x 8 coefficient block per lane
+  // each lane's sample's xi, staged in LDS (column per lane) when the family
+  // has at most XL of them: the bump sums over the 64 elements then read
+  // them from LDS instead of issuing a dependent global load per candidate
+  // bump; 40 KB per workgroup keeps four workgroups (one per SIMD) per CU
+  constexpr int XL = 16;
+  __shared__ double xl[XL][64];
   const int lane = threadIdx.x;
   const unsigned long long count = *a.count;
   const double h = 1.0 / (a.ncx * 8);
@@ -836,15 +850,25 @@ __global__ __launch_bounds__(64) void mlp_fallback_kernel(MlpInferArgs a) {
         syv[q] = sin(2.0 * M_PI * yq / bp.eps);
       }
       const double* xs = a.xi + s * a.nxi;
+      const int nb = bp.g * bp.g;
+      auto regen = [&](auto xsc, const double* src) {
+        constexpr int XS = decltype(xsc)::value;
 #pragma unroll
-      for (int ey = 0; ey < 8; ++ey)
+        for (int ey = 0; ey < 8; ++ey)
 #pragma unroll
-        for (int ex = 0; ex < 8; ++ex) {
-          const double x = (kx * 8 + ex + 0.5) * h, y = (ky * 8 + ey + 0.5) * h;
-          const double field = bump_field(x, y, xs, bp);
-          const double osc = bp.base + bp.amp * sxv[ex] * syv[ey];
-          blk[lane][8 * ey + ex] = osc * exp(bp.beta * field);
-        }
+          for (int ex = 0; ex < 8; ++ex) {
+            const double x = (kx * 8 + ex + 0.5) * h, y = (ky * 8 + ey + 0.5) * h;
+            const double field = bump_field<XS>(x, y, src, bp);
+            const double osc = bp.base + bp.amp * sxv[ex] * syv[ey];
+            blk[lane][8 * ey + ex] = osc * exp(bp.beta * field);
+          }
+      };
+      if (nb <= XL) {
+        for (int j = 0; j < nb; ++j) xl[j][lane] = xs[j];
+        regen(std::integral_constant<int, 64>{}, &xl[0][lane]);
+      } else {
+        regen(std::integral_constant<int, 1>{}, xs);
+      }
       double Sp[10];
       int32_t st = 0;
       small_cell_solve<8, double>(&blk[lane][0], 8, Sp, &st);
