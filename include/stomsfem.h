@@ -259,7 +259,9 @@ int stomsfem_coarse_solve_noalloc(int32_t ncx, int32_t ncy, int64_t nsamples, co
  * hold [nsamples][ncy*ncx][16].  S is not symmetric when oversample > 0;
  * oversample = 0 gives the unpacked stiffness of stomsfem_upscale.  The
  * oversampling ratio is M/m (2 for oversample = m/2).  Requires
- * 2 <= M <= 32 and M <= ncx*m, ncy*m (EINVAL otherwise).  Per-pair status
+ * 2 <= M <= 64 and M <= ncx*m, ncy*m (EINVAL otherwise); patches of 16 and
+ * 24 cells take the register-tiled kernel, others one wavefront per pair
+ * with the patch in LDS (104 KB at M = 64, one pair per CU there).  Per-pair status
  * ENOTSPD if a pivot is not positive or the corner values of the patch
  * solutions are singular (S undefined).  Asynchronous.
  *
@@ -701,7 +703,7 @@ int stomsfem_sgi_apply(stomsfem_model* model, const double* xi, int32_t nxi, int
  * Petrov-Galerkin stiffness (Sec. 2.2) in the parameters of the oversampled
  * patches, the setting of Sec. 5.3: mu, modes of side m + 2 oversample (from
  * stomsfem_local_kl with that side), 1 <= oversample <= m, m + 2 oversample
- * <= 32, square mesh.  An element's patch is moved inside the domain at the
+ * <= 64, square mesh.  An element's patch is moved inside the domain at the
  * edge, so along each axis the element sits at offset 0, oversample or
  * 2 oversample in it (first, interior, last elements); one table of the 16
  * entries (row-major [trial][test], as stomsfem_upscale_os) per pair of

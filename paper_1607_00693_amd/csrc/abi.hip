@@ -1143,7 +1143,7 @@ int stomsfem_kl_interp_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t ove
   if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m ||
       K < 1 || K > RI_KMAX || nnodes < RI_NN_MIN || nnodes > RI_NN_MAX || !(box > 0))
     return fail(STOMSFEM_EINVAL,
-                "kl_interp_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
+                "kl_interp_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 64 and <= the "
                 "domain, "
                 "1 <= K <= 4, 2 <= nnodes <= 9, box > 0");
   if (!device_ptr(mu) || !device_ptr(modes))
@@ -1175,7 +1175,7 @@ int stomsfem_kl_sgi_os_build(int32_t ncx, int32_t ncy, int32_t m, int32_t oversa
   if (ncx < 1 || ncx != ncy || m < 1 || o < 1 || o > m || !upscale_os_supports(m, o) || P > ncx * m || K < 1 ||
       K > RI_KMAX || level < 0 || level > SGI_LEVEL_MAX || !(box > 0))
     return fail(STOMSFEM_EINVAL,
-                "kl_sgi_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 32 and <= the "
+                "kl_sgi_os_build: need a square mesh, 1 <= oversample <= m, m + 2 oversample <= 64 and <= the "
                 "domain, 1 <= K <= 4, 0 <= level <= 5, box > 0");
   if (!device_ptr(mu) || !device_ptr(modes)) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: mu and modes on device");
   if (ncx * ncy > 65535) return fail(STOMSFEM_EINVAL, "kl_sgi_os_build: at most 65535 coarse elements");
@@ -1363,7 +1363,7 @@ int stomsfem_upscale_os(const stomsfem_batch* batch, int32_t oversample, void* s
   if (rc != STOMSFEM_OK) return rc;
   const stomsfem_batch& b = *batch;
   if (oversample < 0 || !upscale_os_supports(b.m, oversample))
-    return fail(STOMSFEM_EINVAL, "upscale_os: need oversample >= 0 and 2 <= m + 2*oversample <= 32");
+    return fail(STOMSFEM_EINVAL, "upscale_os: need oversample >= 0 and 2 <= m + 2*oversample <= 64");
   const int64_t M = b.m + 2 * (int64_t)oversample;
   if (M > (int64_t)b.ncx * b.m || M > (int64_t)b.ncy * b.m)
     return fail(STOMSFEM_EINVAL, "upscale_os: the oversampled patch is larger than the domain");

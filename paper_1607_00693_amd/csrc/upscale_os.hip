@@ -31,7 +31,7 @@ namespace stomsfem {
   } while (0)
 
 constexpr int OS_NV = 10;    // columns: f^0..2, corner tests 0..3, r^0..2
-constexpr int OS_MAXM = 32;  // largest patch (band half-width)
+constexpr int OS_MAXM = 64;  // largest patch (band half-width); 64-cell patches need 104 KB of LDS
 constexpr int OS_EP = 32;    // epilogue scratch per wavefront (doubles)
 
 struct OsArgs {
@@ -174,28 +174,32 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
     const bool inK = px >= cx && px <= cx + m && py >= cy && py <= cy + m;
     const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
     const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
-    if (lane <= B) {
-      const int t = lane;
-      double v = 0.0;
-      if (t == 0) v += (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
-      if (t == 1 && ix >= 1) v += -(aSW + aNW) * (1.0 / 6.0);
-      if (t == n - 1 && iy >= 1 && ix <= n - 2) v += -aSE * (1.0 / 3.0);
-      if (t == n && iy >= 1) v += -(aSW + aSE) * (1.0 / 6.0);
-      if (t == n + 1 && iy >= 1 && ix >= 1) v += -aSW * (1.0 / 3.0);
-      if (r - t >= 0) Wn[rs * WN + (rs - t >= 0 ? rs - t : rs - t + WN)] = v;
-    } else if (lane <= B + OS_NV) {
-      const int v = lane - B - 1;
-      double val = 0.0;
-      if (v < 3) {
-        if (nearb) val = Fb[ring_pos(ix, iy) * 3 + v];
-      } else if (v < 7) {
-        const int k = v - 3;  // corner k of K (CCW from lower left)
-        const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
-        val = (px == kpx && py == kpy) ? 1.0 : 0.0;
-      } else if (inK) {
-        val = Rk[(v - 7) * mm * mm + (py - cy) * mm + (px - cx)];
+    // slots u = 0..B: band entry at distance u; u = B+1..B+OS_NV: the ten
+    // right-hand sides (two rounds of the wavefront when B + OS_NV >= 64)
+    for (int u = lane; u <= B + OS_NV; u += 64) {
+      if (u <= B) {
+        const int t = u;
+        double v = 0.0;
+        if (t == 0) v += (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+        if (t == 1 && ix >= 1) v += -(aSW + aNW) * (1.0 / 6.0);
+        if (t == n - 1 && iy >= 1 && ix <= n - 2) v += -aSE * (1.0 / 3.0);
+        if (t == n && iy >= 1) v += -(aSW + aSE) * (1.0 / 6.0);
+        if (t == n + 1 && iy >= 1 && ix >= 1) v += -aSW * (1.0 / 3.0);
+        if (r - t >= 0) Wn[rs * WN + (rs - t >= 0 ? rs - t : rs - t + WN)] = v;
+      } else {
+        const int v = u - B - 1;
+        double val = 0.0;
+        if (v < 3) {
+          if (nearb) val = Fb[ring_pos(ix, iy) * 3 + v];
+        } else if (v < 7) {
+          const int k = v - 3;  // corner k of K (CCW from lower left)
+          const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
+          val = (px == kpx && py == kpy) ? 1.0 : 0.0;
+        } else if (inK) {
+          val = Rk[(v - 7) * mm * mm + (py - cy) * mm + (px - cx)];
+        }
+        R[rs * OS_NV + v] = val;
       }
-      R[rs * OS_NV + v] = val;
     }
   };
 
@@ -372,6 +376,23 @@ int upscale_os_waves(int m, int o) {
 
 bool upscale_os_supports(int m, int o) { return m >= 1 && o >= 0 && m + 2 * o >= 2 && m + 2 * o <= OS_MAXM; }
 
+// Launch with `lds` bytes of dynamic LDS; above 64 KB the kernel's limit is
+// raised first (once per instantiation).
+template <typename TA, int NQ>
+static hipError_t launch_os_nq(const OsArgs& args, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (lds > 64 * 1024) {
+    static size_t raised = 0;
+    if (raised < lds) {
+      hipError_t e = hipFuncSetAttribute((const void*)upscale_os_kernel<TA, NQ>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      raised = lds;
+    }
+  }
+  hipLaunchKernelGGL((upscale_os_kernel<TA, NQ>), grid, block, lds, st, args);
+  return hipGetLastError();
+}
+
 template <typename TA>
 static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
   const int M = args.up.m + 2 * args.o;
@@ -380,13 +401,11 @@ static hipError_t launch_os_t(const OsArgs& args, hipStream_t st) {
   const size_t lds = upscale_os_lds_bytes(args.up.m, args.o, waves);
   const int need = (M * (M + 1) / 2 + 63) / 64;
   const dim3 grid((unsigned)blocks), block(64 * waves);
-  if (need <= 3)
-    hipLaunchKernelGGL((upscale_os_kernel<TA, 3>), grid, block, lds, st, args);
-  else if (need <= 5)
-    hipLaunchKernelGGL((upscale_os_kernel<TA, 5>), grid, block, lds, st, args);
-  else
-    hipLaunchKernelGGL((upscale_os_kernel<TA, 9>), grid, block, lds, st, args);
-  return hipGetLastError();
+  if (need <= 3) return launch_os_nq<TA, 3>(args, grid, block, lds, st);
+  if (need <= 5) return launch_os_nq<TA, 5>(args, grid, block, lds, st);
+  if (need <= 9) return launch_os_nq<TA, 9>(args, grid, block, lds, st);
+  if (need <= 17) return launch_os_nq<TA, 17>(args, grid, block, lds, st);
+  return launch_os_nq<TA, 33>(args, grid, block, lds, st);
 }
 
 bool upscale_os_tiled_supports(int m, int o);

@@ -85,6 +85,26 @@ def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
     assert err <= STOL
 
 
+@pytest.mark.parametrize("m,o,ncx,ncy,N", [(10, 12, 4, 4, 1), (20, 11, 3, 3, 1), (16, 16, 3, 3, 1),
+                                           (32, 15, 3, 3, 1), (24, 20, 3, 3, 1), (32, 16, 3, 2, 1)])
+def test_large_patches_match_oracle(sm, orc, m, o, ncx, ncy, N):
+    # patches of 34 to 64 cells (the paper's Sec. 5.3 geometry has 64-cell
+    # patches: h = 2^-11, H/h = 32, ratio 2): one wavefront per pair with up to
+    # 104 KB of LDS, the trailing triangle in 17 or 33 entries per lane, the
+    # entering row's band and right-hand sides in two rounds of the wavefront
+    say(f"large patch m={m} o={o} (M={m + 2 * o}) {ncx}x{ncy} N={N}")
+    a_ref = W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1250 + m + o)
+    a = torch.from_numpy(a_ref).cuda()
+    status = torch.full((N, ncx * ncy), 99, dtype=torch.int32, device="cuda")
+    S = sm.upscale_os(a, ncx, ncy, m, o, status=status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    S_ref, _ = orc.upscale_os(a_ref, ncx, ncy, m, o)
+    err = s_relerr(S.cpu().numpy(), S_ref)
+    say(f"  S rel err {err:.2e}")
+    assert err <= STOL
+
+
 def test_float32_coefficients(sm, orc):
     m, o, ncx, ncy, N = 8, 4, 4, 4, 2
     a32 = torch.from_numpy(W.uniform_array((N, ncy * m, ncx * m), 0.2, 5.0, 1300)).float().cuda()
@@ -162,7 +182,7 @@ def test_coarse_pg_symmetric_input_matches_cholesky_path(sm, orc):
 
 
 def test_invalid_arguments(sm):
-    for m, o, nc in ((8, 13, 2), (8, -1, 2), (4, 8, 2)):  # patch > 32, negative, patch > domain
+    for m, o, nc in ((16, 25, 5), (8, -1, 2), (4, 8, 2)):  # patch > 64, negative, patch > domain
         a = torch.zeros((1, nc * m, nc * m), dtype=torch.float64, device="cuda")
         with pytest.raises(sm.StomsfemError) as e:
             sm.upscale_os(a, nc, nc, m, o)
