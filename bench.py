@@ -1080,6 +1080,72 @@ def measure_gauss(log, N=1024, n_trunc=64):
     return out
 
 
+def measure_gauss_paper_mesh(log, N=8):
+    """The Gaussian medium on the paper's own Sec. 5.3 mesh: h = 2^-11
+    (2048 x 2048 fine elements), H/h = 32 (64 x 64 coarse elements),
+    oversampling ratio 2 (patches of 2H = 64 fine cells, moved inside at the
+    edge) and the local KL on those patches with l2 = H, four terms, source
+    b = 2 + x1 x2.  N samples: field, projection, the oversampled
+    Petrov-Galerkin solve of every pair, and the interpolation of the
+    oversampled stiffness in the patch parameters (5 tensor nodes per
+    parameter, nine class tables) with the oversampled solve as fallback
+    outside the box; errors of S and of the coarse solution against the solve
+    of every pair."""
+    import math
+
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.GAUSS16
+    nc, m, o = 64, 32, 16
+    nfine, l2 = nc * m, 1.0 / nc
+    pairs = N * nc * nc
+    gl = sm.element_loads(nc, nc)
+    z, u = W.spectral_draws(N, wl.nterms, wl.seed + 11)
+    z, u = torch.from_numpy(z).cuda(), torch.from_numpy(u).cuda()
+    t_field = _timed(lambda: sm.coef_gauss(z, u, nfine, wl.l1, l2, with_beta=True), reps=2)
+    kap, beta = sm.coef_gauss(z, u, nfine, wl.l1, l2, with_beta=True)
+    mu, V, _ = sm.local_kl(m + 2 * o, 1.0 / nfine, wl.l1, l2, wl.kl_terms)
+    mu_d, V_d = torch.from_numpy(mu).cuda(), torch.from_numpy(V).cuda()
+    t_proj = _timed(lambda: sm.kl_project(beta, nc, m, mu_d, V_d, wl.box, oversample=o))
+    xi, out, count = sm.kl_project(beta, nc, m, mu_d, V_d, wl.box, oversample=o)
+    S_pl = sm.upscale_os(kap, nc, nc, m, o)
+    torch.cuda.synchronize()
+    t_pl = _timed(lambda: sm.upscale_os(kap, nc, nc, m, o, S=S_pl), reps=1)
+    log(f"paper mesh: oversampled solve of {pairs} pairs in {t_pl * 1e3:.1f} ms")
+    U_pl, _, _ = sm.coarse_solve_pg(S_pl, nc, nc, load=gl)
+    t0 = time.perf_counter()
+    model = sm.kl_interp_build(nc, nc, m, mu_d, V_d, 5, wl.box, oversample=o)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    S_i = torch.empty_like(S_pl)
+    t_i = _timed(lambda: sm.kl_interp_apply(model, xi, kap, S=S_i), reps=1)
+    _, nfb = sm.kl_interp_apply(model, xi, kap, S=S_i)
+    U_i, _, _ = sm.coarse_solve_pg(S_i, nc, nc, load=gl)
+    model.free()
+    sc = S_pl.abs().amax(dim=2)
+    ins = ~out.bool()
+    res = {"workload": f"Gaussian medium on the paper's Sec. 5.3 mesh: h = 2^-11 ({nfine}x{nfine}), {nc}x{nc} coarse "
+                       f"(H/h = {m}), oversampling ratio 2 (patches of {m + 2 * o} cells), local KL on the patches "
+                       f"with l2 = H, {wl.kl_terms} terms, b = 2 + x1 x2, {N} samples",
+           "pairs": pairs, "kept_fraction": float(mu.sum() / (m + 2 * o) ** 2),
+           "outside_rate": int(count.item()) / pairs,
+           "outside_rate_gaussian": 1.0 - math.erf(wl.box / math.sqrt(2.0)) ** wl.kl_terms,
+           "field_ms": t_field * 1e3, "projection_ms": t_proj * 1e3,
+           "oversampled_solve_ms": t_pl * 1e3, "oversampled_solve_pairs_per_s": pairs / t_pl,
+           "interpolation_nodes_5": {"table_rows": 9 * 5 ** 4, "build_s": t_build, "apply_ms": t_i * 1e3,
+                                     "pairs_per_s": pairs / t_i, "ratio_vs_oversampled_solve": t_pl / t_i,
+                                     "fallback_pairs": nfb,
+                                     "max_S_rel_err_interpolated_pairs": float(((S_i - S_pl).abs().amax(dim=2)
+                                                                                / sc)[ins].max().item()),
+                                     "max_coarse_rel_err": float((torch.linalg.norm(U_i - U_pl, dim=1) /
+                                                                  torch.linalg.norm(U_pl, dim=1)).max().item())}}
+    log(f"gaussian medium, paper mesh: {res}")
+    return res
+
+
 def measure_accelerations(log):
     """Reduced basis (8x8 coarse, H/h = 8, 256 training samples, r <= 8,
     16384 online samples, FP32 coefficients) and learned surrogate (same mesh,
@@ -1192,7 +1258,7 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
                          "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, collocation, "
-                         "two_level, gauss); "
+                         "two_level, gauss, gauss_paper_mesh); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters in a profile)")
@@ -1390,6 +1456,9 @@ def main():
         if want("gauss"):
             lg("Gaussian medium and local KL")
             out["gaussian_local_kl"] = measure_gauss(lg)
+        if want("gauss_paper_mesh"):
+            lg("Gaussian medium on the paper's h = 2^-11 mesh with 64-cell oversampled patches")
+            out["gaussian_paper_mesh"] = measure_gauss_paper_mesh(lg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
