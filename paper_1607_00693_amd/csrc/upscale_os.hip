@@ -16,8 +16,11 @@
 // C = Psi^{-T} makes phi^i = sum_j C[i][j] psi^j nodal at K's corners, and
 // S[l][l'] = int_K a grad phi^l . grad p^l' = (C A)[l][l'].
 //
-// One wavefront per pair: the patch coefficients, the (M+1) x (M+1) circular
-// band window and the ten right-hand-side columns live in LDS; the rank-1
+// One wavefront per pair: the (M+1) x (M+1) circular band window and the ten
+// right-hand-side columns live in LDS (11.6 KB at M = 32, 39 KB at M = 64, so
+// several pairs share a CU); the patch coefficients stay in global memory,
+// the four around the next entering row's node are fetched a pivot ahead,
+// and the entering row, its lifts and r^l are formed from them; the rank-1
 // update of each pivot is spread over the 64 lanes; no workgroup barriers.
 #include "common.h"
 
@@ -49,9 +52,9 @@ __host__ __device__ inline int os_origin(int k, int m, int o, int nf) {
   return x0 < 0 ? 0 : x0;
 }
 
-__host__ __device__ inline int os_lds_doubles(int m, int M) {
+__host__ __device__ inline int os_lds_doubles(int, int M) {
   const int WN = M + 1;
-  return M * M + WN * WN + WN * OS_NV + OS_EP + 3 * (m + 1) * (m + 1) + 3 * 4 * M;
+  return WN * WN + WN * OS_NV + OS_EP;
 }
 
 // x mod w for 0 <= x < 2w
@@ -66,8 +69,9 @@ __device__ __forceinline__ double os_pc(int l, int px, int py, double rs) {
 }
 
 // r^l = (K^K p^l) at patch node (px, py): the elements of K around the node
-// (SW, SE, NW, NE see it as local node 2, 3, 1, 0), each a_e K_ref p^l_e.
-__device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, int M, const double* Ap) {
+// (SW, SE, NW, NE see it as local node 2, 3, 1, 0), each a_e K_ref p^l_e;
+// q4 = the coefficients of the four elements around the node (SW, SE, NW, NE).
+__device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, const double* q4) {
   const double rm = 1.0 / m;
   double v = 0.0;
 #pragma unroll
@@ -81,7 +85,7 @@ __device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, int
       const int bx = ex + (be == 1 || be == 2), by = ey + (be >= 2);
       s += kref(al, be) * os_pc(l, bx - cx, by - cy, rm);
     }
-    v += Ap[ey * M + ex] * s;
+    v += q4[e] * s;
   }
   return v;
 }
@@ -92,12 +96,9 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   extern __shared__ double smem[];
   const int m = args.up.m, o = args.o, M = m + 2 * o, n = M - 1, NI = n * n, B = M, WN = B + 1;
   const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* Ap = smem + wave * os_lds_doubles(m, M);  // patch coefficients [M][M]
-  double* Wn = Ap + M * M;                          // window, (r, c) at [r % WN][c % WN]
-  double* R = Wn + WN * WN;                         // right-hand sides, row r at [r % WN][OS_NV]
-  double* Ep = R + WN * OS_NV;                      // epilogue scratch
-  double* Rk = Ep + OS_EP;                          // r^l at K's nodes [3][(m+1)^2]
-  double* Fb = Rk + 3 * (m + 1) * (m + 1);          // lifts f^v of the rows next to the boundary [M*M][3]
+  double* Wn = smem + wave * os_lds_doubles(m, M);  // window, (r, c) at [r % WN][c % WN]
+  double* R = Wn + WN * WN;                          // right-hand sides, row r at [r % WN][OS_NV]
+  double* Ep = R + WN * OS_NV;                       // epilogue scratch
   const int64_t io = (int64_t)blockIdx.x * waves + wave;  // output slot
   if (io >= (args.list ? args.nlist : args.up.npairs)) return;  // the whole wavefront; no workgroup barrier follows
   const int64_t p = args.list ? args.list[io] : io;
@@ -107,51 +108,18 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   const int nfx = ncx * m, nfy = ncy * m;
   const int x0 = os_origin(kx, m, o, nfx), y0 = os_origin(ky, m, o, nfy);
   const int cx = kx * m - x0, cy = ky * m - y0;  // K's lower-left node in patch nodes
-  const TA* a = (const TA*)args.up.a + s * (int64_t)nfy * nfx;
-  for (int i = lane; i < M * M; i += 64) Ap[i] = ld(a, (int64_t)(y0 + i / M) * nfx + x0 + i % M);
+  const TA* a = (const TA*)args.up.a + s * (int64_t)nfy * nfx + (int64_t)y0 * nfx + x0;  // patch origin
   for (int i = lane; i < WN * WN; i += 64) Wn[i] = 0.0;
   for (int i = lane; i < WN * OS_NV; i += 64) R[i] = 0.0;
   OS_WAVE_SYNC();
-  const int mm = m + 1;
-  for (int i = lane; i < 3 * mm * mm; i += 64) {
-    const int l = i / (mm * mm), id = i - l * mm * mm;
-    Rk[i] = os_rK(l, cx + id % mm, cy + id / mm, cx, cy, m, M, Ap);
-  }
   const double rM = 1.0 / M;
-  // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q) for the rows
-  // next to the patch boundary, indexed by the row's position on that ring
-  const int nring = n == 1 ? 1 : 4 * (n - 1);
-  for (int i = lane; i < 3 * nring; i += 64) {
-    const int v = i / nring, b = i - v * nring;
-    int ix, iy;  // ring position b -> node: bottom, right, top, left (corners once)
-    if (n == 1) { ix = 0; iy = 0; }
-    else if (b < n - 1) { ix = b; iy = 0; }
-    else if (b < 2 * (n - 1)) { ix = n - 1; iy = b - (n - 1); }
-    else if (b < 3 * (n - 1)) { ix = n - 1 - (b - 2 * (n - 1)); iy = n - 1; }
-    else { ix = 0; iy = n - 1 - (b - 3 * (n - 1)); }
-    const int px = ix + 1, py = iy + 1;
-    const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
-    const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
-    const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-    const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
-    const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0), -(aSW + aSE) * (1.0 / 6.0),
-                          -(aNW + aNE) * (1.0 / 6.0), -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
-                          -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
-    double val = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int qx = px + dxs[q], qy = py + dys[q];
-      if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * os_pc(v, qx, qy, rM);
-    }
-    Fb[b * 3 + v] = val;
-  }
-  // ring position of an interior node next to the boundary
-  auto ring_pos = [&](int ix, int iy) {
-    if (n == 1) return 0;
-    if (iy == 0) return ix;
-    if (ix == n - 1) return (n - 1) + iy;
-    if (iy == n - 1) return 2 * (n - 1) + (n - 1 - ix);
-    return 3 * (n - 1) + (n - 1 - iy);
+  // coefficients of the four patch elements around interior node (ix, iy):
+  // SW, SE, NW, NE (every lane loads the same four values)
+  auto load_quad = [&](int ix, int iy, double* q4) {
+    q4[0] = ld(a, (int64_t)iy * nfx + ix);
+    q4[1] = ld(a, (int64_t)iy * nfx + ix + 1);
+    q4[2] = ld(a, (int64_t)(iy + 1) * nfx + ix);
+    q4[3] = ld(a, (int64_t)(iy + 1) * nfx + ix + 1);
   };
   // this lane's entries (io >= ko) of the B x B trailing triangle
   int tik[NQ];
@@ -164,16 +132,16 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   }
   OS_WAVE_SYNC();
 
-  // original row r = iy n + ix of K_II, in window slot rs (lanes 0..B: band
-  // entry at distance lane) and its ten right-hand sides (lanes B+1..B+10)
-  auto insert_row = [&](int r, int rs, int ix, int iy) {
+  // original row r = iy n + ix of K_II, in window slot rs (slots 0..B: band
+  // entry at distance u; B+1..B+OS_NV: its ten right-hand sides), from the
+  // coefficients q4 of the four elements around its node
+  auto insert_row = [&](int r, int rs, int ix, int iy, const double* q4) {
     const int px = ix + 1, py = iy + 1;
     // wave-uniform: only rows next to the patch boundary have lifts, only
     // nodes of K carry r^l
     const bool nearb = ix == 0 || ix == n - 1 || iy == 0 || iy == n - 1;
     const bool inK = px >= cx && px <= cx + m && py >= cy && py <= cy + m;
-    const double aSW = Ap[iy * M + ix], aSE = Ap[iy * M + ix + 1];
-    const double aNW = Ap[(iy + 1) * M + ix], aNE = Ap[(iy + 1) * M + ix + 1];
+    const double aSW = q4[0], aSE = q4[1], aNW = q4[2], aNE = q4[3];
     // slots u = 0..B: band entry at distance u; u = B+1..B+OS_NV: the ten
     // right-hand sides (two rounds of the wavefront when B + OS_NV >= 64)
     for (int u = lane; u <= B + OS_NV; u += 64) {
@@ -190,13 +158,26 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
         const int v = u - B - 1;
         double val = 0.0;
         if (v < 3) {
-          if (nearb) val = Fb[ring_pos(ix, iy) * 3 + v];
+          // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q)
+          if (nearb) {
+            const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+            const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+            const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0),
+                                  -(aSW + aSE) * (1.0 / 6.0), -(aNW + aNE) * (1.0 / 6.0),
+                                  -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
+                                  -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int qx = px + dxs[q], qy = py + dys[q];
+              if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * os_pc(v, qx, qy, rM);
+            }
+          }
         } else if (v < 7) {
           const int k = v - 3;  // corner k of K (CCW from lower left)
           const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
           val = (px == kpx && py == kpy) ? 1.0 : 0.0;
         } else if (inK) {
-          val = Rk[(v - 7) * mm * mm + (py - cy) * mm + (px - cx)];
+          val = os_rK(v - 7, px, py, cx, cy, m, q4);
         }
         R[rs * OS_NV + v] = val;
       }
@@ -204,23 +185,34 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   };
 
   const int r0 = B < NI ? B : NI;
-  for (int r = 0; r < r0; ++r) insert_row(r, r, r % n, r / n);
+  for (int r = 0; r < r0; ++r) {
+    double q4[4];
+    load_quad(r % n, r / n, q4);
+    insert_row(r, r, r % n, r / n, q4);
+  }
   OS_WAVE_SYNC();
   // the row entering at pivot j is j + B: slot (j + B) mod WN = (j - 1) mod WN,
   // node (eix, eiy), both advanced incrementally
   int eix = B % n, eiy = B / n;
+  double q4n[4] = {0.0, 0.0, 0.0, 0.0};  // the next entering row's coefficients, fetched a pivot ahead
+  if (B < NI) load_quad(eix, eiy, q4n);
   // lanes 0..20 accumulate Y[jv][tv] = f^jv . K_II^{-1} (test column 3 + tv)
   const int jv = lane / 7, tv = 3 + lane % 7;
   double yacc = 0.0;
   bool bad = false;
   for (int j = 0, jj = 0; j < NI; ++j, jj = jj + 1 == WN ? 0 : jj + 1) {
     if (j + B < NI) {
-      insert_row(j + B, jj == 0 ? WN - 1 : jj - 1, eix, eiy);
-      OS_WAVE_SYNC();
-      if (++eix == n) {
-        eix = 0;
-        ++eiy;
+      const double q4[4] = {q4n[0], q4n[1], q4n[2], q4n[3]};
+      int nix = eix + 1, niy = eiy;
+      if (nix == n) {
+        nix = 0;
+        ++niy;
       }
+      if (j + B + 1 < NI) load_quad(nix, niy, q4n);
+      insert_row(j + B, jj == 0 ? WN - 1 : jj - 1, eix, eiy, q4);
+      OS_WAVE_SYNC();
+      eix = nix;
+      eiy = niy;
     }
     const double d = Wn[jj * WN + jj];
     bad = bad || !(d > 0.0);
@@ -258,9 +250,17 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   for (int id = lane; id < (m + 1) * (m + 1); id += 64) {
     const int ax = cx + id % (m + 1), ay = cy + id / (m + 1);
     if (!(ax == 0 || ax == M || ay == 0 || ay == M)) continue;
+    // coefficients of the patch elements around the node (0 outside the
+    // patch; os_rK reads only elements of K)
+    double q4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = ax - 1 + (e & 1), ey = ay - 1 + (e >> 1);
+      q4[e] = (ex >= 0 && ex < M && ey >= 0 && ey < M) ? ld(a, (int64_t)ey * nfx + ex) : 0.0;
+    }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      const double rl = Rk[l * mm * mm + id];
+      const double rl = os_rK(l, ax, ay, cx, cy, m, q4);
 #pragma unroll
       for (int jb = 0; jb < 3; ++jb) bt[3 * jb + l] += os_pc(jb, ax, ay, rM) * rl;
     }
