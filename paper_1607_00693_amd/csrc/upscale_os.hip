@@ -17,11 +17,12 @@
 // S[l][l'] = int_K a grad phi^l . grad p^l' = (C A)[l][l'].
 //
 // One wavefront per pair: the (M+1) x (M+1) circular band window and the ten
-// right-hand-side columns live in LDS (11.6 KB at M = 32, 39 KB at M = 64, so
-// several pairs share a CU); the patch coefficients stay in global memory,
-// the four around the next entering row's node are fetched a pivot ahead,
-// and the entering row, its lifts and r^l are formed from them; the rank-1
-// update of each pivot is spread over the 64 lanes; no workgroup barriers.
+// right-hand-side columns live in LDS (with the lifts, 14.6 KB at M = 32; 39 KB
+// at M = 64, so several pairs share a CU); the patch coefficients stay in
+// global memory, the four around the next entering row's node are fetched a
+// pivot ahead, and the entering row and its r^l are formed from them; the
+// rank-1 update of each pivot is spread over the 64 lanes; no workgroup
+// barriers.
 #include "common.h"
 
 namespace stomsfem {
@@ -52,9 +53,17 @@ __host__ __device__ inline int os_origin(int k, int m, int o, int nf) {
   return x0 < 0 ? 0 : x0;
 }
 
+// Patches of up to OS_TABM cells (the kernels with at most 9 trailing entries
+// per lane) keep the lifts of the rows next to the patch boundary in LDS,
+// formed once per pair (3 KB at 32 cells), and form r^l of an entering row in
+// closed form (os_rK_cf): the kernel then stays within 128 registers (four
+// wavefronts per SIMD) and 14.6 KB of LDS per pair at 32 cells (ten pairs
+// per CU).  Larger patches form both on the fly with the general os_rK.
+constexpr int OS_TABM = 33;
+__host__ __device__ inline bool os_tables(int M) { return M <= OS_TABM; }
 __host__ __device__ inline int os_lds_doubles(int, int M) {
   const int WN = M + 1;
-  return WN * WN + WN * OS_NV + OS_EP;
+  return WN * WN + WN * OS_NV + OS_EP + (os_tables(M) ? 3 * 4 * M : 0);
 }
 
 // x mod w for 0 <= x < 2w
@@ -90,6 +99,48 @@ __device__ inline double os_rK(int l, int px, int py, int cx, int cy, int m, con
   return v;
 }
 
+// The same r^l in closed form.  On element e of K at (xe, ye) = its lower-left
+// node relative to K's, p^l is bilinear in the element's local coordinates
+// (s, t): A + B s + C t + D s t with (times m^2)
+//   l = 0: B = -(m - ye), C = -(m - xe), D = 1;
+//   l = 1: B =  (m - ye), C = -xe,       D = -1;
+//   l = 2: B =  ye,       C = xe,        D = 1,
+// and K_ref annihilates constants, so row al of K_ref applied to its corner
+// values is B sig_s(al) + C sig_t(al) + D sig_st(al), with sig_s = K_ref row
+// sums over the corners with s = 1, sig_t over t = 1, sig_st over s = t = 1:
+// (-1/2, -1/2, -1/3), (1/2, -1/2, -1/6), (1/2, 1/2, 2/3), (-1/2, 1/2, -1/6)
+// for al = 0..3.
+__device__ inline double os_rK_cf(int l, int px, int py, int cx, int cy, int m, const double* q4) {
+  const double im2 = 1.0 / ((double)m * m);
+  double v = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ex = px - 1 + (e & 1), ey = py - 1 + (e >> 1);
+    if (ex < cx || ex >= cx + m || ey < cy || ey >= cy + m) continue;
+    const double xe = ex - cx, ye = ey - cy;
+    // local index of the node in element e: SW -> 2, SE -> 3, NW -> 1, NE -> 0
+    const double ss = (e == 0 || e == 2) ? 0.5 : -0.5;            // al = 2, 1 : 1/2; al = 3, 0 : -1/2
+    const double st = (e == 0 || e == 1) ? 0.5 : -0.5;            // al = 2, 3 : 1/2; al = 1, 0 : -1/2
+    const double sst = e == 0 ? 2.0 / 3.0 : (e == 3 ? -1.0 / 3.0 : -1.0 / 6.0);
+    double B, C, D;
+    if (l == 0) {
+      B = -(m - ye);
+      C = -(m - xe);
+      D = 1.0;
+    } else if (l == 1) {
+      B = m - ye;
+      C = -xe;
+      D = -1.0;
+    } else {
+      B = ye;
+      C = xe;
+      D = 1.0;
+    }
+    v += q4[e] * ((B * ss + C * st + D * sst) * im2);
+  }
+  return v;
+}
+
 // NQ >= B (B + 1) / (2 * 64): trailing-triangle entries per lane.
 template <typename TA, int NQ>
 __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
@@ -99,6 +150,8 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   double* Wn = smem + wave * os_lds_doubles(m, M);  // window, (r, c) at [r % WN][c % WN]
   double* R = Wn + WN * WN;                          // right-hand sides, row r at [r % WN][OS_NV]
   double* Ep = R + WN * OS_NV;                       // epilogue scratch
+  constexpr bool tab = NQ <= 9;  // with M <= 33 exactly (os_tables)
+  double* Fb = Ep + OS_EP;                           // lifts of the rows next to the boundary [ring][3] (tab)
   const int64_t io = (int64_t)blockIdx.x * waves + wave;  // output slot
   if (io >= (args.list ? args.nlist : args.up.npairs)) return;  // the whole wavefront; no workgroup barrier follows
   const int64_t p = args.list ? args.list[io] : io;
@@ -121,6 +174,57 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
     q4[2] = ld(a, (int64_t)(iy + 1) * nfx + ix);
     q4[3] = ld(a, (int64_t)(iy + 1) * nfx + ix + 1);
   };
+  // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q), for the row
+  // of interior node (ix, iy) with coefficients q4
+  auto lift = [&](int v, int ix, int iy, const double* q4) {
+    const int px = ix + 1, py = iy + 1;
+    const double aSW = q4[0], aSE = q4[1], aNW = q4[2], aNE = q4[3];
+    const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+    const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+    const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0), -(aSW + aSE) * (1.0 / 6.0),
+                          -(aNW + aNE) * (1.0 / 6.0), -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
+                          -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
+    double val = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int qx = px + dxs[q], qy = py + dys[q];
+      if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * os_pc(v, qx, qy, rM);
+    }
+    return val;
+  };
+  // coefficients of the patch elements around node (ax, ay), 0 outside the
+  // patch (os_rK reads only elements of K)
+  auto quad_at = [&](int ax, int ay, double* q4) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = ax - 1 + (e & 1), ey = ay - 1 + (e >> 1);
+      q4[e] = (ex >= 0 && ex < M && ey >= 0 && ey < M) ? ld(a, (int64_t)ey * nfx + ex) : 0.0;
+    }
+  };
+  // ring position of an interior node next to the boundary: bottom, right,
+  // top, left (corners once)
+  const int nring = n == 1 ? 1 : 4 * (n - 1);
+  auto ring_pos = [&](int ix, int iy) {
+    if (n == 1) return 0;
+    if (iy == 0) return ix;
+    if (ix == n - 1) return (n - 1) + iy;
+    if (iy == n - 1) return 2 * (n - 1) + (n - 1 - ix);
+    return 3 * (n - 1) + (n - 1 - iy);
+  };
+  if constexpr (tab) {
+    for (int i = lane; i < 3 * nring; i += 64) {
+      const int v = i / nring, b = i - v * nring;
+      int ix, iy;
+      if (n == 1) { ix = 0; iy = 0; }
+      else if (b < n - 1) { ix = b; iy = 0; }
+      else if (b < 2 * (n - 1)) { ix = n - 1; iy = b - (n - 1); }
+      else if (b < 3 * (n - 1)) { ix = n - 1 - (b - 2 * (n - 1)); iy = n - 1; }
+      else { ix = 0; iy = n - 1 - (b - 3 * (n - 1)); }
+      double q4[4];
+      load_quad(ix, iy, q4);
+      Fb[b * 3 + v] = lift(v, ix, iy, q4);
+    }
+  }
   // this lane's entries (io >= ko) of the B x B trailing triangle
   int tik[NQ];
 #pragma unroll
@@ -158,26 +262,17 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
         const int v = u - B - 1;
         double val = 0.0;
         if (v < 3) {
-          // f^v = -sum over the boundary neighbours q of K[r][q] g^v(q)
           if (nearb) {
-            const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-            const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
-            const double ks[8] = {-(aSW + aNW) * (1.0 / 6.0), -(aSE + aNE) * (1.0 / 6.0),
-                                  -(aSW + aSE) * (1.0 / 6.0), -(aNW + aNE) * (1.0 / 6.0),
-                                  -aSW * (1.0 / 3.0),         -aSE * (1.0 / 3.0),
-                                  -aNW * (1.0 / 3.0),         -aNE * (1.0 / 3.0)};
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int qx = px + dxs[q], qy = py + dys[q];
-              if (qx == 0 || qx == M || qy == 0 || qy == M) val -= ks[q] * os_pc(v, qx, qy, rM);
-            }
+            if constexpr (tab) val = Fb[ring_pos(ix, iy) * 3 + v];
+            else val = lift(v, ix, iy, q4);
           }
         } else if (v < 7) {
           const int k = v - 3;  // corner k of K (CCW from lower left)
           const int kpx = cx + ((k == 1 || k == 2) ? m : 0), kpy = cy + (k >= 2 ? m : 0);
           val = (px == kpx && py == kpy) ? 1.0 : 0.0;
         } else if (inK) {
-          val = os_rK(v - 7, px, py, cx, cy, m, q4);
+          if constexpr (tab) val = os_rK_cf(v - 7, px, py, cx, cy, m, q4);
+          else val = os_rK(v - 7, px, py, cx, cy, m, q4);
         }
         R[rs * OS_NV + v] = val;
       }
@@ -250,14 +345,8 @@ __global__ __launch_bounds__(256) void upscale_os_kernel(OsArgs args) {
   for (int id = lane; id < (m + 1) * (m + 1); id += 64) {
     const int ax = cx + id % (m + 1), ay = cy + id / (m + 1);
     if (!(ax == 0 || ax == M || ay == 0 || ay == M)) continue;
-    // coefficients of the patch elements around the node (0 outside the
-    // patch; os_rK reads only elements of K)
     double q4[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int ex = ax - 1 + (e & 1), ey = ay - 1 + (e >> 1);
-      q4[e] = (ex >= 0 && ex < M && ey >= 0 && ey < M) ? ld(a, (int64_t)ey * nfx + ex) : 0.0;
-    }
+    quad_at(ax, ay, q4);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const double rl = os_rK(l, ax, ay, cx, cy, m, q4);
