@@ -1018,9 +1018,11 @@ static hipError_t launch_coarse_any(int ncx, int ncy, int64_t N, const double* S
       } else if (pg) {
         hipLaunchKernelGGL((coarse_solve_kernel<4, true, COARSE_THREADS>), grid, block, lds, st, a);
       } else if (use_blocked(ncx, pg)) {
-        static const hipError_t attr = hipFuncSetAttribute(
-            (const void*)coarse_blocked_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)coarse_blocked_lds_bytes(CB_BMAX));
+        // the kernel's dynamic-LDS limit raised before each launch (a host call;
+        // it then holds on whichever device is current)
+        const hipError_t attr = hipFuncSetAttribute((const void*)coarse_blocked_kernel,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)coarse_blocked_lds_bytes(CB_BMAX));
         if (attr != hipSuccess) return attr;
         hipLaunchKernelGGL(coarse_blocked_kernel, grid, dim3(CB_TH), lds, st, a);
       } else {

@@ -466,17 +466,14 @@ int upscale_os_waves(int m, int o) {
 bool upscale_os_supports(int m, int o) { return m >= 1 && o >= 0 && m + 2 * o >= 2 && m + 2 * o <= OS_MAXM; }
 
 // Launch with `lds` bytes of dynamic LDS; above 64 KB the kernel's limit is
-// raised first (once per instantiation).
+// raised first (a host call before each such launch, so it holds on whichever
+// device is current).
 template <typename TA, int NQ>
 static hipError_t launch_os_nq(const OsArgs& args, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
   if (lds > 64 * 1024) {
-    static size_t raised = 0;
-    if (raised < lds) {
-      hipError_t e = hipFuncSetAttribute((const void*)upscale_os_kernel<TA, NQ>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      raised = lds;
-    }
+    hipError_t e = hipFuncSetAttribute((const void*)upscale_os_kernel<TA, NQ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((upscale_os_kernel<TA, NQ>), grid, block, lds, st, args);
   return hipGetLastError();
