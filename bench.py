@@ -1345,6 +1345,26 @@ def main():
     print(f"[bench] {args.steps} steps: {ms:.2f} ms/step (gen {t_gen:.2f}, upscale {t_up:.2f}, coarse {t_co:.2f} ms),"
           f" non-OK pairs {bad}", file=sys.stderr, flush=True)
 
+    # the same step captured once in a HIP graph (an execution plan of one
+    # stage: coefficient generation, upscaling, coarse solve and QoI) and
+    # replayed: its time per step and its QoI against the eager step's
+    qm_e = qm.clone()
+    qm_p = torch.empty_like(qm)
+    plan = stomsfem.plan_create([stomsfem.make_stage(wl.nc, wl.m, xi, bumps=stomsfem.bump_family(wl),
+                                                     qoi_mean=qm_p)])
+    plan.launch(-1, stream)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(3):
+        plan.launch(-1, stream)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    t_graph = ev[0].elapsed_time(ev[1]) / 3
+    graph = {"ms_per_step": t_graph, "pairs_per_s": pairs / (t_graph * 1e-3),
+             "qoi_mean_equal_to_eager": bool(torch.equal(qm_p, qm_e))}
+    plan.free()
+    print(f"[bench] graph-captured step: {graph}", file=sys.stderr, flush=True)
+
     out = {
         "metric": "upscaled (patch x sample)/s, plain FP64 path",
         "value": pairs / (ms * 1e-3),
@@ -1364,6 +1384,7 @@ def main():
             "nc": wl.nc, "m": wl.m, "nsamples": wl.nsamples, "pairs": pairs,
         },
         "kernel_ms": {"coef_bumps": t_gen, "upscale": t_up, "coarse_solve_qoi": t_co},
+        "graph_captured_step": graph,
         "tuning": tuning,
         "roofline": {
             "bound": "alu",
