@@ -91,3 +91,63 @@ def rb_online_S(model: dict, a_blk: np.ndarray) -> np.ndarray:
     """Packed S_rb[10] by the element sum of eq. stiffness_local."""
     phi = rb_online_phi(model, a_blk)
     return core.pack(core.energy_S(a_blk, phi))
+
+
+# --- reduced basis on oversampled patches (Secs. 2.2 and 3.2 together; the
+# high-contrast example of Sec. 5.2 combines them with the Petrov-Galerkin
+# stiffness) -----------------------------------------------------------------
+# The cell problems of element K are posed on its oversampled patch (side
+# M = m + 2o, moved inside the domain at the edge, core.os_origin) with the
+# bilinear data of the patch corners; the reduced basis of the patch is built
+# from those patch solutions exactly as above (rb_offline on the patch
+# blocks).  Online, the reduced patch solutions psi^j (j = 0..3, psi^3 = 1 -
+# sum) give, as in the plain oversampled stiffness: Psi[k][j] = psi^j at the
+# corners x_k of K (CCW from the lower left), C = Psi^{-T}, the multiscale
+# trial functions phi^i = sum_j C[i][j] psi^j on K, and
+#   S16[l][l'] = int_K a grad phi^l . grad p^l'   (p^l': K's bilinear functions)
+# by the element sum over K.
+
+
+def patch_block(a: np.ndarray, K: int, ncx: int, ncy: int, m: int, o: int) -> np.ndarray:
+    """The oversampled patch [M][M] of element K of one sample's field a."""
+    nfx, nfy = ncx * m, ncy * m
+    kx, ky = K % ncx, K // ncx
+    x0, y0 = core.os_origin(kx, m, o, nfx), core.os_origin(ky, m, o, nfy)
+    M = m + 2 * o
+    return a[y0:y0 + M, x0:x0 + M]
+
+
+def rb_os_online_S16(model: dict, a_patch: np.ndarray, m: int, cx: int, cy: int) -> np.ndarray:
+    """S16 [4][4] (row: trial l, column: bilinear test l') of the element whose
+    lower-left node is patch node (cx, cy), from the reduced patch solutions."""
+    psi = rb_online_phi(model, a_patch)                     # [4][M+1][M+1]
+    kx = [cx, cx + m, cx + m, cx]
+    ky = [cy, cy, cy + m, cy + m]
+    Psi = np.array([[psi[j, ky[k], kx[k]] for j in range(4)] for k in range(4)])
+    C = np.linalg.inv(Psi.T)
+    phiK = np.einsum("ij,jyx->iyx", C, psi[:, cy:cy + m + 1, cx:cx + m + 1])
+    t = np.arange(m + 1) / m
+    X, Y = np.meshgrid(t, t)
+    test = np.stack([(1 - X) * (1 - Y), X * (1 - Y), X * Y, (1 - X) * Y])
+    return core.energy_S(np.ascontiguousarray(a_patch[cy:cy + m, cx:cx + m]), phiK, test)
+
+
+def rb_os(a_train: np.ndarray, a: np.ndarray, ncx: int, ncy: int, m: int, o: int, r_max: int = 8,
+          tail_tol: float = 1e-6):
+    """Per element: offline on the training fields' patches, online S16 for
+    every sample of a.  Returns (S16 [N][ncy*ncx][16], r [ncy*ncx])."""
+    N = a.shape[0]
+    Mc = ncx * ncy
+    S = np.zeros((N, Mc, 16))
+    rs = np.zeros(Mc, dtype=np.int64)
+    for K in range(Mc):
+        blocks = np.stack([patch_block(a_train[s], K, ncx, ncy, m, o) for s in range(a_train.shape[0])])
+        model = rb_offline(np.ascontiguousarray(blocks), r_max, tail_tol)
+        rs[K] = model["r"]
+        kx, ky = K % ncx, K // ncx
+        cx = kx * m - core.os_origin(kx, m, o, ncx * m)
+        cy = ky * m - core.os_origin(ky, m, o, ncy * m)
+        for s in range(N):
+            S[s, K] = rb_os_online_S16(model, np.ascontiguousarray(patch_block(a[s], K, ncx, ncy, m, o)), m, cx,
+                                       cy).ravel()
+    return S, rs
