@@ -11,7 +11,8 @@ Offline, per coarse element (patch):
   5. E = R^T R (Cholesky), SVD of R Psi (the KL expansion in that inner
      product);
   6. r = min(r_max, smallest r whose relative tail
-     sqrt(sum_{q>r} s_q^2 / sum_q s_q^2) <= tail_tol);
+     sqrt(sum_{q>r} s_q^2 / sum_q s_q^2) <= tail_tol, number of s_q^2 above
+     RANK_TOL s_0^2: the numerical rank of the snapshots);
   7. modes Z = R^{-1} U_r, so that Z^T E Z = I.
 Online, per (patch, sample): the Galerkin system of eq. localRBsystem,
   A = Z^T K_II(a) Z,  F^l = -Z^T (K_II(a) phibar^l + K_IB(a) g^l),
@@ -27,6 +28,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import core
+
+RANK_TOL = 1e-12
 
 
 def _interior(phi_full: np.ndarray) -> np.ndarray:
@@ -66,6 +69,10 @@ def rb_offline(a_train: np.ndarray, r_max: int = 8, tail_tol: float = 1e-6, bc: 
     if r is None:
         r = len(sig)
     r = min(r, r_max, len(sig))
+    # numerical rank: modes whose eigenvalue sigma^2 is at or below 1e-12 of
+    # the largest are rounding, not part of the snapshot space
+    rank = int(np.sum(sig**2 > RANK_TOL * sig[0] ** 2)) if len(sig) and sig[0] > 0 else 0
+    r = min(r, rank)
     Z = np.linalg.solve(R, U[:, :r])                                      # R^{-1} U_r
     return {"m": m, "r": r, "Z": Z, "phibar": phibar, "abar": abar, "sigma": sig, "bc": bc}
 

@@ -1,7 +1,7 @@
 """Pins of the reduced basis on oversampled patches (oracle): the reduced
 Petrov-Galerkin stiffness of a training sample, whose patch solutions lie in
 the reduced space when no mode is truncated, equals the oversampled solve of
-that sample (core.upscale_os); with all modes (3 N_train >= interior
+that sample (core.upscale_os); with all modes (3 (N_train - 1) >= interior
 unknowns) it equals it for any sample; without oversampling and with all modes
 it is the plain element stiffness of the C oracle; rows and columns sum to
 zero at any rank; on a medium with few local variables the error falls by
@@ -25,9 +25,10 @@ def test_training_samples_are_reproduced():
 
 
 def test_full_rank_basis_matches_the_oversampled_solve():
-    # patch of 8 cells: 49 interior unknowns, 17 training samples give 51 snapshots
+    # patch of 8 cells: 49 interior unknowns; the centred snapshots of 18
+    # training samples span 3 * 17 = 51 >= 49 directions
     m, o, nc = 4, 2, 3
-    a_tr = W.uniform_array((17, nc * m, nc * m), 0.3, 4.0, 3102)
+    a_tr = W.uniform_array((18, nc * m, nc * m), 0.3, 4.0, 3102)
     a = W.uniform_array((2, nc * m, nc * m), 0.3, 4.0, 3103)
     S_rb, rs = rb.rb_os(a_tr, a, nc, nc, m, o, r_max=49, tail_tol=0.0)
     assert (rs == 49).all()
@@ -76,3 +77,17 @@ def test_error_falls_with_the_rank_on_few_local_variables():
     e2 = _rel(rb.rb_os(a_tr, a, nc, nc, m, o, r_max=2, tail_tol=0.0)[0], S_os)
     e32 = _rel(rb.rb_os(a_tr, a, nc, nc, m, o, r_max=32, tail_tol=0.0)[0], S_os)
     assert e32 < e2 / 100, (e2, e32)
+
+
+def test_degenerate_training_sets_keep_the_numerical_rank():
+    # one sample: the centred snapshots vanish, r = 0 and psi = phibar, which
+    # is that sample's own patch solution; two samples: the centred snapshots
+    # of the two are opposite, rank 3 -- both reproduce their training
+    # samples exactly
+    m, o, nc = 4, 2, 3
+    for N, r_expect in ((1, 0), (2, 3)):
+        a = W.uniform_array((N, nc * m, nc * m), 0.3, 4.0, 3110 + N)
+        S_rb, rs = rb.rb_os(a, a, nc, nc, m, o, r_max=8, tail_tol=0.0)
+        assert (rs == r_expect).all()
+        S_os, _ = core.upscale_os(a, nc, nc, m, o)
+        assert _rel(S_rb, S_os) < 1e-12
