@@ -393,7 +393,9 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * the KL expansion of the centred phi^l in the energy inner product of
  * K_II(abar) (abar = training mean of the coefficient), with one shared basis
  * for the three l.  r_K = min(r_max, smallest r whose relative tail
- * sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol).  The model stores,
+ * sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol, number of eigenvalues
+ * above 1e-12 lambda_max: the numerical rank of the snapshots, 0 for a
+ * single training sample).  The model stores,
  * per patch and fine element e, the P = r(r+1)/2 + 3r + 6 coefficients that
  * make the online Galerkin system a linear function of the coefficient
  * values a_e (the Q1 stiffness is affine in a_e).  Requires 2 <= m <= 32,
@@ -420,6 +422,44 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
                     void* stream);
 int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
                           void* stream);
+
+/* ------------------------------------------------------------------------
+ * Reduced basis on oversampled patches (Sec. 3.2 on the patches of the
+ * oversampled Petrov-Galerkin MsFEM of Sec. 2.2; the high-contrast example
+ * of Sec. 5.2 uses the two together).
+ *
+ * stomsfem_reduce_os (offline): the cell problems of element K are those of
+ * stomsfem_upscale_os, posed on the patch of Mp = m + 2*oversample fine
+ * cells per side around K (moved inside the domain where it would stick
+ * out) with the bilinear data of the patch corners.  From the training
+ * samples `train` (device [ntrain][ncy*m][ncx*m]; S and status unused, may
+ * be NULL) the patch blocks are reduced exactly as the elements of
+ * stomsfem_reduce: means phibar^l, KL modes of the centred patch solutions
+ * in the energy inner product of the training-mean coefficient, r_K by the
+ * same rule.  Requires 2 <= Mp <= 32, Mp <= ncx*m and ncy*m,
+ * 1 <= r_max <= 8, 1 <= ntrain <= 341 and the eigenproblem limit of
+ * stomsfem_reduce (EINVAL otherwise).  Allocates device memory (owned by the
+ * model; a gathered copy of the training patches, ntrain*M*Mp*Mp doubles,
+ * only during the call) and synchronises `stream`.  model_export 0..3 return
+ * the patch quantities ((Mp-1)^2 interior nodes); the model cannot be saved.
+ *
+ * stomsfem_reduce_os_apply (online): for every pair of `batch` (same ncx,
+ * ncy, m as the training batch) the reduced patch solutions
+ *   psi^l = phibar^l + sum_q c^l_q zeta_q,  A c^l = -Fh_l (l = 0..2),
+ *   psi^3 = 1 - sum_l psi^l,
+ * recombined as in stomsfem_upscale_os: Psi[k][j] = psi^j at K's corners
+ * (counter-clockwise from the lower left), phi^i = sum_j (Psi^{-T})[i][j]
+ * psi^j, and
+ *   S[i][l'] = int_K a grad phi^i . grad p^l'   (p^l': K's bilinear functions)
+ * written as 16 row-major doubles per pair to batch->S ([nsamples][ncy*ncx]
+ * [16]).  precision must be STOMSFEM_PREC_F64 (FP64 throughout).  Per-pair
+ * status ENOTSPD if the r x r system is not positive definite or Psi is
+ * singular.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t r_max, double tail_tol,
+                       stomsfem_model** model, void* stream);
+int stomsfem_reduce_os_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
+                             void* stream);
 
 /* Copy model data to host memory (synchronous).  which:
  *   0 = r per patch        (int32  [ncy*ncx])

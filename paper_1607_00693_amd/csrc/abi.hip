@@ -340,12 +340,40 @@ struct stomsfem_model {
   // KL interpolation (kind 6; kind 7 = of the oversampled Petrov-Galerkin
   // stiffness: nine class tables of 16 entries, os_o cells of oversampling)
   int32_t os_o = 0;
+  // reduced basis on oversampled patches (kind 8): m is the patch side, os_o
+  // the oversampling, os_m the element side; online tables GO / GO32
+  // [M][KD][RBO_PO] and corner values Pc [M][4][RBO_NF]
+  int32_t os_m = 0;
+  double* GO = nullptr;
+  float* GO32 = nullptr;
+  double* Pc = nullptr;
   // ordering of the calls that use the model's scratch buffers (OrderedUse)
   std::mutex order_mu;
   hipEvent_t order_ev = nullptr;
 };
 
 namespace {
+RbOsArgs rb_os_args(const stomsfem_model* md) {
+  RbOsArgs t{};
+  t.ncx = md->ncx;
+  t.ncy = md->ncy;
+  t.m = md->os_m;
+  t.o = md->os_o;
+  t.Mp = md->m;
+  t.rmax = md->rmax;
+  t.KD = md->KD;
+  t.PP = md->PP;
+  t.KDo = md->KD;
+  t.rK = md->rK;
+  t.Z = md->Z;
+  t.phibar = md->phibar;
+  t.G64 = md->G64;
+  t.GO = md->GO;
+  t.GO32 = md->GO32;
+  t.Pc = md->Pc;
+  return t;
+}
+
 void model_release(stomsfem_model* md) {
   if (!md) return;
   int cur = 0;
@@ -358,6 +386,9 @@ void model_release(stomsfem_model* md) {
   hipFree(md->phibar);
   hipFree(md->G32);
   hipFree(md->G64);
+  hipFree(md->GO);
+  hipFree(md->GO32);
+  hipFree(md->Pc);
   hipFree(md->lv);
   hipFree(md->params);
   hipFree(md->m1);
@@ -1547,12 +1578,100 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "reduce_apply launch");
 }
 
+int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t r_max, double tail_tol,
+                       stomsfem_model** model, void* stream) {
+  if (!train || !model) return fail(STOMSFEM_EINVAL, "reduce_os: NULL argument");
+  *model = nullptr;
+  const stomsfem_batch& b = *train;
+  if (b.ncx < 1 || b.ncy < 1 || b.m < 1 || oversample < 0)
+    return fail(STOMSFEM_EINVAL, "reduce_os: need ncx, ncy, m >= 1 and oversample >= 0");
+  const int Mp = b.m + 2 * oversample;
+  if (Mp < 2 || Mp > 32) return fail(STOMSFEM_EINVAL, "reduce_os: need 2 <= m + 2*oversample <= 32");
+  if (Mp > b.ncx * b.m || Mp > b.ncy * b.m)
+    return fail(STOMSFEM_EINVAL, "reduce_os: the patch is larger than the domain");
+  if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32)
+    return fail(STOMSFEM_EINVAL, "reduce_os: bad a_dtype");
+  if (b.nsamples < 1) return fail(STOMSFEM_EINVAL, "reduce_os: need at least one training sample");
+  if (b.nsamples > 341) return fail(STOMSFEM_EINVAL, "reduce_os: ntrain must be <= 341");
+  if (!device_ptr(b.a)) return fail(STOMSFEM_EINVAL, "reduce_os: a is not a device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nemb = b.nsamples * (int64_t)b.ncy * Mp * b.ncx * Mp;
+  double* emb = nullptr;
+  hipError_t e = hipMalloc((void**)&emb, sizeof(double) * nemb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(STOMSFEM_ENOMEM, "reduce_os: device allocation failed");
+  }
+  e = launch_rb_os_embed(b.a, b.a_dtype, b.nsamples, b.ncx, b.ncy, b.m, oversample, emb, st);
+  if (e != hipSuccess) {
+    hipFree(emb);
+    return hip_fail(e, "reduce_os: gather of the patches");
+  }
+  // the patches as the elements of a batch of side Mp
+  stomsfem_batch pb = b;
+  pb.m = Mp;
+  pb.a = emb;
+  pb.a_dtype = STOMSFEM_F64;
+  pb.S = nullptr;
+  pb.status = nullptr;
+  stomsfem_model* md = nullptr;
+  int rc = stomsfem_reduce(&pb, r_max, tail_tol, &md, stream);
+  hipStreamSynchronize(st);
+  hipFree(emb);
+  if (rc != STOMSFEM_OK) return rc;
+  md->kind = 8;
+  md->os_o = oversample;
+  md->os_m = b.m;
+  const int Mc = b.ncx * b.ncy;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  A((void**)&md->GO, sizeof(double) * (size_t)Mc * md->KD * RBO_PO);
+  A((void**)&md->GO32, sizeof(float) * (size_t)Mc * md->KD * RBO_PO);
+  A((void**)&md->Pc, sizeof(double) * (size_t)Mc * 4 * RBO_NF);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    model_release(md);
+    return fail(STOMSFEM_ENOMEM, "reduce_os: device allocation failed");
+  }
+  RbOsArgs t = rb_os_args(md);
+  e = launch_rb_os_tables(t, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    model_release(md);
+    return hip_fail(e, "reduce_os: online tables");
+  }
+  // the plain patch tables are not used online
+  hipFree(md->G32);
+  hipFree(md->G64);
+  md->G32 = nullptr;
+  md->G64 = nullptr;
+  *model = md;
+  return STOMSFEM_OK;
+}
+
+int stomsfem_reduce_os_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
+                             void* stream) {
+  if (!model || !batch) return fail(STOMSFEM_EINVAL, "reduce_os_apply: NULL argument");
+  if (model->kind != 8) return fail(STOMSFEM_EINVAL, "reduce_os_apply: not a model of stomsfem_reduce_os");
+  int rc = check_batch(*batch, 0);
+  if (rc != STOMSFEM_OK) return rc;
+  if (batch->ncx != model->ncx || batch->ncy != model->ncy || batch->m != model->os_m)
+    return fail(STOMSFEM_EINVAL, "reduce_os_apply: batch mesh differs from the model's");
+  if (precision != STOMSFEM_PREC_F64)
+    return fail(STOMSFEM_EINVAL, "reduce_os_apply: precision must be STOMSFEM_PREC_F64");
+  if (batch->nsamples == 0) return STOMSFEM_OK;
+  const RbOsArgs t = rb_os_args(model);
+  hipError_t e = launch_rb_os_apply(t, to_args(*batch), batch->a_dtype, (hipStream_t)stream);
+  return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "reduce_os_apply launch");
+}
+
 int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host_dst, int64_t bytes) {
   if (!model || !host_dst) return fail(STOMSFEM_EINVAL, "model_export: NULL argument");
   const int Mc = model->ncx * model->ncy, nI = (model->m - 1) * (model->m - 1);
   const void* src = nullptr;
   int64_t need = 0;
-  if (which >= 0 && which <= 3 && model->kind != 1)
+  if (which >= 0 && which <= 3 && model->kind != 1 && model->kind != 8)
     return fail(STOMSFEM_EINVAL, "model_export: not a reduced-basis model");
   switch (which) {
     case 0: src = model->rK; need = 4LL * Mc; break;

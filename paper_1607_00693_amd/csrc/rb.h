@@ -53,3 +53,38 @@ int rb_pad_p(int rmax);
 int rb_pad_kd(int m);
 
 }  // namespace stomsfem
+
+namespace stomsfem {
+
+// Reduced basis on oversampled patches.  The patch of element K (side
+// Mp = m + 2o, moved inside the domain at the edge) is reduced exactly as a
+// plain patch (the build above on the patch blocks); the online table GO of
+// patch K then holds, per patch element e, RBO_PO coefficients that make
+// every linear quantity of the Petrov-Galerkin stiffness a linear function of
+// the patch's coefficient values:
+//   [0, NA + 3 rmax)        A and Fh of the patch's reduced system (as in G)
+//   [RBO_H, RBO_H + 4 NF)   for e inside K: f_e . K_ref p_e^l', f = phibar^0..2
+//                           (with the patch boundary data), zeta_0..rmax-1,
+//                           l' = K's bilinear test functions 0..3 (zero for
+//                           e outside K)
+// and Pc [4][NF] the same fields at K's corners (counter-clockwise).
+constexpr int RBO_NF = 11;                 // 3 means + 8 modes
+constexpr int RBO_H = 60;                  // 36 (A) + 24 (Fh) for rmax = 8
+constexpr int RBO_PO = 112;                // RBO_H + 4 NF = 104, padded to 16
+struct RbOsArgs {
+  int32_t ncx, ncy, m, o, Mp;  // element side m, oversampling o, patch side Mp
+  int32_t rmax, KD, PP, KDo;   // G layout (KD x PP), GO rows KDo
+  const int32_t* rK;
+  const double* Z;       // [Mc][(Mp-1)^2][rmax]
+  const double* phibar;  // [Mc][3][(Mp-1)^2]
+  const double* G64;     // [Mc][KD][PP]
+  double* GO;            // [Mc][KDo][RBO_PO]
+  float* GO32;           // [Mc][KDo][RBO_PO]
+  double* Pc;            // [Mc][4][RBO_NF]
+};
+hipError_t launch_rb_os_embed(const void* a, int a_dtype, int64_t nsamples, int ncx, int ncy, int m, int o,
+                              double* out, hipStream_t st);
+hipError_t launch_rb_os_tables(const RbOsArgs& t, hipStream_t st);
+hipError_t launch_rb_os_apply(const RbOsArgs& t, const UpArgs& up, int a_dtype, hipStream_t st);
+
+}  // namespace stomsfem

@@ -230,8 +230,9 @@ __device__ void rb_jacobi(double* H, double* V, int n, int max_sweeps, double* r
 // Eigenvalues (the diagonal of the rotated H) in descending order into
 // order[] / lambda[0..nlam) (zeros beyond n), and the number of modes:
 // r = min(rcap, rmax, n, smallest r whose relative tail
-// sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol).  Thread 0; the
-// caller synchronises.
+// sqrt(sum_{q>r} lambda_q / sum lambda_q) <= tail_tol, number of eigenvalues
+// above RB_RANK_TOL lambda_max).  Thread 0; the caller synchronises.
+constexpr double RB_RANK_TOL = 1e-12;
 __device__ int rb_sort_tail(const double* H, int n, int* order, double tail_tol, int rcap, int rmax, double* lambda,
                             int nlam) {
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -258,6 +259,13 @@ __device__ int rb_sort_tail(const double* H, int n, int* order, double tail_tol,
   if (r > rcap) r = rcap;
   if (r > rmax) r = rmax;
   if (r > n) r = n;
+  // numerical rank of the snapshots: eigenvalues at or below 1e-12 of the
+  // largest are rounding, not modes (the method of snapshots would divide by
+  // their square roots); r = 0 when the centred snapshots vanish
+  const double lmax = n > 0 ? H[order[0] * n + order[0]] : 0.0;
+  int rank = 0;
+  while (rank < n && H[order[rank] * n + order[rank]] > RB_RANK_TOL * lmax) ++rank;
+  if (r > rank) r = rank;
   for (int i = 0; i < nlam; ++i) lambda[i] = i < n ? H[order[i] * n + order[i]] : 0.0;
   return r;
 }

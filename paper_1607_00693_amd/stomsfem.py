@@ -92,6 +92,8 @@ def lib():
         "stomsfem_workspace_reserve": (C.c_int, [i64]),
         "stomsfem_reduce": (C.c_int, [C.POINTER(Batch), i32, dbl, C.POINTER(vp), vp]),
         "stomsfem_reduce_apply": (C.c_int, [vp, C.POINTER(Batch), i32, vp]),
+        "stomsfem_reduce_os": (C.c_int, [C.POINTER(Batch), i32, i32, dbl, C.POINTER(vp), vp]),
+        "stomsfem_reduce_os_apply": (C.c_int, [vp, C.POINTER(Batch), i32, vp]),
         "stomsfem_model_export": (C.c_int, [vp, i32, vp, i64]),
         "stomsfem_model_free": (C.c_int, [vp]),
         "stomsfem_local_vars_bumps": (C.c_int, [i32, i32, i32, C.POINTER(BumpFamily), i32, vp, vp]),
@@ -512,6 +514,31 @@ def reduce_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,
     b = make_batch(a, model.ncx, model.ncy, model.m, S, status)
     _check("stomsfem_reduce_apply", lib().stomsfem_reduce_apply(model.handle, C.byref(b), precision,
                                                                 _stream(stream)))
+    return S
+
+
+def reduce_os(a_train: torch.Tensor, ncx: int, ncy: int, m: int, oversample: int, r_max: int = 8,
+              tail_tol: float = 1e-6, stream=None) -> Model:
+    """Offline reduced-basis build on the oversampled patches (side m + 2 oversample)
+    from training coefficients [Ntr][ncy*m][ncx*m]."""
+    N = a_train.shape[0]
+    assert a_train.shape[1:] == (ncy * m, ncx * m)
+    b = Batch(ncx, ncy, m, _DT[a_train.dtype], N, _ptr(a_train), None, None)
+    h = C.c_void_p()
+    _check("stomsfem_reduce_os", lib().stomsfem_reduce_os(C.byref(b), oversample, r_max, tail_tol, C.byref(h),
+                                                          _stream(stream)))
+    return Model(h, ncx, ncy, m)
+
+
+def reduce_os_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None, precision: int = PREC_F64, stream=None):
+    """Online Petrov-Galerkin stiffness S[N][M][16] from the reduced oversampled patches."""
+    N = a.shape[0]
+    if S is None:
+        S = torch.empty((N, model.ncx * model.ncy, 16), dtype=torch.float64, device=a.device)
+    b = make_batch(a, model.ncx, model.ncy, model.m, S, status, entries=16)
+    _check("stomsfem_reduce_os_apply", lib().stomsfem_reduce_os_apply(model.handle, C.byref(b), precision,
+                                                                      _stream(stream)))
     return S
 
 
