@@ -737,7 +737,7 @@ def os_flops_per_pair(m: int, o: int) -> float:
     return f + 20 * NI + 300
 
 
-def measure_oversampling(log, N=16384):
+def measure_oversampling(log, N=16384, rb_ntrain=64):
     """Oversampling with the Petrov-Galerkin local stiffness (Sec. 2.2 remark,
     eq. stiffness_local_petrov) on the 8x8 coarse mesh, H/h = 8: patches of
     16 and 24 fine cells per side (oversampling ratios 2 and 3), then the
@@ -776,7 +776,55 @@ def measure_oversampling(log, N=16384):
                     "fp64_peak_frac": fl * N * wl.M / t_os / 1e12 / FP64_VALU_PEAK_TFLOPS,
                     "non_ok_pairs": int((st != 0).sum().item()),
                     "max_rel_change_of_U_vs_plain": float(d.max().item())}
+        out[key]["reduced_basis"] = measure_rb_os(wl, a, o, S, U, t_os, ntrain=rb_ntrain)
         log(f"oversampling ratio {M // wl.m}: {out[key]}")
+    return out
+
+
+def measure_rb_os(wl, a, o, S_os, U_os, t_os, ntrain=64, r_max=8, tail_tol=1e-6):
+    """Reduced basis on the oversampled patches (Sec. 3.2 on the patches of
+    the Petrov-Galerkin MsFEM, as in the high-contrast example of Sec. 5.2):
+    offline from ntrain training samples (seed 2003), FP64 online stage on the
+    samples a, against the oversampled solve S_os (t_os seconds)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    xi_tr = torch.from_numpy(W.uniform_xi(ntrain, wl.nxi, 2003)).cuda()
+    a_tr = sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = sm.reduce_os(a_tr, wl.nc, wl.nc, wl.m, o, r_max=r_max, tail_tol=tail_tol)
+    t_off = time.perf_counter() - t0
+    del a_tr
+    N = a.shape[0]
+    S = torch.empty_like(S_os)
+    st = torch.empty((N, wl.M), dtype=torch.int32, device="cuda")
+    scale = S_os.abs().amax(dim=2, keepdim=True)
+    r = model.export("r")
+    out = {"workload": f"{ntrain} training samples, r<={r_max} (tail {tail_tol:g}); FP32 matrix-core online "
+                       "stage on FP32 coefficients (GEMM [128 samples x Mp^2] x [Mp^2 x 112] per workgroup, "
+                       "FP64 8x8 solve and 4x4 recombination per pair) and the FP64 online stage",
+           "offline_s": t_off, "modes_min": int(r.min()), "modes_max": int(r.max())}
+    a32 = a.float()
+    mp = wl.m + 2 * o
+    for key, prec, aa in (("fp32_matrix_core", sm.PREC_F32, a32), ("fp64", sm.PREC_F64, a)):
+        t_on = _timed(lambda: sm.reduce_os_apply(model, aa, S=S, status=st, precision=prec), reps=3)
+        s_err = float(((S - S_os).abs() / scale).max())
+        U, _, _ = sm.coarse_solve_pg(S, wl.nc, wl.nc)
+        d = torch.linalg.norm(U - U_os, dim=1) / torch.linalg.norm(U_os, dim=1)
+        out[key] = {"online_ms": t_on * 1e3, "pairs_per_s": N * wl.M / t_on, "vs_oversampled_solve": t_os / t_on,
+                    "non_ok_pairs": int((st != 0).sum().item()), "max_S_rel_err": s_err,
+                    "max_coarse_rel_err": float(d.max().item())}
+        if prec == sm.PREC_F32:
+            kd = ((mp * mp + 63) // 64) * 64
+            fl = 2.0 * kd * 112  # the GEMM row of one pair (padded table)
+            out[key]["mfma_flops_per_pair"] = fl
+            out[key]["achieved_tflops"] = fl * N * wl.M / t_on / 1e12
+            out[key]["fp32_mfma_peak_frac"] = fl * N * wl.M / t_on / 1e12 / FP32_MFMA_PEAK_TFLOPS
+    del a32
+    model.free()
     return out
 
 

@@ -452,9 +452,12 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
  * psi^j, and
  *   S[i][l'] = int_K a grad phi^i . grad p^l'   (p^l': K's bilinear functions)
  * written as 16 row-major doubles per pair to batch->S ([nsamples][ncy*ncx]
- * [16]).  precision must be STOMSFEM_PREC_F64 (FP64 throughout).  Per-pair
- * status ENOTSPD if the r x r system is not positive definite or Psi is
- * singular.  Asynchronous.
+ * [16]).  precision STOMSFEM_PREC_F32: the linear quantities (A, Fh and
+ * the element sums over K) by one FP32 matrix-core GEMM [128 samples x
+ * Mp^2] x [Mp^2 x 112] per workgroup with FP32 accumulation, then the r x r
+ * solve and the recombination in FP64 per pair; STOMSFEM_PREC_F64: FP64
+ * throughout (reference).  Per-pair status ENOTSPD if the r x r system is
+ * not positive definite or Psi is singular.  Asynchronous.
  * ------------------------------------------------------------------------ */
 int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t r_max, double tail_tol,
                        stomsfem_model** model, void* stream);

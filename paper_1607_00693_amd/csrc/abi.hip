@@ -1658,11 +1658,24 @@ int stomsfem_reduce_os_apply(const stomsfem_model* model, const stomsfem_batch* 
   if (rc != STOMSFEM_OK) return rc;
   if (batch->ncx != model->ncx || batch->ncy != model->ncy || batch->m != model->os_m)
     return fail(STOMSFEM_EINVAL, "reduce_os_apply: batch mesh differs from the model's");
-  if (precision != STOMSFEM_PREC_F64)
-    return fail(STOMSFEM_EINVAL, "reduce_os_apply: precision must be STOMSFEM_PREC_F64");
+  if (precision != STOMSFEM_PREC_F64 && precision != STOMSFEM_PREC_F32)
+    return fail(STOMSFEM_EINVAL, "reduce_os_apply: precision must be STOMSFEM_PREC_F64 or STOMSFEM_PREC_F32");
   if (batch->nsamples == 0) return STOMSFEM_OK;
-  const RbOsArgs t = rb_os_args(model);
-  hipError_t e = launch_rb_os_apply(t, to_args(*batch), batch->a_dtype, (hipStream_t)stream);
+  hipError_t e = hipSuccess;
+  if (precision == STOMSFEM_PREC_F64) {
+    e = launch_rb_os_apply(rb_os_args(model), to_args(*batch), batch->a_dtype, (hipStream_t)stream);
+  } else {
+    RbApplyArgs ra{};
+    ra.up = to_args(*batch);
+    ra.rmax = model->rmax;
+    ra.KD = model->KD;
+    ra.PP = RBO_PO;
+    ra.rK = model->rK;
+    ra.G32 = model->GO32;
+    ra.os_o = model->os_o;
+    ra.Pc = model->Pc;
+    e = launch_rb_os_apply_mfma(ra, batch->a_dtype, (hipStream_t)stream);
+  }
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "reduce_os_apply launch");
 }
 

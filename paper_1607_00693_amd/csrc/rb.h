@@ -39,6 +39,10 @@ struct RbApplyArgs {
   const int32_t* rK;
   const float* G32;
   const double* G64;
+  // oversampled patches (launch_rb_os_apply_mfma only): oversampling os_o,
+  // corner values Pc [M][4][RBO_NF]; G32 is then the table GO32
+  int32_t os_o;
+  const double* Pc;
 };
 
 hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStream_t st);
@@ -86,5 +90,8 @@ hipError_t launch_rb_os_embed(const void* a, int a_dtype, int64_t nsamples, int 
                               double* out, hipStream_t st);
 hipError_t launch_rb_os_tables(const RbOsArgs& t, hipStream_t st);
 hipError_t launch_rb_os_apply(const RbOsArgs& t, const UpArgs& up, int a_dtype, hipStream_t st);
+// FP32 matrix-core online stage (the GEMM of rb_apply_mfma_kernel over the
+// patch, PP = RBO_PO, FP64 solve and recombination per pair).
+hipError_t launch_rb_os_apply_mfma(const RbApplyArgs& ra, int a_dtype, hipStream_t st);
 
 }  // namespace stomsfem

@@ -36,6 +36,7 @@
 // Online: rb_apply_mfma_kernel (FP32 MFMA 16x16x4, FP32 accumulation, FP32
 // r x r solve) and rb_apply_f64_kernel (FP64 throughout, for parity checks).
 #include "rb.h"
+#include "rb_os_dev.h"
 
 #include <type_traits>
 
@@ -762,11 +763,19 @@ constexpr int RBA_PF = RBA_SAMPLES * RBA_KC / 256;  // coefficients per thread a
 // L = (b mod 8) (n / 8) + b / 8 gives each XCD a contiguous range.
 // Otherwise the sample tile runs fastest and consecutive workgroups share
 // the patch's table.
-template <int RMAX, int PP, typename TA>
-__global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int64_t ntiles, int patch_fast) {
+//
+// OS = true: the oversampled patches (rb_os.hip).  The block of element K is
+// its patch (side m + 2 os_o, origin rbo_origin), the table is GO32 (PP =
+// RBO_PO columns: A, Fh and the element sums U), and the per-sample epilogue
+// is the FP64 solve for c and the recombination at K's corners (16 entries
+// per pair).  vec_ok: every patch row starts on a 16-byte boundary.
+template <int RMAX, int PP, typename TA, bool OS = false>
+__global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int64_t ntiles, int patch_fast,
+                                                            int vec_ok) {
   using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const UpArgs& args = ra.up;
-  const int m = args.m, mm = m * m, Mc = args.ncx * args.ncy, KD = ra.KD;
+  const int m = args.m, Mc = args.ncx * args.ncy, KD = ra.KD;
+  const int bs = OS ? m + 2 * ra.os_o : m, mm = bs * bs;  // block side and elements
   const int64_t nb = ntiles * Mc, b = blockIdx.x;
   const int64_t L = (patch_fast && nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
   const int K = (int)(patch_fast ? L % Mc : L / ntiles);
@@ -782,6 +791,8 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
   float(*Cs)[PP + 1] = reinterpret_cast<float(*)[PP + 1]>(smem);
   const int tid = threadIdx.x;
   const int kx = K % args.ncx, ky = K / args.ncx;
+  const int bx0 = OS ? rbo_origin(kx, m, ra.os_o, args.ncx * m) : kx * m;
+  const int by0 = OS ? rbo_origin(ky, m, ra.os_o, args.ncy * m) : ky * m;
   const int w = tid / 64, lane = tid % 64;
   constexpr int NTILE = PP / 16;
   f4 acc[2][NTILE];
@@ -799,17 +810,17 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
       float x = 0.0f;
       if (s < args.nsamples && e < mm) {
         const TA* a = (const TA*)args.a + s * (int64_t)(args.ncy * m) * lda;
-        x = (float)ld(a, (int64_t)(ky * m + e / m) * lda + kx * m + e % m);
+        x = (float)ld(a, (int64_t)(by0 + e / bs) * lda + bx0 + e % bs);
       }
       v[q] = x;
     }
   };
-  // m in {8, 16, 32} with FP32 coefficients: a chunk of 64 elements is
-  // 64 / m whole rows of the patch, so each sample's share comes in 16-byte
-  // loads (16 per sample and chunk: thread tid takes float4 f = idx % 16 of
-  // sample idx / 16, idx = tid + 256 q)
-  const bool vec = std::is_same<TA, float>::value && (m == 8 || m == 16 || m == 32);
-  const int lm = m == 8 ? 3 : m == 16 ? 4 : 5;
+  // block side in {8, 16, 32} with FP32 coefficients: a chunk of 64
+  // elements is 64 / bs whole rows of the block, so each sample's share comes
+  // in 16-byte loads (16 per sample and chunk: thread tid takes float4
+  // f = idx % 16 of sample idx / 16, idx = tid + 256 q)
+  const bool vec = std::is_same<TA, float>::value && vec_ok && (bs == 8 || bs == 16 || bs == 32);
+  const int lm = bs == 8 ? 3 : bs == 16 ? 4 : 5;
   auto load_chunk_vec = [&](int e0, float (&v)[RBA_PF]) {
 #pragma unroll
     for (int q = 0; q < RBA_PF / 4; ++q) {
@@ -818,7 +829,7 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
       f4 x = f4{0.f, 0.f, 0.f, 0.f};
       if (s < args.nsamples && e < mm) {
         const float* a = (const float*)args.a + s * (int64_t)(args.ncy * m) * lda;
-        x = *reinterpret_cast<const f4*>(a + (int64_t)(ky * m + (e >> lm)) * lda + kx * m + (e & (m - 1)));
+        x = *reinterpret_cast<const f4*>(a + (int64_t)(by0 + (e >> lm)) * lda + bx0 + (e & (bs - 1)));
       }
       v[4 * q] = x[0];
       v[4 * q + 1] = x[1];
@@ -880,6 +891,25 @@ __global__ __launch_bounds__(256) void rb_apply_mfma_kernel(RbApplyArgs ra, int6
 #pragma unroll
       for (int v = 0; v < 4; ++v) Cs[32 * w + 16 * h + 4 * (lane >> 4) + v][16 * t + (lane & 15)] = acc[h][t][v];
   __syncthreads();
+  if constexpr (OS) {
+    if (tid < RBA_SAMPLES) {
+      const int64_t s = s0 + tid;
+      if (s < args.nsamples) {
+        double c[3][RMAX];
+        const bool ok = rbo_coeffs<RMAX>(&Cs[tid][0], ra.rK[K], c);
+        double S[4][4];
+        const bool nonsing = rbo_recombine<RMAX>(c, &Cs[tid][RBO_H], ra.Pc + (int64_t)K * 4 * RBO_NF, S);
+        const int64_t p = s * Mc + K;
+        double* out = args.S + p * 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int lp = 0; lp < 4; ++lp) out[4 * i + lp] = S[i][lp];
+        if (args.status) args.status[p] = (ok && nonsing) ? STOMSFEM_OK : STOMSFEM_ENOTSPD;
+      }
+    }
+    return;
+  }
   if (tid < RBA_SAMPLES) {
     const int64_t s = s0 + tid;
     if (s < args.nsamples) {
@@ -918,10 +948,31 @@ hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStre
   const int patch_fast = u.m * elem < 128 ? 1 : 0;
   if (a_dtype == STOMSFEM_F32)
     hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
-                       patch_fast);
+                       patch_fast, 1);
   else
     hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
-                       patch_fast);
+                       patch_fast, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_os_apply_mfma(const RbApplyArgs& ra, int a_dtype, hipStream_t st) {
+  const UpArgs& u = ra.up;
+  if (u.npairs == 0) return hipSuccess;
+  const int bs = u.m + 2 * ra.os_o;
+  if (ra.rmax != 8 || ra.PP != RBO_PO || ra.KD % RBA_KC != 0 || ra.KD < bs * bs || !ra.Pc)
+    return hipErrorInvalidValue;
+  const int64_t ntiles = (u.nsamples + RBA_SAMPLES - 1) / RBA_SAMPLES, nb = ntiles * u.ncx * u.ncy;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  const int elem = a_dtype == STOMSFEM_F32 ? 4 : 8;
+  const int patch_fast = bs * elem < 128 ? 1 : 0;
+  // patch rows on 16-byte boundaries: every origin is a multiple of 4 cells
+  const int vec_ok = (u.m % 4 == 0 && ra.os_o % 4 == 0 && (u.ncx * u.m) % 4 == 0) ? 1 : 0;
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, RBO_PO, float, true>), dim3((unsigned)nb), dim3(256), 0, st, ra,
+                       ntiles, patch_fast, vec_ok);
+  else
+    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, RBO_PO, double, true>), dim3((unsigned)nb), dim3(256), 0, st, ra,
+                       ntiles, patch_fast, vec_ok);
   return hipGetLastError();
 }
 

@@ -24,16 +24,11 @@
 // online stage is one pass over the patch, an r x r LDL^T solve, and the
 // 4 x 4 recombination.
 #include "rb.h"
+#include "rb_os_dev.h"
 
 namespace stomsfem {
 
 namespace {
-
-__host__ __device__ inline int rbo_origin(int k, int m, int o, int nf) {
-  int x0 = k * m - o;
-  if (x0 > nf - (m + 2 * o)) x0 = nf - (m + 2 * o);
-  return x0 < 0 ? 0 : x0;
-}
 
 // Bilinear function of corner l of an m x m element at its local node (u, v),
 // corners counter-clockwise from the lower left.
@@ -111,144 +106,6 @@ __global__ __launch_bounds__(256) void rb_os_tables_kernel(RbOsArgs t) {
   }
 }
 
-// c^l = -A^{-1} Fh_l (l = 0..2) from v = [A upper triangle | Fh] by Crout
-// LDL^T with the identity on the unused modes q >= r.  False on a
-// non-positive (or NaN) pivot.
-template <int RMAX>
-__device__ __forceinline__ bool rbo_coeffs(const double* v, int r, double c[3][RMAX]) {
-  constexpr int NA = RMAX * (RMAX + 1) / 2;
-  double L[RMAX][RMAX], U[RMAX][RMAX], dinv[RMAX];
-  bool ok = true;
-#pragma unroll
-  for (int q = 0; q < RMAX; ++q)
-#pragma unroll
-    for (int qp = q; qp < RMAX; ++qp) {
-      const double a = v[q * RMAX - q * (q - 1) / 2 + (qp - q)];
-      L[qp][q] = (q < r && qp < r) ? a : (q == qp ? 1.0 : 0.0);
-    }
-#pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    double d = L[j][j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) d -= U[j][k] * L[j][k];
-    ok = ok && d > 0.0;
-    const double inv = 1.0 / d;
-    dinv[j] = inv;
-#pragma unroll
-    for (int i = j + 1; i < RMAX; ++i) {
-      double u = L[i][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) u -= U[i][k] * L[j][k];
-      U[i][j] = u;
-      L[i][j] = u * inv;
-    }
-  }
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    double x[RMAX];
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i) {
-      double s = (i < r) ? v[NA + l * RMAX + i] : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) s -= L[i][k] * x[k];
-      x[i] = s;
-    }
-#pragma unroll
-    for (int i = RMAX - 1; i >= 0; --i) {
-      double s = x[i] * dinv[i];
-#pragma unroll
-      for (int k = i + 1; k < RMAX; ++k) s -= L[k][i] * c[l][k];
-      c[l][i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i) c[l][i] = -c[l][i];
-  }
-  return ok;
-}
-
-// S16 = Psi^{-T} T from the coefficients c, the sums U [NF][4] and the corner
-// values Pc [4][NF] (Gaussian elimination with partial pivoting on Psi^T).
-// False if Psi is singular.
-template <int RMAX>
-__device__ __forceinline__ bool rbo_recombine(const double c[3][RMAX], const double Uf[RBO_NF][4],
-                                              const double* Pc, double S[4][4]) {
-  double Tm[4][4], Pt[4][4];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int lp = 0; lp < 4; ++lp) {
-      double s = Uf[j][lp];
-#pragma unroll
-      for (int q = 0; q < RMAX; ++q) s += c[j][q] * Uf[3 + q][lp];
-      Tm[j][lp] = s;
-    }
-#pragma unroll
-  for (int lp = 0; lp < 4; ++lp) Tm[3][lp] = -(Tm[0][lp] + Tm[1][lp] + Tm[2][lp]);
-  // Pt = Psi^T: Pt[j][k] = psi^j(x_k)
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double sum = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      double s = Pc[k * RBO_NF + j];
-#pragma unroll
-      for (int q = 0; q < RMAX; ++q) s += c[j][q] * Pc[k * RBO_NF + 3 + q];
-      Pt[j][k] = s;
-      sum += s;
-    }
-    Pt[3][k] = 1.0 - sum;
-  }
-  // solve Pt S = Tm (every index compile-time: the row interchange is a
-  // select per entry)
-  bool sing = false;
-#pragma unroll
-  for (int col = 0; col < 4; ++col) {
-    int pr = col;
-    double best = fabs(Pt[col][col]);
-#pragma unroll
-    for (int i = col + 1; i < 4; ++i)
-      if (fabs(Pt[i][col]) > best) {
-        best = fabs(Pt[i][col]);
-        pr = i;
-      }
-#pragma unroll
-    for (int i = col + 1; i < 4; ++i) {
-      const bool sw = i == pr;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const double a = Pt[col][cc], b = Tm[col][cc];
-        Pt[col][cc] = sw ? Pt[i][cc] : a;
-        Pt[i][cc] = sw ? a : Pt[i][cc];
-        Tm[col][cc] = sw ? Tm[i][cc] : b;
-        Tm[i][cc] = sw ? b : Tm[i][cc];
-      }
-    }
-    sing = sing || !(fabs(Pt[col][col]) > 0.0);
-    const double iv = 1.0 / Pt[col][col];
-#pragma unroll
-    for (int i = col + 1; i < 4; ++i) {
-      const double f = Pt[i][col] * iv;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        Pt[i][cc] -= f * Pt[col][cc];
-        Tm[i][cc] -= f * Tm[col][cc];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    const double iv = 1.0 / Pt[i][i];
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      double s = Tm[i][cc];
-#pragma unroll
-      for (int k = i + 1; k < 4; ++k) s -= Pt[i][k] * S[k][cc];
-      S[i][cc] = s * iv;
-    }
-  }
-  return !sing;
-}
-
 // FP64 online stage.  One lane per pair; a wavefront holds 64 samples of one
 // patch, so that the patch's table rows are wavefront-uniform.
 template <typename TA>
@@ -280,20 +137,16 @@ __global__ __launch_bounds__(256) void rb_os_apply_f64_kernel(RbOsArgs t, UpArgs
   const bool ok = rbo_coeffs<RMAX>(v, t.rK[K], c);
   // pass 2: U over the elements of K
   const int cx = kx * m - x0, cy = ky * m - y0;
-  double Uf[RBO_NF][4];
+  double Uf[4 * RBO_NF];  // U[f][l'] at 4 f + l'
 #pragma unroll
-  for (int f = 0; f < RBO_NF; ++f)
-#pragma unroll
-    for (int lp = 0; lp < 4; ++lp) Uf[f][lp] = 0.0;
+  for (int q = 0; q < 4 * RBO_NF; ++q) Uf[q] = 0.0;
   for (int iy = 0; iy < m; ++iy)
     for (int ix = 0; ix < m; ++ix) {
       const int ex = cx + ix, ey = cy + iy;
       const double ae = ld(a, (int64_t)ey * nfx + ex);
       const double* g = GO + (int64_t)(ey * Mp + ex) * RBO_PO + RBO_H;
 #pragma unroll
-      for (int f = 0; f < RBO_NF; ++f)
-#pragma unroll
-        for (int lp = 0; lp < 4; ++lp) Uf[f][lp] += ae * g[4 * f + lp];
+      for (int q = 0; q < 4 * RBO_NF; ++q) Uf[q] += ae * g[q];
     }
   double S[4][4];
   const bool nonsing = rbo_recombine<RMAX>(c, Uf, t.Pc + (int64_t)K * 4 * RBO_NF, S);

@@ -480,7 +480,7 @@ class Model:
         import numpy as np
 
         M = self.ncx * self.ncy
-        nI = (self.m - 1) ** 2
+        nI = (getattr(self, "patch_m", self.m) - 1) ** 2
         spec = {"r": (0, np.int32, (M,)), "lambda": (1, np.float64, (M, nI)),
                 "Z": (2, np.float64, (M, nI, 8)), "phibar": (3, np.float64, (M, 3, nI)),
                 "offsets": (5, np.int64, (M + 1,))}
@@ -527,7 +527,9 @@ def reduce_os(a_train: torch.Tensor, ncx: int, ncy: int, m: int, oversample: int
     h = C.c_void_p()
     _check("stomsfem_reduce_os", lib().stomsfem_reduce_os(C.byref(b), oversample, r_max, tail_tol, C.byref(h),
                                                           _stream(stream)))
-    return Model(h, ncx, ncy, m)
+    md = Model(h, ncx, ncy, m)
+    md.patch_m = m + 2 * oversample  # the exported patch quantities have (patch_m - 1)^2 interior nodes
+    return md
 
 
 def reduce_os_apply(model: Model, a: torch.Tensor, S: torch.Tensor | None = None,

@@ -3,8 +3,10 @@ stomsfem_reduce_os_apply, through the C-ABI) against the oracle
 (oracle.rb.rb_os_online_S16 on the oracle's own patch models) and against
 the GPU's plain oversampled solve.
 
-Tolerances: the FP64 online stage reproduces the oracle's S16 to 1e-7
-relative per pair (both sides build the same energy-KL subspace from the
+Tolerances: the FP32 matrix-core online stage (FP32 GEMM with FP32
+accumulation over the patch's Mp^2 elements, FP64 solve and recombination)
+stays within 2e-4 relative per pair of the FP64 stage and of the oracle; the
+FP64 online stage reproduces the oracle's S16 to 1e-7 relative per pair (both sides build the same energy-KL subspace from the
 same snapshots; their eigen-solvers differ, so agreement is bounded by the
 spectral gap after the last kept mode, not by rounding); where the reduced
 space holds the patch solutions exactly (a training sample with every mode
@@ -95,6 +97,40 @@ def test_online_matches_oracle(sm, orc, setup, dtype):
     assert err < 1e-7
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_matrix_core_stage_matches_oracle_and_fp64(sm, orc, setup, dtype):
+    # 130 samples: one full tile of 128 samples per patch and a ragged one
+    nc, m, o = setup["nc"], setup["m"], setup["o"]
+    a_np = _bumps(orc, 130, 1107, nc, m).astype(dtype)
+    a = torch.from_numpy(a_np).cuda()
+    say(f"FP32 matrix-core stage, dtype={np.dtype(dtype).name}")
+    st = torch.full((130, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S32 = sm.reduce_os_apply(setup["model"], a, status=st, precision=sm.PREC_F32).cpu().numpy()
+    assert (st == sm.OK).all()
+    S64 = sm.reduce_os_apply(setup["model"], a).cpu().numpy()
+    err = _rel_pairs(S32, S64)
+    say(f"vs FP64 stage: {err:.2e}")
+    assert err < 2e-4
+    idx = [0, 1, 127, 128, 129]
+    R = _oracle_S16(orc, setup["orc_models"], a_np[idx].astype(np.float64), nc, m, o)
+    assert _rel_pairs(S32[idx], R) < 2e-4
+
+
+@pytest.mark.parametrize("m,o,nc", [(4, 2, 5), (8, 2, 3), (6, 3, 3), (16, 8, 2)])
+def test_matrix_core_stage_patch_shapes(sm, orc, m, o, nc):
+    # patch sides 8 (rows not on 16-byte boundaries: scalar loads), 12 and 12
+    # (neither 8, 16 nor 32), 32 (vector loads); FP32 coefficients
+    a_tr = torch.from_numpy(_bumps(orc, 12, 2107, nc, m)).cuda()
+    a = torch.from_numpy(_bumps(orc, 7, 2108, nc, m).astype(np.float32)).cuda()
+    say(f"matrix-core stage m={m} o={o} nc={nc}")
+    model = sm.reduce_os(a_tr, nc, nc, m, o, r_max=8, tail_tol=1e-6)
+    st = torch.full((7, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S32 = sm.reduce_os_apply(model, a, status=st, precision=sm.PREC_F32).cpu().numpy()
+    assert (st == sm.OK).all()
+    S64 = sm.reduce_os_apply(model, a).cpu().numpy()
+    assert _rel_pairs(S32, S64) < 2e-4
+
+
 def test_ragged_sample_blocks(sm, orc, setup):
     # 70 samples: one full wavefront of samples per patch and a ragged one;
     # every pair equals the same pair computed alone
@@ -168,7 +204,7 @@ def test_invalid_arguments(sm, orc, setup):
         sm.reduce_os(a[:, :16, :16].contiguous(), 2, 2, m, 8)
     assert e.value.code == sm.EINVAL
     with pytest.raises(sm.StomsfemError) as e:
-        sm.reduce_os_apply(setup["model"], a, precision=sm.PREC_F32)
+        sm.reduce_os_apply(setup["model"], a, precision=sm.PREC_BF16)
     assert e.value.code == sm.EINVAL
     with pytest.raises(sm.StomsfemError) as e:   # the oversampled model is not a plain one
         sm.reduce_apply(setup["model"], a, precision=sm.PREC_F64)
