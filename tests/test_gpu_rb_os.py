@@ -221,3 +221,43 @@ def test_invalid_arguments(sm, orc, setup):
     # empty batch
     S = sm.reduce_os_apply(setup["model"], a[:0])
     assert S.shape == (0, nc * nc, 16)
+
+
+def test_full_size_sampled_against_oracle(sm, orc):
+    # the benchmark's launch: the 8x8 bump mesh, ratio 2, 64 training
+    # samples (seed 2003), 16 384 online samples in FP32 through the
+    # matrix-core stage; 24 sampled pairs against the oracle's own patch
+    # models (each built from the same training fields)
+    from oracle import rb
+
+    wl = W.MESH8
+    nc, m, o, ntr, N = wl.nc, wl.m, 4, 64, 16384
+    xi_tr = W.uniform_xi(ntr, wl.nxi, 2003)
+    a_tr = orc.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, wl.seed)).cuda()
+    say("full size: build")
+    model = sm.reduce_os(torch.from_numpy(a_tr).cuda(), nc, nc, m, o, r_max=8, tail_tol=1e-6)
+    a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)
+    st = torch.full((N, wl.M), 99, dtype=torch.int32, device="cuda")
+    say("full size: online")
+    S = sm.reduce_os_apply(model, a32, status=st, precision=sm.PREC_F32).cpu().numpy()
+    assert (st == sm.OK).all()
+    rng = np.random.default_rng(77)
+    samples = rng.integers(0, N, size=24)
+    patches = rng.integers(0, wl.M, size=24)
+    samples[:2] = (0, N - 1)
+    a_s = a32[torch.from_numpy(samples).cuda()].double().cpu().numpy()
+    models = {}
+    worst = 0.0
+    for i, (s, K) in enumerate(zip(samples, patches)):
+        K = int(K)
+        if K not in models:
+            blocks = np.stack([rb.patch_block(a_tr[t], K, nc, nc, m, o) for t in range(ntr)])
+            models[K] = rb.rb_offline(np.ascontiguousarray(blocks), r_max=8, tail_tol=1e-6)
+        kx, ky = K % nc, K // nc
+        cx = kx * m - orc.os_origin(kx, m, o, nc * m)
+        cy = ky * m - orc.os_origin(ky, m, o, nc * m)
+        R = rb.rb_os_online_S16(models[K], np.ascontiguousarray(rb.patch_block(a_s[i], K, nc, nc, m, o)), m, cx, cy)
+        worst = max(worst, np.abs(S[s, K] - R.ravel()).max() / np.abs(R).max())
+    say(f"full size: worst sampled rel err {worst:.2e}")
+    assert worst < 2e-4
