@@ -441,7 +441,8 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
  * stomsfem_reduce (EINVAL otherwise).  Allocates device memory (owned by the
  * model; a gathered copy of the training patches, ntrain*M*Mp*Mp doubles,
  * only during the call) and synchronises `stream`.  model_export 0..3 return
- * the patch quantities ((Mp-1)^2 interior nodes); the model cannot be saved.
+ * the patch quantities ((Mp-1)^2 interior nodes); stomsfem_model_save /
+ * _load keep the model (kind 9).
  *
  * stomsfem_reduce_os_apply (online): for every pair of `batch` (same ncx,
  * ncy, m as the training batch) the reduced patch solutions
@@ -849,8 +850,8 @@ int stomsfem_tuning_reset(void);
 /* ------------------------------------------------------------------------
  * Model files, counters, training alias.
  *
- * stomsfem_model_save: writes any model (reduced basis, random
- *   interpolation, learned surrogate) to `path`: a header (magic "STOMSFEM",
+ * stomsfem_model_save: writes a reduced-basis (also on oversampled patches),
+ *   random-interpolation or learned-surrogate model to `path`: a header (magic "STOMSFEM",
  *   ABI version, kind, mesh, scalars, coefficient family) followed by the
  *   model's device arrays, each preceded by (index, element size, count).
  *   The surrogate's training data are not written (stomsfem_mlp_set_data
@@ -878,7 +879,8 @@ int stomsfem_model_load(const char* path, stomsfem_model** model);
 /* kind: 1 = reduced basis, 2 = learned surrogate, 3 = random interpolation,
  * 4 = sparse-grid collocation dictionaries, 5 = sparse-grid interpolation,
  * 6 = interpolation in the local KL parameters; 7 = the same for the oversampled
- * Petrov-Galerkin stiffness; 8 = the latter on a sparse grid;
+ * Petrov-Galerkin stiffness; 8 = the latter on a sparse grid; 9 = reduced
+ * basis on oversampled patches (m = the element side);
  * any output pointer may be NULL. */
 int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* ncx, int32_t* ncy, int32_t* m);
 int stomsfem_stats_get(stomsfem_stats* out);

@@ -340,7 +340,7 @@ struct stomsfem_model {
   // KL interpolation (kind 6; kind 7 = of the oversampled Petrov-Galerkin
   // stiffness: nine class tables of 16 entries, os_o cells of oversampling)
   int32_t os_o = 0;
-  // reduced basis on oversampled patches (kind 8): m is the patch side, os_o
+  // reduced basis on oversampled patches (kind 9): m is the patch side, os_o
   // the oversampling, os_m the element side; online tables GO / GO32
   // [M][KD][RBO_PO] and corner values Pc [M][4][RBO_NF]
   int32_t os_m = 0;
@@ -1619,7 +1619,7 @@ int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t 
   hipStreamSynchronize(st);
   hipFree(emb);
   if (rc != STOMSFEM_OK) return rc;
-  md->kind = 8;
+  md->kind = 9;
   md->os_o = oversample;
   md->os_m = b.m;
   const int Mc = b.ncx * b.ncy;
@@ -1653,7 +1653,7 @@ int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t 
 int stomsfem_reduce_os_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
                              void* stream) {
   if (!model || !batch) return fail(STOMSFEM_EINVAL, "reduce_os_apply: NULL argument");
-  if (model->kind != 8) return fail(STOMSFEM_EINVAL, "reduce_os_apply: not a model of stomsfem_reduce_os");
+  if (model->kind != 9) return fail(STOMSFEM_EINVAL, "reduce_os_apply: not a model of stomsfem_reduce_os");
   int rc = check_batch(*batch, 0);
   if (rc != STOMSFEM_OK) return rc;
   if (batch->ncx != model->ncx || batch->ncy != model->ncy || batch->m != model->os_m)
@@ -1684,7 +1684,7 @@ int stomsfem_model_export(const stomsfem_model* model, int32_t which, void* host
   const int Mc = model->ncx * model->ncy, nI = (model->m - 1) * (model->m - 1);
   const void* src = nullptr;
   int64_t need = 0;
-  if (which >= 0 && which <= 3 && model->kind != 1 && model->kind != 8)
+  if (which >= 0 && which <= 3 && model->kind != 1 && model->kind != 9)
     return fail(STOMSFEM_EINVAL, "model_export: not a reduced-basis model");
   switch (which) {
     case 0: src = model->rK; need = 4LL * Mc; break;
@@ -2923,7 +2923,7 @@ int stomsfem_model_shape(const stomsfem_model* model, int32_t* kind, int32_t* nc
   if (kind) *kind = model->kind;
   if (ncx) *ncx = model->ncx;
   if (ncy) *ncy = model->ncy;
-  if (m) *m = model->m;
+  if (m) *m = model->kind == 9 ? model->os_m : model->m;
   return STOMSFEM_OK;
 }
 
@@ -2974,6 +2974,14 @@ std::vector<ArraySpec> model_arrays(stomsfem_model* md) {
               {(void**)&md->nlv, 4, M},
               {(void**)&md->off, 8, M + 1},
               {(void**)&md->table, 8, (size_t)md->rows * 10}};
+    case 9:
+      return {{(void**)&md->rK, 4, M},
+              {(void**)&md->lambda, 8, M * nI},
+              {(void**)&md->Z, 8, M * nI * md->rmax},
+              {(void**)&md->phibar, 8, M * 3 * nI},
+              {(void**)&md->GO32, 4, M * md->KD * RBO_PO},
+              {(void**)&md->GO, 8, M * md->KD * RBO_PO},
+              {(void**)&md->Pc, 8, M * 4 * RBO_NF}};
     default:
       return {};
   }
@@ -2982,7 +2990,8 @@ std::vector<ArraySpec> model_arrays(stomsfem_model* md) {
 
 int stomsfem_model_save(const stomsfem_model* model, const char* path) {
   if (!model || !path) return fail(STOMSFEM_EINVAL, "model_save: NULL argument");
-  if (model->kind < 1 || model->kind > 3) return fail(STOMSFEM_EINVAL, "model_save: unknown model kind");
+  if ((model->kind < 1 || model->kind > 3) && model->kind != 9)
+    return fail(STOMSFEM_EINVAL, "model_save: unknown model kind");
   if (model->family != MLP_FAMILY_BUMPS)
     return fail(STOMSFEM_EINVAL, "model_save: surrogates of the channels medium are not saved");
   ModelFileHeader h{};
@@ -2997,6 +3006,10 @@ int stomsfem_model_save(const stomsfem_model* model, const char* path) {
   h.KD = model->KD;
   h.PP = model->PP;
   h.lv_max = model->lv_max;
+  if (model->kind == 9) {  // the oversampling and the element side travel in nn and lv_max
+    h.nn = model->os_o;
+    h.lv_max = model->os_m;
+  }
   h.rows = model->rows;
   h.adam_t = model->adam_t;
   h.box = model->box;
@@ -3034,9 +3047,12 @@ int stomsfem_model_load(const char* path, stomsfem_model** model) {
     std::fclose(f);
     return fail(STOMSFEM_EVERSION, "model_load: written by ABI version " + std::to_string(h.abi));
   }
-  const bool sane = h.kind >= 1 && h.kind <= 3 && h.ncx >= 1 && h.ncy >= 1 && h.ncx <= 4096 && h.ncy <= 4096 &&
-                    h.m >= 1 && h.m <= 48 && h.rows >= 0 && h.rmax >= 0 && h.rmax <= 8 && h.KD >= 0 && h.PP >= 0 &&
-                    h.KD <= 4096 && h.PP <= 4096 && (h.kind != 3 || (h.nn >= RI_NN_MIN && h.nn <= RI_NN_MAX));
+  const bool sane = ((h.kind >= 1 && h.kind <= 3) || h.kind == 9) && h.ncx >= 1 && h.ncy >= 1 && h.ncx <= 4096 &&
+                    h.ncy <= 4096 && h.m >= 1 && h.m <= 48 && h.rows >= 0 && h.rmax >= 0 && h.rmax <= 8 &&
+                    h.KD >= 0 && h.PP >= 0 && h.KD <= 4096 && h.PP <= 4096 &&
+                    (h.kind != 3 || (h.nn >= RI_NN_MIN && h.nn <= RI_NN_MAX)) &&
+                    (h.kind != 9 || (h.m >= 2 && h.m <= 32 && h.rmax == 8 && h.nn >= 0 && h.lv_max >= 1 &&
+                                     h.lv_max + 2 * h.nn == h.m && h.KD == rb_pad_kd(h.m)));
   if (!sane) {
     std::fclose(f);
     return fail(STOMSFEM_EINVAL, "model_load: corrupt header");
@@ -3058,6 +3074,12 @@ int stomsfem_model_load(const char* path, stomsfem_model** model) {
   md->lo = h.lo;
   md->hi = h.hi;
   md->fam = h.fam;
+  if (md->kind == 9) {
+    md->os_o = h.nn;
+    md->os_m = h.lv_max;
+    md->nn = 0;
+    md->lv_max = -1;
+  }
   int rc = STOMSFEM_OK;
   uint32_t id = 0;
   for (const ArraySpec& a : model_arrays(md)) {

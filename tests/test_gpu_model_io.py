@@ -89,3 +89,49 @@ def test_surrogate_model_roundtrip(sm, tmp_path, base, m, nc):
     sm.mlp_train(again, 1, 1e-3)
     model.free()
     again.free()
+
+
+def test_oversampled_reduced_basis_model_roundtrip(sm, tmp_path):
+    wl = W.MESH8
+    xi_tr = torch.from_numpy(W.uniform_xi(24, wl.nxi, 7104)).cuda()
+    model = sm.reduce_os(sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params()), wl.nc, wl.nc, wl.m, 4)
+    path = str(tmp_path / "rb_os.bin")
+    model.save(path)
+    again = sm.model_load(path)
+    assert (again.ncx, again.ncy, again.m) == (wl.nc, wl.nc, wl.m)
+    again.patch_m = model.patch_m
+    for which in ("r", "lambda", "Z", "phibar"):
+        np.testing.assert_array_equal(again.export(which), model.export(which))
+    xi = torch.from_numpy(W.uniform_xi(150, wl.nxi, 7105)).cuda()
+    a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)
+    for prec in (sm.PREC_F32, sm.PREC_F64):
+        S1 = sm.reduce_os_apply(model, a32, precision=prec)
+        S2 = sm.reduce_os_apply(again, a32, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(S1, S2)
+    model.free()
+    again.free()
+
+
+def test_model_kinds_are_not_interchangeable(sm):
+    # an oversampled reduced-basis model is refused by the other online
+    # stages, and the other models by its online stage, before any launch
+    wl = W.MESH8
+    xi_tr = torch.from_numpy(W.uniform_xi(8, wl.nxi, 7106)).cuda()
+    a = sm.coef_bumps(xi_tr, wl.nfine, **wl.coef_params())
+    os_model = sm.reduce_os(a, wl.nc, wl.nc, wl.m, 4)
+    plain = sm.reduce(a, wl.nc, wl.nc, wl.m)
+    S = torch.empty((8, wl.M, 16), dtype=torch.float64, device="cuda")
+    kappa = torch.ones((8, wl.nfine, wl.nfine), dtype=torch.float64, device="cuda")
+    xi = torch.zeros((8, wl.M, 4), dtype=torch.float64, device="cuda")
+    rc = sm.lib().stomsfem_kl_interp_apply(os_model.handle, xi.data_ptr(), kappa.data_ptr(), 8, S.data_ptr(), None,
+                                           None, None)
+    assert rc == sm.EINVAL
+    with pytest.raises(sm.StomsfemError) as e:
+        sm.reduce_apply(os_model, a)
+    assert e.value.code == sm.EINVAL
+    with pytest.raises(sm.StomsfemError) as e:
+        sm.reduce_os_apply(plain, a)
+    assert e.value.code == sm.EINVAL
+    os_model.free()
+    plain.free()
