@@ -828,6 +828,84 @@ def measure_rb_os(wl, a, o, S_os, U_os, t_os, ntrain=64, r_max=8, tail_tol=1e-6)
     return out
 
 
+def measure_rb_os_channels(log, nsub=16, ntrain=64, N=1024, r_max=8, tail_tol=1e-6):
+    """Reduced basis on oversampled patches in the high-contrast medium (the
+    setting of the example of Sec. 5.2: oversampling, Petrov-Galerkin, a few
+    reduced modes per patch): the channels-and-inclusions medium at H/h = 8
+    (64 x 64 coarse mesh, 512 x 512 fine), restricted to the nsub x nsub coarse
+    elements with the most features, ratios 2 and 3; ntrain training samples
+    (seed 6005), N test samples (seed 6006); both online stages against the
+    oversampled solve of the same pairs."""
+    import numpy as np
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.CHANNELS64
+    m = 8
+    kind, x0, y0, size = W.channel_geometry(wl)
+    g = [torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (kind, x0, y0, size)]
+    fmap = sm.feature_map(wl.nc * m, *g)
+    # the sub-domain of nsub x nsub elements (aligned to nsub) holding the most distinct features
+    f = fmap.cpu().numpy()
+    w = nsub * m
+    best, org = -1, (0, 0)
+    for by in range(0, wl.nc * m, w):
+        for bx in range(0, wl.nc * m, w):
+            nf = len(np.unique(f[by:by + w, bx:bx + w]))
+            if nf > best:
+                best, org = nf, (by, bx)
+    by, bx = org
+
+    def field(n, seed):
+        xi = torch.from_numpy(W.normal_xi(n, wl.nxi, seed)).cuda()
+        return sm.coef_features(fmap, wl.nxi, xi, wl.decades)[:, by:by + w, bx:bx + w].contiguous()
+
+    a_tr, a = field(ntrain, 6005), field(N, 6006)
+    out = {"workload": f"channels medium, H/h = {m}, the {nsub}x{nsub} coarse elements at fine offset ({by}, {bx}) "
+                       f"({best - 1} features), {ntrain} training samples, r<={r_max} (tail {tail_tol:g}), {N} samples",
+           "contrast": float(a.max() / a.min())}
+    for o in (m // 2, m):
+        S_os = torch.empty((N, nsub * nsub, 16), dtype=torch.float64, device="cuda")
+        t_os = _timed(lambda: sm.upscale_os(a, nsub, nsub, m, o, S=S_os), reps=2)
+        U_os, _, _ = sm.coarse_solve_pg(S_os, nsub, nsub)
+        t0 = time.perf_counter()
+        model = sm.reduce_os(a_tr, nsub, nsub, m, o, r_max=r_max, tail_tol=tail_tol)
+        t_off = time.perf_counter() - t0
+        r = model.export("r")
+        res = {"patch_cells": m + 2 * o, "offline_s": t_off, "modes_min": int(r.min()),
+               "modes_mean": float(r.mean()), "modes_max": int(r.max()),
+               "oversampled_solve_pairs_per_s": N * nsub * nsub / t_os}
+        S = torch.empty_like(S_os)
+        st = torch.empty((N, nsub * nsub), dtype=torch.int32, device="cuda")
+        a32 = a.float()
+        for key, prec, aa in (("fp32_matrix_core", sm.PREC_F32, a32), ("fp64", sm.PREC_F64, a)):
+            t_on = _timed(lambda: sm.reduce_os_apply(model, aa, S=S, status=st, precision=prec), reps=3)
+            scale = S_os.abs().amax(dim=2, keepdim=True)
+            rel = ((S - S_os).abs() / scale).amax(dim=2)
+            U, _, _ = sm.coarse_solve_pg(S, nsub, nsub)
+            d = torch.linalg.norm(U - U_os, dim=1) / torch.linalg.norm(U_os, dim=1)
+            res[key] = {"pairs_per_s": N * nsub * nsub / t_on, "vs_oversampled_solve": t_os / t_on,
+                        "non_ok_pairs": int((st != 0).sum().item()), "max_S_rel_err": float(rel.max()),
+                        "median_S_rel_err": float(rel.median()),
+                        "fraction_of_pairs_above": {f"{t:g}": float((rel > t).float().mean()) for t in (1e-6, 1e-3, 1e-1)},
+                        "median_coarse_rel_err": float(d.median()), "max_coarse_rel_err": float(d.max())}
+        # the same pairs, coefficients rounded to FP32 for both sides: the matrix-core stage's own error
+        S32_os = sm.upscale_os(a32, nsub, nsub, m, o)
+        sm.reduce_os_apply(model, a32, S=S, status=st, precision=sm.PREC_F64)
+        S64 = S.clone()
+        sm.reduce_os_apply(model, a32, S=S, status=st, precision=sm.PREC_F32)
+        res["fp32_stage_vs_fp64_stage_max_rel"] = float(((S - S64).abs() / S64.abs().amax(dim=2, keepdim=True)).max())
+        res["fp64_stage_on_fp32_a_vs_solve_max_rel"] = float(
+            ((S64 - S32_os).abs() / S32_os.abs().amax(dim=2, keepdim=True)).max())
+        out[f"ratio_{(m + 2 * o) // m}"] = res
+        log(f"reduced basis, oversampled, channels medium, ratio {(m + 2 * o) // m}: {res}")
+        model.free()
+        del a32, S32_os, S64
+    return out
+
+
 def measure_collocation(log, wl=None, level=4, errors=True, plain_chunk=1024):
     """Sparse-grid stochastic collocation with search-and-plug-in
     dictionaries (Sec. 4.1.2, global SC methods; Sec. 5.2)
@@ -1305,7 +1383,8 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, collocation, "
+                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, rb_os_channels, "
+                         "collocation, "
                          "two_level, gauss, gauss_paper_mesh); "
                          "default: all of them")
     ap.add_argument("--calib-copy", action="store_true",
@@ -1514,6 +1593,9 @@ def main():
         if want("oversampling"):
             lg("oversampled Petrov-Galerkin upscaling at the 8x8 mesh")
             out["oversampled_petrov_galerkin"] = measure_oversampling(lg)
+        if want("rb_os_channels"):
+            lg("reduced basis on oversampled patches in the channels medium")
+            out["reduced_basis_oversampled_channels"] = measure_rb_os_channels(lg)
         if want("collocation"):
             lg("sparse-grid collocation with dictionaries at the 8x8 mesh")
             from paper_1607_00693_amd import workloads as W

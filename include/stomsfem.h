@@ -403,7 +403,7 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * fewer snapshots than interior unknowns, 3 ntrain < (m-1)^2, the modes come
  * from the 3 ntrain x 3 ntrain snapshot matrix in the energy inner product,
  * the method of snapshots).  Where the FP64 band of a cell problem does not
- * fit a workgroup's LDS the training phi come from the FP32 factorisation
+ * fit a workgroup's 160 KB of LDS (m > 26) the training phi come from the FP32 factorisation
  * with FP64 residual refinement, and the call fails with ENOCONV if any of
  * them does not converge.  Allocates device memory (owned by the model) and
  * synchronises `stream` before returning.

@@ -1471,7 +1471,7 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   A((void**)&phi, sizeof(double) * (size_t)b.nsamples * Mc * 3 * nI);
   A((void**)&work, sizeof(double) * (size_t)rb_work_doubles(b.ncx, b.ncy, m, (int)b.nsamples));
   // snapshots through the refined kernel where the FP64 band does not fit LDS
-  const bool refined_phi = cell_phi_lds_bytes(m) > 64 * 1024;
+  const bool refined_phi = cell_phi_lds_bytes(m) > CELL_PHI_LDS_MAX;
   int64_t* fail_list = nullptr;
   unsigned long long* fail_count = nullptr;
   if (refined_phi) {

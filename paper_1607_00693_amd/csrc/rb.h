@@ -47,6 +47,8 @@ struct RbApplyArgs {
 
 hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStream_t st);
 size_t cell_phi_lds_bytes(int m);
+// LDS of one workgroup on gfx950: the FP64 snapshot kernel serves m <= 26
+constexpr size_t CELL_PHI_LDS_MAX = 160 * 1024;
 hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st);
 // Work doubles of the offline build and whether it takes the dual form (the
 // method of snapshots, 3 ntrain < (m-1)^2).

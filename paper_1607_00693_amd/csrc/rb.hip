@@ -137,11 +137,22 @@ hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStre
   const int64_t blocks = args.npairs < 65536 ? args.npairs : 65536;
   if (blocks == 0) return hipSuccess;
   const size_t lds = cell_phi_lds_bytes(args.m);
-  if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL(cell_phi_kernel<float>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
-  else
-    hipLaunchKernelGGL(cell_phi_kernel<double>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
-  return hipGetLastError();
+  if (lds > CELL_PHI_LDS_MAX) return hipErrorInvalidValue;
+  // above 64 KB the kernel's dynamic-LDS limit is raised on the current
+  // device before the launch
+  hipError_t e = hipSuccess;
+  if (a_dtype == STOMSFEM_F32) {
+    if (lds > 65536)
+      e = hipFuncSetAttribute((const void*)cell_phi_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e == hipSuccess) hipLaunchKernelGGL(cell_phi_kernel<float>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
+  } else {
+    if (lds > 65536)
+      e = hipFuncSetAttribute((const void*)cell_phi_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e == hipSuccess) hipLaunchKernelGGL(cell_phi_kernel<double>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

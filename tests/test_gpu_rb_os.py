@@ -261,3 +261,21 @@ def test_full_size_sampled_against_oracle(sm, orc):
         worst = max(worst, np.abs(S[s, K] - R.ravel()).max() / np.abs(R).max())
     say(f"full size: worst sampled rel err {worst:.2e}")
     assert worst < 2e-4
+
+
+def test_high_contrast_patches_of_24_cells(sm, orc):
+    # two-phase medium (1 or 1e4 per fine cell), patches of 24 cells (ratio
+    # 3): the FP64 snapshots of the build (band in 123 KB of LDS) and the
+    # exact reproduction of the training samples (r = 3 for two samples)
+    nc, m, o = 3, 8, 8
+    rng = np.random.default_rng(2109)
+    a_np = np.where(rng.random((2, nc * m, nc * m)) < 0.3, 1e4, 1.0)
+    a = torch.from_numpy(a_np).cuda()
+    say("high-contrast patches of 24 cells")
+    model = sm.reduce_os(a, nc, nc, m, o, r_max=8, tail_tol=0.0)
+    r = np.zeros(nc * nc, dtype=np.int32)
+    sm.lib().stomsfem_model_export(model.handle, 0, r.ctypes.data, r.nbytes)
+    assert (r == 3).all()
+    S = sm.reduce_os_apply(model, a).cpu().numpy()
+    R, _ = orc.upscale_os(a_np, nc, nc, m, o)
+    assert _rel_pairs(S, R) < 1e-8
