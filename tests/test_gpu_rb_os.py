@@ -6,9 +6,10 @@ the GPU's plain oversampled solve.
 Tolerances: the FP32 matrix-core online stage (FP32 GEMM with FP32
 accumulation over the patch's Mp^2 elements, FP64 solve and recombination)
 stays within 2e-4 relative per pair of the FP64 stage and of the oracle; the
-FP64 online stage reproduces the oracle's S16 to 1e-7 relative per pair (both sides build the same energy-KL subspace from the
-same snapshots; their eigen-solvers differ, so agreement is bounded by the
-spectral gap after the last kept mode, not by rounding); where the reduced
+FP64 online stage reproduces the oracle's S16 to 1e-7 relative per pair
+(both sides build the same energy-KL subspace from the same snapshots; their
+eigen-solvers differ, so agreement is bounded by the spectral gap after the
+last kept mode, not by rounding); where the reduced
 space holds the patch solutions exactly (a training sample with every mode
 kept, or a patch with fewer interior unknowns than modes) S16 equals the
 oversampled solve to 1e-9.
