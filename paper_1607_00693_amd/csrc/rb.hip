@@ -781,13 +781,13 @@ constexpr int RBA_PF = RBA_SAMPLES * RBA_KC / 256;  // coefficients per thread a
 // is the FP64 solve for c and the recombination at K's corners (16 entries
 // per pair).  vec_ok: every patch row starts on a 16-byte boundary.
 //
-// A workgroup of the plain variant takes tpw consecutive sample tiles of its
-// patch: the (tile, chunk) steps form one loop, so the next step's
-// coefficients (the next tile's first chunk after a tile's last) are in
-// flight during the current step's products and, at the end of a tile,
-// during its solves (tpw = 1 for the oversampled variant).
-template <int RMAX, int PP, typename TA, bool OS = false>
-__global__ __launch_bounds__(256, OS ? 1 : 2) void rb_apply_mfma_kernel(RbApplyArgs ra, int64_t ntiles,
+// MT = true (plain variant, single-chunk tiles): a workgroup takes tpw
+// consecutive sample tiles of its patch and the (tile, chunk) steps form one
+// loop, so the next tile's coefficients are in flight during the current
+// tile's products and solves (two wavefronts per SIMD kept for the extra
+// prefetch registers).  MT = false: one tile per workgroup (tpw = 1).
+template <int RMAX, int PP, typename TA, bool OS = false, bool MT = false>
+__global__ __launch_bounds__(256, MT ? 2 : 1) void rb_apply_mfma_kernel(RbApplyArgs ra, int64_t ntiles,
                                                                        int patch_fast, int vec_ok, int tpw) {
   using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
   const UpArgs& args = ra.up;
@@ -854,9 +854,7 @@ __global__ __launch_bounds__(256, OS ? 1 : 2) void rb_apply_mfma_kernel(RbApplyA
       v[4 * q + 3] = x[3];
     }
   };
-  // the oversampled variant keeps one tile per workgroup: its FP64 solves
-  // need the registers that the next tile's prefetch would hold
-  const int nch = KD / RBA_KC, nit = (OS ? 1 : tpw) * nch;
+  const int nch = KD / RBA_KC, nit = (MT ? tpw : 1) * nch;
   auto load_step = [&](int it, float (&v)[RBA_PF]) {
     const int64_t s0 = (tile0 + it / nch) * RBA_SAMPLES;
     const int e0 = (it % nch) * RBA_KC;
@@ -945,7 +943,7 @@ __global__ __launch_bounds__(256, OS ? 1 : 2) void rb_apply_mfma_kernel(RbApplyA
     }
   };
   load_step(0, pf);
-  if constexpr (OS) {
+  if constexpr (!MT) {
     for (int it = 0; it < nch; ++it) step(it);
     finish_tile(tile0);
   } else {
@@ -956,11 +954,15 @@ __global__ __launch_bounds__(256, OS ? 1 : 2) void rb_apply_mfma_kernel(RbApplyA
   }
 }
 
-// Tiles per workgroup: about four workgroups per CU (1024) when the batch
-// has that many tiles, at most eight tiles each (measured at the 8x8 mesh,
-// 16 384 samples: 0.205 ms with one tile per workgroup, 0.175 ms with four,
-// 0.170 ms with eight).
-static int rba_tiles_per_workgroup(int64_t ntiles, int Mc) {
+// Tiles per workgroup.  Where a tile is a single chunk (m <= 8) nothing
+// overlaps its loads otherwise: about four workgroups per CU (1024) when the
+// batch has that many tiles, at most eight tiles each (8x8 mesh, 16 384
+// samples: 0.205 ms with one tile per workgroup, 0.175 ms with four, 0.170 ms
+// with eight).  Longer tiles already overlap chunk with chunk, and grouping
+// them only costs parallelism (32x32 mesh, H/h = 32: 6.2 ms with one, 6.8 ms
+// with eight).
+static int rba_tiles_per_workgroup(int64_t ntiles, int Mc, int KD) {
+  if (KD > RBA_KC) return 1;
   const int64_t t = ntiles * Mc / 1024;
   return (int)(t < 1 ? 1 : t > 8 ? 8 : t);
 }
@@ -983,17 +985,27 @@ hipError_t launch_rb_apply(const RbApplyArgs& ra, int a_dtype, bool f64, hipStre
   if (ra.PP != 80 || ra.KD % RBA_KC != 0 || ra.KD < u.m * u.m) return hipErrorInvalidValue;
   const int Mc = u.ncx * u.ncy;
   const int64_t ntiles = (u.nsamples + RBA_SAMPLES - 1) / RBA_SAMPLES;
-  const int tpw = rba_tiles_per_workgroup(ntiles, Mc);
+  const int tpw = rba_tiles_per_workgroup(ntiles, Mc, ra.KD);
   const int64_t nb = (ntiles + tpw - 1) / tpw * Mc;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   const int elem = a_dtype == STOMSFEM_F32 ? 4 : 8;
   const int patch_fast = u.m * elem < 128 ? 1 : 0;
-  if (a_dtype == STOMSFEM_F32)
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
-                       patch_fast, 1, tpw);
-  else
-    hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
-                       patch_fast, 1, tpw);
+  // single-chunk tiles take the multi-tile variant
+  if (ra.KD == RBA_KC) {
+    if (a_dtype == STOMSFEM_F32)
+      hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float, false, true>), dim3((unsigned)nb), dim3(256), 0, st, ra,
+                         ntiles, patch_fast, 1, tpw);
+    else
+      hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double, false, true>), dim3((unsigned)nb), dim3(256), 0, st,
+                         ra, ntiles, patch_fast, 1, tpw);
+  } else {
+    if (a_dtype == STOMSFEM_F32)
+      hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, float>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
+                         patch_fast, 1, tpw);
+    else
+      hipLaunchKernelGGL((rb_apply_mfma_kernel<8, 80, double>), dim3((unsigned)nb), dim3(256), 0, st, ra, ntiles,
+                         patch_fast, 1, tpw);
+  }
   return hipGetLastError();
 }
 
