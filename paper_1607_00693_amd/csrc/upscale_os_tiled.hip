@@ -1,6 +1,7 @@
 // Oversampled Petrov-Galerkin local upscaling, register-tiled (Sec. 2.2
 // remark on oversampling; eq. stiffness_local_petrov) for patches of
-// M = 4T fine cells per side (M = 16: oversampling ratio 2 at H/h = 8).
+// M = 4T fine cells per side, M = 16, 24, 32 (M = 16: oversampling ratio 2
+// at H/h = 8; M = 32: ratio 2 at H/h = 16).
 //
 // Same quantities as upscale_os.hip (corner values psi^j(x_k) and Galerkin
 // products A_jl = psi^j . K^K p^l as Schur products f^j . K_II^{-1} t with
@@ -109,7 +110,10 @@ __device__ __forceinline__ double ot_rK(int l, int px, int py, int cx, int cy, i
 }
 
 template <int M, int T, typename TA>
-__global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
+// M = 32 (T = 8) runs one wavefront per SIMD: its tiles and ten right-hand
+// sides take the whole register file (256 VGPRs and about 100 AGPRs, no
+// scratch; at two wavefronts per SIMD it spilled 444 bytes per lane).
+__global__ __launch_bounds__(64, M == 32 ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
   constexpr int NT = OT_NT, NV = OT_NV;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(64, 2) void upscale_os_tiled_kernel(OtArgs args) {
   }
 }
 
-bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16 || m + 2 * o == 24; }
+bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16 || m + 2 * o == 24 || m + 2 * o == 32; }
 
 template <int M, int T>
 static void launch_ot(const OtArgs& args, int a_dtype, hipStream_t st) {
@@ -567,8 +571,10 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
   const OtArgs args{up, o, list, nlist};
   if (up.m + 2 * o == 16)
     launch_ot<16, 4>(args, a_dtype, st);
-  else
+  else if (up.m + 2 * o == 24)
     launch_ot<24, 6>(args, a_dtype, st);
+  else
+    launch_ot<32, 8>(args, a_dtype, st);
   return hipGetLastError();
 }
 

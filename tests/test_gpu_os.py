@@ -114,7 +114,7 @@ def test_float32_coefficients(sm, orc):
     assert s_relerr(S.cpu().numpy(), S_ref) <= STOL
 
 
-@pytest.mark.parametrize("m,o", [(4, 2), (8, 4), (8, 8)])
+@pytest.mark.parametrize("m,o", [(4, 2), (8, 4), (8, 8), (16, 8)])
 def test_non_positive_coefficient_sets_status(sm, m, o):
     ncx, ncy = 3, 3
     a = torch.from_numpy(W.uniform_array((2, ncy * m, ncx * m), 0.5, 2.0, 1301)).cuda()
