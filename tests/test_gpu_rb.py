@@ -98,6 +98,26 @@ def test_rb_online_mfma_fp32(sm, orc, setup):
     assert rel(S.cpu().numpy(), S_plain) < 1e-3
 
 
+def test_rb_mfma_multi_tile_workgroups_with_a_partial_group(sm, setup):
+    # at H/h = 8 a workgroup takes up to eight 128-sample tiles of its patch;
+    # 515 tiles per patch (the last one ragged) leave the last workgroup of
+    # each patch three tiles: every pair against the FP64 stage (2e-4)
+    nc, m = setup["nc"], setup["m"]
+    wl = W.MESH8
+    N = 128 * 515 - 58
+    say(f"multi-tile workgroups: {N} samples")
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1009)).cuda()
+    a32 = sm.coef_bumps(xi, wl.nfine, **wl.coef_params(), dtype=torch.float32)[:, : nc * m, : nc * m].contiguous()
+    st = torch.full((N, nc * nc), 99, dtype=torch.int32, device="cuda")
+    S32 = sm.reduce_apply(setup["model"], a32, status=st, precision=sm.PREC_F32)
+    S64 = sm.reduce_apply(setup["model"], a32, precision=sm.PREC_F64)
+    torch.cuda.synchronize()
+    assert (st == sm.OK).all()
+    err = ((S32 - S64).abs().amax(dim=2) / S64.abs().amax(dim=2)).max().item()
+    say(f"  max rel err vs FP64 stage {err:.2e}")
+    assert err < 2e-4
+
+
 def test_rb_coarse_solution_error(sm, orc, setup):
     say("coarse solution through the reduced path")
     a = setup["a_te"]
