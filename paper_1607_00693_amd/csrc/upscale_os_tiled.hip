@@ -30,9 +30,15 @@ namespace stomsfem {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
   } while (0)
 
-constexpr int OT_NT = 4;                 // tiles per window side
-constexpr int OT_G = 10;                 // lanes per pair
-constexpr int OT_SLOTS = 64 / OT_G;      // pairs per wavefront (6)
+// The live window is NT x NT tiles; its NT(NT+1)/2 lower tiles sit in as
+// many lanes of one pair (NT = 4: ten lanes, six pairs per wavefront; the
+// 40- to 64-cell patches take T = 8 and NT = 5..8: 15 to 36 lanes, four to
+// one pairs per wavefront).
+template <int NT>
+struct OtShape {
+  static constexpr int G = NT * (NT + 1) / 2;  // lanes per pair
+  static constexpr int SLOTS = 64 / G;         // pairs per wavefront
+};
 constexpr int OT_NV = 10;                // columns: lifts f^0..2, corner tests 0..3, r^0..2
 constexpr int OT_NY = 21;                // Schur products f^jv . K_II^{-1} (column 3 + tv)
 constexpr int OT_RED = 9 + 1;            // reduced over the lanes: boundary terms, bad flag
@@ -45,12 +51,12 @@ struct OtArgs {
   int64_t nlist;
 };
 
-template <int T>
+template <int T, int NT>
 struct OtLdsCore {
-  static constexpr int NT = OT_NT, FW = NT * T;
+  static constexpr int FW = NT * T;
   union {
-    double pw[T][NT][T];     // panel rows: pw[k][R'][i] = W(row R'*T+i of the panel, column k)
-    double red[OT_G][OT_RED];  // final reduction (after the last panel)
+    double pw[T][NT][T];                   // panel rows: pw[k][R'][i] = W(row R'*T+i of the panel, column k)
+    double red[OtShape<NT>::G][OT_RED];    // final reduction (after the last panel)
   };
   double Y[OT_NY];            // Schur products f^jv . K_II^{-1} t, accumulated by the diagonal lane
   double L[T * (T - 1) / 2];  // strict lower part of the unit factor of the diagonal tile
@@ -60,9 +66,9 @@ struct OtLdsCore {
   double f[FW][OT_NV];        // right-hand sides of the live rows (circular); pivot rows hold D^{-1} y
 };
 
-template <int T>
-struct OtLds : OtLdsCore<T> {
-  static constexpr int PADB = ((80 - (int)(sizeof(OtLdsCore<T>) % 128)) + 128) % 128;
+template <int T, int NT>
+struct OtLds : OtLdsCore<T, NT> {
+  static constexpr int PADB = ((80 - (int)(sizeof(OtLdsCore<T, NT>) % 128)) + 128) % 128;
   char pad[PADB == 0 ? 128 : PADB];
 };
 
@@ -109,23 +115,26 @@ __device__ __forceinline__ double ot_rK(int l, int px, int py, int cx, int cy, i
   return v;
 }
 
+// T = 8 (M = 32 ... 64) runs one wavefront per SIMD: its tiles and ten
+// right-hand sides take the whole register file (at M = 32, 256 VGPRs and
+// about 100 AGPRs, no scratch; at two wavefronts per SIMD it spilled 444
+// bytes per lane).
 template <int M, int T, typename TA>
-// M = 32 (T = 8) runs one wavefront per SIMD: its tiles and ten right-hand
-// sides take the whole register file (256 VGPRs and about 100 AGPRs, no
-// scratch; at two wavefronts per SIMD it spilled 444 bytes per lane).
-__global__ __launch_bounds__(64, M == 32 ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
-  constexpr int NT = OT_NT, NV = OT_NV;
+__global__ __launch_bounds__(64, T == 8 ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
+  constexpr int NT = M / T, NV = OT_NV, OT_G = OtShape<NT>::G, OT_SLOTS = OtShape<NT>::SLOTS;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
   constexpr int FW = NT * T;
-  using Lds = OtLds<T>;
+  using Lds = OtLds<T, NT>;
   __shared__ Lds lds_all[OT_SLOTS];
 
   const int lane = threadIdx.x & 63;
   if (lane >= OT_SLOTS * OT_G) return;
   const int q = lane / OT_G, g = lane - q * OT_G;
   Lds& sh = lds_all[q];
-  const int P = g >= 6 ? 3 : g >= 3 ? 2 : g >= 1 ? 1 : 0;
+  // lane g of the pair owns the residue pair {P, Q}, Q <= P < NT, g = P(P+1)/2 + Q
+  int P = 0;
+  while ((P + 1) * (P + 2) / 2 <= g) ++P;
   const int Q = g - P * (P + 1) / 2;
 
   const int64_t nout = args.list ? args.nlist : args.up.npairs;
@@ -553,11 +562,17 @@ __global__ __launch_bounds__(64, M == 32 ? 1 : 2) void upscale_os_tiled_kernel(O
   }
 }
 
-bool upscale_os_tiled_supports(int m, int o) { return m + 2 * o == 16 || m + 2 * o == 24 || m + 2 * o == 32; }
+// patches of 16 and 24 cells (T = 4, 6 and NT = 4) and of 32 to 64 cells in
+// steps of 8 (T = 8, NT = 4 ... 8)
+bool upscale_os_tiled_supports(int m, int o) {
+  const int M = m + 2 * o;
+  return M == 16 || M == 24 || (M >= 32 && M <= 64 && M % 8 == 0);
+}
 
 template <int M, int T>
 static void launch_ot(const OtArgs& args, int a_dtype, hipStream_t st) {
-  const int64_t blocks = ((args.list ? args.nlist : args.up.npairs) + OT_SLOTS - 1) / OT_SLOTS;
+  constexpr int SLOTS = OtShape<M / T>::SLOTS;
+  const int64_t blocks = ((args.list ? args.nlist : args.up.npairs) + SLOTS - 1) / SLOTS;
   if (a_dtype == STOMSFEM_F32)
     hipLaunchKernelGGL((upscale_os_tiled_kernel<M, T, float>), dim3((unsigned)blocks), dim3(64), 0, st, args);
   else
@@ -569,12 +584,15 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
   if (!upscale_os_tiled_supports(up.m, o)) return hipErrorInvalidValue;
   if ((list ? nlist : up.npairs) <= 0) return hipSuccess;
   const OtArgs args{up, o, list, nlist};
-  if (up.m + 2 * o == 16)
-    launch_ot<16, 4>(args, a_dtype, st);
-  else if (up.m + 2 * o == 24)
-    launch_ot<24, 6>(args, a_dtype, st);
-  else
-    launch_ot<32, 8>(args, a_dtype, st);
+  switch (up.m + 2 * o) {
+    case 16: launch_ot<16, 4>(args, a_dtype, st); break;
+    case 24: launch_ot<24, 6>(args, a_dtype, st); break;
+    case 32: launch_ot<32, 8>(args, a_dtype, st); break;
+    case 40: launch_ot<40, 8>(args, a_dtype, st); break;
+    case 48: launch_ot<48, 8>(args, a_dtype, st); break;
+    case 56: launch_ot<56, 8>(args, a_dtype, st); break;
+    default: launch_ot<64, 8>(args, a_dtype, st); break;
+  }
   return hipGetLastError();
 }
 
