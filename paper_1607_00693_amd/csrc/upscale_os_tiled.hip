@@ -33,7 +33,7 @@ namespace stomsfem {
 // The live window is NT x NT tiles; its NT(NT+1)/2 lower tiles sit in as
 // many lanes of one pair (NT = 4: ten lanes, six pairs per wavefront; the
 // 40- to 64-cell patches take T = 8 and NT = 5..8: 15 to 36 lanes, four to
-// one pairs per wavefront).
+// one pairs per wavefront; 60-cell patches T = 6 and NT = 10: 55 lanes).
 template <int NT>
 struct OtShape {
   static constexpr int G = NT * (NT + 1) / 2;  // lanes per pair
@@ -120,7 +120,7 @@ __device__ __forceinline__ double ot_rK(int l, int px, int py, int cx, int cy, i
 // about 100 AGPRs, no scratch; at two wavefronts per SIMD it spilled 444
 // bytes per lane).
 template <int M, int T, typename TA>
-__global__ __launch_bounds__(64, T == 8 ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
+__global__ __launch_bounds__(64, (T == 8 || M / T > 8) ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
   constexpr int NT = M / T, NV = OT_NV, OT_G = OtShape<NT>::G, OT_SLOTS = OtShape<NT>::SLOTS;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
@@ -562,11 +562,12 @@ __global__ __launch_bounds__(64, T == 8 ? 1 : 2) void upscale_os_tiled_kernel(Ot
   }
 }
 
-// patches of 16 and 24 cells (T = 4, 6 and NT = 4) and of 32 to 64 cells in
-// steps of 8 (T = 8, NT = 4 ... 8)
+// patches of 16 and 24 cells (T = 4, 6 and NT = 4), of 32 to 64 cells in
+// steps of 8 (T = 8, NT = 4 ... 8), and of 60 cells (T = 6, NT = 10: 55 lanes
+// per pair; H/h = 20 at oversampling ratio 3)
 bool upscale_os_tiled_supports(int m, int o) {
   const int M = m + 2 * o;
-  return M == 16 || M == 24 || (M >= 32 && M <= 64 && M % 8 == 0);
+  return M == 16 || M == 24 || M == 60 || (M >= 32 && M <= 64 && M % 8 == 0);
 }
 
 template <int M, int T>
@@ -591,6 +592,7 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
     case 40: launch_ot<40, 8>(args, a_dtype, st); break;
     case 48: launch_ot<48, 8>(args, a_dtype, st); break;
     case 56: launch_ot<56, 8>(args, a_dtype, st); break;
+    case 60: launch_ot<60, 6>(args, a_dtype, st); break;
     default: launch_ot<64, 8>(args, a_dtype, st); break;
   }
   return hipGetLastError();

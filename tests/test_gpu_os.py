@@ -86,12 +86,13 @@ def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
 
 
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(10, 12, 4, 4, 1), (20, 11, 3, 3, 1), (16, 16, 3, 3, 1),
-                                           (24, 8, 3, 3, 2), (40, 8, 2, 2, 1), (32, 15, 3, 3, 1),
-                                           (24, 20, 3, 3, 1), (32, 16, 3, 2, 1)])
+                                           (24, 8, 3, 3, 2), (40, 8, 2, 2, 1), (20, 20, 3, 3, 1),
+                                           (32, 15, 3, 3, 1), (24, 20, 3, 3, 1), (32, 16, 3, 2, 1)])
 def test_large_patches_match_oracle(sm, orc, m, o, ncx, ncy, N):
     # patches of 34 to 64 cells (the paper's Sec. 5.3 geometry has 64-cell
     # patches: h = 2^-11, H/h = 32, ratio 2).  Sides 40, 48, 56 and 64 take
-    # the register-tiled kernel (8 x 8 tiles, 15 to 36 lanes per pair); the
+    # the register-tiled kernel (8 x 8 tiles, 15 to 36 lanes per pair), 60
+    # (Sec. 5.2: H/h = 20, ratio 3) the same with 6 x 6 tiles and 55 lanes; the
     # others one wavefront per pair with up to 104 KB of LDS, the trailing
     # triangle in 17 or 33 entries per lane, the entering row's band and
     # right-hand sides in two rounds of the wavefront
