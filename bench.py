@@ -781,6 +781,34 @@ def measure_oversampling(log, N=16384, rb_ntrain=64):
     return out
 
 
+def measure_oversampling_large(log):
+    """Oversampled Petrov-Galerkin upscaling with patches of 40 to 64 cells
+    (log-normal coefficients, sigma = 1, seed 11): 48 cells (16x16 coarse,
+    H/h = 16, ratio 3, 64 samples), 60 cells (12x12 coarse, H/h = 20, ratio 3:
+    the geometry of the high-contrast example of Sec. 5.2, 64 samples) and 64
+    cells (16x16 coarse, H/h = 32, ratio 2, 16 samples)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    out = {}
+    for nc, m, o, N in ((16, 16, 16, 64), (12, 20, 20, 64), (16, 32, 16, 16)):
+        a = torch.from_numpy(W.lognormal_field((N, nc * m, nc * m), 1.0, 11)).cuda()
+        S = torch.empty((N, nc * nc, 16), dtype=torch.float64, device="cuda")
+        st = torch.empty((N, nc * nc), dtype=torch.int32, device="cuda")
+        t = _timed(lambda: sm.upscale_os(a, nc, nc, m, o, S=S, status=st), reps=3)
+        fl = os_flops_per_pair(m, o)
+        pairs = N * nc * nc
+        out[f"patch_{m + 2 * o}"] = {"mesh": f"{nc}x{nc} coarse, H/h={m}, oversample {o}, {N} samples",
+                                     "ms": t * 1e3, "pairs_per_s": pairs / t, "flops_per_pair": fl,
+                                     "fp64_peak_frac": fl * pairs / t / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                                     "non_ok_pairs": int((st != 0).sum().item())}
+        log(f"oversampled patches of {m + 2 * o} cells: {out[f'patch_{m + 2 * o}']}")
+        del a, S, st
+    return out
+
+
 def measure_rb_os(wl, a, o, S_os, U_os, t_os, ntrain=64, r_max=8, tail_tol=1e-6):
     """Reduced basis on the oversampled patches (Sec. 3.2 on the patches of
     the Petrov-Galerkin MsFEM, as in the high-contrast example of Sec. 5.2):
@@ -1383,7 +1411,7 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, rb_os_channels, "
+                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, oversampling_large, rb_os_channels, "
                          "collocation, "
                          "two_level, gauss, gauss_paper_mesh); "
                          "default: all of them")
@@ -1593,6 +1621,9 @@ def main():
         if want("oversampling"):
             lg("oversampled Petrov-Galerkin upscaling at the 8x8 mesh")
             out["oversampled_petrov_galerkin"] = measure_oversampling(lg)
+        if want("oversampling_large"):
+            lg("oversampled Petrov-Galerkin upscaling with patches of 48 to 64 cells")
+            out["oversampled_large_patches"] = measure_oversampling_large(lg)
         if want("rb_os_channels"):
             lg("reduced basis on oversampled patches in the channels medium")
             out["reduced_basis_oversampled_channels"] = measure_rb_os_channels(lg)
