@@ -120,7 +120,7 @@ __device__ __forceinline__ double ot_rK(int l, int px, int py, int cx, int cy, i
 // about 100 AGPRs, no scratch; at two wavefronts per SIMD it spilled 444
 // bytes per lane).
 template <int M, int T, typename TA>
-__global__ __launch_bounds__(64, (T == 8 || M / T > 8) ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
+__global__ __launch_bounds__(64, (T >= 7 || M / T > 8) ? 1 : 2) void upscale_os_tiled_kernel(OtArgs args) {
   constexpr int NT = M / T, NV = OT_NV, OT_G = OtShape<NT>::G, OT_SLOTS = OtShape<NT>::SLOTS;
   static_assert(M == NT * T, "window must be NT x NT tiles");
   constexpr int n = M - 1, NI = n * n, NP = (NI + T - 1) / T;
@@ -562,12 +562,13 @@ __global__ __launch_bounds__(64, (T == 8 || M / T > 8) ? 1 : 2) void upscale_os_
   }
 }
 
-// patches of 16 and 24 cells (T = 4, 6 and NT = 4), of 32 to 64 cells in
-// steps of 8 (T = 8, NT = 4 ... 8), and of 60 cells (T = 6, NT = 10: 55 lanes
-// per pair; H/h = 20 at oversampling ratio 3)
+// patches of 16, 20, 24 and 28 cells (T = 4 ... 7, NT = 4), of 32 to 64
+// cells in steps of 8 (T = 8, NT = 4 ... 8), of 36 cells (T = 6, NT = 6) and
+// of 60 cells (T = 6, NT = 10: 55 lanes per pair; H/h = 20 at oversampling
+// ratio 3)
 bool upscale_os_tiled_supports(int m, int o) {
   const int M = m + 2 * o;
-  return M == 16 || M == 24 || M == 60 || (M >= 32 && M <= 64 && M % 8 == 0);
+  return M == 16 || M == 20 || M == 24 || M == 28 || M == 36 || M == 60 || (M >= 32 && M <= 64 && M % 8 == 0);
 }
 
 template <int M, int T>
@@ -587,7 +588,10 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
   const OtArgs args{up, o, list, nlist};
   switch (up.m + 2 * o) {
     case 16: launch_ot<16, 4>(args, a_dtype, st); break;
+    case 20: launch_ot<20, 5>(args, a_dtype, st); break;
     case 24: launch_ot<24, 6>(args, a_dtype, st); break;
+    case 28: launch_ot<28, 7>(args, a_dtype, st); break;
+    case 36: launch_ot<36, 6>(args, a_dtype, st); break;
     case 32: launch_ot<32, 8>(args, a_dtype, st); break;
     case 40: launch_ot<40, 8>(args, a_dtype, st); break;
     case 48: launch_ot<48, 8>(args, a_dtype, st); break;

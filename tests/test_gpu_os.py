@@ -67,6 +67,7 @@ def test_mesh8_matches_oracle(sm, orc, o):
 
 
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(6, 3, 5, 3, 1), (4, 2, 3, 7, 2), (16, 8, 4, 3, 1), (8, 12, 4, 4, 1),
+                                           (10, 5, 3, 4, 2), (14, 7, 3, 3, 1), (12, 12, 4, 3, 1),
                                            (2, 1, 9, 2, 3), (4, 6, 4, 5, 2), (2, 7, 9, 8, 1), (8, 4, 5, 3, 3),
                                            (8, 8, 4, 3, 2), (4, 10, 6, 7, 1), (6, 9, 5, 4, 1)])
 def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
