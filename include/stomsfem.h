@@ -437,9 +437,12 @@ int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* bat
  * be NULL) the patch blocks are reduced exactly as the elements of
  * stomsfem_reduce: means phibar^l, KL modes of the centred patch solutions
  * in the energy inner product of the training-mean coefficient, r_K by the
- * same rule.  Requires 2 <= Mp <= 32, Mp <= ncx*m and ncy*m,
+ * same rule.  Requires 2 <= Mp <= 64, Mp <= ncx*m and ncy*m,
  * 1 <= r_max <= 8, 1 <= ntrain <= 341 and the eigenproblem limit of
- * stomsfem_reduce (EINVAL otherwise).  Allocates device memory (owned by the
+ * stomsfem_reduce (EINVAL otherwise); patches of more than 32 cells take
+ * their snapshots from a band-window kernel (one wavefront per pair, the
+ * finished factor rows in a device row store of about (Mp-1)^2 (Mp+4)
+ * doubles for each of up to 1024 pairs in flight).  Allocates device memory (owned by the
  * model; a gathered copy of the training patches, ntrain*M*Mp*Mp doubles,
  * only during the call) and synchronises `stream`.  model_export 0..3 return
  * the patch quantities ((Mp-1)^2 interior nodes); stomsfem_model_save /

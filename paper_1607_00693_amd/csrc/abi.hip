@@ -1429,12 +1429,16 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
   return e == hipSuccess ? STOMSFEM_OK : hip_fail(e, "coarse_solve_pg launch");
 }
 
-int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,
-                    void* stream) {
+namespace {
+// The reduced-basis build; m_max = 32 for stomsfem_reduce, 64 for the
+// oversampled patches (cells past 32 take the band-window snapshot kernel).
+int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model, void* stream,
+                 int m_max) {
   if (!train || !model) return fail(STOMSFEM_EINVAL, "reduce: NULL argument");
   *model = nullptr;
   const stomsfem_batch& b = *train;
-  if (b.ncx < 1 || b.ncy < 1 || b.m < 2 || b.m > 32) return fail(STOMSFEM_EINVAL, "reduce: need 2 <= m <= 32");
+  if (b.ncx < 1 || b.ncy < 1 || b.m < 2 || b.m > m_max)
+    return fail(STOMSFEM_EINVAL, "reduce: need 2 <= m <= " + std::to_string(m_max));
   if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32) return fail(STOMSFEM_EINVAL, "reduce: bad a_dtype");
   if (b.nsamples < 1) return fail(STOMSFEM_EINVAL, "reduce: need at least one training sample");
   if (r_max < 1 || r_max > 8) return fail(STOMSFEM_EINVAL, "reduce: r_max must be in 1..8");
@@ -1470,8 +1474,13 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   A((void**)&md->G64, sizeof(double) * (size_t)Mc * md->KD * md->PP);
   A((void**)&phi, sizeof(double) * (size_t)b.nsamples * Mc * 3 * nI);
   A((void**)&work, sizeof(double) * (size_t)rb_work_doubles(b.ncx, b.ncy, m, (int)b.nsamples));
-  // snapshots through the refined kernel where the FP64 band does not fit LDS
-  const bool refined_phi = cell_phi_lds_bytes(m) > CELL_PHI_LDS_MAX;
+  // snapshots: the FP64 band in LDS where it fits, the refined kernel up to
+  // m = 32, the band-window kernel (global row store) beyond
+  const bool band_phi = m > 32;
+  const bool refined_phi = !band_phi && cell_phi_lds_bytes(m) > CELL_PHI_LDS_MAX;
+  const int64_t band_blocks = band_phi ? std::min<int64_t>(b.nsamples * Mc, 1024) : 0;
+  double* band_ws = nullptr;
+  if (band_phi) A((void**)&band_ws, sizeof(double) * (size_t)band_blocks * cell_phi_band_ws_doubles(m));
   int64_t* fail_list = nullptr;
   unsigned long long* fail_count = nullptr;
   if (refined_phi) {
@@ -1485,6 +1494,7 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
     hipFree(work);
     hipFree(fail_list);
     hipFree(fail_count);
+    hipFree(band_ws);
     model_release(md);
     return fail(STOMSFEM_ENOMEM, "reduce: device allocation failed");
   }
@@ -1503,6 +1513,8 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
     e = launch_upscale_mixed(ma, b.a_dtype, st);
     if (e == hipSuccess) e = hipMemcpyAsync(&nfail, fail_count, sizeof(nfail), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+  } else if (band_phi) {
+    e = launch_cell_phi_band(up, b.a_dtype, phi, band_ws, band_blocks, st);
   } else {
     e = launch_cell_phi(up, b.a_dtype, phi, st);
   }
@@ -1511,6 +1523,7 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
     hipFree(work);
     hipFree(fail_list);
     hipFree(fail_count);
+    hipFree(band_ws);
     model_release(md);
     return fail(STOMSFEM_ENOCONV, "reduce: " + std::to_string(nfail) +
                                       " training cell problems did not converge in the refined solver");
@@ -1544,12 +1557,19 @@ int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol,
   hipFree(work);
   hipFree(fail_list);
   hipFree(fail_count);
+  hipFree(band_ws);
   if (e != hipSuccess) {
     model_release(md);
     return hip_fail(e, "reduce");
   }
   *model = md;
   return STOMSFEM_OK;
+}
+}  // namespace
+
+int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,
+                    void* stream) {
+  return reduce_build(train, r_max, tail_tol, model, stream, 32);
 }
 
 int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,
@@ -1586,7 +1606,7 @@ int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t 
   if (b.ncx < 1 || b.ncy < 1 || b.m < 1 || oversample < 0)
     return fail(STOMSFEM_EINVAL, "reduce_os: need ncx, ncy, m >= 1 and oversample >= 0");
   const int Mp = b.m + 2 * oversample;
-  if (Mp < 2 || Mp > 32) return fail(STOMSFEM_EINVAL, "reduce_os: need 2 <= m + 2*oversample <= 32");
+  if (Mp < 2 || Mp > 64) return fail(STOMSFEM_EINVAL, "reduce_os: need 2 <= m + 2*oversample <= 64");
   if (Mp > b.ncx * b.m || Mp > b.ncy * b.m)
     return fail(STOMSFEM_EINVAL, "reduce_os: the patch is larger than the domain");
   if (b.a_dtype != STOMSFEM_F64 && b.a_dtype != STOMSFEM_F32)
@@ -1615,7 +1635,7 @@ int stomsfem_reduce_os(const stomsfem_batch* train, int32_t oversample, int32_t 
   pb.S = nullptr;
   pb.status = nullptr;
   stomsfem_model* md = nullptr;
-  int rc = stomsfem_reduce(&pb, r_max, tail_tol, &md, stream);
+  int rc = reduce_build(&pb, r_max, tail_tol, &md, stream, 64);
   hipStreamSynchronize(st);
   hipFree(emb);
   if (rc != STOMSFEM_OK) return rc;
@@ -3048,10 +3068,10 @@ int stomsfem_model_load(const char* path, stomsfem_model** model) {
     return fail(STOMSFEM_EVERSION, "model_load: written by ABI version " + std::to_string(h.abi));
   }
   const bool sane = ((h.kind >= 1 && h.kind <= 3) || h.kind == 9) && h.ncx >= 1 && h.ncy >= 1 && h.ncx <= 4096 &&
-                    h.ncy <= 4096 && h.m >= 1 && h.m <= 48 && h.rows >= 0 && h.rmax >= 0 && h.rmax <= 8 &&
+                    h.ncy <= 4096 && h.m >= 1 && (h.m <= 48 || (h.kind == 9 && h.m <= 64)) && h.rows >= 0 && h.rmax >= 0 && h.rmax <= 8 &&
                     h.KD >= 0 && h.PP >= 0 && h.KD <= 4096 && h.PP <= 4096 &&
                     (h.kind != 3 || (h.nn >= RI_NN_MIN && h.nn <= RI_NN_MAX)) &&
-                    (h.kind != 9 || (h.m >= 2 && h.m <= 32 && h.rmax == 8 && h.nn >= 0 && h.lv_max >= 1 &&
+                    (h.kind != 9 || (h.m >= 2 && h.m <= 64 && h.rmax == 8 && h.nn >= 0 && h.lv_max >= 1 &&
                                      h.lv_max + 2 * h.nn == h.m && h.KD == rb_pad_kd(h.m)));
   if (!sane) {
     std::fclose(f);

@@ -49,6 +49,13 @@ hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStre
 size_t cell_phi_lds_bytes(int m);
 // LDS of one workgroup on gfx950: the FP64 snapshot kernel serves m <= 26
 constexpr size_t CELL_PHI_LDS_MAX = 160 * 1024;
+// Snapshots of cells beyond the LDS kernels (m <= 64): one wavefront per
+// pair, a circular band window in LDS and a global row store of
+// cell_phi_band_ws_doubles(m) doubles per workgroup; blocks = workgroups
+// (at most npairs), ws holds blocks of them.
+hipError_t launch_cell_phi_band(const UpArgs& args, int a_dtype, double* phi, double* ws, int64_t blocks,
+                                hipStream_t st);
+int64_t cell_phi_band_ws_doubles(int m);
 hipError_t launch_rb_build(const RbBuildArgs& b, hipStream_t st);
 // Work doubles of the offline build and whether it takes the dual form (the
 // method of snapshots, 3 ntrain < (m-1)^2).

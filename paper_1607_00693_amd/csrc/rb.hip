@@ -155,6 +155,157 @@ hipError_t launch_cell_phi(const UpArgs& args, int a_dtype, double* phi, hipStre
   return e != hipSuccess ? e : hipGetLastError();
 }
 
+// Snapshots of cells whose band does not fit a workgroup's LDS (used for
+// m > 32, past the refined kernel).  One wavefront per pair.  The band rows
+// j .. j+B of the elimination window sit in a circular LDS ring of B+1 rows
+// (row i in slot i mod (B+1), entry d = K(i, i-d), column j kept unscaled as
+// in cell_phi_kernel); the three lifts are forward-substituted in the same
+// pivot loop.  A row leaves the ring after its pivot, finished, to the
+// workgroup's global row store with its forward-substituted right-hand
+// sides, and the backward substitution reads the stored rows in reverse: the
+// B products of a step are taken by the lanes and reduced over the
+// wavefront, the next step's entries fetched one step ahead.
+struct PhiBandArgs {
+  UpArgs up;
+  double* phi;   // [npairs][3][nI]
+  double* rows;  // [gridDim.x][nI][B+1] finished rows
+  double* ys;    // [gridDim.x][3][nI] forward-substituted right-hand sides
+};
+
+#define RB_WAVE_SYNC()                                     \
+  do {                                                     \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                       \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+  } while (0)
+
+template <typename TA>
+__global__ __launch_bounds__(64) void cell_phi_band_kernel(PhiBandArgs pa) {
+  extern __shared__ double smem[];
+  const UpArgs& args = pa.up;
+  const int m = args.m, n = m - 1, nI = n * n, B = m, W = B + 1;
+  double* Wn = smem;          // [W][W] ring of band rows
+  double* Fr = Wn + W * W;    // [3][W] right-hand sides of the ring rows
+  double* Xr = Fr + 3 * W;    // [3][W] solution values of the last B rows (backward pass)
+  const int lane = threadIdx.x;
+  const int Mc = args.ncx * args.ncy;
+  const int64_t lda = (int64_t)args.ncx * m;
+  double* rows = pa.rows + (int64_t)blockIdx.x * nI * W;
+  double* ys = pa.ys + (int64_t)blockIdx.x * 3 * nI;
+  for (int64_t p = blockIdx.x; p < args.npairs; p += gridDim.x) {
+    const int64_t s = p / Mc;
+    const int K = (int)(p - s * Mc);
+    const TA* a = (const TA*)args.a + block_offset(s, K, args.ncx, args.ncy, m);
+    // row r of K_II into slot r mod W and its lifts (the stencil of cell_phi_kernel)
+    auto build = [&](int r) {
+      double* row = Wn + (r % W) * W;
+      for (int d = lane; d <= B; d += 64) row[d] = 0.0;
+      RB_WAVE_SYNC();
+      if (lane == 0) {
+        const int ix = r % n, iy = r / n, px = ix + 1, py = iy + 1;
+        const double aSW = ld(a, (int64_t)iy * lda + ix), aSE = ld(a, (int64_t)iy * lda + ix + 1);
+        const double aNW = ld(a, (int64_t)(iy + 1) * lda + ix), aNE = ld(a, (int64_t)(iy + 1) * lda + ix + 1);
+        row[0] = (2.0 / 3.0) * ((aSW + aSE) + (aNW + aNE));
+        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+        const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+        const double ks[8] = {-(aSW + aNW) / 6.0, -(aSE + aNE) / 6.0, -(aSW + aSE) / 6.0, -(aNW + aNE) / 6.0,
+                              -aSW / 3.0,         -aSE / 3.0,         -aNW / 3.0,         -aNE / 3.0};
+        double f[3] = {0, 0, 0};
+        for (int q = 0; q < 8; ++q) {
+          const int qx = px + dxs[q], qy = py + dys[q];
+          if (qx == 0 || qx == m || qy == 0 || qy == m) {
+            for (int l = 0; l < 3; ++l) f[l] -= ks[q] * pcorner(l, qx, qy, m);
+          } else {
+            const int c = (qy - 1) * n + (qx - 1);
+            if (c < r) row[r - c] = ks[q];
+          }
+        }
+        for (int l = 0; l < 3; ++l) Fr[l * W + r % W] = f[l];
+      }
+      RB_WAVE_SYNC();
+    };
+    for (int r = 0; r < W && r < nI; ++r) build(r);
+    for (int j = 0; j < nI; ++j) {
+      const int sj = j % W;
+      const double inv = 1.0 / Wn[sj * W];
+      const int cnt = (j + B < nI - 1 ? j + B : nI - 1) - j;
+      const int npr = cnt * (cnt + 1) / 2;
+      for (int q = lane; q < npr; q += 64) {
+        int io = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+        while (io * (io + 1) / 2 > q) --io;
+        while ((io + 1) * (io + 2) / 2 <= q) ++io;
+        const int ko = q - io * (io + 1) / 2;
+        const int i = j + 1 + io, k = j + 1 + ko;
+        Wn[(i % W) * W + (i - k)] -= Wn[(i % W) * W + (i - j)] * inv * Wn[(k % W) * W + (k - j)];
+      }
+      for (int t = lane; t < 3 * cnt; t += 64) {
+        const int i = j + 1 + t / 3, l = t % 3;
+        Fr[l * W + i % W] -= Wn[(i % W) * W + (i - j)] * inv * Fr[l * W + sj];
+      }
+      RB_WAVE_SYNC();
+      // row j is finished: to the row store, its slot to the row entering at j + W
+      for (int d = lane; d <= B; d += 64) rows[(int64_t)j * W + d] = Wn[sj * W + d];
+      if (lane < 3) ys[(int64_t)lane * nI + j] = Fr[lane * W + sj];
+      RB_WAVE_SYNC();
+      if (j + W < nI) build(j + W);
+    }
+    // the stored rows are read back by other lanes of the wavefront
+    __threadfence();
+    __syncthreads();
+    // backward: x_j = (y_j - sum_{t=1..B} W_{j+t,j} x_{j+t}) / d_j; lane t
+    // takes t (lane 0 takes t = 64 when B = 64)
+    const int t = lane == 0 ? 64 : lane;
+    const bool tl = t <= B;
+    auto fetch = [&](int j) { return (j >= 0 && tl && j + t < nI) ? rows[(int64_t)(j + t) * W + t] : 0.0; };
+    double wc = fetch(nI - 1);
+    double* out = pa.phi + p * 3 * nI;
+    for (int j = nI - 1; j >= 0; --j) {
+      const double wn = fetch(j - 1);
+      double v[3];
+      const bool on = tl && j + t < nI;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) v[l] = on ? wc * Xr[l * W + (j + t) % W] : 0.0;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) v[l] += __shfl_xor(v[l], off, 64);
+      if (lane < 3) {
+        const double x = (ys[(int64_t)lane * nI + j] - v[lane]) / rows[(int64_t)j * W];
+        Xr[lane * W + j % W] = x;
+        out[(int64_t)lane * nI + j] = x;
+      }
+      RB_WAVE_SYNC();
+      wc = wn;
+    }
+    __syncthreads();  // the ring and the row store are reused by the next pair
+  }
+}
+
+size_t cell_phi_band_lds_bytes(int m) {
+  const size_t W = (size_t)m + 1;
+  return sizeof(double) * (W * W + 6 * W);
+}
+
+int64_t cell_phi_band_ws_doubles(int m) {
+  const int64_t nI = (int64_t)(m - 1) * (m - 1);
+  return nI * (m + 1) + 3 * nI;
+}
+
+hipError_t launch_cell_phi_band(const UpArgs& args, int a_dtype, double* phi, double* ws, int64_t blocks,
+                                hipStream_t st) {
+  if (args.npairs == 0) return hipSuccess;
+  if (args.m < 2 || args.m > 64 || blocks < 1) return hipErrorInvalidValue;
+  const int64_t nI = (int64_t)(args.m - 1) * (args.m - 1);
+  if (blocks > args.npairs) blocks = args.npairs;
+  PhiBandArgs pa{args, phi, ws, ws + blocks * nI * (args.m + 1)};
+  const size_t lds = cell_phi_band_lds_bytes(args.m);
+  if (a_dtype == STOMSFEM_F32)
+    hipLaunchKernelGGL(cell_phi_band_kernel<float>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
+  else
+    hipLaunchKernelGGL(cell_phi_band_kernel<double>, dim3((unsigned)blocks), dim3(64), lds, st, pa);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Offline build
 // ---------------------------------------------------------------------------

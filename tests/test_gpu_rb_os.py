@@ -280,3 +280,48 @@ def test_high_contrast_patches_of_24_cells(sm, orc):
     S = sm.reduce_os_apply(model, a).cpu().numpy()
     R, _ = orc.upscale_os(a_np, nc, nc, m, o)
     assert _rel_pairs(S, R) < 1e-8
+
+
+@pytest.mark.parametrize("m,o,nc", [(8, 16, 5), (20, 20, 3), (32, 16, 2)])
+def test_patches_beyond_32_cells_reproduce_training_samples(sm, m, o, nc):
+    # patches of 40, 60 (Sec. 5.2: H/h = 20, ratio 3) and 64 cells (the Sec.
+    # 5.3 mesh's): snapshots from the band-window kernel; two training
+    # samples (r = 3) are reproduced exactly, so S16 equals the oversampled
+    # solve of those samples; the FP32 matrix-core stage within 2e-4
+    a = torch.from_numpy(W.uniform_array((2, nc * m, nc * m), 0.3, 4.0, 2110 + m)).cuda()
+    say(f"patch of {m + 2 * o} cells: build")
+    model = sm.reduce_os(a, nc, nc, m, o, r_max=8, tail_tol=0.0)
+    r = np.zeros(nc * nc, dtype=np.int32)
+    sm.lib().stomsfem_model_export(model.handle, 0, r.ctypes.data, r.nbytes)
+    assert (r == 3).all()
+    S = sm.reduce_os_apply(model, a)
+    R = sm.upscale_os(a, nc, nc, m, o)
+    err = _rel_pairs(S.cpu().numpy(), R.cpu().numpy())
+    say(f"  vs oversampled solve {err:.2e}")
+    assert err < 1e-8
+    S32 = sm.reduce_os_apply(model, a.float(), precision=sm.PREC_F32)
+    assert _rel_pairs(S32.cpu().numpy(), S.cpu().numpy()) < 2e-4
+
+
+def test_40_cell_patches_match_oracle(sm, orc):
+    # the band-window snapshots, the dual build and both online stages at 40
+    # cells against the oracle's own patch models on three patches (corner,
+    # centre, corner); three training samples keep every mode (r = 6)
+    from oracle import rb
+    nc, m, o = 5, 8, 16
+    a_tr = W.uniform_array((3, nc * m, nc * m), 0.3, 4.0, 2120)
+    a = W.uniform_array((2, nc * m, nc * m), 0.3, 4.0, 2121)
+    say("40-cell patches against the oracle")
+    model = sm.reduce_os(torch.from_numpy(a_tr).cuda(), nc, nc, m, o, r_max=8, tail_tol=0.0)
+    S = sm.reduce_os_apply(model, torch.from_numpy(a).cuda()).cpu().numpy()
+    for K in (0, 12, 24):
+        blocks = np.stack([rb.patch_block(a_tr[s], K, nc, nc, m, o) for s in range(3)])
+        mo = rb.rb_offline(np.ascontiguousarray(blocks), r_max=8, tail_tol=0.0)
+        assert mo["r"] == 6
+        kx, ky = K % nc, K // nc
+        cx = kx * m - orc.os_origin(kx, m, o, nc * m)
+        cy = ky * m - orc.os_origin(ky, m, o, nc * m)
+        for s in range(2):
+            R = rb.rb_os_online_S16(mo, np.ascontiguousarray(rb.patch_block(a[s], K, nc, nc, m, o)), m, cx, cy)
+            err = np.abs(S[s, K] - R.ravel()).max() / np.abs(R).max()
+            assert err < 1e-7, (K, s, err)
