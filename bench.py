@@ -809,6 +809,54 @@ def measure_oversampling_large(log):
     return out
 
 
+def measure_rb_os_sec52(log, nc=12, m=20, o=20, ntrain=64, N=1024):
+    """Reduced basis on oversampled patches in the geometry of the example of
+    Sec. 5.2 (H/h = 20, oversampling ratio 3: 60-cell patches) on the bump
+    medium (16 bumps of radius 1/4 on a 4x4 grid, eps = 1/32; xi ~ U[-1,1]^16,
+    training seed 2003, samples seed 1003): offline time (band-window
+    snapshots, method of snapshots), both online stages against the
+    oversampled solve of the same pairs (register-tiled kernel)."""
+    import torch
+
+    from paper_1607_00693_amd import stomsfem as sm
+    from paper_1607_00693_amd import workloads as W
+
+    wl = W.MESH8
+    nf = nc * m
+    xi_tr = torch.from_numpy(W.uniform_xi(ntrain, wl.nxi, 2003)).cuda()
+    a_tr = sm.coef_bumps(xi_tr, nf, **wl.coef_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = sm.reduce_os(a_tr, nc, nc, m, o, r_max=8, tail_tol=1e-6)
+    t_off = time.perf_counter() - t0
+    del a_tr
+    xi = torch.from_numpy(W.uniform_xi(N, wl.nxi, 1003)).cuda()
+    a = sm.coef_bumps(xi, nf, **wl.coef_params())
+    M = nc * nc
+    S_os = torch.empty((N, M, 16), dtype=torch.float64, device="cuda")
+    t_os = _timed(lambda: sm.upscale_os(a, nc, nc, m, o, S=S_os), reps=2)
+    U_os, _, _ = sm.coarse_solve_pg(S_os, nc, nc)
+    r = model.export("r")
+    out = {"workload": f"{nc}x{nc} coarse, H/h={m}, oversample {o} (patches of {m + 2 * o} cells, ratio "
+                       f"{(m + 2 * o) // m}), bump medium, {ntrain} training samples, {N} samples",
+           "offline_s": t_off, "modes_min": int(r.min()), "modes_max": int(r.max()),
+           "oversampled_solve_ms": t_os * 1e3, "oversampled_solve_pairs_per_s": N * M / t_os}
+    S = torch.empty_like(S_os)
+    a32 = a.float()
+    scale = S_os.abs().amax(dim=2, keepdim=True)
+    for key, prec, aa in (("fp32_matrix_core", sm.PREC_F32, a32), ("fp64", sm.PREC_F64, a)):
+        t_on = _timed(lambda: sm.reduce_os_apply(model, aa, S=S, precision=prec), reps=3)
+        rel = ((S - S_os).abs() / scale).amax(dim=2)
+        U, _, _ = sm.coarse_solve_pg(S, nc, nc)
+        d = torch.linalg.norm(U - U_os, dim=1) / torch.linalg.norm(U_os, dim=1)
+        out[key] = {"online_ms": t_on * 1e3, "pairs_per_s": N * M / t_on, "vs_oversampled_solve": t_os / t_on,
+                    "max_S_rel_err": float(rel.max()), "median_S_rel_err": float(rel.median()),
+                    "max_coarse_rel_err": float(d.max())}
+    log(f"reduced basis, oversampled, Sec. 5.2 geometry: {out}")
+    model.free()
+    return out
+
+
 def measure_rb_os(wl, a, o, S_os, U_os, t_os, ntrain=64, r_max=8, tail_tol=1e-6):
     """Reduced basis on the oversampled patches (Sec. 3.2 on the patches of
     the Petrov-Galerkin MsFEM, as in the high-contrast example of Sec. 5.2):
@@ -1411,7 +1459,7 @@ def main():
     ap.add_argument("--no-accelerations", action="store_true", help="skip the reduced-basis / surrogate comparison")
     ap.add_argument("--only", default="",
                     help="comma-separated subset of the extra measurements (ri_bench, rb_bench, two_level_bench, surrogate_bench, "
-                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, oversampling_large, rb_os_channels, "
+                         "mixed_bench, mesh8, coarse_bench, queue, channels, channels_surrogate, oversampling, oversampling_large, rb_os_sec52, rb_os_channels, "
                          "collocation, "
                          "two_level, gauss, gauss_paper_mesh); "
                          "default: all of them")
@@ -1624,6 +1672,9 @@ def main():
         if want("oversampling_large"):
             lg("oversampled Petrov-Galerkin upscaling with patches of 48 to 64 cells")
             out["oversampled_large_patches"] = measure_oversampling_large(lg)
+        if want("rb_os_sec52"):
+            lg("reduced basis on oversampled patches, Sec. 5.2 geometry")
+            out["reduced_basis_oversampled_sec52"] = measure_rb_os_sec52(lg)
         if want("rb_os_channels"):
             lg("reduced basis on oversampled patches in the channels medium")
             out["reduced_basis_oversampled_channels"] = measure_rb_os_channels(lg)
