@@ -399,14 +399,15 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * single training sample).  The model stores,
  * per patch and fine element e, the P = r(r+1)/2 + 3r + 6 coefficients that
  * make the online Galerkin system a linear function of the coefficient
- * values a_e (the Q1 stiffness is affine in a_e).  Requires 2 <= m <= 32,
+ * values a_e (the Q1 stiffness is affine in a_e).  Requires 2 <= m <= 48,
  * 1 <= r_max <= 8 and min((m-1)^2, 3 ntrain) <= 1024 (the eigenproblem: with
  * fewer snapshots than interior unknowns, 3 ntrain < (m-1)^2, the modes come
  * from the 3 ntrain x 3 ntrain snapshot matrix in the energy inner product,
  * the method of snapshots).  Where the FP64 band of a cell problem does not
- * fit a workgroup's 160 KB of LDS (m > 26) the training phi come from the FP32 factorisation
+ * fit a workgroup's 160 KB of LDS (26 < m <= 32) the training phi come from the FP32 factorisation
  * with FP64 residual refinement, and the call fails with ENOCONV if any of
- * them does not converge.  Allocates device memory (owned by the model) and
+ * them does not converge; beyond 32 from the FP64 band-window kernel (band
+ * rows in an LDS ring, finished factor rows in a device row store).  Allocates device memory (owned by the model) and
  * synchronises `stream` before returning.
  *
  * stomsfem_reduce_apply (online, Algorithm 4): S_rb for every pair of

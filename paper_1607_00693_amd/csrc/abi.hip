@@ -1430,8 +1430,9 @@ int stomsfem_coarse_solve_pg(int32_t ncx, int32_t ncy, int64_t nsamples, const d
 }
 
 namespace {
-// The reduced-basis build; m_max = 32 for stomsfem_reduce, 64 for the
-// oversampled patches (cells past 32 take the band-window snapshot kernel).
+// The reduced-basis build; m_max = 48 for stomsfem_reduce (the batch limit),
+// 64 for the oversampled patches (cells past 32 take the band-window snapshot
+// kernel).
 int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model, void* stream,
                  int m_max) {
   if (!train || !model) return fail(STOMSFEM_EINVAL, "reduce: NULL argument");
@@ -1569,7 +1570,7 @@ int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, st
 
 int stomsfem_reduce(const stomsfem_batch* train, int32_t r_max, double tail_tol, stomsfem_model** model,
                     void* stream) {
-  return reduce_build(train, r_max, tail_tol, model, stream, 32);
+  return reduce_build(train, r_max, tail_tol, model, stream, 48);
 }
 
 int stomsfem_reduce_apply(const stomsfem_model* model, const stomsfem_batch* batch, int32_t precision,

@@ -225,3 +225,22 @@ def test_rb_larger_cells_against_oracle(sm, orc, m, nsub, ntr, form):
     assert e64 < 1e-7
     assert e32 < 2e-4
     model.free()
+
+
+@pytest.mark.parametrize("m", [40, 48])
+def test_rb_cells_beyond_32_reproduce_training_samples(sm, m):
+    # H/h = 40 and 48: the band-window snapshot kernel and the method of
+    # snapshots; two training samples (r = 3) are reproduced exactly, so S_rb
+    # equals the plain upscaling of those samples (both online stages)
+    nc = 2
+    a = torch.from_numpy(W.uniform_array((2, nc * m, nc * m), 0.3, 4.0, 2130 + m)).cuda()
+    say(f"H/h = {m}: build")
+    model = sm.reduce(a, nc, nc, m, r_max=8, tail_tol=0.0)
+    assert (model.export("r") == 3).all()
+    S_ref = sm.upscale(a, nc, nc, m)
+    for prec, tol in ((sm.PREC_F64, 1e-9), (sm.PREC_F32, 2e-4)):
+        S = sm.reduce_apply(model, a if prec == sm.PREC_F64 else a.float(), precision=prec)
+        err = rel(S.cpu().numpy(), S_ref.cpu().numpy())
+        say(f"  precision {prec}: {err:.2e}")
+        assert err < tol
+    model.free()
