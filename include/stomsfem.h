@@ -403,11 +403,10 @@ int stomsfem_two_level_mc(const double* U_H, int64_t n_H, const double* U_Hh, co
  * 1 <= r_max <= 8 and min((m-1)^2, 3 ntrain) <= 1024 (the eigenproblem: with
  * fewer snapshots than interior unknowns, 3 ntrain < (m-1)^2, the modes come
  * from the 3 ntrain x 3 ntrain snapshot matrix in the energy inner product,
- * the method of snapshots).  Where the FP64 band of a cell problem does not
- * fit a workgroup's 160 KB of LDS (26 < m <= 32) the training phi come from the FP32 factorisation
- * with FP64 residual refinement, and the call fails with ENOCONV if any of
- * them does not converge; beyond 32 from the FP64 band-window kernel (band
- * rows in an LDS ring, finished factor rows in a device row store).  Allocates device memory (owned by the model) and
+ * the method of snapshots).  The training phi are FP64 banded solves: the
+ * band in LDS up to m = 26, beyond that the band-window kernel (band rows in
+ * an LDS ring, the finished factor rows in a device row store of about
+ * (m-1)^2 (m+4) doubles for each of up to 1024 pairs in flight).  Allocates device memory (owned by the model) and
  * synchronises `stream` before returning.
  *
  * stomsfem_reduce_apply (online, Algorithm 4): S_rb for every pair of

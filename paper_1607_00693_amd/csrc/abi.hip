@@ -1475,26 +1475,16 @@ int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, st
   A((void**)&md->G64, sizeof(double) * (size_t)Mc * md->KD * md->PP);
   A((void**)&phi, sizeof(double) * (size_t)b.nsamples * Mc * 3 * nI);
   A((void**)&work, sizeof(double) * (size_t)rb_work_doubles(b.ncx, b.ncy, m, (int)b.nsamples));
-  // snapshots: the FP64 band in LDS where it fits, the refined kernel up to
-  // m = 32, the band-window kernel (global row store) beyond
-  const bool band_phi = m > 32;
-  const bool refined_phi = !band_phi && cell_phi_lds_bytes(m) > CELL_PHI_LDS_MAX;
+  // snapshots: the FP64 band in LDS where it fits (m <= 26), the FP64
+  // band-window kernel (global row store) beyond
+  const bool band_phi = cell_phi_lds_bytes(m) > CELL_PHI_LDS_MAX;
   const int64_t band_blocks = band_phi ? std::min<int64_t>(b.nsamples * Mc, 1024) : 0;
   double* band_ws = nullptr;
   if (band_phi) A((void**)&band_ws, sizeof(double) * (size_t)band_blocks * cell_phi_band_ws_doubles(m));
-  int64_t* fail_list = nullptr;
-  unsigned long long* fail_count = nullptr;
-  if (refined_phi) {
-    A((void**)&fail_list, sizeof(int64_t) * (size_t)b.nsamples * Mc);
-    A((void**)&fail_count, sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemsetAsync(fail_count, 0, sizeof(unsigned long long), st);
-  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     hipFree(phi);
     hipFree(work);
-    hipFree(fail_list);
-    hipFree(fail_count);
     hipFree(band_ws);
     model_release(md);
     return fail(STOMSFEM_ENOMEM, "reduce: device allocation failed");
@@ -1502,33 +1492,10 @@ int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, st
   UpArgs up = to_args(b);
   up.S = nullptr;
   up.status = nullptr;
-  unsigned long long nfail = 0;
-  if (refined_phi) {
-    MixedArgs ma{};
-    ma.up = up;
-    ma.tol = STOMSFEM_REFINE_TOL * 1e-2;
-    ma.max_iter = 2 * STOMSFEM_REFINE_MAXIT;
-    ma.list = fail_list;
-    ma.count = fail_count;
-    ma.phi = phi;
-    e = launch_upscale_mixed(ma, b.a_dtype, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&nfail, fail_count, sizeof(nfail), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-  } else if (band_phi) {
+  if (band_phi)
     e = launch_cell_phi_band(up, b.a_dtype, phi, band_ws, band_blocks, st);
-  } else {
+  else
     e = launch_cell_phi(up, b.a_dtype, phi, st);
-  }
-  if (e == hipSuccess && nfail > 0) {
-    hipFree(phi);
-    hipFree(work);
-    hipFree(fail_list);
-    hipFree(fail_count);
-    hipFree(band_ws);
-    model_release(md);
-    return fail(STOMSFEM_ENOCONV, "reduce: " + std::to_string(nfail) +
-                                      " training cell problems did not converge in the refined solver");
-  }
   if (e == hipSuccess) {
     RbBuildArgs ba{};
     ba.ncx = b.ncx;
@@ -1556,8 +1523,6 @@ int reduce_build(const stomsfem_batch* train, int32_t r_max, double tail_tol, st
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   hipFree(phi);
   hipFree(work);
-  hipFree(fail_list);
-  hipFree(fail_count);
   hipFree(band_ws);
   if (e != hipSuccess) {
     model_release(md);

@@ -11,7 +11,6 @@ struct MixedArgs {
   int32_t max_iter;             // refinement solves
   int64_t* list;                // pairs handed to the FP64 path
   unsigned long long* count;
-  double* phi;                  // optional: refined cell solutions [npairs][3][(m-1)^2] of converged pairs
 };
 
 size_t upscale_mixed_lds_bytes(int m);

@@ -196,9 +196,6 @@ __global__ __launch_bounds__(64) void upscale_mixed_kernel(MixedArgs args) {
     return;
   }
 
-  if (args.phi) {  // the refined cell solutions (interior nodes), e.g. as reduced-basis snapshots
-    for (int idx = lane; idx < 3 * NI; idx += 64) args.phi[p * 3 * NI + idx] = X[idx];
-  }
   if (!up.S) return;
   // 4. S by the element energy sum, FP64
   double e6[6] = {0, 0, 0, 0, 0, 0};
