@@ -563,12 +563,16 @@ __global__ __launch_bounds__(64, (T >= 7 || M / T > 8) ? 1 : 2) void upscale_os_
 }
 
 // patches of 16, 20, 24 and 28 cells (T = 4 ... 7, NT = 4), of 32 to 64
-// cells in steps of 8 (T = 8, NT = 4 ... 8), of 36 cells (T = 6, NT = 6) and
-// of 60 cells (T = 6, NT = 10: 55 lanes per pair; H/h = 20 at oversampling
-// ratio 3)
+// cells in steps of 8 (T = 8, NT = 4 ... 8), and of 30, 36, 42, 54 and 60
+// cells (T = 6, NT = 5, 6, 7, 9, 10: up to 55 lanes per pair; ratio 3 at
+// H/h = 10 ... 20)
 bool upscale_os_tiled_supports(int m, int o) {
   const int M = m + 2 * o;
-  return M == 16 || M == 20 || M == 24 || M == 28 || M == 36 || M == 60 || (M >= 32 && M <= 64 && M % 8 == 0);
+  if (M >= 32 && M <= 64 && M % 8 == 0) return true;
+  switch (M) {
+    case 16: case 20: case 24: case 28: case 30: case 36: case 42: case 54: case 60: return true;
+    default: return false;
+  }
 }
 
 template <int M, int T>
@@ -591,10 +595,13 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
     case 20: launch_ot<20, 5>(args, a_dtype, st); break;
     case 24: launch_ot<24, 6>(args, a_dtype, st); break;
     case 28: launch_ot<28, 7>(args, a_dtype, st); break;
-    case 36: launch_ot<36, 6>(args, a_dtype, st); break;
+    case 30: launch_ot<30, 6>(args, a_dtype, st); break;
     case 32: launch_ot<32, 8>(args, a_dtype, st); break;
+    case 36: launch_ot<36, 6>(args, a_dtype, st); break;
     case 40: launch_ot<40, 8>(args, a_dtype, st); break;
+    case 42: launch_ot<42, 6>(args, a_dtype, st); break;
     case 48: launch_ot<48, 8>(args, a_dtype, st); break;
+    case 54: launch_ot<54, 6>(args, a_dtype, st); break;
     case 56: launch_ot<56, 8>(args, a_dtype, st); break;
     case 60: launch_ot<60, 6>(args, a_dtype, st); break;
     default: launch_ot<64, 8>(args, a_dtype, st); break;

@@ -88,6 +88,7 @@ def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
 
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(10, 12, 4, 4, 1), (20, 11, 3, 3, 1), (16, 16, 3, 3, 1),
                                            (24, 8, 3, 3, 2), (40, 8, 2, 2, 1), (20, 20, 3, 3, 1),
+                                           (10, 10, 3, 3, 2), (14, 14, 3, 3, 1), (18, 18, 3, 3, 1),
                                            (32, 15, 3, 3, 1), (24, 20, 3, 3, 1), (32, 16, 3, 2, 1)])
 def test_large_patches_match_oracle(sm, orc, m, o, ncx, ncy, N):
     # patches of 34 to 64 cells (the paper's Sec. 5.3 geometry has 64-cell
