@@ -260,8 +260,8 @@ int stomsfem_coarse_solve_noalloc(int32_t ncx, int32_t ncy, int64_t nsamples, co
  * oversample = 0 gives the unpacked stiffness of stomsfem_upscale.  The
  * oversampling ratio is M/m (2 for oversample = m/2).  Requires
  * 2 <= M <= 64 and M <= ncx*m, ncy*m (EINVAL otherwise); patches of 16,
- * 20, 24, 28, 30, 36, 42, 54, 60 and 32 to 64 cells in steps of 8 take the
- * register-tiled kernel, others
+ * 20, 24, 25, 28, 30, 35, 36, 42, 45, 49, 50, 54, 60, 63 and 32 to 64 cells
+ * in steps of 8 take the register-tiled kernel, others
  * one wavefront per pair with the band window in LDS.  Per-pair status
  * ENOTSPD if a pivot is not positive or the corner values of the patch
  * solutions are singular (S undefined).  Asynchronous.

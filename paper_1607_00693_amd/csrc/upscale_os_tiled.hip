@@ -563,14 +563,16 @@ __global__ __launch_bounds__(64, (T >= 7 || M / T > 8) ? 1 : 2) void upscale_os_
 }
 
 // patches of 16, 20, 24 and 28 cells (T = 4 ... 7, NT = 4), of 32 to 64
-// cells in steps of 8 (T = 8, NT = 4 ... 8), and of 30, 36, 42, 54 and 60
-// cells (T = 6, NT = 5, 6, 7, 9, 10: up to 55 lanes per pair; ratio 3 at
-// H/h = 10 ... 20)
+// cells in steps of 8 (T = 8, NT = 4 ... 8), of 30, 36, 42, 54 and 60 cells
+// (T = 6, NT = 5, 6, 7, 9, 10: up to 55 lanes per pair; ratio 3 at H/h = 10
+// ... 20), of 25, 35, 45 and 50 cells (T = 5, NT = 5, 7, 9, 10) and of 49
+// and 63 cells (T = 7, NT = 7, 9)
 bool upscale_os_tiled_supports(int m, int o) {
   const int M = m + 2 * o;
   if (M >= 32 && M <= 64 && M % 8 == 0) return true;
   switch (M) {
-    case 16: case 20: case 24: case 28: case 30: case 36: case 42: case 54: case 60: return true;
+    case 16: case 20: case 24: case 25: case 28: case 30: case 35: case 36: case 42: case 45: case 49: case 50:
+    case 54: case 60: case 63: return true;
     default: return false;
   }
 }
@@ -594,16 +596,22 @@ hipError_t launch_upscale_os_tiled(const UpArgs& up, int o, int a_dtype, hipStre
     case 16: launch_ot<16, 4>(args, a_dtype, st); break;
     case 20: launch_ot<20, 5>(args, a_dtype, st); break;
     case 24: launch_ot<24, 6>(args, a_dtype, st); break;
+    case 25: launch_ot<25, 5>(args, a_dtype, st); break;
     case 28: launch_ot<28, 7>(args, a_dtype, st); break;
     case 30: launch_ot<30, 6>(args, a_dtype, st); break;
     case 32: launch_ot<32, 8>(args, a_dtype, st); break;
+    case 35: launch_ot<35, 5>(args, a_dtype, st); break;
     case 36: launch_ot<36, 6>(args, a_dtype, st); break;
     case 40: launch_ot<40, 8>(args, a_dtype, st); break;
     case 42: launch_ot<42, 6>(args, a_dtype, st); break;
+    case 45: launch_ot<45, 5>(args, a_dtype, st); break;
     case 48: launch_ot<48, 8>(args, a_dtype, st); break;
+    case 49: launch_ot<49, 7>(args, a_dtype, st); break;
+    case 50: launch_ot<50, 5>(args, a_dtype, st); break;
     case 54: launch_ot<54, 6>(args, a_dtype, st); break;
     case 56: launch_ot<56, 8>(args, a_dtype, st); break;
     case 60: launch_ot<60, 6>(args, a_dtype, st); break;
+    case 63: launch_ot<63, 7>(args, a_dtype, st); break;
     default: launch_ot<64, 8>(args, a_dtype, st); break;
   }
   return hipGetLastError();

@@ -89,12 +89,15 @@ def test_ragged_shapes_and_patch_sizes(sm, orc, m, o, ncx, ncy, N):
 @pytest.mark.parametrize("m,o,ncx,ncy,N", [(10, 12, 4, 4, 1), (20, 11, 3, 3, 1), (16, 16, 3, 3, 1),
                                            (24, 8, 3, 3, 2), (40, 8, 2, 2, 1), (20, 20, 3, 3, 1),
                                            (10, 10, 3, 3, 2), (14, 14, 3, 3, 1), (18, 18, 3, 3, 1),
+                                           (15, 5, 2, 2, 2), (15, 10, 3, 3, 1), (15, 15, 3, 3, 1),
+                                           (21, 14, 3, 3, 1), (26, 12, 2, 2, 1), (21, 21, 3, 3, 1),
                                            (32, 15, 3, 3, 1), (24, 20, 3, 3, 1), (32, 16, 3, 2, 1)])
 def test_large_patches_match_oracle(sm, orc, m, o, ncx, ncy, N):
-    # patches of 34 to 64 cells (the paper's Sec. 5.3 geometry has 64-cell
+    # patches of 25 to 64 cells (the paper's Sec. 5.3 geometry has 64-cell
     # patches: h = 2^-11, H/h = 32, ratio 2).  Sides 40, 48, 56 and 64 take
-    # the register-tiled kernel (8 x 8 tiles, 15 to 36 lanes per pair), 60
-    # (Sec. 5.2: H/h = 20, ratio 3) the same with 6 x 6 tiles and 55 lanes; the
+    # the register-tiled kernel (8 x 8 tiles, 15 to 36 lanes per pair), 30, 42,
+    # 54 and 60 (Sec. 5.2: H/h = 20, ratio 3) the same with 6 x 6 tiles and up
+    # to 55 lanes, 25, 35, 45 and 50 with 5 x 5 tiles, 49 and 63 with 7 x 7; the
     # others one wavefront per pair with up to 104 KB of LDS, the trailing
     # triangle in 17 or 33 entries per lane, the entering row's band and
     # right-hand sides in two rounds of the wavefront
