@@ -782,18 +782,20 @@ def measure_oversampling(log, N=16384, rb_ntrain=64):
 
 
 def measure_oversampling_large(log):
-    """Oversampled Petrov-Galerkin upscaling with patches of 40 to 64 cells
-    (log-normal coefficients, sigma = 1, seed 11): 48 cells (16x16 coarse,
-    H/h = 16, ratio 3, 64 samples), 60 cells (12x12 coarse, H/h = 20, ratio 3:
-    the geometry of the high-contrast example of Sec. 5.2, 64 samples) and 64
-    cells (16x16 coarse, H/h = 32, ratio 2, 16 samples)."""
+    """Oversampled Petrov-Galerkin upscaling with patches of 30 to 64 cells
+    (log-normal coefficients, sigma = 1, seed 11), ratio 3 at H/h = 10, 14,
+    16, 18 and 20 (30, 42, 48, 54 and 60 cells; 16x16, 16x16, 16x16, 8x8 and
+    12x12 coarse meshes, 64 samples; 60 cells is the geometry of the
+    high-contrast example of Sec. 5.2) and 64 cells (16x16 coarse, H/h = 32,
+    ratio 2, 16 samples)."""
     import torch
 
     from paper_1607_00693_amd import stomsfem as sm
     from paper_1607_00693_amd import workloads as W
 
     out = {}
-    for nc, m, o, N in ((16, 16, 16, 64), (12, 20, 20, 64), (16, 32, 16, 16)):
+    for nc, m, o, N in ((16, 10, 10, 64), (16, 14, 14, 64), (16, 16, 16, 64), (8, 18, 18, 64), (12, 20, 20, 64),
+                        (16, 32, 16, 16)):
         a = torch.from_numpy(W.lognormal_field((N, nc * m, nc * m), 1.0, 11)).cuda()
         S = torch.empty((N, nc * nc, 16), dtype=torch.float64, device="cuda")
         st = torch.empty((N, nc * nc), dtype=torch.int32, device="cuda")
